@@ -1,0 +1,54 @@
+"""Occupations of one subsystem (test infrastructure, FP64).
+
+Sec. 2 allows fractional occupations 0 <= n_jk <= 1 (f = 2n here) summing to
+the subsystem's electrons; Sec. 3 smears only metallic subsystems and keeps
+integer occupations for molecules. Reading used here: one Fermi level mu per
+subsystem with the Brillouin-zone averaged constraint
+sum_k w_k sum_n f_nk = N_I.
+
+* integer: f = 2 on the lowest N_I/2 bands of every k;
+* fermi-dirac (width sigma): f = 1 - tanh((eps - mu) / (2 sigma)), the
+  overflow-free form of 2 / (1 + e^{(eps-mu)/sigma}); mu by bisection on
+  [min eps - 20 sigma, max eps + 20 sigma] until |sum w f - N| < 1e-13
+  (at most 200 halvings).
+
+Pins: electron count; sigma -> 0 gives integer filling of a gapped spectrum;
+mu lies in the gap (tests/test_oracle_solver.py).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def fermi_dirac(eps, mu, sigma):
+    return 1.0 - np.tanh((np.asarray(eps) - mu) / (2.0 * sigma))
+
+
+def occupations(eps: np.ndarray, wk: np.ndarray, nelec: float, mode: str, sigma: float = 0.0):
+    """(f [nk, nb], mu) for eigenvalues eps [nk, nb] ascending per k."""
+    eps = np.asarray(eps, dtype=np.float64)
+    wk = np.asarray(wk, dtype=np.float64)
+    nk, nb = eps.shape
+    if mode == "integer":
+        nocc = int(round(nelec / 2.0))
+        if nocc > nb:
+            raise ValueError("not enough bands")
+        f = np.zeros_like(eps)
+        f[:, :nocc] = 2.0
+        mu = float(np.max(eps[:, nocc - 1])) if nocc > 0 else float(np.min(eps))
+        return f, mu
+    if mode != "fermi-dirac":
+        raise ValueError(mode)
+    lo = float(eps.min()) - 20.0 * sigma
+    hi = float(eps.max()) + 20.0 * sigma
+    mu = 0.5 * (lo + hi)
+    for _ in range(200):
+        mu = 0.5 * (lo + hi)
+        n = float(np.sum(wk[:, None] * fermi_dirac(eps, mu, sigma)))
+        if abs(n - nelec) < 1e-13:
+            break
+        if n < nelec:
+            lo = mu
+        else:
+            hi = mu
+    return fermi_dirac(eps, mu, sigma), mu
