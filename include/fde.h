@@ -1,0 +1,262 @@
+/*
+ * fde.h -- C ABI of the MI355X (gfx950) periodic frozen-density-embedding
+ * hot path.
+ *
+ * Method: Genova, Ceresoli & Pavanello, "Periodic Subsystem Density-Functional
+ * Theory" (arXiv:1406.7803). Each subsystem I solves the Kohn-Sham-like
+ * equation of Sec. 2 (Eq. KS) in a plane-wave basis at every k-point, with the
+ * effective potential in the recast form of the Appendix ("Recast of the
+ * Effective Potential expression"):
+ *     V_eff^I = V_eN(all nuclei) + V_H[rho] + V_XC[rho_I]
+ *               + V_kin^nad[rho, rho_I] + V_XC^nad[rho, rho_I],
+ * the densities are the Brillouin-zone sums of Sec. 2, and rho = sum_I rho_I.
+ *
+ * Conventions (all calls):
+ *  - Units: Hartree atomic units. Orthorhombic cell L1 x L2 x L3.
+ *  - Grids are real arrays in C order [N3][N2][N1] (x fastest), of the plan's
+ *    precision (double for FDE_F64, float for FDE_F32).
+ *  - Bands are band-major [nb][npw_k] interleaved complex of the plan's
+ *    precision. The plane waves of k are S_k = {G : |k+G|^2/2 <= E_cut},
+ *    ordered lexicographically on centred Miller indices (m1, m2, m3), m3
+ *    fastest (fde_plan_miller returns the list). Orbitals are
+ *    u(r) = Omega^{-1/2} sum_G c(G) e^{iG.r}; a normalised band has sum|c|^2 = 1.
+ *  - Transform pair: f(G) = (1/N) sum_r f(r) e^{-iG.r}, f(r) = sum_G f(G) e^{iG.r}.
+ *    The density sphere is D = {G : |G|^2 <= 8 E_cut}.
+ *  - Pointers named d_* (and every array argument unless stated "host") are
+ *    device pointers; the caller owns all of them. The library allocates no
+ *    device memory: scratch comes from the workspace the caller attaches with
+ *    fde_plan_set_workspace. The plan owns only host metadata.
+ *  - Every compute call only enqueues work on `stream` and returns. Calls on
+ *    one plan share its workspace and must be ordered (one stream, or
+ *    synchronised streams). Distinct plans are independent. A plan is not
+ *    thread-safe.
+ *  - Errors detectable on the host return a negative fde_status synchronously,
+ *    with a message in fde_last_error() (thread-local). Numerical failures on
+ *    the device are written to a caller-provided device int* info (read after
+ *    a stream synchronisation): 0 = success.
+ *  - Outputs never alias inputs unless stated.
+ */
+#ifndef FDE_H
+#define FDE_H
+
+#include <hip/hip_runtime_api.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int fde_status;
+enum {
+  FDE_OK = 0,
+  FDE_ERR_ARG = -1,         /* invalid argument (null pointer, out-of-range value) */
+  FDE_ERR_SHAPE = -2,       /* sizes inconsistent with the plan or the workspace */
+  FDE_ERR_DEVICE = -3,      /* a HIP runtime call failed */
+  FDE_ERR_UNSUPPORTED = -4, /* grid length or configuration not supported */
+  FDE_ERR_WORKSPACE = -5    /* no (or too small a) workspace attached */
+};
+
+enum { FDE_F64 = 0, FDE_F32 = 1 };
+
+typedef struct fde_plan fde_plan;
+
+/* Thread-local message of the last failing call (never NULL). */
+const char* fde_last_error(void);
+
+/*
+ * Plane-wave plan of one cell, FFT grid, cutoff and k-point list (Sec. 1 and
+ * Sec. 3: plane waves with a k-point mesh).
+ *   L[3]      host, cell lengths (bohr), orthorhombic.
+ *   grid[3]   host, (N1, N2, N3); each a product of 2, 3, 5 and at most 512;
+ *             must satisfy N_i > 4 sqrt(2 E_cut) / b_i (no aliasing of
+ *             orbital products), b_i = 2 pi / L_i.
+ *   ecut_ha   wavefunction kinetic cutoff (Ha).
+ *   kfrac     host [nk][3] reduced k-points (k_i = kfrac_i b_i).
+ *   prec      FDE_F64 or FDE_F32: precision of bands, grids and FFTs.
+ *   out       receives the plan (release with fde_plan_destroy).
+ */
+fde_status fde_plan_create(const double L[3], const int grid[3], double ecut_ha, int nk,
+                           const double* kfrac, int prec, fde_plan** out);
+void fde_plan_destroy(fde_plan* plan);
+
+/* Sizes of k-point ik: plane waves npw and z-sticks ncol (either may be NULL). */
+fde_status fde_plan_info(const fde_plan* plan, int ik, int* npw, int* ncol);
+
+/* host mill[npw][3]: centred Miller indices (m1, m2, m3) of S_k, in band order. */
+fde_status fde_plan_miller(const fde_plan* plan, int ik, int32_t* mill);
+
+/*
+ * Workspace size for calls with at most max_nb bands per call (subspace calls
+ * use m <= 2 max_nb) and at most max_nproj projectors.
+ */
+fde_status fde_plan_workspace_bytes(const fde_plan* plan, int max_nb, int max_nproj, size_t* bytes);
+
+/*
+ * Attach a device workspace of at least fde_plan_workspace_bytes(max_nb,
+ * max_nproj) bytes (256-byte aligned). Uploads the plan's device tables into
+ * it (synchronous). The caller keeps ownership; it must outlive the plan's use.
+ */
+fde_status fde_plan_set_workspace(fde_plan* plan, void* d_ws, size_t bytes, int max_nb, int max_nproj);
+
+/*
+ * H_I |psi_nk> (Eq. KS with the recast V_eff of the Appendix, and the
+ * Kleinman-Bylander projectors of the subsystem's own atoms as in the
+ * Appendix on non-local pseudopotentials):
+ *   hpsi(G) = |k+G|^2/2 psi(G) + [FFT_fwd(V_eff . FFT_inv(psi))](G)
+ *             + sum_i beta_i(G) D_i <beta_i|psi>,    G in S_k.
+ *   ik        k-point index of the plan.
+ *   nb        bands (any number; processed in chunks of the workspace's max_nb).
+ *   psi       [nb][npw] complex, input.   hpsi  [nb][npw] complex, output.
+ *   veff      [N3][N2][N1] real.
+ *   nproj     projectors (0: none; beta and dkb may then be NULL).
+ *   beta      [nproj][npw] complex (from fde_kb_projectors or the caller).
+ *   dkb       [nproj] double, KB energies D_i (Ha).
+ */
+fde_status fde_apply_h(fde_plan* plan, int ik, int nb, const void* psi, void* hpsi, const void* veff,
+                       int nproj, const void* beta, const double* dkb, hipStream_t stream);
+
+/*
+ * Subsystem density (Sec. 2, BZ-integrated density with occupations):
+ *   rho(r) += sum_n occw[n] |u_n(r)|^2,  u = Omega^{-1/2} FFT_inv(psi).
+ *   occw  [nb] double, w_k f_nk (f in [0, 2], sum_k w_k = 1).
+ *   rho   [N3][N2][N1] real, accumulated (+=): sum the k-points into one grid.
+ */
+fde_status fde_density(fde_plan* plan, int ik, int nb, const void* psi, const double* occw, void* rho,
+                       hipStream_t stream);
+
+/* Functional ids for fde_embed_potential. */
+enum { FDE_XC_NONE = 0, FDE_XC_LDA = 1 };            /* Slater + Perdew-Zunger 1981 */
+enum { FDE_KIN_NONE = 0, FDE_KIN_TF = 1, FDE_KIN_LC94 = 2 }; /* Thomas-Fermi x F(s) */
+
+typedef struct fde_functionals {
+  int xc;        /* V_XC[rho_I] of the subsystem                      */
+  int xc_nad;    /* functional of the nonadditive xc term (E~xc)      */
+  int kin_nad;   /* kinetic functional of the nonadditive term (T~)   */
+  double rho_thr;/* below this density a functional contributes zero */
+} fde_functionals;
+
+/* Energy slots per row of fde_embed_potential (rows 0..ns-1: subsystem
+ * densities X = rho_I; row ns: the total density X = rho). */
+enum {
+  FDE_E_XC = 0,     /* E_xc[X]                                  */
+  FDE_E_XCNAD = 1,  /* E~xc[X] (nonadditive functional)         */
+  FDE_E_KIN = 2,    /* T~[X] (kinetic functional)               */
+  FDE_E_LOC = 3,    /* int V_loc X                              */
+  FDE_E_HEMB = 4,   /* int V_H[rho] X                           */
+  FDE_E_HSELF = 5,  /* E_H[X] = 1/2 int V_H[X] X                */
+  FDE_E_DEBAND = 6, /* -int (V_eff^I - V_loc) rho_I (0 in row ns)*/
+  FDE_E_CHARGE = 7, /* int X                                    */
+  FDE_NE = 8
+};
+
+/*
+ * Embedding potentials of all subsystems (Appendix, recast of the effective
+ * potential; Eq. embedding for the nonadditive terms; Appendix, kinetic
+ * energy functional and potential for V~_kin; Sec. 2 for the FFT Poisson
+ * solve of V_H[rho], rho = sum_I rho_I):
+ *   veff[I] = vloc + V_H[rho] + V_xc[rho_I] + (V~xc[rho] - V~xc[rho_I])
+ *             + (V~kin[rho] - V~kin[rho_I])
+ *   rho_sub   [ns][N3][N2][N1] real.      vloc  [N3][N2][N1] real.
+ *   f         host, functional choice and density threshold.
+ *   veff      [ns][N3][N2][N1] real, output.
+ *   energies  device double [ns+1][FDE_NE], output (slots above).
+ *   info      device int, output: 0, or 1 if a non-finite value appeared.
+ */
+fde_status fde_embed_potential(fde_plan* plan, int ns, const void* rho_sub, const void* vloc,
+                               const fde_functionals* f, void* veff, double* energies, int* info,
+                               hipStream_t stream);
+
+/*
+ * Rayleigh-Ritz on V = rows of v [m][npw] with HV in hv [m][npw]
+ * (the solver of Eq. KS; the paper does not describe it):
+ *   S = V^H V, A = V^H HV accumulated in FP64; inactive columns (active[j]
+ *   = 0) and columns j >= nb whose Cholesky pivot falls below drop_tol*S_jj
+ *   are masked (S = e_j, A = 1e6 e_j); S = L L^H; A~ = L^{-1} A L^{-H};
+ *   A~ W = W Theta (FP64 Jacobi, ascending); C = L^{-H} W[:, :nb];
+ *   rows 0..nb-1 of v and hv are overwritten with X = V C and HX = HV C.
+ *   active  [m] uint8 or NULL (all active).
+ *   eval    [nb] double, output Theta[:nb].
+ *   info    device int: 0, j+1 if column j < nb is not positive definite,
+ *           -1 if the eigensolver did not converge.
+ */
+fde_status fde_subspace_rr(fde_plan* plan, int ik, int m, int nb, void* v, void* hv,
+                           const uint8_t* active, double drop_tol, double* eval, int* info,
+                           hipStream_t stream);
+
+/*
+ * Residual and Teter-Payne-Allan preconditioner of the band solver:
+ *   R_n = hx_n - eval_n x_n; rnorm_n = ||R_n||; active_n = rnorm_n > 1e-10;
+ *   t_n = K(x) R_n / ||K(x) R_n||, x = (|k+G|^2/2) / sum_G |k+G|^2/2 |x_nG|^2,
+ *   K(x) = (27+18x+12x^2+8x^3)/(27+18x+12x^2+8x^3+16x^4); t_n = 0 if inactive.
+ *   x, hx, t  [nb][npw] complex (t is output; may be rows of a larger block).
+ *   eval      [nb] double.   active [nb] uint8 out.   rnorm [nb] double out.
+ */
+fde_status fde_precondition(fde_plan* plan, int ik, int nb, const void* x, const void* hx,
+                            const double* eval, void* t, uint8_t* active, double* rnorm,
+                            hipStream_t stream);
+
+enum { FDE_OCC_INTEGER = 0, FDE_OCC_FERMI_DIRAC = 1 };
+
+/*
+ * Occupations of one subsystem (Sec. 2 fractional occupations, Sec. 3 smearing
+ * of metallic subsystems only):
+ *   eval  [nk][nb] double ascending per k.    wk [nk] double, sum 1.
+ *   integer: f = 2 on the lowest nelec/2 bands of every k.
+ *   Fermi-Dirac: f = 1 - tanh((eps - mu)/(2 sigma)), mu by bisection so that
+ *   sum_k wk sum_n f = nelec to 1e-13.
+ *   occw  [nk][nb] double out, w_k f_nk.   mu [1] double out.
+ *   info  device int: 0, or 1 if nelec/2 exceeds nb (integer mode).
+ */
+fde_status fde_occupations(int nk, int nb, const double* eval, const double* wk, double nelec, int mode,
+                           double sigma, double* occw, double* mu, int* info, hipStream_t stream);
+
+/* Linear density mixing rho_in <- (1-beta) rho_in + beta rho_out over n
+ * grid values of precision prec. */
+fde_status fde_mix(size_t n, double beta, void* rho_in, const void* rho_out, int prec, hipStream_t stream);
+
+/*
+ * Local potential of Gaussian ions (the nuclei of all subsystems, Appendix
+ * recast: V_eN groups all nuclei; Sec. 2 E_eN). Ion potential
+ * -Z erf(r/(sqrt(2) s))/r:
+ *   V_loc(G) = (1/Omega) sum_a -4 pi Z_a e^{-G^2 s_a^2/2}/G^2 e^{-iG.R_a} on D,
+ *   V_loc(0) = sum_a 2 pi Z_a s_a^2 / Omega; vloc(r) = FFT_inv.
+ *   pos [natoms][3], Z, width: host double.   vloc [N3][N2][N1] real out.
+ *   Synchronous with respect to the host arrays (they are copied first).
+ */
+fde_status fde_local_potential(fde_plan* plan, int natoms, const double* pos, const double* Z,
+                               const double* width, void* vloc, hipStream_t stream);
+
+/*
+ * Gaussian Kleinman-Bylander projectors at k-point ik (own atoms of a
+ * subsystem, Appendix on non-local pseudopotentials), q = k + G:
+ *   s:   Omega^{-1/2} 2^{3/2} pi^{3/4} r^{3/2} e^{-q^2 r^2/2} e^{-i q.R}
+ *   p_a: Omega^{-1/2} 4 pi^{3/4} r^{5/2} q_a e^{-q^2 r^2/2} e^{-i q.R}, a = x,y,z
+ *   pos [natoms][3], rbeta [natoms] host double; lmax [natoms] host int
+ *   (-1 none, 0 s, 1 s+p). beta [nproj][npw] complex out, channel order per
+ *   atom s, px, py, pz. *nproj (host) receives the count.
+ */
+fde_status fde_kb_projectors(fde_plan* plan, int ik, int natoms, const double* pos, const int* lmax,
+                             const double* rbeta, void* beta, int* nproj, hipStream_t stream);
+
+/* Initial bands: psi[n][G] = raw[n][G] / (1 + |k+G|^2). raw, psi [nb][npw]. */
+fde_status fde_init_bands(fde_plan* plan, int ik, int nb, const void* raw, void* psi, hipStream_t stream);
+
+/*
+ * Band energy terms at k-point ik for occupation weights occw [nb]:
+ *   out[0] += sum_n occw_n sum_G |k+G|^2/2 |psi_nG|^2   (Janak kinetic, Sec. 2)
+ *   out[1] += sum_n occw_n sum_i D_i |<beta_i|psi_n>|^2 (nonlocal energy)
+ *   out: device double [2], accumulated.
+ */
+fde_status fde_band_energies(fde_plan* plan, int ik, int nb, const void* psi, const double* occw,
+                             int nproj, const void* beta, const double* dkb, double* out,
+                             hipStream_t stream);
+
+/* out[0] += sum_j a_j b_j * dV over the plan's grid (a, b real grids). */
+fde_status fde_grid_dot(fde_plan* plan, const void* a, const void* b, double* out, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDE_H */

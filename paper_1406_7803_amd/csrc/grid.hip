@@ -1,0 +1,567 @@
+// Host entry points of the grid kernels: fde_embed_potential,
+// fde_local_potential, fde_mix, fde_grid_dot.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "kernels_grid.hpp"
+#include "launch.hpp"
+
+namespace fde {
+
+static GridGeo geo(const fde_plan* p) {
+  GridGeo g;
+  g.N1 = p->N[0];
+  g.N2 = p->N[1];
+  g.N3 = p->N[2];
+  g.b1 = p->b[0];
+  g.b2 = p->b[1];
+  g.b3 = p->b[2];
+  g.gd2 = 8.0 * p->ecut;
+  g.n = p->npts();
+  return g;
+}
+
+static unsigned red_blocks(size_t n) { return (unsigned)std::min<size_t>(kRedBlocks, (n + kGBlk - 1) / kGBlk); }
+
+// ---------------------------------------------------------------------------
+// Pointwise kernels. All use the grid-stride pattern
+//   for i0 in [bx*256, n) step nblk*256: for l in [tid, 256) step nthr: i = i0 + l
+// and reduce kNQ doubles per block into part[block][kNQ] when part != nullptr.
+// ---------------------------------------------------------------------------
+#define GRID_FOR(c, n, nblk)                                                           \
+  for (size_t i0_ = (size_t)(c).bx() * kGBlk; i0_ < (n); i0_ += (size_t)(nblk) * kGBlk) \
+    for (int l_ = (c).tid(); l_ < kGBlk; l_ += (c).nthr())
+
+// rho = sum_I rho_sub[I]; W = (rho, 0)
+template <typename T>
+struct KSumSub {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char*, const T* __restrict__ sub, int ns, size_t n, T* __restrict__ rho,
+                         unsigned nblk) {
+    GRID_FOR(c, n, nblk) {
+      const size_t i = i0_ + l_;
+      if (i >= n) break;
+      T s = 0;
+      for (int I = 0; I < ns; ++I) s += sub[(size_t)I * n + i];
+      rho[i] = s;
+    }
+  }
+};
+
+template <typename T>
+struct KToComplex {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char*, const T* __restrict__ x, size_t n, cplx<T>* __restrict__ w,
+                         unsigned nblk) {
+    GRID_FOR(c, n, nblk) {
+      const size_t i = i0_ + l_;
+      if (i >= n) break;
+      w[i] = mk<T>(x[i], T(0));
+    }
+  }
+};
+
+// XG <- XG/N on D, 0 outside; optionally H <- 4 pi XG / G^2 (G != 0) for the
+// Hartree potential. q0 = sum_{D, G!=0} 4 pi |XG|^2 / G^2 (self Hartree, x Omega/2).
+template <typename T>
+struct KMaskXG {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, cplx<T>* __restrict__ xg, cplx<T>* __restrict__ h, GridGeo g,
+                         double invN, double* __restrict__ part, unsigned nblk) {
+    const double fpi = 4.0 * 3.14159265358979323846;
+    double acc[kNQ] = {0, 0, 0, 0, 0, 0, 0, 0};
+    GRID_FOR(c, g.n, nblk) {
+      const size_t i = i0_ + l_;
+      if (i >= g.n) break;
+      double gx, gy, gz;
+      grid_g(g, i, gx, gy, gz);
+      const double G2 = gx * gx + gy * gy + gz * gz;
+      const bool inD = G2 <= g.gd2;
+      const cplx<T> v = xg[i];
+      const double vx = inD ? invN * v.x : 0.0, vy = inD ? invN * v.y : 0.0;
+      xg[i] = mk<T>((T)vx, (T)vy);
+      if (inD && G2 > 0) acc[0] += fpi * (vx * vx + vy * vy) / G2;
+      if (h) {
+        const double f = (inD && G2 > 0) ? fpi / G2 : 0.0;
+        h[i] = mk<T>((T)(f * vx), (T)(f * vy));
+      }
+    }
+    block_store(c, (double*)lds, acc, part);
+  }
+};
+
+// W_d = i G_d XG (d = x, y, z)
+template <typename T>
+struct KGradPrep {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char*, const cplx<T>* __restrict__ xg, cplx<T>* __restrict__ w1,
+                         cplx<T>* __restrict__ w2, cplx<T>* __restrict__ w3, GridGeo g, unsigned nblk) {
+    GRID_FOR(c, g.n, nblk) {
+      const size_t i = i0_ + l_;
+      if (i >= g.n) break;
+      double gx, gy, gz;
+      grid_g(g, i, gx, gy, gz);
+      const cplx<T> v = xg[i];
+      w1[i] = mk<T>((T)(-gx * v.y), (T)(gx * v.x));
+      w2[i] = mk<T>((T)(-gy * v.y), (T)(gy * v.x));
+      w3[i] = mk<T>((T)(-gz * v.y), (T)(gz * v.x));
+    }
+  }
+};
+
+// Kinetic functional at each point. kind 1: Thomas-Fermi, 2: TF x LC94.
+// In:  X, and for kind 2 the gradient in Re(W_d). Out: v (local part
+// dG/drho), and for kind 2 the field h_d = C_TF C_s^2 (F'/s) grad_d X / X in W_d.
+// q0 = sum of the energy density C_TF X^{5/3} F(s).
+template <typename T>
+struct KKedfPoint {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const T* __restrict__ X, cplx<T>* __restrict__ w1,
+                         cplx<T>* __restrict__ w2, cplx<T>* __restrict__ w3, T* __restrict__ v, size_t n, int kind,
+                         KinConst k, double thr, double* __restrict__ part, unsigned nblk) {
+    double acc[kNQ] = {0, 0, 0, 0, 0, 0, 0, 0};
+    GRID_FOR(c, n, nblk) {
+      const size_t i = i0_ + l_;
+      if (i >= n) break;
+      const double x = X[i];
+      if (!(x >= thr)) {
+        v[i] = T(0);
+        if (kind == 2) {
+          w1[i] = mk<T>(0, 0);
+          w2[i] = mk<T>(0, 0);
+          w3[i] = mk<T>(0, 0);
+        }
+        continue;
+      }
+      const double x13 = cbrt(x);
+      const double x23 = x13 * x13;
+      const double x53 = x * x23;
+      if (kind == 1) {
+        acc[0] += k.ctf * x53;
+        v[i] = (T)(k.ctf * (5.0 / 3.0) * x23);
+        continue;
+      }
+      const double dx = w1[i].x, dy = w2[i].x, dz = w3[i].x;
+      const double gabs = sqrt(dx * dx + dy * dy + dz * dz);
+      const double s = k.cs * gabs / (x * x13);
+      double F, dFs;
+      lc94(s, F, dFs);
+      acc[0] += k.ctf * x53 * F;
+      v[i] = (T)(k.ctf * x23 * ((5.0 / 3.0) * F - (4.0 / 3.0) * s * s * dFs));
+      const double hf = k.ctf * k.cs * k.cs * dFs / x;
+      w1[i] = mk<T>((T)(hf * dx), T(0));
+      w2[i] = mk<T>((T)(hf * dy), T(0));
+      w3[i] = mk<T>((T)(hf * dz), T(0));
+    }
+    block_store(c, (double*)lds, acc, part);
+  }
+};
+
+// W0 = (1/N) sum_d i G_d W_d on D (the divergence in reciprocal space)
+template <typename T>
+struct KDivPrep {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char*, cplx<T>* __restrict__ w0, const cplx<T>* __restrict__ w1,
+                         const cplx<T>* __restrict__ w2, const cplx<T>* __restrict__ w3, GridGeo g, double invN,
+                         unsigned nblk) {
+    GRID_FOR(c, g.n, nblk) {
+      const size_t i = i0_ + l_;
+      if (i >= g.n) break;
+      double gx, gy, gz;
+      grid_g(g, i, gx, gy, gz);
+      const bool inD = gx * gx + gy * gy + gz * gz <= g.gd2;
+      const cplx<T> a = w1[i], b = w2[i], d = w3[i];
+      const double re = -(gx * a.y + gy * b.y + gz * d.y);
+      const double im = gx * a.x + gy * b.x + gz * d.x;
+      w0[i] = inD ? mk<T>((T)(invN * re), (T)(invN * im)) : mk<T>(0, 0);
+    }
+  }
+};
+
+// v <- v - Re(W0)
+template <typename T>
+struct KKinFinish {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char*, T* __restrict__ v, const cplx<T>* __restrict__ w0, size_t n,
+                         unsigned nblk) {
+    GRID_FOR(c, n, nblk) {
+      const size_t i = i0_ + l_;
+      if (i >= n) break;
+      v[i] = v[i] - w0[i].x;
+    }
+  }
+};
+
+// out = Re(W)
+template <typename T>
+struct KRealPart {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char*, const cplx<T>* __restrict__ w, T* __restrict__ out, size_t n,
+                         unsigned nblk) {
+    GRID_FOR(c, n, nblk) {
+      const size_t i = i0_ + l_;
+      if (i >= n) break;
+      out[i] = w[i].x;
+    }
+  }
+};
+
+FDE_HD void xc_point(int kind, double rho, double thr, double& e, double& v) {
+  e = 0.0;
+  v = 0.0;
+  if (kind == FDE_XC_LDA && rho >= thr) lda_point(rho, e, v);
+}
+
+// Total density: vxt = V~xc[rho]. q0 = E~xc[rho], q1 = E_xc[rho], q3 = int vloc rho,
+// q4 = int V_H rho, q7 = int rho (sums; scaled by dV later).
+template <typename T>
+struct KXcTotal {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const T* __restrict__ rho, const T* __restrict__ vloc,
+                         const T* __restrict__ vh, T* __restrict__ vxt, size_t n, int xc, int xc_nad, double thr,
+                         double* __restrict__ part, unsigned nblk) {
+    double acc[kNQ] = {0, 0, 0, 0, 0, 0, 0, 0};
+    GRID_FOR(c, n, nblk) {
+      const size_t i = i0_ + l_;
+      if (i >= n) break;
+      const double r = rho[i];
+      double e, v, e2, v2;
+      xc_point(xc_nad, r, thr, e, v);
+      xc_point(xc, r, thr, e2, v2);
+      vxt[i] = (T)v;
+      acc[0] += e;
+      acc[1] += e2;
+      acc[3] += (double)vloc[i] * r;
+      acc[4] += (double)vh[i] * r;
+      acc[7] += r;
+    }
+    block_store(c, (double*)lds, acc, part);
+  }
+};
+
+// Subsystem assembly (recast effective potential):
+//   veff = vloc + V_H + v_xc[rho_I] + (V~xc[rho] - v~xc[rho_I]) + (V~kin[rho] - vk_I)
+// where vk_I is read from veff on entry. q0 = E_xc[rho_I], q1 = E~xc[rho_I],
+// q3 = int vloc rho_I, q4 = int V_H rho_I, q6 = -int (veff - vloc) rho_I, q7 = int rho_I.
+template <typename T>
+struct KAssemble {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const T* __restrict__ rhoI, const T* __restrict__ vloc,
+                         const T* __restrict__ vh, const T* __restrict__ vxt, const T* __restrict__ vkt,
+                         T* __restrict__ veff, size_t n, int xc, int xc_nad, double thr, double* __restrict__ part,
+                         int* __restrict__ info, unsigned nblk) {
+    double acc[kNQ] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int bad = 0;
+    GRID_FOR(c, n, nblk) {
+      const size_t i = i0_ + l_;
+      if (i >= n) break;
+      const double r = rhoI[i];
+      double e, v, et, vt;
+      xc_point(xc, r, thr, e, v);
+      xc_point(xc_nad, r, thr, et, vt);
+      const double vl = vloc[i];
+      const double out = vl + (double)vh[i] + v + ((double)vxt[i] - vt) + ((double)vkt[i] - (double)veff[i]);
+      const T o = (T)out;
+      veff[i] = o;
+      if (!(out == out) || out > 1e300 || out < -1e300) bad = 1;
+      acc[0] += e;
+      acc[1] += et;
+      acc[3] += vl * r;
+      acc[4] += (double)vh[i] * r;
+      acc[6] -= ((double)o - vl) * r;
+      acc[7] += r;
+    }
+    if (bad) info[0] = 1;
+    block_store(c, (double*)lds, acc, part);
+  }
+};
+
+template <typename T>
+static fde_status fft3(fde_plan* p, cplx<T>* w, bool inv, hipStream_t s) {
+  const int N1 = p->N[0], N2 = p->N[1], N3 = p->N[2];
+  for (int axis = 0; axis < 3; ++axis) {
+    const int n = p->N[axis];
+    int L = 16;
+    while (L > 1 && (2 * (size_t)L * n + n) * sizeof(cplx<T>) > 64 * 1024) L /= 2;
+    const size_t lds = (2 * (size_t)L * n + n) * sizeof(cplx<T>);
+    dim3 grid;
+    if (axis == 0) grid = dim3((N2 * N3 + L - 1) / L);
+    else grid = dim3((N1 + L - 1) / L, axis == 1 ? N3 : N2);
+    const cplx<T>* tw = (const cplx<T>*)p->d_tw[axis];
+    if (inv) FDE_TRY(launch<KFftAxis<T, true>>(grid, kBlock, lds, s, w, N1, N2, N3, axis, p->rad[axis], tw, L));
+    else FDE_TRY(launch<KFftAxis<T, false>>(grid, kBlock, lds, s, w, N1, N2, N3, axis, p->rad[axis], tw, L));
+  }
+  return FDE_OK;
+}
+
+template <typename T>
+struct EmbedWs {
+  cplx<T>*W0, *W1, *W2, *W3;
+  T *rho, *vh, *vxt, *vkt;
+  double* part;  // [kRedBlocks][kNQ]
+};
+
+template <typename T>
+static EmbedWs<T> embed_ws(fde_plan* p) {
+  EmbedWs<T> e;
+  const size_t n = p->npts();
+  char* w = p->scratch;
+  size_t off = 0;
+  cplx<T>** cg[4] = {&e.W0, &e.W1, &e.W2, &e.W3};
+  for (int i = 0; i < 4; ++i) {
+    *cg[i] = (cplx<T>*)(w + off);
+    off += align256(n * sizeof(cplx<T>));
+  }
+  T** rg[4] = {&e.rho, &e.vh, &e.vxt, &e.vkt};
+  for (int i = 0; i < 4; ++i) {
+    *rg[i] = (T*)(w + off);
+    off += align256(n * sizeof(T));
+  }
+  e.part = (double*)(w + off);
+  return e;
+}
+
+// Kinetic potential of density X into vout; writes T~[X] and, from the
+// transformed density, E_H[X] into the energy row. If vh != nullptr also
+// returns V_H[X] (used for the total density).
+template <typename T>
+static fde_status kinetic_and_hartree(fde_plan* p, EmbedWs<T>& e, const T* X, T* vout, const fde_functionals* f,
+                                      T* vh, double* erow, hipStream_t s) {
+  const GridGeo g = geo(p);
+  const size_t n = g.n;
+  const unsigned nb = red_blocks(n);
+  const double invN = 1.0 / (double)n;
+  const double dV = p->omega / (double)n;
+  const KinConst kc = {0.3 * std::pow(3.0 * M_PI * M_PI, 2.0 / 3.0), 1.0 / (2.0 * std::cbrt(3.0 * M_PI * M_PI))};
+  const size_t red = 17 * sizeof(double);
+  // X(G) on D, self Hartree energy, optional V_H
+  FDE_TRY(launch<KToComplex<T>>(dim3(nb), kBlock, 0, s, X, n, e.W0, nb));
+  FDE_TRY(fft3<T>(p, e.W0, false, s));
+  FDE_TRY(launch<KMaskXG<T>>(dim3(nb), kBlock, red, s, e.W0, vh ? e.W1 : (cplx<T>*)nullptr, g, invN, e.part, nb));
+  FDE_TRY(launch<KRedFinal>(dim3(1), kBlock, red, s, (const double*)e.part, (int)nb, 0.5 * p->omega, erow,
+                            (int)FDE_E_HSELF, -1, -1, -1, -1, -1, -1, -1));
+  if (vh) {
+    FDE_TRY(fft3<T>(p, e.W1, true, s));
+    FDE_TRY(launch<KRealPart<T>>(dim3(nb), kBlock, 0, s, (const cplx<T>*)e.W1, vh, n, nb));
+  }
+  if (f->kin_nad == FDE_KIN_NONE) {
+    FDE_TRY(zero_bytes(vout, n * sizeof(T), s));
+    FDE_TRY(zero_bytes(erow + FDE_E_KIN, sizeof(double), s));
+    return FDE_OK;
+  }
+  if (f->kin_nad == FDE_KIN_TF) {
+    FDE_TRY(launch<KKedfPoint<T>>(dim3(nb), kBlock, red, s, X, e.W1, e.W2, e.W3, vout, n, 1, kc, f->rho_thr, e.part,
+                                  nb));
+    FDE_TRY(launch<KRedFinal>(dim3(1), kBlock, red, s, (const double*)e.part, (int)nb, dV, erow, (int)FDE_E_KIN, -1,
+                              -1, -1, -1, -1, -1, -1));
+    return FDE_OK;
+  }
+  // gradient
+  FDE_TRY(launch<KGradPrep<T>>(dim3(nb), kBlock, 0, s, (const cplx<T>*)e.W0, e.W1, e.W2, e.W3, g, nb));
+  FDE_TRY(fft3<T>(p, e.W1, true, s));
+  FDE_TRY(fft3<T>(p, e.W2, true, s));
+  FDE_TRY(fft3<T>(p, e.W3, true, s));
+  FDE_TRY(launch<KKedfPoint<T>>(dim3(nb), kBlock, red, s, X, e.W1, e.W2, e.W3, vout, n, 2, kc, f->rho_thr, e.part,
+                                nb));
+  FDE_TRY(launch<KRedFinal>(dim3(1), kBlock, red, s, (const double*)e.part, (int)nb, dV, erow, (int)FDE_E_KIN, -1, -1,
+                            -1, -1, -1, -1, -1));
+  // divergence of h
+  FDE_TRY(fft3<T>(p, e.W1, false, s));
+  FDE_TRY(fft3<T>(p, e.W2, false, s));
+  FDE_TRY(fft3<T>(p, e.W3, false, s));
+  FDE_TRY(launch<KDivPrep<T>>(dim3(nb), kBlock, 0, s, e.W0, (const cplx<T>*)e.W1, (const cplx<T>*)e.W2,
+                              (const cplx<T>*)e.W3, g, invN, nb));
+  FDE_TRY(fft3<T>(p, e.W0, true, s));
+  FDE_TRY(launch<KKinFinish<T>>(dim3(nb), kBlock, 0, s, vout, (const cplx<T>*)e.W0, n, nb));
+  return FDE_OK;
+}
+
+template <typename T>
+static fde_status embed_t(fde_plan* p, int ns, const T* rho_sub, const T* vloc, const fde_functionals* f, T* veff,
+                          double* en, int* info, hipStream_t s) {
+  EmbedWs<T> e = embed_ws<T>(p);
+  const size_t n = p->npts();
+  const unsigned nb = red_blocks(n);
+  const double dV = p->omega / (double)n;
+  const size_t red = 17 * sizeof(double);
+  FDE_TRY(zero_bytes(info, sizeof(int), s));
+  FDE_TRY(zero_bytes(en, (size_t)(ns + 1) * FDE_NE * sizeof(double), s));
+  FDE_TRY(launch<KSumSub<T>>(dim3(nb), kBlock, 0, s, rho_sub, ns, n, e.rho, nb));
+  double* etot = en + (size_t)ns * FDE_NE;
+  FDE_TRY(kinetic_and_hartree<T>(p, e, e.rho, e.vkt, f, e.vh, etot, s));
+  FDE_TRY(launch<KXcTotal<T>>(dim3(nb), kBlock, red, s, (const T*)e.rho, vloc, (const T*)e.vh, e.vxt, n, f->xc,
+                              f->xc_nad, f->rho_thr, e.part, nb));
+  FDE_TRY(launch<KRedFinal>(dim3(1), kBlock, red, s, (const double*)e.part, (int)nb, dV, etot, (int)FDE_E_XCNAD,
+                            (int)FDE_E_XC, -1, (int)FDE_E_LOC, (int)FDE_E_HEMB, -1, -1, (int)FDE_E_CHARGE));
+  for (int I = 0; I < ns; ++I) {
+    const T* rI = rho_sub + (size_t)I * n;
+    T* vI = veff + (size_t)I * n;
+    double* erow = en + (size_t)I * FDE_NE;
+    FDE_TRY(kinetic_and_hartree<T>(p, e, rI, vI, f, (T*)nullptr, erow, s));
+    FDE_TRY(launch<KAssemble<T>>(dim3(nb), kBlock, red, s, rI, vloc, (const T*)e.vh, (const T*)e.vxt,
+                                 (const T*)e.vkt, vI, n, f->xc, f->xc_nad, f->rho_thr, e.part, info, nb));
+    FDE_TRY(launch<KRedFinal>(dim3(1), kBlock, red, s, (const double*)e.part, (int)nb, dV, erow, (int)FDE_E_XC,
+                              (int)FDE_E_XCNAD, -1, (int)FDE_E_LOC, (int)FDE_E_HEMB, -1, (int)FDE_E_DEBAND,
+                              (int)FDE_E_CHARGE));
+  }
+  return FDE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Local potential of Gaussian ions
+// ---------------------------------------------------------------------------
+struct Ion {
+  double R[3];
+  double Z, w;
+};
+
+template <typename T>
+struct KVlocG {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char*, const Ion* __restrict__ ions, int nion, GridGeo g, double omega,
+                         cplx<T>* __restrict__ w, unsigned nblk) {
+    const double pi = 3.14159265358979323846;
+    GRID_FOR(c, g.n, nblk) {
+      const size_t i = i0_ + l_;
+      if (i >= g.n) break;
+      double gx, gy, gz;
+      grid_g(g, i, gx, gy, gz);
+      const double G2 = gx * gx + gy * gy + gz * gz;
+      double re = 0.0, im = 0.0;
+      if (G2 <= g.gd2) {
+        for (int a = 0; a < nion; ++a) {
+          const Ion at = ions[a];
+          if (G2 > 0) {
+            const double amp = -4.0 * pi * at.Z * exp(-0.5 * G2 * at.w * at.w) / G2;
+            const double ph = -(gx * at.R[0] + gy * at.R[1] + gz * at.R[2]);
+            re += amp * cos(ph);
+            im += amp * sin(ph);
+          } else {
+            re += 2.0 * pi * at.Z * at.w * at.w;
+          }
+        }
+      }
+      w[i] = mk<T>((T)(re / omega), (T)(im / omega));
+    }
+  }
+};
+
+template <typename T>
+static fde_status vloc_t(fde_plan* p, const std::vector<Ion>& ions, T* vloc, hipStream_t s) {
+  EmbedWs<T> e = embed_ws<T>(p);
+  const size_t n = p->npts();
+  const unsigned nb = red_blocks(n);
+  Ion* d_ions = (Ion*)e.W1;  // staged in a work grid (synchronous copy)
+  FDE_TRY(stream_sync(s));
+  FDE_TRY(copy_h2d_sync(d_ions, ions.data(), ions.size() * sizeof(Ion)));
+  FDE_TRY(launch<KVlocG<T>>(dim3(nb), kBlock, 0, s, (const Ion*)d_ions, (int)ions.size(), geo(p), p->omega, e.W0, nb));
+  FDE_TRY(fft3<T>(p, e.W0, true, s));
+  FDE_TRY(launch<KRealPart<T>>(dim3(nb), kBlock, 0, s, (const cplx<T>*)e.W0, vloc, n, nb));
+  return FDE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Mixing and grid dot product
+// ---------------------------------------------------------------------------
+template <typename T>
+struct KMix {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char*, T* __restrict__ a, const T* __restrict__ b, size_t n, double beta,
+                         unsigned nblk) {
+    GRID_FOR(c, n, nblk) {
+      const size_t i = i0_ + l_;
+      if (i >= n) break;
+      a[i] = (T)((1.0 - beta) * (double)a[i] + beta * (double)b[i]);
+    }
+  }
+};
+
+template <typename T>
+struct KDot {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const T* __restrict__ a, const T* __restrict__ b, size_t n,
+                         double* __restrict__ part, unsigned nblk) {
+    double acc[kNQ] = {0, 0, 0, 0, 0, 0, 0, 0};
+    GRID_FOR(c, n, nblk) {
+      const size_t i = i0_ + l_;
+      if (i >= n) break;
+      acc[0] += (double)a[i] * (double)b[i];
+    }
+    block_store(c, (double*)lds, acc, part);
+  }
+};
+
+// out[0] += scale * sum part[b][0]
+struct KRedAdd {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const double* __restrict__ part, int nblk, double scale,
+                         double* __restrict__ out) {
+    double acc = 0.0;
+    for (int b = c.tid(); b < nblk; b += c.nthr()) acc += part[(size_t)b * kNQ];
+    acc = c.sum(acc, (double*)lds);
+    if (c.tid() == 0) out[0] += scale * acc;
+  }
+};
+
+}  // namespace fde
+
+using namespace fde;
+
+extern "C" {
+
+fde_status fde_embed_potential(fde_plan* p, int ns, const void* rho_sub, const void* vloc, const fde_functionals* f,
+                               void* veff, double* energies, int* info, hipStream_t s) {
+  if (!p) return fail(FDE_ERR_ARG, "null plan");
+  if (!p->ws) return fail(FDE_ERR_WORKSPACE, "no workspace attached (fde_plan_set_workspace)");
+  if (ns < 1) return fail(FDE_ERR_ARG, "ns must be >= 1");
+  if (!rho_sub || !vloc || !f || !veff || !energies || !info) return fail(FDE_ERR_ARG, "null argument");
+  if (f->xc < 0 || f->xc > 1 || f->xc_nad < 0 || f->xc_nad > 1 || f->kin_nad < 0 || f->kin_nad > 2)
+    return fail(FDE_ERR_ARG, "unknown functional id");
+  if (!(f->rho_thr >= 0)) return fail(FDE_ERR_ARG, "rho_thr must be >= 0");
+  if (p->prec == FDE_F64)
+    return embed_t<double>(p, ns, (const double*)rho_sub, (const double*)vloc, f, (double*)veff, energies, info, s);
+  return embed_t<float>(p, ns, (const float*)rho_sub, (const float*)vloc, f, (float*)veff, energies, info, s);
+}
+
+fde_status fde_local_potential(fde_plan* p, int natoms, const double* pos, const double* Z, const double* width,
+                               void* vloc, hipStream_t s) {
+  if (!p) return fail(FDE_ERR_ARG, "null plan");
+  if (!p->ws) return fail(FDE_ERR_WORKSPACE, "no workspace attached (fde_plan_set_workspace)");
+  if (natoms < 0 || (natoms > 0 && (!pos || !Z || !width)) || !vloc) return fail(FDE_ERR_ARG, "null argument");
+  if ((size_t)natoms * sizeof(Ion) > p->npts() * p->csize()) return fail(FDE_ERR_SHAPE, "too many atoms for the grid");
+  std::vector<Ion> ions(natoms);
+  for (int a = 0; a < natoms; ++a) {
+    for (int i = 0; i < 3; ++i) ions[a].R[i] = pos[3 * a + i];
+    ions[a].Z = Z[a];
+    ions[a].w = width[a];
+  }
+  if (p->prec == FDE_F64) return vloc_t<double>(p, ions, (double*)vloc, s);
+  return vloc_t<float>(p, ions, (float*)vloc, s);
+}
+
+fde_status fde_mix(size_t n, double beta, void* rho_in, const void* rho_out, int prec, hipStream_t s) {
+  if (!rho_in || !rho_out) return fail(FDE_ERR_ARG, "null argument");
+  if (prec != FDE_F64 && prec != FDE_F32) return fail(FDE_ERR_ARG, "prec must be FDE_F64 or FDE_F32");
+  const unsigned nb = red_blocks(n);
+  if (n == 0) return FDE_OK;
+  if (prec == FDE_F64) return launch<KMix<double>>(dim3(nb), kBlock, 0, s, (double*)rho_in, (const double*)rho_out, n, beta, nb);
+  return launch<KMix<float>>(dim3(nb), kBlock, 0, s, (float*)rho_in, (const float*)rho_out, n, beta, nb);
+}
+
+fde_status fde_grid_dot(fde_plan* p, const void* a, const void* b, double* out, hipStream_t s) {
+  if (!p) return fail(FDE_ERR_ARG, "null plan");
+  if (!p->ws) return fail(FDE_ERR_WORKSPACE, "no workspace attached (fde_plan_set_workspace)");
+  if (!a || !b || !out) return fail(FDE_ERR_ARG, "null argument");
+  const size_t n = p->npts();
+  const unsigned nb = red_blocks(n);
+  double* part = (double*)p->scratch;
+  const size_t red = 17 * sizeof(double);
+  if (p->prec == FDE_F64)
+    FDE_TRY(launch<KDot<double>>(dim3(nb), kBlock, red, s, (const double*)a, (const double*)b, n, part, nb));
+  else
+    FDE_TRY(launch<KDot<float>>(dim3(nb), kBlock, red, s, (const float*)a, (const float*)b, n, part, nb));
+  return launch<KRedAdd>(dim3(1), kBlock, red, s, (const double*)part, (int)nb, p->omega / (double)n, out);
+}
+
+}  // extern "C"

@@ -1,0 +1,381 @@
+// Plane-wave kernels: the H|psi> FFT sandwich, the density, and the
+// Kleinman-Bylander projector products.
+//
+// Data flow of one band-apply (Eq. KS; coefficients on the sphere S_k):
+//   psi [nb][npw] --KZInv--> sticks [nb][N3][ncol] (inverse z-FFT of each
+//   z-stick of the sphere) --KPlaneH--> same layout (per z-plane: inverse y-FFT
+//   on the active x-columns, inverse x-FFT per row, times V_eff, forward x-FFT,
+//   forward y-FFT, keep the sticks) --KZFwd--> hpsi [nb][npw] (forward z-FFT,
+//   1/N, plus |k+G|^2/2 psi).
+// The sticks buffer holds, for every z-plane, the ncol sticks contiguously so
+// both the z-passes and the plane pass read and write it coalesced.
+#pragma once
+
+#include "common.hpp"
+
+namespace fde {
+
+constexpr int kBlk = 256;  // nominal threads per block of element-wise kernels
+
+struct KVec {
+  double kf[3];
+  double b[3];
+};
+
+// |k+G|^2 / 2 for G = (m1, m2, m3), evaluated exactly as the plan's sphere test.
+FDE_HD double kin_of(const KVec& k, int m1, int m2, int m3) {
+  const double q1 = (m1 + k.kf[0]) * k.b[0];
+  const double q2 = (m2 + k.kf[1]) * k.b[1];
+  const double q3 = (m3 + k.kf[2]) * k.b[2];
+  return 0.5 * (q1 * q1 + q2 * q2 + q3 * q3);
+}
+
+FDE_HD void unpack_mill(int p, int& m1, int& m2, int& m3) {
+  m1 = (p & 1023) - 512;
+  m2 = ((p >> 10) & 1023) - 512;
+  m3 = ((p >> 20) & 1023) - 512;
+}
+
+// ---------------------------------------------------------------------------
+// Inverse z-FFT of SZ sticks of one band: grid (ceil(ncol/SZ), nb).
+// LDS: 2*N3*SZ + N3 complex.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct KZInv {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const cplx<T>* __restrict__ psi, int npw,
+                         const int4* __restrict__ sticks, int ncol, Radix r3, const cplx<T>* __restrict__ tw,
+                         cplx<T>* __restrict__ sb, int SZ) {
+    const int N3 = r3.n;
+    const int c0 = c.bx() * SZ;
+    const int band = c.by();
+    const int nsz = (ncol - c0) < SZ ? (ncol - c0) : SZ;
+    cplx<T>* a = (cplx<T>*)lds;
+    cplx<T>* b = a + N3 * SZ;
+    cplx<T>* twl = b + N3 * SZ;
+    for (int i = c.tid(); i < N3; i += c.nthr()) twl[i] = tw[i];
+    for (int i = c.tid(); i < N3 * SZ; i += c.nthr()) a[i] = mk<T>(0, 0);
+    c.sync();
+    const cplx<T>* pb = psi + (size_t)band * npw;
+    for (int idx = c.tid(); idx < SZ * N3; idx += c.nthr()) {
+      const int s = idx / N3, t = idx - s * N3;
+      if (s < nsz) {
+        const int4 st = sticks[c0 + s];
+        if (t < st.y) a[imod(st.z + t, N3) * SZ + s] = pb[st.x + t];
+      }
+    }
+    c.sync();
+    cplx<T>* r = lds_fft<T, true>(c, a, b, SZ, 1, SZ, r3, twl);
+    cplx<T>* ob = sb + (size_t)band * N3 * ncol;
+    for (int idx = c.tid(); idx < N3 * SZ; idx += c.nthr()) {
+      const int z = idx / SZ, s = idx - z * SZ;
+      if (s < nsz) ob[(size_t)z * ncol + c0 + s] = r[z * SZ + s];
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Forward z-FFT of SZ sticks, gather of the sphere, 1/N and kinetic term:
+//   hpsi(G) = (1/N) FFT_z(...)(G) + |k+G|^2/2 psi(G).   grid (ceil(ncol/SZ), nb)
+// ---------------------------------------------------------------------------
+template <typename T>
+struct KZFwd {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const cplx<T>* __restrict__ sb, const cplx<T>* __restrict__ psi,
+                         cplx<T>* __restrict__ hpsi, int npw, const int4* __restrict__ sticks,
+                         const int* __restrict__ xlist, int ncol, int N1, int N2, Radix r3,
+                         const cplx<T>* __restrict__ tw, KVec kv, double invN, int SZ) {
+    const int N3 = r3.n;
+    const int c0 = c.bx() * SZ;
+    const int band = c.by();
+    const int nsz = (ncol - c0) < SZ ? (ncol - c0) : SZ;
+    cplx<T>* a = (cplx<T>*)lds;
+    cplx<T>* b = a + N3 * SZ;
+    cplx<T>* twl = b + N3 * SZ;
+    for (int i = c.tid(); i < N3; i += c.nthr()) twl[i] = tw[i];
+    const cplx<T>* ib = sb + (size_t)band * N3 * ncol;
+    for (int idx = c.tid(); idx < N3 * SZ; idx += c.nthr()) {
+      const int z = idx / SZ, s = idx - z * SZ;
+      a[idx] = s < nsz ? ib[(size_t)z * ncol + c0 + s] : mk<T>(0, 0);
+    }
+    c.sync();
+    cplx<T>* r = lds_fft<T, false>(c, a, b, SZ, 1, SZ, r3, twl);
+    const cplx<T>* pb = psi + (size_t)band * npw;
+    cplx<T>* hb = hpsi + (size_t)band * npw;
+    for (int idx = c.tid(); idx < SZ * N3; idx += c.nthr()) {
+      const int s = idx / N3, t = idx - s * N3;
+      if (s < nsz) {
+        const int4 st = sticks[c0 + s];
+        if (t < st.y) {
+          const int g = st.x + t;
+          const int m1 = centred(xlist[st.w & 0xffff], N1);
+          const int m2 = centred(st.w >> 16, N2);
+          const T kin = (T)kin_of(kv, m1, m2, st.z + t);
+          const cplx<T> v = r[imod(st.z + t, N3) * SZ + s];
+          const cplx<T> p = pb[g];
+          hb[g] = mk<T>((T)invN * v.x + kin * p.x, (T)invN * v.y + kin * p.y);
+        }
+      }
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Plane pass, shared by H application and density. Layout in LDS:
+//   P0, P1 : [N2][nxa]   the active x-columns of the plane (ping-pong)
+//   R0, R1 : [RB][N1]    a batch of full rows (ping-pong)
+//   tw1[N1], tw2[N2], stk[ncol] (packed xa | iy << 16)
+// ---------------------------------------------------------------------------
+template <typename T>
+struct PlaneLds {
+  cplx<T>*P0, *P1, *R0, *R1, *tw1, *tw2;
+  int* stk;
+  T* acc;  // density accumulator [N2][N1] (density pass only)
+  FDE_HD static size_t bytes(int N1, int N2, int nxa, int RB, int ncol, bool with_acc) {
+    size_t s = sizeof(cplx<T>) * ((size_t)2 * N2 * nxa + (size_t)2 * RB * N1 + N1 + N2);
+    s += sizeof(int) * (size_t)ncol;
+    s = (s + 15) & ~(size_t)15;
+    if (with_acc) s += sizeof(T) * (size_t)N1 * N2;
+    return s;
+  }
+  FDE_HD PlaneLds(char* lds, int N1, int N2, int nxa, int RB, int ncol) {
+    P0 = (cplx<T>*)lds;
+    P1 = P0 + (size_t)N2 * nxa;
+    R0 = P1 + (size_t)N2 * nxa;
+    R1 = R0 + (size_t)RB * N1;
+    tw1 = R1 + (size_t)RB * N1;
+    tw2 = tw1 + N1;
+    stk = (int*)(tw2 + N2);
+    size_t off = sizeof(cplx<T>) * ((size_t)2 * N2 * nxa + (size_t)2 * RB * N1 + N1 + N2) + sizeof(int) * (size_t)ncol;
+    off = (off + 15) & ~(size_t)15;
+    acc = (T*)(lds + off);
+  }
+};
+
+template <typename T, class Ctx>
+FDE_HD void plane_load_tables(const Ctx& c, PlaneLds<T>& L, const int4* __restrict__ sticks, int ncol,
+                              const cplx<T>* __restrict__ tw1, const cplx<T>* __restrict__ tw2, int N1, int N2) {
+  for (int i = c.tid(); i < N1; i += c.nthr()) L.tw1[i] = tw1[i];
+  for (int i = c.tid(); i < N2; i += c.nthr()) L.tw2[i] = tw2[i];
+  for (int i = c.tid(); i < ncol; i += c.nthr()) L.stk[i] = sticks[i].w;
+}
+
+// Scatter the ncol sticks of one plane into P0 (zeroed first); inverse y-FFT
+// of the nxa active columns. Returns the buffer holding the result.
+template <typename T, class Ctx>
+FDE_HD cplx<T>* plane_inverse_y(const Ctx& c, PlaneLds<T>& L, const cplx<T>* __restrict__ row, int ncol, int nxa,
+                                Radix r2) {
+  const int N2 = r2.n;
+  for (int i = c.tid(); i < N2 * nxa; i += c.nthr()) L.P0[i] = mk<T>(0, 0);
+  c.sync();
+  for (int i = c.tid(); i < ncol; i += c.nthr()) {
+    const int w = L.stk[i];
+    L.P0[(w >> 16) * nxa + (w & 0xffff)] = row[i];
+  }
+  c.sync();
+  return lds_fft<T, true>(c, L.P0, L.P1, nxa, 1, nxa, r2, L.tw2);
+}
+
+template <typename T>
+struct KPlaneH {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, cplx<T>* __restrict__ sb, int nbands, int BPW,
+                         const int4* __restrict__ sticks, const int* __restrict__ xlist, int ncol, int nxa,
+                         Radix r1, Radix r2, int N3, const cplx<T>* __restrict__ tw1,
+                         const cplx<T>* __restrict__ tw2, const T* __restrict__ veff, int RB) {
+    const int N1 = r1.n, N2 = r2.n;
+    const int z = c.bx();
+    PlaneLds<T> L(lds, N1, N2, nxa, RB, ncol);
+    plane_load_tables<T>(c, L, sticks, ncol, tw1, tw2, N1, N2);
+    c.sync();
+    const T* vz = veff + (size_t)z * N1 * N2;
+    const int b0 = c.by() * BPW;
+    for (int band = b0; band < b0 + BPW && band < nbands; ++band) {
+      cplx<T>* row = sb + ((size_t)band * N3 + z) * ncol;
+      cplx<T>* P = plane_inverse_y<T>(c, L, row, ncol, nxa, r2);
+      for (int y0 = 0; y0 < N2; y0 += RB) {
+        const int rb = (N2 - y0) < RB ? (N2 - y0) : RB;
+        for (int i = c.tid(); i < rb * N1; i += c.nthr()) L.R0[i] = mk<T>(0, 0);
+        c.sync();
+        for (int i = c.tid(); i < rb * nxa; i += c.nthr()) {
+          const int r = i / nxa, xa = i - r * nxa;
+          L.R0[r * N1 + xlist[xa]] = P[(y0 + r) * nxa + xa];
+        }
+        c.sync();
+        cplx<T>* R = lds_fft<T, true>(c, L.R0, L.R1, rb, N1, 1, r1, L.tw1);
+        for (int i = c.tid(); i < rb * N1; i += c.nthr()) {
+          const T v = vz[(size_t)y0 * N1 + i];
+          R[i] = mk<T>(v * R[i].x, v * R[i].y);
+        }
+        c.sync();
+        cplx<T>* Rf = lds_fft<T, false>(c, R, R == L.R0 ? L.R1 : L.R0, rb, N1, 1, r1, L.tw1);
+        for (int i = c.tid(); i < rb * nxa; i += c.nthr()) {
+          const int r = i / nxa, xa = i - r * nxa;
+          P[(y0 + r) * nxa + xa] = Rf[r * N1 + xlist[xa]];
+        }
+        c.sync();
+      }
+      cplx<T>* Pf = lds_fft<T, false>(c, P, P == L.P0 ? L.P1 : L.P0, nxa, 1, nxa, r2, L.tw2);
+      for (int i = c.tid(); i < ncol; i += c.nthr()) {
+        const int w = L.stk[i];
+        row[i] = Pf[(w >> 16) * nxa + (w & 0xffff)];
+      }
+      c.sync();
+    }
+  }
+};
+
+// Density plane pass: acc(r) = sum_n occw_n |u_n(r)|^2 over the WG's bands;
+// out[group][z][y][x] = acc * scale (scale = 1/Omega). grid (N3, ngroups)
+template <typename T>
+struct KPlaneRho {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const cplx<T>* __restrict__ sb, int nbands, int BPW,
+                         const double* __restrict__ occw, const int4* __restrict__ sticks,
+                         const int* __restrict__ xlist, int ncol, int nxa, Radix r1, Radix r2, int N3,
+                         const cplx<T>* __restrict__ tw1, const cplx<T>* __restrict__ tw2, T* __restrict__ out,
+                         double scale, int RB) {
+    const int N1 = r1.n, N2 = r2.n;
+    const int z = c.bx();
+    PlaneLds<T> L(lds, N1, N2, nxa, RB, ncol);
+    plane_load_tables<T>(c, L, sticks, ncol, tw1, tw2, N1, N2);
+    for (int i = c.tid(); i < N1 * N2; i += c.nthr()) L.acc[i] = T(0);
+    c.sync();
+    const int b0 = c.by() * BPW;
+    for (int band = b0; band < b0 + BPW && band < nbands; ++band) {
+      const T w = (T)occw[band];
+      const cplx<T>* row = sb + ((size_t)band * N3 + z) * ncol;
+      cplx<T>* P = plane_inverse_y<T>(c, L, row, ncol, nxa, r2);
+      for (int y0 = 0; y0 < N2; y0 += RB) {
+        const int rb = (N2 - y0) < RB ? (N2 - y0) : RB;
+        for (int i = c.tid(); i < rb * N1; i += c.nthr()) L.R0[i] = mk<T>(0, 0);
+        c.sync();
+        for (int i = c.tid(); i < rb * nxa; i += c.nthr()) {
+          const int r = i / nxa, xa = i - r * nxa;
+          L.R0[r * N1 + xlist[xa]] = P[(y0 + r) * nxa + xa];
+        }
+        c.sync();
+        cplx<T>* R = lds_fft<T, true>(c, L.R0, L.R1, rb, N1, 1, r1, L.tw1);
+        for (int i = c.tid(); i < rb * N1; i += c.nthr()) L.acc[y0 * N1 + i] += w * norm2(R[i]);
+        c.sync();
+      }
+    }
+    T* o = out + ((size_t)c.by() * N3 + z) * N1 * N2;
+    for (int i = c.tid(); i < N1 * N2; i += c.nthr()) o[i] = (T)scale * L.acc[i];
+  }
+};
+
+// rho[p] += sum_g part[g][p]
+template <typename T>
+struct KRhoReduce {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char*, const T* __restrict__ part, int ngroups, size_t n, T* __restrict__ rho) {
+    for (int l = c.tid(); l < kBlk; l += c.nthr()) {
+      const size_t i = (size_t)c.bx() * kBlk + l;
+      if (i >= n) break;
+      T s = rho[i];
+      for (int g = 0; g < ngroups; ++g) s += part[(size_t)g * n + i];
+      rho[i] = s;
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Kleinman-Bylander products.
+// KKbProj: partial[chunk][i][n] = sum_{G in chunk} conj(beta_i(G)) psi_n(G)
+//   grid (nchunk, ceil(nproj/32), ceil(nb/32)); chunk = 2048 plane waves.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct KKbProj {
+  static constexpr int CH = 2048, TG = 64, TI = 32, TN = 32;
+  static size_t lds_bytes() { return sizeof(cplx<T>) * (TI + TN) * TG + sizeof(cplx<double>) * TI * TN; }
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const cplx<T>* __restrict__ beta, const cplx<T>* __restrict__ psi,
+                         int npw, int nproj, int nb, cplx<double>* __restrict__ part) {
+    const int g0 = c.bx() * CH;
+    const int i0 = c.by() * TI, n0 = c.bz() * TN;
+    cplx<T>* sB = (cplx<T>*)lds;       // [TI][TG]
+    cplx<T>* sP = sB + TI * TG;        // [TN][TG]
+    cplx<double>* acc = (cplx<double>*)(sP + TN * TG);  // [TI][TN]
+    for (int o = c.tid(); o < TI * TN; o += c.nthr()) acc[o] = mk<double>(0, 0);
+    const int gend = (g0 + CH) < npw ? (g0 + CH) : npw;
+    for (int gs = g0; gs < gend; gs += TG) {
+      for (int idx = c.tid(); idx < TI * TG; idx += c.nthr()) {
+        const int r = idx / TG, g = gs + (idx - r * TG);
+        sB[idx] = (i0 + r < nproj && g < gend) ? beta[(size_t)(i0 + r) * npw + g] : mk<T>(0, 0);
+        sP[idx] = (n0 + r < nb && g < gend) ? psi[(size_t)(n0 + r) * npw + g] : mk<T>(0, 0);
+      }
+      c.sync();
+      for (int o = c.tid(); o < TI * TN; o += c.nthr()) {
+        const int i = o / TN, n = o - i * TN;
+        double ax = 0, ay = 0;
+        for (int g = 0; g < TG; ++g) {
+          const cplx<T> bv = sB[i * TG + g];
+          const cplx<T> pv = sP[n * TG + g];
+          ax += (double)bv.x * pv.x + (double)bv.y * pv.y;
+          ay += (double)bv.x * pv.y - (double)bv.y * pv.x;
+        }
+        acc[o].x += ax;
+        acc[o].y += ay;
+      }
+      c.sync();
+    }
+    for (int o = c.tid(); o < TI * TN; o += c.nthr()) {
+      const int i = o / TN, n = o - i * TN;
+      if (i0 + i < nproj && n0 + n < nb) part[((size_t)c.bx() * nproj + i0 + i) * nb + n0 + n] = acc[o];
+    }
+  }
+};
+
+// dp[i][n] = D_i * sum_chunk part[chunk][i][n]   (grid ceil(nproj*nb/256))
+template <typename T>
+struct KKbReduce {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char*, const cplx<double>* __restrict__ part, int nchunk, int nproj, int nb,
+                         const double* __restrict__ dkb, cplx<T>* __restrict__ dp) {
+    for (int l = c.tid(); l < kBlk; l += c.nthr()) {
+      const int o = c.bx() * kBlk + l;
+      if (o >= nproj * nb) break;
+      double sx = 0, sy = 0;
+      for (int k = 0; k < nchunk; ++k) {
+        sx += part[(size_t)k * nproj * nb + o].x;
+        sy += part[(size_t)k * nproj * nb + o].y;
+      }
+      const double d = dkb[o / nb];
+      dp[o] = mk<T>((T)(d * sx), (T)(d * sy));
+    }
+  }
+};
+
+// hpsi[n][G] += sum_i beta_i(G) dp[i][n]; grid (ceil(npw/256), ceil(nb/16))
+template <typename T>
+struct KKbAdd {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const cplx<T>* __restrict__ beta, const cplx<T>* __restrict__ dp,
+                         cplx<T>* __restrict__ hpsi, int npw, int nproj, int nb) {
+    const int NT = 16;
+    const int n0 = c.by() * NT;
+    cplx<T>* sD = (cplx<T>*)lds;  // [nproj][NT]
+    for (int idx = c.tid(); idx < nproj * NT; idx += c.nthr()) {
+      const int i = idx / NT, q = idx - i * NT;
+      sD[idx] = (n0 + q < nb) ? dp[(size_t)i * nb + n0 + q] : mk<T>(0, 0);
+    }
+    c.sync();
+    for (int l = c.tid(); l < kBlk; l += c.nthr()) {
+      const int g = c.bx() * kBlk + l;
+      if (g >= npw) break;
+      cplx<T> acc[NT];
+      for (int q = 0; q < NT; ++q) acc[q] = mk<T>(0, 0);
+      for (int i = 0; i < nproj; ++i) {
+        const cplx<T> bv = beta[(size_t)i * npw + g];
+        for (int q = 0; q < NT; ++q) acc[q] = acc[q] + bv * sD[i * NT + q];
+      }
+      for (int q = 0; q < NT && n0 + q < nb; ++q) {
+        cplx<T>& h = hpsi[(size_t)(n0 + q) * npw + g];
+        h = h + acc[q];
+      }
+    }
+  }
+};
+
+}  // namespace fde

@@ -1,0 +1,344 @@
+// Host entry points of the plane-wave kernels: fde_apply_h, fde_density,
+// fde_kb_projectors, fde_init_bands, fde_band_energies.
+#include <algorithm>
+#include <cmath>
+
+#include "kernels_pw.hpp"
+#include "launch.hpp"
+
+namespace fde {
+
+static KVec kvec(const fde_plan* p, int ik) {
+  KVec k;
+  for (int i = 0; i < 3; ++i) {
+    k.kf[i] = p->k[ik].kf[i];
+    k.b[i] = p->b[i];
+  }
+  return k;
+}
+
+// Sticks per z-pass workgroup: the largest of 16, 8, 4, 2, 1 whose LDS fits 64 KiB.
+static int stick_group(const fde_plan* p) {
+  const size_t cs = p->csize();
+  for (int sz = 16; sz > 1; sz /= 2)
+    if ((2 * (size_t)p->N[2] * sz + p->N[2]) * cs <= 64 * 1024) return sz;
+  return 1;
+}
+
+// Rows per batch of the plane pass: as many as fit 64 KiB, else 160 KiB.
+template <typename T>
+static int plane_rows(const fde_plan* p, int ik, bool acc, size_t* lds) {
+  const KTables& t = p->k[ik];
+  for (size_t budget : {(size_t)64 * 1024, kLdsMax}) {
+    for (int rb = p->N[1]; rb >= 1; rb = (rb > 8 ? rb / 2 : rb - 1)) {
+      size_t b = PlaneLds<T>::bytes(p->N[0], p->N[1], t.nxa, rb, t.ncol, acc);
+      if (b <= budget) {
+        *lds = b;
+        return rb;
+      }
+    }
+  }
+  return 0;
+}
+
+template <typename T>
+static fde_status apply_h_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, cplx<T>* hpsi, const T* veff, int nproj,
+                            const cplx<T>* beta, const double* dkb, hipStream_t s) {
+  const KTables& t = p->k[ik];
+  const int N1 = p->N[0], N2 = p->N[1], N3 = p->N[2];
+  const int SZ = stick_group(p);
+  const size_t zlds = (2 * (size_t)N3 * SZ + N3) * sizeof(cplx<T>);
+  size_t plds = 0;
+  const int RB = plane_rows<T>(p, ik, false, &plds);
+  if (RB == 0) return fail(FDE_ERR_UNSUPPORTED, "plane does not fit in LDS");
+  const double invN = 1.0 / ((double)N1 * N2 * N3);
+  const KVec kv = kvec(p, ik);
+  cplx<T>* sb = (cplx<T>*)p->scratch;
+  size_t off = align256((size_t)p->max_nb * N3 * p->ncol_max * sizeof(cplx<T>));
+  cplx<double>* part = (cplx<double>*)(p->scratch + off);
+  const int nchunk = (t.npw + 2047) / 2048;
+  off += align256((size_t)nchunk * p->max_nproj * p->max_nb * 16);
+  cplx<T>* dp = (cplx<T>*)(p->scratch + off);
+  const cplx<T>* tw1 = (const cplx<T>*)p->d_tw[0];
+  const cplx<T>* tw2 = (const cplx<T>*)p->d_tw[1];
+  const cplx<T>* tw3 = (const cplx<T>*)p->d_tw[2];
+  for (int b0 = 0; b0 < nb; b0 += p->max_nb) {
+    const int nbc = std::min(p->max_nb, nb - b0);
+    const cplx<T>* ps = psi + (size_t)b0 * t.npw;
+    cplx<T>* hs = hpsi + (size_t)b0 * t.npw;
+    const unsigned ngz = (unsigned)((t.ncol + SZ - 1) / SZ);
+    FDE_TRY(launch<KZInv<T>>(dim3(ngz, nbc), kBlock, zlds, s, ps, t.npw, (const int4*)t.d_sticks, t.ncol,
+                             p->rad[2], tw3, sb, SZ));
+    const int BPW = std::max(1, std::min(nbc, (N3 * nbc) / 2048));
+    FDE_TRY(launch<KPlaneH<T>>(dim3(N3, (nbc + BPW - 1) / BPW), kBlock, plds, s, sb, nbc, BPW,
+                               (const int4*)t.d_sticks, (const int*)t.d_xlist, t.ncol, t.nxa, p->rad[0], p->rad[1],
+                               N3, tw1, tw2, veff, RB));
+    FDE_TRY(launch<KZFwd<T>>(dim3(ngz, nbc), kBlock, zlds, s, (const cplx<T>*)sb, ps, hs, t.npw,
+                             (const int4*)t.d_sticks, (const int*)t.d_xlist, t.ncol, N1, N2, p->rad[2], tw3, kv, invN,
+                             SZ));
+    if (nproj > 0) {
+      FDE_TRY(launch<KKbProj<T>>(dim3(nchunk, (nproj + 31) / 32, (nbc + 31) / 32), kBlock, KKbProj<T>::lds_bytes(),
+                                 s, beta, ps, t.npw, nproj, nbc, part));
+      FDE_TRY(launch<KKbReduce<T>>(dim3((nproj * nbc + kBlk - 1) / kBlk), kBlock, 0, s, (const cplx<double>*)part,
+                                   nchunk, nproj, nbc, dkb, dp));
+      FDE_TRY(launch<KKbAdd<T>>(dim3((t.npw + kBlk - 1) / kBlk, (nbc + 15) / 16), kBlock,
+                                (size_t)nproj * 16 * sizeof(cplx<T>), s, beta, (const cplx<T>*)dp, hs, t.npw, nproj,
+                                nbc));
+    }
+  }
+  return FDE_OK;
+}
+
+template <typename T>
+static fde_status density_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, const double* occw, T* rho,
+                            hipStream_t s) {
+  const KTables& t = p->k[ik];
+  const int N3 = p->N[2];
+  const int SZ = stick_group(p);
+  const size_t zlds = (2 * (size_t)N3 * SZ + N3) * sizeof(cplx<T>);
+  size_t plds = 0;
+  const int RB = plane_rows<T>(p, ik, true, &plds);
+  if (RB == 0) return fail(FDE_ERR_UNSUPPORTED, "plane does not fit in LDS");
+  cplx<T>* sb = (cplx<T>*)p->scratch;
+  T* part = (T*)(p->scratch + align256((size_t)p->max_nb * N3 * p->ncol_max * sizeof(cplx<T>)));
+  const cplx<T>* tw1 = (const cplx<T>*)p->d_tw[0];
+  const cplx<T>* tw2 = (const cplx<T>*)p->d_tw[1];
+  const cplx<T>* tw3 = (const cplx<T>*)p->d_tw[2];
+  const size_t n = p->npts();
+  for (int b0 = 0; b0 < nb; b0 += p->max_nb) {
+    const int nbc = std::min(p->max_nb, nb - b0);
+    const unsigned ngz = (unsigned)((t.ncol + SZ - 1) / SZ);
+    FDE_TRY(launch<KZInv<T>>(dim3(ngz, nbc), kBlock, zlds, s, psi + (size_t)b0 * t.npw, t.npw,
+                             (const int4*)t.d_sticks, t.ncol, p->rad[2], tw3, sb, SZ));
+    const int ngroups = std::min(4, nbc);
+    const int BPW = (nbc + ngroups - 1) / ngroups;
+    const int ng = (nbc + BPW - 1) / BPW;
+    FDE_TRY(launch<KPlaneRho<T>>(dim3(N3, ng), kBlock, plds, s, (const cplx<T>*)sb, nbc, BPW, occw + b0,
+                                 (const int4*)t.d_sticks, (const int*)t.d_xlist, t.ncol, t.nxa, p->rad[0],
+                                 p->rad[1], N3, tw1, tw2, part, 1.0 / p->omega, RB));
+    FDE_TRY(launch<KRhoReduce<T>>(dim3((unsigned)((n + kBlk - 1) / kBlk)), kBlock, 0, s, (const T*)part, ng, n, rho));
+  }
+  return FDE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Projectors, initial bands, band energies
+// ---------------------------------------------------------------------------
+struct KbAtom {
+  double R[3];
+  double r;
+  int lmax;
+  int first;  // index of its first channel
+};
+
+template <typename T>
+struct KKbBuild {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char*, const KbAtom* __restrict__ atoms, int natoms, const int* __restrict__ millp,
+                         int npw, KVec kv, double omega, cplx<T>* __restrict__ beta) {
+    const double pi = 3.14159265358979323846;
+    for (int l = c.tid(); l < kBlk; l += c.nthr()) {
+      const int g = c.bx() * kBlk + l;
+      if (g >= npw) break;
+      int m1, m2, m3;
+      unpack_mill(millp[g], m1, m2, m3);
+      const double q[3] = {(m1 + kv.kf[0]) * kv.b[0], (m2 + kv.kf[1]) * kv.b[1], (m3 + kv.kf[2]) * kv.b[2]};
+      const double q2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+      const double pref = 1.0 / sqrt(omega);
+      for (int a = 0; a < natoms; ++a) {
+        const KbAtom at = atoms[a];
+        if (at.lmax < 0) continue;
+        const double ph = -(q[0] * at.R[0] + q[1] * at.R[1] + q[2] * at.R[2]);
+        const double cr = cos(ph), ci = sin(ph);
+        const double gs = exp(-0.5 * q2 * at.r * at.r);
+        const double ss = pref * 2.0 * sqrt(2.0) * pow(pi, 0.75) * pow(at.r, 1.5) * gs;
+        beta[(size_t)at.first * npw + g] = mk<T>((T)(ss * cr), (T)(ss * ci));
+        if (at.lmax >= 1) {
+          const double sp = pref * 4.0 * pow(pi, 0.75) * pow(at.r, 2.5) * gs;
+          for (int d = 0; d < 3; ++d)
+            beta[(size_t)(at.first + 1 + d) * npw + g] = mk<T>((T)(sp * q[d] * cr), (T)(sp * q[d] * ci));
+        }
+      }
+    }
+  }
+};
+
+template <typename T>
+struct KInitBands {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char*, const cplx<T>* __restrict__ raw, cplx<T>* __restrict__ psi,
+                         const int* __restrict__ millp, int npw, KVec kv) {
+    const int n = c.by();
+    for (int l = c.tid(); l < kBlk; l += c.nthr()) {
+      const int g = c.bx() * kBlk + l;
+      if (g >= npw) break;
+      int m1, m2, m3;
+      unpack_mill(millp[g], m1, m2, m3);
+      const double d = 1.0 / (1.0 + 2.0 * kin_of(kv, m1, m2, m3));
+      const cplx<T> r = raw[(size_t)n * npw + g];
+      psi[(size_t)n * npw + g] = mk<T>((T)(d * r.x), (T)(d * r.y));
+    }
+  }
+};
+
+// out[0] += sum_n w_n sum_G kin |psi|^2 ; one block per band (deterministic per band), then KSum
+template <typename T>
+struct KBandKin {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const cplx<T>* __restrict__ psi, const double* __restrict__ occw,
+                         const int* __restrict__ millp, int npw, KVec kv, double* __restrict__ per_band) {
+    const int n = c.bx();
+    double acc = 0.0;
+    for (int g = c.tid(); g < npw; g += c.nthr()) {
+      int m1, m2, m3;
+      unpack_mill(millp[g], m1, m2, m3);
+      const cplx<T> v = psi[(size_t)n * npw + g];
+      acc += kin_of(kv, m1, m2, m3) * ((double)v.x * v.x + (double)v.y * v.y);
+    }
+    acc = c.sum(acc, (double*)lds);
+    if (c.tid() == 0) per_band[n] = occw[n] * acc;
+  }
+};
+
+// out[slot] += sum_i per_item[i]  (single block, fixed order)
+struct KSumInto {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const double* __restrict__ v, int n, double* __restrict__ out) {
+    double acc = 0.0;
+    for (int i = c.tid(); i < n; i += c.nthr()) acc += v[i];
+    acc = c.sum(acc, (double*)lds);
+    if (c.tid() == 0) out[0] += acc;
+  }
+};
+
+// per_band[n] = occw_n sum_i D_i |dp-free projections|^2 from part (FP64) partials
+struct KBandNl {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const cplx<double>* __restrict__ part, int nchunk, int nproj, int nb,
+                         const double* __restrict__ dkb, const double* __restrict__ occw, double* __restrict__ per_band) {
+    const int n = c.bx();
+    double acc = 0.0;
+    for (int i = c.tid(); i < nproj; i += c.nthr()) {
+      double sx = 0, sy = 0;
+      for (int k = 0; k < nchunk; ++k) {
+        sx += part[((size_t)k * nproj + i) * nb + n].x;
+        sy += part[((size_t)k * nproj + i) * nb + n].y;
+      }
+      acc += dkb[i] * (sx * sx + sy * sy);
+    }
+    acc = c.sum(acc, (double*)lds);
+    if (c.tid() == 0) per_band[n] = occw[n] * acc;
+  }
+};
+
+template <typename T>
+static fde_status band_energies_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, const double* occw, int nproj,
+                                  const cplx<T>* beta, const double* dkb, double* out, hipStream_t s) {
+  const KTables& t = p->k[ik];
+  if (nb > p->max_nb) return fail(FDE_ERR_SHAPE, "fde_band_energies: nb exceeds the workspace's max_nb");
+  if (nproj > p->max_nproj) return fail(FDE_ERR_SHAPE, "nproj exceeds the workspace's max_nproj");
+  const int nchunk = (t.npw + 2047) / 2048;
+  cplx<double>* part = (cplx<double>*)(p->scratch);
+  double* per_band = (double*)(p->scratch + align256((size_t)nchunk * p->max_nproj * p->max_nb * 16 + 16));
+  const KVec kv = kvec(p, ik);
+  FDE_TRY(launch<KBandKin<T>>(dim3(nb), kBlock, 17 * sizeof(double), s, psi, occw, (const int*)t.d_millp, t.npw, kv,
+                              per_band));
+  FDE_TRY(launch<KSumInto>(dim3(1), kBlock, 17 * sizeof(double), s, (const double*)per_band, nb, out));
+  if (nproj > 0) {
+    FDE_TRY(launch<KKbProj<T>>(dim3(nchunk, (nproj + 31) / 32, (nb + 31) / 32), kBlock, KKbProj<T>::lds_bytes(), s,
+                               beta, psi, t.npw, nproj, nb, part));
+    FDE_TRY(launch<KBandNl>(dim3(nb), kBlock, 17 * sizeof(double), s, (const cplx<double>*)part, nchunk, nproj, nb,
+                            dkb, occw, per_band));
+    FDE_TRY(launch<KSumInto>(dim3(1), kBlock, 17 * sizeof(double), s, (const double*)per_band, nb, out + 1));
+  }
+  return FDE_OK;
+}
+
+}  // namespace fde
+
+using namespace fde;
+
+extern "C" {
+
+fde_status fde_apply_h(fde_plan* p, int ik, int nb, const void* psi, void* hpsi, const void* veff, int nproj,
+                       const void* beta, const double* dkb, hipStream_t s) {
+  FDE_TRY(check_plan(p, ik));
+  if (nb < 0 || nproj < 0) return fail(FDE_ERR_ARG, "negative size");
+  if (nb == 0) return FDE_OK;
+  if (!psi || !hpsi || !veff) return fail(FDE_ERR_ARG, "null array");
+  if (psi == hpsi) return fail(FDE_ERR_ARG, "hpsi must not alias psi");
+  if (nproj > 0 && (!beta || !dkb)) return fail(FDE_ERR_ARG, "nproj > 0 needs beta and dkb");
+  if (nproj > p->max_nproj) return fail(FDE_ERR_SHAPE, "nproj exceeds the workspace's max_nproj");
+  if (p->prec == FDE_F64)
+    return apply_h_t<double>(p, ik, nb, (const cplx<double>*)psi, (cplx<double>*)hpsi, (const double*)veff, nproj,
+                             (const cplx<double>*)beta, dkb, s);
+  return apply_h_t<float>(p, ik, nb, (const cplx<float>*)psi, (cplx<float>*)hpsi, (const float*)veff, nproj,
+                          (const cplx<float>*)beta, dkb, s);
+}
+
+fde_status fde_density(fde_plan* p, int ik, int nb, const void* psi, const double* occw, void* rho, hipStream_t s) {
+  FDE_TRY(check_plan(p, ik));
+  if (nb < 0) return fail(FDE_ERR_ARG, "negative size");
+  if (nb == 0) return FDE_OK;
+  if (!psi || !occw || !rho) return fail(FDE_ERR_ARG, "null array");
+  if (p->prec == FDE_F64)
+    return density_t<double>(p, ik, nb, (const cplx<double>*)psi, occw, (double*)rho, s);
+  return density_t<float>(p, ik, nb, (const cplx<float>*)psi, occw, (float*)rho, s);
+}
+
+fde_status fde_kb_projectors(fde_plan* p, int ik, int natoms, const double* pos, const int* lmax, const double* rbeta,
+                             void* beta, int* nproj, hipStream_t s) {
+  FDE_TRY(check_plan(p, ik));
+  if (natoms < 0 || (natoms > 0 && (!pos || !lmax || !rbeta)) || !nproj) return fail(FDE_ERR_ARG, "null argument");
+  std::vector<KbAtom> at(natoms);
+  int np = 0;
+  for (int a = 0; a < natoms; ++a) {
+    for (int i = 0; i < 3; ++i) at[a].R[i] = pos[3 * a + i];
+    at[a].r = rbeta[a];
+    at[a].lmax = lmax[a];
+    at[a].first = np;
+    if (lmax[a] > 1 || lmax[a] < -1) return fail(FDE_ERR_ARG, "lmax must be -1, 0 or 1");
+    if (lmax[a] >= 0) np += (lmax[a] == 0 ? 1 : 4);
+  }
+  *nproj = np;
+  if (np == 0) return FDE_OK;
+  if (!beta) return fail(FDE_ERR_ARG, "null beta");
+  // atom table staged in the scratch area (synchronous copy)
+  KbAtom* d_at = (KbAtom*)p->scratch;
+  FDE_TRY(stream_sync(s));  // the scratch area may still be in use by earlier work on s
+  FDE_TRY(copy_h2d_sync(d_at, at.data(), natoms * sizeof(KbAtom)));
+  const KTables& t = p->k[ik];
+  if (p->prec == FDE_F64)
+    return launch<KKbBuild<double>>(dim3((t.npw + kBlk - 1) / kBlk), kBlock, 0, s, (const KbAtom*)d_at, natoms,
+                                    (const int*)t.d_millp, t.npw, kvec(p, ik), p->omega, (cplx<double>*)beta);
+  return launch<KKbBuild<float>>(dim3((t.npw + kBlk - 1) / kBlk), kBlock, 0, s, (const KbAtom*)d_at, natoms,
+                                 (const int*)t.d_millp, t.npw, kvec(p, ik), p->omega, (cplx<float>*)beta);
+}
+
+fde_status fde_init_bands(fde_plan* p, int ik, int nb, const void* raw, void* psi, hipStream_t s) {
+  FDE_TRY(check_plan(p, ik));
+  if (nb < 0) return fail(FDE_ERR_ARG, "negative size");
+  if (nb == 0) return FDE_OK;
+  if (!raw || !psi) return fail(FDE_ERR_ARG, "null array");
+  const KTables& t = p->k[ik];
+  dim3 g((t.npw + kBlk - 1) / kBlk, nb);
+  if (p->prec == FDE_F64)
+    return launch<KInitBands<double>>(g, kBlock, 0, s, (const cplx<double>*)raw, (cplx<double>*)psi,
+                                      (const int*)t.d_millp, t.npw, kvec(p, ik));
+  return launch<KInitBands<float>>(g, kBlock, 0, s, (const cplx<float>*)raw, (cplx<float>*)psi, (const int*)t.d_millp,
+                                   t.npw, kvec(p, ik));
+}
+
+fde_status fde_band_energies(fde_plan* p, int ik, int nb, const void* psi, const double* occw, int nproj,
+                             const void* beta, const double* dkb, double* out, hipStream_t s) {
+  FDE_TRY(check_plan(p, ik));
+  if (nb < 0 || nproj < 0) return fail(FDE_ERR_ARG, "negative size");
+  if (nb == 0) return FDE_OK;
+  if (!psi || !occw || !out || (nproj > 0 && (!beta || !dkb))) return fail(FDE_ERR_ARG, "null array");
+  if (p->prec == FDE_F64)
+    return band_energies_t<double>(p, ik, nb, (const cplx<double>*)psi, occw, nproj, (const cplx<double>*)beta, dkb,
+                                   out, s);
+  return band_energies_t<float>(p, ik, nb, (const cplx<float>*)psi, occw, nproj, (const cplx<float>*)beta, dkb, out, s);
+}
+
+}  // extern "C"

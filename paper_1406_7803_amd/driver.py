@@ -1,0 +1,149 @@
+"""Embedding-cycle driver over the C ABI (orchestration only).
+
+One cycle (Fig. 1b of the paper: the subsystem SCF step runs once per cycle
+and the total density is rebuilt every cycle; all subsystems see the densities
+of the cycle start):
+  1. fde_embed_potential: V_eff^I of every subsystem (recast form, Appendix);
+  2. per subsystem and k-point: fde_apply_h + fde_subspace_rr on X, then
+     n_david iterations of fde_precondition, fde_apply_h, fde_subspace_rr on [X|T];
+  3. fde_occupations, fde_density;
+  4. fde_mix (linear, beta = 0.3); the next fde_embed_potential sums rho = sum rho_I.
+Every arithmetic step runs in the library's kernels; this module only owns
+buffers (PyTorch tensors) and the order of the calls.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+import torch
+
+import fde_synth
+
+from . import fde
+
+
+@dataclass
+class BandBlock:
+    isub: int
+    ik: int              # plan k index
+    j: int               # k index within the subsystem
+    V: torch.Tensor      # [2 nb][npw]: rows 0..nb-1 = X, nb..2nb-1 = T
+    HV: torch.Tensor
+    beta: Optional[torch.Tensor]
+    dkb: Optional[torch.Tensor]
+    eval: torch.Tensor   # [nb] float64
+    active: torch.Tensor  # [2 nb] uint8
+    rnorm: torch.Tensor  # [nb] float64
+    info: torch.Tensor   # [1] int32
+    nb: int
+
+
+@dataclass
+class Engine:
+    system: object
+    prec: int = fde.F64
+    backend: Optional[fde.Backend] = None
+    kinds: dict = field(default_factory=lambda: dict(xc=fde.XC_LDA, xc_nad=fde.XC_LDA, kin_nad=fde.KIN_LC94))
+
+    def __post_init__(self):
+        s = self.system
+        self.be = self.backend or fde.gpu_backend()
+        max_nb = max(sub.nbands for sub in s.subsystems)
+        nproj_max = max([self._nproj(sub) for sub in s.subsystems] + [0])
+        self.plan = fde.Plan(s.L, s.grid, s.ecut, s.all_kfrac, prec=self.prec, max_nb=max_nb, max_nproj=nproj_max,
+                             backend=self.be)
+        p = self.plan
+        dev = self.be.device
+        atoms = [a for sub in s.subsystems for a in sub.atoms]
+        self.vloc = p.local_potential([a.pos for a in atoms], [a.Z for a in atoms], [a.width for a in atoms])
+        self.blocks: List[List[BandBlock]] = []
+        for I, sub in enumerate(s.subsystems):
+            row = []
+            for j, ik in enumerate(s.k_index(I)):
+                nb = sub.nbands
+                npw = p.npw(ik)
+                beta = dkb = None
+                if self._nproj(sub):
+                    beta = p.kb_projectors(ik, [a.pos for a in sub.atoms], [a.lmax for a in sub.atoms],
+                                           [a.rbeta for a in sub.atoms]).contiguous()
+                    d = []
+                    for a in sub.atoms:
+                        if a.lmax >= 0:
+                            d.append(a.d_s)
+                        if a.lmax >= 1:
+                            d += [a.d_p] * 3
+                    dkb = torch.tensor(d, dtype=torch.float64, device=dev)
+                V = torch.zeros((2 * nb, npw), dtype=p.cdtype, device=dev)
+                raw = torch.from_numpy(fde_synth.random_coefficients(s.cfg, s.geometry, I, ik, nb, npw)).to(
+                    dtype=p.cdtype, device=dev)
+                p.init_bands(ik, raw, out=V[:nb])
+                row.append(BandBlock(I, ik, j, V, torch.zeros_like(V), beta, dkb,
+                                     torch.zeros(nb, dtype=torch.float64, device=dev),
+                                     torch.ones(2 * nb, dtype=torch.uint8, device=dev),
+                                     torch.zeros(nb, dtype=torch.float64, device=dev),
+                                     torch.zeros(1, dtype=torch.int32, device=dev), nb))
+            self.blocks.append(row)
+        ns = len(s.subsystems)
+        self.rho_in = p.zeros_grid(ns)
+        self.rho_out = p.zeros_grid(ns)
+        self.veff = p.zeros_grid(ns)
+        self.energies = torch.zeros((ns + 1, fde.NE), dtype=torch.float64, device=dev)
+        self.einfo = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.wk = [torch.tensor(sub.kweight, dtype=torch.float64, device=dev) for sub in s.subsystems]
+        self.eps = [torch.zeros((len(sub.kfrac), sub.nbands), dtype=torch.float64, device=dev) for sub in s.subsystems]
+        self.occw = [torch.zeros_like(e) for e in self.eps]
+        self.mu = [torch.zeros(1, dtype=torch.float64, device=dev) for _ in s.subsystems]
+        self.oinfo = [torch.zeros(1, dtype=torch.int32, device=dev) for _ in s.subsystems]
+        self._initial_density()
+
+    @staticmethod
+    def _nproj(sub) -> int:
+        return sum(0 if a.lmax < 0 else (1 if a.lmax == 0 else 4) for a in sub.atoms)
+
+    def _initial_density(self):
+        """Orthonormalise the initial bands and take their density with f = N_I / nb."""
+        p = self.plan
+        for I, sub in enumerate(self.system.subsystems):
+            for b in self.blocks[I]:
+                X = b.V[:b.nb]
+                HX = b.HV[:b.nb]
+                HX.copy_(X)                       # A = S: the Rayleigh-Ritz step only orthonormalises
+                p.subspace_rr(b.ik, X, HX, b.nb, eval=b.eval, info=b.info)
+                w = float(sub.kweight[b.j]) * sub.nelec / sub.nbands
+                occw = torch.full((b.nb,), w, dtype=torch.float64, device=self.be.device)
+                p.density(b.ik, X, occw, self.rho_in[I])
+
+    def davidson(self, b: BandBlock, veff: torch.Tensor, n_david: int):
+        p = self.plan
+        nb = b.nb
+        X, HX, T, HT = b.V[:nb], b.HV[:nb], b.V[nb:], b.HV[nb:]
+        p.apply_h(b.ik, X, veff, b.beta, b.dkb, out=HX)
+        p.subspace_rr(b.ik, X, HX, nb, eval=b.eval, info=b.info)
+        for _ in range(n_david):
+            p.precondition(b.ik, X, HX, b.eval, T, b.active[nb:], b.rnorm)
+            p.apply_h(b.ik, T, veff, b.beta, b.dkb, out=HT)
+            p.subspace_rr(b.ik, b.V, b.HV, nb, active=b.active, eval=b.eval, info=b.info)
+
+    def cycle(self, n_david: Optional[int] = None):
+        s = self.system
+        p = self.plan
+        n_david = s.n_david if n_david is None else n_david
+        p.embed_potential(self.rho_in, self.vloc, rho_thr=s.rho_thr, veff=self.veff, energies=self.energies,
+                          info=self.einfo, **self.kinds)
+        for I, sub in enumerate(s.subsystems):
+            for b in self.blocks[I]:
+                self.davidson(b, self.veff[I], n_david)
+                self.eps[I][b.j].copy_(b.eval)
+            mode = fde.OCC_INTEGER if sub.smearing == "integer" else fde.OCC_FERMI_DIRAC
+            fde.occupations(self.be, self.eps[I], self.wk[I], sub.nelec, mode, max(sub.sigma, 1e-300),
+                            occw=self.occw[I], mu=self.mu[I], info=self.oinfo[I])
+            self.rho_out[I].zero_()
+            for b in self.blocks[I]:
+                p.density(b.ik, b.V[:b.nb], self.occw[I][b.j], self.rho_out[I])
+        fde.mix(self.be, self.rho_in, self.rho_out, s.mix_beta)
+
+    def band_applies_per_cycle(self, n_david: Optional[int] = None) -> int:
+        n_david = self.system.n_david if n_david is None else n_david
+        return sum(b.nb * (1 + n_david) for row in self.blocks for b in row)

@@ -1,0 +1,338 @@
+"""Python binding of the C ABI in include/fde.h (argument marshalling only).
+
+PyTorch provides device memory and streams; every step of the method runs in
+the HIP kernels of libfde.so. The binding raises if the library is missing:
+there is no CPU path.
+
+Names follow include/fde.h: ``Plan`` wraps fde_plan_* and the compute calls
+are methods with the same names as the C functions minus the ``fde_`` prefix.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfde.so")
+EMU_PATH = os.path.join(HERE, "libfde_emu.so")
+
+F64, F32 = 0, 1
+XC_NONE, XC_LDA = 0, 1
+KIN_NONE, KIN_TF, KIN_LC94 = 0, 1, 2
+OCC_INTEGER, OCC_FERMI_DIRAC = 0, 1
+NE = 8
+E_XC, E_XCNAD, E_KIN, E_LOC, E_HEMB, E_HSELF, E_DEBAND, E_CHARGE = range(NE)
+
+SYMBOLS = [
+    "fde_last_error", "fde_plan_create", "fde_plan_destroy", "fde_plan_info", "fde_plan_miller",
+    "fde_plan_workspace_bytes", "fde_plan_set_workspace", "fde_apply_h", "fde_density",
+    "fde_embed_potential", "fde_subspace_rr", "fde_precondition", "fde_occupations", "fde_mix",
+    "fde_local_potential", "fde_kb_projectors", "fde_init_bands", "fde_band_energies", "fde_grid_dot",
+]
+
+
+class FdeError(RuntimeError):
+    pass
+
+
+class Functionals(ctypes.Structure):
+    _fields_ = [("xc", ctypes.c_int), ("xc_nad", ctypes.c_int), ("kin_nad", ctypes.c_int),
+                ("rho_thr", ctypes.c_double)]
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+_S = ctypes.c_size_t
+
+
+def _declare(lib):
+    lib.fde_last_error.restype = ctypes.c_char_p
+    lib.fde_plan_create.argtypes = [_P, _P, _D, _I, _P, _I, ctypes.POINTER(_P)]
+    lib.fde_plan_destroy.argtypes = [_P]
+    lib.fde_plan_destroy.restype = None
+    lib.fde_plan_info.argtypes = [_P, _I, _P, _P]
+    lib.fde_plan_miller.argtypes = [_P, _I, _P]
+    lib.fde_plan_workspace_bytes.argtypes = [_P, _I, _I, ctypes.POINTER(_S)]
+    lib.fde_plan_set_workspace.argtypes = [_P, _P, _S, _I, _I]
+    lib.fde_apply_h.argtypes = [_P, _I, _I, _P, _P, _P, _I, _P, _P, _P]
+    lib.fde_density.argtypes = [_P, _I, _I, _P, _P, _P, _P]
+    lib.fde_embed_potential.argtypes = [_P, _I, _P, _P, ctypes.POINTER(Functionals), _P, _P, _P, _P]
+    lib.fde_subspace_rr.argtypes = [_P, _I, _I, _I, _P, _P, _P, _D, _P, _P, _P]
+    lib.fde_precondition.argtypes = [_P, _I, _I, _P, _P, _P, _P, _P, _P, _P]
+    lib.fde_occupations.argtypes = [_I, _I, _P, _P, _D, _I, _D, _P, _P, _P, _P]
+    lib.fde_mix.argtypes = [_S, _D, _P, _P, _I, _P]
+    lib.fde_local_potential.argtypes = [_P, _I, _P, _P, _P, _P, _P]
+    lib.fde_kb_projectors.argtypes = [_P, _I, _I, _P, _P, _P, _P, _P, _P]
+    lib.fde_init_bands.argtypes = [_P, _I, _I, _P, _P, _P]
+    lib.fde_band_energies.argtypes = [_P, _I, _I, _P, _P, _I, _P, _P, _P, _P]
+    lib.fde_grid_dot.argtypes = [_P, _P, _P, _P, _P]
+    for name in SYMBOLS:
+        if name not in ("fde_last_error", "fde_plan_destroy"):
+            getattr(lib, name).restype = _I
+    return lib
+
+
+_LIBS = {}
+
+
+def load(path: str = LIB_PATH):
+    """Load a build of the library (default: the gfx950 product library)."""
+    if path in _LIBS:
+        return _LIBS[path]
+    if not os.path.exists(path):
+        raise FdeError(f"{path} not found: build it with `python -m paper_1406_7803_amd.build`")
+    lib = _declare(ctypes.CDLL(path))
+    _LIBS[path] = lib
+    return lib
+
+
+class Backend:
+    """Where buffers live and which library runs the kernels."""
+
+    def __init__(self, lib, device: torch.device, emulated: bool):
+        self.lib = lib
+        self.device = device
+        self.emulated = emulated
+
+    def stream(self):
+        if self.emulated:
+            return None
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def sync(self):
+        if not self.emulated:
+            torch.cuda.synchronize(self.device)
+
+
+def gpu_backend(device="cuda:0") -> Backend:
+    if not torch.cuda.is_available():
+        raise FdeError("no GPU visible: the library runs on MI355X (gfx950) only")
+    return Backend(load(LIB_PATH), torch.device(device), emulated=False)
+
+
+def emulation_backend() -> Backend:
+    """Host emulation of the kernels, for the CPU test suite only."""
+    return Backend(load(EMU_PATH), torch.device("cpu"), emulated=True)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """fde_plan_create + an attached workspace tensor owned by this object."""
+
+    def __init__(self, L: Sequence[float], grid: Sequence[int], ecut: float, kfrac, prec: int = F64,
+                 max_nb: int = 64, max_nproj: int = 0, backend: Optional[Backend] = None):
+        self.be = backend or gpu_backend()
+        self.lib = self.be.lib
+        kf = np.ascontiguousarray(np.asarray(kfrac, dtype=np.float64).reshape(-1, 3))
+        Lc = (ctypes.c_double * 3)(*[float(x) for x in L])
+        gc = (ctypes.c_int * 3)(*[int(n) for n in grid])
+        h = ctypes.c_void_p()
+        self._check(self.lib.fde_plan_create(Lc, gc, float(ecut), len(kf), kf.ctypes.data_as(_P), int(prec),
+                                             ctypes.byref(h)))
+        self.h = h
+        self.L = tuple(float(x) for x in L)
+        self.grid = tuple(int(n) for n in grid)
+        self.ecut = float(ecut)
+        self.kfrac = kf
+        self.prec = prec
+        self.rdtype = torch.float64 if prec == F64 else torch.float32
+        self.cdtype = torch.complex128 if prec == F64 else torch.complex64
+        self.max_nb = max_nb
+        self.max_nproj = max_nproj
+        nbytes = ctypes.c_size_t()
+        self._check(self.lib.fde_plan_workspace_bytes(self.h, max_nb, max_nproj, ctypes.byref(nbytes)))
+        self.ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.be.device)
+        base = self.ws.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self._check(self.lib.fde_plan_set_workspace(self.h, ctypes.c_void_p(aligned), nbytes.value, max_nb,
+                                                    max_nproj))
+
+    # -- helpers ---------------------------------------------------------------
+    def _check(self, st: int):
+        if st != 0:
+            raise FdeError(f"fde error {st}: {self.lib.fde_last_error().decode()}")
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                self.lib.fde_plan_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    @property
+    def shape(self):
+        N1, N2, N3 = self.grid
+        return (N3, N2, N1)
+
+    def npw(self, ik: int) -> int:
+        n = ctypes.c_int()
+        self._check(self.lib.fde_plan_info(self.h, ik, ctypes.byref(n), None))
+        return n.value
+
+    def ncol(self, ik: int) -> int:
+        n = ctypes.c_int()
+        self._check(self.lib.fde_plan_info(self.h, ik, None, ctypes.byref(n)))
+        return n.value
+
+    def miller(self, ik: int) -> np.ndarray:
+        out = np.zeros((self.npw(ik), 3), dtype=np.int32)
+        self._check(self.lib.fde_plan_miller(self.h, ik, out.ctypes.data_as(_P)))
+        return out
+
+    def zeros_bands(self, nb: int, ik: int) -> torch.Tensor:
+        return torch.zeros((nb, self.npw(ik)), dtype=self.cdtype, device=self.be.device)
+
+    def zeros_grid(self, *lead) -> torch.Tensor:
+        return torch.zeros(tuple(lead) + self.shape, dtype=self.rdtype, device=self.be.device)
+
+    def _bands(self, t: torch.Tensor, ik: int, name: str):
+        if t.dtype != self.cdtype or not t.is_contiguous() or t.device != self.be.device:
+            raise FdeError(f"{name}: expected a contiguous {self.cdtype} tensor on {self.be.device}")
+        if t.shape[-1] != self.npw(ik):
+            raise FdeError(f"{name}: last dimension {t.shape[-1]} != npw {self.npw(ik)}")
+
+    def _grid(self, t: torch.Tensor, name: str):
+        if t.dtype != self.rdtype or not t.is_contiguous() or t.device != self.be.device:
+            raise FdeError(f"{name}: expected a contiguous {self.rdtype} tensor on {self.be.device}")
+        if tuple(t.shape[-3:]) != self.shape:
+            raise FdeError(f"{name}: grid shape {tuple(t.shape[-3:])} != {self.shape}")
+
+    def _f64(self, t: torch.Tensor, name: str):
+        if t.dtype != torch.float64 or not t.is_contiguous() or t.device != self.be.device:
+            raise FdeError(f"{name}: expected a contiguous float64 tensor on {self.be.device}")
+
+    # -- the C ABI -------------------------------------------------------------
+    def apply_h(self, ik: int, psi: torch.Tensor, veff: torch.Tensor, beta=None, dkb=None, out=None):
+        self._bands(psi, ik, "psi")
+        self._grid(veff, "veff")
+        nb = psi.shape[0]
+        out = torch.empty_like(psi) if out is None else out
+        self._bands(out, ik, "hpsi")
+        nproj = 0 if beta is None else beta.shape[0]
+        if nproj:
+            self._bands(beta, ik, "beta")
+            self._f64(dkb, "dkb")
+        self._check(self.lib.fde_apply_h(self.h, ik, nb, _ptr(psi), _ptr(out), _ptr(veff), nproj,
+                                         _ptr(beta) if nproj else None, _ptr(dkb) if nproj else None,
+                                         self.be.stream()))
+        return out
+
+    def density(self, ik: int, psi: torch.Tensor, occw: torch.Tensor, rho: torch.Tensor):
+        self._bands(psi, ik, "psi")
+        self._f64(occw, "occw")
+        self._grid(rho, "rho")
+        if occw.numel() < psi.shape[0]:
+            raise FdeError("occw shorter than the number of bands")
+        self._check(self.lib.fde_density(self.h, ik, psi.shape[0], _ptr(psi), _ptr(occw), _ptr(rho),
+                                         self.be.stream()))
+        return rho
+
+    def embed_potential(self, rho_sub: torch.Tensor, vloc: torch.Tensor, xc=XC_LDA, xc_nad=XC_LDA,
+                        kin_nad=KIN_LC94, rho_thr=1e-10, veff=None, energies=None, info=None):
+        self._grid(rho_sub, "rho_sub")
+        self._grid(vloc, "vloc")
+        ns = rho_sub.shape[0]
+        veff = torch.empty_like(rho_sub) if veff is None else veff
+        self._grid(veff, "veff")
+        dev = self.be.device
+        energies = torch.zeros((ns + 1, NE), dtype=torch.float64, device=dev) if energies is None else energies
+        info = torch.zeros(1, dtype=torch.int32, device=dev) if info is None else info
+        f = Functionals(int(xc), int(xc_nad), int(kin_nad), float(rho_thr))
+        self._check(self.lib.fde_embed_potential(self.h, ns, _ptr(rho_sub), _ptr(vloc), ctypes.byref(f),
+                                                 _ptr(veff), _ptr(energies), _ptr(info), self.be.stream()))
+        return veff, energies, info
+
+    def subspace_rr(self, ik: int, v: torch.Tensor, hv: torch.Tensor, nb: int, active=None, drop_tol=1e-10,
+                    eval=None, info=None):
+        self._bands(v, ik, "v")
+        self._bands(hv, ik, "hv")
+        m = v.shape[0]
+        dev = self.be.device
+        eval = torch.empty(nb, dtype=torch.float64, device=dev) if eval is None else eval
+        info = torch.zeros(1, dtype=torch.int32, device=dev) if info is None else info
+        if active is not None and (active.dtype != torch.uint8 or active.numel() < m):
+            raise FdeError("active must be a uint8 tensor of length m")
+        self._check(self.lib.fde_subspace_rr(self.h, ik, m, nb, _ptr(v), _ptr(hv), _ptr(active), float(drop_tol),
+                                             _ptr(eval), _ptr(info), self.be.stream()))
+        return eval, info
+
+    def precondition(self, ik: int, x: torch.Tensor, hx: torch.Tensor, eval: torch.Tensor, t: torch.Tensor,
+                     active: torch.Tensor, rnorm: torch.Tensor):
+        for a, nme in ((x, "x"), (hx, "hx"), (t, "t")):
+            self._bands(a, ik, nme)
+        self._f64(eval, "eval")
+        self._f64(rnorm, "rnorm")
+        self._check(self.lib.fde_precondition(self.h, ik, x.shape[0], _ptr(x), _ptr(hx), _ptr(eval), _ptr(t),
+                                              _ptr(active), _ptr(rnorm), self.be.stream()))
+
+    def local_potential(self, pos, Z, width, vloc=None):
+        pos = np.ascontiguousarray(np.asarray(pos, dtype=np.float64).reshape(-1, 3))
+        Z = np.ascontiguousarray(np.asarray(Z, dtype=np.float64))
+        width = np.ascontiguousarray(np.asarray(width, dtype=np.float64))
+        vloc = self.zeros_grid() if vloc is None else vloc
+        self._check(self.lib.fde_local_potential(self.h, len(pos), pos.ctypes.data_as(_P), Z.ctypes.data_as(_P),
+                                                 width.ctypes.data_as(_P), _ptr(vloc), self.be.stream()))
+        return vloc
+
+    def kb_projectors(self, ik: int, pos, lmax, rbeta):
+        pos = np.ascontiguousarray(np.asarray(pos, dtype=np.float64).reshape(-1, 3))
+        lmax = np.ascontiguousarray(np.asarray(lmax, dtype=np.int32))
+        rbeta = np.ascontiguousarray(np.asarray(rbeta, dtype=np.float64))
+        nproj = int(sum(0 if l < 0 else (1 if l == 0 else 4) for l in lmax))
+        beta = self.zeros_bands(max(nproj, 1), ik)
+        n = ctypes.c_int()
+        self._check(self.lib.fde_kb_projectors(self.h, ik, len(pos), pos.ctypes.data_as(_P),
+                                               lmax.ctypes.data_as(_P), rbeta.ctypes.data_as(_P), _ptr(beta),
+                                               ctypes.byref(n), self.be.stream()))
+        return beta[:n.value]
+
+    def init_bands(self, ik: int, raw: torch.Tensor, out=None):
+        self._bands(raw, ik, "raw")
+        out = torch.empty_like(raw) if out is None else out
+        self._check(self.lib.fde_init_bands(self.h, ik, raw.shape[0], _ptr(raw), _ptr(out), self.be.stream()))
+        return out
+
+    def band_energies(self, ik: int, psi, occw, beta=None, dkb=None, out=None):
+        self._bands(psi, ik, "psi")
+        out = torch.zeros(2, dtype=torch.float64, device=self.be.device) if out is None else out
+        nproj = 0 if beta is None else beta.shape[0]
+        self._check(self.lib.fde_band_energies(self.h, ik, psi.shape[0], _ptr(psi), _ptr(occw), nproj,
+                                               _ptr(beta) if nproj else None, _ptr(dkb) if nproj else None,
+                                               _ptr(out), self.be.stream()))
+        return out
+
+    def grid_dot(self, a, b, out=None):
+        out = torch.zeros(1, dtype=torch.float64, device=self.be.device) if out is None else out
+        self._check(self.lib.fde_grid_dot(self.h, _ptr(a), _ptr(b), _ptr(out), self.be.stream()))
+        return out
+
+
+def occupations(be: Backend, eval: torch.Tensor, wk: torch.Tensor, nelec: float, mode: int, sigma: float,
+                occw=None, mu=None, info=None):
+    nk, nb = eval.shape
+    dev = be.device
+    occw = torch.empty((nk, nb), dtype=torch.float64, device=dev) if occw is None else occw
+    mu = torch.empty(1, dtype=torch.float64, device=dev) if mu is None else mu
+    info = torch.zeros(1, dtype=torch.int32, device=dev) if info is None else info
+    st = be.lib.fde_occupations(nk, nb, _ptr(eval), _ptr(wk), float(nelec), int(mode), float(sigma), _ptr(occw),
+                                _ptr(mu), _ptr(info), be.stream())
+    if st != 0:
+        raise FdeError(f"fde error {st}: {be.lib.fde_last_error().decode()}")
+    return occw, mu, info
+
+
+def mix(be: Backend, rho_in: torch.Tensor, rho_out: torch.Tensor, beta: float):
+    prec = F64 if rho_in.dtype == torch.float64 else F32
+    st = be.lib.fde_mix(rho_in.numel(), float(beta), _ptr(rho_in), _ptr(rho_out), prec, be.stream())
+    if st != 0:
+        raise FdeError(f"fde error {st}: {be.lib.fde_last_error().decode()}")
+    return rho_in

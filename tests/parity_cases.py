@@ -1,0 +1,225 @@
+"""Parity cases shared by the host-emulation tests and the GPU tests.
+
+Each case builds the same seeded inputs for the CPU oracle and for the
+library (through the C ABI), and compares element by element. Tolerances:
+FP64 plans to 1e-12 relative (rounding-order differences only), FP32 plans
+to a few 1e-6 relative (single-precision FFTs: about log2(N) * 6e-8 per
+transform, with FP64 accumulation of every reduction).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+import fde_synth
+from oracle import basis, dft, density as odens, embed as oembed, hamiltonian as oham, occupations as oocc
+from oracle import pseudo as opseudo, scf as oscf, subspace as osub
+from paper_1406_7803_amd import driver, fde
+
+TOL = {fde.F64: 1e-12, fde.F32: 5e-6}
+
+
+def to_dev(plan, a, kind):
+    dt = plan.cdtype if kind == "c" else (plan.rdtype if kind == "r" else torch.float64)
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype=dt, device=plan.be.device)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+SMALL = dict(L=(6.0, 7.0, 5.5), grid=(10, 12, 9), ecut=3.0, kf=[(0.25, -0.25, 0.0), (0.0, 0.0, 0.0)])
+KB_ATOMS = [fde_synth.Atom((1.0, 2.0, 3.0), 1.0, 0.7, lmax=1, rbeta=0.8, d_s=0.9, d_p=-0.3),
+            fde_synth.Atom((4.0, 5.5, 1.0), 1.0, 0.7, lmax=0, rbeta=0.6, d_s=1.3)]
+
+
+def small_plan(be, prec, max_nb=4, max_nproj=8, case=SMALL):
+    return fde.Plan(case["L"], case["grid"], case["ecut"], case["kf"], prec=prec, max_nb=max_nb,
+                    max_nproj=max_nproj, backend=be)
+
+
+def check_plan_sets(be, prec):
+    plan = small_plan(be, prec)
+    cell = basis.Cell(SMALL["L"], SMALL["grid"])
+    for ik, kf in enumerate(SMALL["kf"]):
+        sph = basis.sphere(cell, SMALL["ecut"], kf)
+        assert plan.npw(ik) == sph.npw
+        assert np.array_equal(plan.miller(ik), sph.miller)
+
+
+def check_apply_h(be, prec, nb=9, with_kb=True):
+    """nb > max_nb exercises the band chunking; ncol is not a multiple of the stick group."""
+    plan = small_plan(be, prec)
+    cell = basis.Cell(SMALL["L"], SMALL["grid"])
+    veff = fde_synth.random_real(4, cell.shape)
+    for ik, kf in enumerate(SMALL["kf"]):
+        sph = basis.sphere(cell, SMALL["ecut"], kf)
+        psi = fde_synth.random_complex(5 + ik, (nb, sph.npw))
+        beta = dkb = None
+        tb = tdkb = None
+        if with_kb:
+            beta, dkb = opseudo.kb_projectors(cell, sph, KB_ATOMS)
+            tb = plan.kb_projectors(ik, [a.pos for a in KB_ATOMS], [a.lmax for a in KB_ATOMS],
+                                    [a.rbeta for a in KB_ATOMS])
+            assert rel(host(tb), beta) < TOL[prec]
+            tdkb = to_dev(plan, dkb, "d")
+        ref = oham.apply_h(cell, sph, psi, veff, beta, dkb)
+        out = plan.apply_h(ik, to_dev(plan, psi, "c"), to_dev(plan, veff, "r"), tb, tdkb)
+        be.sync()
+        assert rel(host(out), ref) < TOL[prec], rel(host(out), ref)
+
+
+def check_density(be, prec, nb=7):
+    plan = small_plan(be, prec)
+    cell = basis.Cell(SMALL["L"], SMALL["grid"])
+    rho = plan.zeros_grid()
+    ref = np.zeros(cell.shape)
+    for ik, kf in enumerate(SMALL["kf"]):
+        sph = basis.sphere(cell, SMALL["ecut"], kf)
+        psi = osub.orthonormalise(fde_synth.random_complex(11 + ik, (nb, sph.npw)))
+        occw = np.linspace(1.0, 0.0, nb) * 0.5
+        ref += odens.density(cell, sph, psi, occw)
+        plan.density(ik, to_dev(plan, psi, "c"), to_dev(plan, occw, "d"), rho)
+    be.sync()
+    assert rel(host(rho), ref) < TOL[prec]
+    # charge conservation
+    assert abs(float(host(rho).sum()) * cell.dV - np.linspace(1.0, 0.0, nb).sum()) < 50 * TOL[prec]
+
+
+def _smooth_densities(cell, ecut, ns=2, nb=3, seed=20):
+    sph = basis.sphere(cell, ecut, (0.0, 0.0, 0.0))
+    out = []
+    for I in range(ns):
+        c = fde_synth.random_complex(seed + I, (nb, sph.npw)) / (1 + 2 * sph.kin)[None] ** 2
+        out.append(odens.density(cell, sph, osub.orthonormalise(c), np.full(nb, 2.0)))
+    return np.array(out)
+
+
+def check_embed(be, prec, kin=fde.KIN_LC94, grid=(12, 12, 15), L=(6.0, 6.0, 7.0), ecut=2.2, ns=2):
+    kinds = {fde.KIN_LC94: "lc94", fde.KIN_TF: "tf", fde.KIN_NONE: "none"}
+    cell = basis.Cell(L, grid)
+    rs = _smooth_densities(cell, ecut, ns=ns)
+    vloc = fde_synth.random_real(5, cell.shape, -0.3, 0.3)
+    vref, eref = oembed.embed_potential(cell, ecut, rs, vloc, kin_nad=kinds[kin])
+    plan = fde.Plan(L, grid, ecut, [(0, 0, 0)], prec=prec, max_nb=4, backend=be)
+    veff, en, info = plan.embed_potential(to_dev(plan, rs, "r"), to_dev(plan, vloc, "r"), kin_nad=kin)
+    be.sync()
+    assert int(host(info)[0]) == 0
+    assert rel(host(veff), vref) < TOL[prec]
+    assert np.max(np.abs(host(en) - eref)) < 10 * TOL[prec] * max(1.0, np.max(np.abs(eref)))
+
+
+def check_local_potential(be, prec):
+    L, grid, ecut = (6.0, 6.0, 7.0), (12, 12, 15), 2.2
+    cell = basis.Cell(L, grid)
+    atoms = [fde_synth.Atom((1.0, 2.0, 3.0), 2.0, 0.6), fde_synth.Atom((4.0, 4.5, 5.0), 1.0, 0.7)]
+    ref = opseudo.local_potential(cell, ecut, atoms)
+    plan = fde.Plan(L, grid, ecut, [(0, 0, 0)], prec=prec, max_nb=4, backend=be)
+    v = plan.local_potential([a.pos for a in atoms], [a.Z for a in atoms], [a.width for a in atoms])
+    be.sync()
+    assert rel(host(v), ref) < TOL[prec]
+
+
+def check_subspace_rr(be, prec, drop_case=False):
+    plan = small_plan(be, prec)
+    cell = basis.Cell(SMALL["L"], SMALL["grid"])
+    ik = 0
+    sph = basis.sphere(cell, SMALL["ecut"], SMALL["kf"][ik])
+    v = opseudo.local_potential(cell, SMALL["ecut"], KB_ATOMS)
+    beta, dkb = opseudo.kb_projectors(cell, sph, KB_ATOMS)
+    nb = 4
+    X = osub.orthonormalise(fde_synth.random_complex(21, (nb, sph.npw)))
+    HX = oham.apply_h(cell, sph, X, v, beta, dkb)
+    X, HX, lam = osub.subspace_rr(X, HX, nb)
+    T, active, _ = osub.precondition(X, HX, lam, sph.kin)
+    act = np.concatenate([np.ones(nb, bool), active])
+    if drop_case:
+        act[nb + 1] = False          # an inactive column
+        T[1] = 0.0
+        T[2] = X[0] + 1e-7 * T[3]     # nearly dependent: dropped by the pivot test
+    HT = oham.apply_h(cell, sph, T, v, beta, dkb)
+    Xr, HXr, lr = osub.subspace_rr(np.vstack([X, T]), np.vstack([HX, HT]), nb, act)
+    V = to_dev(plan, np.vstack([X, T]), "c")
+    HV = to_dev(plan, np.vstack([HX, HT]), "c")
+    ev, info = plan.subspace_rr(ik, V, HV, nb, active=torch.from_numpy(act.astype(np.uint8)).to(plan.be.device))
+    be.sync()
+    assert int(host(info)[0]) == 0
+    tol = 1e-11 if prec == fde.F64 else 2e-5
+    assert np.max(np.abs(host(ev) - lr)) < tol
+    Xg = host(V)[:nb]
+    # eigenvectors are unique up to a phase: compare projectors and Ritz values
+    assert np.max(np.abs(Xg.conj() @ Xg.T - np.eye(nb))) < (1e-12 if prec == fde.F64 else 1e-5)
+    P_gpu = Xg.T @ Xg.conj()
+    P_ref = Xr.T @ Xr.conj()
+    assert np.max(np.abs(P_gpu - P_ref)) < (1e-10 if prec == fde.F64 else 1e-4)
+    # HX rows are H applied to the new X
+    assert rel(host(HV)[:nb], oham.apply_h(cell, sph, Xg, v, beta, dkb)) < (1e-10 if prec == fde.F64 else 1e-4)
+
+
+def check_singular_gram(be, prec):
+    """Two identical X columns (j < nb cannot be dropped): info = column + 1, X left unchanged."""
+    plan = small_plan(be, prec)
+    sph_npw = plan.npw(0)
+    X = fde_synth.random_complex(31, (3, sph_npw))
+    X[2] = X[1]
+    V = to_dev(plan, X, "c")
+    HV = V.clone()
+    ev, info = plan.subspace_rr(0, V, HV, 3)
+    be.sync()
+    assert int(host(info)[0]) == 3
+    assert np.array_equal(host(V), X.astype(host(V).dtype))
+
+
+def check_precondition(be, prec):
+    plan = small_plan(be, prec)
+    cell = basis.Cell(SMALL["L"], SMALL["grid"])
+    ik = 0
+    sph = basis.sphere(cell, SMALL["ecut"], SMALL["kf"][ik])
+    X = fde_synth.random_complex(41, (4, sph.npw))
+    HX = fde_synth.random_complex(42, (4, sph.npw))
+    lam = np.array([0.1, -0.2, 0.3, 0.5])
+    HX[3] = lam[3] * X[3]      # zero residual -> inactive, T = 0
+    T, active, rn = osub.precondition(X, HX, lam, sph.kin)
+    t = plan.zeros_bands(4, ik)
+    act = torch.zeros(4, dtype=torch.uint8, device=plan.be.device)
+    rnorm = torch.zeros(4, dtype=torch.float64, device=plan.be.device)
+    plan.precondition(ik, to_dev(plan, X, "c"), to_dev(plan, HX, "c"), to_dev(plan, lam, "d"), t, act, rnorm)
+    be.sync()
+    assert np.array_equal(host(act).astype(bool), active)
+    assert rel(host(t), T) < TOL[prec] * 10
+    assert rel(host(rnorm)[:3], rn[:3]) < TOL[prec] * 10
+
+
+def check_occupations(be):
+    dev = be.device
+    eps = np.array([[-0.5, -0.3, -0.1, 0.2, 0.4], [-0.45, -0.28, -0.05, 0.25, 0.5]])
+    wk = np.array([0.5, 0.5])
+    for nel, mode, sig in [(6.0, "fermi-dirac", 0.01), (5.0, "fermi-dirac", 0.05), (4.0, "integer", 0.0)]:
+        f, mu = oocc.occupations(eps, wk, nel, mode, sig)
+        m = fde.OCC_INTEGER if mode == "integer" else fde.OCC_FERMI_DIRAC
+        occw, tmu, info = fde.occupations(be, torch.tensor(eps, device=dev), torch.tensor(wk, device=dev), nel, m,
+                                          max(sig, 1e-300))
+        be.sync()
+        assert int(host(info)[0]) == 0
+        assert np.max(np.abs(host(occw) - wk[:, None] * f)) < 1e-10
+        assert abs(float(host(occw).sum()) - nel) < 1e-12
+
+
+def check_trajectory(be, prec, system, n_cycles, eps_tol, drho_tol):
+    recs, _, st = oscf.run(system, n_cycles=n_cycles)
+    eng = driver.Engine(system, prec=prec, backend=be)
+    worst = (0.0, 0.0)
+    for c in range(n_cycles):
+        eng.cycle()
+        be.sync()
+        for I in range(len(system.subsystems)):
+            e = np.max(np.abs(host(eng.eps[I]) - recs[c].eps[I]))
+            d = float(np.sum(np.abs(host(eng.rho_out[I]) - recs[c].rho_out[I]))) * st.cell.dV
+            worst = (max(worst[0], e), max(worst[1], d))
+    assert all(int(host(b.info)[0]) == 0 for row in eng.blocks for b in row)
+    assert worst[0] < eps_tol and worst[1] < drho_tol, worst
+    return worst

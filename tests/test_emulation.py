@@ -1,0 +1,76 @@
+"""The library's kernel bodies run serially on the host (the FDE_EMULATE
+build) and match the oracle: indexing, FFT plans and arithmetic are checked
+without a GPU. The GPU tests repeat these cases on the MI355X."""
+import pytest
+
+import fde_synth
+from paper_1406_7803_amd import fde
+
+import parity_cases as pc
+
+PRECS = [fde.F64, fde.F32]
+
+
+@pytest.fixture(scope="module")
+def be():
+    return fde.emulation_backend()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_plan_sets(be, prec):
+    pc.check_plan_sets(be, prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_apply_h(be, prec):
+    pc.check_apply_h(be, prec)
+    pc.check_apply_h(be, prec, nb=3, with_kb=False)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_density(be, prec):
+    pc.check_density(be, prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("kin", [fde.KIN_LC94, fde.KIN_TF, fde.KIN_NONE])
+def test_embed(be, prec, kin):
+    pc.check_embed(be, prec, kin)
+
+
+def test_embed_single_subsystem(be):
+    pc.check_embed(be, fde.F64, ns=1)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_local_potential(be, prec):
+    pc.check_local_potential(be, prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("drop", [False, True])
+def test_subspace_rr(be, prec, drop):
+    pc.check_subspace_rr(be, prec, drop)
+
+
+def test_singular_gram(be):
+    pc.check_singular_gram(be, fde.F64)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_precondition(be, prec):
+    pc.check_precondition(be, prec)
+
+
+def test_occupations(be):
+    pc.check_occupations(be)
+
+
+def test_trajectory_c1_fp64(be):
+    pc.check_trajectory(be, fde.F64, fde_synth.config1(), 3, 1e-10, 1e-10)
+
+
+def test_trajectory_kpoints_projectors(be):
+    s = fde_synth.tiny(0, with_kb=True, kfrac=[(0.25, 0.0, 0.0), (-0.25, 0.0, 0.0)], grid=(12, 12, 15))
+    pc.check_trajectory(be, fde.F64, s, 3, 1e-10, 1e-10)
+    pc.check_trajectory(be, fde.F32, s, 3, 1e-6, 1e-5)
