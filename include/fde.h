@@ -88,16 +88,21 @@ fde_status fde_plan_miller(const fde_plan* plan, int ik, int32_t* mill);
 
 /*
  * Workspace size for calls with at most max_nb bands per call (subspace calls
- * use m <= 2 max_nb) and at most max_nproj projectors.
+ * use m <= 2 max_nb), at most max_nproj projectors, and batched subspace calls
+ * of at most max_batch (1..16) band blocks per launch (larger batches are
+ * split into launches of max_batch).
  */
-fde_status fde_plan_workspace_bytes(const fde_plan* plan, int max_nb, int max_nproj, size_t* bytes);
+fde_status fde_plan_workspace_bytes(const fde_plan* plan, int max_nb, int max_nproj, int max_batch,
+                                    size_t* bytes);
 
 /*
  * Attach a device workspace of at least fde_plan_workspace_bytes(max_nb,
- * max_nproj) bytes (256-byte aligned). Uploads the plan's device tables into
- * it (synchronous). The caller keeps ownership; it must outlive the plan's use.
+ * max_nproj, max_batch) bytes (256-byte aligned). Uploads the plan's device
+ * tables into it (synchronous). The caller keeps ownership; it must outlive
+ * the plan's use.
  */
-fde_status fde_plan_set_workspace(fde_plan* plan, void* d_ws, size_t bytes, int max_nb, int max_nproj);
+fde_status fde_plan_set_workspace(fde_plan* plan, void* d_ws, size_t bytes, int max_nb, int max_nproj,
+                                  int max_batch);
 
 /*
  * H_I |psi_nk> (Eq. KS with the recast V_eff of the Appendix, and the
@@ -177,12 +182,45 @@ fde_status fde_embed_potential(fde_plan* plan, int ns, const void* rho_sub, cons
  *   rows 0..nb-1 of v and hv are overwritten with X = V C and HX = HV C.
  *   active  [m] uint8 or NULL (all active).
  *   eval    [nb] double, output Theta[:nb].
- *   info    device int: 0, j+1 if column j < nb is not positive definite,
- *           -1 if the eigensolver did not converge.
+ *   info    device int: 0; j+1 if band column j < nb has a Cholesky pivot
+ *           below drop_tol*S_jj (dependent bands: rows 0..nb-1 are then left
+ *           unchanged and eval is NaN); -1 if the eigensolver did not converge.
  */
 fde_status fde_subspace_rr(fde_plan* plan, int ik, int m, int nb, void* v, void* hv,
                            const uint8_t* active, double drop_tol, double* eval, int* info,
                            hipStream_t stream);
+
+/*
+ * One band block of the solver: the bands of one subsystem at one k-point.
+ * v and hv are [m][npw] with rows 0..nb-1 = X, HX and rows nb..m-1 the
+ * corrections T, HT (m = nb or 2 nb). Fields not used by a call may be NULL.
+ */
+typedef struct fde_block {
+  int ik;              /* k-point index of the plan                          */
+  int nb;              /* bands                                              */
+  int m;               /* rows of v/hv entering the Rayleigh-Ritz step       */
+  void* v;             /* [m][npw] complex                                   */
+  void* hv;            /* [m][npw] complex                                   */
+  const uint8_t* active; /* [m] Rayleigh-Ritz column flags (NULL: all)        */
+  uint8_t* t_active;   /* [nb] preconditioner output: flags of rows nb..2nb-1 */
+  double* eval;        /* [nb] Ritz values (Rayleigh-Ritz output, preconditioner input) */
+  double* rnorm;       /* [nb] residual norms (preconditioner output)        */
+  int* info;           /* [1] Rayleigh-Ritz status, as fde_subspace_rr        */
+} fde_block;
+
+/*
+ * fde_subspace_rr on nblk independent band blocks in one set of launches
+ * (one workgroup per block for the FP64 solve). blk is a host array.
+ */
+fde_status fde_subspace_rr_batched(fde_plan* plan, int nblk, const fde_block* blk, double drop_tol,
+                                   hipStream_t stream);
+
+/*
+ * fde_precondition on nblk band blocks: for each block, reads X, HX = rows
+ * 0..nb-1 of v, hv and eval, writes T into rows nb..2nb-1 of v, t_active and
+ * rnorm. blk is a host array.
+ */
+fde_status fde_precondition_batched(fde_plan* plan, int nblk, const fde_block* blk, hipStream_t stream);
 
 /*
  * Residual and Teter-Payne-Allan preconditioner of the band solver:

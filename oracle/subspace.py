@@ -92,7 +92,8 @@ def cholesky_drop(S: np.ndarray, first_droppable: int, tol: float):
 
     Column j >= first_droppable whose pivot S_jj - sum_k |L_jk|^2 falls below
     tol * S_jj is treated as masked: its row and column become e_j (exactly the
-    factor of S with row/column j replaced by e_j). Returns (L, dropped).
+    factor of S with row/column j replaced by e_j). A band column (j <
+    first_droppable) with such a pivot is an error. Returns (L, dropped).
     """
     m = S.shape[0]
     L = np.zeros_like(S)
@@ -104,8 +105,8 @@ def cholesky_drop(S: np.ndarray, first_droppable: int, tol: float):
             L[j, j] = 1.0
             dropped.append(j)
             continue
-        if not d > 0.0:
-            raise np.linalg.LinAlgError(f"Gram matrix not positive definite at column {j}")
+        if not d >= tol * S[j, j].real:
+            raise np.linalg.LinAlgError(f"band column {j} is linearly dependent (pivot {d:.3e})")
         L[j, j] = np.sqrt(d)
         for i in range(j + 1, m):
             L[i, j] = (S[i, j] - np.sum(L[i, :j] * L[j, :j].conj())) / L[j, j]

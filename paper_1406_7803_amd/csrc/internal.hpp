@@ -43,7 +43,7 @@ struct fde_plan {
   // workspace
   char* ws = nullptr;
   size_t ws_bytes = 0;
-  int max_nb = 0, max_nproj = 0;
+  int max_nb = 0, max_nproj = 0, max_batch = 1;
   void* d_tw[3] = {nullptr, nullptr, nullptr};  // twiddles exp(-2 pi i m/N_a), plan precision
   char* scratch = nullptr;
   size_t scratch_bytes = 0;
@@ -72,7 +72,8 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 size_t scratch_apply(const fde_plan* p, int max_nb, int max_nproj);
 size_t scratch_density(const fde_plan* p, int max_nb);
 size_t scratch_embed(const fde_plan* p);
-size_t scratch_subspace(const fde_plan* p, int max_nb);
+size_t scratch_subspace(const fde_plan* p, int max_nb, int max_batch);
+size_t rr_problem_bytes(const fde_plan* p, int mcap, int nbcap);
 
 fde_status check_plan(const fde_plan* p, int ik);
 

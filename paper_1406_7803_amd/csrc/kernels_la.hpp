@@ -10,125 +10,83 @@ namespace fde {
 constexpr int kLBlk = 256;
 constexpr double kInactiveDiag = 1.0e6;
 
-// ---------------------------------------------------------------------------
-// Gram partials: part[chunk][0][i][j] = sum_{G in chunk} conj(V_i) V_j,
-//                part[chunk][1][i][j] = sum_{G in chunk} conj(V_i) HV_j.
-// grid (nchunk, ceil(m/TI), ceil(m/TI)); chunk = 2048 plane waves.
-// ---------------------------------------------------------------------------
+
+constexpr int kMaxBatch = 16;   // problems per batched launch (descriptors travel as kernel arguments)
+constexpr int kMaxChunks = 16;  // plane-wave chunks of a Gram product
+
+// One band block of the solver: a (subsystem, k-point) pair. Rows 0..nb-1 of
+// v/hv are X/HX, rows nb..m-1 the correction vectors T/HT.
 template <typename T>
-struct KGram {
-  static constexpr int CH = 2048, TG = 32, TI = 32;
-  static size_t lds_bytes() { return sizeof(cplx<T>) * 3 * TI * TG + sizeof(cplx<double>) * 2 * TI * TI; }
-  template <class Ctx>
-  FDE_HD static void run(const Ctx& c, char* lds, const cplx<T>* __restrict__ v, const cplx<T>* __restrict__ hv,
-                         int npw, int m, cplx<double>* __restrict__ part) {
-    const int g0 = c.bx() * CH;
-    const int i0 = c.by() * TI, j0 = c.bz() * TI;
-    cplx<T>* sA = (cplx<T>*)lds;   // V_i   [TI][TG]
-    cplx<T>* sB = sA + TI * TG;    // V_j   [TI][TG]
-    cplx<T>* sH = sB + TI * TG;    // HV_j  [TI][TG]
-    cplx<double>* accS = (cplx<double>*)(sH + TI * TG);
-    cplx<double>* accA = accS + TI * TI;
-    for (int o = c.tid(); o < TI * TI; o += c.nthr()) {
-      accS[o] = mk<double>(0, 0);
-      accA[o] = mk<double>(0, 0);
-    }
-    const int gend = (g0 + CH) < npw ? (g0 + CH) : npw;
-    for (int gs = g0; gs < gend; gs += TG) {
-      for (int idx = c.tid(); idx < TI * TG; idx += c.nthr()) {
-        const int r = idx / TG, g = gs + (idx - r * TG);
-        const bool gi = g < gend;
-        sA[idx] = (i0 + r < m && gi) ? v[(size_t)(i0 + r) * npw + g] : mk<T>(0, 0);
-        sB[idx] = (j0 + r < m && gi) ? v[(size_t)(j0 + r) * npw + g] : mk<T>(0, 0);
-        sH[idx] = (j0 + r < m && gi) ? hv[(size_t)(j0 + r) * npw + g] : mk<T>(0, 0);
-      }
-      c.sync();
-      for (int o = c.tid(); o < TI * TI; o += c.nthr()) {
-        const int i = o / TI, j = o - i * TI;
-        double sx = 0, sy = 0, ax = 0, ay = 0;
-        for (int g = 0; g < TG; ++g) {
-          const cplx<T> a = sA[i * TG + g];
-          const cplx<T> b = sB[j * TG + g];
-          const cplx<T> h = sH[j * TG + g];
-          sx += (double)a.x * b.x + (double)a.y * b.y;
-          sy += (double)a.x * b.y - (double)a.y * b.x;
-          ax += (double)a.x * h.x + (double)a.y * h.y;
-          ay += (double)a.x * h.y - (double)a.y * h.x;
-        }
-        accS[o].x += sx;
-        accS[o].y += sy;
-        accA[o].x += ax;
-        accA[o].y += ay;
-      }
-      c.sync();
-    }
-    const size_t mm = (size_t)m * m;
-    for (int o = c.tid(); o < TI * TI; o += c.nthr()) {
-      const int i = o / TI, j = o - i * TI;
-      if (i0 + i < m && j0 + j < m) {
-        const size_t e = (size_t)(i0 + i) * m + j0 + j;
-        part[(size_t)c.bx() * 2 * mm + e] = accS[o];
-        part[(size_t)c.bx() * 2 * mm + mm + e] = accA[o];
-      }
-    }
-  }
+struct Prob {
+  cplx<T>* v;
+  cplx<T>* hv;
+  cplx<T>* t;              // [nb][npw] preconditioner output (rows nb.. of v in a block)
+  const uint8_t* active;   // [m] or null (Rayleigh-Ritz input)
+  uint8_t* act_out;        // [nb] (preconditioner output, the T rows' flags)
+  double* eval;            // [nb]
+  double* rnorm;           // [nb]
+  int* info;
+  const int* millp;        // packed Miller indices [npw]
+  double kf[3];
+  int npw, m, nb, nchunk, chunk;
+  // per-problem scratch
+  cplx<double>* part;      // Gram partials [nchunk][2][m][m]
+  cplx<double>*S, *A, *L, *B, *W, *Cd;
+  void* Ct;                // C in plan precision [m][nb]
+  double* theta;
+  int* order;
+  int* masked;
 };
 
-// S, A = sum over chunks (fixed order). grid ceil(2*m*m/256)
+template <typename T>
+struct ProbSet {
+  int n;
+  double b[3];
+  double drop_tol;
+  Prob<T> p[kMaxBatch];
+};
+
+// S, A = sum over chunks (fixed order). grid (ceil(2 m^2/256), n)
+template <typename T>
 struct KGramReduce {
   template <class Ctx>
-  FDE_HD static void run(const Ctx& c, char*, const cplx<double>* __restrict__ part, int nchunk, int m,
-                         cplx<double>* __restrict__ S, cplx<double>* __restrict__ A) {
-    const size_t mm = (size_t)m * m;
+  FDE_HD static void run(const Ctx& c, char*, const ProbSet<T> ps) {
+    const Prob<T>& P = ps.p[c.by()];
+    const size_t mm = (size_t)P.m * P.m;
     for (int l = c.tid(); l < kLBlk; l += c.nthr()) {
       const size_t o = (size_t)c.bx() * kLBlk + l;
       if (o >= 2 * mm) break;
       double sx = 0, sy = 0;
-      for (int k = 0; k < nchunk; ++k) {
-        const cplx<double> v = part[(size_t)k * 2 * mm + o];
+      for (int k = 0; k < P.nchunk; ++k) {
+        const cplx<double> v = P.part[(size_t)k * 2 * mm + o];
         sx += v.x;
         sy += v.y;
       }
-      if (o < mm) S[o] = mk<double>(sx, sy);
-      else A[o - mm] = mk<double>(sx, sy);
+      if (o < mm) P.S[o] = mk<double>(sx, sy);
+      else P.A[o - mm] = mk<double>(sx, sy);
     }
   }
 };
 
-// ---------------------------------------------------------------------------
-// Single-workgroup FP64 Rayleigh-Ritz solve. Matrices row-major [i][j] in
-// global memory (L2 resident at these sizes). Uses LDS for: reduction scratch
-// (17 doubles), rotation parameters (3*mp/2 + 2 doubles), flags.
-//   In:  S, A (overwritten), active[m] (nullable), nb, drop_tol
-//   Out: eval[nb], Cd[m][nb] (FP64), Ct[m][nb] (plan precision), info
-// ---------------------------------------------------------------------------
-struct RRArgs {
-  cplx<double>*S, *A, *L, *B, *W;
-  const uint8_t* active;
-  int m, nb;
-  double drop_tol;
-  double* eval;
-  cplx<double>* Cd;
-  void* Ct;
-  int ct_double;
-  int* info;
-  int* order;      // [m] scratch
-  double* theta;   // [m] scratch
-  int* masked;     // [m] scratch
-};
-
 FDE_HD cplx<double> cdiv_real(cplx<double> a, double d) { return mk<double>(a.x / d, a.y / d); }
 
+template <typename T>
 struct KRRSolve {
-  static size_t lds_bytes(int m) { return sizeof(double) * (32 + 4 * ((m + 2) / 2 + 1)); }
+  // reduction scratch + rotation parameters; the Jacobi matrices A~ and W are
+  // staged in LDS when they fit in `lds_mats` bytes (A~ first, then W).
+  FDE_HD static size_t lds_fixed(int m) { return sizeof(double) * (32 + 4 * ((m + 2) / 2 + 1)); }
 
   template <class Ctx>
-  FDE_HD static void run(const Ctx& c, char* lds, RRArgs a) {
+  FDE_HD static void run(const Ctx& c, char* lds, const ProbSet<T> ps, size_t lds_mats) {
+    const Prob<T>& a = ps.p[c.bx()];
     double* red = (double*)lds;            // 17 used
     double* rot = red + 32;                // [4][mp/2]
     const int m = a.m, nb = a.nb;
     const int tid = c.tid(), nt = c.nthr();
     cplx<double>*S = a.S, *A = a.A, *L = a.L, *B = a.B, *W = a.W;
+    const double drop_tol = ps.drop_tol;
+    char* mats = lds + ((lds_fixed(m) + 15) & ~(size_t)15);
+    const size_t mbytes = (size_t)m * m * sizeof(cplx<double>);
     if (tid == 0) a.info[0] = 0;
     // ---- masks
     for (int j = tid; j < m; j += nt) a.masked[j] = (a.active && !a.active[j]) ? 1 : 0;
@@ -148,7 +106,7 @@ struct KRRSolve {
       for (int k = tid; k < j; k += nt) part += norm2(L[(size_t)j * m + k]);
       const double sjj = S[(size_t)j * m + j].x;
       const double d = sjj - c.sum(part, red);
-      const bool drop = (j >= nb) && !(d >= a.drop_tol * sjj);
+      const bool drop = (j >= nb) && !(d >= drop_tol * sjj);
       if (drop) {
         for (int k = tid; k < j; k += nt) L[(size_t)j * m + k] = mk<double>(0, 0);
         for (int i = tid; i < m; i += nt) {
@@ -165,15 +123,15 @@ struct KRRSolve {
         c.sync();
         continue;
       }
-      if (!(d > 0.0)) {
-        // not positive definite: report, and leave X = the first nb columns of V
+      if (!(d >= drop_tol * sjj) || !(d > 0.0)) {
+        // a band column (j < nb) that is (numerically) dependent: report, and
+        // leave X = the first nb columns of V
         if (tid == 0) a.info[0] = j + 1;
         for (int e = tid; e < m * nb; e += nt) {
           const int i = e / nb, n = e - i * nb;
           const cplx<double> v = mk<double>(i == n ? 1.0 : 0.0, 0.0);
           a.Cd[e] = v;
-          if (a.ct_double) ((cplx<double>*)a.Ct)[e] = v;
-          else ((cplx<float>*)a.Ct)[e] = mk<float>((float)v.x, 0.0f);
+          ((cplx<T>*)a.Ct)[e] = mk<T>((T)v.x, (T)v.y);
         }
         for (int n = tid; n < nb; n += nt) a.eval[n] = 0.0 / 0.0;
         c.sync();
@@ -210,20 +168,24 @@ struct KRRSolve {
       }
     }
     c.sync();
-    // hermitise: A~ <- (A~ + A~^H)/2
+    // hermitise: A~ <- (A~ + A~^H)/2, staged into LDS when it fits
+    cplx<double>* Aj = (mbytes <= lds_mats) ? (cplx<double>*)mats : A;
+    cplx<double>* Wj = (2 * mbytes <= lds_mats) ? (cplx<double>*)(mats + mbytes) : W;
     for (int e = tid; e < m * m; e += nt) {
       const int i = e / m, j = e - i * m;
       if (i < j) {
         const cplx<double> u = A[(size_t)i * m + j], l = A[(size_t)j * m + i];
         const cplx<double> h = mk<double>(0.5 * (u.x + l.x), 0.5 * (u.y - l.y));
-        A[(size_t)i * m + j] = h;
-        A[(size_t)j * m + i] = conj(h);
+        Aj[(size_t)i * m + j] = h;
+        Aj[(size_t)j * m + i] = conj(h);
       } else if (i == j) {
-        A[e].y = 0.0;
+        Aj[e] = mk<double>(A[e].x, 0.0);
       }
-      W[e] = mk<double>(i == j ? 1.0 : 0.0, 0.0);
+      Wj[e] = mk<double>(i == j ? 1.0 : 0.0, 0.0);
     }
     c.sync();
+    A = Aj;
+    W = Wj;
     // ---- cyclic parallel Jacobi (round-robin pairs), W accumulates U
     const int mp = m + (m & 1);
     const int npair = mp / 2;
@@ -351,71 +313,74 @@ struct KRRSolve {
     c.sync();
     for (int e = tid; e < m * nb; e += nt) {
       const cplx<double> v = a.Cd[e];
-      if (a.ct_double) ((cplx<double>*)a.Ct)[e] = v;
-      else ((cplx<float>*)a.Ct)[e] = mk<float>((float)v.x, (float)v.y);
+      ((cplx<T>*)a.Ct)[e] = mk<T>((T)v.x, (T)v.y);
     }
   }
 };
 
 // ---------------------------------------------------------------------------
-// Rotation X[n][G] = sum_j C[j][n] V[j][G]; grid (ceil(npw/256), ceil(nb/16)).
-// C chunk of JC rows staged in LDS.
+// In-place rotation of every problem: rows 0..nb-1 of V (grid.y = 0) or HV
+// (grid.y = 1) become sum_j C[j][n] V_j. Each block stages its plane-wave
+// chunk of all m rows in LDS first, so overwriting rows 0..nb-1 is safe.
+// grid (ceil(npw_max/GC), 2, n)
 // ---------------------------------------------------------------------------
 template <typename T>
 struct KRotate {
-  static constexpr int NT = 16, JC = 64;
-  static size_t lds_bytes() { return sizeof(cplx<T>) * JC * NT; }
   template <class Ctx>
-  FDE_HD static void run(const Ctx& c, char* lds, const cplx<T>* __restrict__ v, const cplx<T>* __restrict__ C,
-                         cplx<T>* __restrict__ x, int npw, int m, int nb) {
-    cplx<T>* sC = (cplx<T>*)lds;
-    const int n0 = c.by() * NT;
-    // each thread owns G = bx*256 + l for l = tid, tid + nthr, ...; partial sums kept in x
-    for (int j0 = 0; j0 < m; j0 += JC) {
-      const int jc = (m - j0) < JC ? (m - j0) : JC;
-      for (int idx = c.tid(); idx < JC * NT; idx += c.nthr()) {
-        const int j = idx / NT, q = idx - j * NT;
-        sC[idx] = (j < jc && n0 + q < nb) ? C[(size_t)(j0 + j) * nb + n0 + q] : mk<T>(0, 0);
-      }
-      c.sync();
-      for (int l = c.tid(); l < kLBlk; l += c.nthr()) {
-        const int g = c.bx() * kLBlk + l;
-        if (g >= npw) break;
-        cplx<T> acc[NT];
-        for (int q = 0; q < NT; ++q) acc[q] = (j0 == 0 || n0 + q >= nb) ? mk<T>(0, 0) : x[(size_t)(n0 + q) * npw + g];
-        for (int j = 0; j < jc; ++j) {
-          const cplx<T> vv = v[(size_t)(j0 + j) * npw + g];
-          for (int q = 0; q < NT; ++q) acc[q] = acc[q] + vv * sC[j * NT + q];
-        }
-        for (int q = 0; q < NT && n0 + q < nb; ++q) x[(size_t)(n0 + q) * npw + g] = acc[q];
-      }
-      c.sync();
+  FDE_HD static void run(const Ctx& c, char* lds, const ProbSet<T> ps, int GC, int c_in_lds) {
+    const Prob<T>& P = ps.p[c.bz()];
+    const int m = P.m, nb = P.nb, npw = P.npw;
+    const int g0 = c.bx() * GC;
+    if (g0 >= npw) return;  // uniform per block
+    const int gc = (npw - g0) < GC ? (npw - g0) : GC;
+    cplx<T>* M = c.by() == 0 ? P.v : P.hv;
+    const cplx<T>* Cg = (const cplx<T>*)P.Ct;
+    cplx<T>* sV = (cplx<T>*)lds;               // [m][GC]
+    cplx<T>* sC = sV + (size_t)m * GC;         // [m][nb] when staged
+    for (int idx = c.tid(); idx < m * GC; idx += c.nthr()) {
+      const int j = idx / GC, g = idx - j * GC;
+      sV[idx] = g < gc ? M[(size_t)j * npw + g0 + g] : mk<T>(0, 0);
+    }
+    if (c_in_lds)
+      for (int idx = c.tid(); idx < m * nb; idx += c.nthr()) sC[idx] = Cg[idx];
+    c.sync();
+    const cplx<T>* Cs = c_in_lds ? sC : Cg;
+    for (int o = c.tid(); o < nb * GC; o += c.nthr()) {
+      const int n = o / GC, g = o - n * GC;
+      if (g >= gc) continue;
+      cplx<T> acc = mk<T>(0, 0);
+      for (int j = 0; j < m; ++j) acc = acc + sV[j * GC + g] * Cs[(size_t)j * nb + n];
+      M[(size_t)n * npw + g0 + g] = acc;
     }
   }
 };
 
 // ---------------------------------------------------------------------------
-// Residual + TPA preconditioner, one block per band.
+// Residual + Teter-Payne-Allan preconditioner of every problem; block (n, p)
+// handles band n of problem p and writes the correction T_n into row n of its
+// t (rows nb.. of V in a band block). grid (nb_max, n)
 // ---------------------------------------------------------------------------
 template <typename T>
 struct KPrecond {
   template <class Ctx>
-  FDE_HD static void run(const Ctx& c, char* lds, const cplx<T>* __restrict__ x, const cplx<T>* __restrict__ hx,
-                         const double* __restrict__ eval, cplx<T>* __restrict__ t, uint8_t* __restrict__ active,
-                         double* __restrict__ rnorm, const int* __restrict__ millp, int npw, double kf0, double kf1,
-                         double kf2, double b0, double b1, double b2) {
-    double* red = (double*)lds;
+  FDE_HD static void run(const Ctx& c, char* lds, const ProbSet<T> ps) {
+    const Prob<T>& P = ps.p[c.by()];
     const int n = c.bx();
-    const double lam = eval[n];
-    const cplx<T>* xn = x + (size_t)n * npw;
-    const cplx<T>* hn = hx + (size_t)n * npw;
-    cplx<T>* tn = t + (size_t)n * npw;
+    if (n >= P.nb) return;  // uniform per block
+    double* red = (double*)lds;
+    const int npw = P.npw;
+    const double lam = P.eval[n];
+    const cplx<T>* xn = P.v + (size_t)n * npw;
+    const cplx<T>* hn = P.hv + (size_t)n * npw;
+    cplx<T>* tn = P.t + (size_t)n * npw;
+    const double kf0 = P.kf[0], kf1 = P.kf[1], kf2 = P.kf[2];
+    const double b0 = ps.b[0], b1 = ps.b[1], b2 = ps.b[2];
     double r2 = 0.0, tk = 0.0;
     for (int g = c.tid(); g < npw; g += c.nthr()) {
       const cplx<T> xv = xn[g], hv = hn[g];
       const double rx = (double)hv.x - lam * xv.x, ry = (double)hv.y - lam * xv.y;
       r2 += rx * rx + ry * ry;
-      const int p = millp[g];
+      const int p = P.millp[g];
       const double q1 = (((p & 1023) - 512) + kf0) * b0;
       const double q2 = ((((p >> 10) & 1023) - 512) + kf1) * b1;
       const double q3 = ((((p >> 20) & 1023) - 512) + kf2) * b2;
@@ -429,7 +394,7 @@ struct KPrecond {
     for (int g = c.tid(); g < npw; g += c.nthr()) {
       const cplx<T> xv = xn[g], hv = hn[g];
       const double rx = (double)hv.x - lam * xv.x, ry = (double)hv.y - lam * xv.y;
-      const int p = millp[g];
+      const int p = P.millp[g];
       const double q1 = (((p & 1023) - 512) + kf0) * b0;
       const double q2 = ((((p >> 10) & 1023) - 512) + kf1) * b1;
       const double q3 = ((((p >> 20) & 1023) - 512) + kf2) * b2;
@@ -447,8 +412,8 @@ struct KPrecond {
       tn[g] = mk<T>((T)(sc * v.x), (T)(sc * v.y));
     }
     if (c.tid() == 0) {
-      active[n] = act ? 1 : 0;
-      rnorm[n] = rn;
+      P.act_out[n] = act ? 1 : 0;
+      P.rnorm[n] = rn;
     }
   }
 };

@@ -281,52 +281,8 @@ struct KRhoReduce {
 };
 
 // ---------------------------------------------------------------------------
-// Kleinman-Bylander products.
-// KKbProj: partial[chunk][i][n] = sum_{G in chunk} conj(beta_i(G)) psi_n(G)
-//   grid (nchunk, ceil(nproj/32), ceil(nb/32)); chunk = 2048 plane waves.
+// Kleinman-Bylander products (the projections <beta_i|psi_n> come from KAhB).
 // ---------------------------------------------------------------------------
-template <typename T>
-struct KKbProj {
-  static constexpr int CH = 2048, TG = 64, TI = 32, TN = 32;
-  static size_t lds_bytes() { return sizeof(cplx<T>) * (TI + TN) * TG + sizeof(cplx<double>) * TI * TN; }
-  template <class Ctx>
-  FDE_HD static void run(const Ctx& c, char* lds, const cplx<T>* __restrict__ beta, const cplx<T>* __restrict__ psi,
-                         int npw, int nproj, int nb, cplx<double>* __restrict__ part) {
-    const int g0 = c.bx() * CH;
-    const int i0 = c.by() * TI, n0 = c.bz() * TN;
-    cplx<T>* sB = (cplx<T>*)lds;       // [TI][TG]
-    cplx<T>* sP = sB + TI * TG;        // [TN][TG]
-    cplx<double>* acc = (cplx<double>*)(sP + TN * TG);  // [TI][TN]
-    for (int o = c.tid(); o < TI * TN; o += c.nthr()) acc[o] = mk<double>(0, 0);
-    const int gend = (g0 + CH) < npw ? (g0 + CH) : npw;
-    for (int gs = g0; gs < gend; gs += TG) {
-      for (int idx = c.tid(); idx < TI * TG; idx += c.nthr()) {
-        const int r = idx / TG, g = gs + (idx - r * TG);
-        sB[idx] = (i0 + r < nproj && g < gend) ? beta[(size_t)(i0 + r) * npw + g] : mk<T>(0, 0);
-        sP[idx] = (n0 + r < nb && g < gend) ? psi[(size_t)(n0 + r) * npw + g] : mk<T>(0, 0);
-      }
-      c.sync();
-      for (int o = c.tid(); o < TI * TN; o += c.nthr()) {
-        const int i = o / TN, n = o - i * TN;
-        double ax = 0, ay = 0;
-        for (int g = 0; g < TG; ++g) {
-          const cplx<T> bv = sB[i * TG + g];
-          const cplx<T> pv = sP[n * TG + g];
-          ax += (double)bv.x * pv.x + (double)bv.y * pv.y;
-          ay += (double)bv.x * pv.y - (double)bv.y * pv.x;
-        }
-        acc[o].x += ax;
-        acc[o].y += ay;
-      }
-      c.sync();
-    }
-    for (int o = c.tid(); o < TI * TN; o += c.nthr()) {
-      const int i = o / TN, n = o - i * TN;
-      if (i0 + i < nproj && n0 + n < nb) part[((size_t)c.bx() * nproj + i0 + i) * nb + n0 + n] = acc[o];
-    }
-  }
-};
-
 // dp[i][n] = D_i * sum_chunk part[chunk][i][n]   (grid ceil(nproj*nb/256))
 template <typename T>
 struct KKbReduce {

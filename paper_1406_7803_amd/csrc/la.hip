@@ -1,62 +1,154 @@
-// Host entry points of the band-solver kernels: fde_subspace_rr,
-// fde_precondition, fde_occupations.
+// Host entry points of the band-solver kernels: fde_subspace_rr(_batched),
+// fde_precondition(_batched), fde_occupations.
 #include <algorithm>
 
+#include "kernels_gemm.hpp"
 #include "kernels_la.hpp"
 #include "launch.hpp"
 
 namespace fde {
 
+// Per-problem scratch of the Rayleigh-Ritz solve, for m <= mcap.
+size_t rr_problem_bytes(const fde_plan* p, int mcap, int nbcap) {
+  const size_t mm = (size_t)mcap * mcap;
+  size_t s = align256((size_t)kMaxChunks * 2 * mm * 16);  // Gram partials
+  s += 5 * align256(mm * 16);                            // S, A, L, B, W
+  s += align256((size_t)mcap * nbcap * 16);              // C (FP64)
+  s += align256((size_t)mcap * nbcap * p->csize());      // C (plan precision)
+  s += align256(4 * (size_t)mcap * sizeof(double) + 2 * (size_t)mcap * sizeof(int));
+  return s;
+}
+
 template <typename T>
-static fde_status rr_t(fde_plan* p, int ik, int m, int nb, cplx<T>* v, cplx<T>* hv, const uint8_t* active,
-                       double drop_tol, double* eval, int* info, hipStream_t s) {
-  const KTables& t = p->k[ik];
+static void bind_scratch(fde_plan* p, int slot, Prob<T>& P) {
   const int mcap = 2 * p->max_nb;
   const size_t mm = (size_t)mcap * mcap;
-  char* w = p->scratch;
+  char* w = p->scratch + (size_t)slot * rr_problem_bytes(p, mcap, p->max_nb);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     char* r = w + off;
     off += align256(bytes);
     return r;
   };
-  RRArgs a;
-  a.S = (cplx<double>*)take(mm * 16);
-  a.A = (cplx<double>*)take(mm * 16);
-  a.L = (cplx<double>*)take(mm * 16);
-  a.B = (cplx<double>*)take(mm * 16);
-  a.W = (cplx<double>*)take(mm * 16);
-  a.Cd = (cplx<double>*)take((size_t)mcap * p->max_nb * 16);
-  a.Ct = take((size_t)mcap * p->max_nb * p->csize());
-  cplx<T>* xs = (cplx<T>*)take((size_t)p->max_nb * p->npw_max * sizeof(cplx<T>));
-  cplx<T>* hxs = (cplx<T>*)take((size_t)p->max_nb * p->npw_max * sizeof(cplx<T>));
-  const int nchunk = (t.npw + KGram<T>::CH - 1) / KGram<T>::CH;
-  const int nchunk_cap = (p->npw_max + 2047) / 2048;
-  cplx<double>* part = (cplx<double>*)take((size_t)nchunk_cap * mm * 16 * 2);
-  char* misc = take(4 * (size_t)mcap * sizeof(double) + mcap * sizeof(int));
-  a.theta = (double*)misc;
-  a.order = (int*)(misc + (size_t)mcap * sizeof(double));
-  a.masked = (int*)(misc + (size_t)mcap * (sizeof(double) + sizeof(int)));
-  a.active = active;
-  a.m = m;
-  a.nb = nb;
-  a.drop_tol = drop_tol;
-  a.eval = eval;
-  a.ct_double = (sizeof(T) == 8);
-  a.info = info;
-  const int ti = KGram<T>::TI;
-  FDE_TRY(launch<KGram<T>>(dim3(nchunk, (m + ti - 1) / ti, (m + ti - 1) / ti), kBlock, KGram<T>::lds_bytes(), s,
-                           (const cplx<T>*)v, (const cplx<T>*)hv, t.npw, m, part));
-  FDE_TRY(launch<KGramReduce>(dim3((unsigned)((2 * (size_t)m * m + kLBlk - 1) / kLBlk)), kBlock, 0, s,
-                              (const cplx<double>*)part, nchunk, m, a.S, a.A));
-  FDE_TRY((launch<KRRSolve, 1024>(dim3(1), 1024, KRRSolve::lds_bytes(m), s, a)));
-  const dim3 rg((t.npw + kLBlk - 1) / kLBlk, (nb + KRotate<T>::NT - 1) / KRotate<T>::NT);
-  FDE_TRY(launch<KRotate<T>>(rg, kBlock, KRotate<T>::lds_bytes(), s, (const cplx<T>*)v, (const cplx<T>*)a.Ct, xs,
-                             t.npw, m, nb));
-  FDE_TRY(launch<KRotate<T>>(rg, kBlock, KRotate<T>::lds_bytes(), s, (const cplx<T>*)hv, (const cplx<T>*)a.Ct, hxs,
-                             t.npw, m, nb));
-  FDE_TRY(copy_d2d(v, xs, (size_t)nb * t.npw * sizeof(cplx<T>), s));
-  FDE_TRY(copy_d2d(hv, hxs, (size_t)nb * t.npw * sizeof(cplx<T>), s));
+  P.part = (cplx<double>*)take((size_t)kMaxChunks * 2 * mm * 16);
+  P.S = (cplx<double>*)take(mm * 16);
+  P.A = (cplx<double>*)take(mm * 16);
+  P.L = (cplx<double>*)take(mm * 16);
+  P.B = (cplx<double>*)take(mm * 16);
+  P.W = (cplx<double>*)take(mm * 16);
+  P.Cd = (cplx<double>*)take((size_t)mcap * p->max_nb * 16);
+  P.Ct = take((size_t)mcap * p->max_nb * sizeof(cplx<T>));
+  char* misc = take(4 * (size_t)mcap * sizeof(double) + 2 * (size_t)mcap * sizeof(int));
+  P.theta = (double*)misc;
+  P.order = (int*)(misc + (size_t)mcap * sizeof(double));
+  P.masked = (int*)(misc + (size_t)mcap * (sizeof(double) + sizeof(int)));
+}
+
+static fde_status check_block(const fde_plan* p, const fde_block& b, bool rr) {
+  if (b.ik < 0 || b.ik >= p->nk) return fail(FDE_ERR_ARG, "block k-point index out of range");
+  if (!b.v || !b.hv || !b.eval) return fail(FDE_ERR_ARG, "block: null v, hv or eval");
+  if (b.v == b.hv) return fail(FDE_ERR_ARG, "block: hv must not alias v");
+  if (b.nb < 1 || b.nb > p->max_nb) return fail(FDE_ERR_SHAPE, "block: nb must be in [1, max_nb]");
+  if (rr) {
+    if (b.m < b.nb || b.m > 2 * p->max_nb) return fail(FDE_ERR_SHAPE, "block: need nb <= m <= 2 max_nb");
+    if (!b.info) return fail(FDE_ERR_ARG, "block: null info");
+  } else if (!b.rnorm || !b.t_active) {
+    return fail(FDE_ERR_ARG, "block: null rnorm or t_active");
+  }
+  return FDE_OK;
+}
+
+template <typename T>
+static Prob<T> make_prob(fde_plan* p, const fde_block& b) {
+  Prob<T> P;
+  const KTables& t = p->k[b.ik];
+  P.v = (cplx<T>*)b.v;
+  P.hv = (cplx<T>*)b.hv;
+  P.t = P.v + (size_t)b.nb * t.npw;
+  P.active = b.active;
+  P.act_out = b.t_active;
+  P.eval = b.eval;
+  P.rnorm = b.rnorm;
+  P.info = b.info;
+  P.millp = (const int*)t.d_millp;
+  for (int i = 0; i < 3; ++i) P.kf[i] = t.kf[i];
+  P.npw = t.npw;
+  P.m = b.m;
+  P.nb = b.nb;
+  P.nchunk = std::min(kMaxChunks, (t.npw + 2047) / 2048);
+  P.chunk = (t.npw + P.nchunk - 1) / P.nchunk;
+  P.chunk = (P.chunk + 31) / 32 * 32;
+  return P;
+}
+
+template <typename T>
+static fde_status rr_launch(fde_plan* p, ProbSet<T>& ps, hipStream_t s) {
+  int mmax = 0, nbmax = 0, npwmax = 0;
+  for (int i = 0; i < ps.n; ++i) {
+    mmax = std::max(mmax, ps.p[i].m);
+    nbmax = std::max(nbmax, ps.p[i].nb);
+    npwmax = std::max(npwmax, ps.p[i].npw);
+  }
+  AhBSet<T> gs;
+  gs.n = ps.n;
+  for (int i = 0; i < ps.n; ++i) {
+    const Prob<T>& P = ps.p[i];
+    gs.p[i] = AhBProb<T>{P.v, P.v, P.hv, P.m, P.m, P.npw, P.nchunk, P.chunk, P.part};
+  }
+  const int nt = (mmax + KAhB<T>::TI - 1) / KAhB<T>::TI;
+  FDE_TRY(launch<KAhB<T>>(dim3(kMaxChunks, nt * nt, ps.n), kBlock, KAhB<T>::lds_bytes(), s, gs));
+  FDE_TRY(launch<KGramReduce<T>>(dim3((unsigned)((2 * (size_t)mmax * mmax + kLBlk - 1) / kLBlk), ps.n), kBlock, 0, s,
+                                 ps));
+  // LDS: fixed part + as much of the Jacobi matrices as fits in 160 KiB
+  const size_t fixed = (KRRSolve<T>::lds_fixed(mmax) + 15) & ~(size_t)15;
+  const size_t mbytes = (size_t)mmax * mmax * sizeof(cplx<double>);
+  size_t mats = 0;
+  if (fixed + 2 * mbytes <= kLdsMax) mats = 2 * mbytes;
+  else if (fixed + mbytes <= kLdsMax) mats = mbytes;
+  FDE_TRY((launch<KRRSolve<T>, 1024>(dim3(ps.n), 1024, fixed + mats, s, ps, mats)));
+  // in-place rotation: plane-wave chunk of all m rows (+ C when it fits) in LDS
+  const size_t cs = sizeof(cplx<T>);
+  int GC = 64;
+  while (GC > 4 && (size_t)mmax * GC * cs > 96 * 1024) GC /= 2;
+  const int c_in_lds = ((size_t)mmax * GC * cs + (size_t)mmax * nbmax * cs) <= kLdsMax ? 1 : 0;
+  const size_t rl = (size_t)mmax * GC * cs + (c_in_lds ? (size_t)mmax * nbmax * cs : 0);
+  FDE_TRY(launch<KRotate<T>>(dim3((npwmax + GC - 1) / GC, 2, ps.n), kBlock, rl, s, ps, GC, c_in_lds));
+  return FDE_OK;
+}
+
+template <typename T>
+static fde_status rr_batched_t(fde_plan* p, int nblk, const fde_block* blk, double drop_tol, hipStream_t s) {
+  const int per = std::min(kMaxBatch, p->max_batch);
+  for (int b0 = 0; b0 < nblk; b0 += per) {
+    ProbSet<T> ps;
+    ps.n = std::min(per, nblk - b0);
+    ps.drop_tol = drop_tol;
+    for (int i = 0; i < 3; ++i) ps.b[i] = p->b[i];
+    for (int i = 0; i < ps.n; ++i) {
+      ps.p[i] = make_prob<T>(p, blk[b0 + i]);
+      bind_scratch<T>(p, i, ps.p[i]);
+    }
+    FDE_TRY(rr_launch<T>(p, ps, s));
+  }
+  return FDE_OK;
+}
+
+template <typename T>
+static fde_status precond_batched_t(fde_plan* p, int nblk, const fde_block* blk, const void* t_single,
+                                    hipStream_t s) {
+  for (int b0 = 0; b0 < nblk; b0 += kMaxBatch) {
+    ProbSet<T> ps;
+    ps.n = std::min(kMaxBatch, nblk - b0);
+    ps.drop_tol = 0;
+    for (int i = 0; i < 3; ++i) ps.b[i] = p->b[i];
+    int nbmax = 0;
+    for (int i = 0; i < ps.n; ++i) {
+      ps.p[i] = make_prob<T>(p, blk[b0 + i]);
+      if (t_single) ps.p[i].t = (cplx<T>*)t_single;
+      nbmax = std::max(nbmax, ps.p[i].nb);
+    }
+    FDE_TRY(launch<KPrecond<T>>(dim3(nbmax, ps.n), kBlock, 17 * sizeof(double), s, ps));
+  }
   return FDE_OK;
 }
 
@@ -66,6 +158,16 @@ using namespace fde;
 
 extern "C" {
 
+fde_status fde_subspace_rr_batched(fde_plan* p, int nblk, const fde_block* blk, double drop_tol, hipStream_t s) {
+  if (!p) return fail(FDE_ERR_ARG, "null plan");
+  if (!p->ws) return fail(FDE_ERR_WORKSPACE, "no workspace attached (fde_plan_set_workspace)");
+  if (nblk < 0 || (nblk > 0 && !blk)) return fail(FDE_ERR_ARG, "bad block list");
+  if (!(drop_tol >= 0) || drop_tol >= 1) return fail(FDE_ERR_ARG, "drop_tol must be in [0, 1)");
+  for (int i = 0; i < nblk; ++i) FDE_TRY(check_block(p, blk[i], true));
+  if (p->prec == FDE_F64) return rr_batched_t<double>(p, nblk, blk, drop_tol, s);
+  return rr_batched_t<float>(p, nblk, blk, drop_tol, s);
+}
+
 fde_status fde_subspace_rr(fde_plan* p, int ik, int m, int nb, void* v, void* hv, const uint8_t* active,
                            double drop_tol, double* eval, int* info, hipStream_t s) {
   FDE_TRY(check_plan(p, ik));
@@ -73,10 +175,25 @@ fde_status fde_subspace_rr(fde_plan* p, int ik, int m, int nb, void* v, void* hv
   if (v == hv) return fail(FDE_ERR_ARG, "hv must not alias v");
   if (nb < 1 || m < nb) return fail(FDE_ERR_ARG, "need 1 <= nb <= m");
   if (nb > p->max_nb || m > 2 * p->max_nb) return fail(FDE_ERR_SHAPE, "m or nb exceeds the workspace (m <= 2 max_nb)");
-  if (!(drop_tol >= 0) || drop_tol >= 1) return fail(FDE_ERR_ARG, "drop_tol must be in [0, 1)");
-  if (p->prec == FDE_F64)
-    return rr_t<double>(p, ik, m, nb, (cplx<double>*)v, (cplx<double>*)hv, active, drop_tol, eval, info, s);
-  return rr_t<float>(p, ik, m, nb, (cplx<float>*)v, (cplx<float>*)hv, active, drop_tol, eval, info, s);
+  fde_block b = {};
+  b.ik = ik;
+  b.nb = nb;
+  b.m = m;
+  b.v = v;
+  b.hv = hv;
+  b.active = active;
+  b.eval = eval;
+  b.info = info;
+  return fde_subspace_rr_batched(p, 1, &b, drop_tol, s);
+}
+
+fde_status fde_precondition_batched(fde_plan* p, int nblk, const fde_block* blk, hipStream_t s) {
+  if (!p) return fail(FDE_ERR_ARG, "null plan");
+  if (!p->ws) return fail(FDE_ERR_WORKSPACE, "no workspace attached (fde_plan_set_workspace)");
+  if (nblk < 0 || (nblk > 0 && !blk)) return fail(FDE_ERR_ARG, "bad block list");
+  for (int i = 0; i < nblk; ++i) FDE_TRY(check_block(p, blk[i], false));
+  if (p->prec == FDE_F64) return precond_batched_t<double>(p, nblk, blk, nullptr, s);
+  return precond_batched_t<float>(p, nblk, blk, nullptr, s);
 }
 
 fde_status fde_precondition(fde_plan* p, int ik, int nb, const void* x, const void* hx, const double* eval, void* t,
@@ -85,15 +202,18 @@ fde_status fde_precondition(fde_plan* p, int ik, int nb, const void* x, const vo
   if (nb < 0) return fail(FDE_ERR_ARG, "negative size");
   if (nb == 0) return FDE_OK;
   if (!x || !hx || !eval || !t || !active || !rnorm) return fail(FDE_ERR_ARG, "null argument");
-  const KTables& k = p->k[ik];
-  const size_t red = 17 * sizeof(double);
-  if (p->prec == FDE_F64)
-    return launch<KPrecond<double>>(dim3(nb), kBlock, red, s, (const cplx<double>*)x, (const cplx<double>*)hx, eval,
-                                    (cplx<double>*)t, active, rnorm, (const int*)k.d_millp, k.npw, k.kf[0], k.kf[1],
-                                    k.kf[2], p->b[0], p->b[1], p->b[2]);
-  return launch<KPrecond<float>>(dim3(nb), kBlock, red, s, (const cplx<float>*)x, (const cplx<float>*)hx, eval,
-                                 (cplx<float>*)t, active, rnorm, (const int*)k.d_millp, k.npw, k.kf[0], k.kf[1],
-                                 k.kf[2], p->b[0], p->b[1], p->b[2]);
+  if (nb > p->max_nb) return fail(FDE_ERR_SHAPE, "nb exceeds the workspace's max_nb");
+  fde_block b = {};
+  b.ik = ik;
+  b.nb = nb;
+  b.m = nb;
+  b.v = (void*)x;
+  b.hv = (void*)hx;
+  b.eval = (double*)eval;
+  b.rnorm = rnorm;
+  b.t_active = active;
+  if (p->prec == FDE_F64) return precond_batched_t<double>(p, 1, &b, t, s);
+  return precond_batched_t<float>(p, 1, &b, t, s);
 }
 
 fde_status fde_occupations(int nk, int nb, const double* eval, const double* wk, double nelec, int mode, double sigma,

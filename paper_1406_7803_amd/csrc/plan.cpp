@@ -121,16 +121,8 @@ size_t scratch_embed(const fde_plan* p) {
   return s;
 }
 
-size_t scratch_subspace(const fde_plan* p, int max_nb) {
-  const size_t m = 2 * (size_t)max_nb;
-  size_t s = 5 * align256(m * m * 16);                     // S, A, L, B / A~, W
-  s += align256(m * max_nb * 16);                          // C (FP64)
-  s += align256(m * max_nb * p->csize());                  // C in plan precision
-  s += 2 * align256((size_t)max_nb * p->npw_max * p->csize());  // X, HX staging
-  const size_t nchunk = (p->npw_max + 2047) / 2048;
-  s += align256(nchunk * m * m * 16 * 2);                  // Gram partials (S and A)
-  s += align256(4 * m * sizeof(double) + m * sizeof(int)); // misc
-  return s;
+size_t scratch_subspace(const fde_plan* p, int max_nb, int max_batch) {
+  return (size_t)max_batch * rr_problem_bytes(p, 2 * max_nb, max_nb);
 }
 
 }  // namespace fde
@@ -209,22 +201,23 @@ static size_t tables_bytes(const fde_plan* p) {
   return s;
 }
 
-fde_status fde_plan_workspace_bytes(const fde_plan* p, int max_nb, int max_nproj, size_t* bytes) {
+fde_status fde_plan_workspace_bytes(const fde_plan* p, int max_nb, int max_nproj, int max_batch, size_t* bytes) {
   if (!p || !bytes) return fail(FDE_ERR_ARG, "null argument");
   if (max_nb < 1 || max_nproj < 0) return fail(FDE_ERR_ARG, "max_nb must be >= 1 and max_nproj >= 0");
+  if (max_batch < 1 || max_batch > 16) return fail(FDE_ERR_ARG, "max_batch must be in [1, 16]");
   size_t s = scratch_apply(p, max_nb, max_nproj);
   s = std::max(s, scratch_density(p, max_nb));
   s = std::max(s, scratch_embed(p));
-  s = std::max(s, scratch_subspace(p, max_nb));
+  s = std::max(s, scratch_subspace(p, max_nb, max_batch));
   *bytes = tables_bytes(p) + s;
   return FDE_OK;
 }
 
-fde_status fde_plan_set_workspace(fde_plan* p, void* d_ws, size_t bytes, int max_nb, int max_nproj) {
+fde_status fde_plan_set_workspace(fde_plan* p, void* d_ws, size_t bytes, int max_nb, int max_nproj, int max_batch) {
   if (!p || !d_ws) return fail(FDE_ERR_ARG, "null argument");
   if (((uintptr_t)d_ws) & 255) return fail(FDE_ERR_ARG, "workspace must be 256-byte aligned");
   size_t need = 0;
-  fde_status st = fde_plan_workspace_bytes(p, max_nb, max_nproj, &need);
+  fde_status st = fde_plan_workspace_bytes(p, max_nb, max_nproj, max_batch, &need);
   if (st != FDE_OK) return st;
   if (bytes < need) return fail(FDE_ERR_WORKSPACE, "workspace too small");
   char* w = (char*)d_ws;
@@ -269,6 +262,7 @@ fde_status fde_plan_set_workspace(fde_plan* p, void* d_ws, size_t bytes, int max
   p->scratch_bytes = bytes - off;
   p->max_nb = max_nb;
   p->max_nproj = max_nproj;
+  p->max_batch = max_batch;
   return FDE_OK;
 }
 

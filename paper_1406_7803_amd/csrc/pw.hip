@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "kernels_gemm.hpp"
 #include "kernels_pw.hpp"
 #include "launch.hpp"
 
@@ -41,6 +42,17 @@ static int plane_rows(const fde_plan* p, int ik, bool acc, size_t* lds) {
   return 0;
 }
 
+// part[chunk][i][n] = sum_{G in chunk} conj(beta_i(G)) psi_n(G), chunks of 2048 plane waves
+template <typename T>
+static fde_status kb_project(const cplx<T>* beta, const cplx<T>* psi, int npw, int nproj, int nb, int nchunk,
+                             cplx<double>* part, hipStream_t s) {
+  AhBSet<T> set;
+  set.n = 1;
+  set.p[0] = AhBProb<T>{beta, psi, nullptr, nproj, nb, npw, nchunk, 2048, part};
+  const int nti = (nproj + KAhB<T>::TI - 1) / KAhB<T>::TI, ntj = (nb + KAhB<T>::TJ - 1) / KAhB<T>::TJ;
+  return launch<KAhB<T>>(dim3(nchunk, nti * ntj, 1), kBlock, KAhB<T>::lds_bytes(), s, set);
+}
+
 template <typename T>
 static fde_status apply_h_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, cplx<T>* hpsi, const T* veff, int nproj,
                             const cplx<T>* beta, const double* dkb, hipStream_t s) {
@@ -77,8 +89,7 @@ static fde_status apply_h_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, cpl
                              (const int4*)t.d_sticks, (const int*)t.d_xlist, t.ncol, N1, N2, p->rad[2], tw3, kv, invN,
                              SZ));
     if (nproj > 0) {
-      FDE_TRY(launch<KKbProj<T>>(dim3(nchunk, (nproj + 31) / 32, (nbc + 31) / 32), kBlock, KKbProj<T>::lds_bytes(),
-                                 s, beta, ps, t.npw, nproj, nbc, part));
+      FDE_TRY(kb_project<T>(beta, ps, t.npw, nproj, nbc, nchunk, part, s));
       FDE_TRY(launch<KKbReduce<T>>(dim3((nproj * nbc + kBlk - 1) / kBlk), kBlock, 0, s, (const cplx<double>*)part,
                                    nchunk, nproj, nbc, dkb, dp));
       FDE_TRY(launch<KKbAdd<T>>(dim3((t.npw + kBlk - 1) / kBlk, (nbc + 15) / 16), kBlock,
@@ -245,8 +256,7 @@ static fde_status band_energies_t(fde_plan* p, int ik, int nb, const cplx<T>* ps
                               per_band));
   FDE_TRY(launch<KSumInto>(dim3(1), kBlock, 17 * sizeof(double), s, (const double*)per_band, nb, out));
   if (nproj > 0) {
-    FDE_TRY(launch<KKbProj<T>>(dim3(nchunk, (nproj + 31) / 32, (nb + 31) / 32), kBlock, KKbProj<T>::lds_bytes(), s,
-                               beta, psi, t.npw, nproj, nb, part));
+    FDE_TRY(kb_project<T>(beta, psi, t.npw, nproj, nb, nchunk, part, s));
     FDE_TRY(launch<KBandNl>(dim3(nb), kBlock, 17 * sizeof(double), s, (const cplx<double>*)part, nchunk, nproj, nb,
                             dkb, occw, per_band));
     FDE_TRY(launch<KSumInto>(dim3(1), kBlock, 17 * sizeof(double), s, (const double*)per_band, nb, out + 1));

@@ -52,8 +52,9 @@ class Engine:
         self.be = self.backend or fde.gpu_backend()
         max_nb = max(sub.nbands for sub in s.subsystems)
         nproj_max = max([self._nproj(sub) for sub in s.subsystems] + [0])
+        nblocks = sum(len(sub.kfrac) for sub in s.subsystems)
         self.plan = fde.Plan(s.L, s.grid, s.ecut, s.all_kfrac, prec=self.prec, max_nb=max_nb, max_nproj=nproj_max,
-                             backend=self.be)
+                             max_batch=min(16, nblocks), backend=self.be)
         p = self.plan
         dev = self.be.device
         atoms = [a for sub in s.subsystems for a in sub.atoms]
@@ -115,16 +116,27 @@ class Engine:
                 occw = torch.full((b.nb,), w, dtype=torch.float64, device=self.be.device)
                 p.density(b.ik, X, occw, self.rho_in[I])
 
-    def davidson(self, b: BandBlock, veff: torch.Tensor, n_david: int):
+    def _rr_blocks(self, m_of):
+        return [self.plan.make_block(b.ik, b.nb, m_of(b), b.V, b.HV, active=b.active, eval=b.eval, info=b.info)
+                for row in self.blocks for b in row]
+
+    def _pc_blocks(self):
+        return [self.plan.make_block(b.ik, b.nb, b.nb, b.V, b.HV, t_active=b.active[b.nb:], eval=b.eval,
+                                     rnorm=b.rnorm) for row in self.blocks for b in row]
+
+    def solve(self, n_david: int):
+        """Every band block in lockstep: H X and Rayleigh-Ritz on X, then n_david
+        block-Davidson iterations; the solver calls are batched over blocks."""
         p = self.plan
-        nb = b.nb
-        X, HX, T, HT = b.V[:nb], b.HV[:nb], b.V[nb:], b.HV[nb:]
-        p.apply_h(b.ik, X, veff, b.beta, b.dkb, out=HX)
-        p.subspace_rr(b.ik, X, HX, nb, eval=b.eval, info=b.info)
+        blocks = [b for row in self.blocks for b in row]
+        for b in blocks:
+            p.apply_h(b.ik, b.V[:b.nb], self.veff[b.isub], b.beta, b.dkb, out=b.HV[:b.nb])
+        p.subspace_rr_batched(self._rr_blocks(lambda b: b.nb))
         for _ in range(n_david):
-            p.precondition(b.ik, X, HX, b.eval, T, b.active[nb:], b.rnorm)
-            p.apply_h(b.ik, T, veff, b.beta, b.dkb, out=HT)
-            p.subspace_rr(b.ik, b.V, b.HV, nb, active=b.active, eval=b.eval, info=b.info)
+            p.precondition_batched(self._pc_blocks())
+            for b in blocks:
+                p.apply_h(b.ik, b.V[b.nb:], self.veff[b.isub], b.beta, b.dkb, out=b.HV[b.nb:])
+            p.subspace_rr_batched(self._rr_blocks(lambda b: 2 * b.nb))
 
     def cycle(self, n_david: Optional[int] = None):
         s = self.system
@@ -132,9 +144,9 @@ class Engine:
         n_david = s.n_david if n_david is None else n_david
         p.embed_potential(self.rho_in, self.vloc, rho_thr=s.rho_thr, veff=self.veff, energies=self.energies,
                           info=self.einfo, **self.kinds)
+        self.solve(n_david)
         for I, sub in enumerate(s.subsystems):
             for b in self.blocks[I]:
-                self.davidson(b, self.veff[I], n_david)
                 self.eps[I][b.j].copy_(b.eval)
             mode = fde.OCC_INTEGER if sub.smearing == "integer" else fde.OCC_FERMI_DIRAC
             fde.occupations(self.be, self.eps[I], self.wk[I], sub.nelec, mode, max(sub.sigma, 1e-300),

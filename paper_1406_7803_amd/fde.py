@@ -32,6 +32,7 @@ SYMBOLS = [
     "fde_plan_workspace_bytes", "fde_plan_set_workspace", "fde_apply_h", "fde_density",
     "fde_embed_potential", "fde_subspace_rr", "fde_precondition", "fde_occupations", "fde_mix",
     "fde_local_potential", "fde_kb_projectors", "fde_init_bands", "fde_band_energies", "fde_grid_dot",
+    "fde_subspace_rr_batched", "fde_precondition_batched",
 ]
 
 
@@ -50,6 +51,12 @@ _D = ctypes.c_double
 _S = ctypes.c_size_t
 
 
+class Block(ctypes.Structure):
+    """fde_block: one (subsystem, k-point) band block of the solver."""
+    _fields_ = [("ik", _I), ("nb", _I), ("m", _I), ("v", _P), ("hv", _P), ("active", _P), ("t_active", _P),
+                ("eval", _P), ("rnorm", _P), ("info", _P)]
+
+
 def _declare(lib):
     lib.fde_last_error.restype = ctypes.c_char_p
     lib.fde_plan_create.argtypes = [_P, _P, _D, _I, _P, _I, ctypes.POINTER(_P)]
@@ -57,8 +64,10 @@ def _declare(lib):
     lib.fde_plan_destroy.restype = None
     lib.fde_plan_info.argtypes = [_P, _I, _P, _P]
     lib.fde_plan_miller.argtypes = [_P, _I, _P]
-    lib.fde_plan_workspace_bytes.argtypes = [_P, _I, _I, ctypes.POINTER(_S)]
-    lib.fde_plan_set_workspace.argtypes = [_P, _P, _S, _I, _I]
+    lib.fde_plan_workspace_bytes.argtypes = [_P, _I, _I, _I, ctypes.POINTER(_S)]
+    lib.fde_plan_set_workspace.argtypes = [_P, _P, _S, _I, _I, _I]
+    lib.fde_subspace_rr_batched.argtypes = [_P, _I, _P, _D, _P]
+    lib.fde_precondition_batched.argtypes = [_P, _I, _P, _P]
     lib.fde_apply_h.argtypes = [_P, _I, _I, _P, _P, _P, _I, _P, _P, _P]
     lib.fde_density.argtypes = [_P, _I, _I, _P, _P, _P, _P]
     lib.fde_embed_potential.argtypes = [_P, _I, _P, _P, ctypes.POINTER(Functionals), _P, _P, _P, _P]
@@ -128,7 +137,7 @@ class Plan:
     """fde_plan_create + an attached workspace tensor owned by this object."""
 
     def __init__(self, L: Sequence[float], grid: Sequence[int], ecut: float, kfrac, prec: int = F64,
-                 max_nb: int = 64, max_nproj: int = 0, backend: Optional[Backend] = None):
+                 max_nb: int = 64, max_nproj: int = 0, max_batch: int = 1, backend: Optional[Backend] = None):
         self.be = backend or gpu_backend()
         self.lib = self.be.lib
         kf = np.ascontiguousarray(np.asarray(kfrac, dtype=np.float64).reshape(-1, 3))
@@ -147,13 +156,14 @@ class Plan:
         self.cdtype = torch.complex128 if prec == F64 else torch.complex64
         self.max_nb = max_nb
         self.max_nproj = max_nproj
+        self.max_batch = max_batch
         nbytes = ctypes.c_size_t()
-        self._check(self.lib.fde_plan_workspace_bytes(self.h, max_nb, max_nproj, ctypes.byref(nbytes)))
+        self._check(self.lib.fde_plan_workspace_bytes(self.h, max_nb, max_nproj, max_batch, ctypes.byref(nbytes)))
         self.ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.be.device)
         base = self.ws.data_ptr()
         aligned = (base + 255) // 256 * 256
         self._check(self.lib.fde_plan_set_workspace(self.h, ctypes.c_void_p(aligned), nbytes.value, max_nb,
-                                                    max_nproj))
+                                                    max_nproj, max_batch))
 
     # -- helpers ---------------------------------------------------------------
     def _check(self, st: int):
@@ -264,6 +274,25 @@ class Plan:
         self._check(self.lib.fde_subspace_rr(self.h, ik, m, nb, _ptr(v), _ptr(hv), _ptr(active), float(drop_tol),
                                              _ptr(eval), _ptr(info), self.be.stream()))
         return eval, info
+
+    def subspace_rr_batched(self, blocks, drop_tol=1e-10):
+        """blocks: list of Block (see make_block)."""
+        arr = (Block * len(blocks))(*blocks)
+        self._check(self.lib.fde_subspace_rr_batched(self.h, len(blocks), arr, float(drop_tol), self.be.stream()))
+
+    def precondition_batched(self, blocks):
+        arr = (Block * len(blocks))(*blocks)
+        self._check(self.lib.fde_precondition_batched(self.h, len(blocks), arr, self.be.stream()))
+
+    def make_block(self, ik: int, nb: int, m: int, v, hv, active=None, t_active=None, eval=None, rnorm=None,
+                   info=None) -> Block:
+        self._bands(v, ik, "v")
+        self._bands(hv, ik, "hv")
+        if v.shape[0] < m or hv.shape[0] < m:
+            raise FdeError("block: v and hv need m rows")
+        return Block(ik, nb, m, v.data_ptr(), hv.data_ptr(), None if active is None else active.data_ptr(),
+                     None if t_active is None else t_active.data_ptr(), None if eval is None else eval.data_ptr(),
+                     None if rnorm is None else rnorm.data_ptr(), None if info is None else info.data_ptr())
 
     def precondition(self, ik: int, x: torch.Tensor, hx: torch.Tensor, eval: torch.Tensor, t: torch.Tensor,
                      active: torch.Tensor, rnorm: torch.Tensor):
