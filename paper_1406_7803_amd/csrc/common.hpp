@@ -225,8 +225,8 @@ FDE_HD cplx<T>* lds_fft(const Ctx& c, cplx<T>* a, cplx<T>* b, int nl, int ls, in
     const int nbf = n / R;
     const int total = nl * nbf;
     for (int idx = c.tid(); idx < total; idx += c.nthr()) {
-      const int l = idx / nbf;
-      const int j = idx - l * nbf;
+      const int l = es == 1 ? idx / nbf : idx % nl;
+      const int j = es == 1 ? idx - l * nbf : idx / nl;
       const int base = l * ls;
       switch (R) {
         case 2: bfly<T, INV, 2>(a, b, base, es, n, j, Ns, tw); break;
@@ -243,6 +243,224 @@ FDE_HD cplx<T>* lds_fft(const Ctx& c, cplx<T>* a, cplx<T>* b, int nl, int ls, in
     Ns *= R;
   }
   return a;
+}
+
+
+// --------------------------------------------------------------------------
+// Compile-time specialised Stockham passes for the grid lengths of the
+// configured cells; every index computation folds to constants.
+// --------------------------------------------------------------------------
+struct RadixList {
+  int nst;
+  int r[12];
+};
+
+constexpr RadixList radix_list(int n) {
+  RadixList p{0, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
+  int m = n;
+  while (m % 5 == 0) { p.r[p.nst++] = 5; m /= 5; }
+  while (m % 3 == 0) { p.r[p.nst++] = 3; m /= 3; }
+  while (m % 8 == 0 && m != 16) { p.r[p.nst++] = 8; m /= 8; }
+  while (m % 4 == 0) { p.r[p.nst++] = 4; m /= 4; }
+  while (m % 2 == 0) { p.r[p.nst++] = 2; m /= 2; }
+  return p;
+}
+
+template <typename T, bool INV, int N, int R, int NS>
+FDE_HD void bfly_c(const cplx<T>* __restrict__ src, cplx<T>* __restrict__ dst, int base, int es, int j,
+                   const cplx<T>* __restrict__ tw) {
+  constexpr int nbf = N / R;
+  const int k = j % NS;
+  cplx<T> v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = src[base + (j + r * nbf) * es];
+  if (NS > 1) {
+    constexpr int step = N / (NS * R);
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      const cplx<T> w = tw[r * k * step];
+      v[r] = INV ? cmulc(w, v[r]) : w * v[r];
+    }
+  }
+  if (R == 2) dft2<T, INV>(v);
+  if (R == 3) dft3<T, INV>(v);
+  if (R == 4) dft4<T, INV>(v);
+  if (R == 5) dft5<T, INV>(v);
+  if (R == 8) dft8<T, INV>(v);
+  const int d = (j / NS) * NS * R + k;
+#pragma unroll
+  for (int r = 0; r < R; ++r) dst[base + (d + r * NS) * es] = v[r];
+}
+
+template <typename T, bool INV, int N, int S, int NS>
+struct FftStages {
+  template <class Ctx>
+  FDE_HD static cplx<T>* run(const Ctx& c, cplx<T>* a, cplx<T>* b, int nl, int ls, int es,
+                             const cplx<T>* __restrict__ tw) {
+    constexpr RadixList RL = radix_list(N);
+    if constexpr (S >= RL.nst) {
+      return a;
+    } else {
+      constexpr int R = RL.r[S];
+      constexpr int nbf = N / R;
+      const int total = nl * nbf;
+      if (es == 1) {  // contiguous lines: neighbouring threads take neighbouring butterflies
+        for (int idx = c.tid(); idx < total; idx += c.nthr()) {
+          const int l = idx / nbf;
+          const int j = idx - l * nbf;
+          bfly_c<T, INV, N, R, NS>(a, b, l * ls, es, j, tw);
+        }
+      } else {        // strided lines: neighbouring threads take neighbouring lines (no bank conflicts)
+        for (int idx = c.tid(); idx < total; idx += c.nthr()) {
+          const int j = idx / nl;
+          const int l = idx - j * nl;
+          bfly_c<T, INV, N, R, NS>(a, b, l * ls, es, j, tw);
+        }
+      }
+      c.sync();
+      return FftStages<T, INV, N, S + 1, NS * R>::run(c, b, a, nl, ls, es, tw);
+    }
+  }
+};
+
+// Dispatch: specialised lengths, else the runtime-radix passes.
+template <typename T, bool INV, class Ctx>
+FDE_HD cplx<T>* lds_fft_any(const Ctx& c, cplx<T>* a, cplx<T>* b, int nl, int ls, int es, const Radix& rp,
+                            const cplx<T>* __restrict__ tw) {
+  switch (rp.n) {
+    case 24: return FftStages<T, INV, 24, 0, 1>::run(c, a, b, nl, ls, es, tw);
+    case 48: return FftStages<T, INV, 48, 0, 1>::run(c, a, b, nl, ls, es, tw);
+    case 60: return FftStages<T, INV, 60, 0, 1>::run(c, a, b, nl, ls, es, tw);
+    case 72: return FftStages<T, INV, 72, 0, 1>::run(c, a, b, nl, ls, es, tw);
+    case 96: return FftStages<T, INV, 96, 0, 1>::run(c, a, b, nl, ls, es, tw);
+    case 120: return FftStages<T, INV, 120, 0, 1>::run(c, a, b, nl, ls, es, tw);
+    case 144: return FftStages<T, INV, 144, 0, 1>::run(c, a, b, nl, ls, es, tw);
+    case 180: return FftStages<T, INV, 180, 0, 1>::run(c, a, b, nl, ls, es, tw);
+    case 240: return FftStages<T, INV, 240, 0, 1>::run(c, a, b, nl, ls, es, tw);
+    case 432: return FftStages<T, INV, 432, 0, 1>::run(c, a, b, nl, ls, es, tw);
+    default: return lds_fft<T, INV>(c, a, b, nl, ls, es, rp, tw);
+  }
+}
+
+
+
+// --------------------------------------------------------------------------
+// Compile-time twiddles exp(-2 pi i m / N): the angle is reduced to [0, pi/4]
+// by exact integer quadrant/octant arithmetic and evaluated with Taylor series
+// (terms to x^27; error below 1e-17 there).
+// --------------------------------------------------------------------------
+constexpr double kPiHalf = 1.57079632679489661923;
+
+constexpr double cx_sin(double x) {
+  double t = x, s = x;
+  for (int n = 1; n < 14; ++n) {
+    t *= -x * x / ((2.0 * n) * (2.0 * n + 1.0));
+    s += t;
+  }
+  return s;
+}
+
+constexpr double cx_cos(double x) {
+  double t = 1.0, s = 1.0;
+  for (int n = 1; n < 14; ++n) {
+    t *= -x * x / ((2.0 * n - 1.0) * (2.0 * n));
+    s += t;
+  }
+  return s;
+}
+
+// (cos, sin) of 2 pi m / n
+struct CS {
+  double c, s;
+};
+constexpr CS cx_cossin(int m, int n) {
+  m %= n;
+  if (m < 0) m += n;
+  const int q = (4 * m) / n;            // quadrant
+  const int rem = 4 * m - q * n;        // angle within it: (pi/2) rem / n
+  double c = 0, s = 0;
+  if (2 * rem <= n) {
+    const double phi = kPiHalf * rem / n;
+    c = cx_cos(phi);
+    s = cx_sin(phi);
+  } else {
+    const double phi = kPiHalf * (n - rem) / n;
+    c = cx_sin(phi);
+    s = cx_cos(phi);
+  }
+  for (int k = 0; k < q; ++k) {  // rotate by pi/2 per quadrant
+    const double t = c;
+    c = -s;
+    s = t;
+  }
+  return CS{c, s};
+}
+
+template <int N>
+struct TwTable {
+  double re[N], im[N];
+  constexpr TwTable() : re(), im() {
+    for (int m = 0; m < N; ++m) {
+      const CS v = cx_cossin(m, N);
+      re[m] = v.c;
+      im[m] = -v.s;
+    }
+  }
+};
+
+template <int N>
+inline constexpr TwTable<N> kTwTable{};
+
+template <typename T, int N>
+FDE_HD cplx<T> tw_const(int m) {
+  return mk<T>((T)kTwTable<N>.re[m], (T)kTwTable<N>.im[m]);
+}
+
+// --------------------------------------------------------------------------
+// Whole-line FFT in registers (one thread per line): compile-time Stockham
+// stages, every index a constant after unrolling, so v[] stays in VGPRs.
+// --------------------------------------------------------------------------
+template <typename T, bool INV, int N, int S, int NS>
+FDE_HD void reg_stage(cplx<T>* x, cplx<T>* y, const cplx<T>* __restrict__ tw) {
+  constexpr RadixList RL = radix_list(N);
+  if constexpr (S < RL.nst) {
+    constexpr int R = RL.r[S];
+    constexpr int nbf = N / R;
+    constexpr int step = N / (NS * R);
+#pragma unroll
+    for (int j = 0; j < nbf; ++j) {
+      const int k = j % NS;
+      cplx<T> v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = x[j + r * nbf];
+      if (k != 0) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const cplx<T> w = tw_const<T, N>(r * k * step);
+          v[r] = INV ? cmulc(w, v[r]) : w * v[r];
+        }
+      }
+      if (R == 2) dft2<T, INV>(v);
+      if (R == 3) dft3<T, INV>(v);
+      if (R == 4) dft4<T, INV>(v);
+      if (R == 5) dft5<T, INV>(v);
+      if (R == 8) dft8<T, INV>(v);
+      const int d = (j / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) y[d + r * NS] = v[r];
+    }
+    reg_stage<T, INV, N, S + 1, NS * R>(y, x, tw);
+  }
+}
+
+template <typename T, bool INV, int N>
+FDE_HD void reg_fft(cplx<T>* v, const cplx<T>* __restrict__ tw) {
+  cplx<T> t[N];
+  reg_stage<T, INV, N, 0, 1>(v, t, tw);
+  if constexpr (radix_list(N).nst % 2 == 1) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = t[i];
+  }
 }
 
 FDE_HD int imod(int a, int n) {

@@ -16,10 +16,13 @@ namespace fde {
 struct KTables {
   double kf[3];
   int npw = 0, ncol = 0, nxa = 0;
+  int mlo = 0;          // smallest m1 of the sphere
+  bool xrange = false;  // active x-columns are exactly m1 in [mlo, mlo + nxa), xa = m1 - mlo
   std::vector<int32_t> mill;   // host [npw][3]
   std::vector<int4> sticks;    // host copy of the device table
   std::vector<int> xlist;      // host: x grid index of each active column
   std::vector<int> millp;      // host: packed Miller (m1+512) | (m2+512)<<10 | (m3+512)<<20
+
   // device pointers into the workspace
   int4* d_sticks = nullptr;
   int* d_xlist = nullptr;

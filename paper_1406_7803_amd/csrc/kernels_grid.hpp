@@ -48,7 +48,7 @@ struct KFftAxis {
       const int nl = (nrows - r0) < L ? (nrows - r0) : L;
       for (int idx = c.tid(); idx < nl * n; idx += c.nthr()) a[idx] = data[(size_t)r0 * N1 + idx];
       c.sync();
-      cplx<T>* res = lds_fft<T, INV>(c, a, b, nl, n, 1, r, twl);
+      cplx<T>* res = lds_fft_any<T, INV>(c, a, b, nl, n, 1, r, twl);
       for (int idx = c.tid(); idx < nl * n; idx += c.nthr()) data[(size_t)r0 * N1 + idx] = res[idx];
       return;
     }
@@ -62,7 +62,7 @@ struct KFftAxis {
       else a[idx] = mk<T>(0, 0);
     }
     c.sync();
-    cplx<T>* res = lds_fft<T, INV>(c, a, b, L, 1, L, r, twl);
+    cplx<T>* res = lds_fft_any<T, INV>(c, a, b, L, 1, L, r, twl);
     for (int idx = c.tid(); idx < n * L; idx += c.nthr()) {
       const int e = idx / L, l = idx - e * L;
       if (l < nl) data[base + e * estride + l] = res[idx];

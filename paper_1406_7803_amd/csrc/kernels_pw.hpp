@@ -42,34 +42,37 @@ FDE_HD void unpack_mill(int p, int& m1, int& m2, int& m3) {
 // ---------------------------------------------------------------------------
 template <typename T>
 struct KZInv {
+  // LDS: two buffers of N3 x (SZ + 1) (padded stride against bank conflicts) + N3 twiddles
+  FDE_HD static size_t lds_bytes(int N3, int SZ) { return sizeof(cplx<T>) * ((size_t)2 * N3 * (SZ + 1) + N3); }
   template <class Ctx>
   FDE_HD static void run(const Ctx& c, char* lds, const cplx<T>* __restrict__ psi, int npw,
                          const int4* __restrict__ sticks, int ncol, Radix r3, const cplx<T>* __restrict__ tw,
                          cplx<T>* __restrict__ sb, int SZ) {
     const int N3 = r3.n;
+    const int ES = SZ + 1;
     const int c0 = c.bx() * SZ;
     const int band = c.by();
     const int nsz = (ncol - c0) < SZ ? (ncol - c0) : SZ;
     cplx<T>* a = (cplx<T>*)lds;
-    cplx<T>* b = a + N3 * SZ;
-    cplx<T>* twl = b + N3 * SZ;
+    cplx<T>* b = a + N3 * ES;
+    cplx<T>* twl = b + N3 * ES;
     for (int i = c.tid(); i < N3; i += c.nthr()) twl[i] = tw[i];
-    for (int i = c.tid(); i < N3 * SZ; i += c.nthr()) a[i] = mk<T>(0, 0);
+    for (int i = c.tid(); i < N3 * ES; i += c.nthr()) a[i] = mk<T>(0, 0);
     c.sync();
     const cplx<T>* pb = psi + (size_t)band * npw;
     for (int idx = c.tid(); idx < SZ * N3; idx += c.nthr()) {
       const int s = idx / N3, t = idx - s * N3;
       if (s < nsz) {
         const int4 st = sticks[c0 + s];
-        if (t < st.y) a[imod(st.z + t, N3) * SZ + s] = pb[st.x + t];
+        if (t < st.y) a[imod(st.z + t, N3) * ES + s] = pb[st.x + t];
       }
     }
     c.sync();
-    cplx<T>* r = lds_fft<T, true>(c, a, b, SZ, 1, SZ, r3, twl);
+    cplx<T>* r = lds_fft_any<T, true>(c, a, b, SZ, 1, ES, r3, twl);
     cplx<T>* ob = sb + (size_t)band * N3 * ncol;
     for (int idx = c.tid(); idx < N3 * SZ; idx += c.nthr()) {
       const int z = idx / SZ, s = idx - z * SZ;
-      if (s < nsz) ob[(size_t)z * ncol + c0 + s] = r[z * SZ + s];
+      if (s < nsz) ob[(size_t)z * ncol + c0 + s] = r[z * ES + s];
     }
   }
 };
@@ -86,20 +89,21 @@ struct KZFwd {
                          const int* __restrict__ xlist, int ncol, int N1, int N2, Radix r3,
                          const cplx<T>* __restrict__ tw, KVec kv, double invN, int SZ) {
     const int N3 = r3.n;
+    const int ES = SZ + 1;
     const int c0 = c.bx() * SZ;
     const int band = c.by();
     const int nsz = (ncol - c0) < SZ ? (ncol - c0) : SZ;
     cplx<T>* a = (cplx<T>*)lds;
-    cplx<T>* b = a + N3 * SZ;
-    cplx<T>* twl = b + N3 * SZ;
+    cplx<T>* b = a + N3 * ES;
+    cplx<T>* twl = b + N3 * ES;
     for (int i = c.tid(); i < N3; i += c.nthr()) twl[i] = tw[i];
     const cplx<T>* ib = sb + (size_t)band * N3 * ncol;
     for (int idx = c.tid(); idx < N3 * SZ; idx += c.nthr()) {
       const int z = idx / SZ, s = idx - z * SZ;
-      a[idx] = s < nsz ? ib[(size_t)z * ncol + c0 + s] : mk<T>(0, 0);
+      a[z * ES + s] = s < nsz ? ib[(size_t)z * ncol + c0 + s] : mk<T>(0, 0);
     }
     c.sync();
-    cplx<T>* r = lds_fft<T, false>(c, a, b, SZ, 1, SZ, r3, twl);
+    cplx<T>* r = lds_fft_any<T, false>(c, a, b, SZ, 1, ES, r3, twl);
     const cplx<T>* pb = psi + (size_t)band * npw;
     cplx<T>* hb = hpsi + (size_t)band * npw;
     for (int idx = c.tid(); idx < SZ * N3; idx += c.nthr()) {
@@ -111,7 +115,7 @@ struct KZFwd {
           const int m1 = centred(xlist[st.w & 0xffff], N1);
           const int m2 = centred(st.w >> 16, N2);
           const T kin = (T)kin_of(kv, m1, m2, st.z + t);
-          const cplx<T> v = r[imod(st.z + t, N3) * SZ + s];
+          const cplx<T> v = r[imod(st.z + t, N3) * ES + s];
           const cplx<T> p = pb[g];
           hb[g] = mk<T>((T)invN * v.x + kin * p.x, (T)invN * v.y + kin * p.y);
         }
@@ -173,7 +177,7 @@ FDE_HD cplx<T>* plane_inverse_y(const Ctx& c, PlaneLds<T>& L, const cplx<T>* __r
     L.P0[(w >> 16) * nxa + (w & 0xffff)] = row[i];
   }
   c.sync();
-  return lds_fft<T, true>(c, L.P0, L.P1, nxa, 1, nxa, r2, L.tw2);
+  return lds_fft_any<T, true>(c, L.P0, L.P1, nxa, 1, nxa, r2, L.tw2);
 }
 
 template <typename T>
@@ -202,20 +206,20 @@ struct KPlaneH {
           L.R0[r * N1 + xlist[xa]] = P[(y0 + r) * nxa + xa];
         }
         c.sync();
-        cplx<T>* R = lds_fft<T, true>(c, L.R0, L.R1, rb, N1, 1, r1, L.tw1);
+        cplx<T>* R = lds_fft_any<T, true>(c, L.R0, L.R1, rb, N1, 1, r1, L.tw1);
         for (int i = c.tid(); i < rb * N1; i += c.nthr()) {
           const T v = vz[(size_t)y0 * N1 + i];
           R[i] = mk<T>(v * R[i].x, v * R[i].y);
         }
         c.sync();
-        cplx<T>* Rf = lds_fft<T, false>(c, R, R == L.R0 ? L.R1 : L.R0, rb, N1, 1, r1, L.tw1);
+        cplx<T>* Rf = lds_fft_any<T, false>(c, R, R == L.R0 ? L.R1 : L.R0, rb, N1, 1, r1, L.tw1);
         for (int i = c.tid(); i < rb * nxa; i += c.nthr()) {
           const int r = i / nxa, xa = i - r * nxa;
           P[(y0 + r) * nxa + xa] = Rf[r * N1 + xlist[xa]];
         }
         c.sync();
       }
-      cplx<T>* Pf = lds_fft<T, false>(c, P, P == L.P0 ? L.P1 : L.P0, nxa, 1, nxa, r2, L.tw2);
+      cplx<T>* Pf = lds_fft_any<T, false>(c, P, P == L.P0 ? L.P1 : L.P0, nxa, 1, nxa, r2, L.tw2);
       for (int i = c.tid(); i < ncol; i += c.nthr()) {
         const int w = L.stk[i];
         row[i] = Pf[(w >> 16) * nxa + (w & 0xffff)];
@@ -255,7 +259,7 @@ struct KPlaneRho {
           L.R0[r * N1 + xlist[xa]] = P[(y0 + r) * nxa + xa];
         }
         c.sync();
-        cplx<T>* R = lds_fft<T, true>(c, L.R0, L.R1, rb, N1, 1, r1, L.tw1);
+        cplx<T>* R = lds_fft_any<T, true>(c, L.R0, L.R1, rb, N1, 1, r1, L.tw1);
         for (int i = c.tid(); i < rb * N1; i += c.nthr()) L.acc[y0 * N1 + i] += w * norm2(R[i]);
         c.sync();
       }

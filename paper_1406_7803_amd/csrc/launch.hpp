@@ -16,7 +16,7 @@ namespace fde {
 
 #ifdef FDE_EMULATE
 
-template <class Body, int BS = 256, class... Args>
+template <class Body, int BS = 256, int MINW = 1, class... Args>
 inline fde_status launch(dim3 grid, int /*block*/, size_t lds, hipStream_t, Args... args) {
   std::vector<double> buf(lds / sizeof(double) + 2);
   for (unsigned z = 0; z < grid.z; ++z)
@@ -45,20 +45,21 @@ inline fde_status stream_sync(hipStream_t) { return FDE_OK; }
 
 #else
 
-template <class Body, int BS, class... Args>
-__global__ void __launch_bounds__(BS) kgen(Args... args) {
+template <class Body, int BS, int MINW, class... Args>
+__global__ void __launch_bounds__(BS, MINW) kgen(Args... args) {
   extern __shared__ __align__(16) char fde_smem[];
   Body::run(DevCtx{}, fde_smem, args...);
 }
 
 // Launch Body on `grid` blocks of `block` threads (block <= BS, the kernel's
-// launch bound: 256 by default, 1024 for single-workgroup solvers).
-template <class Body, int BS = 256, class... Args>
+// launch bound: 256 by default, 1024 for single-workgroup solvers; MINW is the
+// minimum number of waves per SIMD the register allocation must allow).
+template <class Body, int BS = 256, int MINW = 1, class... Args>
 inline fde_status launch(dim3 grid, int block, size_t lds, hipStream_t s, Args... args) {
   if (grid.x == 0 || grid.y == 0 || grid.z == 0) return FDE_OK;
   if (lds > kLdsMax) return fail(FDE_ERR_UNSUPPORTED, "kernel needs more LDS than a CU has");
   if (block > BS) return fail(FDE_ERR_ARG, "block larger than the kernel's launch bound");
-  auto k = kgen<Body, BS, Args...>;
+  auto k = kgen<Body, BS, MINW, Args...>;
   if (lds > 64 * 1024) {
     static size_t opted = 0;  // per instantiation
     if (lds > opted) {

@@ -95,6 +95,10 @@ static fde_status build_k(fde_plan* p, const double kf[3], KTables& t) {
     t.millp[q] = (t.mill[3 * q] + 512) | ((t.mill[3 * q + 1] + 512) << 10) | ((t.mill[3 * q + 2] + 512) << 20);
   t.ncol = (int)t.sticks.size();
   t.nxa = (int)t.xlist.size();
+  t.mlo = t.mill[0];
+  t.xrange = true;
+  for (int xa = 0; xa < t.nxa; ++xa)
+    if (t.xlist[xa] != imod(t.mlo + xa, p->N[0])) t.xrange = false;
   return FDE_OK;
 }
 

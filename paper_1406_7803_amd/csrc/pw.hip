@@ -4,8 +4,12 @@
 #include <cmath>
 
 #include "kernels_gemm.hpp"
+#include "kernels_plane.hpp"
 #include "kernels_pw.hpp"
 #include "launch.hpp"
+
+// register plane passes: at least two waves per SIMD
+constexpr int REGW = 2;
 
 namespace fde {
 
@@ -18,19 +22,21 @@ static KVec kvec(const fde_plan* p, int ik) {
   return k;
 }
 
-// Sticks per z-pass workgroup: the largest of 16, 8, 4, 2, 1 whose LDS fits 64 KiB.
+// Sticks per z-pass workgroup: the largest of 16, 8, 4, 2, 1 whose LDS fits
+// 80 KiB (two workgroups per CU).
 static int stick_group(const fde_plan* p) {
   const size_t cs = p->csize();
   for (int sz = 16; sz > 1; sz /= 2)
-    if ((2 * (size_t)p->N[2] * sz + p->N[2]) * cs <= 64 * 1024) return sz;
+    if ((2 * (size_t)p->N[2] * (sz + 1) + p->N[2]) * cs <= 80 * 1024) return sz;
   return 1;
 }
 
-// Rows per batch of the plane pass: as many as fit 64 KiB, else 160 KiB.
+// Rows per batch of the plane pass: as many as fit 80 KiB (two workgroups per
+// CU), else 160 KiB.
 template <typename T>
 static int plane_rows(const fde_plan* p, int ik, bool acc, size_t* lds) {
   const KTables& t = p->k[ik];
-  for (size_t budget : {(size_t)64 * 1024, kLdsMax}) {
+  for (size_t budget : {(size_t)80 * 1024, kLdsMax}) {
     for (int rb = p->N[1]; rb >= 1; rb = (rb > 8 ? rb / 2 : rb - 1)) {
       size_t b = PlaneLds<T>::bytes(p->N[0], p->N[1], t.nxa, rb, t.ncol, acc);
       if (b <= budget) {
@@ -59,10 +65,14 @@ static fde_status apply_h_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, cpl
   const KTables& t = p->k[ik];
   const int N1 = p->N[0], N2 = p->N[1], N3 = p->N[2];
   const int SZ = stick_group(p);
-  const size_t zlds = (2 * (size_t)N3 * SZ + N3) * sizeof(cplx<T>);
+  const size_t zlds = KZInv<T>::lds_bytes(N3, SZ);
   size_t plds = 0;
   const int RB = plane_rows<T>(p, ik, false, &plds);
-  if (RB == 0) return fail(FDE_ERR_UNSUPPORTED, "plane does not fit in LDS");
+  const bool fp64 = sizeof(T) == 8;
+  const size_t rlds = reg_plane_lds<T>(N2, t.nxa, t.ncol);
+  const int cls = reg_len_class(N1, fp64);
+  const bool reg_plane = t.xrange && cls >= 0 && cls == reg_len_class(N2, fp64) && rlds <= kLdsMax;
+  if (RB == 0 && !reg_plane) return fail(FDE_ERR_UNSUPPORTED, "plane does not fit in LDS");
   const double invN = 1.0 / ((double)N1 * N2 * N3);
   const KVec kv = kvec(p, ik);
   cplx<T>* sb = (cplx<T>*)p->scratch;
@@ -81,10 +91,22 @@ static fde_status apply_h_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, cpl
     const unsigned ngz = (unsigned)((t.ncol + SZ - 1) / SZ);
     FDE_TRY(launch<KZInv<T>>(dim3(ngz, nbc), kBlock, zlds, s, ps, t.npw, (const int4*)t.d_sticks, t.ncol,
                              p->rad[2], tw3, sb, SZ));
-    const int BPW = std::max(1, std::min(nbc, (N3 * nbc) / 2048));
-    FDE_TRY(launch<KPlaneH<T>>(dim3(N3, (nbc + BPW - 1) / BPW), kBlock, plds, s, sb, nbc, BPW,
-                               (const int4*)t.d_sticks, (const int*)t.d_xlist, t.ncol, t.nxa, p->rad[0], p->rad[1],
-                               N3, tw1, tw2, veff, RB));
+    if (reg_plane) {
+      // about two workgroups (one wave each) per SIMD over the whole chip
+      const int BPW = std::max(1, std::min(nbc, (N3 * nbc) / 2048));
+      const dim3 g(N3, (nbc + BPW - 1) / BPW);
+      if (cls == 0)
+        FDE_TRY(launch<KPlaneHReg<T, 0>, 64, REGW>(g, 64, rlds, s, sb, nbc, BPW, (const int4*)t.d_sticks, t.ncol,
+                                                   t.nxa, t.mlo, N1, N2, N3, veff));
+      else
+        FDE_TRY(launch<KPlaneHReg<T, 1>, 64, REGW>(g, 64, rlds, s, sb, nbc, BPW, (const int4*)t.d_sticks, t.ncol,
+                                                   t.nxa, t.mlo, N1, N2, N3, veff));
+    } else {
+      const int BPW = std::max(1, std::min(nbc, (N3 * nbc) / 2048));
+      FDE_TRY(launch<KPlaneH<T>>(dim3(N3, (nbc + BPW - 1) / BPW), kBlock, plds, s, sb, nbc, BPW,
+                                 (const int4*)t.d_sticks, (const int*)t.d_xlist, t.ncol, t.nxa, p->rad[0], p->rad[1],
+                                 N3, tw1, tw2, veff, RB));
+    }
     FDE_TRY(launch<KZFwd<T>>(dim3(ngz, nbc), kBlock, zlds, s, (const cplx<T>*)sb, ps, hs, t.npw,
                              (const int4*)t.d_sticks, (const int*)t.d_xlist, t.ncol, N1, N2, p->rad[2], tw3, kv, invN,
                              SZ));
@@ -106,10 +128,15 @@ static fde_status density_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, con
   const KTables& t = p->k[ik];
   const int N3 = p->N[2];
   const int SZ = stick_group(p);
-  const size_t zlds = (2 * (size_t)N3 * SZ + N3) * sizeof(cplx<T>);
+  const size_t zlds = KZInv<T>::lds_bytes(N3, SZ);
   size_t plds = 0;
   const int RB = plane_rows<T>(p, ik, true, &plds);
-  if (RB == 0) return fail(FDE_ERR_UNSUPPORTED, "plane does not fit in LDS");
+  const int N1 = p->N[0], N2 = p->N[1];
+  const bool fp64 = sizeof(T) == 8;
+  const size_t rlds = reg_plane_lds<T>(N2, t.nxa, t.ncol);
+  const int cls = reg_len_class(N1, fp64);
+  const bool reg_plane = t.xrange && cls >= 0 && cls == reg_len_class(N2, fp64) && rlds <= kLdsMax;
+  if (RB == 0 && !reg_plane) return fail(FDE_ERR_UNSUPPORTED, "plane does not fit in LDS");
   cplx<T>* sb = (cplx<T>*)p->scratch;
   T* part = (T*)(p->scratch + align256((size_t)p->max_nb * N3 * p->ncol_max * sizeof(cplx<T>)));
   const cplx<T>* tw1 = (const cplx<T>*)p->d_tw[0];
@@ -124,9 +151,18 @@ static fde_status density_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, con
     const int ngroups = std::min(4, nbc);
     const int BPW = (nbc + ngroups - 1) / ngroups;
     const int ng = (nbc + BPW - 1) / BPW;
-    FDE_TRY(launch<KPlaneRho<T>>(dim3(N3, ng), kBlock, plds, s, (const cplx<T>*)sb, nbc, BPW, occw + b0,
-                                 (const int4*)t.d_sticks, (const int*)t.d_xlist, t.ncol, t.nxa, p->rad[0],
-                                 p->rad[1], N3, tw1, tw2, part, 1.0 / p->omega, RB));
+    if (reg_plane && cls == 0)
+      FDE_TRY(launch<KPlaneRhoReg<T, 0>, 64, REGW>(dim3(N3, ng), 64, rlds, s, (const cplx<T>*)sb, nbc, BPW,
+                                                   occw + b0, (const int4*)t.d_sticks, t.ncol, t.nxa, t.mlo, N1, N2,
+                                                   N3, part, 1.0 / p->omega));
+    else if (reg_plane)
+      FDE_TRY(launch<KPlaneRhoReg<T, 1>, 64, REGW>(dim3(N3, ng), 64, rlds, s, (const cplx<T>*)sb, nbc, BPW,
+                                                   occw + b0, (const int4*)t.d_sticks, t.ncol, t.nxa, t.mlo, N1, N2,
+                                                   N3, part, 1.0 / p->omega));
+    else
+      FDE_TRY(launch<KPlaneRho<T>>(dim3(N3, ng), kBlock, plds, s, (const cplx<T>*)sb, nbc, BPW, occw + b0,
+                                   (const int4*)t.d_sticks, (const int*)t.d_xlist, t.ncol, t.nxa, p->rad[0],
+                                   p->rad[1], N3, tw1, tw2, part, 1.0 / p->omega, RB));
     FDE_TRY(launch<KRhoReduce<T>>(dim3((unsigned)((n + kBlk - 1) / kBlk)), kBlock, 0, s, (const T*)part, ng, n, rho));
   }
   return FDE_OK;

@@ -223,3 +223,24 @@ def check_trajectory(be, prec, system, n_cycles, eps_tol, drho_tol):
     assert all(int(host(b.info)[0]) == 0 for row in eng.blocks for b in row)
     assert worst[0] < eps_tol and worst[1] < drho_tol, worst
     return worst
+
+
+def check_apply_h_grid(be, prec, grid, spacing=0.3, ecut=3.0, nb=2, kf=(0.25, -0.25, 0.0)):
+    """H application and density on a grid of the given FFT lengths (the
+    specialised in-LDS FFT lengths of the configured cells)."""
+    L = tuple(n * spacing for n in grid)
+    cell = basis.Cell(L, grid)
+    sph = basis.sphere(cell, ecut, kf)
+    plan = fde.Plan(L, grid, ecut, [kf], prec=prec, max_nb=nb, backend=be)
+    assert plan.npw(0) == sph.npw
+    veff = fde_synth.random_real(50, cell.shape)
+    psi = fde_synth.random_complex(51, (nb, sph.npw)) / (1 + 2 * sph.kin)[None]
+    ref = oham.apply_h(cell, sph, psi, veff)
+    out = plan.apply_h(0, to_dev(plan, psi, "c"), to_dev(plan, veff, "r"))
+    occw = np.array([1.0, 0.5][:nb])
+    rho = plan.zeros_grid()
+    plan.density(0, to_dev(plan, psi, "c"), to_dev(plan, occw, "d"), rho)
+    be.sync()
+    assert rel(host(out), ref) < TOL[prec], rel(host(out), ref)
+    rref = odens.density(cell, sph, psi, occw)
+    assert rel(host(rho), rref) < TOL[prec]

@@ -74,3 +74,8 @@ def test_trajectory_kpoints_projectors(be):
     s = fde_synth.tiny(0, with_kb=True, kfrac=[(0.25, 0.0, 0.0), (-0.25, 0.0, 0.0)], grid=(12, 12, 15))
     pc.check_trajectory(be, fde.F64, s, 3, 1e-10, 1e-10)
     pc.check_trajectory(be, fde.F32, s, 3, 1e-6, 1e-5)
+
+
+@pytest.mark.parametrize("grid", [(60, 48, 240), (144, 24, 432), (72, 96, 120), (180, 24, 45)])
+def test_apply_h_specialised_lengths(be, grid):
+    pc.check_apply_h_grid(be, fde.F64, grid)

@@ -137,3 +137,9 @@ def test_c2_vloc_and_density_charge(be, prec, c2):
     be.sync()
     ref = odens.density(cell, sph, psi[:3], occw[:3])
     assert pc.rel(pc.host(rho3), ref) < pc.TOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("grid", [(60, 48, 240), (144, 24, 432), (72, 96, 120), (180, 24, 45)])
+def test_apply_h_specialised_lengths(be, prec, grid):
+    pc.check_apply_h_grid(be, prec, grid)
