@@ -4,6 +4,7 @@
 
 #include "kernels_gemm.hpp"
 #include "kernels_la.hpp"
+#include "kernels_rr.hpp"
 #include "launch.hpp"
 
 namespace fde {
@@ -105,7 +106,10 @@ static fde_status rr_launch(fde_plan* p, ProbSet<T>& ps, hipStream_t s) {
   size_t mats = 0;
   if (fixed + 2 * mbytes <= kLdsMax) mats = 2 * mbytes;
   else if (fixed + mbytes <= kLdsMax) mats = mbytes;
-  FDE_TRY((launch<KRRSolve<T>, 1024>(dim3(ps.n), 1024, fixed + mats, s, ps, mats)));
+  if (mmax <= kRRLdsMax)
+    FDE_TRY((launch<KRRSolveLds<T>, 1024>(dim3(ps.n), 1024, KRRSolveLds<T>::lds_bytes(mmax), s, ps)));
+  else
+    FDE_TRY((launch<KRRSolve<T>, 1024>(dim3(ps.n), 1024, fixed + mats, s, ps, mats)));
   // in-place rotation: plane-wave chunk of all m rows (+ C when it fits) in LDS
   const size_t cs = sizeof(cplx<T>);
   int GC = 64;

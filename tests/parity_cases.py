@@ -124,14 +124,17 @@ def check_local_potential(be, prec):
     assert rel(host(v), ref) < TOL[prec]
 
 
-def check_subspace_rr(be, prec, drop_case=False):
-    plan = small_plan(be, prec)
-    cell = basis.Cell(SMALL["L"], SMALL["grid"])
+MEDIUM = dict(L=(8.0, 8.0, 9.0), grid=(18, 18, 20), ecut=5.0, kf=[(0.25, 0.0, -0.25)])
+
+
+def check_subspace_rr(be, prec, drop_case=False, nb=4, case=SMALL):
+    """nb = 45 (m = 90) exercises the global-memory solver, smaller m the LDS one."""
+    plan = small_plan(be, prec, max_nb=max(4, nb), case=case)
+    cell = basis.Cell(case["L"], case["grid"])
     ik = 0
-    sph = basis.sphere(cell, SMALL["ecut"], SMALL["kf"][ik])
-    v = opseudo.local_potential(cell, SMALL["ecut"], KB_ATOMS)
+    sph = basis.sphere(cell, case["ecut"], case["kf"][ik])
+    v = opseudo.local_potential(cell, case["ecut"], KB_ATOMS)
     beta, dkb = opseudo.kb_projectors(cell, sph, KB_ATOMS)
-    nb = 4
     X = osub.orthonormalise(fde_synth.random_complex(21, (nb, sph.npw)))
     HX = oham.apply_h(cell, sph, X, v, beta, dkb)
     X, HX, lam = osub.subspace_rr(X, HX, nb)

@@ -53,6 +53,12 @@ def test_subspace_rr(be, prec, drop):
     pc.check_subspace_rr(be, prec, drop)
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_subspace_rr_large_m(be, prec):
+    pc.check_subspace_rr(be, prec, nb=45, case=pc.MEDIUM)
+    pc.check_subspace_rr(be, prec, drop_case=True, nb=40, case=pc.MEDIUM)
+
+
 def test_singular_gram(be):
     pc.check_singular_gram(be, fde.F64)
 
