@@ -12,12 +12,14 @@ subsystem and k-point one H application + Rayleigh-Ritz then 4 Davidson
 iterations (preconditioner, H application, Rayleigh-Ritz), occupations,
 densities and mixing. `value` is band-applies per cycle / cycle time.
 
-The roofline object covers the H-application FFT sandwich (stick inverse FFT,
-plane pass with V_eff, stick forward FFT + kinetic term), timed with HIP
-events on the stream the kernels run on, over an isolated resident batch of
-all 40 slab bands at one k-point. Algorithmic bytes per band-apply (complex
-of `cs` bytes, V_eff real of `rs` bytes, shared by the BPW bands a plane
-workgroup handles):  3*cs*npw + 4*cs*ncol*N3 + rs*N/BPW.
+The roofline object covers one H application (stick inverse FFT, plane pass
+with V_eff, stick forward FFT + kinetic term, Kleinman-Bylander projector
+products and update), timed with HIP events on the stream the kernels run on,
+over an isolated resident batch of all 40 slab bands at one k-point with the
+slab's 36 projectors. Algorithmic bytes per call (complex of `cs` bytes, V_eff
+real of `rs` bytes, shared by the BPW bands a plane workgroup handles; the
+projectors read once per call):
+    nb * (3*cs*npw + 4*cs*ncol*N3 + rs*N/BPW) + nproj*cs*npw.
 """
 from __future__ import annotations
 
@@ -46,13 +48,13 @@ def parse():
     return ap.parse_args()
 
 
-def apply_bytes(plan, ik, nb, bpw):
+def apply_bytes(plan, ik, nb, bpw, nproj):
     cs = 16 if plan.prec == 0 else 8
     rs = cs // 2
     N1, N2, N3 = plan.grid
     npw, ncol = plan.npw(ik), plan.ncol(ik)
     per_band = 3 * cs * npw + 4 * cs * ncol * N3 + rs * N1 * N2 * N3 / bpw
-    return per_band * nb
+    return per_band * nb + cs * npw * nproj
 
 
 def time_cycles(eng, steps, warmup):
@@ -106,19 +108,20 @@ def main():
     HX = torch.empty_like(X)
     veff = eng.veff[0]
     for _ in range(3):
-        plan.apply_h(b.ik, X, veff, out=HX)
+        plan.apply_h(b.ik, X, veff, b.beta, b.dkb, out=HX)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(a.apply_reps):
-        plan.apply_h(b.ik, X, veff, out=HX)
+        plan.apply_h(b.ik, X, veff, b.beta, b.dkb, out=HX)
     e1.record()
     torch.cuda.synchronize()
     t_apply = e0.elapsed_time(e1) / 1e3 / a.apply_reps
     N3 = plan.grid[2]
     bpw = max(1, min(nb, (N3 * nb) // 2048))
-    alg_bytes = apply_bytes(plan, b.ik, nb, bpw)
+    nproj = 0 if b.beta is None else b.beta.shape[0]
+    alg_bytes = apply_bytes(plan, b.ik, nb, bpw, nproj)
     achieved = alg_bytes / t_apply / 1e9
     isolated = nb / t_apply
 
@@ -163,7 +166,8 @@ def main():
                    "band_applies_per_cycle": per_cycle, "davidson_per_cycle": system.n_david,
                    "parallelism": "single GPU"},
         "isolated_apply_h": {"band_applies_per_s": isolated, "bands": nb, "ms_per_call": t_apply * 1e3},
-        "roofline": {"kernel": "H-apply FFT sandwich (KZInv + KPlaneH + KZFwd)", "bound": "hbm",
+        "roofline": {"kernel": "fde_apply_h: FFT sandwich (KZInv, KPlaneHReg, KZFwd) + projectors "
+                               "(KAhB, KKbReduce, KKbAdd)", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None},
         "cpu_baseline": cpu,

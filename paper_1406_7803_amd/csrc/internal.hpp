@@ -84,6 +84,8 @@ fde_status check_plan(const fde_plan* p, int ik);
 hipError_t allow_lds(const void* kernel, size_t bytes);
 
 constexpr int kBlock = 256;
+// plane waves per partial-sum chunk of the projector products beta^H psi
+constexpr int kKbChunk = 256;
 constexpr size_t kLdsMax = 160 * 1024;
 
 }  // namespace fde

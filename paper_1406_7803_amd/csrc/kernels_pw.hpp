@@ -287,20 +287,21 @@ struct KRhoReduce {
 // ---------------------------------------------------------------------------
 // Kleinman-Bylander products (the projections <beta_i|psi_n> come from KAhB).
 // ---------------------------------------------------------------------------
-// dp[i][n] = D_i * sum_chunk part[chunk][i][n]   (grid ceil(nproj*nb/256))
+// dp[i][n] = D_i * sum_chunk part[chunk][i][n]; one workgroup per (i, n), grid nproj*nb
 template <typename T>
 struct KKbReduce {
   template <class Ctx>
-  FDE_HD static void run(const Ctx& c, char*, const cplx<double>* __restrict__ part, int nchunk, int nproj, int nb,
+  FDE_HD static void run(const Ctx& c, char* lds, const cplx<double>* __restrict__ part, int nchunk, int nproj, int nb,
                          const double* __restrict__ dkb, cplx<T>* __restrict__ dp) {
-    for (int l = c.tid(); l < kBlk; l += c.nthr()) {
-      const int o = c.bx() * kBlk + l;
-      if (o >= nproj * nb) break;
-      double sx = 0, sy = 0;
-      for (int k = 0; k < nchunk; ++k) {
-        sx += part[(size_t)k * nproj * nb + o].x;
-        sy += part[(size_t)k * nproj * nb + o].y;
-      }
+    const int o = c.bx();  // o = i * nb + n
+    double sx = 0, sy = 0;
+    for (int k = c.tid(); k < nchunk; k += c.nthr()) {
+      sx += part[(size_t)k * nproj * nb + o].x;
+      sy += part[(size_t)k * nproj * nb + o].y;
+    }
+    sx = c.sum(sx, (double*)lds);
+    sy = c.sum(sy, (double*)lds);
+    if (c.tid() == 0) {
       const double d = dkb[o / nb];
       dp[o] = mk<T>((T)(d * sx), (T)(d * sy));
     }

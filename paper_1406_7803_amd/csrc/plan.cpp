@@ -104,7 +104,7 @@ static fde_status build_k(fde_plan* p, const double kf[3], KTables& t) {
 
 size_t scratch_apply(const fde_plan* p, int max_nb, int max_nproj) {
   size_t s = align256((size_t)max_nb * p->N[2] * p->ncol_max * p->csize());
-  const size_t nchunk = (p->npw_max + 2047) / 2048;
+  const size_t nchunk = (p->npw_max + kKbChunk - 1) / kKbChunk;
   s += align256(nchunk * (size_t)max_nproj * max_nb * 16);
   s += align256((size_t)max_nproj * max_nb * p->csize());
   return s;

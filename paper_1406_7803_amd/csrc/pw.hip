@@ -48,13 +48,13 @@ static int plane_rows(const fde_plan* p, int ik, bool acc, size_t* lds) {
   return 0;
 }
 
-// part[chunk][i][n] = sum_{G in chunk} conj(beta_i(G)) psi_n(G), chunks of 2048 plane waves
+// part[chunk][i][n] = sum_{G in chunk} conj(beta_i(G)) psi_n(G), chunks of kKbChunk plane waves
 template <typename T>
 static fde_status kb_project(const cplx<T>* beta, const cplx<T>* psi, int npw, int nproj, int nb, int nchunk,
                              cplx<double>* part, hipStream_t s) {
   AhBSet<T> set;
   set.n = 1;
-  set.p[0] = AhBProb<T>{beta, psi, nullptr, nproj, nb, npw, nchunk, 2048, part};
+  set.p[0] = AhBProb<T>{beta, psi, nullptr, nproj, nb, npw, nchunk, kKbChunk, part};
   const int nti = (nproj + KAhB<T>::TI - 1) / KAhB<T>::TI, ntj = (nb + KAhB<T>::TJ - 1) / KAhB<T>::TJ;
   return launch<KAhB<T>>(dim3(nchunk, nti * ntj, 1), kBlock, KAhB<T>::lds_bytes(), s, set);
 }
@@ -78,7 +78,7 @@ static fde_status apply_h_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, cpl
   cplx<T>* sb = (cplx<T>*)p->scratch;
   size_t off = align256((size_t)p->max_nb * N3 * p->ncol_max * sizeof(cplx<T>));
   cplx<double>* part = (cplx<double>*)(p->scratch + off);
-  const int nchunk = (t.npw + 2047) / 2048;
+  const int nchunk = (t.npw + kKbChunk - 1) / kKbChunk;
   off += align256((size_t)nchunk * p->max_nproj * p->max_nb * 16);
   cplx<T>* dp = (cplx<T>*)(p->scratch + off);
   const cplx<T>* tw1 = (const cplx<T>*)p->d_tw[0];
@@ -112,8 +112,8 @@ static fde_status apply_h_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, cpl
                              SZ));
     if (nproj > 0) {
       FDE_TRY(kb_project<T>(beta, ps, t.npw, nproj, nbc, nchunk, part, s));
-      FDE_TRY(launch<KKbReduce<T>>(dim3((nproj * nbc + kBlk - 1) / kBlk), kBlock, 0, s, (const cplx<double>*)part,
-                                   nchunk, nproj, nbc, dkb, dp));
+      FDE_TRY(launch<KKbReduce<T>, 64>(dim3(nproj * nbc), 64, 17 * sizeof(double), s, (const cplx<double>*)part,
+                                       nchunk, nproj, nbc, dkb, dp));
       FDE_TRY(launch<KKbAdd<T>>(dim3((t.npw + kBlk - 1) / kBlk, (nbc + 15) / 16), kBlock,
                                 (size_t)nproj * 16 * sizeof(cplx<T>), s, beta, (const cplx<T>*)dp, hs, t.npw, nproj,
                                 nbc));
@@ -284,7 +284,7 @@ static fde_status band_energies_t(fde_plan* p, int ik, int nb, const cplx<T>* ps
   const KTables& t = p->k[ik];
   if (nb > p->max_nb) return fail(FDE_ERR_SHAPE, "fde_band_energies: nb exceeds the workspace's max_nb");
   if (nproj > p->max_nproj) return fail(FDE_ERR_SHAPE, "nproj exceeds the workspace's max_nproj");
-  const int nchunk = (t.npw + 2047) / 2048;
+  const int nchunk = (t.npw + kKbChunk - 1) / kKbChunk;
   cplx<double>* part = (cplx<double>*)(p->scratch);
   double* per_band = (double*)(p->scratch + align256((size_t)nchunk * p->max_nproj * p->max_nb * 16 + 16));
   const KVec kv = kvec(p, ik);
