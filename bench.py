@@ -33,6 +33,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# sources of the kernels one fde_apply_h call runs (the counter summary is tied to them)
+APPLY_SOURCES = ["common.hpp", "kernels_gemm.hpp", "kernels_plane.hpp", "kernels_pw.hpp", "pw.hip"]
 
 
 def parse():
@@ -43,9 +45,32 @@ def parse():
     ap.add_argument("--prec", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--apply-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-bands", type=int, default=8)
+    ap.add_argument("--cpu-bands", type=int, default=40)
     ap.add_argument("--also-fp64", action="store_true", help="also time the FP64 cycle")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only time a plain device-to-device copy of MIB MiB (stream bandwidth and "
+                         "the calibration of the HBM byte counters), then exit")
     return ap.parse_args()
+
+
+def copy_probe(mib, reps=10):
+    """Plain device copy of a known size: attainable stream bandwidth."""
+    import torch
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    return {"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "reps": reps + 1,
+            "copy_GBps": 2 * 4 * n / t / 1e9}
 
 
 def apply_bytes(plan, ik, nb, bpw, nproj):
@@ -55,6 +80,23 @@ def apply_bytes(plan, ik, nb, bpw, nproj):
     npw, ncol = plan.npw(ik), plan.ncol(ik)
     per_band = 3 * cs * npw + 4 * cs * ncol * N3 + rs * N1 * N2 * N3 / bpw
     return per_band * nb + cs * npw * nproj
+
+
+def measured_traffic():
+    """HBM bytes per fde_apply_h call from the committed counter summary, or None
+    when the sources of its kernels changed since the counters were taken."""
+    import hashlib
+    f = os.path.join(ROOT, "profiles", "apply_h_slab_molecule_60x60x240.traffic.txt")
+    if not os.path.exists(f):
+        return None
+    kv = dict(line.split()[:2] for line in open(f) if line.strip() and not line.startswith("#"))
+    h = hashlib.sha256()
+    for src in sorted(os.path.join(ROOT, "paper_1406_7803_amd", "csrc", n) for n in APPLY_SOURCES):
+        h.update(os.path.basename(src).encode())
+        h.update(open(src, "rb").read())
+    if h.hexdigest() != kv.get("sources_sha256"):
+        return None
+    return float(kv["traffic_bytes_per_call"])
 
 
 def time_cycles(eng, steps, warmup):
@@ -81,6 +123,9 @@ def main():
         print(json.dumps({"error": "this build measures one GPU only; multi-GPU runs are not part of it",
                           "n_gpus": a.gpus}))
         return 2
+    if a.copy_probe:
+        print(json.dumps(copy_probe(a.copy_probe)))
+        return 0
     import numpy as np
     import torch
 
@@ -169,8 +214,9 @@ def main():
         "roofline": {"kernel": "fde_apply_h: FFT sandwich (KZInv, KPlaneHReg, KZFwd) + projectors "
                                "(KAhB, KKbReduce, KKbAdd)", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None},
+                     "traffic": measured_traffic(), "algorithmic_bytes": alg_bytes},
         "cpu_baseline": cpu,
+        "stream_copy_GBps": copy_probe(1024)["copy_GBps"],
         "fp64_cycle": fp64,
         "device_info_ok": eps_err_ok,
         "wall_s_timed": wall,

@@ -302,3 +302,13 @@ def random_complex(seed: int, shape, dtype=np.complex128) -> np.ndarray:
 def random_real(seed: int, shape, lo=-1.0, hi=1.0, dtype=np.float64) -> np.ndarray:
     rng = rng_for(0, 0, 17, seed)
     return rng.uniform(lo, hi, tuple(shape)).astype(dtype)
+
+
+def mlp_init(seed: int = 0) -> np.ndarray:
+    """Initial parameters of the 4 -> 64 -> 64 -> 1 preconditioner network, flat
+    [W1 (64x4), b1, W2 (64x64), b2, w3, b3]: normal hidden weights scaled by
+    1/sqrt(fan-in), zero biases, zero output layer (so the network starts at 0)."""
+    rng = rng_for(5, 0, 23, seed)
+    w1 = rng.normal(0.0, 0.5, 64 * 4)
+    w2 = rng.normal(0.0, 0.125, 64 * 64)
+    return np.concatenate([w1, np.zeros(64), w2, np.zeros(64), np.zeros(64), np.zeros(1)])

@@ -290,8 +290,57 @@ fde_status fde_band_energies(fde_plan* plan, int ik, int nb, const void* psi, co
                              int nproj, const void* beta, const double* dkb, double* out,
                              hipStream_t stream);
 
-/* out[0] += sum_j a_j b_j * dV over the plan's grid (a, b real grids). */
+/* out[0] += sum_j a_j b_j * dV over the plan's grid (a, b real grids; b NULL means b = 1). */
 fde_status fde_grid_dot(fde_plan* plan, const void* a, const void* b, double* out, hipStream_t stream);
+
+/* out[0] = (1/N) sum_j a_j (mean of a real grid, e.g. the mean effective potential
+ * that the learned preconditioner's fourth feature uses). out: device double. */
+fde_status fde_grid_mean(fde_plan* plan, const void* a, double* out, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned preconditioner (an extension of the band solver step; the paper
+ * leaves the solver to its host code). A 4 -> 64 -> 64 -> 1 network with tanh
+ * hidden layers maps per-coefficient features
+ *   u = (log(1 + kin_G/T_n), log T_n, log max(|R_G| sqrt(npw)/||R_n||, 1e-6),
+ *        (lambda_n - vbar)/T_n)
+ * (kin_G = |k+G|^2/2, T_n = sum_G kin_G |x_nG|^2, vbar = mean V_eff) to y, and
+ * the correction is T_G = K_TPA(kin_G/T_n) exp(y) R_G, normalised; y = 0 is
+ * exactly the Teter-Payne-Allan preconditioner of fde_precondition.
+ * Parameters: FP32 flat vector of FDE_MLP_NPARAM values, in the order
+ * W1[64][4], b1[64], W2[64][64], b2[64], w3[64], b3 (y = w3.h2 + b3,
+ * h2 = tanh(W2 h1 + b2), h1 = tanh(W1 u + b1)). Kernels round W1, W2, w3 and
+ * the first hidden layer to BF16 and accumulate in FP32; the 64 x 64 products
+ * run on BF16 matrix cores.
+ * Training samples: rows of FDE_MLP_SAMPLE floats (u1..u4, A, B, C) with loss
+ * (1/n) sum (A e^{2y} - 2 B e^y + C): for the Jacobi-Davidson correction
+ * delta of band n, A = w a^2 K^2 |R_G|^2, B = w a K Re(conj(R_G) delta_G),
+ * C = w |delta_G|^2, a = Re<K R, delta>/||K R||^2, w = npw/||delta||^2.
+ * All pointers are device pointers; every call only enqueues on `stream`.
+ * ------------------------------------------------------------------------- */
+#define FDE_MLP_NPARAM 4545
+#define FDE_MLP_NIN 4
+#define FDE_MLP_SAMPLE 7
+
+/* fde_precondition_batched with the network: vbar [nblk] device doubles (mean
+ * V_eff of each block's subsystem), params as above. Same outputs. */
+fde_status fde_precondition_mlp_batched(fde_plan* plan, int nblk, const fde_block* blk, const float* params,
+                                        const double* vbar, hipStream_t stream);
+
+/* y[s] = network(u[s]) for u [n][4] (FP32). */
+fde_status fde_mlp_forward(int n, const float* u, const float* params, float* y, hipStream_t stream);
+
+/* Workspace (device bytes) for fde_mlp_loss_grad over n samples. */
+fde_status fde_mlp_workspace_bytes(int n, size_t* bytes);
+
+/* loss[0] = (1/n) sum_s (A e^{2y} - 2 B e^y + C) over samples [n][7]; grad
+ * [FDE_MLP_NPARAM] = its gradient (FP32, fixed summation order, overwritten). */
+fde_status fde_mlp_loss_grad(int n, const float* samples, const float* params, float* grad, double* loss,
+                             void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* One Adam step (Kingma & Ba) on params with moments m, v (FP32, FDE_MLP_NPARAM
+ * each, updated in place); t counts from 1. */
+fde_status fde_mlp_adam(const float* grad, float* params, float* m, float* v, int t, float lr, float beta1,
+                        float beta2, float eps, hipStream_t stream);
 
 #ifdef __cplusplus
 }

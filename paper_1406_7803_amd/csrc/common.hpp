@@ -468,6 +468,10 @@ FDE_HD int imod(int a, int n) {
   return r < 0 ? r + n : r;
 }
 
+// Row stride of the z-stick buffer [band][z][stick]: ncol rounded up to 16
+// complex, so every plane row starts on a 128-byte boundary.
+FDE_HD constexpr int stick_stride(int ncol) { return (ncol + 15) & ~15; }
+
 FDE_HD int centred(int j, int n) { return j <= n / 2 ? j : j - n; }
 
 }  // namespace fde

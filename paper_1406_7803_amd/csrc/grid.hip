@@ -1,5 +1,5 @@
 // Host entry points of the grid kernels: fde_embed_potential,
-// fde_local_potential, fde_mix, fde_grid_dot.
+// fde_local_potential, fde_mix, fde_grid_dot, fde_grid_mean.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -486,21 +486,21 @@ struct KDot {
     GRID_FOR(c, n, nblk) {
       const size_t i = i0_ + l_;
       if (i >= n) break;
-      acc[0] += (double)a[i] * (double)b[i];
+      acc[0] += b ? (double)a[i] * (double)b[i] : (double)a[i];
     }
     block_store(c, (double*)lds, acc, part);
   }
 };
 
-// out[0] += scale * sum part[b][0]
+// out[0] += scale * sum part[b][0]   (out[0] = ... when set)
 struct KRedAdd {
   template <class Ctx>
   FDE_HD static void run(const Ctx& c, char* lds, const double* __restrict__ part, int nblk, double scale,
-                         double* __restrict__ out) {
+                         double* __restrict__ out, int set) {
     double acc = 0.0;
     for (int b = c.tid(); b < nblk; b += c.nthr()) acc += part[(size_t)b * kNQ];
     acc = c.sum(acc, (double*)lds);
-    if (c.tid() == 0) out[0] += scale * acc;
+    if (c.tid() == 0) out[0] = (set ? 0.0 : out[0]) + scale * acc;
   }
 };
 
@@ -561,7 +561,22 @@ fde_status fde_grid_dot(fde_plan* p, const void* a, const void* b, double* out, 
     FDE_TRY(launch<KDot<double>>(dim3(nb), kBlock, red, s, (const double*)a, (const double*)b, n, part, nb));
   else
     FDE_TRY(launch<KDot<float>>(dim3(nb), kBlock, red, s, (const float*)a, (const float*)b, n, part, nb));
-  return launch<KRedAdd>(dim3(1), kBlock, red, s, (const double*)part, (int)nb, p->omega / (double)n, out);
+  return launch<KRedAdd>(dim3(1), kBlock, red, s, (const double*)part, (int)nb, p->omega / (double)n, out, 0);
+}
+
+fde_status fde_grid_mean(fde_plan* p, const void* a, double* out, hipStream_t s) {
+  if (!p) return fail(FDE_ERR_ARG, "null plan");
+  if (!p->ws) return fail(FDE_ERR_WORKSPACE, "no workspace attached (fde_plan_set_workspace)");
+  if (!a || !out) return fail(FDE_ERR_ARG, "null argument");
+  const size_t n = p->npts();
+  const unsigned nb = red_blocks(n);
+  double* part = (double*)p->scratch;
+  const size_t red = 17 * sizeof(double);
+  if (p->prec == FDE_F64)
+    FDE_TRY(launch<KDot<double>>(dim3(nb), kBlock, red, s, (const double*)a, (const double*)nullptr, n, part, nb));
+  else
+    FDE_TRY(launch<KDot<float>>(dim3(nb), kBlock, red, s, (const float*)a, (const float*)nullptr, n, part, nb));
+  return launch<KRedAdd>(dim3(1), kBlock, red, s, (const double*)part, (int)nb, 1.0 / (double)n, out, 1);
 }
 
 }  // extern "C"

@@ -177,7 +177,7 @@ struct KPlaneHReg {
     T* vz = const_cast<T*>(veff) + (size_t)z * N1 * N2;
     const int b0 = c.by() * BPW;
     for (int band = b0; band < b0 + BPW && band < nbands; ++band) {
-      cplx<T>* row = sb + ((size_t)band * N3 + z) * ncol;
+      cplx<T>* row = sb + ((size_t)band * N3 + z) * stick_stride(ncol);
       reg_scatter<T>(c, P, cpos, row, ncol, N2 * nxa);
       columns_fft<T, true, CLS>(c, P, N2, nxa);
       c.sync();
@@ -208,7 +208,7 @@ struct KPlaneRhoReg {
     for (int i = c.tid(); i < n; i += c.nthr()) o[i] = T(0);
     const int b0 = c.by() * BPW;
     for (int band = b0; band < b0 + BPW && band < nbands; ++band) {
-      const cplx<T>* row = sb + ((size_t)band * N3 + z) * ncol;
+      const cplx<T>* row = sb + ((size_t)band * N3 + z) * stick_stride(ncol);
       reg_scatter<T>(c, P, cpos, row, ncol, N2 * nxa);
       columns_fft<T, true, CLS>(c, P, N2, nxa);
       c.sync();

@@ -2,13 +2,14 @@
 // Kleinman-Bylander projector products.
 //
 // Data flow of one band-apply (Eq. KS; coefficients on the sphere S_k):
-//   psi [nb][npw] --KZInv--> sticks [nb][N3][ncol] (inverse z-FFT of each
+//   psi [nb][npw] --KZInv--> sticks [nb][N3][ncs] (inverse z-FFT of each
 //   z-stick of the sphere) --KPlaneH--> same layout (per z-plane: inverse y-FFT
 //   on the active x-columns, inverse x-FFT per row, times V_eff, forward x-FFT,
 //   forward y-FFT, keep the sticks) --KZFwd--> hpsi [nb][npw] (forward z-FFT,
 //   1/N, plus |k+G|^2/2 psi).
-// The sticks buffer holds, for every z-plane, the ncol sticks contiguously so
-// both the z-passes and the plane pass read and write it coalesced.
+// The sticks buffer holds, for every z-plane, the ncol sticks contiguously
+// (row stride ncs = stick_stride(ncol), 128-byte aligned rows) so both the
+// z-passes and the plane pass read and write it coalesced.
 #pragma once
 
 #include "common.hpp"
@@ -69,10 +70,11 @@ struct KZInv {
     }
     c.sync();
     cplx<T>* r = lds_fft_any<T, true>(c, a, b, SZ, 1, ES, r3, twl);
-    cplx<T>* ob = sb + (size_t)band * N3 * ncol;
+    const int ncs = stick_stride(ncol);
+    cplx<T>* ob = sb + (size_t)band * N3 * ncs;
     for (int idx = c.tid(); idx < N3 * SZ; idx += c.nthr()) {
       const int z = idx / SZ, s = idx - z * SZ;
-      if (s < nsz) ob[(size_t)z * ncol + c0 + s] = r[z * ES + s];
+      if (s < nsz) ob[(size_t)z * ncs + c0 + s] = r[z * ES + s];
     }
   }
 };
@@ -97,10 +99,11 @@ struct KZFwd {
     cplx<T>* b = a + N3 * ES;
     cplx<T>* twl = b + N3 * ES;
     for (int i = c.tid(); i < N3; i += c.nthr()) twl[i] = tw[i];
-    const cplx<T>* ib = sb + (size_t)band * N3 * ncol;
+    const int ncs = stick_stride(ncol);
+    const cplx<T>* ib = sb + (size_t)band * N3 * ncs;
     for (int idx = c.tid(); idx < N3 * SZ; idx += c.nthr()) {
       const int z = idx / SZ, s = idx - z * SZ;
-      a[z * ES + s] = s < nsz ? ib[(size_t)z * ncol + c0 + s] : mk<T>(0, 0);
+      a[z * ES + s] = s < nsz ? ib[(size_t)z * ncs + c0 + s] : mk<T>(0, 0);
     }
     c.sync();
     cplx<T>* r = lds_fft_any<T, false>(c, a, b, SZ, 1, ES, r3, twl);
@@ -195,7 +198,7 @@ struct KPlaneH {
     const T* vz = veff + (size_t)z * N1 * N2;
     const int b0 = c.by() * BPW;
     for (int band = b0; band < b0 + BPW && band < nbands; ++band) {
-      cplx<T>* row = sb + ((size_t)band * N3 + z) * ncol;
+      cplx<T>* row = sb + ((size_t)band * N3 + z) * stick_stride(ncol);
       cplx<T>* P = plane_inverse_y<T>(c, L, row, ncol, nxa, r2);
       for (int y0 = 0; y0 < N2; y0 += RB) {
         const int rb = (N2 - y0) < RB ? (N2 - y0) : RB;
@@ -248,7 +251,7 @@ struct KPlaneRho {
     const int b0 = c.by() * BPW;
     for (int band = b0; band < b0 + BPW && band < nbands; ++band) {
       const T w = (T)occw[band];
-      const cplx<T>* row = sb + ((size_t)band * N3 + z) * ncol;
+      const cplx<T>* row = sb + ((size_t)band * N3 + z) * stick_stride(ncol);
       cplx<T>* P = plane_inverse_y<T>(c, L, row, ncol, nxa, r2);
       for (int y0 = 0; y0 < N2; y0 += RB) {
         const int rb = (N2 - y0) < RB ? (N2 - y0) : RB;
@@ -287,53 +290,94 @@ struct KRhoReduce {
 // ---------------------------------------------------------------------------
 // Kleinman-Bylander products (the projections <beta_i|psi_n> come from KAhB).
 // ---------------------------------------------------------------------------
-// dp[i][n] = D_i * sum_chunk part[chunk][i][n]; one workgroup per (i, n), grid nproj*nb
+// dp[o] = D_i * sum_chunk part[chunk][o], o = i nb + n. grid ceil(nproj nb / 64), 256
+// threads: four chunk classes (k mod 4) of 64 consecutive outputs each, so every
+// read of a chunk row is one contiguous 64-element segment; the four partial
+// sums are added in a fixed order.
 template <typename T>
 struct KKbReduce {
+  static constexpr int NO = 64;
   template <class Ctx>
   FDE_HD static void run(const Ctx& c, char* lds, const cplx<double>* __restrict__ part, int nchunk, int nproj, int nb,
                          const double* __restrict__ dkb, cplx<T>* __restrict__ dp) {
-    const int o = c.bx();  // o = i * nb + n
-    double sx = 0, sy = 0;
-    for (int k = c.tid(); k < nchunk; k += c.nthr()) {
-      sx += part[(size_t)k * nproj * nb + o].x;
-      sy += part[(size_t)k * nproj * nb + o].y;
+    cplx<double>* red = (cplx<double>*)lds;  // [4][NO]
+    const int nout = nproj * nb;
+    for (int idx = c.tid(); idx < 4 * NO; idx += c.nthr()) {
+      const int w = idx / NO, l = idx - w * NO;
+      const int o = c.bx() * NO + l;
+      double sx = 0, sy = 0;
+      if (o < nout)
+        for (int k = w; k < nchunk; k += 4) {
+          const cplx<double> v = part[(size_t)k * nout + o];
+          sx += v.x;
+          sy += v.y;
+        }
+      red[idx] = mk<double>(sx, sy);
     }
-    sx = c.sum(sx, (double*)lds);
-    sy = c.sum(sy, (double*)lds);
-    if (c.tid() == 0) {
+    c.sync();
+    for (int l = c.tid(); l < NO; l += c.nthr()) {
+      const int o = c.bx() * NO + l;
+      if (o >= nout) continue;
+      const double sx = (red[l].x + red[NO + l].x) + (red[2 * NO + l].x + red[3 * NO + l].x);
+      const double sy = (red[l].y + red[NO + l].y) + (red[2 * NO + l].y + red[3 * NO + l].y);
       const double d = dkb[o / nb];
       dp[o] = mk<T>((T)(d * sx), (T)(d * sy));
     }
   }
 };
 
-// hpsi[n][G] += sum_i beta_i(G) dp[i][n]; grid (ceil(npw/256), ceil(nb/16))
+// hpsi[n][G] += sum_i beta_i(G) dp[i][n]. grid ceil(npw / 64), 256 threads.
+// Per block: a tile of 64 plane waves; projectors in chunks of PC staged in
+// LDS (beta read from HBM once per chunk), bands in chunks of 64 (dp staged in
+// LDS); a thread item is a quarter of the band chunk at one G (lanes run along
+// G), with its 16 sums in registers.
 template <typename T>
 struct KKbAdd {
+  static constexpr int TG = 64, PC = sizeof(T) == 4 ? 40 : 20, NBC = 64, NQ = NBC / 4;
+  static size_t lds_bytes() { return sizeof(cplx<T>) * (size_t)PC * (TG + NBC); }
   template <class Ctx>
   FDE_HD static void run(const Ctx& c, char* lds, const cplx<T>* __restrict__ beta, const cplx<T>* __restrict__ dp,
                          cplx<T>* __restrict__ hpsi, int npw, int nproj, int nb) {
-    const int NT = 16;
-    const int n0 = c.by() * NT;
-    cplx<T>* sD = (cplx<T>*)lds;  // [nproj][NT]
-    for (int idx = c.tid(); idx < nproj * NT; idx += c.nthr()) {
-      const int i = idx / NT, q = idx - i * NT;
-      sD[idx] = (n0 + q < nb) ? dp[(size_t)i * nb + n0 + q] : mk<T>(0, 0);
-    }
-    c.sync();
-    for (int l = c.tid(); l < kBlk; l += c.nthr()) {
-      const int g = c.bx() * kBlk + l;
-      if (g >= npw) break;
-      cplx<T> acc[NT];
-      for (int q = 0; q < NT; ++q) acc[q] = mk<T>(0, 0);
-      for (int i = 0; i < nproj; ++i) {
-        const cplx<T> bv = beta[(size_t)i * npw + g];
-        for (int q = 0; q < NT; ++q) acc[q] = acc[q] + bv * sD[i * NT + q];
+    cplx<T>* sB = (cplx<T>*)lds;   // [PC][TG]
+    cplx<T>* sD = sB + PC * TG;    // [PC][NBC]
+    const int g0 = c.bx() * TG;
+    for (int i0 = 0; i0 < nproj; i0 += PC) {
+      const int np = (nproj - i0) < PC ? (nproj - i0) : PC;
+      c.sync();
+      for (int idx = c.tid(); idx < np * TG; idx += c.nthr()) {
+        const int i = idx / TG, g = idx - i * TG;
+        sB[idx] = (g0 + g < npw) ? beta[(size_t)(i0 + i) * npw + g0 + g] : mk<T>(0, 0);
       }
-      for (int q = 0; q < NT && n0 + q < nb; ++q) {
-        cplx<T>& h = hpsi[(size_t)(n0 + q) * npw + g];
-        h = h + acc[q];
+      for (int n0 = 0; n0 < nb; n0 += NBC) {
+        const int nbc = (nb - n0) < NBC ? (nb - n0) : NBC;
+        c.sync();
+        for (int idx = c.tid(); idx < np * nbc; idx += c.nthr()) {
+          const int i = idx / nbc, q = idx - i * nbc;
+          sD[i * NBC + q] = dp[(size_t)(i0 + i) * nb + n0 + q];
+        }
+        c.sync();
+        // item (quarter w of the band chunk, G): NQ accumulators, beta_i(G) read once per i
+        for (int idx = c.tid(); idx < 4 * TG; idx += c.nthr()) {
+          const int w = idx / TG, g = idx - w * TG;
+          const int qa = w * NQ, qn = (nbc - qa) < NQ ? (nbc - qa) : NQ;
+          if (g0 + g >= npw || qn <= 0) continue;
+          cplx<T> acc[NQ];  // compile-time indices only: stays in registers
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) acc[q] = mk<T>(0, 0);
+          for (int i = 0; i < np; ++i) {
+            const cplx<T> b = sB[i * TG + g];
+            const cplx<T>* d = sD + i * NBC + qa;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) acc[q] = acc[q] + b * d[q];
+          }
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            if (q < qn) {
+              cplx<T>& h = hpsi[(size_t)(n0 + qa + q) * npw + g0 + g];
+              h = h + acc[q];
+            }
+          }
+        }
       }
     }
   }

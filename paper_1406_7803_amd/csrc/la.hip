@@ -4,6 +4,7 @@
 
 #include "kernels_gemm.hpp"
 #include "kernels_la.hpp"
+#include "kernels_mlp.hpp"
 #include "kernels_rr.hpp"
 #include "launch.hpp"
 
@@ -156,6 +157,27 @@ static fde_status precond_batched_t(fde_plan* p, int nblk, const fde_block* blk,
   return FDE_OK;
 }
 
+template <typename T>
+static fde_status precond_mlp_batched_t(fde_plan* p, int nblk, const fde_block* blk, const float* params,
+                                        const double* vbar, hipStream_t s) {
+  for (int b0 = 0; b0 < nblk; b0 += kMaxBatch) {
+    ProbSet<T> ps;
+    ps.n = std::min(kMaxBatch, nblk - b0);
+    ps.drop_tol = 0;
+    for (int i = 0; i < 3; ++i) ps.b[i] = p->b[i];
+    int nbmax = 0;
+    for (int i = 0; i < ps.n; ++i) {
+      ps.p[i] = make_prob<T>(p, blk[b0 + i]);
+      nbmax = std::max(nbmax, ps.p[i].nb);
+    }
+    FDE_TRY(launch<KPrecondMlp<T>>(dim3(nbmax, ps.n), kBlock, KPrecondMlp<T>::lds_bytes, s, ps, params, vbar + b0));
+  }
+  return FDE_OK;
+}
+
+// samples per block of the loss/gradient pass: a multiple of 64, at most 1024 blocks
+static int mlp_per_block(int n) { return 64 * std::max(1, (n + 64 * 1024 - 1) / (64 * 1024)); }
+
 }  // namespace fde
 
 using namespace fde;
@@ -229,6 +251,54 @@ fde_status fde_occupations(int nk, int nb, const double* eval, const double* wk,
   if (!(nelec >= 0) || nelec > 2.0 * nb) return fail(FDE_ERR_ARG, "nelec must be in [0, 2 nb]");
   return launch<KOccupations>(dim3(1), kBlock, 17 * sizeof(double), s, eval, wk, nk, nb, nelec, mode, sigma, occw, mu,
                               info);
+}
+
+fde_status fde_precondition_mlp_batched(fde_plan* p, int nblk, const fde_block* blk, const float* params,
+                                        const double* vbar, hipStream_t s) {
+  if (!p) return fail(FDE_ERR_ARG, "null plan");
+  if (nblk < 0 || (nblk > 0 && (!blk || !params || !vbar))) return fail(FDE_ERR_ARG, "null argument");
+  for (int i = 0; i < nblk; ++i) FDE_TRY(check_block(p, blk[i], false));
+  if (p->prec == FDE_F64) return precond_mlp_batched_t<double>(p, nblk, blk, params, vbar, s);
+  return precond_mlp_batched_t<float>(p, nblk, blk, params, vbar, s);
+}
+
+fde_status fde_mlp_forward(int n, const float* u, const float* params, float* y, hipStream_t s) {
+  if (n < 0) return fail(FDE_ERR_ARG, "negative size");
+  if (n == 0) return FDE_OK;
+  if (!u || !params || !y) return fail(FDE_ERR_ARG, "null argument");
+  return launch<KMlpForward>(dim3((unsigned)((n + 63) / 64)), kBlock, KMlpForward::lds_bytes, s, u, n, params, y);
+}
+
+fde_status fde_mlp_workspace_bytes(int n, size_t* bytes) {
+  if (n < 1 || !bytes) return fail(FDE_ERR_ARG, "need n >= 1 and an output pointer");
+  const int pb = mlp_per_block(n);
+  const size_t nblk = (size_t)((n + pb - 1) / pb);
+  *bytes = nblk * kMlpNPad * sizeof(float) + nblk * sizeof(double) + 256;
+  return FDE_OK;
+}
+
+fde_status fde_mlp_loss_grad(int n, const float* samples, const float* params, float* grad, double* loss, void* ws,
+                             size_t ws_bytes, hipStream_t s) {
+  if (n < 1) return fail(FDE_ERR_ARG, "need at least one sample");
+  if (!samples || !params || !grad || !loss || !ws) return fail(FDE_ERR_ARG, "null argument");
+  size_t need = 0;
+  FDE_TRY(fde_mlp_workspace_bytes(n, &need));
+  if (ws_bytes < need) return fail(FDE_ERR_WORKSPACE, "workspace smaller than fde_mlp_workspace_bytes(n)");
+  const int pb = mlp_per_block(n);
+  const int nblk = (n + pb - 1) / pb;
+  float* part = (float*)ws;
+  double* lpart = (double*)((char*)ws + align256((size_t)nblk * kMlpNPad * sizeof(float)));  // inside `need`
+  FDE_TRY(launch<KMlpLossGrad>(dim3(nblk), kBlock, KMlpLossGrad::lds_bytes, s, samples, n, pb, params, part, lpart));
+  return launch<KMlpReduce>(dim3((kMlpNPad + 255) / 256), kBlock, 0, s, (const float*)part, (const double*)lpart, nblk,
+                            grad, loss);
+}
+
+fde_status fde_mlp_adam(const float* grad, float* params, float* m, float* v, int t, float lr, float beta1, float beta2,
+                        float eps, hipStream_t s) {
+  if (!grad || !params || !m || !v) return fail(FDE_ERR_ARG, "null argument");
+  if (t < 1 || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+    return fail(FDE_ERR_ARG, "bad Adam hyper-parameters");
+  return launch<KMlpAdam>(dim3((kMlpNParam + 255) / 256), kBlock, 0, s, grad, params, m, v, t, lr, beta1, beta2, eps);
 }
 
 }  // extern "C"

@@ -103,7 +103,7 @@ static fde_status build_k(fde_plan* p, const double kf[3], KTables& t) {
 }
 
 size_t scratch_apply(const fde_plan* p, int max_nb, int max_nproj) {
-  size_t s = align256((size_t)max_nb * p->N[2] * p->ncol_max * p->csize());
+  size_t s = align256((size_t)max_nb * p->N[2] * stick_stride(p->ncol_max) * p->csize());
   const size_t nchunk = (p->npw_max + kKbChunk - 1) / kKbChunk;
   s += align256(nchunk * (size_t)max_nproj * max_nb * 16);
   s += align256((size_t)max_nproj * max_nb * p->csize());
@@ -111,7 +111,7 @@ size_t scratch_apply(const fde_plan* p, int max_nb, int max_nproj) {
 }
 
 size_t scratch_density(const fde_plan* p, int max_nb) {
-  size_t s = align256((size_t)max_nb * p->N[2] * p->ncol_max * p->csize());
+  size_t s = align256((size_t)max_nb * p->N[2] * stick_stride(p->ncol_max) * p->csize());
   s += align256((size_t)4 * p->npts() * p->rsize());
   return s;
 }

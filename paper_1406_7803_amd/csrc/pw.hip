@@ -76,7 +76,7 @@ static fde_status apply_h_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, cpl
   const double invN = 1.0 / ((double)N1 * N2 * N3);
   const KVec kv = kvec(p, ik);
   cplx<T>* sb = (cplx<T>*)p->scratch;
-  size_t off = align256((size_t)p->max_nb * N3 * p->ncol_max * sizeof(cplx<T>));
+  size_t off = align256((size_t)p->max_nb * N3 * stick_stride(p->ncol_max) * sizeof(cplx<T>));
   cplx<double>* part = (cplx<double>*)(p->scratch + off);
   const int nchunk = (t.npw + kKbChunk - 1) / kKbChunk;
   off += align256((size_t)nchunk * p->max_nproj * p->max_nb * 16);
@@ -112,11 +112,11 @@ static fde_status apply_h_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, cpl
                              SZ));
     if (nproj > 0) {
       FDE_TRY(kb_project<T>(beta, ps, t.npw, nproj, nbc, nchunk, part, s));
-      FDE_TRY(launch<KKbReduce<T>, 64>(dim3(nproj * nbc), 64, 17 * sizeof(double), s, (const cplx<double>*)part,
-                                       nchunk, nproj, nbc, dkb, dp));
-      FDE_TRY(launch<KKbAdd<T>>(dim3((t.npw + kBlk - 1) / kBlk, (nbc + 15) / 16), kBlock,
-                                (size_t)nproj * 16 * sizeof(cplx<T>), s, beta, (const cplx<T>*)dp, hs, t.npw, nproj,
-                                nbc));
+      FDE_TRY(launch<KKbReduce<T>>(dim3((nproj * nbc + KKbReduce<T>::NO - 1) / KKbReduce<T>::NO), kBlock,
+                                   4 * KKbReduce<T>::NO * sizeof(cplx<double>), s, (const cplx<double>*)part, nchunk,
+                                   nproj, nbc, dkb, dp));
+      FDE_TRY(launch<KKbAdd<T>>(dim3((t.npw + KKbAdd<T>::TG - 1) / KKbAdd<T>::TG), kBlock, KKbAdd<T>::lds_bytes(), s,
+                                beta, (const cplx<T>*)dp, hs, t.npw, nproj, nbc));
     }
   }
   return FDE_OK;
@@ -138,7 +138,7 @@ static fde_status density_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, con
   const bool reg_plane = t.xrange && cls >= 0 && cls == reg_len_class(N2, fp64) && rlds <= kLdsMax;
   if (RB == 0 && !reg_plane) return fail(FDE_ERR_UNSUPPORTED, "plane does not fit in LDS");
   cplx<T>* sb = (cplx<T>*)p->scratch;
-  T* part = (T*)(p->scratch + align256((size_t)p->max_nb * N3 * p->ncol_max * sizeof(cplx<T>)));
+  T* part = (T*)(p->scratch + align256((size_t)p->max_nb * N3 * stick_stride(p->ncol_max) * sizeof(cplx<T>)));
   const cplx<T>* tw1 = (const cplx<T>*)p->d_tw[0];
   const cplx<T>* tw2 = (const cplx<T>*)p->d_tw[1];
   const cplx<T>* tw3 = (const cplx<T>*)p->d_tw[2];

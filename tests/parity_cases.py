@@ -73,6 +73,28 @@ def check_apply_h(be, prec, nb=9, with_kb=True):
         assert rel(host(out), ref) < TOL[prec], rel(host(out), ref)
 
 
+def check_apply_h_many_projectors(be, prec, nb=70, natoms=24):
+    """More projectors than one LDS chunk and more bands than one band chunk of the
+    projector update; npw is not a multiple of the plane-wave tile."""
+    case = MEDIUM
+    plan = small_plan(be, prec, max_nb=nb, max_nproj=4 * natoms, case=case)
+    cell = basis.Cell(case["L"], case["grid"])
+    rng = np.random.default_rng(5150)
+    atoms = [fde_synth.Atom(tuple(rng.uniform(0, 1, 3) * np.array(case["L"])), 1.0, 0.7, lmax=int(i % 3 != 0),
+                            rbeta=0.7 + 0.01 * i, d_s=0.5 + 0.05 * i, d_p=-0.2 + 0.03 * i) for i in range(natoms)]
+    sph = basis.sphere(cell, case["ecut"], case["kf"][0])
+    assert sph.npw % 64 != 0
+    veff = fde_synth.random_real(6, cell.shape)
+    psi = fde_synth.random_complex(7, (nb, sph.npw))
+    beta, dkb = opseudo.kb_projectors(cell, sph, atoms)
+    assert beta.shape[0] > 64
+    tb = plan.kb_projectors(0, [a.pos for a in atoms], [a.lmax for a in atoms], [a.rbeta for a in atoms])
+    ref = oham.apply_h(cell, sph, psi, veff, beta, dkb)
+    out = plan.apply_h(0, to_dev(plan, psi, "c"), to_dev(plan, veff, "r"), tb, to_dev(plan, dkb, "d"))
+    be.sync()
+    assert rel(host(out), ref) < TOL[prec], rel(host(out), ref)
+
+
 def check_density(be, prec, nb=7):
     plan = small_plan(be, prec)
     cell = basis.Cell(SMALL["L"], SMALL["grid"])

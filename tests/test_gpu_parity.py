@@ -29,6 +29,11 @@ def test_apply_h(be, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_apply_h_many_projectors(be, prec):
+    pc.check_apply_h_many_projectors(be, prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_density(be, prec):
     pc.check_density(be, prec)
 
