@@ -32,8 +32,10 @@ SYMBOLS = [
     "fde_plan_workspace_bytes", "fde_plan_set_workspace", "fde_apply_h", "fde_density",
     "fde_embed_potential", "fde_subspace_rr", "fde_precondition", "fde_occupations", "fde_mix",
     "fde_local_potential", "fde_kb_projectors", "fde_init_bands", "fde_band_energies", "fde_grid_dot",
-    "fde_subspace_rr_batched", "fde_precondition_batched",
+    "fde_subspace_rr_batched", "fde_precondition_batched", "fde_grid_mean", "fde_precondition_mlp_batched",
+    "fde_mlp_forward", "fde_mlp_workspace_bytes", "fde_mlp_loss_grad", "fde_mlp_adam",
 ]
+MLP_NPARAM, MLP_NIN, MLP_SAMPLE = 4545, 4, 7
 
 
 class FdeError(RuntimeError):
@@ -80,6 +82,13 @@ def _declare(lib):
     lib.fde_init_bands.argtypes = [_P, _I, _I, _P, _P, _P]
     lib.fde_band_energies.argtypes = [_P, _I, _I, _P, _P, _I, _P, _P, _P, _P]
     lib.fde_grid_dot.argtypes = [_P, _P, _P, _P, _P]
+    lib.fde_grid_mean.argtypes = [_P, _P, _P, _P]
+    lib.fde_precondition_mlp_batched.argtypes = [_P, _I, _P, _P, _P, _P]
+    lib.fde_mlp_forward.argtypes = [_I, _P, _P, _P, _P]
+    lib.fde_mlp_workspace_bytes.argtypes = [_I, ctypes.POINTER(_S)]
+    lib.fde_mlp_loss_grad.argtypes = [_I, _P, _P, _P, _P, _P, _S, _P]
+    _F = ctypes.c_float
+    lib.fde_mlp_adam.argtypes = [_P, _P, _P, _P, _I, _F, _F, _F, _F, _P]
     for name in SYMBOLS:
         if name not in ("fde_last_error", "fde_plan_destroy"):
             getattr(lib, name).restype = _I
@@ -344,6 +353,22 @@ class Plan:
         self._check(self.lib.fde_grid_dot(self.h, _ptr(a), _ptr(b), _ptr(out), self.be.stream()))
         return out
 
+    def grid_mean(self, a, out=None):
+        self._grid(a, "a")
+        out = torch.zeros(1, dtype=torch.float64, device=self.be.device) if out is None else out
+        self._check(self.lib.fde_grid_mean(self.h, _ptr(a), _ptr(out), self.be.stream()))
+        return out
+
+    def precondition_mlp_batched(self, blocks, params: torch.Tensor, vbar: torch.Tensor):
+        """fde_precondition_batched with the learned network; vbar: [len(blocks)] float64 device."""
+        _check_params(params, self.be)
+        self._f64(vbar, "vbar")
+        if vbar.numel() < len(blocks):
+            raise FdeError("vbar needs one value per block")
+        arr = (Block * len(blocks))(*blocks)
+        self._check(self.lib.fde_precondition_mlp_batched(self.h, len(blocks), arr, _ptr(params), _ptr(vbar),
+                                                          self.be.stream()))
+
 
 def occupations(be: Backend, eval: torch.Tensor, wk: torch.Tensor, nelec: float, mode: int, sigma: float,
                 occw=None, mu=None, info=None):
@@ -365,3 +390,66 @@ def mix(be: Backend, rho_in: torch.Tensor, rho_out: torch.Tensor, beta: float):
     if st != 0:
         raise FdeError(f"fde error {st}: {be.lib.fde_last_error().decode()}")
     return rho_in
+
+
+# ---------------------------------------------------------------------------
+# Learned preconditioner network (FP32 parameters, layout of FDE_MLP_NPARAM)
+# ---------------------------------------------------------------------------
+def _check_params(params: torch.Tensor, be: Backend):
+    if params.dtype != torch.float32 or params.numel() != MLP_NPARAM or not params.is_contiguous():
+        raise FdeError(f"params must be a contiguous float32 vector of {MLP_NPARAM}")
+    if params.device != be.device:
+        raise FdeError("params on the wrong device")
+
+
+def _raise(be: Backend, st: int):
+    if st != 0:
+        raise FdeError(f"fde error {st}: {be.lib.fde_last_error().decode()}")
+
+
+def mlp_forward(be: Backend, u: torch.Tensor, params: torch.Tensor, y=None) -> torch.Tensor:
+    """y[s] = network(u[s]) for u [n][4] float32."""
+    _check_params(params, be)
+    if u.dtype != torch.float32 or u.dim() != 2 or u.shape[1] != MLP_NIN or not u.is_contiguous():
+        raise FdeError("u must be contiguous float32 [n][4]")
+    y = torch.empty(u.shape[0], dtype=torch.float32, device=be.device) if y is None else y
+    _raise(be, be.lib.fde_mlp_forward(u.shape[0], _ptr(u), _ptr(params), _ptr(y), be.stream()))
+    return y
+
+
+class MlpTrainer:
+    """Loss/gradient passes and Adam steps on one sample set (all on the device)."""
+
+    def __init__(self, be: Backend, samples: torch.Tensor, params: torch.Tensor, lr=1e-3, beta1=0.9, beta2=0.999,
+                 eps=1e-8):
+        _check_params(params, be)
+        if samples.dtype != torch.float32 or samples.dim() != 2 or samples.shape[1] != MLP_SAMPLE \
+                or not samples.is_contiguous():
+            raise FdeError("samples must be contiguous float32 [n][7]")
+        self.be, self.samples, self.params = be, samples, params
+        self.lr, self.beta1, self.beta2, self.eps = lr, beta1, beta2, eps
+        n = samples.shape[0]
+        nbytes = ctypes.c_size_t()
+        _raise(be, be.lib.fde_mlp_workspace_bytes(n, ctypes.byref(nbytes)))
+        self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device=be.device)
+        self.grad = torch.zeros(MLP_NPARAM, dtype=torch.float32, device=be.device)
+        self.m = torch.zeros_like(self.grad)
+        self.v = torch.zeros_like(self.grad)
+        self.loss = torch.zeros(1, dtype=torch.float64, device=be.device)
+        self.t = 0
+
+    def loss_grad(self):
+        n = self.samples.shape[0]
+        _raise(self.be, self.be.lib.fde_mlp_loss_grad(n, _ptr(self.samples), _ptr(self.params), _ptr(self.grad),
+                                                      _ptr(self.loss), _ptr(self.ws), self.ws.numel(),
+                                                      self.be.stream()))
+        return self.loss, self.grad
+
+    def step(self):
+        """One full-batch loss/gradient pass and one Adam step."""
+        self.loss_grad()
+        self.t += 1
+        _raise(self.be, self.be.lib.fde_mlp_adam(_ptr(self.grad), _ptr(self.params), _ptr(self.m), _ptr(self.v),
+                                                 self.t, self.lr, self.beta1, self.beta2, self.eps,
+                                                 self.be.stream()))
+        return self.loss

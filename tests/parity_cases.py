@@ -12,6 +12,7 @@ import numpy as np
 import torch
 
 import fde_synth
+from oracle import mlp as omlp
 from oracle import basis, dft, density as odens, embed as oembed, hamiltonian as oham, occupations as oocc
 from oracle import pseudo as opseudo, scf as oscf, subspace as osub
 from paper_1406_7803_amd import driver, fde
@@ -269,3 +270,143 @@ def check_apply_h_grid(be, prec, grid, spacing=0.3, ecut=3.0, nb=2, kf=(0.25, -0
     assert rel(host(out), ref) < TOL[prec], rel(host(out), ref)
     rref = odens.density(cell, sph, psi, occw)
     assert rel(host(rho), rref) < TOL[prec]
+
+
+# ---------------------------------------------------------------------------
+# Learned preconditioner network
+# ---------------------------------------------------------------------------
+def bf16_round(a):
+    """Round float values to the nearest BF16 value (ties to even), as float64."""
+    u = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def mlp_params(seed):
+    """Parameters with a nonzero output layer, BF16-representable weights."""
+    t = fde_synth.mlp_init(seed)
+    rng = np.random.default_rng(seed + 1)
+    t[omlp.OFF_W3:omlp.OFF_B3] = rng.normal(0.0, 0.3, omlp.HID)
+    t[omlp.OFF_B3] = 0.1
+    t[omlp.OFF_B1:omlp.OFF_W2] = rng.normal(0.0, 0.1, omlp.HID)
+    t[omlp.OFF_B2:omlp.OFF_W3] = rng.normal(0.0, 0.1, omlp.HID)
+    return bf16_round(t)
+
+
+def mlp_samples(n, seed):
+    rng = np.random.default_rng(seed)
+    U = np.stack([rng.uniform(0.0, 3.0, n), rng.normal(0.0, 1.0, n), rng.normal(-1.0, 1.5, n),
+                  rng.normal(0.0, 1.0, n)], axis=1)
+    A = rng.uniform(0.1, 2.0, n)
+    B = rng.uniform(-1.0, 1.0, n) * np.sqrt(A)
+    C = B * B / A + rng.uniform(0.0, 1.0, n)
+    return np.concatenate([U, A[:, None], B[:, None], C[:, None]], axis=1)
+
+
+def fdev(be, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(be.device)
+
+
+def check_mlp_forward(be, n=1000):
+    """BF16 weights and first hidden layer, FP32 accumulation, against the FP64 network."""
+    th = mlp_params(11)
+    U = mlp_samples(n, 12)[:, :4].astype(np.float32).astype(np.float64)
+    ref, _ = omlp.forward(th, U)
+    y = fde.mlp_forward(be, fdev(be, U), fdev(be, th))
+    be.sync()
+    err = np.abs(host(y) - ref)
+    assert err.max() < 0.03 and err.mean() < 0.005, (err.max(), err.mean())
+
+
+def check_mlp_loss_grad(be, n=3000):
+    th = mlp_params(13)
+    S = mlp_samples(n, 14).astype(np.float32).astype(np.float64)
+    L, g = omlp.loss_grad(th, S)
+    tr = fde.MlpTrainer(be, fdev(be, S), fdev(be, th))
+    loss, grad = tr.loss_grad()
+    be.sync()
+    gg = host(grad).astype(np.float64)
+    assert abs(float(host(loss)[0]) - L) < 1e-2 * abs(L)
+    cos = gg @ g / (np.linalg.norm(gg) * np.linalg.norm(g))
+    assert cos > 0.999, cos
+    assert np.linalg.norm(gg - g) < 3e-2 * np.linalg.norm(g)
+    # every block of the parameter vector carries gradient
+    for a, b in [(omlp.OFF_W1, omlp.OFF_B1), (omlp.OFF_B1, omlp.OFF_W2), (omlp.OFF_W2, omlp.OFF_B2),
+                 (omlp.OFF_B2, omlp.OFF_W3), (omlp.OFF_W3, omlp.OFF_B3), (omlp.OFF_B3, omlp.NPARAM)]:
+        assert np.linalg.norm(gg[a:b] - g[a:b]) < 5e-2 * np.linalg.norm(g[a:b]) + 1e-9, (a, b)
+
+
+def check_mlp_adam(be):
+    th = mlp_params(15)
+    rng = np.random.default_rng(16)
+    g = rng.normal(0.0, 1.0, omlp.NPARAM)
+    m = np.zeros(omlp.NPARAM)
+    v = np.zeros(omlp.NPARAM)
+    p = fdev(be, th)
+    gm = torch.zeros_like(p)
+    gv = torch.zeros_like(p)
+    gd = fdev(be, g)
+    ref = th.copy()
+    for t in range(1, 4):
+        ref, m, v = omlp.adam(ref, g, m, v, t, 1e-3)
+        st = be.lib.fde_mlp_adam(gd.data_ptr(), p.data_ptr(), gm.data_ptr(), gv.data_ptr(), t, 1e-3, 0.9, 0.999,
+                                 1e-8, be.stream())
+        assert st == 0
+    be.sync()
+    assert np.max(np.abs(host(p) - ref)) < 1e-6
+
+
+def check_precondition_mlp(be, prec):
+    plan = small_plan(be, prec)
+    cell = basis.Cell(SMALL["L"], SMALL["grid"])
+    ik = 0
+    sph = basis.sphere(cell, SMALL["ecut"], SMALL["kf"][ik])
+    X = osub.orthonormalise(fde_synth.random_complex(51, (4, sph.npw)))
+    HX = fde_synth.random_complex(52, (4, sph.npw)) * 0.3 + X
+    lam = np.array([0.9, 1.1, 0.95, 0.5])  # 0.5: HX = lam X is exact in FP32 too
+    HX[3] = lam[3] * X[3]      # zero residual -> inactive, T = 0
+    vbar = 0.37
+    th = mlp_params(17)
+    T, active, rn = omlp.precondition(th, X, HX, lam, sph.kin, vbar)
+    dev = plan.be.device
+    V = to_dev(plan, np.vstack([X, np.zeros_like(X)]), "c")
+    HV = to_dev(plan, np.vstack([HX, np.zeros_like(HX)]), "c")
+    ev = to_dev(plan, lam, "d")
+    act = torch.zeros(4, dtype=torch.uint8, device=dev)
+    rnorm = torch.zeros(4, dtype=torch.float64, device=dev)
+    blk = plan.make_block(ik, 4, 4, V, HV, t_active=act, eval=ev, rnorm=rnorm)
+    plan.precondition_mlp_batched([blk], fdev(be, th), torch.tensor([vbar], dtype=torch.float64, device=dev))
+    be.sync()
+    assert np.array_equal(host(act).astype(bool), active)
+    got = host(V)[4:]
+    assert rel(got, T) < 2e-2, rel(got, T)
+    assert rel(host(rnorm)[:3], rn[:3]) < TOL[prec] * 10
+    # zero output layer: exactly the TPA preconditioner
+    th0 = fde_synth.mlp_init(3)
+    T0, _, _ = osub.precondition(X, HX, lam, sph.kin)
+    plan.precondition_mlp_batched([blk], fdev(be, th0), torch.tensor([vbar], dtype=torch.float64, device=dev))
+    be.sync()
+    assert rel(host(V)[4:], T0) < TOL[prec] * 10
+
+
+def check_mlp_training_reduces_loss(be, n=4096, steps=150):
+    """A target the network can represent: y* = 0.5 tanh(u1) - 0.3 u4 (through B/A)."""
+    rng = np.random.default_rng(21)
+    U = np.stack([rng.uniform(0.0, 3.0, n), rng.normal(0.0, 1.0, n), rng.normal(-1.0, 1.5, n),
+                  rng.normal(0.0, 1.0, n)], axis=1)
+    ystar = 0.5 * np.tanh(U[:, 0]) - 0.3 * U[:, 3]
+    A = rng.uniform(0.5, 1.5, n)
+    B = A * np.exp(ystar)
+    C = B * B / A
+    S = np.concatenate([U, A[:, None], B[:, None], C[:, None]], axis=1)
+    th = fde_synth.mlp_init(5)
+    tr = fde.MlpTrainer(be, fdev(be, S), fdev(be, th), lr=3e-3)
+    l0 = float(host(tr.loss_grad()[0])[0])
+    for _ in range(steps):
+        tr.step()
+    l1 = float(host(tr.loss_grad()[0])[0])
+    be.sync()
+    assert l1 < 0.1 * l0, (l0, l1)
+    # the oracle agrees on the trained parameters' loss
+    Lo = omlp.loss(host(tr.params).astype(np.float64), S.astype(np.float32).astype(np.float64))
+    assert abs(Lo - l1) < 0.05 * l0, (Lo, l1)

@@ -154,3 +154,24 @@ def test_c2_vloc_and_density_charge(be, prec, c2):
 @pytest.mark.parametrize("grid", [(60, 48, 240), (144, 24, 432), (72, 96, 120), (180, 24, 45)])
 def test_apply_h_specialised_lengths(be, prec, grid):
     pc.check_apply_h_grid(be, prec, grid)
+
+
+def test_mlp_forward(be):
+    pc.check_mlp_forward(be)
+
+
+def test_mlp_loss_grad(be):
+    pc.check_mlp_loss_grad(be)
+
+
+def test_mlp_adam(be):
+    pc.check_mlp_adam(be)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_precondition_mlp(be, prec):
+    pc.check_precondition_mlp(be, prec)
+
+
+def test_mlp_training_reduces_loss(be):
+    pc.check_mlp_training_reduces_loss(be)
