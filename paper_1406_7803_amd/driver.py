@@ -46,6 +46,7 @@ class Engine:
     prec: int = fde.F64
     backend: Optional[fde.Backend] = None
     kinds: dict = field(default_factory=lambda: dict(xc=fde.XC_LDA, xc_nad=fde.XC_LDA, kin_nad=fde.KIN_LC94))
+    mlp_params: Optional[torch.Tensor] = None   # learned preconditioner (FP32, FDE_MLP_NPARAM); None = TPA
 
     def __post_init__(self):
         s = self.system
@@ -97,6 +98,7 @@ class Engine:
         self.occw = [torch.zeros_like(e) for e in self.eps]
         self.mu = [torch.zeros(1, dtype=torch.float64, device=dev) for _ in s.subsystems]
         self.oinfo = [torch.zeros(1, dtype=torch.int32, device=dev) for _ in s.subsystems]
+        self.vbar = torch.zeros(sum(len(r) for r in self.blocks), dtype=torch.float64, device=dev)
         self._initial_density()
 
     @staticmethod
@@ -132,8 +134,14 @@ class Engine:
         for b in blocks:
             p.apply_h(b.ik, b.V[:b.nb], self.veff[b.isub], b.beta, b.dkb, out=b.HV[:b.nb])
         p.subspace_rr_batched(self._rr_blocks(lambda b: b.nb))
+        if self.mlp_params is not None:
+            for i, b in enumerate(blocks):
+                p.grid_mean(self.veff[b.isub], out=self.vbar[i:i + 1])
         for _ in range(n_david):
-            p.precondition_batched(self._pc_blocks())
+            if self.mlp_params is None:
+                p.precondition_batched(self._pc_blocks())
+            else:
+                p.precondition_mlp_batched(self._pc_blocks(), self.mlp_params, self.vbar)
             for b in blocks:
                 p.apply_h(b.ik, b.V[b.nb:], self.veff[b.isub], b.beta, b.dkb, out=b.HV[b.nb:])
             p.subspace_rr_batched(self._rr_blocks(lambda b: 2 * b.nb))
@@ -159,3 +167,34 @@ class Engine:
     def band_applies_per_cycle(self, n_david: Optional[int] = None) -> int:
         n_david = self.system.n_david if n_david is None else n_david
         return sum(b.nb * (1 + n_david) for row in self.blocks for b in row)
+
+
+def davidson_fixed(plan: fde.Plan, ik: int, X0: torch.Tensor, veff: torch.Tensor, n_iter: int, beta=None, dkb=None,
+                   mlp_params: Optional[torch.Tensor] = None):
+    """Block Davidson at a fixed potential (the band solver of one cycle, iterated):
+    H X and Rayleigh-Ritz on X, then n_iter iterations of preconditioner (TPA, or
+    the learned network when mlp_params is given), H T and Rayleigh-Ritz on [X | T].
+    Returns the Ritz values after every iteration (list of float64 tensors [nb])."""
+    nb, npw = X0.shape
+    dev = plan.be.device
+    V = torch.zeros((2 * nb, npw), dtype=plan.cdtype, device=dev)
+    HV = torch.zeros_like(V)
+    V[:nb].copy_(X0)
+    eval_ = torch.zeros(nb, dtype=torch.float64, device=dev)
+    active = torch.ones(2 * nb, dtype=torch.uint8, device=dev)
+    rnorm = torch.zeros(nb, dtype=torch.float64, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    vbar = plan.grid_mean(veff) if mlp_params is not None else None
+    plan.apply_h(ik, V[:nb], veff, beta, dkb, out=HV[:nb])
+    plan.subspace_rr_batched([plan.make_block(ik, nb, nb, V, HV, active=active, eval=eval_, info=info)])
+    hist = []
+    for _ in range(n_iter):
+        pcb = [plan.make_block(ik, nb, nb, V, HV, t_active=active[nb:], eval=eval_, rnorm=rnorm)]
+        if mlp_params is None:
+            plan.precondition_batched(pcb)
+        else:
+            plan.precondition_mlp_batched(pcb, mlp_params, vbar)
+        plan.apply_h(ik, V[nb:], veff, beta, dkb, out=HV[nb:])
+        plan.subspace_rr_batched([plan.make_block(ik, nb, 2 * nb, V, HV, active=active, eval=eval_, info=info)])
+        hist.append(eval_.clone())
+    return hist, info

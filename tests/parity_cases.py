@@ -410,3 +410,17 @@ def check_mlp_training_reduces_loss(be, n=4096, steps=150):
     # the oracle agrees on the trained parameters' loss
     Lo = omlp.loss(host(tr.params).astype(np.float64), S.astype(np.float32).astype(np.float64))
     assert abs(Lo - l1) < 0.05 * l0, (Lo, l1)
+
+
+def check_engine_mlp_zero_output_is_tpa(be):
+    """The cycle with a network whose output layer is zero reproduces the TPA cycle."""
+    from paper_1406_7803_amd import driver
+    s = fde_synth.config1()
+    e1 = driver.Engine(s, prec=fde.F64, backend=be)
+    e2 = driver.Engine(s, prec=fde.F64, backend=be, mlp_params=fdev(be, fde_synth.mlp_init(0)))
+    for _ in range(2):
+        e1.cycle()
+        e2.cycle()
+    be.sync()
+    for a, b in zip(e1.eps, e2.eps):
+        assert np.max(np.abs(host(a) - host(b))) < 1e-12

@@ -175,3 +175,7 @@ def test_precondition_mlp(be, prec):
 
 def test_mlp_training_reduces_loss(be):
     pc.check_mlp_training_reduces_loss(be)
+
+
+def test_engine_mlp_zero_output_is_tpa(be):
+    pc.check_engine_mlp_zero_output_is_tpa(be)
