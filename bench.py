@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-bands", type=int, default=40)
     ap.add_argument("--also-fp64", action="store_true", help="also time the FP64 cycle")
+    ap.add_argument("--gemm", choices=["fp64", "bf16x3", "bf16x6"], default="fp64",
+                    help="arithmetic of the Rayleigh-Ritz subspace products (FP32 plan)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only time a plain device-to-device copy of MIB MiB (stream bandwidth and "
                          "the calibration of the HBM byte counters), then exit")
@@ -136,7 +138,8 @@ def main():
     be = fde.gpu_backend("cuda:0")
     system = fde_synth.config2()
     print("# building engine", file=sys.stderr, flush=True)
-    eng = driver.Engine(system, prec=prec, backend=be)
+    gemm = {"fp64": fde.GEMM_FP64, "bf16x3": fde.GEMM_BF16X3, "bf16x6": fde.GEMM_BF16X6}[a.gemm]
+    eng = driver.Engine(system, prec=prec, backend=be, gemm=gemm)
     torch.cuda.synchronize()
     print("# engine ready", file=sys.stderr, flush=True)
     secs, wall = time_cycles(eng, a.steps, a.warmup)
@@ -209,6 +212,7 @@ def main():
         "config": {"workload": "slab+molecule 10.2x10.2x40 bohr, 60x60x240 grid, Ecut 40 Ha, "
                                "slab 36 ions/40 bands/4 k + molecule 6 ions/8 bands/Gamma",
                    "band_applies_per_cycle": per_cycle, "davidson_per_cycle": system.n_david,
+                   "subspace_products": a.gemm,
                    "parallelism": "single GPU"},
         "isolated_apply_h": {"band_applies_per_s": isolated, "bands": nb, "ms_per_call": t_apply * 1e3},
         "roofline": {"kernel": "fde_apply_h: FFT sandwich (KZInv, KPlaneHReg, KZFwd) + projectors "

@@ -105,6 +105,25 @@ fde_status fde_plan_set_workspace(fde_plan* plan, void* d_ws, size_t bytes, int 
                                   int max_batch);
 
 /*
+ * Arithmetic of the subspace products S = V^H V and A = V^H HV of
+ * fde_subspace_rr(_batched) (the Rayleigh-Ritz step of the band solver):
+ *   FDE_GEMM_FP64   inputs widened to FP64, FP64 matrix cores (default);
+ *   FDE_GEMM_BF16X3 FP32 inputs split in two BF16 terms, products of the term
+ *                   pairs (0,0), (0,1), (1,0) on BF16 matrix cores, FP32
+ *                   accumulation over 32-wide k tiles, FP64 sums of the tiles
+ *                   (about 16 significant bits per product);
+ *   FDE_GEMM_BF16X6 three BF16 terms, six term pairs (about FP32 products).
+ * The split modes need an FP32 plan (FDE_ERR_UNSUPPORTED otherwise). The
+ * Cholesky and the eigensolver stay FP64 in every mode. In the split modes the
+ * dependent-column threshold of the Cholesky is at least 2e-4 (BF16X3) or
+ * 1e-6 (BF16X6) of S_jj: about ten times the products' relative noise.
+ */
+#define FDE_GEMM_FP64 0
+#define FDE_GEMM_BF16X3 1
+#define FDE_GEMM_BF16X6 2
+fde_status fde_plan_set_gemm_mode(fde_plan* plan, int mode);
+
+/*
  * H_I |psi_nk> (Eq. KS with the recast V_eff of the Appendix, and the
  * Kleinman-Bylander projectors of the subsystem's own atoms as in the
  * Appendix on non-local pseudopotentials):

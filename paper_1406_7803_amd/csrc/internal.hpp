@@ -47,6 +47,7 @@ struct fde_plan {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   int max_nb = 0, max_nproj = 0, max_batch = 1;
+  int gemm = 0;  // FDE_GEMM_* of the subspace products
   void* d_tw[3] = {nullptr, nullptr, nullptr};  // twiddles exp(-2 pi i m/N_a), plan precision
   char* scratch = nullptr;
   size_t scratch_bytes = 0;

@@ -149,4 +149,201 @@ struct KAhB {
   }
 };
 
+// ---------------------------------------------------------------------------
+// The same products from FP32 inputs on BF16 matrix cores (FP32 plans only).
+// Every real component x is split into NS BF16 terms, x = x_0 + x_1 (+ x_2),
+// x_s = bf16(x - x_0 - ... - x_{s-1}); a real product keeps the term pairs
+// (s, t) with s + t < NS: (0,0), (0,1), (1,0) for NS = 2 ("BF16x3", about 16
+// significant bits) and additionally (1,1), (0,2), (2,0) for NS = 3 ("BF16x6",
+// about FP32). Products of BF16 terms are exact in FP32; v_mfma_f32_16x16x16bf16_1k
+// accumulates a 32-wide k tile in FP32, which is then added to FP64 sums.
+// Operand layout (wave64): a[i] = A[l%16][4(l/16)+i], b[i] = B[4(l/16)+i][l%16],
+// c[r] = C[4(l/16)+r][l%16]. The split terms are formed once when a tile is
+// staged in LDS: planes [term][re|im][row][k] of BF16.
+// ---------------------------------------------------------------------------
+template <int NS>
+struct KAhBSplit {
+  static constexpr int TI = 32, TJ = 32, KT = 32, LDK = KT + 4;
+  static constexpr int PLANE = 32 * LDK;             // one [row][k] plane (BF16)
+  static constexpr int MAT = NS * 2 * PLANE;         // one matrix: NS terms x (re, im)
+  static size_t lds_bytes() {
+    size_t s = sizeof(unsigned short) * 3 * MAT;
+#ifdef FDE_EMULATE
+    s += sizeof(double) * 4 * TI * TJ;
+#endif
+    return s;
+  }
+  FDE_HD static unsigned short bf(float x) {
+    unsigned u = __builtin_bit_cast(unsigned, x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)(u >> 16);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+  }
+  FDE_HD static float fb(unsigned short h) { return __builtin_bit_cast(float, (unsigned)h << 16); }
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const AhBSet<float> set) {
+    const AhBProb<float>& P = set.p[c.bz()];
+    const int ntj = (P.mb + TJ - 1) / TJ;
+    const int nti = (P.ma + TI - 1) / TI;
+    if (c.bx() >= P.nchunk || c.by() >= nti * ntj) return;  // uniform per block
+    const int i0 = (c.by() / ntj) * TI, j0 = (c.by() % ntj) * TJ;
+    const int g0 = c.bx() * P.chunk;
+    const int gend = (g0 + P.chunk) < P.npw ? (g0 + P.chunk) : P.npw;
+    const bool two = P.B1 != nullptr;
+    const int npw = P.npw;
+    unsigned short* sA = (unsigned short*)lds;
+    unsigned short* sB0 = sA + MAT;
+    unsigned short* sB1 = sB0 + MAT;
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef short s4 __attribute__((ext_vector_type(4)));
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const int lane = c.tid() & 63, wave = c.tid() >> 6;
+    const int wi = wave >> 1, wj = wave & 1;
+    double dre0[4] = {0, 0, 0, 0}, dim0[4] = {0, 0, 0, 0}, dre1[4] = {0, 0, 0, 0}, dim1[4] = {0, 0, 0, 0};
+    auto ld4 = [&](const unsigned short* base, int term, int ri, int row, int k) {
+      const uint2 v = *(const uint2*)(base + (term * 2 + ri) * PLANE + row * LDK + k);
+      s4 r;
+      r[0] = (short)(v.x & 0xffff);
+      r[1] = (short)(v.x >> 16);
+      r[2] = (short)(v.y & 0xffff);
+      r[3] = (short)(v.y >> 16);
+      return r;
+    };
+    auto neg = [](s4 v) {
+      s4 r;
+      for (int i = 0; i < 4; ++i) r[i] = (short)(v[i] ^ (short)0x8000);
+      return r;
+    };
+#else
+    double* acc = (double*)(sB1 + MAT);  // [4][TI][TJ]: re0, im0, re1, im1
+    for (int o = c.tid(); o < 4 * TI * TJ; o += c.nthr()) acc[o] = 0.0;
+#endif
+    for (int gs = g0; gs < gend; gs += KT) {
+      // one item: 4 consecutive k of one row of one matrix -> NS x 2 packed 8-byte stores
+      const int nmat = two ? 3 : 2;
+      for (int idx = c.tid(); idx < nmat * TI * (KT / 4); idx += c.nthr()) {
+        const int mat = idx / (TI * (KT / 4)), rem = idx - mat * (TI * (KT / 4));
+        const int r = rem / (KT / 4), k = 4 * (rem - r * (KT / 4));
+        const cplx<float>* src = mat == 0 ? P.A : (mat == 1 ? P.B0 : P.B1);
+        const int row = (mat == 0 ? i0 : j0) + r;
+        const bool rok = row < (mat == 0 ? P.ma : P.mb);
+        unsigned short* dst = (mat == 0 ? sA : (mat == 1 ? sB0 : sB1)) + r * LDK + k;
+        float vx[4], vy[4];
+        for (int q = 0; q < 4; ++q) {
+          const int g = gs + k + q;
+          const cplx<float> v = (rok && g < gend) ? src[(size_t)row * npw + g] : mk<float>(0, 0);
+          vx[q] = v.x;
+          vy[q] = v.y;
+        }
+        for (int t = 0; t < NS; ++t) {
+          unsigned short hx[4], hy[4];
+          for (int q = 0; q < 4; ++q) {
+            hx[q] = bf(vx[q]);
+            hy[q] = bf(vy[q]);
+            vx[q] -= fb(hx[q]);
+            vy[q] -= fb(hy[q]);
+          }
+          uint2 px, py;
+          px.x = (unsigned)hx[0] | ((unsigned)hx[1] << 16);
+          px.y = (unsigned)hx[2] | ((unsigned)hx[3] << 16);
+          py.x = (unsigned)hy[0] | ((unsigned)hy[1] << 16);
+          py.y = (unsigned)hy[2] | ((unsigned)hy[3] << 16);
+          *(uint2*)(dst + (t * 2) * PLANE) = px;
+          *(uint2*)(dst + (t * 2 + 1) * PLANE) = py;
+        }
+      }
+      c.sync();
+#if defined(__HIP_DEVICE_COMPILE__)
+      f4 re0 = {0, 0, 0, 0}, im0 = {0, 0, 0, 0}, re1 = {0, 0, 0, 0}, im1 = {0, 0, 0, 0};
+      const int ra = wi * 16 + (lane & 15), rb = wj * 16 + (lane & 15);
+#pragma unroll
+      for (int k0 = 0; k0 < KT; k0 += 16) {
+        const int kk = k0 + 4 * (lane >> 4);
+        s4 ar[NS], ai[NS], nai[NS], br[NS], bi[NS], hr[NS], hi[NS];
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+          ar[t] = ld4(sA, t, 0, ra, kk);
+          ai[t] = ld4(sA, t, 1, ra, kk);
+          nai[t] = neg(ai[t]);
+          br[t] = ld4(sB0, t, 0, rb, kk);
+          bi[t] = ld4(sB0, t, 1, rb, kk);
+          if (two) {
+            hr[t] = ld4(sB1, t, 0, rb, kk);
+            hi[t] = ld4(sB1, t, 1, rb, kk);
+          }
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+#pragma unroll
+          for (int t = 0; t < NS; ++t) {
+            if (s + t >= NS) continue;
+            re0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar[s], br[t], re0, 0, 0, 0);
+            re0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai[s], bi[t], re0, 0, 0, 0);
+            im0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar[s], bi[t], im0, 0, 0, 0);
+            im0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(nai[s], br[t], im0, 0, 0, 0);
+            if (two) {
+              re1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar[s], hr[t], re1, 0, 0, 0);
+              re1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai[s], hi[t], re1, 0, 0, 0);
+              im1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar[s], hi[t], im1, 0, 0, 0);
+              im1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(nai[s], hr[t], im1, 0, 0, 0);
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        dre0[r] += re0[r];
+        dim0[r] += im0[r];
+        dre1[r] += re1[r];
+        dim1[r] += im1[r];
+      }
+#else
+      for (int o = c.tid(); o < TI * TJ; o += c.nthr()) {
+        const int i = o / TJ, j = o - i * TJ;
+        float sx = 0, sy = 0, tx = 0, ty = 0;
+        for (int k = 0; k < KT; ++k)
+          for (int s = 0; s < NS; ++s)
+            for (int t = 0; t + s < NS; ++t) {
+              const float ar = fb(sA[(s * 2) * PLANE + i * LDK + k]), ai = fb(sA[(s * 2 + 1) * PLANE + i * LDK + k]);
+              const float br = fb(sB0[(t * 2) * PLANE + j * LDK + k]), bi = fb(sB0[(t * 2 + 1) * PLANE + j * LDK + k]);
+              sx += ar * br + ai * bi;
+              sy += ar * bi - ai * br;
+              if (two) {
+                const float hr = fb(sB1[(t * 2) * PLANE + j * LDK + k]), hi = fb(sB1[(t * 2 + 1) * PLANE + j * LDK + k]);
+                tx += ar * hr + ai * hi;
+                ty += ar * hi - ai * hr;
+              }
+            }
+        acc[o] += sx;
+        acc[TI * TJ + o] += sy;
+        acc[2 * TI * TJ + o] += tx;
+        acc[3 * TI * TJ + o] += ty;
+      }
+#endif
+      c.sync();
+    }
+    const int nprod = two ? 2 : 1;
+    const size_t mab = (size_t)P.ma * P.mb;
+    cplx<double>* out = P.part + (size_t)c.bx() * nprod * mab;
+#if defined(__HIP_DEVICE_COMPILE__)
+    const int j = j0 + wj * 16 + (lane & 15);
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + wi * 16 + 4 * (lane >> 4) + r;
+      if (i < P.ma && j < P.mb) {
+        out[(size_t)i * P.mb + j] = mk<double>(dre0[r], dim0[r]);
+        if (two) out[mab + (size_t)i * P.mb + j] = mk<double>(dre1[r], dim1[r]);
+      }
+    }
+#else
+    for (int o = c.tid(); o < TI * TJ; o += c.nthr()) {
+      const int i = i0 + o / TJ, j = j0 + o % TJ;
+      if (i < P.ma && j < P.mb) {
+        out[(size_t)i * P.mb + j] = mk<double>(acc[o], acc[TI * TJ + o]);
+        if (two) out[mab + (size_t)i * P.mb + j] = mk<double>(acc[2 * TI * TJ + o], acc[3 * TI * TJ + o]);
+      }
+    }
+#endif
+  }
+};
+
 }  // namespace fde

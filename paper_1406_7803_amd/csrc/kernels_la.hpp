@@ -345,6 +345,58 @@ struct KRotate {
       for (int idx = c.tid(); idx < m * nb; idx += c.nthr()) sC[idx] = Cg[idx];
     c.sync();
     const cplx<T>* Cs = c_in_lds ? sC : Cg;
+#if defined(__HIP_DEVICE_COMPILE__)
+    if (GC == 64 && c_in_lds && c.nthr() == 256 && nb <= 64) {
+      // matrix cores: wave w owns plane-wave columns 16 w .. 16 w + 15 and every 16-band tile;
+      // X = C^T V as four real products per complex one (Re = CrVr - CiVi, Im = CrVi + CiVr)
+      const int lane = c.tid() & 63, w = c.tid() >> 6;
+      const int col = lane & 15, kq = lane >> 4;
+      constexpr int MT = 4;  // up to 64 bands per block
+      typedef T v4 __attribute__((ext_vector_type(4)));
+      v4 re[MT], im[MT];
+#pragma unroll
+      for (int t = 0; t < MT; ++t) {
+        re[t] = v4{0, 0, 0, 0};
+        im[t] = v4{0, 0, 0, 0};
+      }
+      const int nmt = (nb + 15) / 16;
+      for (int k0 = 0; k0 < m; k0 += 4) {
+        const int k = k0 + kq;
+        const cplx<T> b = k < m ? sV[k * GC + 16 * w + col] : mk<T>(0, 0);
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+          if (t >= nmt) break;
+          const int n = 16 * t + col;
+          const cplx<T> a_ = (k < m && n < nb) ? sC[(size_t)k * nb + n] : mk<T>(0, 0);
+          if constexpr (sizeof(T) == 8) {
+            re[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_.x, b.x, re[t], 0, 0, 0);
+            re[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_.y, b.y, re[t], 0, 0, 0);
+            im[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_.x, b.y, im[t], 0, 0, 0);
+            im[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_.y, b.x, im[t], 0, 0, 0);
+          } else {
+            re[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_.x, b.x, re[t], 0, 0, 0);
+            re[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a_.y, b.y, re[t], 0, 0, 0);
+            im[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_.x, b.y, im[t], 0, 0, 0);
+            im[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_.y, b.x, im[t], 0, 0, 0);
+          }
+        }
+      }
+      const int g = 16 * w + col;
+      if (g < gc) {
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+          if (t >= nmt) break;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            // output row of register r: FP64 MFMA 4 r + l/16, FP32 MFMA 4 (l/16) + r
+            const int n = 16 * t + (sizeof(T) == 8 ? 4 * r + kq : 4 * kq + r);
+            if (n < nb) M[(size_t)n * npw + g0 + g] = mk<T>(re[t][r], im[t][r]);
+          }
+        }
+      }
+      return;
+    }
+#endif
     for (int o = c.tid(); o < nb * GC; o += c.nthr()) {
       const int n = o / GC, g = o - n * GC;
       if (g >= gc) continue;

@@ -20,6 +20,7 @@
 namespace fde {
 
 constexpr int kRRLdsMax = 80;
+constexpr int kWRows = 15;  // row groups of the eigenvector update items
 
 FDE_HD int tri(int i, int j) { return i * (i + 1) / 2 + j; }  // j <= i
 
@@ -55,8 +56,8 @@ struct KRRSolveLds {
     const int mp = m + (m & 1), npair = mp / 2;
     const int nblk = npair * (npair - 1) / 2;
     size_t b = sizeof(cplx<double>) * ((size_t)m * (m + 1) / 2 + (size_t)m * (m + 1));
-    b += sizeof(double) * (32 + 6 * (size_t)npair + m);   // red, rotations, diag of S
-    b += sizeof(int) * (2 * (size_t)m + 2 * (size_t)npair);  // masked, order, pair table
+    b += sizeof(double) * (32 + 8 * (size_t)npair + m);   // red, rotations (two rounds), diag of S
+    b += sizeof(int) * (2 * (size_t)m + 4 * (size_t)npair);  // masked, order, pair tables (two rounds)
     b += sizeof(unsigned short) * ((size_t)nblk + 2);
     return b + 64;
   }
@@ -73,16 +74,12 @@ struct KRRSolveLds {
     cplx<double>* U = (cplx<double>*)lds;
     cplx<double>* M = U + (size_t)m * (m + 1) / 2;
     double* red = (double*)(M + (size_t)m * ld);
-    double* rc = red + 32;
-    double* rs = rc + npair;
-    double* rex = rs + npair;
-    double* rey = rex + npair;
-    double* sdiag = rey + npair;     // S_jj after masking
+    double* rot = red + 32;          // [2 rounds][4][npair]: c, s, Re e^{i phi}, Im e^{i phi}
+    double* sdiag = rot + 8 * npair; // S_jj after masking
     int* masked = (int*)(sdiag + m);
     int* order = masked + m;
-    int* pp = order + m;             // pair table of the current round
-    int* pq = pp + npair;
-    unsigned short* blk = (unsigned short*)(pq + npair);  // block item -> K | Q << 8
+    int* ptab = order + m;           // [2 rounds][2][npair]: the pairs (p, q)
+    unsigned short* blk = (unsigned short*)(ptab + 4 * npair);  // block item -> K | Q << 8
     const float inv_m = 1.0f / (float)m;
 
     if (tid == 0) a.info[0] = 0;
@@ -206,96 +203,132 @@ struct KRRSolveLds {
       blk[it] = (unsigned short)(K | (Q << 8));
     }
     c.sync();
-    // ---- cyclic parallel Jacobi on the packed Hermitian A~
+    // ---- cyclic parallel Jacobi on the packed Hermitian A~. Round r's rotations are computed by
+    //      the first wavefront while the others apply round r-1's rotations to the W^T rows
+    //      (rotation parameters double-buffered by round parity); then the 2 x 2 blocks.
     bool conv = false;
     double prev_off = 1e300;
-    for (int sweep = 0; sweep < 40 && !conv; ++sweep) {
-      for (int r = 0; r < mp - 1; ++r) {
-        // rotation of each pair; the pair's own 2 x 2 block is updated here
-        for (int k = tid; k < npair; k += nt) {
-          int p, q;
-          rr_pair(r, k, mp, p, q);
-          pp[k] = p;
-          pq[k] = q;
-          double cc = 1.0, ss = 0.0, ex = 1.0, ey = 0.0;
-          if (p < m && q < m) {
-            const cplx<double> bpq = hget(U, p, q);
-            const double app = U[tri(p, p)].x, aqq = U[tri(q, q)].x;
-            const double ab = sqrt(norm2(bpq));
-            if (ab > 1e-300) {
-              const double th = (aqq - app) / (2.0 * ab);
-              const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-              cc = 1.0 / sqrt(t * t + 1.0);
-              ss = t * cc;
-              ex = bpq.x / ab;
-              ey = bpq.y / ab;
-              U[tri(p, p)] = mk<double>(app - t * ab, 0.0);
-              U[tri(q, q)] = mk<double>(aqq + t * ab, 0.0);
-              hset(U, p, q, mk<double>(0.0, 0.0));
+    int rg = 0;  // rounds done
+    const int wbase = nt > 64 ? 64 : 0, wstride = nt > 64 ? nt - 64 : nt;
+    auto w_update = [&](int buf) {  // W^T rows p, q of every pair, rotated by round `buf`'s parameters
+      const double* rc = rot + buf * 4 * npair;
+      const double* rs = rc + npair;
+      const double* rex = rs + npair;
+      const double* rey = rex + npair;
+      const int* pp = ptab + buf * 2 * npair;
+      const int* pq = pp + npair;
+      for (int e = tid - wbase; e >= 0 && e < npair * kWRows; e += wstride) {
+        const int K = e / kWRows, i0 = e - K * kWRows;
+        if (rs[K] == 0.0) continue;
+        const int p = pp[K], q = pq[K];
+        const double cc = rc[K], ss = rs[K];
+        const cplx<double> em = mk<double>(rex[K], -rey[K]);
+        cplx<double>* wpr = M + (size_t)p * ld;
+        cplx<double>* wqr = M + (size_t)q * ld;
+        for (int ib = i0; ib < m; ib += 4 * kWRows) {
+          cplx<double> xp[4], xq[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int i = ib + u * kWRows;
+            if (i < m) {
+              xp[u] = wpr[i];
+              xq[u] = wqr[i];
             }
           }
-          rc[k] = cc;
-          rs[k] = ss;
-          rex[k] = ex;
-          rey[k] = ey;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int i = ib + u * kWRows;
+            if (i < m) {
+              const cplx<double> emq = em * xq[u];
+              wpr[i] = mk<double>(cc * xp[u].x - ss * emq.x, cc * xp[u].y - ss * emq.y);
+              wqr[i] = mk<double>(ss * xp[u].x + cc * emq.x, ss * xp[u].y + cc * emq.y);
+            }
+          }
         }
-        c.sync();
-        // off-diagonal 2 x 2 blocks (pairs K < Q): B' = G_K^H B G_Q; then the W^T rows
-        const int items = nblk + npair * m;
-        for (int it = tid; it < items; it += nt) {
-          if (it < nblk) {
-            const int K = blk[it] & 255, Q = blk[it] >> 8;
-            const bool rotK = rs[K] != 0.0, rotQ = rs[Q] != 0.0;
-            if (!rotK && !rotQ) continue;
-            const int p = pp[K], q = pq[K], p2 = pp[Q], q2 = pq[Q];
-            // rows {p, q} (one may be the dummy index m when m is odd), cols {p2, q2}
-            cplx<double> b00 = (p < m && p2 < m) ? hget(U, p, p2) : mk<double>(0, 0);
-            cplx<double> b01 = (p < m && q2 < m) ? hget(U, p, q2) : mk<double>(0, 0);
-            cplx<double> b10 = (q < m && p2 < m) ? hget(U, q, p2) : mk<double>(0, 0);
-            cplx<double> b11 = (q < m && q2 < m) ? hget(U, q, q2) : mk<double>(0, 0);
-            if (rotK) {  // rows: [c, -s e^{i phi}; s, c e^{i phi}]
-              const double c1 = rc[K], s1 = rs[K];
-              const cplx<double> ep = mk<double>(rex[K], rey[K]);
-              const cplx<double> e10 = ep * b10, e11 = ep * b11;
-              const cplx<double> n00 = mk<double>(c1 * b00.x - s1 * e10.x, c1 * b00.y - s1 * e10.y);
-              const cplx<double> n01 = mk<double>(c1 * b01.x - s1 * e11.x, c1 * b01.y - s1 * e11.y);
-              const cplx<double> n10 = mk<double>(s1 * b00.x + c1 * e10.x, s1 * b00.y + c1 * e10.y);
-              const cplx<double> n11 = mk<double>(s1 * b01.x + c1 * e11.x, s1 * b01.y + c1 * e11.y);
-              b00 = n00;
-              b01 = n01;
-              b10 = n10;
-              b11 = n11;
+      }
+    };
+    for (int sweep = 0; sweep < 40 && !conv; ++sweep) {
+      for (int r = 0; r < mp - 1; ++r, ++rg) {
+        const int buf = rg & 1;
+        double* rc = rot + buf * 4 * npair;
+        double* rs = rc + npair;
+        double* rex = rs + npair;
+        double* rey = rex + npair;
+        int* pp = ptab + buf * 2 * npair;
+        int* pq = pp + npair;
+        // rotation of each pair; the pair's own 2 x 2 block is updated here
+        if (tid < 64) {
+          for (int k = tid; k < npair; k += (nt < 64 ? nt : 64)) {
+            int p, q;
+            rr_pair(r, k, mp, p, q);
+            pp[k] = p;
+            pq[k] = q;
+            double cc = 1.0, ss = 0.0, ex = 1.0, ey = 0.0;
+            if (p < m && q < m) {
+              const cplx<double> bpq = hget(U, p, q);
+              const double app = U[tri(p, p)].x, aqq = U[tri(q, q)].x;
+              const double ab = sqrt(norm2(bpq));
+              if (ab > 1e-300) {
+                const double th = (aqq - app) / (2.0 * ab);
+                const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                cc = 1.0 / sqrt(t * t + 1.0);
+                ss = t * cc;
+                ex = bpq.x / ab;
+                ey = bpq.y / ab;
+                U[tri(p, p)] = mk<double>(app - t * ab, 0.0);
+                U[tri(q, q)] = mk<double>(aqq + t * ab, 0.0);
+                hset(U, p, q, mk<double>(0.0, 0.0));
+              }
             }
-            if (rotQ) {  // columns: [c, s; -s e^{-i phi}, c e^{-i phi}]
-              const double c2 = rc[Q], s2 = rs[Q];
-              const cplx<double> em = mk<double>(rex[Q], -rey[Q]);
-              const cplx<double> f01 = em * b01, f11 = em * b11;
-              const cplx<double> n00 = mk<double>(c2 * b00.x - s2 * f01.x, c2 * b00.y - s2 * f01.y);
-              const cplx<double> n01 = mk<double>(s2 * b00.x + c2 * f01.x, s2 * b00.y + c2 * f01.y);
-              const cplx<double> n10 = mk<double>(c2 * b10.x - s2 * f11.x, c2 * b10.y - s2 * f11.y);
-              const cplx<double> n11 = mk<double>(s2 * b10.x + c2 * f11.x, s2 * b10.y + c2 * f11.y);
-              b00 = n00;
-              b01 = n01;
-              b10 = n10;
-              b11 = n11;
-            }
-            if (p < m && p2 < m) hset(U, p, p2, b00);
-            if (p < m && q2 < m) hset(U, p, q2, b01);
-            if (q < m && p2 < m) hset(U, q, p2, b10);
-            if (q < m && q2 < m) hset(U, q, q2, b11);
-          } else {
-            const int e = it - nblk;
-            const int K = qdiv(e, inv_m), i = e - K * m;
-            if (rs[K] == 0.0) continue;
-            const int p = pp[K], q = pq[K];
-            const double cc = rc[K], ss = rs[K];
-            const cplx<double> em = mk<double>(rex[K], -rey[K]);
-            cplx<double>& wp = M[(size_t)p * ld + i];
-            cplx<double>& wq = M[(size_t)q * ld + i];
-            const cplx<double> xp = wp, emq = em * wq;
-            wp = mk<double>(cc * xp.x - ss * emq.x, cc * xp.y - ss * emq.y);
-            wq = mk<double>(ss * xp.x + cc * emq.x, ss * xp.y + cc * emq.y);
+            rc[k] = cc;
+            rs[k] = ss;
+            rex[k] = ex;
+            rey[k] = ey;
           }
+        }
+        if (rg > 0) w_update(buf ^ 1);
+        c.sync();
+        // off-diagonal 2 x 2 blocks (pairs K < Q): B' = G_K^H B G_Q
+        for (int it = tid; it < nblk; it += nt) {
+          const int K = blk[it] & 255, Q = blk[it] >> 8;
+          const bool rotK = rs[K] != 0.0, rotQ = rs[Q] != 0.0;
+          if (!rotK && !rotQ) continue;
+          const int p = pp[K], q = pq[K], p2 = pp[Q], q2 = pq[Q];
+          // rows {p, q} (one may be the dummy index m when m is odd), cols {p2, q2}
+          cplx<double> b00 = (p < m && p2 < m) ? hget(U, p, p2) : mk<double>(0, 0);
+          cplx<double> b01 = (p < m && q2 < m) ? hget(U, p, q2) : mk<double>(0, 0);
+          cplx<double> b10 = (q < m && p2 < m) ? hget(U, q, p2) : mk<double>(0, 0);
+          cplx<double> b11 = (q < m && q2 < m) ? hget(U, q, q2) : mk<double>(0, 0);
+          if (rotK) {  // rows: [c, -s e^{i phi}; s, c e^{i phi}]
+            const double c1 = rc[K], s1 = rs[K];
+            const cplx<double> ep = mk<double>(rex[K], rey[K]);
+            const cplx<double> e10 = ep * b10, e11 = ep * b11;
+            const cplx<double> n00 = mk<double>(c1 * b00.x - s1 * e10.x, c1 * b00.y - s1 * e10.y);
+            const cplx<double> n01 = mk<double>(c1 * b01.x - s1 * e11.x, c1 * b01.y - s1 * e11.y);
+            const cplx<double> n10 = mk<double>(s1 * b00.x + c1 * e10.x, s1 * b00.y + c1 * e10.y);
+            const cplx<double> n11 = mk<double>(s1 * b01.x + c1 * e11.x, s1 * b01.y + c1 * e11.y);
+            b00 = n00;
+            b01 = n01;
+            b10 = n10;
+            b11 = n11;
+          }
+          if (rotQ) {  // columns: [c, s; -s e^{-i phi}, c e^{-i phi}]
+            const double c2 = rc[Q], s2 = rs[Q];
+            const cplx<double> em = mk<double>(rex[Q], -rey[Q]);
+            const cplx<double> f01 = em * b01, f11 = em * b11;
+            const cplx<double> n00 = mk<double>(c2 * b00.x - s2 * f01.x, c2 * b00.y - s2 * f01.y);
+            const cplx<double> n01 = mk<double>(s2 * b00.x + c2 * f01.x, s2 * b00.y + c2 * f01.y);
+            const cplx<double> n10 = mk<double>(c2 * b10.x - s2 * f11.x, c2 * b10.y - s2 * f11.y);
+            const cplx<double> n11 = mk<double>(s2 * b10.x + c2 * f11.x, s2 * b10.y + c2 * f11.y);
+            b00 = n00;
+            b01 = n01;
+            b10 = n10;
+            b11 = n11;
+          }
+          if (p < m && p2 < m) hset(U, p, p2, b00);
+          if (p < m && q2 < m) hset(U, p, q2, b01);
+          if (q < m && p2 < m) hset(U, q, p2, b10);
+          if (q < m && q2 < m) hset(U, q, q2, b11);
         }
         c.sync();
       }
@@ -314,6 +347,8 @@ struct KRRSolveLds {
       prev_off = off;
       if (sweep == 39 && !conv && tid == 0) a.info[0] = -1;
     }
+    if (rg > 0) w_update((rg - 1) & 1);  // the last round's rotations
+    c.sync();
     // ---- eigenvalues, ascending order (ties by index)
     for (int i = tid; i < m; i += nt) a.theta[i] = U[tri(i, i)].x;
     c.sync();

@@ -98,7 +98,16 @@ static fde_status rr_launch(fde_plan* p, ProbSet<T>& ps, hipStream_t s) {
     gs.p[i] = AhBProb<T>{P.v, P.v, P.hv, P.m, P.m, P.npw, P.nchunk, P.chunk, P.part};
   }
   const int nt = (mmax + KAhB<T>::TI - 1) / KAhB<T>::TI;
-  FDE_TRY(launch<KAhB<T>>(dim3(kMaxChunks, nt * nt, ps.n), kBlock, KAhB<T>::lds_bytes(), s, gs));
+  if constexpr (sizeof(T) == 4) {
+    if (p->gemm == FDE_GEMM_BF16X3)
+      FDE_TRY(launch<KAhBSplit<2>>(dim3(kMaxChunks, nt * nt, ps.n), kBlock, KAhBSplit<2>::lds_bytes(), s, gs));
+    else if (p->gemm == FDE_GEMM_BF16X6)
+      FDE_TRY(launch<KAhBSplit<3>>(dim3(kMaxChunks, nt * nt, ps.n), kBlock, KAhBSplit<3>::lds_bytes(), s, gs));
+    else
+      FDE_TRY(launch<KAhB<T>>(dim3(kMaxChunks, nt * nt, ps.n), kBlock, KAhB<T>::lds_bytes(), s, gs));
+  } else {
+    FDE_TRY(launch<KAhB<T>>(dim3(kMaxChunks, nt * nt, ps.n), kBlock, KAhB<T>::lds_bytes(), s, gs));
+  }
   FDE_TRY(launch<KGramReduce<T>>(dim3((unsigned)((2 * (size_t)mmax * mmax + kLBlk - 1) / kLBlk), ps.n), kBlock, 0, s,
                                  ps));
   // LDS: fixed part + as much of the Jacobi matrices as fits in 160 KiB
@@ -127,7 +136,10 @@ static fde_status rr_batched_t(fde_plan* p, int nblk, const fde_block* blk, doub
   for (int b0 = 0; b0 < nblk; b0 += per) {
     ProbSet<T> ps;
     ps.n = std::min(per, nblk - b0);
-    ps.drop_tol = drop_tol;
+    // the split products carry relative noise of about 2^-16 (BF16x3) or 2^-24 (BF16x6): a smaller
+    // Cholesky pivot than ten times that is indistinguishable from a dependent column
+    const double floor_tol = p->gemm == FDE_GEMM_BF16X3 ? 2e-4 : (p->gemm == FDE_GEMM_BF16X6 ? 1e-6 : 0.0);
+    ps.drop_tol = drop_tol > floor_tol ? drop_tol : floor_tol;
     for (int i = 0; i < 3; ++i) ps.b[i] = p->b[i];
     for (int i = 0; i < ps.n; ++i) {
       ps.p[i] = make_prob<T>(p, blk[b0 + i]);
@@ -183,6 +195,15 @@ static int mlp_per_block(int n) { return 64 * std::max(1, (n + 64 * 1024 - 1) / 
 using namespace fde;
 
 extern "C" {
+
+fde_status fde_plan_set_gemm_mode(fde_plan* p, int mode) {
+  if (!p) return fail(FDE_ERR_ARG, "null plan");
+  if (mode != FDE_GEMM_FP64 && mode != FDE_GEMM_BF16X3 && mode != FDE_GEMM_BF16X6)
+    return fail(FDE_ERR_ARG, "unknown GEMM mode");
+  if (mode != FDE_GEMM_FP64 && p->prec != FDE_F32) return fail(FDE_ERR_UNSUPPORTED, "BF16-split products need an FP32 plan");
+  p->gemm = mode;
+  return FDE_OK;
+}
 
 fde_status fde_subspace_rr_batched(fde_plan* p, int nblk, const fde_block* blk, double drop_tol, hipStream_t s) {
   if (!p) return fail(FDE_ERR_ARG, "null plan");

@@ -47,6 +47,7 @@ class Engine:
     backend: Optional[fde.Backend] = None
     kinds: dict = field(default_factory=lambda: dict(xc=fde.XC_LDA, xc_nad=fde.XC_LDA, kin_nad=fde.KIN_LC94))
     mlp_params: Optional[torch.Tensor] = None   # learned preconditioner (FP32, FDE_MLP_NPARAM); None = TPA
+    gemm: int = fde.GEMM_FP64                   # arithmetic of the Rayleigh-Ritz subspace products
 
     def __post_init__(self):
         s = self.system
@@ -57,6 +58,8 @@ class Engine:
         self.plan = fde.Plan(s.L, s.grid, s.ecut, s.all_kfrac, prec=self.prec, max_nb=max_nb, max_nproj=nproj_max,
                              max_batch=min(16, nblocks), backend=self.be)
         p = self.plan
+        if self.gemm != fde.GEMM_FP64:
+            p.set_gemm_mode(self.gemm)
         dev = self.be.device
         atoms = [a for sub in s.subsystems for a in sub.atoms]
         self.vloc = p.local_potential([a.pos for a in atoms], [a.Z for a in atoms], [a.width for a in atoms])

@@ -179,3 +179,22 @@ def test_mlp_training_reduces_loss(be):
 
 def test_engine_mlp_zero_output_is_tpa(be):
     pc.check_engine_mlp_zero_output_is_tpa(be)
+
+
+@pytest.mark.parametrize("gemm", [fde.GEMM_BF16X3, fde.GEMM_BF16X6])
+def test_subspace_rr_bf16_split(be, gemm):
+    pc.check_subspace_rr(be, fde.F32, gemm=gemm)
+    pc.check_subspace_rr(be, fde.F32, drop_case=True, gemm=gemm)
+    pc.check_subspace_rr(be, fde.F32, nb=40, case=pc.MEDIUM, gemm=gemm)
+
+
+def test_gemm_mode_needs_fp32_plan(be):
+    plan = pc.small_plan(be, fde.F64)
+    with pytest.raises(fde.FdeError):
+        plan.set_gemm_mode(fde.GEMM_BF16X3)
+
+
+@pytest.mark.parametrize("gemm,tol", [(fde.GEMM_BF16X6, 1e-6), (fde.GEMM_BF16X3, 1e-4)])
+def test_trajectory_c1_fp32_bf16_split(be, gemm, tol):
+    w = pc.check_trajectory(be, fde.F32, fde_synth.config1(), 10, tol, 10 * tol, gemm=gemm)
+    print(f"\nc1 FP32 trajectory, GEMM mode {gemm}: max |d eps| {w[0]:.2e} Ha, max int |d rho| {w[1]:.2e}")
