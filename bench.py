@@ -17,9 +17,9 @@ with V_eff, stick forward FFT + kinetic term, Kleinman-Bylander projector
 products and update), timed with HIP events on the stream the kernels run on,
 over an isolated resident batch of all 40 slab bands at one k-point with the
 slab's 36 projectors. Algorithmic bytes per call (complex of `cs` bytes, V_eff
-real of `rs` bytes, shared by the BPW bands a plane workgroup handles; the
-projectors read once per call):
-    nb * (3*cs*npw + 4*cs*ncol*N3 + rs*N/BPW) + nproj*cs*npw.
+real of `rs` bytes; V_eff and the projectors counted once per call, whatever the
+launch shape re-reads):
+    nb * (3*cs*npw + 4*cs*ncol*N3) + rs*N + nproj*cs*npw.
 """
 from __future__ import annotations
 
@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-bands", type=int, default=40)
     ap.add_argument("--also-fp64", action="store_true", help="also time the FP64 cycle")
+    ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--gemm", choices=["fp64", "bf16x3", "bf16x6"], default="fp64",
                     help="arithmetic of the Rayleigh-Ritz subspace products (FP32 plan)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -75,13 +77,13 @@ def copy_probe(mib, reps=10):
             "copy_GBps": 2 * 4 * n / t / 1e9}
 
 
-def apply_bytes(plan, ik, nb, bpw, nproj):
+def apply_bytes(plan, ik, nb, nproj):
     cs = 16 if plan.prec == 0 else 8
     rs = cs // 2
     N1, N2, N3 = plan.grid
     npw, ncol = plan.npw(ik), plan.ncol(ik)
-    per_band = 3 * cs * npw + 4 * cs * ncol * N3 + rs * N1 * N2 * N3 / bpw
-    return per_band * nb + cs * npw * nproj
+    per_band = 3 * cs * npw + 4 * cs * ncol * N3
+    return per_band * nb + rs * N1 * N2 * N3 + cs * npw * nproj
 
 
 def measured_traffic():
@@ -101,17 +103,23 @@ def measured_traffic():
     return float(kv["traffic_bytes_per_call"])
 
 
-def time_cycles(eng, steps, warmup):
+def time_cycles(eng, steps, warmup, graph=False):
+    """Time `steps` cycles (eager launches, or replays of one captured HIP graph)."""
     import torch
     for _ in range(warmup):
         eng.cycle()
+    if graph:
+        eng.capture()
     torch.cuda.synchronize()
     s0 = torch.cuda.Event(enable_timing=True)
     s1 = torch.cuda.Event(enable_timing=True)
     s0.record()
     t0 = time.perf_counter()
     for k in range(steps):
-        eng.cycle()
+        if graph:
+            eng.replay()
+        else:
+            eng.cycle()
         print(f"# cycle {k + 1}/{steps} enqueued", file=sys.stderr, flush=True)
     s1.record()
     torch.cuda.synchronize()
@@ -142,7 +150,12 @@ def main():
     eng = driver.Engine(system, prec=prec, backend=be, gemm=gemm)
     torch.cuda.synchronize()
     print("# engine ready", file=sys.stderr, flush=True)
-    secs, wall = time_cycles(eng, a.steps, a.warmup)
+    tuned = None
+    if not a.no_autotune:
+        eng.cycle()  # a potential and bands to time with
+        tuned = eng.autotune()
+        print(f"# autotune: {tuned}", file=sys.stderr, flush=True)
+    secs, wall = time_cycles(eng, a.steps, a.warmup, graph=not a.eager)
     per_cycle = eng.band_applies_per_cycle()
     ms_step = secs / a.steps * 1e3
     value = per_cycle * a.steps / secs
@@ -167,9 +180,8 @@ def main():
     torch.cuda.synchronize()
     t_apply = e0.elapsed_time(e1) / 1e3 / a.apply_reps
     N3 = plan.grid[2]
-    bpw = max(1, min(nb, (N3 * nb) // 2048))
     nproj = 0 if b.beta is None else b.beta.shape[0]
-    alg_bytes = apply_bytes(plan, b.ik, nb, bpw, nproj)
+    alg_bytes = apply_bytes(plan, b.ik, nb, nproj)
     achieved = alg_bytes / t_apply / 1e9
     isolated = nb / t_apply
 
@@ -212,7 +224,8 @@ def main():
         "config": {"workload": "slab+molecule 10.2x10.2x40 bohr, 60x60x240 grid, Ecut 40 Ha, "
                                "slab 36 ions/40 bands/4 k + molecule 6 ions/8 bands/Gamma",
                    "band_applies_per_cycle": per_cycle, "davidson_per_cycle": system.n_david,
-                   "subspace_products": a.gemm,
+                   "subspace_products": a.gemm, "launch": "eager" if a.eager else "one HIP graph per cycle",
+                   "apply_bands_per_plane_workgroup": None if tuned is None else tuned[0],
                    "parallelism": "single GPU"},
         "isolated_apply_h": {"band_applies_per_s": isolated, "bands": nb, "ms_per_call": t_apply * 1e3},
         "roofline": {"kernel": "fde_apply_h: FFT sandwich (KZInv, KPlaneHReg, KZFwd) + projectors "

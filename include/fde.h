@@ -118,6 +118,16 @@ fde_status fde_plan_set_workspace(fde_plan* plan, void* d_ws, size_t bytes, int 
  * dependent-column threshold of the Cholesky is at least 2e-4 (BF16X3) or
  * 1e-6 (BF16X6) of S_jj: about ten times the products' relative noise.
  */
+/*
+ * Launch-shape tuning (no effect on results). FDE_TUNE_APPLY_BPW: bands per
+ * plane-pass workgroup of fde_apply_h (each workgroup reads one V_eff plane
+ * for that many bands); 0 restores the automatic choice. The driver's
+ * autotuner times candidate values on the plan's own shapes and keeps the
+ * fastest.
+ */
+#define FDE_TUNE_APPLY_BPW 1
+fde_status fde_plan_set_tuning(fde_plan* plan, int key, int value);
+
 #define FDE_GEMM_FP64 0
 #define FDE_GEMM_BF16X3 1
 #define FDE_GEMM_BF16X6 2

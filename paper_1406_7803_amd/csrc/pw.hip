@@ -92,8 +92,8 @@ static fde_status apply_h_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, cpl
     FDE_TRY(launch<KZInv<T>>(dim3(ngz, nbc), kBlock, zlds, s, ps, t.npw, (const int4*)t.d_sticks, t.ncol,
                              p->rad[2], tw3, sb, SZ));
     if (reg_plane) {
-      // about two workgroups (one wave each) per SIMD over the whole chip
-      const int BPW = std::max(1, std::min(nbc, (N3 * nbc) / 2048));
+      // about two workgroups (one wave each) per SIMD over the whole chip, unless tuned
+      const int BPW = p->tune_bpw > 0 ? std::min(nbc, p->tune_bpw) : std::max(1, std::min(nbc, (N3 * nbc) / 4096));
       const dim3 g(N3, (nbc + BPW - 1) / BPW);
       if (cls == 0)
         FDE_TRY(launch<KPlaneHReg<T, 0>, 64, REGW>(g, 64, rlds, s, sb, nbc, BPW, (const int4*)t.d_sticks, t.ncol,
@@ -102,7 +102,7 @@ static fde_status apply_h_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, cpl
         FDE_TRY(launch<KPlaneHReg<T, 1>, 64, REGW>(g, 64, rlds, s, sb, nbc, BPW, (const int4*)t.d_sticks, t.ncol,
                                                    t.nxa, t.mlo, N1, N2, N3, veff));
     } else {
-      const int BPW = std::max(1, std::min(nbc, (N3 * nbc) / 2048));
+      const int BPW = p->tune_bpw > 0 ? std::min(nbc, p->tune_bpw) : std::max(1, std::min(nbc, (N3 * nbc) / 4096));
       FDE_TRY(launch<KPlaneH<T>>(dim3(N3, (nbc + BPW - 1) / BPW), kBlock, plds, s, sb, nbc, BPW,
                                  (const int4*)t.d_sticks, (const int*)t.d_xlist, t.ncol, t.nxa, p->rad[0], p->rad[1],
                                  N3, tw1, tw2, veff, RB));
@@ -385,6 +385,14 @@ fde_status fde_band_energies(fde_plan* p, int ik, int nb, const void* psi, const
     return band_energies_t<double>(p, ik, nb, (const cplx<double>*)psi, occw, nproj, (const cplx<double>*)beta, dkb,
                                    out, s);
   return band_energies_t<float>(p, ik, nb, (const cplx<float>*)psi, occw, nproj, (const cplx<float>*)beta, dkb, out, s);
+}
+
+fde_status fde_plan_set_tuning(fde_plan* p, int key, int value) {
+  if (!p) return fail(FDE_ERR_ARG, "null plan");
+  if (key != FDE_TUNE_APPLY_BPW) return fail(FDE_ERR_ARG, "unknown tuning key");
+  if (value < 0 || value > 1024) return fail(FDE_ERR_ARG, "tuning value out of range");
+  p->tune_bpw = value;
+  return FDE_OK;
 }
 
 }  // extern "C"

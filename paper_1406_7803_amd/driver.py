@@ -167,6 +167,53 @@ class Engine:
                 p.density(b.ik, b.V[:b.nb], self.occw[I][b.j], self.rho_out[I])
         fde.mix(self.be, self.rho_in, self.rho_out, s.mix_beta)
 
+    # ---- one HIP graph per cycle ------------------------------------------------
+    def capture(self, n_david: Optional[int] = None):
+        """Run one cycle eagerly (first-use set-up of every kernel), then record the
+        next cycle into a HIP graph; replay() runs the recorded cycle. The state
+        tensors are fixed, so every replay advances the same engine by one cycle."""
+        if self.be.emulated:
+            raise fde.FdeError("graph capture needs the GPU backend")
+        self.cycle(n_david)
+        torch.cuda.synchronize(self.be.device)
+        self._graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self._graph):
+            self.cycle(n_david)
+        torch.cuda.synchronize(self.be.device)
+
+    def replay(self):
+        self._graph.replay()
+
+    # ---- launch-shape autotuning ----------------------------------------------
+    def autotune(self, candidates=(1, 2, 4, 8, 16), reps: int = 5):
+        """Time fde_apply_h of the largest band block with each bands-per-plane-
+        workgroup value and keep the fastest (launch shape only; results unchanged)."""
+        if self.be.emulated:
+            return None
+        b = max((b for row in self.blocks for b in row), key=lambda b: b.nb * self.plan.npw(b.ik))
+        X = b.V[:b.nb]
+        HX = b.HV[b.nb:2 * b.nb] if b.HV.shape[0] >= 2 * b.nb else torch.empty_like(X)
+        veff = self.veff[b.isub]
+        best = None
+        times = {}
+        for bpw in candidates:
+            if bpw > b.nb:
+                continue
+            self.plan.set_tuning(fde.TUNE_APPLY_BPW, bpw)
+            self.plan.apply_h(b.ik, X, veff, b.beta, b.dkb, out=HX)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                self.plan.apply_h(b.ik, X, veff, b.beta, b.dkb, out=HX)
+            e1.record()
+            torch.cuda.synchronize(self.be.device)
+            times[bpw] = e0.elapsed_time(e1) / reps
+            if best is None or times[bpw] < times[best]:
+                best = bpw
+        self.plan.set_tuning(fde.TUNE_APPLY_BPW, best)
+        return best, times
+
     def band_applies_per_cycle(self, n_david: Optional[int] = None) -> int:
         n_david = self.system.n_david if n_david is None else n_david
         return sum(b.nb * (1 + n_david) for row in self.blocks for b in row)

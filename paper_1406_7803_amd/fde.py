@@ -34,7 +34,9 @@ SYMBOLS = [
     "fde_local_potential", "fde_kb_projectors", "fde_init_bands", "fde_band_energies", "fde_grid_dot",
     "fde_subspace_rr_batched", "fde_precondition_batched", "fde_grid_mean", "fde_precondition_mlp_batched",
     "fde_mlp_forward", "fde_mlp_workspace_bytes", "fde_mlp_loss_grad", "fde_mlp_adam", "fde_plan_set_gemm_mode",
+    "fde_plan_set_tuning",
 ]
+TUNE_APPLY_BPW = 1
 GEMM_FP64, GEMM_BF16X3, GEMM_BF16X6 = 0, 1, 2
 MLP_NPARAM, MLP_NIN, MLP_SAMPLE = 4545, 4, 7
 
@@ -85,6 +87,7 @@ def _declare(lib):
     lib.fde_grid_dot.argtypes = [_P, _P, _P, _P, _P]
     lib.fde_grid_mean.argtypes = [_P, _P, _P, _P]
     lib.fde_plan_set_gemm_mode.argtypes = [_P, _I]
+    lib.fde_plan_set_tuning.argtypes = [_P, _I, _I]
     lib.fde_precondition_mlp_batched.argtypes = [_P, _I, _P, _P, _P, _P]
     lib.fde_mlp_forward.argtypes = [_I, _P, _P, _P, _P]
     lib.fde_mlp_workspace_bytes.argtypes = [_I, ctypes.POINTER(_S)]
@@ -354,6 +357,9 @@ class Plan:
         out = torch.zeros(1, dtype=torch.float64, device=self.be.device) if out is None else out
         self._check(self.lib.fde_grid_dot(self.h, _ptr(a), _ptr(b), _ptr(out), self.be.stream()))
         return out
+
+    def set_tuning(self, key: int, value: int):
+        self._check(self.lib.fde_plan_set_tuning(self.h, int(key), int(value)))
 
     def set_gemm_mode(self, mode: int):
         """Arithmetic of the Rayleigh-Ritz subspace products (GEMM_FP64, GEMM_BF16X3, GEMM_BF16X6)."""

@@ -431,3 +431,19 @@ def check_engine_mlp_zero_output_is_tpa(be):
     be.sync()
     for a, b in zip(e1.eps, e2.eps):
         assert np.max(np.abs(host(a) - host(b))) < 1e-12
+
+
+def check_tuning_keeps_results(be, prec):
+    """The bands-per-plane-workgroup launch shape does not change fde_apply_h's result."""
+    plan = small_plan(be, prec, max_nb=9)
+    cell = basis.Cell(SMALL["L"], SMALL["grid"])
+    sph = basis.sphere(cell, SMALL["ecut"], SMALL["kf"][0])
+    veff = to_dev(plan, fde_synth.random_real(4, cell.shape), "r")
+    psi = to_dev(plan, fde_synth.random_complex(5, (9, sph.npw)), "c")
+    ref = host(plan.apply_h(0, psi, veff)).copy()
+    for bpw in (1, 2, 3, 9):
+        plan.set_tuning(fde.TUNE_APPLY_BPW, bpw)
+        out = host(plan.apply_h(0, psi, veff))
+        be.sync()
+        assert np.max(np.abs(out - ref)) <= 1e-14 * np.max(np.abs(ref)), bpw
+    plan.set_tuning(fde.TUNE_APPLY_BPW, 0)

@@ -128,3 +128,8 @@ def test_gemm_mode_needs_fp32_plan(be):
     plan = pc.small_plan(be, fde.F64)
     with pytest.raises(fde.FdeError):
         plan.set_gemm_mode(fde.GEMM_BF16X3)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_tuning_keeps_results(be, prec):
+    pc.check_tuning_keeps_results(be, prec)

@@ -198,3 +198,36 @@ def test_gemm_mode_needs_fp32_plan(be):
 def test_trajectory_c1_fp32_bf16_split(be, gemm, tol):
     w = pc.check_trajectory(be, fde.F32, fde_synth.config1(), 10, tol, 10 * tol, gemm=gemm)
     print(f"\nc1 FP32 trajectory, GEMM mode {gemm}: max |d eps| {w[0]:.2e} Ha, max int |d rho| {w[1]:.2e}")
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_tuning_keeps_results(be, prec):
+    pc.check_tuning_keeps_results(be, prec)
+
+
+def test_graph_replay_matches_eager(be):
+    """One cycle captured in a HIP graph, replayed three times with eager work and
+    synchronisations in between; every replay matches the eager engine."""
+    from paper_1406_7803_amd import driver
+    s = fde_synth.config1()
+    eg = driver.Engine(s, prec=fde.F64, backend=be)
+    ee = driver.Engine(s, prec=fde.F64, backend=be)
+    eg.capture()
+    ee.cycle()
+    for k in range(3):
+        eg.replay()
+        ee.cycle()
+        extra = eg.plan.grid_dot(eg.rho_in[0], eg.rho_in[0])   # eager work between replays
+        be.sync()
+        assert float(pc.host(extra)[0]) > 0
+        for a, b in zip(eg.eps, ee.eps):
+            assert np.max(np.abs(pc.host(a) - pc.host(b))) < 1e-13, k
+        assert np.max(np.abs(pc.host(eg.rho_in) - pc.host(ee.rho_in))) < 1e-13, k
+
+
+def test_autotune_on_c2(be):
+    from paper_1406_7803_amd import driver
+    eng = driver.Engine(fde_synth.config2(), prec=fde.F32, backend=be)
+    best, times = eng.autotune()
+    print(f"\napply_h ms by bands per plane workgroup: {times}; chosen {best}")
+    assert best in times and times[best] == min(times.values())
