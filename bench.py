@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--cpu-bands", type=int, default=40)
     ap.add_argument("--also-fp64", action="store_true", help="also time the FP64 cycle")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
+    ap.add_argument("--no-tta", action="store_true", help="skip the time-to-1e-6 Ha comparison")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--gemm", choices=["fp64", "bf16x3", "bf16x6"], default="fp64",
                     help="arithmetic of the Rayleigh-Ritz subspace products (FP32 plan)")
@@ -127,6 +128,59 @@ def time_cycles(eng, steps, warmup, graph=False):
     return s0.elapsed_time(s1) / 1e3, wall
 
 
+def time_to_accuracy(be, max_cycles=300):
+    """Wall time until the two-subsystem cube's occupied eigenvalues are within 1e-6 Ha
+    and every subsystem density within 1e-5 (integrated |drho|) of the converged FP64
+    result, per precision mode (engine set-up excluded; each cycle is followed by the
+    same device-to-host check in every mode)."""
+    import numpy as np
+    import torch
+
+    import fde_synth
+    from paper_1406_7803_amd import driver, fde
+
+    s = fde_synth.config1()
+    dv = float(np.prod(s.L)) / float(np.prod(s.grid))
+
+    def state(e):
+        torch.cuda.synchronize()
+        return [x.double().cpu().numpy().copy() for x in e.eps], e.rho_out.double().cpu().numpy().copy()
+
+    ref = driver.Engine(s, prec=fde.F64, backend=be)
+    prev = None
+    for c in range(max_cycles):
+        ref.cycle()
+        eps, rho = state(ref)
+        if prev is not None and max(np.max(np.abs(a - b)) for a, b in zip(eps, prev[0])) < 1e-11 \
+                and np.sum(np.abs(rho - prev[1])) * dv < 1e-10:
+            break
+        prev = (eps, rho)
+    ref_cycles = c + 1
+    occ = [o.cpu().numpy() > 1e-8 for o in ref.occw]
+    out = {"system": "two-subsystem 10 bohr cube, 24^3, E_cut 7 Ha", "reference": f"FP64, {ref_cycles} cycles"}
+    for name, prec, gemm in (("fp64", fde.F64, fde.GEMM_FP64), ("fp32", fde.F32, fde.GEMM_FP64),
+                             ("fp32_bf16x6", fde.F32, fde.GEMM_BF16X6)):
+        warm = driver.Engine(s, prec=prec, backend=be, gemm=gemm)  # first launches of this mode's kernels
+        warm.cycle()
+        del warm
+        eng = driver.Engine(s, prec=prec, backend=be, gemm=gemm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hit = None
+        for c in range(max_cycles):
+            eng.cycle()
+            e, r = state(eng)
+            de = max(np.max(np.abs(a[o] - b[o])) for a, b, o in zip(e, eps, occ))
+            dr = max(np.sum(np.abs(r[I] - rho[I])) * dv for I in range(len(s.subsystems)))
+            if de <= 1e-6 and dr <= 1e-5:
+                hit = (c + 1, time.perf_counter() - t0)
+                break
+        out[name] = None if hit is None else {"cycles": hit[0], "seconds": hit[1]}
+    if out["fp64"] and out["fp32"]:
+        out["speedup_fp32_over_fp64"] = out["fp64"]["seconds"] / out["fp32"]["seconds"]
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -192,6 +246,8 @@ def main():
         fp64 = {"ms_per_cycle": s64 / max(2, a.steps // 2) * 1e3}
         del eng64
 
+    tta = None if a.no_tta else time_to_accuracy(be)
+
     cpu = None
     if not a.no_cpu_baseline:
         from oracle import basis, hamiltonian as oham, pseudo as opseudo
@@ -234,6 +290,7 @@ def main():
                      "traffic": measured_traffic(), "algorithmic_bytes": alg_bytes},
         "cpu_baseline": cpu,
         "stream_copy_GBps": copy_probe(1024)["copy_GBps"],
+        "time_to_1e-6Ha": tta,
         "fp64_cycle": fp64,
         "device_info_ok": eps_err_ok,
         "wall_s_timed": wall,
