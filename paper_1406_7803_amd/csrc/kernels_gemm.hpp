@@ -346,4 +346,126 @@ struct KAhBSplit {
   }
 };
 
+// ---------------------------------------------------------------------------
+// Both Gram products of a Rayleigh-Ritz problem in one pass over the plane
+// waves: S = V^H V and A = V^H HV for V, HV [m][npw] (m <= 16 kGramTiles).
+// One workgroup per (chunk, problem) stages all m rows of V and HV for a
+// 32-wide k tile, so every input element is read from HBM once; only the
+// lower-triangular 16 x 16 tiles are computed (both products are Hermitian) and
+// written with their mirror. FP64 matrix cores (inputs widened), FP64 partial
+// sums per chunk: part[chunk][prod][m][m].
+// ---------------------------------------------------------------------------
+constexpr int kGramTiles = 6;  // up to m = 96
+
+template <typename T>
+struct KGram {
+  static constexpr int KT = 32, LD = KT + 1, NW = 8;
+  static constexpr int MAXTP = (kGramTiles * (kGramTiles + 1) + NW - 1) / NW;  // tile-products per wave
+  static size_t lds_bytes(int m) { return sizeof(cplx<T>) * 2 * (size_t)m * LD; }
+  FDE_HD static void tile_of(int tp, int& I, int& J, int& prod) {
+    prod = tp & 1;  // S and A interleaved
+    int t = tp >> 1, i = 0;
+    while ((i + 1) * (i + 2) / 2 <= t) ++i;
+    I = i;
+    J = t - i * (i + 1) / 2;
+  }
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const AhBSet<T> set) {
+    const AhBProb<T>& P = set.p[c.by()];
+    const int m = P.ma, npw = P.npw;
+    if (c.bx() >= P.nchunk) return;  // uniform per block
+    const int g0 = c.bx() * P.chunk;
+    const int gend = (g0 + P.chunk) < npw ? (g0 + P.chunk) : npw;
+    const int nt = (m + 15) / 16, ntp = nt * (nt + 1);  // lower tiles x 2 products
+    cplx<T>* sV = (cplx<T>*)lds;
+    cplx<T>* sH = sV + (size_t)m * LD;
+    const size_t mm = (size_t)m * m;
+    cplx<double>* out = P.part + (size_t)c.bx() * 2 * mm;
+#if defined(__HIP_DEVICE_COMPILE__)
+    const int lane = c.tid() & 63, wave = c.tid() >> 6;
+    const int col = lane & 15, kq = lane >> 4;
+    fde_d4 re[MAXTP], im[MAXTP];
+#pragma unroll
+    for (int u = 0; u < MAXTP; ++u) {
+      re[u] = fde_d4{0, 0, 0, 0};
+      im[u] = fde_d4{0, 0, 0, 0};
+    }
+#else
+    cplx<double>* acc = out;  // the chunk's own partials serve as the accumulator
+    for (size_t o = c.tid(); o < 2 * mm; o += c.nthr()) acc[o] = mk<double>(0, 0);
+#endif
+    for (int gs = g0; gs < gend; gs += KT) {
+      for (int idx = c.tid(); idx < 2 * m * KT; idx += c.nthr()) {
+        const int h = idx / (m * KT), rem = idx - h * (m * KT);
+        const int r = rem / KT, k = rem - r * KT;
+        const int g = gs + k;
+        const cplx<T>* src = h ? P.B1 : P.A;
+        (h ? sH : sV)[r * LD + k] = g < gend ? src[(size_t)r * npw + g] : mk<T>(0, 0);
+      }
+      c.sync();
+#if defined(__HIP_DEVICE_COMPILE__)
+#pragma unroll
+      for (int u = 0; u < MAXTP; ++u) {
+        const int tp = wave + NW * u;
+        if (tp >= ntp) break;
+        int I, J, prod;
+        tile_of(tp, I, J, prod);
+        const int ra = 16 * I + col, rb = 16 * J + col;
+        const cplx<T>* sB = prod ? sH : sV;
+        for (int k0 = 0; k0 < KT; k0 += 4) {
+          const cplx<T> a = ra < m ? sV[ra * LD + k0 + kq] : mk<T>(0, 0);
+          const cplx<T> b = rb < m ? sB[rb * LD + k0 + kq] : mk<T>(0, 0);
+          const double ax = a.x, ay = a.y, bx = b.x, by = b.y;
+          re[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, bx, re[u], 0, 0, 0);
+          re[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ay, by, re[u], 0, 0, 0);
+          im[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, by, im[u], 0, 0, 0);
+          im[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ay, bx, im[u], 0, 0, 0);
+        }
+      }
+#else
+      for (size_t o = c.tid(); o < 2 * mm; o += c.nthr()) {
+        const int prod = (int)(o / mm), e = (int)(o - prod * mm);
+        const int i = e / m, j = e - i * m;
+        if (j > i) continue;
+        const cplx<T>* sB = prod ? sH : sV;
+        double sx = 0, sy = 0;
+        for (int k = 0; k < KT; ++k) {
+          const cplx<T> a = sV[i * LD + k], b = sB[j * LD + k];
+          sx += (double)a.x * b.x + (double)a.y * b.y;
+          sy += (double)a.x * b.y - (double)a.y * b.x;
+        }
+        acc[o].x += sx;
+        acc[o].y += sy;
+      }
+#endif
+      c.sync();
+    }
+#if defined(__HIP_DEVICE_COMPILE__)
+#pragma unroll
+    for (int u = 0; u < MAXTP; ++u) {
+      const int tp = wave + NW * u;
+      if (tp >= ntp) break;
+      int I, J, prod;
+      tile_of(tp, I, J, prod);
+      cplx<double>* o = out + (size_t)prod * mm;
+      const int j = 16 * J + col;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * I + 4 * r + kq;  // FP64 MFMA result layout
+        if (i < m && j < m) {
+          o[(size_t)i * m + j] = mk<double>(re[u][r], im[u][r]);
+          if (I != J) o[(size_t)j * m + i] = mk<double>(re[u][r], -im[u][r]);
+        }
+      }
+    }
+#else
+    for (size_t o = c.tid(); o < 2 * mm; o += c.nthr()) {  // mirror the lower triangle
+      const int prod = (int)(o / mm), e = (int)(o - prod * mm);
+      const int i = e / m, j = e - i * m;
+      if (j > i) out[o] = conj(acc[(size_t)prod * mm + (size_t)j * m + i]);
+    }
+#endif
+  }
+};
+
 }  // namespace fde

@@ -12,7 +12,7 @@ constexpr double kInactiveDiag = 1.0e6;
 
 
 constexpr int kMaxBatch = 16;   // problems per batched launch (descriptors travel as kernel arguments)
-constexpr int kMaxChunks = 16;  // plane-wave chunks of a Gram product
+constexpr int kMaxChunks = 64;  // plane-wave chunks of a Gram product
 
 // One band block of the solver: a (subsystem, k-point) pair. Rows 0..nb-1 of
 // v/hv are X/HX, rows nb..m-1 the correction vectors T/HT.

@@ -77,7 +77,7 @@ static Prob<T> make_prob(fde_plan* p, const fde_block& b) {
   P.npw = t.npw;
   P.m = b.m;
   P.nb = b.nb;
-  P.nchunk = std::min(kMaxChunks, (t.npw + 2047) / 2048);
+  P.nchunk = std::min(kMaxChunks, (t.npw + 767) / 768);
   P.chunk = (t.npw + P.nchunk - 1) / P.nchunk;
   P.chunk = (P.chunk + 31) / 32 * 32;
   return P;
@@ -103,10 +103,15 @@ static fde_status rr_launch(fde_plan* p, ProbSet<T>& ps, hipStream_t s) {
       FDE_TRY(launch<KAhBSplit<2>>(dim3(kMaxChunks, nt * nt, ps.n), kBlock, KAhBSplit<2>::lds_bytes(), s, gs));
     else if (p->gemm == FDE_GEMM_BF16X6)
       FDE_TRY(launch<KAhBSplit<3>>(dim3(kMaxChunks, nt * nt, ps.n), kBlock, KAhBSplit<3>::lds_bytes(), s, gs));
+    else if (mmax <= 16 * kGramTiles)
+      FDE_TRY((launch<KGram<T>, 512>(dim3(kMaxChunks, ps.n), 512, KGram<T>::lds_bytes(mmax), s, gs)));
     else
       FDE_TRY(launch<KAhB<T>>(dim3(kMaxChunks, nt * nt, ps.n), kBlock, KAhB<T>::lds_bytes(), s, gs));
   } else {
-    FDE_TRY(launch<KAhB<T>>(dim3(kMaxChunks, nt * nt, ps.n), kBlock, KAhB<T>::lds_bytes(), s, gs));
+    if (mmax <= 16 * kGramTiles)
+      FDE_TRY((launch<KGram<T>, 512>(dim3(kMaxChunks, ps.n), 512, KGram<T>::lds_bytes(mmax), s, gs)));
+    else
+      FDE_TRY(launch<KAhB<T>>(dim3(kMaxChunks, nt * nt, ps.n), kBlock, KAhB<T>::lds_bytes(), s, gs));
   }
   FDE_TRY(launch<KGramReduce<T>>(dim3((unsigned)((2 * (size_t)mmax * mmax + kLBlk - 1) / kLBlk), ps.n), kBlock, 0, s,
                                  ps));
