@@ -468,4 +468,94 @@ struct KGram {
   }
 };
 
+// ---------------------------------------------------------------------------
+// part[chunk][i][j] = sum_{G in chunk} conj(A_i(G)) B_j(G) for small ma, mb
+// (<= 64 each, e.g. projectors x bands): one workgroup per chunk stages all rows
+// of A and B for a 32-wide k tile, so each input element is read once; the
+// 16 x 16 output tiles are spread over eight wavefronts. FP64 matrix cores.
+// grid (nchunk), 512 threads.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct KAhBAll {
+  static constexpr int KT = 32, LD = KT + 1, NW = 8, MAXT = 2;  // 16 tiles over 8 waves
+  static size_t lds_bytes(int ma, int mb) { return sizeof(cplx<T>) * (size_t)(ma + mb) * LD; }
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const AhBProb<T> P) {
+    const int ma = P.ma, mb = P.mb, npw = P.npw;
+    if (c.bx() >= P.nchunk) return;
+    const int g0 = c.bx() * P.chunk;
+    const int gend = (g0 + P.chunk) < npw ? (g0 + P.chunk) : npw;
+    const int ti = (ma + 15) / 16, tj = (mb + 15) / 16, ntl = ti * tj;
+    cplx<T>* sA = (cplx<T>*)lds;
+    cplx<T>* sB = sA + (size_t)ma * LD;
+    cplx<double>* out = P.part + (size_t)c.bx() * ma * mb;
+#if defined(__HIP_DEVICE_COMPILE__)
+    const int lane = c.tid() & 63, wave = c.tid() >> 6;
+    const int col = lane & 15, kq = lane >> 4;
+    fde_d4 re[MAXT], im[MAXT];
+#pragma unroll
+    for (int u = 0; u < MAXT; ++u) {
+      re[u] = fde_d4{0, 0, 0, 0};
+      im[u] = fde_d4{0, 0, 0, 0};
+    }
+#else
+    for (int o = c.tid(); o < ma * mb; o += c.nthr()) out[o] = mk<double>(0, 0);
+#endif
+    for (int gs = g0; gs < gend; gs += KT) {
+      for (int idx = c.tid(); idx < (ma + mb) * KT; idx += c.nthr()) {
+        const int r = idx / KT, k = idx - r * KT;
+        const int g = gs + k;
+        const cplx<T>* src = r < ma ? P.A + (size_t)r * npw : P.B0 + (size_t)(r - ma) * npw;
+        sA[r * LD + k] = g < gend ? src[g] : mk<T>(0, 0);
+      }
+      c.sync();
+#if defined(__HIP_DEVICE_COMPILE__)
+#pragma unroll
+      for (int u = 0; u < MAXT; ++u) {
+        const int t = wave + NW * u;
+        if (t >= ntl) break;
+        const int I = t / tj, J = t - I * tj;
+        const int ra = 16 * I + col, rb = 16 * J + col;
+        for (int k0 = 0; k0 < KT; k0 += 4) {
+          const cplx<T> a = ra < ma ? sA[ra * LD + k0 + kq] : mk<T>(0, 0);
+          const cplx<T> b = rb < mb ? sB[rb * LD + k0 + kq] : mk<T>(0, 0);
+          const double ax = a.x, ay = a.y, bx = b.x, by = b.y;
+          re[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, bx, re[u], 0, 0, 0);
+          re[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ay, by, re[u], 0, 0, 0);
+          im[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, by, im[u], 0, 0, 0);
+          im[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ay, bx, im[u], 0, 0, 0);
+        }
+      }
+#else
+      for (int o = c.tid(); o < ma * mb; o += c.nthr()) {
+        const int i = o / mb, j = o - i * mb;
+        double sx = 0, sy = 0;
+        for (int k = 0; k < KT; ++k) {
+          const cplx<T> a = sA[i * LD + k], b = sB[j * LD + k];
+          sx += (double)a.x * b.x + (double)a.y * b.y;
+          sy += (double)a.x * b.y - (double)a.y * b.x;
+        }
+        out[o].x += sx;
+        out[o].y += sy;
+      }
+#endif
+      c.sync();
+    }
+#if defined(__HIP_DEVICE_COMPILE__)
+#pragma unroll
+    for (int u = 0; u < MAXT; ++u) {
+      const int t = wave + NW * u;
+      if (t >= ntl) break;
+      const int I = t / tj, J = t - I * tj;
+      const int j = 16 * J + col;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * I + 4 * r + kq;  // FP64 MFMA result layout
+        if (i < ma && j < mb) out[(size_t)i * mb + j] = mk<double>(re[u][r], im[u][r]);
+      }
+    }
+#endif
+  }
+};
+
 }  // namespace fde

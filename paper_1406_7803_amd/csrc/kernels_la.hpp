@@ -470,6 +470,121 @@ struct KPrecond {
   }
 };
 
+// The same preconditioner spread over plane-wave chunks (kPcChunks blocks per
+// band), in three passes with fixed-order reductions of per-chunk partials
+// (kept in the problem's Gram-partial scratch, free between Rayleigh-Ritz
+// steps): (A) |R|^2 and T_n^kin, (B) T = K R unnormalised and |T|^2, (C) the
+// normalisation, the active flag and ||R||. grid (kPcChunks, nb_max, nprob).
+constexpr int kPcChunks = 16;
+
+template <typename T>
+struct KPcBase {
+  FDE_HD static double kin_of_g(const Prob<T>& P, const ProbSet<T>& ps, int g) {
+    const int p = P.millp[g];
+    const double q1 = (((p & 1023) - 512) + P.kf[0]) * ps.b[0];
+    const double q2 = ((((p >> 10) & 1023) - 512) + P.kf[1]) * ps.b[1];
+    const double q3 = ((((p >> 20) & 1023) - 512) + P.kf[2]) * ps.b[2];
+    return 0.5 * (q1 * q1 + q2 * q2 + q3 * q3);
+  }
+  FDE_HD static void range(const Prob<T>& P, int ch, int& g0, int& g1) {
+    const int len = (P.npw + kPcChunks - 1) / kPcChunks;
+    g0 = ch * len;
+    g1 = (g0 + len) < P.npw ? (g0 + len) : P.npw;
+  }
+  FDE_HD static double* part(const Prob<T>& P, int n) { return (double*)P.part + (size_t)n * kPcChunks * 3; }
+};
+
+template <typename T>
+struct KPrecondA : KPcBase<T> {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const ProbSet<T> ps) {
+    const Prob<T>& P = ps.p[c.bz()];
+    const int n = c.by(), ch = c.bx();
+    if (n >= P.nb) return;  // uniform per block
+    int g0, g1;
+    KPcBase<T>::range(P, ch, g0, g1);
+    const double lam = P.eval[n];
+    const cplx<T>* xn = P.v + (size_t)n * P.npw;
+    const cplx<T>* hn = P.hv + (size_t)n * P.npw;
+    double r2 = 0.0, tk = 0.0;
+    for (int g = g0 + c.tid(); g < g1; g += c.nthr()) {
+      const cplx<T> xv = xn[g], hv = hn[g];
+      const double rx = (double)hv.x - lam * xv.x, ry = (double)hv.y - lam * xv.y;
+      r2 += rx * rx + ry * ry;
+      tk += KPcBase<T>::kin_of_g(P, ps, g) * ((double)xv.x * xv.x + (double)xv.y * xv.y);
+    }
+    r2 = c.sum(r2, (double*)lds);
+    tk = c.sum(tk, (double*)lds);
+    if (c.tid() == 0) {
+      double* pt = KPcBase<T>::part(P, n);
+      pt[ch] = r2;
+      pt[kPcChunks + ch] = tk;
+    }
+  }
+};
+
+template <typename T>
+struct KPrecondB : KPcBase<T> {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const ProbSet<T> ps) {
+    const Prob<T>& P = ps.p[c.bz()];
+    const int n = c.by(), ch = c.bx();
+    if (n >= P.nb) return;
+    int g0, g1;
+    KPcBase<T>::range(P, ch, g0, g1);
+    double* pt = KPcBase<T>::part(P, n);
+    double tk = 0.0;
+    for (int k = 0; k < kPcChunks; ++k) tk += pt[kPcChunks + k];
+    const double lam = P.eval[n];
+    const cplx<T>* xn = P.v + (size_t)n * P.npw;
+    const cplx<T>* hn = P.hv + (size_t)n * P.npw;
+    cplx<T>* tn = P.t + (size_t)n * P.npw;
+    double t2 = 0.0;
+    for (int g = g0 + c.tid(); g < g1; g += c.nthr()) {
+      const cplx<T> xv = xn[g], hv = hn[g];
+      const double rx = (double)hv.x - lam * xv.x, ry = (double)hv.y - lam * xv.y;
+      const double xx = KPcBase<T>::kin_of_g(P, ps, g) / tk;
+      const double pp = 27.0 + xx * (18.0 + xx * (12.0 + 8.0 * xx));
+      const double K = pp / (pp + 16.0 * xx * xx * xx * xx);
+      const double ux = K * rx, uy = K * ry;
+      t2 += ux * ux + uy * uy;
+      tn[g] = mk<T>((T)ux, (T)uy);
+    }
+    t2 = c.sum(t2, (double*)lds);
+    if (c.tid() == 0) pt[2 * kPcChunks + ch] = t2;
+  }
+};
+
+template <typename T>
+struct KPrecondC : KPcBase<T> {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char*, const ProbSet<T> ps) {
+    const Prob<T>& P = ps.p[c.bz()];
+    const int n = c.by(), ch = c.bx();
+    if (n >= P.nb) return;
+    int g0, g1;
+    KPcBase<T>::range(P, ch, g0, g1);
+    const double* pt = KPcBase<T>::part(P, n);
+    double r2 = 0.0, t2 = 0.0;
+    for (int k = 0; k < kPcChunks; ++k) {
+      r2 += pt[k];
+      t2 += pt[2 * kPcChunks + k];
+    }
+    const double rn = sqrt(r2);
+    const bool act = rn > 1e-10;
+    const double sc = (act && t2 > 0.0) ? 1.0 / sqrt(t2) : 0.0;
+    cplx<T>* tn = P.t + (size_t)n * P.npw;
+    for (int g = g0 + c.tid(); g < g1; g += c.nthr()) {
+      const cplx<T> v = tn[g];
+      tn[g] = mk<T>((T)(sc * v.x), (T)(sc * v.y));
+    }
+    if (ch == 0 && c.tid() == 0) {
+      P.act_out[n] = act ? 1 : 0;
+      P.rnorm[n] = rn;
+    }
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Occupations of one subsystem (single block).
 // ---------------------------------------------------------------------------

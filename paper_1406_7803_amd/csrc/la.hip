@@ -158,18 +158,30 @@ static fde_status rr_batched_t(fde_plan* p, int nblk, const fde_block* blk, doub
 template <typename T>
 static fde_status precond_batched_t(fde_plan* p, int nblk, const fde_block* blk, const void* t_single,
                                     hipStream_t s) {
-  for (int b0 = 0; b0 < nblk; b0 += kMaxBatch) {
+  // the chunked form keeps its partials in the per-problem Rayleigh-Ritz scratch slots
+  const int per = t_single ? kMaxBatch : std::min(kMaxBatch, p->max_batch);
+  for (int b0 = 0; b0 < nblk; b0 += per) {
     ProbSet<T> ps;
-    ps.n = std::min(kMaxBatch, nblk - b0);
+    ps.n = std::min(per, nblk - b0);
     ps.drop_tol = 0;
     for (int i = 0; i < 3; ++i) ps.b[i] = p->b[i];
     int nbmax = 0;
     for (int i = 0; i < ps.n; ++i) {
       ps.p[i] = make_prob<T>(p, blk[b0 + i]);
-      if (t_single) ps.p[i].t = (cplx<T>*)t_single;
+      if (t_single)
+        ps.p[i].t = (cplx<T>*)t_single;
+      else
+        bind_scratch<T>(p, i, ps.p[i]);
       nbmax = std::max(nbmax, ps.p[i].nb);
     }
-    FDE_TRY(launch<KPrecond<T>>(dim3(nbmax, ps.n), kBlock, 17 * sizeof(double), s, ps));
+    if (t_single) {
+      FDE_TRY(launch<KPrecond<T>>(dim3(nbmax, ps.n), kBlock, 17 * sizeof(double), s, ps));
+    } else {
+      const dim3 g(kPcChunks, nbmax, ps.n);
+      FDE_TRY(launch<KPrecondA<T>>(g, kBlock, 17 * sizeof(double), s, ps));
+      FDE_TRY(launch<KPrecondB<T>>(g, kBlock, 17 * sizeof(double), s, ps));
+      FDE_TRY(launch<KPrecondC<T>>(g, kBlock, 0, s, ps));
+    }
   }
   return FDE_OK;
 }

@@ -52,9 +52,12 @@ static int plane_rows(const fde_plan* p, int ik, bool acc, size_t* lds) {
 template <typename T>
 static fde_status kb_project(const cplx<T>* beta, const cplx<T>* psi, int npw, int nproj, int nb, int nchunk,
                              cplx<double>* part, hipStream_t s) {
+  const AhBProb<T> prob{beta, psi, nullptr, nproj, nb, npw, nchunk, kKbChunk, part};
+  if (nproj <= 64 && nb <= 64)
+    return launch<KAhBAll<T>, 512>(dim3(nchunk), 512, KAhBAll<T>::lds_bytes(nproj, nb), s, prob);
   AhBSet<T> set;
   set.n = 1;
-  set.p[0] = AhBProb<T>{beta, psi, nullptr, nproj, nb, npw, nchunk, kKbChunk, part};
+  set.p[0] = prob;
   const int nti = (nproj + KAhB<T>::TI - 1) / KAhB<T>::TI, ntj = (nb + KAhB<T>::TJ - 1) / KAhB<T>::TJ;
   return launch<KAhB<T>>(dim3(nchunk, nti * ntj, 1), kBlock, KAhB<T>::lds_bytes(), s, set);
 }

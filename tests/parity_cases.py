@@ -227,6 +227,41 @@ def check_precondition(be, prec):
     assert rel(host(rnorm)[:3], rn[:3]) < TOL[prec] * 10
 
 
+def check_precondition_batched(be, prec):
+    """Three blocks over two k-points with max_batch 2 (two launches), ragged nb, a zero-residual row;
+    T lands in rows nb..2nb-1 of each block's v."""
+    plan = fde.Plan(SMALL["L"], SMALL["grid"], SMALL["ecut"], SMALL["kf"], prec=prec, max_nb=5, max_nproj=8,
+                    max_batch=2, backend=be)
+    cell = basis.Cell(SMALL["L"], SMALL["grid"])
+    blocks, keep, want = [], [], []
+    for j, (ik, nb) in enumerate([(0, 5), (1, 3), (0, 2)]):
+        sph = basis.sphere(cell, SMALL["ecut"], SMALL["kf"][ik])
+        X = fde_synth.random_complex(60 + j, (nb, sph.npw))
+        HX = fde_synth.random_complex(70 + j, (nb, sph.npw))
+        lam = fde_synth.random_real(80 + j, (nb,))
+        if j == 1:
+            lam[1] = 0.5  # exact in FP32 too, so the residual is zero there as well
+            HX[1] = lam[1] * X[1]
+        T, active, rn = osub.precondition(X, HX, lam, sph.kin)
+        v = plan.zeros_bands(2 * nb, ik)
+        v[:nb] = to_dev(plan, X, "c")
+        hv = plan.zeros_bands(2 * nb, ik)
+        hv[:nb] = to_dev(plan, HX, "c")
+        ev = to_dev(plan, lam, "d")
+        act = torch.full((nb,), 7, dtype=torch.uint8, device=plan.be.device)
+        rnorm = torch.zeros(nb, dtype=torch.float64, device=plan.be.device)
+        blocks.append(plan.make_block(ik, nb, 2 * nb, v, hv, t_active=act, eval=ev, rnorm=rnorm))
+        keep.append((v, hv, ev, act, rnorm))
+        want.append((nb, T, active, rn))
+    plan.precondition_batched(blocks)
+    be.sync()
+    for (v, _, _, act, rnorm), (nb, T, active, rn) in zip(keep, want):
+        assert np.array_equal(host(act).astype(bool), active)
+        assert rel(host(v)[nb:], T) < TOL[prec] * 10
+        on = active
+        assert rel(host(rnorm)[on], rn[on]) < TOL[prec] * 10
+
+
 def check_occupations(be):
     dev = be.device
     eps = np.array([[-0.5, -0.3, -0.1, 0.2, 0.4], [-0.45, -0.28, -0.05, 0.25, 0.5]])

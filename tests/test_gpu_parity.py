@@ -70,6 +70,11 @@ def test_precondition(be, prec):
     pc.check_precondition(be, prec)
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_precondition_batched(be, prec):
+    pc.check_precondition_batched(be, prec)
+
+
 def test_occupations(be):
     pc.check_occupations(be)
 
