@@ -64,6 +64,50 @@ struct DevCtx {
     __syncthreads();
     return red[16];
   }
+  // Wavefront-level helpers: lane and wavefront index, an LDS ordering point among the lanes
+  // of one wavefront, and a fixed-order sum over aligned groups of W lanes that every lane of
+  // the group receives (call with all W lanes of the group active).
+  __device__ __forceinline__ int lane() const { return threadIdx.x & 63; }
+  __device__ __forceinline__ int wave() const { return threadIdx.x >> 6; }
+  __device__ __forceinline__ int nwave() const { return (blockDim.x + 63) >> 6; }
+  __device__ __forceinline__ int wlanes() const { return blockDim.x < 64 ? blockDim.x : 64; }
+  __device__ __forceinline__ void wsync() const {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  template <int CTRL>
+  __device__ __forceinline__ static double dpp(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+  }
+  __device__ __forceinline__ static double rdlane(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+  }
+  // W = 16: butterfly of row rotations (8, 4, 2, 1) inside each row of 16 lanes; a + b = b + a
+  // makes the result bit-identical in every lane of the row. W = 64: the four row sums read
+  // out and added in a fixed order (a wavefront-uniform value).
+  template <int W>
+  __device__ __forceinline__ double gsum(double v) const {
+    static_assert(W == 1 || W == 16 || W == 64, "group of 1, 16 or 64 lanes");
+    if (W == 1) return v;
+    v += dpp<0x128>(v);
+    v += dpp<0x124>(v);
+    v += dpp<0x122>(v);
+    v += dpp<0x121>(v);
+    if (W == 16) return v;
+    return (rdlane(v, 0) + rdlane(v, 16)) + (rdlane(v, 32) + rdlane(v, 48));
+  }
+  // 1 / q from the hardware reciprocal and two Newton steps
+  __device__ __forceinline__ static double rcp(double q) {
+    double r = __builtin_amdgcn_rcp(q);
+    r = fma(r, fma(-q, r, 1.0), r);
+    return fma(r, fma(-q, r, 1.0), r);
+  }
   __device__ double max(double v, double* red) const {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -91,6 +135,14 @@ struct HostCtx {
   void sync() const {}
   double sum(double v, double*) const { return v; }
   double max(double v, double*) const { return v; }
+  int lane() const { return 0; }
+  int wave() const { return 0; }
+  int nwave() const { return 1; }
+  int wlanes() const { return 1; }
+  void wsync() const {}
+  template <int W>
+  double gsum(double v) const { return v; }
+  static double rcp(double q) { return 1.0 / q; }
 };
 
 // --------------------------------------------------------------------------

@@ -9,6 +9,8 @@
 //      rotations accumulated in W^T;
 //   4. ascending order (ties by index), C = L^{-H} W[:, order[:nb]] by a
 //      right-looking back substitution.
+// KRRSolveTri (below) keeps steps 1, 2 and 4 and solves step 3 through a tridiagonal
+// reduction instead of Jacobi sweeps.
 // LDS: packed triangle U (m(m+1)/2 complex: L, then A~), a full work matrix M
 // (m rows, padded stride m+1: the lower triangle of S during the Cholesky,
 // then B/E, then W^T), and small per-pair / per-column arrays. While the
@@ -23,6 +25,8 @@ constexpr int kRRLdsMax = 80;
 constexpr int kWRows = 15;  // row groups of the eigenvector update items
 
 FDE_HD int tri(int i, int j) { return i * (i + 1) / 2 + j; }  // j <= i
+// by-value select (a conditional between two lvalues would give v0 an address)
+FDE_HD cplx<double> pick(bool c, cplx<double> a, cplx<double> b) { return c ? a : b; }
 
 // Hermitian packed access: entries (r, c) with r >= c are stored at tri(r, c).
 FDE_HD cplx<double> hget(const cplx<double>* U, int i, int j) {
@@ -49,6 +53,160 @@ FDE_HD void rr_pair(int r, int k, int mp, int& p, int& q) {
 // (e + 1/2) / n lies at least 1/(2n) from an integer, and the float product is
 // within 2^-22 relative (< 0.008/n absolute) of it, so truncation is exact.
 FDE_HD int qdiv(int e, float inv_n) { return (int)(((float)e + 0.5f) * inv_n); }
+
+// Steps 1-2, shared by the LDS solvers: masks, Cholesky with dropping, A~ into the packed
+// triangle U (Hermitian, lower storage); L parked in the problem's global L and its diagonal in
+// sdiag. Returns false, with C = I, NaN eigenvalues and info = j + 1 written, when band column j
+// has no positive pivot (uniform over the workgroup).
+template <typename T, class Ctx>
+FDE_HD bool rr_front(const Ctx& c, const Prob<T>& a, double drop_tol, cplx<double>* U, cplx<double>* M,
+                     double* sdiag, int* masked) {
+  const int m = a.m, nb = a.nb, tid = c.tid(), nt = c.nthr(), ld = m + 1;
+  const float inv_m = 1.0f / (float)m;
+  if (tid == 0) a.info[0] = 0;
+  for (int j = tid; j < m; j += nt) masked[j] = (a.active && !a.active[j]) ? 1 : 0;
+  c.sync();
+  // ---- lower triangle of S into M (masked columns -> e_j)
+  for (int e = tid; e < m * m; e += nt) {
+    const int i = qdiv(e, inv_m), j = e - i * m;
+    if (j > i) continue;
+    const cplx<double> v = (masked[i] || masked[j]) ? mk<double>(i == j ? 1.0 : 0.0, 0.0) : a.S[e];
+    M[(size_t)i * ld + j] = v;
+    if (i == j) sdiag[i] = v.x;
+  }
+  // ---- right-looking Cholesky into U
+  for (int j = 0; j < m; ++j) {
+    c.sync();
+    const double d = M[(size_t)j * ld + j].x;  // S_jj - sum_k<j |L_jk|^2
+    const double sjj = sdiag[j];
+    if (j >= nb && !(d >= drop_tol * sjj)) {
+      // dependent correction column: L column j = e_j, basis vector j dropped
+      for (int k = tid; k < j; k += nt) U[tri(j, k)] = mk<double>(0, 0);
+      for (int i = j + 1 + tid; i < m; i += nt) U[tri(i, j)] = mk<double>(0, 0);
+      if (tid == 0) {
+        U[tri(j, j)] = mk<double>(1.0, 0.0);
+        masked[j] = 1;
+      }
+      continue;
+    }
+    if (!(d >= drop_tol * sjj) || !(d > 0.0)) {
+      // a band column (or a non-positive pivot): report, C = identity
+      if (tid == 0) a.info[0] = j + 1;
+      for (int e = tid; e < m * nb; e += nt) {
+        const int i = e / nb, n = e - i * nb;
+        const cplx<double> v = mk<double>(i == n ? 1.0 : 0.0, 0.0);
+        a.Cd[e] = v;
+        ((cplx<T>*)a.Ct)[e] = mk<T>((T)v.x, (T)v.y);
+      }
+      for (int n = tid; n < nb; n += nt) a.eval[n] = 0.0 / 0.0;
+      return false;  // uniform: every thread read the same d
+    }
+    const double ljj = sqrt(d), inv_d = 1.0 / d;
+    if (tid == 0) U[tri(j, j)] = mk<double>(ljj, 0.0);
+    for (int i = j + 1 + tid; i < m; i += nt) U[tri(i, j)] = cdiv_real(M[(size_t)i * ld + j], ljj);
+    // trailing update of the lower triangle: M_ik -= M_ij conj(M_kj) / d, j < k <= i
+    const int n = m - 1 - j;
+    const float inv_n = 1.0f / (float)(n > 0 ? n : 1);
+    for (int e = tid; e < n * n; e += nt) {
+      const int ii = qdiv(e, inv_n), kk = e - ii * n;
+      if (kk > ii) continue;
+      const int i = j + 1 + ii, k = j + 1 + kk;
+      const cplx<double> lij = M[(size_t)i * ld + j], lkj = M[(size_t)k * ld + j];
+      cplx<double>& t = M[(size_t)i * ld + k];
+      t.x -= (lij.x * lkj.x + lij.y * lkj.y) * inv_d;
+      t.y -= (lij.y * lkj.x - lij.x * lkj.y) * inv_d;
+    }
+  }
+  c.sync();
+  // ---- A into M (masked / dropped columns -> 1e6 e_j)
+  for (int e = tid; e < m * m; e += nt) {
+    const int i = qdiv(e, inv_m), j = e - i * m;
+    M[(size_t)i * ld + j] = (masked[i] || masked[j]) ? mk<double>(i == j ? kInactiveDiag : 0.0, 0.0) : a.A[e];
+  }
+  // ---- B = L^{-1} A: step i removes row i's contribution from the rows below
+  for (int i = 0; i < m; ++i) {
+    c.sync();
+    const double inv_lii = 1.0 / U[tri(i, i)].x;
+    const int n = m - 1 - i;
+    for (int e = tid; e < n * m; e += nt) {
+      const int rr = qdiv(e, inv_m), col = e - rr * m;
+      const int r = i + 1 + rr;
+      const cplx<double> l = U[tri(r, i)];
+      const cplx<double> bi = M[(size_t)i * ld + col];
+      cplx<double>& t = M[(size_t)r * ld + col];
+      t = t - (inv_lii * l) * bi;
+    }
+  }
+  c.sync();
+  for (int e = tid; e < m * m; e += nt) {
+    const int i = qdiv(e, inv_m), j = e - i * m;
+    M[(size_t)i * ld + j] = cdiv_real(M[(size_t)i * ld + j], U[tri(i, i)].x);
+  }
+  // ---- E = B L^{-H}: step j removes column j's contribution from the columns right of it
+  for (int j = 0; j < m; ++j) {
+    c.sync();
+    const double inv_ljj = 1.0 / U[tri(j, j)].x;
+    const int n = m - 1 - j;
+    const float inv_n = 1.0f / (float)(n > 0 ? n : 1);
+    for (int e = tid; e < n * m; e += nt) {
+      const int r = qdiv(e, inv_n), kk = e - r * n;
+      const int k = j + 1 + kk;
+      const cplx<double> l = conj(U[tri(k, j)]);
+      const cplx<double> ej = M[(size_t)r * ld + j];
+      cplx<double>& t = M[(size_t)r * ld + k];
+      t = t - (inv_ljj * ej) * l;
+    }
+  }
+  c.sync();
+  // ---- park L in global memory (its diagonal also in sdiag); A~ = (E + E^H)/2 into U,
+  //      with E_ij = M_ij / L_jj (the column scaling of the last substitution)
+  for (int e = tid; e < m * (m + 1) / 2; e += nt) a.L[e] = U[e];
+  for (int i = tid; i < m; i += nt) sdiag[i] = U[tri(i, i)].x;
+  c.sync();
+  for (int e = tid; e < m * m; e += nt) {
+    const int i = qdiv(e, inv_m), j = e - i * m;
+    if (j > i) continue;
+    const cplx<double> eij = cdiv_real(M[(size_t)i * ld + j], sdiag[j]);
+    const cplx<double> eji = cdiv_real(M[(size_t)j * ld + i], sdiag[i]);
+    U[tri(i, j)] = i == j ? mk<double>(eij.x, 0.0) : mk<double>(0.5 * (eji.x + eij.x), 0.5 * (eij.y - eji.y));
+  }
+  c.sync();
+  return true;
+}
+
+// Step 4, shared by the LDS solvers: eigenvalues theta[order[n]] and C = L^{-H} W[:, order[:nb]]
+// by a right-looking back substitution in place in the W^T rows of M (stride m + 1); L is
+// restored from the problem's global L into U.
+template <typename T, class Ctx>
+FDE_HD void rr_tail(const Ctx& c, const Prob<T>& a, cplx<double>* U, cplx<double>* M, const double* sdiag,
+                    const int* order) {
+  const int m = a.m, nb = a.nb, tid = c.tid(), nt = c.nthr(), ld = m + 1;
+  c.sync();
+  // ---- restore L; C = L^{-H} W[:, order[:nb]] in place in the W^T rows
+  for (int e = tid; e < m * (m + 1) / 2; e += nt) U[e] = a.L[e];
+  for (int n = tid; n < nb; n += nt) a.eval[n] = a.theta[order[n]];
+  const float inv_nb = 1.0f / (float)nb;
+  for (int i = m - 1; i >= 0; --i) {
+    c.sync();
+    // row i of C is final: C_i = W_i / L_ii; remove it from the rows above
+    const double inv_lii = 1.0 / sdiag[i];
+    for (int e = tid; e < i * nb; e += nt) {
+      const int r = qdiv(e, inv_nb), n = e - r * nb;
+      const int col = order[n];
+      const cplx<double> l = conj(U[tri(i, r)]);
+      const cplx<double> ci = M[(size_t)col * ld + i];
+      cplx<double>& t = M[(size_t)col * ld + r];
+      t = t - (inv_lii * l) * ci;
+    }
+  }
+  c.sync();
+  for (int e = tid; e < m * nb; e += nt) {
+    const int i = qdiv(e, inv_nb), n = e - i * nb;
+    const cplx<double> v = cdiv_real(M[(size_t)order[n] * ld + i], sdiag[i]);
+    a.Cd[e] = v;
+    ((cplx<T>*)a.Ct)[e] = mk<T>((T)v.x, (T)v.y);
+  }
+}
 
 template <typename T>
 struct KRRSolveLds {
@@ -82,114 +240,7 @@ struct KRRSolveLds {
     unsigned short* blk = (unsigned short*)(ptab + 4 * npair);  // block item -> K | Q << 8
     const float inv_m = 1.0f / (float)m;
 
-    if (tid == 0) a.info[0] = 0;
-    for (int j = tid; j < m; j += nt) masked[j] = (a.active && !a.active[j]) ? 1 : 0;
-    c.sync();
-    // ---- lower triangle of S into M (masked columns -> e_j)
-    for (int e = tid; e < m * m; e += nt) {
-      const int i = qdiv(e, inv_m), j = e - i * m;
-      if (j > i) continue;
-      const cplx<double> v = (masked[i] || masked[j]) ? mk<double>(i == j ? 1.0 : 0.0, 0.0) : a.S[e];
-      M[(size_t)i * ld + j] = v;
-      if (i == j) sdiag[i] = v.x;
-    }
-    // ---- right-looking Cholesky into U
-    for (int j = 0; j < m; ++j) {
-      c.sync();
-      const double d = M[(size_t)j * ld + j].x;  // S_jj - sum_k<j |L_jk|^2
-      const double sjj = sdiag[j];
-      if (j >= nb && !(d >= drop_tol * sjj)) {
-        // dependent correction column: L column j = e_j, basis vector j dropped
-        for (int k = tid; k < j; k += nt) U[tri(j, k)] = mk<double>(0, 0);
-        for (int i = j + 1 + tid; i < m; i += nt) U[tri(i, j)] = mk<double>(0, 0);
-        if (tid == 0) {
-          U[tri(j, j)] = mk<double>(1.0, 0.0);
-          masked[j] = 1;
-        }
-        continue;
-      }
-      if (!(d >= drop_tol * sjj) || !(d > 0.0)) {
-        // a band column (or a non-positive pivot): report, C = identity
-        if (tid == 0) a.info[0] = j + 1;
-        for (int e = tid; e < m * nb; e += nt) {
-          const int i = e / nb, n = e - i * nb;
-          const cplx<double> v = mk<double>(i == n ? 1.0 : 0.0, 0.0);
-          a.Cd[e] = v;
-          ((cplx<T>*)a.Ct)[e] = mk<T>((T)v.x, (T)v.y);
-        }
-        for (int n = tid; n < nb; n += nt) a.eval[n] = 0.0 / 0.0;
-        return;  // uniform: every thread read the same d
-      }
-      const double ljj = sqrt(d), inv_d = 1.0 / d;
-      if (tid == 0) U[tri(j, j)] = mk<double>(ljj, 0.0);
-      for (int i = j + 1 + tid; i < m; i += nt) U[tri(i, j)] = cdiv_real(M[(size_t)i * ld + j], ljj);
-      // trailing update of the lower triangle: M_ik -= M_ij conj(M_kj) / d, j < k <= i
-      const int n = m - 1 - j;
-      const float inv_n = 1.0f / (float)(n > 0 ? n : 1);
-      for (int e = tid; e < n * n; e += nt) {
-        const int ii = qdiv(e, inv_n), kk = e - ii * n;
-        if (kk > ii) continue;
-        const int i = j + 1 + ii, k = j + 1 + kk;
-        const cplx<double> lij = M[(size_t)i * ld + j], lkj = M[(size_t)k * ld + j];
-        cplx<double>& t = M[(size_t)i * ld + k];
-        t.x -= (lij.x * lkj.x + lij.y * lkj.y) * inv_d;
-        t.y -= (lij.y * lkj.x - lij.x * lkj.y) * inv_d;
-      }
-    }
-    c.sync();
-    // ---- A into M (masked / dropped columns -> 1e6 e_j)
-    for (int e = tid; e < m * m; e += nt) {
-      const int i = qdiv(e, inv_m), j = e - i * m;
-      M[(size_t)i * ld + j] = (masked[i] || masked[j]) ? mk<double>(i == j ? kInactiveDiag : 0.0, 0.0) : a.A[e];
-    }
-    // ---- B = L^{-1} A: step i removes row i's contribution from the rows below
-    for (int i = 0; i < m; ++i) {
-      c.sync();
-      const double inv_lii = 1.0 / U[tri(i, i)].x;
-      const int n = m - 1 - i;
-      for (int e = tid; e < n * m; e += nt) {
-        const int rr = qdiv(e, inv_m), col = e - rr * m;
-        const int r = i + 1 + rr;
-        const cplx<double> l = U[tri(r, i)];
-        const cplx<double> bi = M[(size_t)i * ld + col];
-        cplx<double>& t = M[(size_t)r * ld + col];
-        t = t - (inv_lii * l) * bi;
-      }
-    }
-    c.sync();
-    for (int e = tid; e < m * m; e += nt) {
-      const int i = qdiv(e, inv_m), j = e - i * m;
-      M[(size_t)i * ld + j] = cdiv_real(M[(size_t)i * ld + j], U[tri(i, i)].x);
-    }
-    // ---- E = B L^{-H}: step j removes column j's contribution from the columns right of it
-    for (int j = 0; j < m; ++j) {
-      c.sync();
-      const double inv_ljj = 1.0 / U[tri(j, j)].x;
-      const int n = m - 1 - j;
-      const float inv_n = 1.0f / (float)(n > 0 ? n : 1);
-      for (int e = tid; e < n * m; e += nt) {
-        const int r = qdiv(e, inv_n), kk = e - r * n;
-        const int k = j + 1 + kk;
-        const cplx<double> l = conj(U[tri(k, j)]);
-        const cplx<double> ej = M[(size_t)r * ld + j];
-        cplx<double>& t = M[(size_t)r * ld + k];
-        t = t - (inv_ljj * ej) * l;
-      }
-    }
-    c.sync();
-    // ---- park L in global memory (its diagonal also in sdiag); A~ = (E + E^H)/2 into U,
-    //      with E_ij = M_ij / L_jj (the column scaling of the last substitution)
-    for (int e = tid; e < m * (m + 1) / 2; e += nt) a.L[e] = U[e];
-    for (int i = tid; i < m; i += nt) sdiag[i] = U[tri(i, i)].x;
-    c.sync();
-    for (int e = tid; e < m * m; e += nt) {
-      const int i = qdiv(e, inv_m), j = e - i * m;
-      if (j > i) continue;
-      const cplx<double> eij = cdiv_real(M[(size_t)i * ld + j], sdiag[j]);
-      const cplx<double> eji = cdiv_real(M[(size_t)j * ld + i], sdiag[i]);
-      U[tri(i, j)] = i == j ? mk<double>(eij.x, 0.0) : mk<double>(0.5 * (eji.x + eij.x), 0.5 * (eij.y - eji.y));
-    }
-    c.sync();
+    if (!rr_front<T>(c, a, drop_tol, U, M, sdiag, masked)) return;
     // ---- W^T = I in M; block-item table
     for (int e = tid; e < m * m; e += nt) {
       const int i = qdiv(e, inv_m), j = e - i * m;
@@ -361,30 +412,668 @@ struct KRRSolveLds {
       }
       order[rank] = i;
     }
-    // ---- restore L; C = L^{-H} W[:, order[:nb]] in place in the W^T rows
-    for (int e = tid; e < m * (m + 1) / 2; e += nt) U[e] = a.L[e];
-    for (int n = tid; n < nb; n += nt) a.eval[n] = a.theta[order[n]];
-    const float inv_nb = 1.0f / (float)nb;
-    for (int i = m - 1; i >= 0; --i) {
+    rr_tail<T>(c, a, U, M, sdiag, order);
+  }
+};
+
+// Rayleigh-Ritz solve of one band block in LDS with the eigenproblem of A~ reduced to a real
+// tridiagonal (used when the block fits; steps 1, 2 and 4 as in KRRSolveLds):
+//   3a. the active part of A~ (masked indices dropped) compacted into U; Householder reduction
+//       with reflectors H_k = I - beta_k v_k v_k^H kept in place below the subdiagonal, two
+//       barriers per column;
+//   3b. the complex subdiagonal alpha made real by a diagonal phase D;
+//   3c. the nw lowest eigenvalues by multisection on Sturm counts (nt / nw points per
+//       eigenvalue and step);
+//   3d. their eigenvectors by inverse iteration (partial-pivoting LU of T - lambda I, three
+//       solves from a fixed pseudo-random start), one wavefront per cluster of close
+//       eigenvalues, each solve orthogonalised against the cluster's earlier vectors;
+//   3e. back-transformation W = Q D Y by groups of 16 lanes, one eigenvector per group, and
+//       the rows scattered back to the physical indices.
+// Inside M once A~ is reduced: region R1 (compaction buffer, then Sturm counts, then the
+// per-wavefront LU factors, then the W^T rows), the tridiagonal eigenvectors Y [nw][ma], and the
+// per-column arrays.
+template <typename T>
+struct KRRSolveTri {
+  static constexpr int kThreads = 1024;
+  static constexpr int kWaves = kThreads / 64;
+  static constexpr int kGroup = 16;
+  static constexpr int kInvIt = 3;
+  static constexpr int kMsPoints = 7;  // multisection points per eigenvalue and step
+
+  FDE_HD static size_t lu_stride(int m) { return ((size_t)m * (4 * sizeof(double) + 1) + 15) & ~(size_t)15; }
+  FDE_HD static size_t r1_bytes(int m, int nb) {
+    size_t r = (size_t)nb * (m + 1) * sizeof(cplx<double>);
+    const size_t lu = (size_t)kWaves * lu_stride(m), cnt = (size_t)kThreads * sizeof(int);
+    const size_t pk = (size_t)m * (m + 1) / 2 * sizeof(cplx<double>);
+    r = r > lu ? r : lu;
+    r = r > cnt ? r : cnt;
+    r = r > pk ? r : pk;
+    return (r + 255) & ~(size_t)255;
+  }
+  FDE_HD static size_t y_bytes(int m, int nb) { return ((size_t)m * nb * sizeof(double) + 15) & ~(size_t)15; }
+  FDE_HD static size_t small_bytes(int m) { return (size_t)m * (17 * sizeof(double) + 2 * sizeof(int)) + 64; }
+  // column-packed offset of the reflector vector v_k (ma - k - 1 entries) in U
+  FDE_HD static int voff(int k, int ma) { return k * (ma - 1) - k * (k - 1) / 2; }
+  FDE_HD static size_t mspan(int m, int nb) {
+    const size_t mb = (size_t)m * (m + 1) * sizeof(cplx<double>);
+    const size_t need = r1_bytes(m, nb) + y_bytes(m, nb) + small_bytes(m);
+    return ((mb > need ? mb : need) + 15) & ~(size_t)15;
+  }
+  FDE_HD static size_t lds_bytes(int m, int nb) {
+    return sizeof(cplx<double>) * ((size_t)m * (m + 1) / 2) + mspan(m, nb) + sizeof(double) * (32 + (size_t)m) +
+           sizeof(int) * 2 * (size_t)m + 64;
+  }
+
+  // fixed pseudo-random start vector entry in [-1, 1)
+  FDE_HD static double start_value(int i, int j) {
+    unsigned h = (unsigned)i * 73856093u ^ (unsigned)j * 19349663u ^ 0x9e3779b9u;
+    h ^= h >> 16;
+    h *= 0x7feb352du;
+    h ^= h >> 15;
+    h *= 0x846ca68bu;
+    h ^= h >> 16;
+    return (double)(h >> 8) * (2.0 / 16777216.0) - 1.0;
+  }
+
+  // LU with partial pivoting of the n x n tridiagonal T - lam I (diagonal dg, off-diagonal ea):
+  // reciprocal pivots, the two superdiagonals of U, the multipliers and the interchange flags.
+  // Pivots below tiny in magnitude are replaced by +-tiny. The running row stays in registers.
+  template <class Ctx>
+  FDE_HD static void lu_factor(int n, const double* dg, const double* ea, double lam, double tiny, double* lu,
+                               unsigned char* piv) {
+    double *ru0 = lu, *u1 = lu + n, *u2 = lu + 2 * n, *ml = lu + 3 * n;
+    double cd = dg[0] - lam, cs = n > 1 ? ea[0] : 0.0;  // current row: (i, i), (i, i + 1)
+#pragma unroll 4
+    for (int i = 0; i < n - 1; ++i) {
+      const double sub = ea[i], dn = dg[i + 1] - lam, sn = i + 2 < n ? ea[i + 1] : 0.0;
+      if (fabs(cd) >= fabs(sub)) {
+        const double pv = fabs(cd) < tiny ? (cd < 0.0 ? -tiny : tiny) : cd;
+        const double rp = Ctx::rcp(pv);
+        const double l = sub * rp;
+        ru0[i] = rp;
+        u1[i] = cs;
+        u2[i] = 0.0;
+        ml[i] = l;
+        piv[i] = 0;
+        cd = dn - l * cs;
+        cs = sn;
+      } else {
+        const double rp = Ctx::rcp(sub);
+        const double l = cd * rp;
+        ru0[i] = rp;
+        u1[i] = dn;
+        u2[i] = sn;
+        ml[i] = l;
+        piv[i] = 1;
+        cd = cs - l * dn;
+        cs = -l * sn;
+      }
+    }
+    ru0[n - 1] = Ctx::rcp(fabs(cd) < tiny ? (cd < 0.0 ? -tiny : tiny) : cd);
+  }
+
+  // b <- (T - lam I)^{-1} b with the factors of lu_factor (running values in registers)
+  FDE_HD static void lu_solve(int n, const double* lu, const unsigned char* piv, double* b) {
+    const double *ru0 = lu, *u1 = lu + n, *u2 = lu + 2 * n, *ml = lu + 3 * n;
+    double cur = b[0];
+#pragma unroll 4
+    for (int i = 0; i < n - 1; ++i) {
+      const double nx = b[i + 1];
+      if (piv[i]) {
+        b[i] = nx;
+        cur = cur - ml[i] * nx;
+      } else {
+        b[i] = cur;
+        cur = nx - ml[i] * cur;
+      }
+    }
+    double x1 = cur * ru0[n - 1], x2 = 0.0;  // x_{i+1}, x_{i+2}
+    b[n - 1] = x1;
+#pragma unroll 4
+    for (int i = n - 2; i >= 0; --i) {
+      const double x = (b[i] - u1[i] * x1 - u2[i] * x2) * ru0[i];
+      b[i] = x;
+      x2 = x1;
+      x1 = x;
+    }
+  }
+
+  // Householder reduction in LDS (host twin of house_regs): the active part compacted into U
+  // (logical index i <-> physical act[i]), reduced in place, then the reflector vectors moved to
+  // their column-packed slots voff(k) and the diagonal into dg.
+  template <class Ctx>
+  FDE_HD static void house_lds(const Ctx& c, cplx<double>* U, char* r1, int m, int ma, const int* act, double* dg,
+                               double* beta, double* ar, double* ai, double* pbx, double* pby) {
+    const int tid = c.tid(), nt = c.nthr();
+    const int lane = c.lane(), wl = c.wlanes(), wv = c.wave(), nwv = c.nwave();
+    if (ma < m) {
+      cplx<double>* P = (cplx<double>*)r1;
+      for (int e = tid; e < ma * (ma + 1) / 2; e += nt) {
+        int i = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+        if ((i + 1) * (i + 2) / 2 <= e) ++i;
+        if (i * (i + 1) / 2 > e) --i;
+        P[e] = U[tri(act[i], act[e - i * (i + 1) / 2])];
+      }
       c.sync();
-      // row i of C is final: C_i = W_i / L_ii; remove it from the rows above
-      const double inv_lii = 1.0 / sdiag[i];
-      for (int e = tid; e < i * nb; e += nt) {
-        const int r = qdiv(e, inv_nb), n = e - r * nb;
-        const int col = order[n];
-        const cplx<double> l = conj(U[tri(i, r)]);
-        const cplx<double> ci = M[(size_t)col * ld + i];
-        cplx<double>& t = M[(size_t)col * ld + r];
-        t = t - (inv_lii * l) * ci;
+      for (int e = tid; e < ma * (ma + 1) / 2; e += nt) U[e] = P[e];
+      c.sync();
+    }
+    // column k: x = A~(k+1.., k); H_k x = alpha e_1
+    for (int k = 0; k + 1 < ma; ++k) {
+      const int n1 = ma - k - 1;
+      const cplx<double>* xc = U + tri(k + 1, k);  // x_r at xc[tri(k + 1 + r, k) - tri(k + 1, k)]
+      double s2 = 0.0;
+      for (int r = lane; r < n1; r += wl) s2 += norm2(U[tri(k + 1 + r, k)]);
+      s2 = c.template gsum<64>(s2);
+      const cplx<double> x0 = xc[0];
+      double bt = 0.0;
+      cplx<double> alpha = x0, v0 = x0;
+      if (n1 > 1 && s2 > norm2(x0)) {
+        const double ax0 = sqrt(norm2(x0)), sg = sqrt(s2);
+        const cplx<double> ph = ax0 > 0.0 ? mk<double>(x0.x / ax0, x0.y / ax0) : mk<double>(1.0, 0.0);
+        alpha = mk<double>(-ph.x * sg, -ph.y * sg);
+        v0 = mk<double>(x0.x + ph.x * sg, x0.y + ph.y * sg);
+        bt = 1.0 / (sg * (sg + ax0));
+      }
+      if (tid == 0) {
+        beta[k] = bt;
+        ar[k] = alpha.x;
+        ai[k] = alpha.y;
+      }
+      if (bt != 0.0) {  // uniform: every wavefront summed in the same order
+        // p = beta A' v over the trailing block, one row per wavefront at a time
+        for (int r = wv; r < n1; r += nwv) {
+          const int ir = k + 1 + r;
+          double sx = 0.0, sy = 0.0;
+          for (int j = lane; j < n1; j += wl) {
+            const int ij = k + 1 + j;
+            const cplx<double> vj = pick(j == 0, v0, U[tri(ij, k)]);
+            const cplx<double> arj = ir >= ij ? U[tri(ir, ij)] : conj(U[tri(ij, ir)]);
+            sx += arj.x * vj.x - arj.y * vj.y;
+            sy += arj.x * vj.y + arj.y * vj.x;
+          }
+          sx = c.template gsum<64>(sx);
+          sy = c.template gsum<64>(sy);
+          if (lane == 0) {
+            pbx[r] = bt * sx;
+            pby[r] = bt * sy;
+          }
+        }
+        c.sync();
+        // K = beta/2 v^H p (real), then A' -= v w^H + w v^H with w = p - K v, lower triangle
+        double kk = 0.0;
+        for (int r = lane; r < n1; r += wl) {
+          const cplx<double> vr = pick(r == 0, v0, U[tri(k + 1 + r, k)]);
+          kk += vr.x * pbx[r] + vr.y * pby[r];
+        }
+        kk = 0.5 * bt * c.template gsum<64>(kk);
+        const int ntri = n1 * (n1 + 1) / 2;
+        for (int e = tid; e < ntri; e += nt) {
+          int r = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+          if ((r + 1) * (r + 2) / 2 <= e) ++r;
+          if (r * (r + 1) / 2 > e) --r;
+          const int j = e - r * (r + 1) / 2;
+          const cplx<double> vr = pick(r == 0, v0, U[tri(k + 1 + r, k)]);
+          const cplx<double> vj = pick(j == 0, v0, U[tri(k + 1 + j, k)]);
+          const double wrx = pbx[r] - kk * vr.x, wry = pby[r] - kk * vr.y;
+          const double wjx = pbx[j] - kk * vj.x, wjy = pby[j] - kk * vj.y;
+          cplx<double>& t = U[tri(k + 1 + r, k + 1 + j)];
+          t.x -= (vr.x * wjx + vr.y * wjy) + (wrx * vj.x + wry * vj.y);
+          t.y -= (vr.y * wjx - vr.x * wjy) + (wry * vj.x - wrx * vj.y);
+        }
+        if (tid == 0) U[tri(k + 1, k)] = v0;
+      }
+      c.sync();
+    }
+    cplx<double>* P = (cplx<double>*)r1;
+    for (int k = 0; k + 1 < ma; ++k)
+      for (int r = 0; r < ma - k - 1; ++r) P[voff(k, ma) + r] = U[tri(k + 1 + r, k)];
+    for (int k = 0; k < ma; ++k) dg[k] = U[tri(k, k)].x;
+    for (int e = 0; e < ma * (ma - 1) / 2; ++e) U[e] = P[e];
+    c.sync();
+  }
+
+#if defined(__HIP_DEVICE_COMPILE__)
+  // Householder reduction with the active block in registers (1024 threads): row i on lane
+  // i % 64 (slot i / 64), column j on wavefront j / kCPW (slot j % kCPW). Step k: every
+  // wavefront forms partial sums of A' v over its columns (LDS, [wavefront][row]); the rows'
+  // sums in a fixed order give p = beta A' v and the wavefront sums of Re(v^H p) give K; every
+  // wavefront applies A' -= v w^H + w v^H to its columns; the owner of column k + 1 then forms
+  // the next reflector (v through LDS, double-buffered). Three barriers per column.
+  static constexpr int kRT = (kRRLdsMax + 63) / 64;                // row slots per lane
+  static constexpr int kCPW = (kRRLdsMax + kWaves - 1) / kWaves;    // columns per wavefront
+  __device__ static void house_regs(const DevCtx& c, cplx<double>* U, char* r1, int m, int ma, const int* act,
+                                    double* dg, double* beta, double* ar, double* ai, cplx<double>* xb,
+                                    double* pbx, double* pby) {
+    const int tid = c.tid(), lane = c.lane(), wv = c.wave();
+    cplx<double>* part = (cplx<double>*)r1;  // [kWaves][m]
+    double* kpart = (double*)(part + (size_t)kWaves * m);  // [2]
+    cplx<double> A[kRT][kCPW];
+#pragma unroll
+    for (int t = 0; t < kRT; ++t)
+#pragma unroll
+      for (int s = 0; s < kCPW; ++s) {
+        const int i = lane + 64 * t, j = kCPW * wv + s;
+        A[t][s] = (i < ma && j < ma) ? hget(U, act[i], act[j]) : mk<double>(0.0, 0.0);
+      }
+    c.sync();  // U is free from here on: it receives the reflector vectors
+    // the owner of column k: diagonal entry, reflector of the column below it into xv and U
+    auto gen = [&](int k, cplx<double>* xv) {
+#pragma unroll
+      for (int s = 0; s < kCPW; ++s) {
+        if (kCPW * wv + s != k) continue;  // uniform
+        double loc = 0.0;
+#pragma unroll
+        for (int t = 0; t < kRT; ++t) {
+          const int i = lane + 64 * t;
+          if (i == k) dg[k] = A[t][s].x;
+          if (i > k && i < ma) loc += norm2(A[t][s]);
+        }
+        if (k + 1 >= ma) return;
+        const double s2 = c.gsum<64>(loc);
+        cplx<double> x0 = mk<double>(0.0, 0.0);
+#pragma unroll
+        for (int t = 0; t < kRT; ++t)
+          if ((k + 1) / 64 == t) x0 = mk<double>(DevCtx::rdlane(A[t][s].x, (k + 1) & 63),
+                                                 DevCtx::rdlane(A[t][s].y, (k + 1) & 63));
+        double bt = 0.0;
+        cplx<double> alpha = x0, v0 = x0;
+        if (k + 2 < ma && s2 > norm2(x0)) {
+          const double ax0 = sqrt(norm2(x0)), sg = sqrt(s2);
+          const cplx<double> ph = ax0 > 0.0 ? mk<double>(x0.x / ax0, x0.y / ax0) : mk<double>(1.0, 0.0);
+          alpha = mk<double>(-ph.x * sg, -ph.y * sg);
+          v0 = mk<double>(x0.x + ph.x * sg, x0.y + ph.y * sg);
+          bt = 1.0 / (sg * (sg + ax0));
+        }
+        const int vo = voff(k, ma) - (k + 1);
+#pragma unroll
+        for (int t = 0; t < kRT; ++t) {
+          const int i = lane + 64 * t;
+          if (i > k && i < ma) {
+            const cplx<double> v = pick(i == k + 1, v0, A[t][s]);
+            xv[i] = v;
+            U[vo + i] = v;
+          }
+        }
+        if (lane == 0) {
+          beta[k] = bt;
+          ar[k] = alpha.x;
+          ai[k] = alpha.y;
+        }
+      }
+    };
+    gen(0, xb);
+    c.sync();
+    for (int k = 0; k + 1 < ma; ++k) {
+      const cplx<double>* xk = xb + (k & 1) * m;
+      cplx<double>* xn = xb + ((k + 1) & 1) * m;
+      const double bt = beta[k];
+      if (bt != 0.0) {  // uniform
+        // partial sums of A' v over this wavefront's columns
+        cplx<double> vs[kCPW];
+#pragma unroll
+        for (int s = 0; s < kCPW; ++s) {
+          const int j = kCPW * wv + s;
+          vs[s] = (j > k && j < ma) ? xk[j] : mk<double>(0.0, 0.0);
+        }
+#pragma unroll
+        for (int t = 0; t < kRT; ++t) {
+          const int i = lane + 64 * t;
+          double sx = 0.0, sy = 0.0;
+#pragma unroll
+          for (int s = 0; s < kCPW; ++s) {
+            sx += A[t][s].x * vs[s].x - A[t][s].y * vs[s].y;
+            sy += A[t][s].x * vs[s].y + A[t][s].y * vs[s].x;
+          }
+          if (i > k && i < ma) part[(size_t)wv * m + i] = mk<double>(sx, sy);
+        }
+        c.sync();
+        // p_i = beta sum_w part[w][i]; K partials Re(conj(v_i) p_i) summed per wavefront
+        if (wv < kRT) {  // threads tid < 64 kRT cover every row
+          double kv = 0.0;
+          const int i = tid;
+          if (i > k && i < ma) {
+            double sx = 0.0, sy = 0.0;
+            for (int w = 0; w < kWaves; ++w) {
+              const cplx<double> q = part[(size_t)w * m + i];
+              sx += q.x;
+              sy += q.y;
+            }
+            sx *= bt;
+            sy *= bt;
+            pbx[i] = sx;
+            pby[i] = sy;
+            const cplx<double> vi = xk[i];
+            kv = vi.x * sx + vi.y * sy;
+          }
+          kv = c.gsum<64>(kv);
+          if (lane == 0) kpart[wv] = kv;
+        }
+        c.sync();
+        double kk = 0.0;
+        for (int w = 0; w < kRT; ++w) kk += kpart[w];
+        kk *= 0.5 * bt;
+        cplx<double> ws[kCPW];
+#pragma unroll
+        for (int s = 0; s < kCPW; ++s) {
+          const int j = kCPW * wv + s;
+          ws[s] = (j > k && j < ma) ? mk<double>(pbx[j] - kk * vs[s].x, pby[j] - kk * vs[s].y) : mk<double>(0.0, 0.0);
+        }
+#pragma unroll
+        for (int t = 0; t < kRT; ++t) {
+          const int i = lane + 64 * t;
+          if (i > k && i < ma) {
+            const cplx<double> vi = xk[i];
+            const double wix = pbx[i] - kk * vi.x, wiy = pby[i] - kk * vi.y;
+#pragma unroll
+            for (int s = 0; s < kCPW; ++s) {
+              // A_ij -= v_i conj(w_j) + w_i conj(v_j); columns outside the block have v = w = 0
+              A[t][s].x -= (vi.x * ws[s].x + vi.y * ws[s].y) + (wix * vs[s].x + wiy * vs[s].y);
+              A[t][s].y -= (vi.y * ws[s].x - vi.x * ws[s].y) + (wiy * vs[s].x - wix * vs[s].y);
+            }
+          }
+        }
+      }
+      gen(k + 1, xn);
+      c.sync();
+    }
+  }
+#endif
+
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const ProbSet<T> ps) {
+    const Prob<T>& a = ps.p[c.bx()];
+    const int m = a.m, nb = a.nb, ld = m + 1;
+    const int tid = c.tid(), nt = c.nthr();
+    const int lane = c.lane(), wl = c.wlanes(), wv = c.wave(), nwv = c.nwave();
+    cplx<double>* U = (cplx<double>*)lds;
+    cplx<double>* M = U + (size_t)m * (m + 1) / 2;
+    double* red = (double*)((char*)M + mspan(m, nb));
+    double* sdiag = red + 32;
+    int* masked = (int*)(sdiag + m);
+    int* order = masked + m;
+    char* r1 = (char*)M;
+    double* Y = (double*)(r1 + r1_bytes(m, nb));
+    double* dg = (double*)((char*)Y + y_bytes(m, nb));
+    double *e2 = dg + m, *ea = e2 + m, *beta = ea + m, *ar = beta + m, *ai = ar + m, *dre = ai + m, *dim = dre + m;
+    double *lam = dim + m, *lo = lam + m, *hi = lo + m, *pbx = hi + m, *pby = pbx + m;
+    cplx<double>* xb = (cplx<double>*)(pby + m);  // [2][m]: the current column, double-buffered
+    int* act = (int*)(xb + 2 * m);
+    int* cls = act + m;  // cluster starts (m + 1 entries), then the active count and the cluster count
+    int* cnt = (int*)r1;
+
+    if (!rr_front<T>(c, a, ps.drop_tol, U, M, sdiag, masked)) return;
+    if (tid == 0) {
+      int k = 0;
+      for (int j = 0; j < m; ++j)
+        if (!masked[j]) act[k++] = j;
+      cls[m + 1] = k;
+    }
+    c.sync();
+    const int ma = cls[m + 1];
+    const int nw = nb < ma ? nb : ma;
+    // ---- 3a. Householder reduction of the active part
+#if defined(__HIP_DEVICE_COMPILE__)
+    house_regs(c, U, r1, m, ma, act, dg, beta, ar, ai, xb, pbx, pby);
+#else
+    house_lds(c, U, r1, m, ma, act, dg, beta, ar, ai, pbx, pby);
+#endif
+    // ---- 3b. real tridiagonal (dg, ea) and the phases D
+    for (int k = tid; k + 1 < ma; k += nt) {
+      e2[k] = ar[k] * ar[k] + ai[k] * ai[k];
+      ea[k] = sqrt(e2[k]);
+    }
+    if (tid == 0 && ma > 0) {
+      double px = 1.0, py = 0.0;
+      dre[0] = 1.0;
+      dim[0] = 0.0;
+      for (int k = 0; k + 1 < ma; ++k) {
+        const double ab = sqrt(ar[k] * ar[k] + ai[k] * ai[k]);
+        if (ab > 0.0) {
+          const double ux = ar[k] / ab, uy = ai[k] / ab;
+          const double qx = px * ux - py * uy, qy = px * uy + py * ux;
+          px = qx;
+          py = qy;
+        }
+        dre[k + 1] = px;
+        dim[k + 1] = py;
       }
     }
     c.sync();
-    for (int e = tid; e < m * nb; e += nt) {
-      const int i = qdiv(e, inv_nb), n = e - i * nb;
-      const cplx<double> v = cdiv_real(M[(size_t)order[n] * ld + i], sdiag[i]);
-      a.Cd[e] = v;
-      ((cplx<T>*)a.Ct)[e] = mk<T>((T)v.x, (T)v.y);
+
+    if (nw > 0) {
+      // ---- 3c. multisection for the nw lowest eigenvalues
+      double glo = 1e300, ghi = -1e300, emax2 = 0.0;
+      for (int i = 0; i < ma; ++i) {
+        const double rad = (i > 0 ? ea[i - 1] : 0.0) + (i + 1 < ma ? ea[i] : 0.0);
+        glo = fmin(glo, dg[i] - rad);
+        ghi = fmax(ghi, dg[i] + rad);
+        if (i + 1 < ma) emax2 = fmax(emax2, e2[i]);
+      }
+      const double eps = 2.220446049250313e-16;
+      const double tnorm = fmax(fmax(fabs(glo), fabs(ghi)), 1e-300);
+      const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
+      glo -= 4.0 * eps * tnorm + 2.0 * pivmin;
+      ghi += 4.0 * eps * tnorm + 2.0 * pivmin;
+      const int G = nt >= nw ? (nt / nw < kMsPoints ? nt / nw : kMsPoints) : 1;
+      int niter = 1;
+      for (double w = ghi - glo; w > 2.0 * eps * tnorm; w /= (double)(G + 1)) ++niter;
+      auto sturm = [&](double x) {  // number of eigenvalues below x
+        double q = dg[0] - x;
+        if (fabs(q) < pivmin) q = -pivmin;
+        int n = q < 0.0 ? 1 : 0;
+#pragma unroll 8
+        for (int i = 1; i < ma; ++i) {
+          q = (dg[i] - x) - e2[i - 1] * Ctx::rcp(q);
+          if (fabs(q) < pivmin) q = -pivmin;
+          n += q < 0.0 ? 1 : 0;
+        }
+        return n;
+      };
+      for (int j = tid; j < nw; j += nt) {
+        lo[j] = glo;
+        hi[j] = ghi;
+      }
+      c.sync();
+      for (int it = 0; it < niter; ++it) {
+        for (int vt = tid; vt < nw * G; vt += nt) {
+          const int j = vt / G, g = vt - j * G;
+          const double l = lo[j], step = (hi[j] - l) / (double)(G + 1);
+          cnt[vt] = sturm(l + (double)(g + 1) * step);
+        }
+        c.sync();
+        for (int j = tid; j < nw; j += nt) {
+          const double l0 = lo[j], step = (hi[j] - l0) / (double)(G + 1);
+          double l = l0, h = hi[j];
+          for (int g = 0; g < G; ++g) {
+            const double x = l0 + (double)(g + 1) * step;
+            if (cnt[j * G + g] <= j) {
+              l = x;
+            } else {
+              h = x;
+              break;
+            }
+          }
+          lo[j] = l;
+          hi[j] = h;
+        }
+        c.sync();
+      }
+      for (int j = tid; j < nw; j += nt) lam[j] = 0.5 * (lo[j] + hi[j]);
+      c.sync();
+      // clusters: neighbours closer than 1e-3 |T| share one wavefront
+      const double ortol = 1e-3 * tnorm, pertol = 10.0 * eps * tnorm;
+      if (tid == 0) {
+        int ncl = 0;
+        for (int j = 0; j < nw; ++j)
+          if (j == 0 || lam[j] - lam[j - 1] > ortol) cls[ncl++] = j;
+        cls[ncl] = nw;
+        cls[m + 2] = ncl;
+      }
+      c.sync();
+      // ---- 3d. eigenvectors. An eigenvalue farther than ortol from its neighbours: one thread,
+      //      twisted factorisation N_r D N_r^T of T - lambda I (forward pivots D+, backward D-,
+      //      twist r at the smallest |gamma_r|), x_r = 1 and the two recurrences outward.
+      //      Clusters, and any vector that came out non-finite: inverse iteration below.
+      auto single = [&](int j) {
+        return (j == 0 || lam[j] - lam[j - 1] > ortol) && (j + 1 == nw || lam[j + 1] - lam[j] > ortol);
+      };
+      for (int j = tid; j < nw; j += nt) {
+        lo[j] = 1.0;  // 1: needs inverse iteration
+        if (!single(j)) continue;
+        double* rp = (double*)r1 + (size_t)j * 2 * ma;  // 1 / D+_i
+        double* rm = rp + ma;                            // 1 / D-_i
+        const double lj = lam[j];
+        double q = dg[0] - lj;
+        if (fabs(q) < pivmin) q = -pivmin;
+        rp[0] = Ctx::rcp(q);
+        for (int i = 1; i < ma; ++i) {
+          q = (dg[i] - lj) - e2[i - 1] * rp[i - 1];
+          if (fabs(q) < pivmin) q = -pivmin;
+          rp[i] = Ctx::rcp(q);
+        }
+        double best = fabs(q);  // gamma_{ma-1} = D+_{ma-1}
+        int r = ma - 1;
+        q = dg[ma - 1] - lj;
+        if (fabs(q) < pivmin) q = -pivmin;
+        rm[ma - 1] = Ctx::rcp(q);
+        for (int i = ma - 2; i >= 0; --i) {
+          const double dpi = (dg[i] - lj) - (i > 0 ? e2[i - 1] * rp[i - 1] : 0.0);  // D+_i
+          const double gam = dpi - e2[i] * rm[i + 1];
+          if (fabs(gam) < best) {
+            best = fabs(gam);
+            r = i;
+          }
+          q = (dg[i] - lj) - e2[i] * rm[i + 1];
+          if (fabs(q) < pivmin) q = -pivmin;
+          rm[i] = Ctx::rcp(q);
+        }
+        double* y = Y + (size_t)j * ma;
+        double x = 1.0, nr = 1.0;
+        y[r] = 1.0;
+        for (int i = r - 1; i >= 0; --i) {
+          x = -(ea[i] * rp[i]) * x;
+          y[i] = x;
+          nr += x * x;
+        }
+        x = 1.0;
+        for (int i = r + 1; i < ma; ++i) {
+          x = -(ea[i - 1] * rm[i]) * x;
+          y[i] = x;
+          nr += x * x;
+        }
+        if (nr > 0.0 && nr < 1e300) {
+          const double sc = 1.0 / sqrt(nr);
+          for (int i = 0; i < ma; ++i) y[i] *= sc;
+          lo[j] = 0.0;
+        }
+      }
+      c.sync();
+      // inverse iteration, one cluster (or failed single) per wavefront
+      const int ncl = cls[m + 2];
+      double* lu = (double*)(r1 + (size_t)wv * lu_stride(m));
+      unsigned char* piv = (unsigned char*)(lu + 4 * ma);
+      for (int ci = wv; ci < ncl; ci += nwv) {
+        const int j0 = cls[ci], j1 = cls[ci + 1];
+        if (j1 - j0 == 1 && lo[j0] == 0.0) continue;
+        double lprev = 0.0;
+        for (int j = j0; j < j1; ++j) {
+          double lj = lam[j];
+          if (j > j0 && lj - lprev < pertol) lj = lprev + pertol;
+          lprev = lj;
+          double* y = Y + (size_t)j * ma;
+          for (int i = lane; i < ma; i += wl) y[i] = start_value(i, j);
+          if (lane == 0) lu_factor<Ctx>(ma, dg, ea, lj, eps * tnorm, lu, piv);
+          c.wsync();
+          for (int it = 0; it < kInvIt; ++it) {
+            if (lane == 0) lu_solve(ma, lu, piv, y);
+            c.wsync();
+            for (int q = j0; q < j; ++q) {
+              const double* yq = Y + (size_t)q * ma;
+              double d = 0.0;
+              for (int i = lane; i < ma; i += wl) d += yq[i] * y[i];
+              d = c.template gsum<64>(d);
+              for (int i = lane; i < ma; i += wl) y[i] -= d * yq[i];
+            }
+            double nr = 0.0;
+            for (int i = lane; i < ma; i += wl) nr += y[i] * y[i];
+            nr = c.template gsum<64>(nr);
+            if (nr > 0.0) {
+              const double sc = 1.0 / sqrt(nr);
+              for (int i = lane; i < ma; i += wl) y[i] *= sc;
+            } else {
+              for (int i = lane; i < ma; i += wl) y[i] = i == j % ma ? 1.0 : 0.0;
+            }
+            c.wsync();
+          }
+        }
+      }
+      c.sync();
+      // ---- 3e. W^T rows n < nw: z = D y, H_k z for k = ma - 2 .. 0 (z in registers, rows
+      //      i = gl + GL s of each lane), written to the physical indices act[i], masked rows zero
+#if defined(__HIP_DEVICE_COMPILE__)
+      constexpr int GL = kGroup;
+#else
+      constexpr int GL = 1;
+#endif
+      constexpr int ZR = (kRRLdsMax + GL - 1) / GL;
+      const int ngrp = nt / GL, gl = tid % GL;
+      for (int n = tid / GL; n < nw; n += ngrp) {
+        const double* y = Y + (size_t)n * ma;
+        cplx<double> z[ZR];
+#pragma unroll
+        for (int s = 0; s < ZR; ++s) {
+          const int i = gl + GL * s;
+          z[s] = i < ma ? mk<double>(dre[i] * y[i], dim[i] * y[i]) : mk<double>(0.0, 0.0);
+        }
+        for (int k = ma - 2; k >= 0; --k) {
+          const double bt = beta[k];
+          if (bt == 0.0) continue;
+          const int vo = voff(k, ma) - (k + 1);  // U[vo + i] = v_k for rows i = k + 1 .. ma - 1
+          double sx = 0.0, sy = 0.0;
+#pragma unroll
+          for (int s = 0; s < ZR; ++s) {
+            const int i = gl + GL * s;
+            if (i > k && i < ma) {
+              const cplx<double> vi = U[vo + i];
+              sx += vi.x * z[s].x + vi.y * z[s].y;
+              sy += vi.x * z[s].y - vi.y * z[s].x;
+            }
+          }
+          sx = bt * c.template gsum<GL>(sx);
+          sy = bt * c.template gsum<GL>(sy);
+#pragma unroll
+          for (int s = 0; s < ZR; ++s) {
+            const int i = gl + GL * s;
+            if (i > k && i < ma) {
+              const cplx<double> vi = U[vo + i];
+              z[s].x -= vi.x * sx - vi.y * sy;
+              z[s].y -= vi.x * sy + vi.y * sx;
+            }
+          }
+        }
+        cplx<double>* w = M + (size_t)n * ld;
+#pragma unroll
+        for (int s = 0; s < ZR; ++s) {
+          const int i = gl + GL * s;
+          if (i < ma) w[act[i]] = z[s];
+        }
+        for (int p = gl; p < m; p += GL)
+          if (masked[p]) w[p] = mk<double>(0.0, 0.0);
+      }
     }
+    // masked eigenpairs (A~ = kInactiveDiag e_p e_p^H) fill the columns beyond the active count
+    for (int n = nw + tid; n < nb; n += nt) {
+      int left = n - nw, p = 0;
+      for (; p < m; ++p)
+        if (masked[p] && left-- == 0) break;
+      cplx<double>* z = M + (size_t)n * ld;
+      for (int i = 0; i < m; ++i) z[i] = mk<double>(i == p ? 1.0 : 0.0, 0.0);
+      a.theta[n] = kInactiveDiag;
+    }
+    for (int n = tid; n < nw; n += nt) a.theta[n] = lam[n];
+    for (int n = tid; n < nb; n += nt) order[n] = n;
+    rr_tail<T>(c, a, U, M, sdiag, order);
   }
 };
 

@@ -121,7 +121,9 @@ static fde_status rr_launch(fde_plan* p, ProbSet<T>& ps, hipStream_t s) {
   size_t mats = 0;
   if (fixed + 2 * mbytes <= kLdsMax) mats = 2 * mbytes;
   else if (fixed + mbytes <= kLdsMax) mats = mbytes;
-  if (mmax <= kRRLdsMax && KRRSolveLds<T>::lds_bytes(mmax) <= kLdsMax)
+  if (mmax <= kRRLdsMax && KRRSolveTri<T>::lds_bytes(mmax, nbmax) <= kLdsMax)
+    FDE_TRY((launch<KRRSolveTri<T>, 1024>(dim3(ps.n), 1024, KRRSolveTri<T>::lds_bytes(mmax, nbmax), s, ps)));
+  else if (mmax <= kRRLdsMax && KRRSolveLds<T>::lds_bytes(mmax) <= kLdsMax)
     FDE_TRY((launch<KRRSolveLds<T>, 1024>(dim3(ps.n), 1024, KRRSolveLds<T>::lds_bytes(mmax), s, ps)));
   else
     FDE_TRY((launch<KRRSolve<T>, 1024>(dim3(ps.n), 1024, fixed + mats, s, ps, mats)));
