@@ -285,7 +285,7 @@ def main():
                    "parallelism": "single GPU"},
         "isolated_apply_h": {"band_applies_per_s": isolated, "bands": nb, "ms_per_call": t_apply * 1e3},
         "roofline": {"kernel": "fde_apply_h: FFT sandwich (KZInv, KPlaneHReg, KZFwd) + projectors "
-                               "(KAhB, KKbReduce, KKbAdd)", "bound": "hbm",
+                               "(KAhBAll, KKbReduce, KKbAdd)", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(), "algorithmic_bytes": alg_bytes},
         "cpu_baseline": cpu,
