@@ -281,7 +281,8 @@ def main():
                                "slab 36 ions/40 bands/4 k + molecule 6 ions/8 bands/Gamma",
                    "band_applies_per_cycle": per_cycle, "davidson_per_cycle": system.n_david,
                    "subspace_products": a.gemm, "launch": "eager" if a.eager else "one HIP graph per cycle",
-                   "apply_bands_per_plane_workgroup": None if tuned is None else tuned[0],
+                   "apply_bands_per_plane_workgroup": None if tuned is None else tuned["bpw"],
+                   "z_sticks_per_workgroup": None if tuned is None else tuned["sz"],
                    "parallelism": "single GPU"},
         "isolated_apply_h": {"band_applies_per_s": isolated, "bands": nb, "ms_per_call": t_apply * 1e3},
         "roofline": {"kernel": "fde_apply_h: FFT sandwich (KZInv, KPlaneHReg, KZFwd) + projectors "

@@ -121,11 +121,15 @@ fde_status fde_plan_set_workspace(fde_plan* plan, void* d_ws, size_t bytes, int 
 /*
  * Launch-shape tuning (no effect on results). FDE_TUNE_APPLY_BPW: bands per
  * plane-pass workgroup of fde_apply_h (each workgroup reads one V_eff plane
- * for that many bands); 0 restores the automatic choice. The driver's
+ * for that many bands). FDE_TUNE_STICK_GROUP: z-sticks per workgroup of the
+ * z-FFT passes of fde_apply_h and fde_density (a power of two, capped at 16
+ * and by the LDS budget). 0 restores the automatic choice. The driver's
  * autotuner times candidate values on the plan's own shapes and keeps the
- * fastest.
+ * fastest. Errors: FDE_ERR_ARG for an unknown key, a value outside [0, 1024]
+ * or a stick group that is not a power of two.
  */
 #define FDE_TUNE_APPLY_BPW 1
+#define FDE_TUNE_STICK_GROUP 2
 fde_status fde_plan_set_tuning(fde_plan* plan, int key, int value);
 
 #define FDE_GEMM_FP64 0

@@ -22,11 +22,17 @@ static KVec kvec(const fde_plan* p, int ik) {
   return k;
 }
 
-// Sticks per z-pass workgroup: the largest of 16, 8, 4, 2, 1 whose LDS fits
-// 80 KiB (two workgroups per CU).
+// Threads of a z-pass workgroup: one wavefront per stick up to kBlock.
+static int zthreads(int SZ) { return std::min(kBlock, 64 * SZ); }
+
+// Sticks per z-pass workgroup: the largest power of two up to 4 (or the tuned value, at
+// most 16) whose LDS fits 80 KiB. Small groups keep many workgroups resident per CU,
+// which hides the latency of the scattered sphere loads.
+
 static int stick_group(const fde_plan* p) {
   const size_t cs = p->csize();
-  for (int sz = 16; sz > 1; sz /= 2)
+  const int top = p->tune_sz > 0 ? std::min(16, p->tune_sz) : 4;
+  for (int sz = top; sz > 1; sz /= 2)
     if ((2 * (size_t)p->N[2] * (sz + 1) + p->N[2]) * cs <= 80 * 1024) return sz;
   return 1;
 }
@@ -92,7 +98,7 @@ static fde_status apply_h_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, cpl
     const cplx<T>* ps = psi + (size_t)b0 * t.npw;
     cplx<T>* hs = hpsi + (size_t)b0 * t.npw;
     const unsigned ngz = (unsigned)((t.ncol + SZ - 1) / SZ);
-    FDE_TRY(launch<KZInv<T>>(dim3(ngz, nbc), kBlock, zlds, s, ps, t.npw, (const int4*)t.d_sticks, t.ncol,
+    FDE_TRY(launch<KZInv<T>>(dim3(ngz, nbc), zthreads(SZ), zlds, s, ps, t.npw, (const int4*)t.d_sticks, t.ncol,
                              p->rad[2], tw3, sb, SZ));
     if (reg_plane) {
       // about two workgroups (one wave each) per SIMD over the whole chip, unless tuned
@@ -110,7 +116,7 @@ static fde_status apply_h_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, cpl
                                  (const int4*)t.d_sticks, (const int*)t.d_xlist, t.ncol, t.nxa, p->rad[0], p->rad[1],
                                  N3, tw1, tw2, veff, RB));
     }
-    FDE_TRY(launch<KZFwd<T>>(dim3(ngz, nbc), kBlock, zlds, s, (const cplx<T>*)sb, ps, hs, t.npw,
+    FDE_TRY(launch<KZFwd<T>>(dim3(ngz, nbc), zthreads(SZ), zlds, s, (const cplx<T>*)sb, ps, hs, t.npw,
                              (const int4*)t.d_sticks, (const int*)t.d_xlist, t.ncol, N1, N2, p->rad[2], tw3, kv, invN,
                              SZ));
     if (nproj > 0) {
@@ -149,7 +155,7 @@ static fde_status density_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, con
   for (int b0 = 0; b0 < nb; b0 += p->max_nb) {
     const int nbc = std::min(p->max_nb, nb - b0);
     const unsigned ngz = (unsigned)((t.ncol + SZ - 1) / SZ);
-    FDE_TRY(launch<KZInv<T>>(dim3(ngz, nbc), kBlock, zlds, s, psi + (size_t)b0 * t.npw, t.npw,
+    FDE_TRY(launch<KZInv<T>>(dim3(ngz, nbc), zthreads(SZ), zlds, s, psi + (size_t)b0 * t.npw, t.npw,
                              (const int4*)t.d_sticks, t.ncol, p->rad[2], tw3, sb, SZ));
     const int ngroups = std::min(4, nbc);
     const int BPW = (nbc + ngroups - 1) / ngroups;
@@ -392,10 +398,15 @@ fde_status fde_band_energies(fde_plan* p, int ik, int nb, const void* psi, const
 
 fde_status fde_plan_set_tuning(fde_plan* p, int key, int value) {
   if (!p) return fail(FDE_ERR_ARG, "null plan");
-  if (key != FDE_TUNE_APPLY_BPW) return fail(FDE_ERR_ARG, "unknown tuning key");
   if (value < 0 || value > 1024) return fail(FDE_ERR_ARG, "tuning value out of range");
-  p->tune_bpw = value;
-  return FDE_OK;
+  switch (key) {
+    case FDE_TUNE_APPLY_BPW: p->tune_bpw = value; return FDE_OK;
+    case FDE_TUNE_STICK_GROUP:
+      if ((value & (value - 1)) != 0) return fail(FDE_ERR_ARG, "sticks per workgroup must be 0 or a power of two");
+      p->tune_sz = value;
+      return FDE_OK;
+    default: return fail(FDE_ERR_ARG, "unknown tuning key");
+  }
 }
 
 }  // extern "C"

@@ -185,21 +185,19 @@ class Engine:
         self._graph.replay()
 
     # ---- launch-shape autotuning ----------------------------------------------
-    def autotune(self, candidates=(1, 2, 4, 8, 16), reps: int = 5):
+    def autotune(self, candidates=(1, 2, 4, 8, 16), sz_candidates=(1, 2, 4, 8, 16), reps: int = 5):
         """Time fde_apply_h of the largest band block with each bands-per-plane-
-        workgroup value and keep the fastest (launch shape only; results unchanged)."""
+        workgroup value, then with each z-sticks-per-workgroup value, and keep the
+        fastest of each (launch shapes only; results unchanged). Returns
+        {"bpw": best, "bpw_ms": {value: ms}, "sz": best, "sz_ms": {value: ms}}."""
         if self.be.emulated:
             return None
         b = max((b for row in self.blocks for b in row), key=lambda b: b.nb * self.plan.npw(b.ik))
         X = b.V[:b.nb]
         HX = b.HV[b.nb:2 * b.nb] if b.HV.shape[0] >= 2 * b.nb else torch.empty_like(X)
         veff = self.veff[b.isub]
-        best = None
-        times = {}
-        for bpw in candidates:
-            if bpw > b.nb:
-                continue
-            self.plan.set_tuning(fde.TUNE_APPLY_BPW, bpw)
+
+        def timed():
             self.plan.apply_h(b.ik, X, veff, b.beta, b.dkb, out=HX)
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
@@ -208,11 +206,20 @@ class Engine:
                 self.plan.apply_h(b.ik, X, veff, b.beta, b.dkb, out=HX)
             e1.record()
             torch.cuda.synchronize(self.be.device)
-            times[bpw] = e0.elapsed_time(e1) / reps
-            if best is None or times[bpw] < times[best]:
-                best = bpw
-        self.plan.set_tuning(fde.TUNE_APPLY_BPW, best)
-        return best, times
+            return e0.elapsed_time(e1) / reps
+
+        def search(key, values):
+            times = {}
+            for v in values:
+                self.plan.set_tuning(key, v)
+                times[v] = timed()
+            best = min(times, key=times.get)
+            self.plan.set_tuning(key, best)
+            return best, times
+
+        bpw, bpw_ms = search(fde.TUNE_APPLY_BPW, [v for v in candidates if v <= b.nb])
+        sz, sz_ms = search(fde.TUNE_STICK_GROUP, sz_candidates)
+        return {"bpw": bpw, "bpw_ms": bpw_ms, "sz": sz, "sz_ms": sz_ms}
 
     def band_applies_per_cycle(self, n_david: Optional[int] = None) -> int:
         n_david = self.system.n_david if n_david is None else n_david

@@ -9,6 +9,7 @@ transform, with FP64 accumulation of every reduction).
 from __future__ import annotations
 
 import numpy as np
+import pytest
 import torch
 
 import fde_synth
@@ -305,13 +306,14 @@ def check_apply_h_grid(be, prec, grid, spacing=0.3, ecut=3.0, nb=2, kf=(0.25, -0
     psi = fde_synth.random_complex(51, (nb, sph.npw)) / (1 + 2 * sph.kin)[None]
     ref = oham.apply_h(cell, sph, psi, veff)
     out = plan.apply_h(0, to_dev(plan, psi, "c"), to_dev(plan, veff, "r"))
-    occw = np.array([1.0, 0.5][:nb])
+    occw = np.linspace(1.0, 0.5, nb)
     rho = plan.zeros_grid()
     plan.density(0, to_dev(plan, psi, "c"), to_dev(plan, occw, "d"), rho)
     be.sync()
     assert rel(host(out), ref) < TOL[prec], rel(host(out), ref)
     rref = odens.density(cell, sph, psi, occw)
     assert rel(host(rho), rref) < TOL[prec]
+
 
 
 # ---------------------------------------------------------------------------
@@ -482,3 +484,18 @@ def check_tuning_keeps_results(be, prec):
         be.sync()
         assert np.max(np.abs(out - ref)) <= 1e-14 * np.max(np.abs(ref)), bpw
     plan.set_tuning(fde.TUNE_APPLY_BPW, 0)
+    occw = to_dev(plan, np.linspace(0.1, 0.9, 9), "d")
+    rho = plan.zeros_grid()
+    plan.density(0, psi, occw, rho)
+    rho_ref = host(rho).copy()
+    for sz in (1, 2, 4, 8, 16):  # every z-stick is transformed on its own: results identical
+        plan.set_tuning(fde.TUNE_STICK_GROUP, sz)
+        out = host(plan.apply_h(0, psi, veff))
+        rho.zero_()
+        plan.density(0, psi, occw, rho)
+        be.sync()
+        assert np.array_equal(out, ref), sz
+        assert np.array_equal(host(rho), rho_ref), sz
+    plan.set_tuning(fde.TUNE_STICK_GROUP, 0)
+    with pytest.raises(fde.FdeError):
+        plan.set_tuning(fde.TUNE_STICK_GROUP, 3)

@@ -97,6 +97,11 @@ def test_apply_h_specialised_lengths(be, grid):
     pc.check_apply_h_grid(be, fde.F64, grid)
 
 
+def test_apply_h_register_plane(be):
+    """24 x 24 planes take the register plane pass (FP64 too); three bands."""
+    pc.check_apply_h_grid(be, fde.F64, (24, 24, 30), nb=3)
+
+
 def test_mlp_forward(be):
     pc.check_mlp_forward(be)
 
