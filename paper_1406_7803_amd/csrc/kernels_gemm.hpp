@@ -361,6 +361,7 @@ template <typename T>
 struct KGram {
   static constexpr int KT = 32, LD = KT + 1, NW = 8;
   static constexpr int MAXTP = (kGramTiles * (kGramTiles + 1) + NW - 1) / NW;  // tile-products per wave
+  static constexpr int MAXLD = (2 * 16 * kGramTiles * KT + NW * 64 - 1) / (NW * 64);  // staged values per thread
   static size_t lds_bytes(int m) { return sizeof(cplx<T>) * 2 * (size_t)m * LD; }
   FDE_HD static void tile_of(int tp, int& I, int& J, int& prod) {
     prod = tp & 1;  // S and A interleaved
@@ -394,16 +395,40 @@ struct KGram {
     cplx<double>* acc = out;  // the chunk's own partials serve as the accumulator
     for (size_t o = c.tid(); o < 2 * mm; o += c.nthr()) acc[o] = mk<double>(0, 0);
 #endif
-    for (int gs = g0; gs < gend; gs += KT) {
-      for (int idx = c.tid(); idx < 2 * m * KT; idx += c.nthr()) {
-        const int h = idx / (m * KT), rem = idx - h * (m * KT);
-        const int r = rem / KT, k = rem - r * KT;
-        const int g = gs + k;
-        const cplx<T>* src = h ? P.B1 : P.A;
-        (h ? sH : sV)[r * LD + k] = g < gend ? src[(size_t)r * npw + g] : mk<T>(0, 0);
-      }
-      c.sync();
 #if defined(__HIP_DEVICE_COMPILE__)
+    // the next stage's rows are fetched into registers while the current one is multiplied
+    cplx<T> pre[MAXLD];
+    auto fetch = [&](int gs) {
+#pragma unroll
+      for (int u = 0; u < MAXLD; ++u) {
+        const int idx = c.tid() + NW * 64 * u;
+        if (idx < 2 * m * KT) {
+          const int h = idx / (m * KT), rem = idx - h * (m * KT);
+          const int r = rem / KT, k = rem - r * KT;
+          const int g = gs + k;
+          const cplx<T>* src = h ? P.B1 : P.A;
+          pre[u] = g < gend ? src[(size_t)r * npw + g] : mk<T>(0, 0);
+        }
+      }
+    };
+    auto stage = [&]() {
+#pragma unroll
+      for (int u = 0; u < MAXLD; ++u) {
+        const int idx = c.tid() + NW * 64 * u;
+        if (idx < 2 * m * KT) {
+          const int h = idx / (m * KT), rem = idx - h * (m * KT);
+          const int r = rem / KT, k = rem - r * KT;
+          (h ? sH : sV)[r * LD + k] = pre[u];
+        }
+      }
+    };
+    fetch(g0);
+    stage();
+    c.sync();
+#endif
+    for (int gs = g0; gs < gend; gs += KT) {
+#if defined(__HIP_DEVICE_COMPILE__)
+      if (gs + KT < gend) fetch(gs + KT);
 #pragma unroll
       for (int u = 0; u < MAXTP; ++u) {
         const int tp = wave + NW * u;
@@ -422,7 +447,17 @@ struct KGram {
           im[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ay, bx, im[u], 0, 0, 0);
         }
       }
+      c.sync();
+      if (gs + KT < gend) stage();
 #else
+      for (int idx = c.tid(); idx < 2 * m * KT; idx += c.nthr()) {
+        const int h = idx / (m * KT), rem = idx - h * (m * KT);
+        const int r = rem / KT, k = rem - r * KT;
+        const int g = gs + k;
+        const cplx<T>* src = h ? P.B1 : P.A;
+        (h ? sH : sV)[r * LD + k] = g < gend ? src[(size_t)r * npw + g] : mk<T>(0, 0);
+      }
+      c.sync();
       for (size_t o = c.tid(); o < 2 * mm; o += c.nthr()) {
         const int prod = (int)(o / mm), e = (int)(o - prod * mm);
         const int i = e / m, j = e - i * m;
