@@ -102,6 +102,12 @@ struct DevCtx {
     if (W == 16) return v;
     return (rdlane(v, 0) + rdlane(v, 16)) + (rdlane(v, 32) + rdlane(v, 48));
   }
+  // 1 / sqrt(q) from the hardware estimate and two Newton steps
+  __device__ __forceinline__ static double rsq(double q) {
+    double r = __builtin_amdgcn_rsq(q);
+    r = r * fma(-0.5 * q * r, r, 1.5);
+    return r * fma(-0.5 * q * r, r, 1.5);
+  }
   // 1 / q from the hardware reciprocal and two Newton steps
   __device__ __forceinline__ static double rcp(double q) {
     double r = __builtin_amdgcn_rcp(q);
@@ -143,6 +149,7 @@ struct HostCtx {
   template <int W>
   double gsum(double v) const { return v; }
   static double rcp(double q) { return 1.0 / q; }
+  static double rsq(double q) { return 1.0 / sqrt(q); }
 };
 
 // --------------------------------------------------------------------------

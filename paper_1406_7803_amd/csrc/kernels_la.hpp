@@ -408,6 +408,100 @@ struct KRotate {
 };
 
 // ---------------------------------------------------------------------------
+// The same rotation streamed (m <= 4 kRotSteps, nb <= 64): C staged once per
+// workgroup in LDS; each wavefront takes groups of 16 plane-wave columns in turn,
+// loads all m rows of its group straight into registers (no LDS staging of V),
+// multiplies on the matrix cores and writes the nb rows back in place (every row
+// of the group was read first). grid (gx, 2, n); gx workgroups share the groups.
+// ---------------------------------------------------------------------------
+constexpr int kRotSteps = 20;  // k-steps of 4 rows held in registers: m <= 80
+
+template <typename T>
+struct KRotateStream {
+  FDE_HD static size_t lds_bytes(int m, int nb) { return sizeof(cplx<T>) * (size_t)m * nb; }
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const ProbSet<T> ps, int gx) {
+    const Prob<T>& P = ps.p[c.bz()];
+    const int m = P.m, nb = P.nb, npw = P.npw;
+    cplx<T>* M = c.by() == 0 ? P.v : P.hv;
+    const cplx<T>* Cg = (const cplx<T>*)P.Ct;
+    cplx<T>* sC = (cplx<T>*)lds;
+    for (int idx = c.tid(); idx < m * nb; idx += c.nthr()) sC[idx] = Cg[idx];
+    c.sync();
+    const int ngroups = (npw + 15) / 16;
+#if defined(__HIP_DEVICE_COMPILE__)
+    const int lane = c.tid() & 63, w = c.tid() >> 6, nw = c.nthr() >> 6;
+    const int col = lane & 15, kq = lane >> 4;
+    constexpr int MT = 4;
+    typedef T v4 __attribute__((ext_vector_type(4)));
+    const int nmt = (nb + 15) / 16;
+    for (int grp = c.bx() * nw + w; grp < ngroups; grp += gx * nw) {  // uniform per wavefront
+      const int g = 16 * grp + col;
+      cplx<T> b[kRotSteps];
+#pragma unroll
+      for (int st = 0; st < kRotSteps; ++st) {
+        const int k = 4 * st + kq;
+        b[st] = (k < m && g < npw) ? M[(size_t)k * npw + g] : mk<T>(0, 0);
+      }
+      v4 re[MT], im[MT];
+#pragma unroll
+      for (int t = 0; t < MT; ++t) {
+        re[t] = v4{0, 0, 0, 0};
+        im[t] = v4{0, 0, 0, 0};
+      }
+#pragma unroll
+      for (int st = 0; st < kRotSteps; ++st) {
+        if (4 * st >= m) break;  // uniform
+        const int k = 4 * st + kq;
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+          if (t >= nmt) break;
+          const int n = 16 * t + col;
+          const cplx<T> a_ = (k < m && n < nb) ? sC[(size_t)k * nb + n] : mk<T>(0, 0);
+          if constexpr (sizeof(T) == 8) {
+            re[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_.x, b[st].x, re[t], 0, 0, 0);
+            re[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_.y, b[st].y, re[t], 0, 0, 0);
+            im[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_.x, b[st].y, im[t], 0, 0, 0);
+            im[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_.y, b[st].x, im[t], 0, 0, 0);
+          } else {
+            re[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_.x, b[st].x, re[t], 0, 0, 0);
+            re[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a_.y, b[st].y, re[t], 0, 0, 0);
+            im[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_.x, b[st].y, im[t], 0, 0, 0);
+            im[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_.y, b[st].x, im[t], 0, 0, 0);
+          }
+        }
+      }
+      if (g < npw) {
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+          if (t >= nmt) break;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            // output row of register r: FP64 MFMA 4 r + l/16, FP32 MFMA 4 (l/16) + r
+            const int n = 16 * t + (sizeof(T) == 8 ? 4 * r + kq : 4 * kq + r);
+            if (n < nb) M[(size_t)n * npw + g] = mk<T>(re[t][r], im[t][r]);
+          }
+        }
+      }
+    }
+#else
+    for (int grp = c.bx(); grp < ngroups; grp += gx) {
+      const int gend = 16 * grp + 16 < npw ? 16 * grp + 16 : npw;
+      for (int g = 16 * grp; g < gend; ++g) {
+        cplx<T> col[4 * kRotSteps];
+        for (int k = 0; k < m; ++k) col[k] = M[(size_t)k * npw + g];
+        for (int n = 0; n < nb; ++n) {
+          cplx<T> acc = mk<T>(0, 0);
+          for (int k = 0; k < m; ++k) acc = acc + col[k] * sC[(size_t)k * nb + n];
+          M[(size_t)n * npw + g] = acc;
+        }
+      }
+    }
+#endif
+  }
+};
+
+// ---------------------------------------------------------------------------
 // Residual + Teter-Payne-Allan preconditioner of every problem; block (n, p)
 // handles band n of problem p and writes the correction T_n into row n of its
 // t (rows nb.. of V in a band block). grid (nb_max, n)

@@ -678,12 +678,15 @@ struct KRRSolveTri {
                                                  DevCtx::rdlane(A[t][s].y, (k + 1) & 63));
         double bt = 0.0;
         cplx<double> alpha = x0, v0 = x0;
-        if (k + 2 < ma && s2 > norm2(x0)) {
-          const double ax0 = sqrt(norm2(x0)), sg = sqrt(s2);
-          const cplx<double> ph = ax0 > 0.0 ? mk<double>(x0.x / ax0, x0.y / ax0) : mk<double>(1.0, 0.0);
+        const double n0 = norm2(x0);
+        if (k + 2 < ma && s2 > n0) {
+          // |x0|, sigma and beta from reciprocal square roots / reciprocals with Newton steps
+          const double r0 = n0 > 0.0 ? DevCtx::rsq(n0) : 0.0, rs = DevCtx::rsq(s2);
+          const double ax0 = n0 * r0, sg = s2 * rs;
+          const cplx<double> ph = n0 > 0.0 ? mk<double>(x0.x * r0, x0.y * r0) : mk<double>(1.0, 0.0);
           alpha = mk<double>(-ph.x * sg, -ph.y * sg);
           v0 = mk<double>(x0.x + ph.x * sg, x0.y + ph.y * sg);
-          bt = 1.0 / (sg * (sg + ax0));
+          bt = DevCtx::rcp(sg * (sg + ax0));
         }
         const int vo = voff(k, ma) - (k + 1);
 #pragma unroll
@@ -710,20 +713,27 @@ struct KRRSolveTri {
       const double bt = beta[k];
       if (bt != 0.0) {  // uniform
         // partial sums of A' v over this wavefront's columns
+        // columns of this wavefront inside the trailing block: j in [jlo, jhi) (uniform)
+        const int jlo = kCPW * wv > k + 1 ? kCPW * wv : k + 1;
+        const int jhi = kCPW * wv + kCPW < ma ? kCPW * wv + kCPW : ma;
         cplx<double> vs[kCPW];
 #pragma unroll
         for (int s = 0; s < kCPW; ++s) {
           const int j = kCPW * wv + s;
-          vs[s] = (j > k && j < ma) ? xk[j] : mk<double>(0.0, 0.0);
+          vs[s] = (j >= jlo && j < jhi) ? xk[j] : mk<double>(0.0, 0.0);
         }
 #pragma unroll
         for (int t = 0; t < kRT; ++t) {
+          if (64 * t >= ma || 64 * t + 63 <= k) continue;  // no trailing row in this slot (uniform)
           const int i = lane + 64 * t;
           double sx = 0.0, sy = 0.0;
 #pragma unroll
           for (int s = 0; s < kCPW; ++s) {
-            sx += A[t][s].x * vs[s].x - A[t][s].y * vs[s].y;
-            sy += A[t][s].x * vs[s].y + A[t][s].y * vs[s].x;
+            const int j = kCPW * wv + s;
+            if (j >= jlo && j < jhi) {  // uniform
+              sx += A[t][s].x * vs[s].x - A[t][s].y * vs[s].y;
+              sy += A[t][s].x * vs[s].y + A[t][s].y * vs[s].x;
+            }
           }
           if (i > k && i < ma) part[(size_t)wv * m + i] = mk<double>(sx, sy);
         }
@@ -753,23 +763,29 @@ struct KRRSolveTri {
         double kk = 0.0;
         for (int w = 0; w < kRT; ++w) kk += kpart[w];
         kk *= 0.5 * bt;
-        cplx<double> ws[kCPW];
+        if (jlo < jhi) {  // uniform: this wavefront has trailing columns
+          cplx<double> ws[kCPW];
 #pragma unroll
-        for (int s = 0; s < kCPW; ++s) {
-          const int j = kCPW * wv + s;
-          ws[s] = (j > k && j < ma) ? mk<double>(pbx[j] - kk * vs[s].x, pby[j] - kk * vs[s].y) : mk<double>(0.0, 0.0);
-        }
+          for (int s = 0; s < kCPW; ++s) {
+            const int j = kCPW * wv + s;
+            ws[s] = (j >= jlo && j < jhi) ? mk<double>(pbx[j] - kk * vs[s].x, pby[j] - kk * vs[s].y)
+                                          : mk<double>(0.0, 0.0);
+          }
 #pragma unroll
-        for (int t = 0; t < kRT; ++t) {
-          const int i = lane + 64 * t;
-          if (i > k && i < ma) {
-            const cplx<double> vi = xk[i];
-            const double wix = pbx[i] - kk * vi.x, wiy = pby[i] - kk * vi.y;
+          for (int t = 0; t < kRT; ++t) {
+            if (64 * t >= ma || 64 * t + 63 <= k) continue;  // uniform
+            const int i = lane + 64 * t;
+            const cplx<double> vi = (i > k && i < ma) ? xk[i] : mk<double>(0.0, 0.0);
+            const double wix = (i > k && i < ma) ? pbx[i] - kk * vi.x : 0.0;
+            const double wiy = (i > k && i < ma) ? pby[i] - kk * vi.y : 0.0;
 #pragma unroll
             for (int s = 0; s < kCPW; ++s) {
-              // A_ij -= v_i conj(w_j) + w_i conj(v_j); columns outside the block have v = w = 0
-              A[t][s].x -= (vi.x * ws[s].x + vi.y * ws[s].y) + (wix * vs[s].x + wiy * vs[s].y);
-              A[t][s].y -= (vi.y * ws[s].x - vi.x * ws[s].y) + (wiy * vs[s].x - wix * vs[s].y);
+              const int j = kCPW * wv + s;
+              if (j >= jlo && j < jhi) {  // uniform; rows outside the block have v = w = 0
+                // A_ij -= v_i conj(w_j) + w_i conj(v_j)
+                A[t][s].x -= (vi.x * ws[s].x + vi.y * ws[s].y) + (wix * vs[s].x + wiy * vs[s].y);
+                A[t][s].y -= (vi.y * ws[s].x - vi.x * ws[s].y) + (wiy * vs[s].x - wix * vs[s].y);
+              }
             }
           }
         }
