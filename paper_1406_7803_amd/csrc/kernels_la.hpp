@@ -437,20 +437,25 @@ struct KRotateStream {
     const int nmt = (nb + 15) / 16;
     for (int grp = c.bx() * nw + w; grp < ngroups; grp += gx * nw) {  // uniform per wavefront
       const int g = 16 * grp + col;
-      cplx<T> b[kRotSteps];
-#pragma unroll
-      for (int st = 0; st < kRotSteps; ++st) {
-        const int k = 4 * st + kq;
-        b[st] = (k < m && g < npw) ? M[(size_t)k * npw + g] : mk<T>(0, 0);
-      }
       v4 re[MT], im[MT];
 #pragma unroll
       for (int t = 0; t < MT; ++t) {
         re[t] = v4{0, 0, 0, 0};
         im[t] = v4{0, 0, 0, 0};
       }
+      // the group's rows in two halves of kRotSteps / 2 k-steps (fewer live registers)
 #pragma unroll
-      for (int st = 0; st < kRotSteps; ++st) {
+      for (int hf = 0; hf < 2; ++hf) {
+      constexpr int HS = kRotSteps / 2;
+      cplx<T> b[HS];
+#pragma unroll
+      for (int u = 0; u < HS; ++u) {
+        const int k = 4 * (HS * hf + u) + kq;
+        b[u] = (k < m && g < npw) ? M[(size_t)k * npw + g] : mk<T>(0, 0);
+      }
+#pragma unroll
+      for (int u = 0; u < HS; ++u) {
+        const int st = HS * hf + u;
         if (4 * st >= m) break;  // uniform
         const int k = 4 * st + kq;
 #pragma unroll
@@ -459,17 +464,18 @@ struct KRotateStream {
           const int n = 16 * t + col;
           const cplx<T> a_ = (k < m && n < nb) ? sC[(size_t)k * nb + n] : mk<T>(0, 0);
           if constexpr (sizeof(T) == 8) {
-            re[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_.x, b[st].x, re[t], 0, 0, 0);
-            re[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_.y, b[st].y, re[t], 0, 0, 0);
-            im[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_.x, b[st].y, im[t], 0, 0, 0);
-            im[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_.y, b[st].x, im[t], 0, 0, 0);
+            re[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_.x, b[u].x, re[t], 0, 0, 0);
+            re[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_.y, b[u].y, re[t], 0, 0, 0);
+            im[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_.x, b[u].y, im[t], 0, 0, 0);
+            im[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_.y, b[u].x, im[t], 0, 0, 0);
           } else {
-            re[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_.x, b[st].x, re[t], 0, 0, 0);
-            re[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a_.y, b[st].y, re[t], 0, 0, 0);
-            im[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_.x, b[st].y, im[t], 0, 0, 0);
-            im[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_.y, b[st].x, im[t], 0, 0, 0);
+            re[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_.x, b[u].x, re[t], 0, 0, 0);
+            re[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a_.y, b[u].y, re[t], 0, 0, 0);
+            im[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_.x, b[u].y, im[t], 0, 0, 0);
+            im[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_.y, b[u].x, im[t], 0, 0, 0);
           }
         }
+      }
       }
       if (g < npw) {
 #pragma unroll

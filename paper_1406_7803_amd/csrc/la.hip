@@ -131,7 +131,8 @@ static fde_status rr_launch(fde_plan* p, ProbSet<T>& ps, hipStream_t s) {
     // streamed rotation: about eight workgroups of four wavefronts per CU over all problems
     const int groups = (npwmax + 15) / 16;
     const int gx = std::max(1, std::min((groups + 3) / 4, 2048 / (2 * ps.n)));
-    return launch<KRotateStream<T>>(dim3(gx, 2, ps.n), kBlock, KRotateStream<T>::lds_bytes(mmax, nbmax), s, ps, gx);
+    return launch<KRotateStream<T>, 256, 3>(dim3(gx, 2, ps.n), kBlock, KRotateStream<T>::lds_bytes(mmax, nbmax), s,
+                                            ps, gx);
   }
   // in-place rotation: plane-wave chunk of all m rows (+ C when it fits) in LDS
   const size_t cs = sizeof(cplx<T>);
