@@ -88,7 +88,7 @@ hipError_t allow_lds(const void* kernel, size_t bytes);
 
 constexpr int kBlock = 256;
 // plane waves per partial-sum chunk of the projector products beta^H psi
-constexpr int kKbChunk = 256;
+constexpr int kKbChunk = 128;
 constexpr size_t kLdsMax = 160 * 1024;
 
 }  // namespace fde

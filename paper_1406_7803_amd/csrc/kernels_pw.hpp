@@ -296,18 +296,18 @@ struct KRhoReduce {
 // sums are added in a fixed order.
 template <typename T>
 struct KKbReduce {
-  static constexpr int NO = 64;
+  static constexpr int NO = 16, NG = 16;  // outputs per block, chunk groups per output
   template <class Ctx>
   FDE_HD static void run(const Ctx& c, char* lds, const cplx<double>* __restrict__ part, int nchunk, int nproj, int nb,
                          const double* __restrict__ dkb, cplx<T>* __restrict__ dp) {
-    cplx<double>* red = (cplx<double>*)lds;  // [4][NO]
+    cplx<double>* red = (cplx<double>*)lds;  // [NG][NO]
     const int nout = nproj * nb;
-    for (int idx = c.tid(); idx < 4 * NO; idx += c.nthr()) {
+    for (int idx = c.tid(); idx < NG * NO; idx += c.nthr()) {
       const int w = idx / NO, l = idx - w * NO;
       const int o = c.bx() * NO + l;
       double sx = 0, sy = 0;
       if (o < nout)
-        for (int k = w; k < nchunk; k += 4) {
+        for (int k = w; k < nchunk; k += NG) {
           const cplx<double> v = part[(size_t)k * nout + o];
           sx += v.x;
           sy += v.y;
@@ -318,8 +318,11 @@ struct KKbReduce {
     for (int l = c.tid(); l < NO; l += c.nthr()) {
       const int o = c.bx() * NO + l;
       if (o >= nout) continue;
-      const double sx = (red[l].x + red[NO + l].x) + (red[2 * NO + l].x + red[3 * NO + l].x);
-      const double sy = (red[l].y + red[NO + l].y) + (red[2 * NO + l].y + red[3 * NO + l].y);
+      double sx = 0, sy = 0;
+      for (int w = 0; w < NG; ++w) {
+        sx += red[w * NO + l].x;
+        sy += red[w * NO + l].y;
+      }
       const double d = dkb[o / nb];
       dp[o] = mk<T>((T)(d * sx), (T)(d * sy));
     }

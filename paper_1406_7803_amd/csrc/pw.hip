@@ -122,7 +122,8 @@ static fde_status apply_h_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, cpl
     if (nproj > 0) {
       FDE_TRY(kb_project<T>(beta, ps, t.npw, nproj, nbc, nchunk, part, s));
       FDE_TRY(launch<KKbReduce<T>>(dim3((nproj * nbc + KKbReduce<T>::NO - 1) / KKbReduce<T>::NO), kBlock,
-                                   4 * KKbReduce<T>::NO * sizeof(cplx<double>), s, (const cplx<double>*)part, nchunk,
+                                   KKbReduce<T>::NG * KKbReduce<T>::NO * sizeof(cplx<double>), s,
+                                   (const cplx<double>*)part, nchunk,
                                    nproj, nbc, dkb, dp));
       FDE_TRY(launch<KKbAdd<T>>(dim3((t.npw + KKbAdd<T>::TG - 1) / KKbAdd<T>::TG), kBlock, KKbAdd<T>::lds_bytes(), s,
                                 beta, (const cplx<T>*)dp, hs, t.npw, nproj, nbc));
