@@ -13,6 +13,7 @@ buffers (PyTorch tensors) and the order of the calls.
 """
 from __future__ import annotations
 
+import contextlib
 from dataclasses import dataclass, field
 from typing import List, Optional
 
@@ -41,6 +42,16 @@ class BandBlock:
 
 
 @dataclass
+class SolverGroup:
+    """Band blocks solved together: their own plan (workspace) and HIP stream, so that
+    one group's Rayleigh-Ritz solve (a few CUs) overlaps another group's H applications."""
+    plan: "fde.Plan"
+    blocks: List[BandBlock]
+    stream: Optional[torch.cuda.Stream]
+    vbar: Optional[torch.Tensor] = None
+
+
+@dataclass
 class Engine:
     system: object
     prec: int = fde.F64
@@ -48,6 +59,7 @@ class Engine:
     kinds: dict = field(default_factory=lambda: dict(xc=fde.XC_LDA, xc_nad=fde.XC_LDA, kin_nad=fde.KIN_LC94))
     mlp_params: Optional[torch.Tensor] = None   # learned preconditioner (FP32, FDE_MLP_NPARAM); None = TPA
     gemm: int = fde.GEMM_FP64                   # arithmetic of the Rayleigh-Ritz subspace products
+    streams: int = 2                            # band-solver groups run concurrently (GPU backend)
 
     def __post_init__(self):
         s = self.system
@@ -101,8 +113,34 @@ class Engine:
         self.occw = [torch.zeros_like(e) for e in self.eps]
         self.mu = [torch.zeros(1, dtype=torch.float64, device=dev) for _ in s.subsystems]
         self.oinfo = [torch.zeros(1, dtype=torch.int32, device=dev) for _ in s.subsystems]
-        self.vbar = torch.zeros(sum(len(r) for r in self.blocks), dtype=torch.float64, device=dev)
+        self._make_groups(max_nb, nproj_max, nblocks)
         self._initial_density()
+
+    def _make_groups(self, max_nb, nproj_max, nblocks):
+        """Split the band blocks into `streams` groups of about equal nb * npw."""
+        s, p = self.system, self.plan
+        blocks = [b for row in self.blocks for b in row]
+        ng = 1 if self.be.emulated else max(1, min(self.streams, len(blocks)))
+        loads, members = [0] * ng, [[] for _ in range(ng)]
+        for b in sorted(blocks, key=lambda b: -b.nb * p.npw(b.ik)):
+            g = loads.index(min(loads))
+            members[g].append(b)
+            loads[g] += b.nb * p.npw(b.ik)
+        self.groups = []
+        for g in range(ng):
+            plan = p
+            if g > 0:
+                plan = fde.Plan(s.L, s.grid, s.ecut, s.all_kfrac, prec=self.prec, max_nb=max_nb,
+                                max_nproj=nproj_max, max_batch=min(16, nblocks), backend=self.be)
+                if self.gemm != fde.GEMM_FP64:
+                    plan.set_gemm_mode(self.gemm)
+            stream = torch.cuda.Stream(self.be.device) if ng > 1 else None
+            vbar = torch.zeros(len(members[g]), dtype=torch.float64, device=self.be.device)
+            self.groups.append(SolverGroup(plan, members[g], stream, vbar))
+
+    def set_tuning(self, key: int, value: int):
+        for g in self.groups:
+            g.plan.set_tuning(key, value)
 
     @staticmethod
     def _nproj(sub) -> int:
@@ -121,33 +159,52 @@ class Engine:
                 occw = torch.full((b.nb,), w, dtype=torch.float64, device=self.be.device)
                 p.density(b.ik, X, occw, self.rho_in[I])
 
-    def _rr_blocks(self, m_of):
-        return [self.plan.make_block(b.ik, b.nb, m_of(b), b.V, b.HV, active=b.active, eval=b.eval, info=b.info)
-                for row in self.blocks for b in row]
+    @staticmethod
+    def _rr_blocks(g: SolverGroup, m_of):
+        return [g.plan.make_block(b.ik, b.nb, m_of(b), b.V, b.HV, active=b.active, eval=b.eval, info=b.info)
+                for b in g.blocks]
 
-    def _pc_blocks(self):
-        return [self.plan.make_block(b.ik, b.nb, b.nb, b.V, b.HV, t_active=b.active[b.nb:], eval=b.eval,
-                                     rnorm=b.rnorm) for row in self.blocks for b in row]
+    @staticmethod
+    def _pc_blocks(g: SolverGroup):
+        return [g.plan.make_block(b.ik, b.nb, b.nb, b.V, b.HV, t_active=b.active[b.nb:], eval=b.eval,
+                                  rnorm=b.rnorm) for b in g.blocks]
 
     def solve(self, n_david: int):
-        """Every band block in lockstep: H X and Rayleigh-Ritz on X, then n_david
-        block-Davidson iterations; the solver calls are batched over blocks."""
-        p = self.plan
-        blocks = [b for row in self.blocks for b in row]
-        for b in blocks:
-            p.apply_h(b.ik, b.V[:b.nb], self.veff[b.isub], b.beta, b.dkb, out=b.HV[:b.nb])
-        p.subspace_rr_batched(self._rr_blocks(lambda b: b.nb))
-        if self.mlp_params is not None:
-            for i, b in enumerate(blocks):
-                p.grid_mean(self.veff[b.isub], out=self.vbar[i:i + 1])
+        """Every band block in lockstep within its group: H X and Rayleigh-Ritz on X, then
+        n_david block-Davidson iterations; the solver calls are batched over a group's
+        blocks, and the groups run on their own streams (forked from and joined back to
+        the current stream)."""
+        main = None if self.be.emulated else torch.cuda.current_stream(self.be.device)
+
+        def on(g):
+            return torch.cuda.stream(g.stream) if g.stream is not None else contextlib.nullcontext()
+
+        for g in self.groups:
+            if g.stream is not None:
+                g.stream.wait_stream(main)
+        for g in self.groups:
+            with on(g):
+                p = g.plan
+                for b in g.blocks:
+                    p.apply_h(b.ik, b.V[:b.nb], self.veff[b.isub], b.beta, b.dkb, out=b.HV[:b.nb])
+                p.subspace_rr_batched(self._rr_blocks(g, lambda b: b.nb))
+                if self.mlp_params is not None:
+                    for i, b in enumerate(g.blocks):
+                        p.grid_mean(self.veff[b.isub], out=g.vbar[i:i + 1])
         for _ in range(n_david):
-            if self.mlp_params is None:
-                p.precondition_batched(self._pc_blocks())
-            else:
-                p.precondition_mlp_batched(self._pc_blocks(), self.mlp_params, self.vbar)
-            for b in blocks:
-                p.apply_h(b.ik, b.V[b.nb:], self.veff[b.isub], b.beta, b.dkb, out=b.HV[b.nb:])
-            p.subspace_rr_batched(self._rr_blocks(lambda b: 2 * b.nb))
+            for g in self.groups:
+                with on(g):
+                    p = g.plan
+                    if self.mlp_params is None:
+                        p.precondition_batched(self._pc_blocks(g))
+                    else:
+                        p.precondition_mlp_batched(self._pc_blocks(g), self.mlp_params, g.vbar)
+                    for b in g.blocks:
+                        p.apply_h(b.ik, b.V[b.nb:], self.veff[b.isub], b.beta, b.dkb, out=b.HV[b.nb:])
+                    p.subspace_rr_batched(self._rr_blocks(g, lambda b: 2 * b.nb))
+        for g in self.groups:
+            if g.stream is not None:
+                main.wait_stream(g.stream)
 
     def cycle(self, n_david: Optional[int] = None):
         s = self.system
@@ -214,7 +271,7 @@ class Engine:
                 self.plan.set_tuning(key, v)
                 times[v] = timed()
             best = min(times, key=times.get)
-            self.plan.set_tuning(key, best)
+            self.set_tuning(key, best)
             return best, times
 
         bpw, bpw_ms = search(fde.TUNE_APPLY_BPW, [v for v in candidates if v <= b.nb])

@@ -245,3 +245,28 @@ def test_autotune_on_c2(be):
           f"by z-sticks per workgroup: {t['sz_ms']}; chosen {t['sz']}")
     assert t["bpw_ms"][t["bpw"]] == min(t["bpw_ms"].values())
     assert t["sz_ms"][t["sz"]] == min(t["sz_ms"].values())
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_stream_groups_match_single_group(be, prec):
+    """Band blocks solved in two groups on their own plans and streams give the same bits
+    as one group on the current stream, eagerly and through a captured graph."""
+    from paper_1406_7803_amd import driver
+    s = fde_synth.config1()
+    e1 = driver.Engine(s, prec=prec, backend=be, streams=1)
+    e2 = driver.Engine(s, prec=prec, backend=be, streams=2)
+    eg = driver.Engine(s, prec=prec, backend=be, streams=2)
+    assert len(e1.groups) == 1 and len(e2.groups) == 2
+    eg.capture()
+    e1.cycle()
+    e2.cycle()
+    for k in range(3):
+        e1.cycle()
+        e2.cycle()
+        eg.replay()
+        be.sync()
+        for a, b, c in zip(e1.eps, e2.eps, eg.eps):
+            assert np.array_equal(pc.host(a), pc.host(b)), k
+            assert np.array_equal(pc.host(a), pc.host(c)), k
+        assert np.array_equal(pc.host(e1.rho_in), pc.host(e2.rho_in)), k
+        assert np.array_equal(pc.host(e1.rho_in), pc.host(eg.rho_in)), k
