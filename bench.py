@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
     ap.add_argument("--no-tta", action="store_true", help="skip the time-to-1e-6 Ha comparison")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--streams", type=int, default=3, help="concurrent band-solver groups")
     ap.add_argument("--gemm", choices=["fp64", "bf16x3", "bf16x6"], default="fp64",
                     help="arithmetic of the Rayleigh-Ritz subspace products (FP32 plan)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -201,7 +202,7 @@ def main():
     system = fde_synth.config2()
     print("# building engine", file=sys.stderr, flush=True)
     gemm = {"fp64": fde.GEMM_FP64, "bf16x3": fde.GEMM_BF16X3, "bf16x6": fde.GEMM_BF16X6}[a.gemm]
-    eng = driver.Engine(system, prec=prec, backend=be, gemm=gemm)
+    eng = driver.Engine(system, prec=prec, backend=be, gemm=gemm, streams=a.streams)
     torch.cuda.synchronize()
     print("# engine ready", file=sys.stderr, flush=True)
     tuned = None
@@ -283,6 +284,7 @@ def main():
                    "subspace_products": a.gemm, "launch": "eager" if a.eager else "one HIP graph per cycle",
                    "apply_bands_per_plane_workgroup": None if tuned is None else tuned["bpw"],
                    "z_sticks_per_workgroup": None if tuned is None else tuned["sz"],
+                   "solver_streams": len(eng.groups),
                    "parallelism": "single GPU"},
         "isolated_apply_h": {"band_applies_per_s": isolated, "bands": nb, "ms_per_call": t_apply * 1e3},
         "roofline": {"kernel": "fde_apply_h: FFT sandwich (KZInv, KPlaneHReg, KZFwd) + projectors "

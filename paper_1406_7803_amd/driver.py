@@ -59,7 +59,7 @@ class Engine:
     kinds: dict = field(default_factory=lambda: dict(xc=fde.XC_LDA, xc_nad=fde.XC_LDA, kin_nad=fde.KIN_LC94))
     mlp_params: Optional[torch.Tensor] = None   # learned preconditioner (FP32, FDE_MLP_NPARAM); None = TPA
     gemm: int = fde.GEMM_FP64                   # arithmetic of the Rayleigh-Ritz subspace products
-    streams: int = 2                            # band-solver groups run concurrently (GPU backend)
+    streams: int = 3                            # band-solver groups run concurrently (GPU backend)
 
     def __post_init__(self):
         s = self.system
