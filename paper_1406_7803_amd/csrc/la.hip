@@ -122,7 +122,8 @@ static fde_status rr_launch(fde_plan* p, ProbSet<T>& ps, hipStream_t s) {
   if (fixed + 2 * mbytes <= kLdsMax) mats = 2 * mbytes;
   else if (fixed + mbytes <= kLdsMax) mats = mbytes;
   if (mmax <= kRRLdsMax && KRRSolveTri<T>::lds_bytes(mmax, nbmax) <= kLdsMax)
-    FDE_TRY((launch<KRRSolveTri<T>, 1024>(dim3(ps.n), 1024, KRRSolveTri<T>::lds_bytes(mmax, nbmax), s, ps)));
+    FDE_TRY((launch<KRRSolveTri<T>, KRRSolveTri<T>::kThreads>(dim3(ps.n), KRRSolveTri<T>::kThreads,
+                                                                KRRSolveTri<T>::lds_bytes(mmax, nbmax), s, ps)));
   else if (mmax <= kRRLdsMax && KRRSolveLds<T>::lds_bytes(mmax) <= kLdsMax)
     FDE_TRY((launch<KRRSolveLds<T>, 1024>(dim3(ps.n), 1024, KRRSolveLds<T>::lds_bytes(mmax), s, ps)));
   else
