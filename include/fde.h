@@ -123,13 +123,16 @@ fde_status fde_plan_set_workspace(fde_plan* plan, void* d_ws, size_t bytes, int 
  * plane-pass workgroup of fde_apply_h (each workgroup reads one V_eff plane
  * for that many bands). FDE_TUNE_STICK_GROUP: z-sticks per workgroup of the
  * z-FFT passes of fde_apply_h and fde_density (a power of two, capped at 16
- * and by the LDS budget). 0 restores the automatic choice. The driver's
+ * and by the LDS budget; used by the LDS z-passes). FDE_TUNE_Z_REGISTER: 1
+ * keeps the LDS z-passes where a four-step register z-FFT exists (N3 = 240,
+ * 120). 0 restores the automatic choice. The driver's
  * autotuner times candidate values on the plan's own shapes and keeps the
  * fastest. Errors: FDE_ERR_ARG for an unknown key, a value outside [0, 1024]
  * or a stick group that is not a power of two.
  */
 #define FDE_TUNE_APPLY_BPW 1
 #define FDE_TUNE_STICK_GROUP 2
+#define FDE_TUNE_Z_REGISTER 3
 fde_status fde_plan_set_tuning(fde_plan* plan, int key, int value);
 
 #define FDE_GEMM_FP64 0

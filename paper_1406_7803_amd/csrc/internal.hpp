@@ -50,6 +50,7 @@ struct fde_plan {
   int gemm = 0;  // FDE_GEMM_* of the subspace products
   int tune_bpw = 0;  // bands per plane-pass workgroup of fde_apply_h (0: automatic)
   int tune_sz = 0;   // z-sticks per z-pass workgroup, power of two (0: automatic, at most 16)
+  int tune_zreg = 0; // z-passes: 0 four-step register FFT where specialised, 1 LDS passes always
   void* d_tw[3] = {nullptr, nullptr, nullptr};  // twiddles exp(-2 pi i m/N_a), plan precision
   char* scratch = nullptr;
   size_t scratch_bytes = 0;

@@ -128,6 +128,159 @@ struct KZFwd {
 };
 
 // ---------------------------------------------------------------------------
+// z-FFTs of length N3 = P Q in registers (four-step): the P threads of a stick each
+// transform the Q elements z = P n1 + n2 (own n2) in registers, apply the twiddle
+// W^{n2 k1}, exchange through LDS inside their wavefront, and transform the P values
+// of each row k1 (result X[k1 + Q k2]). One wavefront per workgroup, 64 / P sticks;
+// no workgroup barrier. grid (ceil(ncol / (64 / P)), nb). tw: the N3 twiddles.
+// ---------------------------------------------------------------------------
+template <typename T, int P, int Q>
+struct ZReg {
+  static constexpr int N = P * Q, SPW = 64 / P, RPT = (Q + P - 1) / P;  // rows per thread in step 2
+  FDE_HD static size_t lds_bytes() { return sizeof(cplx<T>) * (size_t)SPW * N; }
+  // step 1 for lane l: v = the stick's elements P n1 + n2 (filled by the caller), transformed,
+  // twiddled, written to buf [stick][k1][n2]
+  template <bool INV>
+  FDE_HD static void step1(cplx<T>* v, const cplx<T>* __restrict__ tw, cplx<T>* sbuf, int n2) {
+    reg_fft<T, INV, Q>(v, nullptr);
+#pragma unroll
+    for (int k1 = 1; k1 < Q; ++k1) {
+      const cplx<T> w = tw[(n2 * k1) % N];
+      v[k1] = INV ? cmulc(w, v[k1]) : w * v[k1];
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < Q; ++k1) sbuf[k1 * P + n2] = v[k1];
+  }
+  // step 2 for lane l: rows k1 = r, r + P, ... of the stick: u[j][k2] = X[k1 + Q k2]
+  template <bool INV>
+  FDE_HD static void step2(cplx<T> (&u)[RPT][P], const cplx<T>* sbuf, int r) {
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      const int k1 = r + P * j;
+      if (k1 < Q) {
+#pragma unroll
+        for (int n2 = 0; n2 < P; ++n2) u[j][n2] = sbuf[k1 * P + n2];
+        reg_fft<T, INV, P>(u[j], nullptr);
+      }
+    }
+  }
+};
+
+template <typename T, int P, int Q>
+struct KZInvReg {
+  using Z = ZReg<T, P, Q>;
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const cplx<T>* __restrict__ psi, int npw,
+                         const int4* __restrict__ sticks, int ncol, const cplx<T>* __restrict__ tw,
+                         cplx<T>* __restrict__ sb) {
+    constexpr int N = Z::N;
+    const int band = c.by();
+    const cplx<T>* pb = psi + (size_t)band * npw;
+    const int ncs = stick_stride(ncol);
+    cplx<T>* ob = sb + (size_t)band * N * ncs;
+    cplx<T>* buf = (cplx<T>*)lds;
+    for (int l = c.tid(); l < 64; l += c.nthr()) {
+      const int s = c.bx() * Z::SPW + l / P, n2 = l % P;
+      if (s >= ncol) continue;
+      const int4 st = sticks[s];
+      cplx<T> v[Q];
+#pragma unroll
+      for (int n1 = 0; n1 < Q; ++n1) {
+        const int t = imod(P * n1 + n2 - st.z, N);
+        v[n1] = t < st.y ? pb[st.x + t] : mk<T>(0, 0);
+      }
+      Z::template step1<true>(v, tw, buf + (l / P) * N, n2);
+    }
+    c.wsync();
+    for (int l = c.tid(); l < 64; l += c.nthr()) {
+      const int s = c.bx() * Z::SPW + l / P, r = l % P;
+      if (s >= ncol || r >= Q) continue;
+      cplx<T> u[Z::RPT][P];
+      Z::template step2<true>(u, buf + (l / P) * N, r);
+#pragma unroll
+      for (int j = 0; j < Z::RPT; ++j) {
+        const int k1 = r + P * j;
+        if (k1 < Q) {
+#pragma unroll
+          for (int k2 = 0; k2 < P; ++k2) ob[(size_t)(k1 + Q * k2) * ncs + s] = u[j][k2];
+        }
+      }
+    }
+  }
+};
+
+template <typename T, int P, int Q>
+struct KZFwdReg {
+  using Z = ZReg<T, P, Q>;
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const cplx<T>* __restrict__ sb, const cplx<T>* __restrict__ psi,
+                         cplx<T>* __restrict__ hpsi, int npw, const int4* __restrict__ sticks,
+                         const int* __restrict__ xlist, int ncol, int N1, int N2, const cplx<T>* __restrict__ tw,
+                         KVec kv, double invN) {
+    constexpr int N = Z::N;
+    const int band = c.by();
+    const int ncs = stick_stride(ncol);
+    const cplx<T>* ib = sb + (size_t)band * N * ncs;
+    cplx<T>* buf = (cplx<T>*)lds;
+    for (int l = c.tid(); l < 64; l += c.nthr()) {
+      const int s = c.bx() * Z::SPW + l / P, n2 = l % P;
+      if (s >= ncol) continue;
+      cplx<T> v[Q];
+#pragma unroll
+      for (int n1 = 0; n1 < Q; ++n1) v[n1] = ib[(size_t)(P * n1 + n2) * ncs + s];
+      Z::template step1<false>(v, tw, buf + (l / P) * N, n2);
+    }
+    c.wsync();
+    // every row of a stick is read before any lane of that stick overwrites the buffer
+    // (the serial host run keeps all 64 lanes' rows)
+#if defined(__HIP_DEVICE_COMPILE__)
+    constexpr int NL = 1;
+#else
+    constexpr int NL = 64;
+#endif
+    cplx<T> u[NL][Z::RPT][P];
+    for (int l = c.tid(); l < 64; l += c.nthr()) {
+      const int s = c.bx() * Z::SPW + l / P, r = l % P;
+      if (s >= ncol || r >= Q) continue;
+      Z::template step2<false>(u[NL == 1 ? 0 : l], buf + (l / P) * N, r);
+    }
+    c.wsync();
+    for (int l = c.tid(); l < 64; l += c.nthr()) {
+      const int s = c.bx() * Z::SPW + l / P, r = l % P;
+      if (s >= ncol || r >= Q) continue;
+      cplx<T>* sbuf = buf + (l / P) * N;
+#pragma unroll
+      for (int j = 0; j < Z::RPT; ++j) {
+        const int k1 = r + P * j;
+        if (k1 < Q) {
+#pragma unroll
+          for (int k2 = 0; k2 < P; ++k2) sbuf[k1 + Q * k2] = u[NL == 1 ? 0 : l][j][k2];
+        }
+      }
+    }
+    c.wsync();
+    // gather of the sphere, 1/N and the kinetic term
+    const cplx<T>* pb = psi + (size_t)band * npw;
+    cplx<T>* hb = hpsi + (size_t)band * npw;
+    for (int l = c.tid(); l < 64; l += c.nthr()) {
+      const int s = c.bx() * Z::SPW + l / P, n2 = l % P;
+      if (s >= ncol) continue;
+      const int4 st = sticks[s];
+      const cplx<T>* sbuf = buf + (l / P) * N;
+      const int m1 = centred(xlist[st.w & 0xffff], N1);
+      const int m2 = centred(st.w >> 16, N2);
+      for (int t = n2; t < st.y; t += P) {
+        const int g = st.x + t;
+        const T kin = (T)kin_of(kv, m1, m2, st.z + t);
+        const cplx<T> v = sbuf[imod(st.z + t, N)];
+        const cplx<T> p = pb[g];
+        hb[g] = mk<T>((T)invN * v.x + kin * p.x, (T)invN * v.y + kin * p.y);
+      }
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
 // Plane pass, shared by H application and density. Layout in LDS:
 //   P0, P1 : [N2][nxa]   the active x-columns of the plane (ping-pong)
 //   R0, R1 : [RB][N1]    a batch of full rows (ping-pong)

@@ -22,6 +22,30 @@ static KVec kvec(const fde_plan* p, int ik) {
   return k;
 }
 
+// z-passes with the four-step register FFT where N3 = P Q is specialised (240 = 16 x 15,
+// 120 = 8 x 15) and not switched off by tuning; the LDS Stockham passes otherwise.
+template <typename T, int P, int Q>
+static fde_status z_inv_reg(const KTables& t, int nbc, const cplx<T>* ps, const cplx<T>* tw3, cplx<T>* sb,
+                            hipStream_t s) {
+  using Z = ZReg<T, P, Q>;
+  return launch<KZInvReg<T, P, Q>, 64>(dim3((t.ncol + Z::SPW - 1) / Z::SPW, nbc), 64, Z::lds_bytes(), s, ps, t.npw,
+                                       (const int4*)t.d_sticks, t.ncol, tw3, sb);
+}
+
+template <typename T, int P, int Q>
+static fde_status z_fwd_reg(const fde_plan* p, const KTables& t, int nbc, const cplx<T>* sb, const cplx<T>* ps,
+                            cplx<T>* hs, const cplx<T>* tw3, KVec kv, double invN, hipStream_t s) {
+  using Z = ZReg<T, P, Q>;
+  return launch<KZFwdReg<T, P, Q>, 64>(dim3((t.ncol + Z::SPW - 1) / Z::SPW, nbc), 64, Z::lds_bytes(), s, sb, ps, hs,
+                                       t.npw, (const int4*)t.d_sticks, (const int*)t.d_xlist, t.ncol, p->N[0],
+                                       p->N[1], tw3, kv, invN);
+}
+
+static int z_reg_kind(const fde_plan* p) {
+  if (p->tune_zreg == 1) return 0;
+  return p->N[2] == 240 ? 1 : (p->N[2] == 120 ? 2 : 0);
+}
+
 // Threads of a z-pass workgroup: one wavefront per stick up to kBlock.
 static int zthreads(int SZ) { return std::min(kBlock, 64 * SZ); }
 
@@ -98,8 +122,14 @@ static fde_status apply_h_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, cpl
     const cplx<T>* ps = psi + (size_t)b0 * t.npw;
     cplx<T>* hs = hpsi + (size_t)b0 * t.npw;
     const unsigned ngz = (unsigned)((t.ncol + SZ - 1) / SZ);
-    FDE_TRY(launch<KZInv<T>>(dim3(ngz, nbc), zthreads(SZ), zlds, s, ps, t.npw, (const int4*)t.d_sticks, t.ncol,
-                             p->rad[2], tw3, sb, SZ));
+    const int zk = z_reg_kind(p);
+    if (zk == 1)
+      FDE_TRY((z_inv_reg<T, 16, 15>(t, nbc, ps, tw3, sb, s)));
+    else if (zk == 2)
+      FDE_TRY((z_inv_reg<T, 8, 15>(t, nbc, ps, tw3, sb, s)));
+    else
+      FDE_TRY(launch<KZInv<T>>(dim3(ngz, nbc), zthreads(SZ), zlds, s, ps, t.npw, (const int4*)t.d_sticks, t.ncol,
+                               p->rad[2], tw3, sb, SZ));
     if (reg_plane) {
       // about two workgroups (one wave each) per SIMD over the whole chip, unless tuned
       const int BPW = p->tune_bpw > 0 ? std::min(nbc, p->tune_bpw) : std::max(1, std::min(nbc, (N3 * nbc) / 4096));
@@ -116,9 +146,14 @@ static fde_status apply_h_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, cpl
                                  (const int4*)t.d_sticks, (const int*)t.d_xlist, t.ncol, t.nxa, p->rad[0], p->rad[1],
                                  N3, tw1, tw2, veff, RB));
     }
-    FDE_TRY(launch<KZFwd<T>>(dim3(ngz, nbc), zthreads(SZ), zlds, s, (const cplx<T>*)sb, ps, hs, t.npw,
-                             (const int4*)t.d_sticks, (const int*)t.d_xlist, t.ncol, N1, N2, p->rad[2], tw3, kv, invN,
-                             SZ));
+    if (zk == 1)
+      FDE_TRY((z_fwd_reg<T, 16, 15>(p, t, nbc, sb, ps, hs, tw3, kv, invN, s)));
+    else if (zk == 2)
+      FDE_TRY((z_fwd_reg<T, 8, 15>(p, t, nbc, sb, ps, hs, tw3, kv, invN, s)));
+    else
+      FDE_TRY(launch<KZFwd<T>>(dim3(ngz, nbc), zthreads(SZ), zlds, s, (const cplx<T>*)sb, ps, hs, t.npw,
+                               (const int4*)t.d_sticks, (const int*)t.d_xlist, t.ncol, N1, N2, p->rad[2], tw3, kv,
+                               invN, SZ));
     if (nproj > 0) {
       FDE_TRY(kb_project<T>(beta, ps, t.npw, nproj, nbc, nchunk, part, s));
       FDE_TRY(launch<KKbReduce<T>>(dim3((nproj * nbc + KKbReduce<T>::NO - 1) / KKbReduce<T>::NO), kBlock,
@@ -156,8 +191,14 @@ static fde_status density_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, con
   for (int b0 = 0; b0 < nb; b0 += p->max_nb) {
     const int nbc = std::min(p->max_nb, nb - b0);
     const unsigned ngz = (unsigned)((t.ncol + SZ - 1) / SZ);
-    FDE_TRY(launch<KZInv<T>>(dim3(ngz, nbc), zthreads(SZ), zlds, s, psi + (size_t)b0 * t.npw, t.npw,
-                             (const int4*)t.d_sticks, t.ncol, p->rad[2], tw3, sb, SZ));
+    const int zk = z_reg_kind(p);
+    if (zk == 1)
+      FDE_TRY((z_inv_reg<T, 16, 15>(t, nbc, psi + (size_t)b0 * t.npw, tw3, sb, s)));
+    else if (zk == 2)
+      FDE_TRY((z_inv_reg<T, 8, 15>(t, nbc, psi + (size_t)b0 * t.npw, tw3, sb, s)));
+    else
+      FDE_TRY(launch<KZInv<T>>(dim3(ngz, nbc), zthreads(SZ), zlds, s, psi + (size_t)b0 * t.npw, t.npw,
+                               (const int4*)t.d_sticks, t.ncol, p->rad[2], tw3, sb, SZ));
     const int ngroups = std::min(4, nbc);
     const int BPW = (nbc + ngroups - 1) / ngroups;
     const int ng = (nbc + BPW - 1) / BPW;
@@ -402,6 +443,10 @@ fde_status fde_plan_set_tuning(fde_plan* p, int key, int value) {
   if (value < 0 || value > 1024) return fail(FDE_ERR_ARG, "tuning value out of range");
   switch (key) {
     case FDE_TUNE_APPLY_BPW: p->tune_bpw = value; return FDE_OK;
+    case FDE_TUNE_Z_REGISTER:
+      if (value > 1) return fail(FDE_ERR_ARG, "z-pass register FFT switch must be 0 or 1");
+      p->tune_zreg = value;
+      return FDE_OK;
     case FDE_TUNE_STICK_GROUP:
       if ((value & (value - 1)) != 0) return fail(FDE_ERR_ARG, "sticks per workgroup must be 0 or a power of two");
       p->tune_sz = value;

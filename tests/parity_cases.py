@@ -313,6 +313,15 @@ def check_apply_h_grid(be, prec, grid, spacing=0.3, ecut=3.0, nb=2, kf=(0.25, -0
     assert rel(host(out), ref) < TOL[prec], rel(host(out), ref)
     rref = odens.density(cell, sph, psi, occw)
     assert rel(host(rho), rref) < TOL[prec]
+    # z-passes through LDS instead of the four-step register FFT (where one exists)
+    plan.set_tuning(fde.TUNE_Z_REGISTER, 1)
+    out2 = plan.apply_h(0, to_dev(plan, psi, "c"), to_dev(plan, veff, "r"))
+    rho2 = plan.zeros_grid()
+    plan.density(0, to_dev(plan, psi, "c"), to_dev(plan, occw, "d"), rho2)
+    be.sync()
+    plan.set_tuning(fde.TUNE_Z_REGISTER, 0)
+    assert rel(host(out2), ref) < TOL[prec]
+    assert rel(host(rho2), rref) < TOL[prec]
 
 
 
