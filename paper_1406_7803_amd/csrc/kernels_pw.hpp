@@ -192,11 +192,13 @@ struct KZInvReg {
       Z::template step1<true>(v, tw, buf + (l / P) * N, n2);
     }
     c.wsync();
+    // sticks fastest along the lanes for the stores (adjacent lanes write one row segment)
     for (int l = c.tid(); l < 64; l += c.nthr()) {
-      const int s = c.bx() * Z::SPW + l / P, r = l % P;
+      const int sl = l % Z::SPW, r = l / Z::SPW;
+      const int s = c.bx() * Z::SPW + sl;
       if (s >= ncol || r >= Q) continue;
       cplx<T> u[Z::RPT][P];
-      Z::template step2<true>(u, buf + (l / P) * N, r);
+      Z::template step2<true>(u, buf + sl * N, r);
 #pragma unroll
       for (int j = 0; j < Z::RPT; ++j) {
         const int k1 = r + P * j;
@@ -222,13 +224,16 @@ struct KZFwdReg {
     const int ncs = stick_stride(ncol);
     const cplx<T>* ib = sb + (size_t)band * N * ncs;
     cplx<T>* buf = (cplx<T>*)lds;
+    // sticks fastest along the lanes: lanes reading one stick row are adjacent, so a load
+    // instruction fetches whole row segments of the wavefront's sticks
     for (int l = c.tid(); l < 64; l += c.nthr()) {
-      const int s = c.bx() * Z::SPW + l / P, n2 = l % P;
+      const int sl = l % Z::SPW, n2 = l / Z::SPW;
+      const int s = c.bx() * Z::SPW + sl;
       if (s >= ncol) continue;
       cplx<T> v[Q];
 #pragma unroll
       for (int n1 = 0; n1 < Q; ++n1) v[n1] = ib[(size_t)(P * n1 + n2) * ncs + s];
-      Z::template step1<false>(v, tw, buf + (l / P) * N, n2);
+      Z::template step1<false>(v, tw, buf + sl * N, n2);
     }
     c.wsync();
     // every row of a stick is read before any lane of that stick overwrites the buffer
