@@ -131,13 +131,15 @@ struct KZFwd {
 // z-FFTs of length N3 = P Q in registers (four-step): the P threads of a stick each
 // transform the Q elements z = P n1 + n2 (own n2) in registers, apply the twiddle
 // W^{n2 k1}, exchange through LDS inside their wavefront, and transform the P values
-// of each row k1 (result X[k1 + Q k2]). One wavefront per workgroup, 64 / P sticks;
-// no workgroup barrier. grid (ceil(ncol / (64 / P)), nb). tw: the N3 twiddles.
+// of each row k1 (result X[k1 + Q k2]). 64 / P sticks per wavefront, four wavefronts per
+// workgroup; no workgroup barrier. grid (ceil(ncol / (256 / P)), nb). tw: the N3 twiddles.
 // ---------------------------------------------------------------------------
 template <typename T, int P, int Q>
 struct ZReg {
-  static constexpr int N = P * Q, SPW = 64 / P, RPT = (Q + P - 1) / P;  // rows per thread in step 2
-  FDE_HD static size_t lds_bytes() { return sizeof(cplx<T>) * (size_t)SPW * N; }
+  // sticks per wavefront, rows per thread in step 2, wavefronts per block (the block's
+  // 4 SPW consecutive sticks share cache lines of the stick buffer, so they stay on one CU)
+  static constexpr int N = P * Q, SPW = 64 / P, RPT = (Q + P - 1) / P, WPB = 4, SPB = WPB * SPW;
+  FDE_HD static size_t lds_bytes() { return sizeof(cplx<T>) * (size_t)SPB * N; }
   // step 1 for lane l: v = the stick's elements P n1 + n2 (filled by the caller), transformed,
   // twiddled, written to buf [stick][k1][n2]
   template <bool INV>
@@ -179,8 +181,10 @@ struct KZInvReg {
     const int ncs = stick_stride(ncol);
     cplx<T>* ob = sb + (size_t)band * N * ncs;
     cplx<T>* buf = (cplx<T>*)lds;
-    for (int l = c.tid(); l < 64; l += c.nthr()) {
-      const int s = c.bx() * Z::SPW + l / P, n2 = l % P;
+    for (int q = c.tid(); q < 64 * Z::WPB; q += c.nthr()) {
+      const int w = q >> 6, l = q & 63;
+      const int s0 = (c.bx() * Z::WPB + w) * Z::SPW;  // this wavefront's first stick
+      const int s = s0 + l / P, n2 = l % P;
       if (s >= ncol) continue;
       const int4 st = sticks[s];
       cplx<T> v[Q];
@@ -189,16 +193,17 @@ struct KZInvReg {
         const int t = imod(P * n1 + n2 - st.z, N);
         v[n1] = t < st.y ? pb[st.x + t] : mk<T>(0, 0);
       }
-      Z::template step1<true>(v, tw, buf + (l / P) * N, n2);
+      Z::template step1<true>(v, tw, buf + (w * Z::SPW + l / P) * N, n2);
     }
     c.wsync();
     // sticks fastest along the lanes for the stores (adjacent lanes write one row segment)
-    for (int l = c.tid(); l < 64; l += c.nthr()) {
+    for (int q = c.tid(); q < 64 * Z::WPB; q += c.nthr()) {
+      const int w = q >> 6, l = q & 63;
       const int sl = l % Z::SPW, r = l / Z::SPW;
-      const int s = c.bx() * Z::SPW + sl;
+      const int s = (c.bx() * Z::WPB + w) * Z::SPW + sl;
       if (s >= ncol || r >= Q) continue;
       cplx<T> u[Z::RPT][P];
-      Z::template step2<true>(u, buf + sl * N, r);
+      Z::template step2<true>(u, buf + (w * Z::SPW + sl) * N, r);
 #pragma unroll
       for (int j = 0; j < Z::RPT; ++j) {
         const int k1 = r + P * j;
@@ -226,40 +231,43 @@ struct KZFwdReg {
     cplx<T>* buf = (cplx<T>*)lds;
     // sticks fastest along the lanes: lanes reading one stick row are adjacent, so a load
     // instruction fetches whole row segments of the wavefront's sticks
-    for (int l = c.tid(); l < 64; l += c.nthr()) {
+    for (int q = c.tid(); q < 64 * Z::WPB; q += c.nthr()) {
+      const int w = q >> 6, l = q & 63;
       const int sl = l % Z::SPW, n2 = l / Z::SPW;
-      const int s = c.bx() * Z::SPW + sl;
+      const int s = (c.bx() * Z::WPB + w) * Z::SPW + sl;
       if (s >= ncol) continue;
       cplx<T> v[Q];
 #pragma unroll
       for (int n1 = 0; n1 < Q; ++n1) v[n1] = ib[(size_t)(P * n1 + n2) * ncs + s];
-      Z::template step1<false>(v, tw, buf + sl * N, n2);
+      Z::template step1<false>(v, tw, buf + (w * Z::SPW + sl) * N, n2);
     }
     c.wsync();
     // every row of a stick is read before any lane of that stick overwrites the buffer
-    // (the serial host run keeps all 64 lanes' rows)
+    // (the serial host run keeps all lanes' rows)
 #if defined(__HIP_DEVICE_COMPILE__)
     constexpr int NL = 1;
 #else
-    constexpr int NL = 64;
+    constexpr int NL = 64 * Z::WPB;
 #endif
     cplx<T> u[NL][Z::RPT][P];
-    for (int l = c.tid(); l < 64; l += c.nthr()) {
-      const int s = c.bx() * Z::SPW + l / P, r = l % P;
+    for (int q = c.tid(); q < 64 * Z::WPB; q += c.nthr()) {
+      const int w = q >> 6, l = q & 63;
+      const int s = (c.bx() * Z::WPB + w) * Z::SPW + l / P, r = l % P;
       if (s >= ncol || r >= Q) continue;
-      Z::template step2<false>(u[NL == 1 ? 0 : l], buf + (l / P) * N, r);
+      Z::template step2<false>(u[NL == 1 ? 0 : q], buf + (w * Z::SPW + l / P) * N, r);
     }
     c.wsync();
-    for (int l = c.tid(); l < 64; l += c.nthr()) {
-      const int s = c.bx() * Z::SPW + l / P, r = l % P;
+    for (int q = c.tid(); q < 64 * Z::WPB; q += c.nthr()) {
+      const int w = q >> 6, l = q & 63;
+      const int s = (c.bx() * Z::WPB + w) * Z::SPW + l / P, r = l % P;
       if (s >= ncol || r >= Q) continue;
-      cplx<T>* sbuf = buf + (l / P) * N;
+      cplx<T>* sbuf = buf + (w * Z::SPW + l / P) * N;
 #pragma unroll
       for (int j = 0; j < Z::RPT; ++j) {
         const int k1 = r + P * j;
         if (k1 < Q) {
 #pragma unroll
-          for (int k2 = 0; k2 < P; ++k2) sbuf[k1 + Q * k2] = u[NL == 1 ? 0 : l][j][k2];
+          for (int k2 = 0; k2 < P; ++k2) sbuf[k1 + Q * k2] = u[NL == 1 ? 0 : q][j][k2];
         }
       }
     }
@@ -267,11 +275,12 @@ struct KZFwdReg {
     // gather of the sphere, 1/N and the kinetic term
     const cplx<T>* pb = psi + (size_t)band * npw;
     cplx<T>* hb = hpsi + (size_t)band * npw;
-    for (int l = c.tid(); l < 64; l += c.nthr()) {
-      const int s = c.bx() * Z::SPW + l / P, n2 = l % P;
+    for (int q = c.tid(); q < 64 * Z::WPB; q += c.nthr()) {
+      const int w = q >> 6, l = q & 63;
+      const int s = (c.bx() * Z::WPB + w) * Z::SPW + l / P, n2 = l % P;
       if (s >= ncol) continue;
       const int4 st = sticks[s];
-      const cplx<T>* sbuf = buf + (l / P) * N;
+      const cplx<T>* sbuf = buf + (w * Z::SPW + l / P) * N;
       const int m1 = centred(xlist[st.w & 0xffff], N1);
       const int m2 = centred(st.w >> 16, N2);
       for (int t = n2; t < st.y; t += P) {

@@ -28,17 +28,18 @@ template <typename T, int P, int Q>
 static fde_status z_inv_reg(const KTables& t, int nbc, const cplx<T>* ps, const cplx<T>* tw3, cplx<T>* sb,
                             hipStream_t s) {
   using Z = ZReg<T, P, Q>;
-  return launch<KZInvReg<T, P, Q>, 64>(dim3((t.ncol + Z::SPW - 1) / Z::SPW, nbc), 64, Z::lds_bytes(), s, ps, t.npw,
-                                       (const int4*)t.d_sticks, t.ncol, tw3, sb);
+  return launch<KZInvReg<T, P, Q>, 64 * Z::WPB>(dim3((t.ncol + Z::SPB - 1) / Z::SPB, nbc), 64 * Z::WPB,
+                                                Z::lds_bytes(), s, ps, t.npw, (const int4*)t.d_sticks, t.ncol, tw3,
+                                                sb);
 }
 
 template <typename T, int P, int Q>
 static fde_status z_fwd_reg(const fde_plan* p, const KTables& t, int nbc, const cplx<T>* sb, const cplx<T>* ps,
                             cplx<T>* hs, const cplx<T>* tw3, KVec kv, double invN, hipStream_t s) {
   using Z = ZReg<T, P, Q>;
-  return launch<KZFwdReg<T, P, Q>, 64>(dim3((t.ncol + Z::SPW - 1) / Z::SPW, nbc), 64, Z::lds_bytes(), s, sb, ps, hs,
-                                       t.npw, (const int4*)t.d_sticks, (const int*)t.d_xlist, t.ncol, p->N[0],
-                                       p->N[1], tw3, kv, invN);
+  return launch<KZFwdReg<T, P, Q>, 64 * Z::WPB>(dim3((t.ncol + Z::SPB - 1) / Z::SPB, nbc), 64 * Z::WPB,
+                                                Z::lds_bytes(), s, sb, ps, hs, t.npw, (const int4*)t.d_sticks,
+                                                (const int*)t.d_xlist, t.ncol, p->N[0], p->N[1], tw3, kv, invN);
 }
 
 static int z_reg_kind(const fde_plan* p) {
