@@ -283,7 +283,7 @@ def main():
                    "band_applies_per_cycle": per_cycle, "davidson_per_cycle": system.n_david,
                    "subspace_products": a.gemm, "launch": "eager" if a.eager else "one HIP graph per cycle",
                    "apply_bands_per_plane_workgroup": None if tuned is None else tuned["bpw"],
-                   "z_sticks_per_workgroup": None if tuned is None else tuned["sz"],
+                   "z_pass": "four-step register FFT" if system.grid[2] in (240, 120) else "LDS Stockham",
                    "solver_streams": len(eng.groups),
                    "parallelism": "single GPU"},
         "isolated_apply_h": {"band_applies_per_s": isolated, "bands": nb, "ms_per_call": t_apply * 1e3},

@@ -242,11 +242,12 @@ class Engine:
         self._graph.replay()
 
     # ---- launch-shape autotuning ----------------------------------------------
-    def autotune(self, candidates=(1, 2, 4, 8, 16), sz_candidates=(1, 2, 4, 8, 16), reps: int = 5):
+    def autotune(self, candidates=(1, 2, 4, 8, 16), sz_candidates=None, reps: int = 5):
         """Time fde_apply_h of the largest band block with each bands-per-plane-
-        workgroup value, then with each z-sticks-per-workgroup value, and keep the
-        fastest of each (launch shapes only; results unchanged). Returns
-        {"bpw": best, "bpw_ms": {value: ms}, "sz": best, "sz_ms": {value: ms}}."""
+        workgroup value, then (on grids without a register z-FFT) with each
+        z-sticks-per-workgroup value, and keep the fastest of each (launch shapes only;
+        results unchanged). Returns {"bpw": best, "bpw_ms": {value: ms}, "sz": best or
+        None, "sz_ms": {value: ms}}."""
         if self.be.emulated:
             return None
         b = max((b for row in self.blocks for b in row), key=lambda b: b.nb * self.plan.npw(b.ik))
@@ -275,7 +276,9 @@ class Engine:
             return best, times
 
         bpw, bpw_ms = search(fde.TUNE_APPLY_BPW, [v for v in candidates if v <= b.nb])
-        sz, sz_ms = search(fde.TUNE_STICK_GROUP, sz_candidates)
+        if sz_candidates is None:  # the stick group only shapes the LDS z-passes
+            sz_candidates = () if self.system.grid[2] in (240, 120) else (1, 2, 4, 8, 16)
+        sz, sz_ms = search(fde.TUNE_STICK_GROUP, sz_candidates) if sz_candidates else (None, {})
         return {"bpw": bpw, "bpw_ms": bpw_ms, "sz": sz, "sz_ms": sz_ms}
 
     def band_applies_per_cycle(self, n_david: Optional[int] = None) -> int:
