@@ -90,6 +90,8 @@ hipError_t allow_lds(const void* kernel, size_t bytes);
 constexpr int kBlock = 256;
 // plane waves per partial-sum chunk of the projector products beta^H psi
 constexpr int kKbChunk = 128;
+// band groups of the density plane pass (partial density planes, summed in a fixed order)
+constexpr int kRhoGroups = 8;
 constexpr size_t kLdsMax = 160 * 1024;
 
 }  // namespace fde

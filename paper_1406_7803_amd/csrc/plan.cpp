@@ -112,7 +112,7 @@ size_t scratch_apply(const fde_plan* p, int max_nb, int max_nproj) {
 
 size_t scratch_density(const fde_plan* p, int max_nb) {
   size_t s = align256((size_t)max_nb * p->N[2] * stick_stride(p->ncol_max) * p->csize());
-  s += align256((size_t)4 * p->npts() * p->rsize());
+  s += align256((size_t)kRhoGroups * p->npts() * p->rsize());
   return s;
 }
 

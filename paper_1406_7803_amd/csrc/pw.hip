@@ -200,7 +200,7 @@ static fde_status density_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, con
     else
       FDE_TRY(launch<KZInv<T>>(dim3(ngz, nbc), zthreads(SZ), zlds, s, psi + (size_t)b0 * t.npw, t.npw,
                                (const int4*)t.d_sticks, t.ncol, p->rad[2], tw3, sb, SZ));
-    const int ngroups = std::min(4, nbc);
+    const int ngroups = std::min(kRhoGroups, nbc);
     const int BPW = (nbc + ngroups - 1) / ngroups;
     const int ng = (nbc + BPW - 1) / BPW;
     if (reg_plane && cls == 0)
