@@ -1,6 +1,7 @@
 // Host entry points of the band-solver kernels: fde_subspace_rr(_batched),
 // fde_precondition(_batched), fde_occupations.
 #include <algorithm>
+#include <vector>
 
 #include "kernels_gemm.hpp"
 #include "kernels_la.hpp"
@@ -146,11 +147,22 @@ static fde_status rr_launch(fde_plan* p, ProbSet<T>& ps, hipStream_t s) {
 }
 
 template <typename T>
-static fde_status rr_batched_t(fde_plan* p, int nblk, const fde_block* blk, double drop_tol, hipStream_t s) {
+static fde_status rr_batched_t(fde_plan* p, int nblk, const fde_block* blk_in, double drop_tol, hipStream_t s) {
+  // launches take the kernels of their largest block: blocks that fit the LDS solvers
+  // (m <= kRRLdsMax) are batched apart from the larger ones, order kept within each kind
+  std::vector<fde_block> sorted;
+  sorted.reserve(nblk);
+  for (int pass = 0; pass < 2; ++pass)
+    for (int i = 0; i < nblk; ++i)
+      if ((blk_in[i].m <= kRRLdsMax) == (pass == 0)) sorted.push_back(blk_in[i]);
+  const fde_block* blk = sorted.data();
+  const int nsmall = (int)std::count_if(blk_in, blk_in + nblk, [](const fde_block& b) { return b.m <= kRRLdsMax; });
   const int per = std::min(kMaxBatch, p->max_batch);
-  for (int b0 = 0; b0 < nblk; b0 += per) {
+  for (int b0 = 0; b0 < nblk;) {
     ProbSet<T> ps;
-    ps.n = std::min(per, nblk - b0);
+    // a batch never mixes the two kinds
+    const int kind_end = b0 < nsmall ? nsmall : nblk;
+    ps.n = std::min(per, kind_end - b0);
     // the split products carry relative noise of about 2^-16 (BF16x3) or 2^-24 (BF16x6): a smaller
     // Cholesky pivot than ten times that is indistinguishable from a dependent column
     const double floor_tol = p->gemm == FDE_GEMM_BF16X3 ? 2e-4 : (p->gemm == FDE_GEMM_BF16X6 ? 1e-6 : 0.0);
@@ -161,6 +173,7 @@ static fde_status rr_batched_t(fde_plan* p, int nblk, const fde_block* blk, doub
       bind_scratch<T>(p, i, ps.p[i]);
     }
     FDE_TRY(rr_launch<T>(p, ps, s));
+    b0 += ps.n;
   }
   return FDE_OK;
 }
