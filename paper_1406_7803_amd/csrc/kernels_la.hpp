@@ -76,17 +76,14 @@ struct KRRSolve {
   // staged in LDS when they fit in `lds_mats` bytes (A~ first, then W).
   FDE_HD static size_t lds_fixed(int m) { return sizeof(double) * (32 + 4 * ((m + 2) / 2 + 1)); }
 
+  // Masks, Cholesky with dropping, B = L^{-1} A, A~ = L^{-1} B^H (in a.A), all in global memory.
+  // Returns false, with C = I, NaN eigenvalues and info written, when a band column has no
+  // positive pivot.
   template <class Ctx>
-  FDE_HD static void run(const Ctx& c, char* lds, const ProbSet<T> ps, size_t lds_mats) {
-    const Prob<T>& a = ps.p[c.bx()];
-    double* red = (double*)lds;            // 17 used
-    double* rot = red + 32;                // [4][mp/2]
+  FDE_HD static bool front(const Ctx& c, double* red, const Prob<T>& a, double drop_tol) {
     const int m = a.m, nb = a.nb;
     const int tid = c.tid(), nt = c.nthr();
-    cplx<double>*S = a.S, *A = a.A, *L = a.L, *B = a.B, *W = a.W;
-    const double drop_tol = ps.drop_tol;
-    char* mats = lds + ((lds_fixed(m) + 15) & ~(size_t)15);
-    const size_t mbytes = (size_t)m * m * sizeof(cplx<double>);
+    cplx<double>*S = a.S, *A = a.A, *L = a.L, *B = a.B;
     if (tid == 0) a.info[0] = 0;
     // ---- masks
     for (int j = tid; j < m; j += nt) a.masked[j] = (a.active && !a.active[j]) ? 1 : 0;
@@ -135,7 +132,7 @@ struct KRRSolve {
         }
         for (int n = tid; n < nb; n += nt) a.eval[n] = 0.0 / 0.0;
         c.sync();
-        return;  // uniform: every thread saw the same d
+        return false;  // uniform: every thread saw the same d
       }
       const double ljj = sqrt(d);
       if (tid == 0) L[(size_t)j * m + j] = mk<double>(ljj, 0.0);
@@ -168,6 +165,21 @@ struct KRRSolve {
       }
     }
     c.sync();
+    return true;
+  }
+
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const ProbSet<T> ps, size_t lds_mats) {
+    const Prob<T>& a = ps.p[c.bx()];
+    double* red = (double*)lds;            // 17 used
+    double* rot = red + 32;                // [4][mp/2]
+    const int m = a.m, nb = a.nb;
+    const int tid = c.tid(), nt = c.nthr();
+    cplx<double>*S = a.S, *A = a.A, *L = a.L, *B = a.B, *W = a.W;
+    const double drop_tol = ps.drop_tol;
+    char* mats = lds + ((lds_fixed(m) + 15) & ~(size_t)15);
+    const size_t mbytes = (size_t)m * m * sizeof(cplx<double>);
+    if (!front(c, red, a, drop_tol)) return;
     // hermitise: A~ <- (A~ + A~^H)/2, staged into LDS when it fits
     cplx<double>* Aj = (mbytes <= lds_mats) ? (cplx<double>*)mats : A;
     cplx<double>* Wj = (2 * mbytes <= lds_mats) ? (cplx<double>*)(mats + mbytes) : W;

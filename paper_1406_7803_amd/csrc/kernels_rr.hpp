@@ -625,11 +625,13 @@ struct KRRSolveTri {
       }
       c.sync();
     }
+    // reflector vectors to their column-packed slots (through r1), diagonal to dg
     cplx<double>* P = (cplx<double>*)r1;
-    for (int k = 0; k + 1 < ma; ++k)
-      for (int r = 0; r < ma - k - 1; ++r) P[voff(k, ma) + r] = U[tri(k + 1 + r, k)];
-    for (int k = 0; k < ma; ++k) dg[k] = U[tri(k, k)].x;
-    for (int e = 0; e < ma * (ma - 1) / 2; ++e) U[e] = P[e];
+    for (int k = wv; k + 1 < ma; k += nwv)
+      for (int r = lane; r < ma - k - 1; r += wl) P[voff(k, ma) + r] = U[tri(k + 1 + r, k)];
+    for (int k = tid; k < ma; k += nt) dg[k] = U[tri(k, k)].x;
+    c.sync();
+    for (int e = tid; e < ma * (ma - 1) / 2; e += nt) U[e] = P[e];
     c.sync();
   }
 
@@ -796,44 +798,33 @@ struct KRRSolveTri {
   }
 #endif
 
-  template <class Ctx>
-  FDE_HD static void run(const Ctx& c, char* lds, const ProbSet<T> ps) {
-    const Prob<T>& a = ps.p[c.bx()];
-    const int m = a.m, nb = a.nb, ld = m + 1;
+  // Work areas of the eigen phases (tri_eigen): per-column arrays, the active-index map and
+  // cluster list, Sturm counts, a scratch area for the twisted factorisations and then the
+  // per-wavefront LU factors (stride lus), the tridiagonal eigenvectors Y [nw][ma], the
+  // column-packed reflectors V, the W^T rows out (stride ld) and the eigenvalues out.
+  struct TriWork {
+    double *dg, *e2, *ea, *beta, *ar, *ai, *dre, *dim, *lam, *lo, *hi;
+    int *act, *cls, *masked, *cnt;
+    char* lu;
+    size_t lus;
+    double* Y;
+    const cplx<double>* V;
+    cplx<double>* Wt;
+    int ld;
+    double* theta;
+  };
+
+  // Steps 3b-3e on the reduced active block (ma rows; dg, beta and alpha from the reduction):
+  // eigenvalues and eigenvectors of the lowest nb, W^T rows n < nb with physical row indices,
+  // masked rows zero, masked eigenpairs after the active ones. ZMAX bounds m.
+  template <int ZMAX, class Ctx>
+  FDE_HD static void tri_eigen(const Ctx& c, const TriWork& w, int m, int nb, int ma) {
     const int tid = c.tid(), nt = c.nthr();
     const int lane = c.lane(), wl = c.wlanes(), wv = c.wave(), nwv = c.nwave();
-    cplx<double>* U = (cplx<double>*)lds;
-    cplx<double>* M = U + (size_t)m * (m + 1) / 2;
-    double* red = (double*)((char*)M + mspan(m, nb));
-    double* sdiag = red + 32;
-    int* masked = (int*)(sdiag + m);
-    int* order = masked + m;
-    char* r1 = (char*)M;
-    double* Y = (double*)(r1 + r1_bytes(m, nb));
-    double* dg = (double*)((char*)Y + y_bytes(m, nb));
-    double *e2 = dg + m, *ea = e2 + m, *beta = ea + m, *ar = beta + m, *ai = ar + m, *dre = ai + m, *dim = dre + m;
-    double *lam = dim + m, *lo = lam + m, *hi = lo + m, *pbx = hi + m, *pby = pbx + m;
-    cplx<double>* xb = (cplx<double>*)(pby + m);  // [2][m]: the current column, double-buffered
-    int* act = (int*)(xb + 2 * m);
-    int* cls = act + m;  // cluster starts (m + 1 entries), then the active count and the cluster count
-    int* cnt = (int*)r1;
-
-    if (!rr_front<T>(c, a, ps.drop_tol, U, M, sdiag, masked)) return;
-    if (tid == 0) {
-      int k = 0;
-      for (int j = 0; j < m; ++j)
-        if (!masked[j]) act[k++] = j;
-      cls[m + 1] = k;
-    }
-    c.sync();
-    const int ma = cls[m + 1];
     const int nw = nb < ma ? nb : ma;
-    // ---- 3a. Householder reduction of the active part
-#if defined(__HIP_DEVICE_COMPILE__)
-    house_regs(c, U, r1, m, ma, act, dg, beta, ar, ai, xb, pbx, pby);
-#else
-    house_lds(c, U, r1, m, ma, act, dg, beta, ar, ai, pbx, pby);
-#endif
+    double *dg = w.dg, *e2 = w.e2, *ea = w.ea, *beta = w.beta, *ar = w.ar, *ai = w.ai, *dre = w.dre, *dim = w.dim;
+    double *lam = w.lam, *lo = w.lo, *hi = w.hi, *Y = w.Y;
+    int *act = w.act, *cls = w.cls, *masked = w.masked, *cnt = w.cnt;
     // ---- 3b. real tridiagonal (dg, ea) and the phases D
     for (int k = tid; k + 1 < ma; k += nt) {
       e2[k] = ar[k] * ar[k] + ai[k] * ai[k];
@@ -937,7 +928,7 @@ struct KRRSolveTri {
       for (int j = tid; j < nw; j += nt) {
         lo[j] = 1.0;  // 1: needs inverse iteration
         if (!single(j)) continue;
-        double* rp = (double*)r1 + (size_t)j * 2 * ma;  // 1 / D+_i
+        double* rp = (double*)w.lu + (size_t)j * 2 * ma;  // 1 / D+_i
         double* rm = rp + ma;                            // 1 / D-_i
         const double lj = lam[j];
         double q = dg[0] - lj;
@@ -987,7 +978,7 @@ struct KRRSolveTri {
       c.sync();
       // inverse iteration, one cluster (or failed single) per wavefront
       const int ncl = cls[m + 2];
-      double* lu = (double*)(r1 + (size_t)wv * lu_stride(m));
+      double* lu = (double*)(w.lu + (size_t)wv * w.lus);
       unsigned char* piv = (unsigned char*)(lu + 4 * ma);
       for (int ci = wv; ci < ncl; ci += nwv) {
         const int j0 = cls[ci], j1 = cls[ci + 1];
@@ -1028,11 +1019,12 @@ struct KRRSolveTri {
       // ---- 3e. W^T rows n < nw: z = D y, H_k z for k = ma - 2 .. 0 (z in registers, rows
       //      i = gl + GL s of each lane), written to the physical indices act[i], masked rows zero
 #if defined(__HIP_DEVICE_COMPILE__)
-      constexpr int GL = kGroup;
+      // a whole wavefront per vector once 16 lanes would need more than 16 rows each
+      constexpr int GL = ZMAX > 16 * kGroup ? 64 : kGroup;
 #else
       constexpr int GL = 1;
 #endif
-      constexpr int ZR = (kRRLdsMax + GL - 1) / GL;
+      constexpr int ZR = (ZMAX + GL - 1) / GL;
       const int ngrp = nt / GL, gl = tid % GL;
       for (int n = tid / GL; n < nw; n += ngrp) {
         const double* y = Y + (size_t)n * ma;
@@ -1045,13 +1037,13 @@ struct KRRSolveTri {
         for (int k = ma - 2; k >= 0; --k) {
           const double bt = beta[k];
           if (bt == 0.0) continue;
-          const int vo = voff(k, ma) - (k + 1);  // U[vo + i] = v_k for rows i = k + 1 .. ma - 1
+          const int vo = voff(k, ma) - (k + 1);  // V[vo + i] = v_k for rows i = k + 1 .. ma - 1
           double sx = 0.0, sy = 0.0;
 #pragma unroll
           for (int s = 0; s < ZR; ++s) {
             const int i = gl + GL * s;
             if (i > k && i < ma) {
-              const cplx<double> vi = U[vo + i];
+              const cplx<double> vi = w.V[vo + i];
               sx += vi.x * z[s].x + vi.y * z[s].y;
               sy += vi.x * z[s].y - vi.y * z[s].x;
             }
@@ -1062,20 +1054,20 @@ struct KRRSolveTri {
           for (int s = 0; s < ZR; ++s) {
             const int i = gl + GL * s;
             if (i > k && i < ma) {
-              const cplx<double> vi = U[vo + i];
+              const cplx<double> vi = w.V[vo + i];
               z[s].x -= vi.x * sx - vi.y * sy;
               z[s].y -= vi.x * sy + vi.y * sx;
             }
           }
         }
-        cplx<double>* w = M + (size_t)n * ld;
+        cplx<double>* wr = w.Wt + (size_t)n * w.ld;
 #pragma unroll
         for (int s = 0; s < ZR; ++s) {
           const int i = gl + GL * s;
-          if (i < ma) w[act[i]] = z[s];
+          if (i < ma) wr[act[i]] = z[s];
         }
         for (int p = gl; p < m; p += GL)
-          if (masked[p]) w[p] = mk<double>(0.0, 0.0);
+          if (masked[p]) wr[p] = mk<double>(0.0, 0.0);
       }
     }
     // masked eigenpairs (A~ = kInactiveDiag e_p e_p^H) fill the columns beyond the active count
@@ -1083,13 +1075,123 @@ struct KRRSolveTri {
       int left = n - nw, p = 0;
       for (; p < m; ++p)
         if (masked[p] && left-- == 0) break;
-      cplx<double>* z = M + (size_t)n * ld;
+      cplx<double>* z = w.Wt + (size_t)n * w.ld;
       for (int i = 0; i < m; ++i) z[i] = mk<double>(i == p ? 1.0 : 0.0, 0.0);
-      a.theta[n] = kInactiveDiag;
+      w.theta[n] = kInactiveDiag;
     }
-    for (int n = tid; n < nw; n += nt) a.theta[n] = lam[n];
+    for (int n = tid; n < nw; n += nt) w.theta[n] = lam[n];
+  }
+
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const ProbSet<T> ps) {
+    const Prob<T>& a = ps.p[c.bx()];
+    const int m = a.m, nb = a.nb, ld = m + 1;
+    const int tid = c.tid(), nt = c.nthr();
+    const int lane = c.lane(), wl = c.wlanes(), wv = c.wave(), nwv = c.nwave();
+    cplx<double>* U = (cplx<double>*)lds;
+    cplx<double>* M = U + (size_t)m * (m + 1) / 2;
+    double* red = (double*)((char*)M + mspan(m, nb));
+    double* sdiag = red + 32;
+    int* masked = (int*)(sdiag + m);
+    int* order = masked + m;
+    char* r1 = (char*)M;
+    double* Y = (double*)(r1 + r1_bytes(m, nb));
+    double* dg = (double*)((char*)Y + y_bytes(m, nb));
+    double *e2 = dg + m, *ea = e2 + m, *beta = ea + m, *ar = beta + m, *ai = ar + m, *dre = ai + m, *dim = dre + m;
+    double *lam = dim + m, *lo = lam + m, *hi = lo + m, *pbx = hi + m, *pby = pbx + m;
+    cplx<double>* xb = (cplx<double>*)(pby + m);  // [2][m]: the current column, double-buffered
+    int* act = (int*)(xb + 2 * m);
+    int* cls = act + m;  // cluster starts (m + 1 entries), then the active count and the cluster count
+    int* cnt = (int*)r1;
+
+    if (!rr_front<T>(c, a, ps.drop_tol, U, M, sdiag, masked)) return;
+    if (tid == 0) {
+      int k = 0;
+      for (int j = 0; j < m; ++j)
+        if (!masked[j]) act[k++] = j;
+      cls[m + 1] = k;
+    }
+    c.sync();
+    const int ma = cls[m + 1];
+    const int nw = nb < ma ? nb : ma;
+    // ---- 3a. Householder reduction of the active part
+#if defined(__HIP_DEVICE_COMPILE__)
+    house_regs(c, U, r1, m, ma, act, dg, beta, ar, ai, xb, pbx, pby);
+#else
+    house_lds(c, U, r1, m, ma, act, dg, beta, ar, ai, pbx, pby);
+#endif
+    // ---- 3b-3e. tridiagonal eigenproblem and back-transformation
+    const TriWork tw{dg, e2, ea, beta, ar, ai, dre, dim, lam, lo, hi, act, cls, masked, cnt, r1, lu_stride(m), Y, U, M,
+                     ld, a.theta};
+    tri_eigen<kRRLdsMax>(c, tw, m, nb, ma);
     for (int n = tid; n < nb; n += nt) order[n] = n;
     rr_tail<T>(c, a, U, M, sdiag, order);
+  }
+};
+
+// Rayleigh-Ritz solve of one band block too large for the LDS solvers (kRRLdsMax < m <=
+// kRRTriMax), matrices in global memory: the front end of KRRSolve (Cholesky, A~), then the
+// tridiagonal route of KRRSolveTri on the packed lower triangle of (A~ + A~^H)/2 held in the
+// problem's W buffer (per-column arrays in LDS; B holds the compaction, the twisted
+// factorisations and the LU factors, S the tridiagonal eigenvectors, A the W^T rows), and
+// C = L^{-H} W one column per thread.
+constexpr int kRRTriMax = 768;
+
+template <typename T>
+struct KRRSolveTriG {
+  using Tri = KRRSolveTri<T>;
+  static constexpr int kThreads = Tri::kThreads;
+  FDE_HD static size_t lds_bytes(int m) {
+    return sizeof(double) * (32 + 13 * (size_t)m) + sizeof(int) * (2 * (size_t)m + 3 + kThreads) + 64;
+  }
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const ProbSet<T> ps) {
+    const Prob<T>& a = ps.p[c.bx()];
+    const int m = a.m, nb = a.nb;
+    const int tid = c.tid(), nt = c.nthr();
+    double* red = (double*)lds;
+    double* dg = red + 32;
+    double *e2 = dg + m, *ea = e2 + m, *beta = ea + m, *ar = beta + m, *ai = ar + m, *dre = ai + m, *dim = dre + m;
+    double *lam = dim + m, *lo = lam + m, *hi = lo + m, *pbx = hi + m, *pby = pbx + m;
+    int* act = (int*)(pby + m);
+    int* cls = act + m;      // cluster starts (m + 1), the active count, the cluster count
+    int* cnt = cls + m + 3;  // Sturm counts, one per thread
+    if (!KRRSolve<T>::front(c, red, a, ps.drop_tol)) return;
+    cplx<double>* U = a.W;
+    for (int e = tid; e < m * m; e += nt) {
+      const int i = e / m, j = e - i * m;
+      if (j > i) continue;
+      const cplx<double> l = a.A[(size_t)i * m + j], u = a.A[(size_t)j * m + i];
+      U[tri(i, j)] = i == j ? mk<double>(l.x, 0.0) : mk<double>(0.5 * (l.x + u.x), 0.5 * (l.y - u.y));
+    }
+    if (tid == 0) {
+      int k = 0;
+      for (int j = 0; j < m; ++j)
+        if (!a.masked[j]) act[k++] = j;
+      cls[m + 1] = k;
+    }
+    c.sync();
+    const int ma = cls[m + 1];
+    Tri::house_lds(c, U, (char*)a.B, m, ma, act, dg, beta, ar, ai, pbx, pby);
+    const typename Tri::TriWork tw{dg,  e2,     ea,       beta, ar, ai,    dre,  dim,     lam,
+                                   lo,  hi,     act,      cls,  a.masked, cnt, (char*)a.B,
+                                   Tri::lu_stride(m), (double*)a.S, U,  a.A,  m,       a.theta};
+    Tri::template tri_eigen<kRRTriMax>(c, tw, m, nb, ma);
+    c.sync();
+    // C = L^{-H} W[:, :nb], W^T rows in A (stride m)
+    for (int n = tid; n < nb; n += nt) {
+      a.eval[n] = a.theta[n];
+      for (int i = m - 1; i >= 0; --i) {
+        cplx<double> acc = a.A[(size_t)n * m + i];
+        for (int k = i + 1; k < m; ++k) acc = acc - conj(a.L[(size_t)k * m + i]) * a.Cd[(size_t)k * nb + n];
+        a.Cd[(size_t)i * nb + n] = cdiv_real(acc, a.L[(size_t)i * m + i].x);
+      }
+    }
+    c.sync();
+    for (int e = tid; e < m * nb; e += nt) {
+      const cplx<double> v = a.Cd[e];
+      ((cplx<T>*)a.Ct)[e] = mk<T>((T)v.x, (T)v.y);
+    }
   }
 };
 

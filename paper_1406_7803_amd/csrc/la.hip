@@ -125,6 +125,9 @@ static fde_status rr_launch(fde_plan* p, ProbSet<T>& ps, hipStream_t s) {
   if (mmax <= kRRLdsMax && KRRSolveTri<T>::lds_bytes(mmax, nbmax) <= kLdsMax)
     FDE_TRY((launch<KRRSolveTri<T>, KRRSolveTri<T>::kThreads>(dim3(ps.n), KRRSolveTri<T>::kThreads,
                                                                 KRRSolveTri<T>::lds_bytes(mmax, nbmax), s, ps)));
+  else if (mmax > kRRLdsMax && mmax <= kRRTriMax && KRRSolveTriG<T>::lds_bytes(mmax) <= kLdsMax)
+    FDE_TRY((launch<KRRSolveTriG<T>, KRRSolveTriG<T>::kThreads>(dim3(ps.n), KRRSolveTriG<T>::kThreads,
+                                                                KRRSolveTriG<T>::lds_bytes(mmax), s, ps)));
   else if (mmax <= kRRLdsMax && KRRSolveLds<T>::lds_bytes(mmax) <= kLdsMax)
     FDE_TRY((launch<KRRSolveLds<T>, 1024>(dim3(ps.n), 1024, KRRSolveLds<T>::lds_bytes(mmax), s, ps)));
   else
