@@ -70,6 +70,28 @@ struct KGramReduce {
 
 FDE_HD cplx<double> cdiv_real(cplx<double> a, double d) { return mk<double>(a.x / d, a.y / d); }
 
+// sum_{k < n} l[k] x[k * ld]: four terms per step (their loads issued together) on two
+// accumulators
+FDE_HD inline cplx<double> tri_row_sum(const cplx<double>* l, const cplx<double>* x, int ld, int n) {
+  double ax0 = 0.0, ay0 = 0.0, ax1 = 0.0, ay1 = 0.0;
+  int k = 0;
+  for (; k + 4 <= n; k += 4) {
+    const cplx<double> l0 = l[k], l1 = l[k + 1], l2 = l[k + 2], l3 = l[k + 3];
+    const cplx<double> x0 = x[(size_t)k * ld], x1 = x[(size_t)(k + 1) * ld];
+    const cplx<double> x2 = x[(size_t)(k + 2) * ld], x3 = x[(size_t)(k + 3) * ld];
+    ax0 += l0.x * x0.x - l0.y * x0.y + l2.x * x2.x - l2.y * x2.y;
+    ay0 += l0.x * x0.y + l0.y * x0.x + l2.x * x2.y + l2.y * x2.x;
+    ax1 += l1.x * x1.x - l1.y * x1.y + l3.x * x3.x - l3.y * x3.y;
+    ay1 += l1.x * x1.y + l1.y * x1.x + l3.x * x3.y + l3.y * x3.x;
+  }
+  for (; k < n; ++k) {
+    const cplx<double> lk = l[k], xk = x[(size_t)k * ld];
+    ax0 += lk.x * xk.x - lk.y * xk.y;
+    ay0 += lk.x * xk.y + lk.y * xk.x;
+  }
+  return mk<double>(ax0 + ax1, ay0 + ay1);
+}
+
 template <typename T>
 struct KRRSolve {
   // reduction scratch + rotation parameters; the Jacobi matrices A~ and W are
@@ -83,6 +105,12 @@ struct KRRSolve {
   FDE_HD static bool front(const Ctx& c, double* red, const Prob<T>& a, double drop_tol) {
     const int m = a.m, nb = a.nb;
     const int tid = c.tid(), nt = c.nthr();
+#if defined(__HIP_DEVICE_COMPILE__)
+    constexpr int GL = 16;
+#else
+    constexpr int GL = 1;
+#endif
+    const int gl = tid % GL, grp = tid / GL, ng = nt / GL;
     cplx<double>*S = a.S, *A = a.A, *L = a.L, *B = a.B;
     if (tid == 0) a.info[0] = 0;
     // ---- masks
@@ -136,32 +164,38 @@ struct KRRSolve {
       }
       const double ljj = sqrt(d);
       if (tid == 0) L[(size_t)j * m + j] = mk<double>(ljj, 0.0);
-      for (int i = j + 1 + tid; i < m; i += nt) {
-        cplx<double> acc = S[(size_t)i * m + j];
-        for (int k = 0; k < j; ++k) {
-          const cplx<double> lik = L[(size_t)i * m + k], ljk = L[(size_t)j * m + k];
-          // acc -= L_ik conj(L_jk)
-          acc.x -= lik.x * ljk.x + lik.y * ljk.y;
-          acc.y -= lik.y * ljk.x - lik.x * ljk.y;
+      // row i by a lane group, lane g summing the terms k = g (mod GL)
+      for (int i = j + 1 + grp; i < m; i += ng) {
+        const cplx<double>*li = L + (size_t)i * m, *lj = L + (size_t)j * m;
+        double ax = 0.0, ay = 0.0;  // sum_k L_ik conj(L_jk)
+        for (int k = gl; k < j; k += GL) {
+          const cplx<double> lik = li[k], ljk = lj[k];
+          ax += lik.x * ljk.x + lik.y * ljk.y;
+          ay += lik.y * ljk.x - lik.x * ljk.y;
         }
-        L[(size_t)i * m + j] = cdiv_real(acc, ljj);
+        ax = c.template gsum<GL>(ax);
+        ay = c.template gsum<GL>(ay);
+        if (gl == 0) {
+          const cplx<double> sij = S[(size_t)i * m + j];
+          L[(size_t)i * m + j] = cdiv_real(mk<double>(sij.x - ax, sij.y - ay), ljj);
+        }
       }
       c.sync();
     }
-    // ---- B = L^{-1} A (column per thread), then A~ = L^{-1} B^H into A
+    // ---- B = L^{-1} A, then A~ = L^{-1} B^H into A: column per thread
     for (int col = tid; col < m; col += nt) {
       for (int i = 0; i < m; ++i) {
-        cplx<double> acc = A[(size_t)i * m + col];
-        for (int k = 0; k < i; ++k) acc = acc - L[(size_t)i * m + k] * B[(size_t)k * m + col];
-        B[(size_t)i * m + col] = cdiv_real(acc, L[(size_t)i * m + i].x);
+        const cplx<double> r = A[(size_t)i * m + col];
+        const cplx<double> s = tri_row_sum(L + (size_t)i * m, B + col, m, i);
+        B[(size_t)i * m + col] = cdiv_real(mk<double>(r.x - s.x, r.y - s.y), L[(size_t)i * m + i].x);
       }
     }
     c.sync();
     for (int col = tid; col < m; col += nt) {
       for (int i = 0; i < m; ++i) {
-        cplx<double> acc = conj(B[(size_t)col * m + i]);
-        for (int k = 0; k < i; ++k) acc = acc - L[(size_t)i * m + k] * A[(size_t)k * m + col];
-        A[(size_t)i * m + col] = cdiv_real(acc, L[(size_t)i * m + i].x);
+        const cplx<double> r = B[(size_t)col * m + i];  // conj of it
+        const cplx<double> s = tri_row_sum(L + (size_t)i * m, A + col, m, i);
+        A[(size_t)i * m + col] = cdiv_real(mk<double>(r.x - s.x, -r.y - s.y), L[(size_t)i * m + i].x);
       }
     }
     c.sync();

@@ -814,6 +814,85 @@ struct KRRSolveTri {
     double* theta;
   };
 
+  // Back-transformation of NV eigenvectors at a time per group of GL lanes: z = D y in
+  // registers (rows i = gl + GL s), then H_k z for k = ma - 2 .. 0; each reflector's entries
+  // are loaded once for the NV vectors. Slots whose rows all lie outside k + 1 .. ma - 1 are
+  // skipped by the whole group.
+  template <int GL, int ZR, int NV, class Ctx>
+  FDE_HD static void back_transform(const Ctx& c, const TriWork& w, int m, int ma, int nw) {
+    const int tid = c.tid(), nt = c.nthr();
+    const int gl = tid % GL, ngrp = nt / GL;
+    for (int n0 = (tid / GL) * NV; n0 < nw; n0 += ngrp * NV) {
+      cplx<double> z[NV][ZR];
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        const double* y = w.Y + (size_t)(n0 + q) * ma;
+#pragma unroll
+        for (int s = 0; s < ZR; ++s) {
+          const int i = gl + GL * s;
+          z[q][s] = (n0 + q < nw && i < ma) ? mk<double>(w.dre[i] * y[i], w.dim[i] * y[i]) : mk<double>(0.0, 0.0);
+        }
+      }
+      for (int k = ma - 2; k >= 0; --k) {
+        const double bt = w.beta[k];
+        if (bt == 0.0) continue;
+        const int vo = voff(k, ma) - (k + 1);  // V[vo + i] = v_k for rows i = k + 1 .. ma - 1
+        // a short reflector slice stays in registers for the update; a long one is loaded again
+        constexpr bool kKeep = ZR <= 8;
+        cplx<double> v[kKeep ? ZR : 1];
+        double sx[NV], sy[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) sx[q] = sy[q] = 0.0;
+#pragma unroll
+        for (int s = 0; s < ZR; ++s) {
+          const int i = gl + GL * s;
+          if (GL * s < ma && GL * s + GL - 1 > k) {
+            const cplx<double> vi = (i > k && i < ma) ? w.V[vo + i] : mk<double>(0.0, 0.0);
+            if constexpr (kKeep) v[s] = vi;
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+              sx[q] += vi.x * z[q][s].x + vi.y * z[q][s].y;
+              sy[q] += vi.x * z[q][s].y - vi.y * z[q][s].x;
+            }
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+          sx[q] = bt * c.template gsum<GL>(sx[q]);
+          sy[q] = bt * c.template gsum<GL>(sy[q]);
+        }
+#pragma unroll
+        for (int s = 0; s < ZR; ++s) {
+          if (GL * s < ma && GL * s + GL - 1 > k) {
+            const int i = gl + GL * s;
+            cplx<double> vi;
+            if constexpr (kKeep)
+              vi = v[s];
+            else
+              vi = (i > k && i < ma) ? w.V[vo + i] : mk<double>(0.0, 0.0);
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+              z[q][s].x -= vi.x * sx[q] - vi.y * sy[q];
+              z[q][s].y -= vi.x * sy[q] + vi.y * sx[q];
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        if (n0 + q >= nw) break;
+        cplx<double>* wr = w.Wt + (size_t)(n0 + q) * w.ld;
+#pragma unroll
+        for (int s = 0; s < ZR; ++s) {
+          const int i = gl + GL * s;
+          if (i < ma) wr[w.act[i]] = z[q][s];
+        }
+        for (int p = gl; p < m; p += GL)
+          if (w.masked[p]) wr[p] = mk<double>(0.0, 0.0);
+      }
+    }
+  }
+
   // Steps 3b-3e on the reduced active block (ma rows; dg, beta and alpha from the reduction):
   // eigenvalues and eigenvectors of the lowest nb, W^T rows n < nb with physical row indices,
   // masked rows zero, masked eigenpairs after the active ones. ZMAX bounds m.
@@ -1016,59 +1095,20 @@ struct KRRSolveTri {
         }
       }
       c.sync();
-      // ---- 3e. W^T rows n < nw: z = D y, H_k z for k = ma - 2 .. 0 (z in registers, rows
-      //      i = gl + GL s of each lane), written to the physical indices act[i], masked rows zero
+      // ---- 3e. W^T rows n < nw: z = D y, H_k z for k = ma - 2 .. 0, written to the physical
+      //      indices act[i], masked rows zero
 #if defined(__HIP_DEVICE_COMPILE__)
-      // a whole wavefront per vector once 16 lanes would need more than 16 rows each
-      constexpr int GL = ZMAX > 16 * kGroup ? 64 : kGroup;
-#else
-      constexpr int GL = 1;
-#endif
-      constexpr int ZR = (ZMAX + GL - 1) / GL;
-      const int ngrp = nt / GL, gl = tid % GL;
-      for (int n = tid / GL; n < nw; n += ngrp) {
-        const double* y = Y + (size_t)n * ma;
-        cplx<double> z[ZR];
-#pragma unroll
-        for (int s = 0; s < ZR; ++s) {
-          const int i = gl + GL * s;
-          z[s] = i < ma ? mk<double>(dre[i] * y[i], dim[i] * y[i]) : mk<double>(0.0, 0.0);
-        }
-        for (int k = ma - 2; k >= 0; --k) {
-          const double bt = beta[k];
-          if (bt == 0.0) continue;
-          const int vo = voff(k, ma) - (k + 1);  // V[vo + i] = v_k for rows i = k + 1 .. ma - 1
-          double sx = 0.0, sy = 0.0;
-#pragma unroll
-          for (int s = 0; s < ZR; ++s) {
-            const int i = gl + GL * s;
-            if (i > k && i < ma) {
-              const cplx<double> vi = w.V[vo + i];
-              sx += vi.x * z[s].x + vi.y * z[s].y;
-              sy += vi.x * z[s].y - vi.y * z[s].x;
-            }
-          }
-          sx = bt * c.template gsum<GL>(sx);
-          sy = bt * c.template gsum<GL>(sy);
-#pragma unroll
-          for (int s = 0; s < ZR; ++s) {
-            const int i = gl + GL * s;
-            if (i > k && i < ma) {
-              const cplx<double> vi = w.V[vo + i];
-              z[s].x -= vi.x * sx - vi.y * sy;
-              z[s].y -= vi.x * sy + vi.y * sx;
-            }
-          }
-        }
-        cplx<double>* wr = w.Wt + (size_t)n * w.ld;
-#pragma unroll
-        for (int s = 0; s < ZR; ++s) {
-          const int i = gl + GL * s;
-          if (i < ma) wr[act[i]] = z[s];
-        }
-        for (int p = gl; p < m; p += GL)
-          if (masked[p]) wr[p] = mk<double>(0.0, 0.0);
+      if constexpr (ZMAX > 16 * kGroup) {  // a whole wavefront per vector
+        if (ma <= 256)
+          back_transform<64, 4, 2>(c, w, m, ma, nw);
+        else
+          back_transform<64, (ZMAX + 63) / 64, 1>(c, w, m, ma, nw);
+      } else {
+        back_transform<kGroup, (ZMAX + kGroup - 1) / kGroup, 1>(c, w, m, ma, nw);
       }
+#else
+      back_transform<1, ZMAX, 1>(c, w, m, ma, nw);
+#endif
     }
     // masked eigenpairs (A~ = kInactiveDiag e_p e_p^H) fill the columns beyond the active count
     for (int n = nw + tid; n < nb; n += nt) {
@@ -1142,8 +1182,88 @@ struct KRRSolveTriG {
   using Tri = KRRSolveTri<T>;
   static constexpr int kThreads = Tri::kThreads;
   FDE_HD static size_t lds_bytes(int m) {
-    return sizeof(double) * (32 + 13 * (size_t)m) + sizeof(int) * (2 * (size_t)m + 3 + kThreads) + 64;
+    return sizeof(double) * (32 + 15 * (size_t)m) + sizeof(int) * (2 * (size_t)m + 3 + kThreads) + 64;
   }
+
+  // Householder reduction of the active block held with both triangles in G (row-major, ld ma,
+  // logical indices): step k reads row k (conjugate of column k), stages v in LDS (vl), forms
+  // p = beta G' v one row per wavefront and applies the rank-2 update to the whole trailing
+  // block. v_k goes to V[voff(k) ..], the diagonal to dg.
+  template <class Ctx>
+  FDE_HD static void house_full(const Ctx& c, cplx<double>* G, cplx<double>* V, cplx<double>* vl, int ma,
+                                double* dg, double* beta, double* ar, double* ai, double* pbx, double* pby) {
+    const int tid = c.tid(), nt = c.nthr();
+    const int lane = c.lane(), wl = c.wlanes(), wv = c.wave(), nwv = c.nwave();
+    for (int k = 0; k + 1 < ma; ++k) {
+      const int n1 = ma - k - 1;
+      const cplx<double>* gk = G + (size_t)k * ma + k + 1;  // x_r = conj(gk[r])
+      double s2 = 0.0;
+      for (int r = lane; r < n1; r += wl) s2 += norm2(gk[r]);
+      s2 = c.template gsum<64>(s2);
+      const cplx<double> x0 = conj(gk[0]);
+      double bt = 0.0;
+      cplx<double> alpha = x0, v0 = x0;
+      if (n1 > 1 && s2 > norm2(x0)) {
+        const double ax0 = sqrt(norm2(x0)), sg = sqrt(s2);
+        const cplx<double> ph = ax0 > 0.0 ? mk<double>(x0.x / ax0, x0.y / ax0) : mk<double>(1.0, 0.0);
+        alpha = mk<double>(-ph.x * sg, -ph.y * sg);
+        v0 = mk<double>(x0.x + ph.x * sg, x0.y + ph.y * sg);
+        bt = 1.0 / (sg * (sg + ax0));
+      }
+      if (tid == 0) {
+        beta[k] = bt;
+        ar[k] = alpha.x;
+        ai[k] = alpha.y;
+        dg[k] = G[(size_t)k * ma + k].x;
+      }
+      cplx<double>* vk = V + Tri::voff(k, ma);
+      for (int r = tid; r < n1; r += nt) {
+        const cplx<double> v = r == 0 ? v0 : conj(gk[r]);
+        vl[r] = v;
+        vk[r] = v;
+      }
+      c.sync();
+      if (bt != 0.0) {  // uniform: every wavefront summed in the same order
+        for (int r = wv; r < n1; r += nwv) {
+          const cplx<double>* gr = G + (size_t)(k + 1 + r) * ma + k + 1;
+          double sx = 0.0, sy = 0.0;
+          for (int j = lane; j < n1; j += wl) {
+            const cplx<double> g = gr[j], v = vl[j];
+            sx += g.x * v.x - g.y * v.y;
+            sy += g.x * v.y + g.y * v.x;
+          }
+          sx = c.template gsum<64>(sx);
+          sy = c.template gsum<64>(sy);
+          if (lane == 0) {
+            pbx[r] = bt * sx;
+            pby[r] = bt * sy;
+          }
+        }
+        c.sync();
+        // K = beta/2 v^H p (real); G' -= v w^H + w v^H with w = p - K v
+        double kk = 0.0;
+        for (int r = lane; r < n1; r += wl) kk += vl[r].x * pbx[r] + vl[r].y * pby[r];
+        kk = 0.5 * bt * c.template gsum<64>(kk);
+        for (int r = wv; r < n1; r += nwv) {
+          cplx<double>* gr = G + (size_t)(k + 1 + r) * ma + k + 1;
+          const cplx<double> vr = vl[r];
+          const double wrx = pbx[r] - kk * vr.x, wry = pby[r] - kk * vr.y;
+          for (int j = lane; j < n1; j += wl) {
+            const cplx<double> vj = vl[j];
+            const double wjx = pbx[j] - kk * vj.x, wjy = pby[j] - kk * vj.y;
+            cplx<double> t = gr[j];
+            t.x -= (vr.x * wjx + vr.y * wjy) + (wrx * vj.x + wry * vj.y);
+            t.y -= (vr.y * wjx - vr.x * wjy) + (wry * vj.x - wrx * vj.y);
+            gr[j] = t;
+          }
+        }
+        c.sync();
+      }
+    }
+    if (tid == 0 && ma > 0) dg[ma - 1] = G[(size_t)(ma - 1) * ma + ma - 1].x;
+    c.sync();
+  }
+
   template <class Ctx>
   FDE_HD static void run(const Ctx& c, char* lds, const ProbSet<T> ps) {
     const Prob<T>& a = ps.p[c.bx()];
@@ -1153,17 +1273,11 @@ struct KRRSolveTriG {
     double* dg = red + 32;
     double *e2 = dg + m, *ea = e2 + m, *beta = ea + m, *ar = beta + m, *ai = ar + m, *dre = ai + m, *dim = dre + m;
     double *lam = dim + m, *lo = lam + m, *hi = lo + m, *pbx = hi + m, *pby = pbx + m;
-    int* act = (int*)(pby + m);
+    cplx<double>* vl = (cplx<double>*)(((size_t)(pby + m) + 15) & ~(size_t)15);  // 16-byte aligned
+    int* act = (int*)(vl + m);
     int* cls = act + m;      // cluster starts (m + 1), the active count, the cluster count
     int* cnt = cls + m + 3;  // Sturm counts, one per thread
     if (!KRRSolve<T>::front(c, red, a, ps.drop_tol)) return;
-    cplx<double>* U = a.W;
-    for (int e = tid; e < m * m; e += nt) {
-      const int i = e / m, j = e - i * m;
-      if (j > i) continue;
-      const cplx<double> l = a.A[(size_t)i * m + j], u = a.A[(size_t)j * m + i];
-      U[tri(i, j)] = i == j ? mk<double>(l.x, 0.0) : mk<double>(0.5 * (l.x + u.x), 0.5 * (l.y - u.y));
-    }
     if (tid == 0) {
       int k = 0;
       for (int j = 0; j < m; ++j)
@@ -1172,19 +1286,51 @@ struct KRRSolveTriG {
     }
     c.sync();
     const int ma = cls[m + 1];
-    Tri::house_lds(c, U, (char*)a.B, m, ma, act, dg, beta, ar, ai, pbx, pby);
+    // (A~ + A~^H)/2 on the active rows and columns, both triangles, into G
+    cplx<double>* G = a.W;
+    for (int e = tid; e < ma * ma; e += nt) {
+      const int i = e / ma, j = e - i * ma;
+      const cplx<double> l = a.A[(size_t)act[i] * m + act[j]], u = a.A[(size_t)act[j] * m + act[i]];
+      G[e] = mk<double>(0.5 * (l.x + u.x), 0.5 * (l.y - u.y));
+    }
+    c.sync();
+    // reflectors behind the inverse-iteration vectors (which take at most m * m doubles of S)
+    cplx<double>* V = (cplx<double>*)((double*)a.S + (size_t)m * m);
+    house_full(c, G, V, vl, ma, dg, beta, ar, ai, pbx, pby);
     const typename Tri::TriWork tw{dg,  e2,     ea,       beta, ar, ai,    dre,  dim,     lam,
                                    lo,  hi,     act,      cls,  a.masked, cnt, (char*)a.B,
-                                   Tri::lu_stride(m), (double*)a.S, U,  a.A,  m,       a.theta};
+                                   Tri::lu_stride(m), (double*)a.S, V,  a.A,  m,       a.theta};
     Tri::template tri_eigen<kRRTriMax>(c, tw, m, nb, ma);
     c.sync();
-    // C = L^{-H} W[:, :nb], W^T rows in A (stride m)
+    // C = L^{-H} W[:, :nb], W^T rows in A (stride m): column n per thread, the sums over
+    // k > i eight terms at a time
     for (int n = tid; n < nb; n += nt) {
       a.eval[n] = a.theta[n];
       for (int i = m - 1; i >= 0; --i) {
-        cplx<double> acc = a.A[(size_t)n * m + i];
-        for (int k = i + 1; k < m; ++k) acc = acc - conj(a.L[(size_t)k * m + i]) * a.Cd[(size_t)k * nb + n];
-        a.Cd[(size_t)i * nb + n] = cdiv_real(acc, a.L[(size_t)i * m + i].x);
+        double ax[4] = {0.0, 0.0, 0.0, 0.0}, ay[4] = {0.0, 0.0, 0.0, 0.0};  // sum_{k > i} conj(L_ki) C_kn
+        int k = i + 1;
+        for (; k + 8 <= m; k += 8) {
+          cplx<double> l[8], x[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            l[q] = a.L[(size_t)(k + q) * m + i];
+            x[q] = a.Cd[(size_t)(k + q) * nb + n];
+          }
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            ax[q & 3] += l[q].x * x[q].x + l[q].y * x[q].y;
+            ay[q & 3] += l[q].x * x[q].y - l[q].y * x[q].x;
+          }
+        }
+        for (; k < m; ++k) {
+          const cplx<double> l = a.L[(size_t)k * m + i], x = a.Cd[(size_t)k * nb + n];
+          ax[0] += l.x * x.x + l.y * x.y;
+          ay[0] += l.x * x.y - l.y * x.x;
+        }
+        const cplx<double> w = a.A[(size_t)n * m + i];
+        a.Cd[(size_t)i * nb + n] = cdiv_real(
+            mk<double>(w.x - ((ax[0] + ax[1]) + (ax[2] + ax[3])), w.y - ((ay[0] + ay[1]) + (ay[2] + ay[3]))),
+            a.L[(size_t)i * m + i].x);
       }
     }
     c.sync();

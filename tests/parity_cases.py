@@ -157,7 +157,8 @@ GEMM_TOL = {fde.GEMM_FP64: (2e-5, 1e-4), fde.GEMM_BF16X6: (2e-5, 1e-4), fde.GEMM
 
 
 def check_subspace_rr(be, prec, drop_case=False, nb=4, case=SMALL, gemm=fde.GEMM_FP64):
-    """nb = 45 (m = 90) exercises the global-memory solver, smaller m the LDS one."""
+    """nb = 45 (m = 90) and nb = 140 (m = 280) exercise the tridiagonal solver with its matrices in
+    global memory, smaller m the LDS ones."""
     plan = small_plan(be, prec, max_nb=max(4, nb), case=case)
     if gemm != fde.GEMM_FP64:
         plan.set_gemm_mode(gemm)
