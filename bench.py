@@ -20,6 +20,10 @@ slab's 36 projectors. Algorithmic bytes per call (complex of `cs` bytes, V_eff
 real of `rs` bytes; V_eff and the projectors counted once per call, whatever the
 launch shape re-reads):
     nb * (3*cs*npw + 4*cs*ncol*N3) + rs*N + nproj*cs*npw.
+
+`--workload 64-subsystems` times the cycle of the 20 bohr cube holding 64 uneven
+subsystems (72^3 grid, E_cut 15 Ha, 4-128 bands and 1-8 k-points each) instead;
+that line is context, without CPU baseline or counter traffic.
 """
 from __future__ import annotations
 
@@ -53,6 +57,9 @@ def parse():
     ap.add_argument("--streams", type=int, default=3, help="concurrent band-solver groups")
     ap.add_argument("--gemm", choices=["fp64", "bf16x3", "bf16x6"], default="fp64",
                     help="arithmetic of the Rayleigh-Ritz subspace products (FP32 plan)")
+    ap.add_argument("--workload", choices=["slab-molecule", "64-subsystems"], default="slab-molecule",
+                    help="slab + molecule cell (the benchmark line) or the cube of 64 uneven subsystems "
+                         "(timed for context: no CPU baseline, no counter traffic)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only time a plain device-to-device copy of MIB MiB (stream bandwidth and "
                          "the calibration of the HBM byte counters), then exit")
@@ -199,7 +206,8 @@ def main():
 
     prec = fde.F32 if a.prec == "fp32" else fde.F64
     be = fde.gpu_backend("cuda:0")
-    system = fde_synth.config2()
+    many = a.workload == "64-subsystems"
+    system = fde_synth.config3() if many else fde_synth.config2()
     print("# building engine", file=sys.stderr, flush=True)
     gemm = {"fp64": fde.GEMM_FP64, "bf16x3": fde.GEMM_BF16X3, "bf16x6": fde.GEMM_BF16X6}[a.gemm]
     eng = driver.Engine(system, prec=prec, backend=be, gemm=gemm, streams=a.streams)
@@ -250,7 +258,7 @@ def main():
     tta = None if a.no_tta else time_to_accuracy(be)
 
     cpu = None
-    if not a.no_cpu_baseline:
+    if not a.no_cpu_baseline and not many:
         from oracle import basis, hamiltonian as oham, pseudo as opseudo
         cell = basis.Cell(system.L, system.grid)
         sph = basis.sphere(cell, system.ecut, system.subsystems[0].kfrac[0])
@@ -278,19 +286,22 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if prec == fde.F32 else "f64",
         "data": "synthetic",
-        "config": {"workload": "slab+molecule 10.2x10.2x40 bohr, 60x60x240 grid, Ecut 40 Ha, "
-                               "slab 36 ions/40 bands/4 k + molecule 6 ions/8 bands/Gamma",
+        "config": {"workload": ("64 uneven subsystems in a 20 bohr cube, 72x72x72 grid, Ecut 15 Ha, "
+                                "4-128 bands and 1-8 k-points each" if many else
+                                "slab+molecule 10.2x10.2x40 bohr, 60x60x240 grid, Ecut 40 Ha, "
+                                "slab 36 ions/40 bands/4 k + molecule 6 ions/8 bands/Gamma"),
                    "band_applies_per_cycle": per_cycle, "davidson_per_cycle": system.n_david,
                    "subspace_products": a.gemm, "launch": "eager" if a.eager else "one HIP graph per cycle",
                    "apply_bands_per_plane_workgroup": None if tuned is None else tuned["bpw"],
                    "z_pass": "four-step register FFT" if system.grid[2] in (240, 120) else "LDS Stockham",
                    "solver_streams": len(eng.groups),
                    "parallelism": "single GPU"},
-        "isolated_apply_h": {"band_applies_per_s": isolated, "bands": nb, "ms_per_call": t_apply * 1e3},
+        "isolated_apply_h": {"band_applies_per_s": isolated, "bands": nb, "projectors": nproj,
+                             "ms_per_call": t_apply * 1e3},
         "roofline": {"kernel": "fde_apply_h: FFT sandwich (KZInv, KPlaneHReg, KZFwd) + projectors "
                                "(KAhBAll, KKbReduce, KKbAdd)", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(), "algorithmic_bytes": alg_bytes},
+                     "traffic": None if many else measured_traffic(), "algorithmic_bytes": alg_bytes},
         "cpu_baseline": cpu,
         "stream_copy_GBps": copy_probe(1024)["copy_GBps"],
         "time_to_1e-6Ha": tta,
