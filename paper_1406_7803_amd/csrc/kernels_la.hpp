@@ -70,26 +70,61 @@ struct KGramReduce {
 
 FDE_HD cplx<double> cdiv_real(cplx<double> a, double d) { return mk<double>(a.x / d, a.y / d); }
 
-// sum_{k < n} l[k] x[k * ld]: four terms per step (their loads issued together) on two
-// accumulators
-FDE_HD inline cplx<double> tri_row_sum(const cplx<double>* l, const cplx<double>* x, int ld, int n) {
-  double ax0 = 0.0, ay0 = 0.0, ax1 = 0.0, ay1 = 0.0;
-  int k = 0;
-  for (; k + 4 <= n; k += 4) {
-    const cplx<double> l0 = l[k], l1 = l[k + 1], l2 = l[k + 2], l3 = l[k + 3];
-    const cplx<double> x0 = x[(size_t)k * ld], x1 = x[(size_t)(k + 1) * ld];
-    const cplx<double> x2 = x[(size_t)(k + 2) * ld], x3 = x[(size_t)(k + 3) * ld];
-    ax0 += l0.x * x0.x - l0.y * x0.y + l2.x * x2.x - l2.y * x2.y;
-    ay0 += l0.x * x0.y + l0.y * x0.x + l2.x * x2.y + l2.y * x2.x;
-    ax1 += l1.x * x1.x - l1.y * x1.y + l3.x * x3.x - l3.y * x3.y;
-    ay1 += l1.x * x1.y + l1.y * x1.x + l3.x * x3.y + l3.y * x3.x;
+// One column of X = L^{-1} R (L lower triangular, row-major, ld m; forward substitution) or,
+// with `upper`, of X = L^{-H} R (backward substitution). Rows go in blocks of 8: each x_k
+// loaded serves the 8 rows of a block, whose L entries are the same for every column (one
+// column per thread), then the block's own triangle is solved in registers. R(i) is
+// conj(r[i * rs]) when `rconj`; x_k lives at x[k * xs].
+FDE_HD inline void tri_solve_col(const cplx<double>* L, int m, const cplx<double>* r, size_t rs, bool rconj,
+                                 cplx<double>* x, size_t xs, bool upper) {
+  constexpr int RB = 8;
+  for (int b0 = 0; b0 < m; b0 += RB) {
+    const int nr = m - b0 < RB ? m - b0 : RB;
+    // rows of the block: i_q = b0 + q (forward) or m - 1 - b0 - q (backward)
+    double ax[RB], ay[RB];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) ax[q] = ay[q] = 0.0;
+    // rows beyond the last (q >= nr) repeat row nr - 1: every load stays unconditional (and in
+    // bounds), so the block's loads issue together; their sums are not used
+    for (int t = 0; t < b0; ++t) {  // the rows already solved
+      const int k = upper ? m - 1 - t : t;
+      const cplx<double> xk = x[(size_t)k * xs];
+      cplx<double> l[RB];
+#pragma unroll
+      for (int q = 0; q < RB; ++q) {
+        const int qq = q < nr ? q : nr - 1;
+        const int i = upper ? m - 1 - b0 - qq : b0 + qq;
+        l[q] = upper ? L[(size_t)k * m + i] : L[(size_t)i * m + k];
+      }
+#pragma unroll
+      for (int q = 0; q < RB; ++q) {
+        // forward: L_ik x_k; backward: conj(L_ki) x_k
+        const double ly = upper ? -l[q].y : l[q].y;
+        ax[q] += l[q].x * xk.x - ly * xk.y;
+        ay[q] += l[q].x * xk.y + ly * xk.x;
+      }
+    }
+    cplx<double> xb[RB];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      if (q < nr) {
+        const int i = upper ? m - 1 - b0 - q : b0 + q;
+        double sx = ax[q], sy = ay[q];
+#pragma unroll
+        for (int p = 0; p < q; ++p) {
+          const int k = upper ? m - 1 - b0 - p : b0 + p;
+          const cplx<double> l = upper ? L[(size_t)k * m + i] : L[(size_t)i * m + k];
+          const double ly = upper ? -l.y : l.y;
+          sx += l.x * xb[p].x - ly * xb[p].y;
+          sy += l.x * xb[p].y + ly * xb[p].x;
+        }
+        const cplx<double> ri = r[(size_t)i * rs];
+        const double rix = ri.x, riy = rconj ? -ri.y : ri.y;
+        xb[q] = cdiv_real(mk<double>(rix - sx, riy - sy), L[(size_t)i * m + i].x);
+        x[(size_t)i * xs] = xb[q];
+      }
+    }
   }
-  for (; k < n; ++k) {
-    const cplx<double> lk = l[k], xk = x[(size_t)k * ld];
-    ax0 += lk.x * xk.x - lk.y * xk.y;
-    ay0 += lk.x * xk.y + lk.y * xk.x;
-  }
-  return mk<double>(ax0 + ax1, ay0 + ay1);
 }
 
 template <typename T>
@@ -183,21 +218,9 @@ struct KRRSolve {
       c.sync();
     }
     // ---- B = L^{-1} A, then A~ = L^{-1} B^H into A: column per thread
-    for (int col = tid; col < m; col += nt) {
-      for (int i = 0; i < m; ++i) {
-        const cplx<double> r = A[(size_t)i * m + col];
-        const cplx<double> s = tri_row_sum(L + (size_t)i * m, B + col, m, i);
-        B[(size_t)i * m + col] = cdiv_real(mk<double>(r.x - s.x, r.y - s.y), L[(size_t)i * m + i].x);
-      }
-    }
+    for (int col = tid; col < m; col += nt) tri_solve_col(L, m, A + col, m, false, B + col, m, false);
     c.sync();
-    for (int col = tid; col < m; col += nt) {
-      for (int i = 0; i < m; ++i) {
-        const cplx<double> r = B[(size_t)col * m + i];  // conj of it
-        const cplx<double> s = tri_row_sum(L + (size_t)i * m, A + col, m, i);
-        A[(size_t)i * m + col] = cdiv_real(mk<double>(r.x - s.x, -r.y - s.y), L[(size_t)i * m + i].x);
-      }
-    }
+    for (int col = tid; col < m; col += nt) tri_solve_col(L, m, B + (size_t)col * m, 1, true, A + col, m, false);
     c.sync();
     return true;
   }

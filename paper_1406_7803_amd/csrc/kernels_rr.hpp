@@ -512,29 +512,58 @@ struct KRRSolveTri {
     ru0[n - 1] = Ctx::rcp(fabs(cd) < tiny ? (cd < 0.0 ? -tiny : tiny) : cd);
   }
 
-  // b <- (T - lam I)^{-1} b with the factors of lu_factor (running values in registers)
+  // b <- (T - lam I)^{-1} b with the factors of lu_factor (running values in registers). Each
+  // pass loads kC entries of b and the factors ahead of the stores they precede (a store to b
+  // could otherwise alias the next loads and serialise them); every load reads the value the
+  // entry held before this pass stored to it, as a one-at-a-time order would.
   FDE_HD static void lu_solve(int n, const double* lu, const unsigned char* piv, double* b) {
+    constexpr int kC = 8;
     const double *ru0 = lu, *u1 = lu + n, *u2 = lu + 2 * n, *ml = lu + 3 * n;
     double cur = b[0];
-#pragma unroll 4
-    for (int i = 0; i < n - 1; ++i) {
-      const double nx = b[i + 1];
-      if (piv[i]) {
-        b[i] = nx;
-        cur = cur - ml[i] * nx;
-      } else {
-        b[i] = cur;
-        cur = nx - ml[i] * cur;
+    for (int i0 = 0; i0 < n - 1; i0 += kC) {
+      double nx[kC], mc[kC];
+      bool pc[kC];
+#pragma unroll
+      for (int t = 0; t < kC; ++t) {
+        const int i = i0 + t < n - 1 ? i0 + t : n - 2;
+        nx[t] = b[i + 1];
+        mc[t] = ml[i];
+        pc[t] = piv[i] != 0;
+      }
+#pragma unroll
+      for (int t = 0; t < kC; ++t) {
+        const int i = i0 + t;
+        if (i >= n - 1) break;
+        if (pc[t]) {
+          b[i] = nx[t];
+          cur = cur - mc[t] * nx[t];
+        } else {
+          b[i] = cur;
+          cur = nx[t] - mc[t] * cur;
+        }
       }
     }
     double x1 = cur * ru0[n - 1], x2 = 0.0;  // x_{i+1}, x_{i+2}
     b[n - 1] = x1;
-#pragma unroll 4
-    for (int i = n - 2; i >= 0; --i) {
-      const double x = (b[i] - u1[i] * x1 - u2[i] * x2) * ru0[i];
-      b[i] = x;
-      x2 = x1;
-      x1 = x;
+    for (int i0 = n - 2; i0 >= 0; i0 -= kC) {
+      double bc[kC], a1[kC], a2[kC], rc[kC];
+#pragma unroll
+      for (int t = 0; t < kC; ++t) {
+        const int i = i0 - t > 0 ? i0 - t : 0;
+        bc[t] = b[i];
+        a1[t] = u1[i];
+        a2[t] = u2[i];
+        rc[t] = ru0[i];
+      }
+#pragma unroll
+      for (int t = 0; t < kC; ++t) {
+        const int i = i0 - t;
+        if (i < 0) break;
+        const double x = (bc[t] - a1[t] * x1 - a2[t] * x2) * rc[t];
+        b[i] = x;
+        x2 = x1;
+        x1 = x;
+      }
     }
   }
 
@@ -1009,48 +1038,87 @@ struct KRRSolveTri {
         if (!single(j)) continue;
         double* rp = (double*)w.lu + (size_t)j * 2 * ma;  // 1 / D+_i
         double* rm = rp + ma;                            // 1 / D-_i
+        // The recurrences carry their previous pivot in a register; where a pass reads back
+        // stored pivots, it loads kC of them before its stores (the stores could otherwise
+        // alias the loads and serialise them).
+        constexpr int kC = 8;
         const double lj = lam[j];
         double q = dg[0] - lj;
         if (fabs(q) < pivmin) q = -pivmin;
-        rp[0] = Ctx::rcp(q);
+        double rprev = Ctx::rcp(q);
+        rp[0] = rprev;
         for (int i = 1; i < ma; ++i) {
-          q = (dg[i] - lj) - e2[i - 1] * rp[i - 1];
+          q = (dg[i] - lj) - e2[i - 1] * rprev;
           if (fabs(q) < pivmin) q = -pivmin;
-          rp[i] = Ctx::rcp(q);
+          rprev = Ctx::rcp(q);
+          rp[i] = rprev;
         }
         double best = fabs(q);  // gamma_{ma-1} = D+_{ma-1}
         int r = ma - 1;
         q = dg[ma - 1] - lj;
         if (fabs(q) < pivmin) q = -pivmin;
-        rm[ma - 1] = Ctx::rcp(q);
-        for (int i = ma - 2; i >= 0; --i) {
-          const double dpi = (dg[i] - lj) - (i > 0 ? e2[i - 1] * rp[i - 1] : 0.0);  // D+_i
-          const double gam = dpi - e2[i] * rm[i + 1];
-          if (fabs(gam) < best) {
-            best = fabs(gam);
-            r = i;
+        double rnext = Ctx::rcp(q);
+        rm[ma - 1] = rnext;
+        for (int i0 = ma - 2; i0 >= 0; i0 -= kC) {
+          double rpc[kC];  // rp[i - 1] for i = i0 - t
+#pragma unroll
+          for (int t = 0; t < kC; ++t) rpc[t] = rp[i0 - t - 1 > 0 ? i0 - t - 1 : 0];
+#pragma unroll
+          for (int t = 0; t < kC; ++t) {
+            const int i = i0 - t;
+            if (i < 0) break;
+            const double dpi = (dg[i] - lj) - (i > 0 ? e2[i - 1] * rpc[t] : 0.0);  // D+_i
+            const double gam = dpi - e2[i] * rnext;
+            if (fabs(gam) < best) {
+              best = fabs(gam);
+              r = i;
+            }
+            q = (dg[i] - lj) - e2[i] * rnext;
+            if (fabs(q) < pivmin) q = -pivmin;
+            rnext = Ctx::rcp(q);
+            rm[i] = rnext;
           }
-          q = (dg[i] - lj) - e2[i] * rm[i + 1];
-          if (fabs(q) < pivmin) q = -pivmin;
-          rm[i] = Ctx::rcp(q);
         }
         double* y = Y + (size_t)j * ma;
         double x = 1.0, nr = 1.0;
         y[r] = 1.0;
-        for (int i = r - 1; i >= 0; --i) {
-          x = -(ea[i] * rp[i]) * x;
-          y[i] = x;
-          nr += x * x;
+        for (int i0 = r - 1; i0 >= 0; i0 -= kC) {
+          double rc[kC];
+#pragma unroll
+          for (int t = 0; t < kC; ++t) rc[t] = rp[i0 - t > 0 ? i0 - t : 0];
+#pragma unroll
+          for (int t = 0; t < kC; ++t) {
+            const int i = i0 - t;
+            if (i < 0) break;
+            x = -(ea[i] * rc[t]) * x;
+            y[i] = x;
+            nr += x * x;
+          }
         }
         x = 1.0;
-        for (int i = r + 1; i < ma; ++i) {
-          x = -(ea[i - 1] * rm[i]) * x;
-          y[i] = x;
-          nr += x * x;
+        for (int i0 = r + 1; i0 < ma; i0 += kC) {
+          double rc[kC];
+#pragma unroll
+          for (int t = 0; t < kC; ++t) rc[t] = rm[i0 + t < ma ? i0 + t : ma - 1];
+#pragma unroll
+          for (int t = 0; t < kC; ++t) {
+            const int i = i0 + t;
+            if (i >= ma) break;
+            x = -(ea[i - 1] * rc[t]) * x;
+            y[i] = x;
+            nr += x * x;
+          }
         }
         if (nr > 0.0 && nr < 1e300) {
           const double sc = 1.0 / sqrt(nr);
-          for (int i = 0; i < ma; ++i) y[i] *= sc;
+          for (int i0 = 0; i0 < ma; i0 += kC) {
+            double yc[kC];
+#pragma unroll
+            for (int t = 0; t < kC; ++t) yc[t] = y[i0 + t < ma ? i0 + t : ma - 1];
+#pragma unroll
+            for (int t = 0; t < kC; ++t)
+              if (i0 + t < ma) y[i0 + t] = yc[t] * sc;
+          }
           lo[j] = 0.0;
         }
       }
@@ -1224,19 +1292,36 @@ struct KRRSolveTriG {
       }
       c.sync();
       if (bt != 0.0) {  // uniform: every wavefront summed in the same order
-        for (int r = wv; r < n1; r += nwv) {
-          const cplx<double>* gr = G + (size_t)(k + 1 + r) * ma + k + 1;
-          double sx = 0.0, sy = 0.0;
+        // rows r0 + q nwv (q < RB) of a wavefront together, so their loads are in flight at once
+        constexpr int RB = 4;
+        for (int r0 = wv; r0 < n1; r0 += RB * nwv) {
+          double sx[RB], sy[RB];
+#pragma unroll
+          for (int q = 0; q < RB; ++q) sx[q] = sy[q] = 0.0;
           for (int j = lane; j < n1; j += wl) {
-            const cplx<double> g = gr[j], v = vl[j];
-            sx += g.x * v.x - g.y * v.y;
-            sy += g.x * v.y + g.y * v.x;
+            const cplx<double> v = vl[j];
+            cplx<double> g[RB];
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {  // rows past the end repeat row r0: loads unconditional
+              const int r = r0 + q * nwv < n1 ? r0 + q * nwv : r0;
+              g[q] = G[(size_t)(k + 1 + r) * ma + k + 1 + j];
+            }
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+              sx[q] += g[q].x * v.x - g[q].y * v.y;
+              sy[q] += g[q].x * v.y + g[q].y * v.x;
+            }
           }
-          sx = c.template gsum<64>(sx);
-          sy = c.template gsum<64>(sy);
-          if (lane == 0) {
-            pbx[r] = bt * sx;
-            pby[r] = bt * sy;
+#pragma unroll
+          for (int q = 0; q < RB; ++q) {
+            const int r = r0 + q * nwv;
+            if (r < n1) {
+              const double tx = c.template gsum<64>(sx[q]), ty = c.template gsum<64>(sy[q]);
+              if (lane == 0) {
+                pbx[r] = bt * tx;
+                pby[r] = bt * ty;
+              }
+            }
           }
         }
         c.sync();
@@ -1244,17 +1329,27 @@ struct KRRSolveTriG {
         double kk = 0.0;
         for (int r = lane; r < n1; r += wl) kk += vl[r].x * pbx[r] + vl[r].y * pby[r];
         kk = 0.5 * bt * c.template gsum<64>(kk);
-        for (int r = wv; r < n1; r += nwv) {
-          cplx<double>* gr = G + (size_t)(k + 1 + r) * ma + k + 1;
-          const cplx<double> vr = vl[r];
-          const double wrx = pbx[r] - kk * vr.x, wry = pby[r] - kk * vr.y;
+        for (int r0 = wv; r0 < n1; r0 += RB * nwv) {
           for (int j = lane; j < n1; j += wl) {
             const cplx<double> vj = vl[j];
             const double wjx = pbx[j] - kk * vj.x, wjy = pby[j] - kk * vj.y;
-            cplx<double> t = gr[j];
-            t.x -= (vr.x * wjx + vr.y * wjy) + (wrx * vj.x + wry * vj.y);
-            t.y -= (vr.y * wjx - vr.x * wjy) + (wry * vj.x - wrx * vj.y);
-            gr[j] = t;
+            cplx<double> t[RB];
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+              const int r = r0 + q * nwv < n1 ? r0 + q * nwv : r0;
+              t[q] = G[(size_t)(k + 1 + r) * ma + k + 1 + j];
+            }
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+              const int r = r0 + q * nwv;
+              if (r < n1) {
+                const cplx<double> vr = vl[r];
+                const double wrx = pbx[r] - kk * vr.x, wry = pby[r] - kk * vr.y;
+                t[q].x -= (vr.x * wjx + vr.y * wjy) + (wrx * vj.x + wry * vj.y);
+                t[q].y -= (vr.y * wjx - vr.x * wjy) + (wry * vj.x - wrx * vj.y);
+                G[(size_t)(k + 1 + r) * ma + k + 1 + j] = t[q];
+              }
+            }
           }
         }
         c.sync();
@@ -1302,36 +1397,10 @@ struct KRRSolveTriG {
                                    Tri::lu_stride(m), (double*)a.S, V,  a.A,  m,       a.theta};
     Tri::template tri_eigen<kRRTriMax>(c, tw, m, nb, ma);
     c.sync();
-    // C = L^{-H} W[:, :nb], W^T rows in A (stride m): column n per thread, the sums over
-    // k > i eight terms at a time
+    // C = L^{-H} W[:, :nb], W^T rows in A (stride m): column n per thread
     for (int n = tid; n < nb; n += nt) {
       a.eval[n] = a.theta[n];
-      for (int i = m - 1; i >= 0; --i) {
-        double ax[4] = {0.0, 0.0, 0.0, 0.0}, ay[4] = {0.0, 0.0, 0.0, 0.0};  // sum_{k > i} conj(L_ki) C_kn
-        int k = i + 1;
-        for (; k + 8 <= m; k += 8) {
-          cplx<double> l[8], x[8];
-#pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            l[q] = a.L[(size_t)(k + q) * m + i];
-            x[q] = a.Cd[(size_t)(k + q) * nb + n];
-          }
-#pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            ax[q & 3] += l[q].x * x[q].x + l[q].y * x[q].y;
-            ay[q & 3] += l[q].x * x[q].y - l[q].y * x[q].x;
-          }
-        }
-        for (; k < m; ++k) {
-          const cplx<double> l = a.L[(size_t)k * m + i], x = a.Cd[(size_t)k * nb + n];
-          ax[0] += l.x * x.x + l.y * x.y;
-          ay[0] += l.x * x.y - l.y * x.x;
-        }
-        const cplx<double> w = a.A[(size_t)n * m + i];
-        a.Cd[(size_t)i * nb + n] = cdiv_real(
-            mk<double>(w.x - ((ax[0] + ax[1]) + (ax[2] + ax[3])), w.y - ((ay[0] + ay[1]) + (ay[2] + ay[3]))),
-            a.L[(size_t)i * m + i].x);
-      }
+      tri_solve_col(a.L, m, a.A + (size_t)n * m, 1, false, a.Cd + n, nb, true);
     }
     c.sync();
     for (int e = tid; e < m * nb; e += nt) {
