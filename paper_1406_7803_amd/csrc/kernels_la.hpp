@@ -477,6 +477,105 @@ struct KRotate {
 };
 
 // ---------------------------------------------------------------------------
+// The same rotation for any m and 64 < nb <= 128 on the matrix cores: a workgroup of four
+// wavefronts takes 64 plane-wave columns (16 per wavefront, read straight from global memory
+// into registers, four k-steps of 4 rows at a time) and every band tile; C passes through
+// LDS in chunks of kRotChunk rows shared by the four wavefronts. Each wavefront writes its
+// nb output rows after it has read all m rows of its columns. grid (ceil(npw / 64), 2, n).
+// ---------------------------------------------------------------------------
+constexpr int kRotChunk = 16;
+
+template <typename T>
+struct KRotateChunk {
+  static constexpr int MT = 8;  // band tiles: nb <= 128
+  FDE_HD static size_t lds_bytes(int nb) { return sizeof(cplx<T>) * (size_t)kRotChunk * nb; }
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const ProbSet<T> ps) {
+    const Prob<T>& P = ps.p[c.bz()];
+    const int m = P.m, nb = P.nb, npw = P.npw;
+    const int g0 = c.bx() * 64;
+    if (g0 >= npw) return;  // uniform per block
+    cplx<T>* M = c.by() == 0 ? P.v : P.hv;
+    const cplx<T>* Cg = (const cplx<T>*)P.Ct;
+    cplx<T>* sC = (cplx<T>*)lds;  // [kRotChunk][nb]
+#if defined(__HIP_DEVICE_COMPILE__)
+    const int lane = c.tid() & 63, w = c.tid() >> 6;
+    const int col = lane & 15, kq = lane >> 4;
+    const int g = g0 + 16 * w + col;
+    const bool gin = g < npw;
+    typedef T v4 __attribute__((ext_vector_type(4)));
+    v4 re[MT], im[MT];
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      re[t] = v4{0, 0, 0, 0};
+      im[t] = v4{0, 0, 0, 0};
+    }
+    const int nmt = (nb + 15) / 16;
+    for (int k0 = 0; k0 < m; k0 += kRotChunk) {
+      const int kc = (m - k0) < kRotChunk ? (m - k0) : kRotChunk;
+      c.sync();  // the previous chunk is consumed
+      for (int idx = c.tid(); idx < kRotChunk * nb; idx += c.nthr())
+        sC[idx] = idx < kc * nb ? Cg[(size_t)k0 * nb + idx] : mk<T>(0, 0);
+      // V rows k0 + 4 s + kq of this lane's column, all loads of the chunk issued together
+      cplx<T> b[kRotChunk / 4];
+#pragma unroll
+      for (int s4 = 0; s4 < kRotChunk / 4; ++s4) {
+        const int k = k0 + 4 * s4 + kq;
+        b[s4] = (gin && k < m) ? M[(size_t)k * npw + g] : mk<T>(0, 0);
+      }
+      c.sync();
+#pragma unroll
+      for (int s4 = 0; s4 < kRotChunk / 4; ++s4) {
+        const int kl = 4 * s4 + kq;  // row within the chunk (zero beyond kc)
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+          if (t >= nmt) break;
+          const int n = 16 * t + col;
+          const cplx<T> a_ = n < nb ? sC[kl * nb + n] : mk<T>(0, 0);
+          if constexpr (sizeof(T) == 8) {
+            re[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_.x, b[s4].x, re[t], 0, 0, 0);
+            re[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_.y, b[s4].y, re[t], 0, 0, 0);
+            im[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_.x, b[s4].y, im[t], 0, 0, 0);
+            im[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_.y, b[s4].x, im[t], 0, 0, 0);
+          } else {
+            re[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_.x, b[s4].x, re[t], 0, 0, 0);
+            re[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a_.y, b[s4].y, re[t], 0, 0, 0);
+            im[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_.x, b[s4].y, im[t], 0, 0, 0);
+            im[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_.y, b[s4].x, im[t], 0, 0, 0);
+          }
+        }
+      }
+    }
+    if (gin) {
+#pragma unroll
+      for (int t = 0; t < MT; ++t) {
+        if (t >= nmt) break;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          // output row of register r: FP64 MFMA 4 r + l/16, FP32 MFMA 4 (l/16) + r
+          const int n = 16 * t + (sizeof(T) == 8 ? 4 * r + kq : 4 * kq + r);
+          if (n < nb) M[(size_t)n * npw + g] = mk<T>(re[t][r], im[t][r]);
+        }
+      }
+    }
+#else
+    // host: column by column, all m rows read before the nb rows are written
+    for (int gg = g0; gg < g0 + 64 && gg < npw; ++gg) {
+      cplx<T>* v = new cplx<T>[m];
+      for (int k = 0; k < m; ++k) v[k] = M[(size_t)k * npw + gg];
+      for (int n = 0; n < nb; ++n) {
+        cplx<T> acc = mk<T>(0, 0);
+        for (int k = 0; k < m; ++k) acc = acc + v[k] * Cg[(size_t)k * nb + n];
+        M[(size_t)n * npw + gg] = acc;
+      }
+      delete[] v;
+    }
+    (void)sC;
+#endif
+  }
+};
+
+// ---------------------------------------------------------------------------
 // The same rotation streamed (m <= 4 kRotSteps, nb <= 64): C staged once per
 // workgroup in LDS; each wavefront takes groups of 16 plane-wave columns in turn,
 // loads all m rows of its group straight into registers (no LDS staging of V),

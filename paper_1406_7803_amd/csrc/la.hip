@@ -139,6 +139,10 @@ static fde_status rr_launch(fde_plan* p, ProbSet<T>& ps, hipStream_t s) {
     return launch<KRotateStream<T>, 256, 3>(dim3(gx, 2, ps.n), kBlock, KRotateStream<T>::lds_bytes(mmax, nbmax), s,
                                             ps, gx);
   }
+  // matrix cores with C in chunks through LDS (up to 128 bands)
+  if (nbmax <= 128)
+    return launch<KRotateChunk<T>, 256>(dim3((npwmax + 63) / 64, 2, ps.n), 256, KRotateChunk<T>::lds_bytes(nbmax), s,
+                                        ps);
   // in-place rotation: plane-wave chunk of all m rows (+ C when it fits) in LDS
   const size_t cs = sizeof(cplx<T>);
   int GC = 64;

@@ -62,6 +62,8 @@ def test_subspace_rr(be, prec, drop):
 def test_subspace_rr_large_m(be, prec):
     pc.check_subspace_rr(be, prec, nb=45, case=pc.MEDIUM)
     pc.check_subspace_rr(be, prec, drop_case=True, nb=40, case=pc.MEDIUM)
+    # m = 200, 100 bands: rotation on the matrix cores with C in chunks
+    pc.check_subspace_rr(be, prec, nb=100, case=pc.MEDIUM)
     # m = 280 > 256: back-transformation with twelve rows per lane
     pc.check_subspace_rr(be, prec, nb=140, case=pc.MEDIUM)
     pc.check_subspace_rr(be, prec, drop_case=True, nb=140, case=pc.MEDIUM)
