@@ -56,6 +56,9 @@ struct KAhB {
     const int ntj = (P.mb + TJ - 1) / TJ;
     const int nti = (P.ma + TI - 1) / TI;
     if (c.bx() >= P.nchunk || c.by() >= nti * ntj) return;  // uniform per block
+    // Gram products (A = B0, square): lower tiles only, written with their mirror
+    const bool herm = P.B1 != nullptr && P.A == P.B0 && P.ma == P.mb;
+    if (herm && c.by() % ntj > c.by() / ntj) return;  // uniform per block
     const int i0 = (c.by() / ntj) * TI, j0 = (c.by() % ntj) * TJ;
     const int g0 = c.bx() * P.chunk;
     const int gend = (g0 + P.chunk) < P.npw ? (g0 + P.chunk) : P.npw;
@@ -132,17 +135,25 @@ struct KAhB {
     const int j = j0 + wj * 16 + (lane & 15);
     for (int r = 0; r < 4; ++r) {
       const int i = i0 + wi * 16 + 4 * r + (lane >> 4);
-      if (i < P.ma && j < P.mb) {
+      if (i < P.ma && j < P.mb && (!herm || j <= i)) {
         out[(size_t)i * P.mb + j] = mk<double>(re0[r], im0[r]);
         if (two) out[mab + (size_t)i * P.mb + j] = mk<double>(re1[r], im1[r]);
+        if (herm && j < i) {
+          out[(size_t)j * P.mb + i] = mk<double>(re0[r], -im0[r]);
+          out[mab + (size_t)j * P.mb + i] = mk<double>(re1[r], -im1[r]);
+        }
       }
     }
 #else
     for (int o = c.tid(); o < TI * TJ; o += c.nthr()) {
       const int i = i0 + o / TJ, j = j0 + o % TJ;
-      if (i < P.ma && j < P.mb) {
+      if (i < P.ma && j < P.mb && (!herm || j <= i)) {
         out[(size_t)i * P.mb + j] = acc[o];
         if (two) out[mab + (size_t)i * P.mb + j] = acc[TI * TJ + o];
+        if (herm && j < i) {
+          out[(size_t)j * P.mb + i] = conj(acc[o]);
+          out[mab + (size_t)j * P.mb + i] = conj(acc[TI * TJ + o]);
+        }
       }
     }
 #endif
