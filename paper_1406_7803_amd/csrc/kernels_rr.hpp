@@ -58,6 +58,54 @@ FDE_HD int qdiv(int e, float inv_n) { return (int)(((float)e + 0.5f) * inv_n); }
 // triangle U (Hermitian, lower storage); L parked in the problem's global L and its diagonal in
 // sdiag. Returns false, with C = I, NaN eigenvalues and info = j + 1 written, when band column j
 // has no positive pivot (uniform over the workgroup).
+#if defined(__HIP_DEVICE_COMPILE__)
+// Forward substitution in place on the m x m matrix M (ld = m + 1) with the packed lower
+// triangle L in U: columns of B = L^{-1} M (ROWS false) or rows of E = M L^{-H} (ROWS true).
+// A column (row) belongs to a group of 8 lanes; lane g keeps entries i = g + 8 s in
+// registers; step i divides entry i by L_ii on its owner, broadcasts it within the group and
+// removes it from the entries below. Needs 8 m threads; m <= kRRLdsMax.
+template <bool ROWS>
+__device__ void tri_lanes(const DevCtx& c, const cplx<double>* U, cplx<double>* M, int m) {
+  constexpr int R = (kRRLdsMax + 7) / 8;
+  const int ld = m + 1, g = c.tid() & 7, grp = c.tid() >> 3;
+  if (grp >= m) return;  // uniform per group; no barrier inside
+  cplx<double> z[R];
+#pragma unroll
+  for (int s = 0; s < R; ++s) {
+    const int r = g + 8 * s;
+    z[s] = r < m ? M[ROWS ? (size_t)grp * ld + r : (size_t)r * ld + grp] : mk<double>(0.0, 0.0);
+  }
+#pragma unroll
+  for (int s = 0; s < R; ++s) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int i = 8 * s + q;
+      if (i >= m) break;  // uniform
+      const double inv = 1.0 / U[tri(i, i)].x;
+      const cplx<double> val = mk<double>(z[s].x * inv, z[s].y * inv);
+      const cplx<double> bi = mk<double>(__shfl(val.x, q, 8), __shfl(val.y, q, 8));
+      if (g == q) z[s] = bi;
+#pragma unroll
+      for (int t = s; t < R; ++t) {
+        const int r = g + 8 * t;
+        const bool below = r > i && r < m;
+        const int rc = r < m ? r : m - 1;  // in bounds for every lane
+        const cplx<double> u = U[tri(rc, i)];
+        const double ly = ROWS ? -u.y : u.y;  // E: conj(L_ri)
+        const double lx = below ? u.x : 0.0, lyy = below ? ly : 0.0;
+        z[t].x -= lx * bi.x - lyy * bi.y;
+        z[t].y -= lx * bi.y + lyy * bi.x;
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < R; ++s) {
+    const int r = g + 8 * s;
+    if (r < m) M[ROWS ? (size_t)grp * ld + r : (size_t)r * ld + grp] = z[s];
+  }
+}
+#endif
+
 template <typename T, class Ctx>
 FDE_HD bool rr_front(const Ctx& c, const Prob<T>& a, double drop_tol, cplx<double>* U, cplx<double>* M,
                      double* sdiag, int* masked) {
@@ -123,6 +171,14 @@ FDE_HD bool rr_front(const Ctx& c, const Prob<T>& a, double drop_tol, cplx<doubl
     const int i = qdiv(e, inv_m), j = e - i * m;
     M[(size_t)i * ld + j] = (masked[i] || masked[j]) ? mk<double>(i == j ? kInactiveDiag : 0.0, 0.0) : a.A[e];
   }
+#if defined(__HIP_DEVICE_COMPILE__)
+  // ---- B = L^{-1} A by columns, then E = B L^{-H} by rows, each in registers of 8-lane groups
+  c.sync();
+  tri_lanes<false>(c, U, M, m);
+  c.sync();
+  tri_lanes<true>(c, U, M, m);
+  c.sync();
+#else
   // ---- B = L^{-1} A: step i removes row i's contribution from the rows below
   for (int i = 0; i < m; ++i) {
     c.sync();
@@ -158,16 +214,21 @@ FDE_HD bool rr_front(const Ctx& c, const Prob<T>& a, double drop_tol, cplx<doubl
     }
   }
   c.sync();
-  // ---- park L in global memory (its diagonal also in sdiag); A~ = (E + E^H)/2 into U,
-  //      with E_ij = M_ij / L_jj (the column scaling of the last substitution)
+  for (int e = tid; e < m * m; e += nt) {  // E_ij = M_ij / L_jj
+    const int i = qdiv(e, inv_m), j = e - i * m;
+    M[(size_t)i * ld + j] = cdiv_real(M[(size_t)i * ld + j], U[tri(j, j)].x);
+  }
+  c.sync();
+#endif
+  // ---- park L in global memory (its diagonal also in sdiag); A~ = (E + E^H)/2 into U
   for (int e = tid; e < m * (m + 1) / 2; e += nt) a.L[e] = U[e];
   for (int i = tid; i < m; i += nt) sdiag[i] = U[tri(i, i)].x;
   c.sync();
   for (int e = tid; e < m * m; e += nt) {
     const int i = qdiv(e, inv_m), j = e - i * m;
     if (j > i) continue;
-    const cplx<double> eij = cdiv_real(M[(size_t)i * ld + j], sdiag[j]);
-    const cplx<double> eji = cdiv_real(M[(size_t)j * ld + i], sdiag[i]);
+    const cplx<double> eij = M[(size_t)i * ld + j];
+    const cplx<double> eji = M[(size_t)j * ld + i];
     U[tri(i, j)] = i == j ? mk<double>(eij.x, 0.0) : mk<double>(0.5 * (eji.x + eij.x), 0.5 * (eij.y - eji.y));
   }
   c.sync();
