@@ -104,6 +104,49 @@ __device__ void tri_lanes(const DevCtx& c, const cplx<double>* U, cplx<double>* 
     if (r < m) M[ROWS ? (size_t)grp * ld + r : (size_t)r * ld + grp] = z[s];
   }
 }
+
+// Backward substitution C = L^{-H} W in place on the rows order[n] (n < nb) of M: a row
+// belongs to a group of 8 lanes holding entries i = g + 8 s; step i (descending) divides
+// entry i by L_ii on its owner, broadcasts it and removes it from the entries above.
+__device__ void tri_lanes_back(const DevCtx& c, const cplx<double>* U, cplx<double>* M, int m, int nb,
+                               const int* order) {
+  constexpr int R = (kRRLdsMax + 7) / 8;
+  const int ld = m + 1, g = c.tid() & 7, grp = c.tid() >> 3;
+  if (grp >= nb) return;  // uniform per group; no barrier inside
+  cplx<double>* row = M + (size_t)order[grp] * ld;
+  cplx<double> z[R];
+#pragma unroll
+  for (int s = 0; s < R; ++s) {
+    const int r = g + 8 * s;
+    z[s] = r < m ? row[r] : mk<double>(0.0, 0.0);
+  }
+#pragma unroll
+  for (int s = R - 1; s >= 0; --s) {
+#pragma unroll
+    for (int q = 7; q >= 0; --q) {
+      const int i = 8 * s + q;
+      if (i >= m) continue;  // uniform
+      const double inv = 1.0 / U[tri(i, i)].x;
+      const cplx<double> val = mk<double>(z[s].x * inv, z[s].y * inv);
+      const cplx<double> ci = mk<double>(__shfl(val.x, q, 8), __shfl(val.y, q, 8));
+      if (g == q) z[s] = ci;
+#pragma unroll
+      for (int t = 0; t <= s; ++t) {
+        const int r = g + 8 * t;
+        const bool above = r < i;
+        const cplx<double> u = U[tri(i, above ? r : i)];  // L_ir, in bounds for every lane
+        const double lx = above ? u.x : 0.0, ly = above ? -u.y : 0.0;  // conj(L_ir)
+        z[t].x -= lx * ci.x - ly * ci.y;
+        z[t].y -= lx * ci.y + ly * ci.x;
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < R; ++s) {
+    const int r = g + 8 * s;
+    if (r < m) row[r] = z[s];
+  }
+}
 #endif
 
 template <typename T, class Ctx>
@@ -247,6 +290,14 @@ FDE_HD void rr_tail(const Ctx& c, const Prob<T>& a, cplx<double>* U, cplx<double
   for (int e = tid; e < m * (m + 1) / 2; e += nt) U[e] = a.L[e];
   for (int n = tid; n < nb; n += nt) a.eval[n] = a.theta[order[n]];
   const float inv_nb = 1.0f / (float)nb;
+#if defined(__HIP_DEVICE_COMPILE__)
+  c.sync();
+  tri_lanes_back(c, U, M, m, nb, order);  // C rows divided by L_ii
+  c.sync();
+  for (int e = tid; e < m * nb; e += nt) {
+    const int i = qdiv(e, inv_nb), n = e - i * nb;
+    const cplx<double> v = M[(size_t)order[n] * ld + i];
+#else
   for (int i = m - 1; i >= 0; --i) {
     c.sync();
     // row i of C is final: C_i = W_i / L_ii; remove it from the rows above
@@ -264,6 +315,7 @@ FDE_HD void rr_tail(const Ctx& c, const Prob<T>& a, cplx<double>* U, cplx<double
   for (int e = tid; e < m * nb; e += nt) {
     const int i = qdiv(e, inv_nb), n = e - i * nb;
     const cplx<double> v = cdiv_real(M[(size_t)order[n] * ld + i], sdiag[i]);
+#endif
     a.Cd[e] = v;
     ((cplx<T>*)a.Ct)[e] = mk<T>((T)v.x, (T)v.y);
   }
