@@ -276,3 +276,38 @@ def test_stream_groups_match_single_group(be, prec):
             assert np.array_equal(pc.host(a), pc.host(c)), k
         assert np.array_equal(pc.host(e1.rho_in), pc.host(e2.rho_in)), k
         assert np.array_equal(pc.host(e1.rho_in), pc.host(eg.rho_in)), k
+
+
+def test_c3_cycle_properties(be):
+    """One FP32 cycle of the 64-subsystem cube at full size (242 blocks, m = 2 nb up to 256:
+    the global tridiagonal solver, the chunked rotation and the lower-tile Gram products).
+    The oracle cannot run this cell, so properties that any correct Rayleigh-Ritz step and
+    density must satisfy are checked on the largest blocks and a small one: X orthonormal,
+    X^H (H X) diagonal with the Ritz values on it, H X equal to a fresh H application of X,
+    Ritz values ascending, every subsystem's charge equal to its electron count."""
+    from paper_1406_7803_amd import driver
+    s = fde_synth.config3()
+    eng = driver.Engine(s, prec=fde.F32, backend=be)
+    eng.cycle()
+    be.sync()
+    blocks = [b for row in eng.blocks for b in row]
+    assert all(int(pc.host(b.info)[0]) == 0 for b in blocks)
+    by_nb = sorted(blocks, key=lambda b: b.nb)
+    sample = by_nb[-2:] + [next((b for b in by_nb if 32 < b.nb <= 64), by_nb[len(by_nb) // 2]), by_nb[0]]
+    for b in sample:
+        X = pc.host(b.V[:b.nb]).astype(np.complex128)
+        HX = pc.host(b.HV[:b.nb]).astype(np.complex128)
+        ev = pc.host(b.eval)
+        assert np.all(np.diff(ev) >= -1e-12), b.nb
+        G = X.conj() @ X.T
+        assert np.max(np.abs(G - np.eye(b.nb))) < 1e-4, (b.nb, np.max(np.abs(G - np.eye(b.nb))))
+        A = X.conj() @ HX.T
+        scale = max(1.0, float(np.max(np.abs(ev))))
+        assert np.max(np.abs(np.diag(A).real - ev)) < 1e-4 * scale, b.nb
+        assert np.max(np.abs(A - np.diag(np.diag(A)))) < 1e-4 * scale, b.nb
+        fresh = pc.host(eng.plan.apply_h(b.ik, b.V[:b.nb], eng.veff[b.isub], b.beta, b.dkb))
+        assert pc.rel(fresh.astype(np.complex128), HX) < 1e-4, b.nb
+    dv = float(np.prod(s.L)) / float(np.prod(s.grid))
+    for I, sub in enumerate(s.subsystems):
+        q = float(pc.host(eng.rho_out[I]).astype(np.float64).sum()) * dv
+        assert abs(q - sub.nelec) < 1e-3 * max(1.0, sub.nelec), (I, q, sub.nelec)
