@@ -954,7 +954,17 @@ struct KRRSolveTri {
     cplx<double>* Wt;
     int ld;
     double* theta;
+    // optional: per-wavefront LDS slots (factors, pivots, working vector) of luls bytes for
+    // the first nlw wavefronts, which then take every cluster's inverse iteration
+    char* lul = nullptr;
+    size_t luls = 0;
+    int nlw = 0;
   };
+  // bytes of one wavefront's LDS slot for the inverse iteration of an m-row problem
+  FDE_HD static size_t lul_stride(int m) {
+    return ((((size_t)m * (4 * sizeof(double) + 1) + 15) & ~(size_t)15) + (size_t)m * sizeof(double) + 15) &
+           ~(size_t)15;
+  }
 
   // Back-transformation of NV eigenvectors at a time per group of GL lanes: z = D y in
   // registers (rows i = gl + GL s), then H_k z for k = ma - 2 .. 0; each reflector's entries
@@ -1238,9 +1248,15 @@ struct KRRSolveTri {
       c.sync();
       // inverse iteration, one cluster (or failed single) per wavefront
       const int ncl = cls[m + 2];
-      double* lu = (double*)(w.lu + (size_t)wv * w.lus);
+      // factors and the working vector in LDS when the problem has per-wavefront slots there
+      // (the serial LU passes then wait on LDS, not global memory); results go to Y either way
+      const bool lds_it = w.lul != nullptr;
+      const int nit = lds_it && w.nlw < nwv ? w.nlw : nwv;  // wavefronts taking clusters
+      double* lu = lds_it ? (double*)(w.lul + (size_t)wv * w.luls) : (double*)(w.lu + (size_t)wv * w.lus);
       unsigned char* piv = (unsigned char*)(lu + 4 * ma);
-      for (int ci = wv; ci < ncl; ci += nwv) {
+      double* yl = lds_it ? (double*)((char*)lu + (((size_t)ma * (4 * sizeof(double) + 1) + 15) & ~(size_t)15))
+                          : nullptr;
+      for (int ci = wv; wv < nit && ci < ncl; ci += nit) {
         const int j0 = cls[ci], j1 = cls[ci + 1];
         if (j1 - j0 == 1 && lo[j0] == 0.0) continue;
         double lprev = 0.0;
@@ -1248,7 +1264,8 @@ struct KRRSolveTri {
           double lj = lam[j];
           if (j > j0 && lj - lprev < pertol) lj = lprev + pertol;
           lprev = lj;
-          double* y = Y + (size_t)j * ma;
+          double* const yout = Y + (size_t)j * ma;
+          double* y = lds_it ? yl : yout;
           for (int i = lane; i < ma; i += wl) y[i] = start_value(i, j);
           if (lane == 0) lu_factor<Ctx>(ma, dg, ea, lj, eps * tnorm, lu, piv);
           c.wsync();
@@ -1271,6 +1288,10 @@ struct KRRSolveTri {
             } else {
               for (int i = lane; i < ma; i += wl) y[i] = i == j % ma ? 1.0 : 0.0;
             }
+            c.wsync();
+          }
+          if (lds_it) {
+            for (int i = lane; i < ma; i += wl) yout[i] = y[i];
             c.wsync();
           }
         }
@@ -1362,8 +1383,18 @@ template <typename T>
 struct KRRSolveTriG {
   using Tri = KRRSolveTri<T>;
   static constexpr int kThreads = Tri::kThreads;
-  FDE_HD static size_t lds_bytes(int m) {
+  FDE_HD static size_t base_bytes(int m) {
     return sizeof(double) * (32 + 15 * (size_t)m) + sizeof(int) * (2 * (size_t)m + 3 + kThreads) + 64;
+  }
+  // wavefronts with an LDS slot for the inverse iteration: as many as fit 160 KiB, none
+  // below four (the factors then stay in global memory)
+  FDE_HD static int lds_waves(int m) {
+    const size_t base = (base_bytes(m) + 15) & ~(size_t)15, lim = 160 * 1024;
+    const int n = base < lim ? (int)((lim - base) / Tri::lul_stride(m)) : 0;
+    return n < 4 ? 0 : (n < Tri::kWaves ? n : Tri::kWaves);
+  }
+  FDE_HD static size_t lds_bytes(int m) {
+    return ((base_bytes(m) + 15) & ~(size_t)15) + (size_t)lds_waves(m) * Tri::lul_stride(m);
   }
 
   // Householder reduction of the active block held with both triangles in G (row-major, ld ma,
@@ -1505,9 +1536,17 @@ struct KRRSolveTriG {
     // reflectors behind the inverse-iteration vectors (which take at most m * m doubles of S)
     cplx<double>* V = (cplx<double>*)((double*)a.S + (size_t)m * m);
     house_full(c, G, V, vl, ma, dg, beta, ar, ai, pbx, pby);
-    const typename Tri::TriWork tw{dg,  e2,     ea,       beta, ar, ai,    dre,  dim,     lam,
-                                   lo,  hi,     act,      cls,  a.masked, cnt, (char*)a.B,
-                                   Tri::lu_stride(m), (double*)a.S, V,  a.A,  m,       a.theta};
+    typename Tri::TriWork tw{dg,  e2,     ea,       beta, ar, ai,    dre,  dim,     lam,
+                             lo,  hi,     act,      cls,  a.masked, cnt, (char*)a.B,
+                             Tri::lu_stride(m), (double*)a.S, V,  a.A,  m,       a.theta};
+    // the launch sized LDS for the batch's largest m: slots of that size
+    int mmax = 0;
+    for (int q = 0; q < ps.n; ++q) mmax = ps.p[q].m > mmax ? ps.p[q].m : mmax;
+    if (lds_waves(mmax) > 0) {
+      tw.lul = lds + ((base_bytes(mmax) + 15) & ~(size_t)15);
+      tw.luls = Tri::lul_stride(mmax);
+      tw.nlw = lds_waves(mmax);
+    }
     Tri::template tri_eigen<kRRTriMax>(c, tw, m, nb, ma);
     c.sync();
     // C = L^{-H} W[:, :nb], W^T rows in A (stride m): column n per thread
