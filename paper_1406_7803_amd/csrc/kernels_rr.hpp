@@ -1373,10 +1373,11 @@ struct KRRSolveTri {
 
 // Rayleigh-Ritz solve of one band block too large for the LDS solvers (kRRLdsMax < m <=
 // kRRTriMax), matrices in global memory: the front end of KRRSolve (Cholesky, A~), then the
-// tridiagonal route of KRRSolveTri on the packed lower triangle of (A~ + A~^H)/2 held in the
-// problem's W buffer (per-column arrays in LDS; B holds the compaction, the twisted
-// factorisations and the LU factors, S the tridiagonal eigenvectors, A the W^T rows), and
-// C = L^{-H} W one column per thread.
+// Householder reduction of (A~ + A~^H)/2 on the active rows and columns, held with both
+// triangles in the problem's W buffer, and the tridiagonal route of KRRSolveTri (per-column
+// arrays in LDS; B holds the twisted factorisations and, when no LDS slots fit, the LU
+// factors; S the tridiagonal eigenvectors and, behind them, the reflectors; A the W^T rows),
+// and C = L^{-H} W one column per thread in blocks of 8 rows.
 constexpr int kRRTriMax = 768;
 
 template <typename T>
