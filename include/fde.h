@@ -214,7 +214,11 @@ fde_status fde_embed_potential(fde_plan* plan, int ns, const void* rho_sub, cons
  *   S = V^H V, A = V^H HV accumulated in FP64; inactive columns (active[j]
  *   = 0) and columns j >= nb whose Cholesky pivot falls below drop_tol*S_jj
  *   are masked (S = e_j, A = 1e6 e_j); S = L L^H; A~ = L^{-1} A L^{-H};
- *   A~ W = W Theta (FP64 Jacobi, ascending); C = L^{-H} W[:, :nb];
+ *   A~ W = W Theta in FP64, ascending (for m <= 768: Householder reduction to
+ *   a real tridiagonal, multisection on Sturm counts, twisted factorisations
+ *   and, for clustered eigenvalues, inverse iteration; cyclic Jacobi beyond
+ *   that or where the tridiagonal workspace does not fit in LDS);
+ *   C = L^{-H} W[:, :nb];
  *   rows 0..nb-1 of v and hv are overwritten with X = V C and HX = HV C.
  *   active  [m] uint8 or NULL (all active).
  *   eval    [nb] double, output Theta[:nb].
