@@ -277,8 +277,9 @@ struct KAssemble {
   }
 };
 
+// 3-D FFT of `count` grids in place, gstride elements apart (one launch per axis for all)
 template <typename T>
-static fde_status fft3(fde_plan* p, cplx<T>* w, bool inv, hipStream_t s) {
+static fde_status fft3(fde_plan* p, cplx<T>* w, bool inv, hipStream_t s, int count = 1, size_t gstride = 0) {
   const int N1 = p->N[0], N2 = p->N[1], N3 = p->N[2];
   for (int axis = 0; axis < 3; ++axis) {
     const int n = p->N[axis];
@@ -286,11 +287,13 @@ static fde_status fft3(fde_plan* p, cplx<T>* w, bool inv, hipStream_t s) {
     while (L > 1 && (2 * (size_t)L * n + n) * sizeof(cplx<T>) > 64 * 1024) L /= 2;
     const size_t lds = (2 * (size_t)L * n + n) * sizeof(cplx<T>);
     dim3 grid;
-    if (axis == 0) grid = dim3((N2 * N3 + L - 1) / L);
-    else grid = dim3((N1 + L - 1) / L, axis == 1 ? N3 : N2);
+    if (axis == 0) grid = dim3((N2 * N3 + L - 1) / L, 1, count);
+    else grid = dim3((N1 + L - 1) / L, axis == 1 ? N3 : N2, count);
     const cplx<T>* tw = (const cplx<T>*)p->d_tw[axis];
-    if (inv) FDE_TRY(launch<KFftAxis<T, true>>(grid, kBlock, lds, s, w, N1, N2, N3, axis, p->rad[axis], tw, L));
-    else FDE_TRY(launch<KFftAxis<T, false>>(grid, kBlock, lds, s, w, N1, N2, N3, axis, p->rad[axis], tw, L));
+    if (inv)
+      FDE_TRY(launch<KFftAxis<T, true>>(grid, kBlock, lds, s, w, gstride, N1, N2, N3, axis, p->rad[axis], tw, L));
+    else
+      FDE_TRY(launch<KFftAxis<T, false>>(grid, kBlock, lds, s, w, gstride, N1, N2, N3, axis, p->rad[axis], tw, L));
   }
   return FDE_OK;
 }
@@ -359,17 +362,13 @@ static fde_status kinetic_and_hartree(fde_plan* p, EmbedWs<T>& e, const T* X, T*
   }
   // gradient
   FDE_TRY(launch<KGradPrep<T>>(dim3(nb), kBlock, 0, s, (const cplx<T>*)e.W0, e.W1, e.W2, e.W3, g, nb));
-  FDE_TRY(fft3<T>(p, e.W1, true, s));
-  FDE_TRY(fft3<T>(p, e.W2, true, s));
-  FDE_TRY(fft3<T>(p, e.W3, true, s));
+  FDE_TRY(fft3<T>(p, e.W1, true, s, 3, (size_t)(e.W2 - e.W1)));  // the three components, W1..W3
   FDE_TRY(launch<KKedfPoint<T>>(dim3(nb), kBlock, red, s, X, e.W1, e.W2, e.W3, vout, n, 2, kc, f->rho_thr, e.part,
                                 nb));
   FDE_TRY(launch<KRedFinal>(dim3(1), kBlock, red, s, (const double*)e.part, (int)nb, dV, erow, (int)FDE_E_KIN, -1, -1,
                             -1, -1, -1, -1, -1));
   // divergence of h
-  FDE_TRY(fft3<T>(p, e.W1, false, s));
-  FDE_TRY(fft3<T>(p, e.W2, false, s));
-  FDE_TRY(fft3<T>(p, e.W3, false, s));
+  FDE_TRY(fft3<T>(p, e.W1, false, s, 3, (size_t)(e.W2 - e.W1)));
   FDE_TRY(launch<KDivPrep<T>>(dim3(nb), kBlock, 0, s, e.W0, (const cplx<T>*)e.W1, (const cplx<T>*)e.W2,
                               (const cplx<T>*)e.W3, g, invN, nb));
   FDE_TRY(fft3<T>(p, e.W0, true, s));

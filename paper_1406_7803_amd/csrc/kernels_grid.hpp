@@ -28,15 +28,18 @@ FDE_HD void grid_g(const GridGeo& g, size_t i, double& gx, double& gy, double& g
 }
 
 // ---------------------------------------------------------------------------
-// One batched pass of a 3-D FFT along `axis` (0: x, 1: y, 2: z) over a
-// complex grid [N3][N2][N1] in place. L lines per workgroup.
-//   axis 0: grid (ceil(N2*N3/L));  axis 1: grid (ceil(N1/L), N3);  axis 2: grid (ceil(N1/L), N2)
+// One batched pass of a 3-D FFT along `axis` (0: x, 1: y, 2: z) over complex
+// grids [N3][N2][N1] in place, grid z of them gstride elements apart. L lines per
+// workgroup.
+//   axis 0: grid (ceil(N2*N3/L), 1, count);  axis 1: grid (ceil(N1/L), N3, count);
+//   axis 2: grid (ceil(N1/L), N2, count)
 // ---------------------------------------------------------------------------
 template <typename T, bool INV>
 struct KFftAxis {
   template <class Ctx>
-  FDE_HD static void run(const Ctx& c, char* lds, cplx<T>* __restrict__ data, int N1, int N2, int N3, int axis,
-                         Radix r, const cplx<T>* __restrict__ tw, int L) {
+  FDE_HD static void run(const Ctx& c, char* lds, cplx<T>* __restrict__ data, size_t gstride, int N1, int N2, int N3,
+                         int axis, Radix r, const cplx<T>* __restrict__ tw, int L) {
+    data += (size_t)c.bz() * gstride;
     const int n = r.n;
     cplx<T>* a = (cplx<T>*)lds;
     cplx<T>* b = a + (size_t)L * n;
