@@ -149,6 +149,8 @@ def check_local_potential(be, prec):
 
 
 MEDIUM = dict(L=(8.0, 8.0, 9.0), grid=(18, 18, 20), ecut=5.0, kf=[(0.25, 0.0, -0.25)])
+# 1877 plane waves: room for m = 600 (the global solver with its inverse-iteration factors in global memory)
+LARGE = dict(L=(12.0, 12.0, 12.0), grid=(32, 32, 32), ecut=8.0, kf=[(0.25, 0.0, -0.25)])
 
 
 # Ritz values / projector tolerances per subspace-product mode (FP32 plans); BF16x3

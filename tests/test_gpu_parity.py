@@ -64,6 +64,8 @@ def test_subspace_rr_large_m(be, prec):
     # m = 280 > 256: back-transformation with twelve rows per lane
     pc.check_subspace_rr(be, prec, nb=140, case=pc.MEDIUM)
     pc.check_subspace_rr(be, prec, drop_case=True, nb=140, case=pc.MEDIUM)
+    # m = 600 > 545: no LDS slots for the inverse iteration, factors in global memory
+    pc.check_subspace_rr(be, prec, nb=300, case=pc.LARGE)
 
 
 def test_singular_gram(be):
