@@ -224,6 +224,27 @@ def config3(geometry: int = 0, nsub: int = 64) -> System:
     return System(3, geometry, L, (72, 72, 72), 15.0, subs, n_cycles=10, n_david=4)
 
 
+def config3_reduced(geometry: int = 0) -> System:
+    """Six uneven subsystems in a 12 bohr cube on a 30^3 grid (E_cut 5 Ha): a cell the
+    CPU reference can follow for a few cycles, with the unevenness of the 64-subsystem
+    cube -- 4 to 48 bands, 1 to 4 k-points, Fermi-Dirac 0.01 Ha, 2 floor(0.8 nb)
+    electrons on ceil(N_e / 4) Gaussian ions each (width 0.8, >= 1.6 bohr apart)."""
+    rng = rng_for(6, geometry)
+    L = (12.0, 12.0, 12.0)
+    existing: List[np.ndarray] = []
+    subs = []
+    for i, (nb, nk) in enumerate([(4, 1), (6, 2), (10, 4), (16, 1), (30, 2), (48, 1)]):
+        ne = 2.0 * math.floor(0.8 * nb)
+        nat = max(1, int(math.ceil(ne / 4.0)))
+        pos = _place_uniform(rng, nat, L, 1.6, existing)
+        existing.extend(pos)
+        atoms = [Atom(tuple(map(float, p)), ne / nat, 0.8) for p in pos]
+        k, w = mp_mesh(*_C3_MESH[nk])
+        subs.append(Subsystem(f"u{i}", atoms, nbands=nb, nelec=ne, kfrac=k, kweight=w,
+                              smearing="fermi-dirac", sigma=0.01))
+    return System(6, geometry, L, (30, 30, 30), 5.0, subs, n_cycles=3, n_david=4)
+
+
 def config4(geometry: int = 0) -> System:
     """144-atom slab (s+p projectors, 2 k, 320 bands) + 4 molecules, 144x144x432 grid."""
     rng = rng_for(4, geometry)

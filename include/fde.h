@@ -280,7 +280,8 @@ enum { FDE_OCC_INTEGER = 0, FDE_OCC_FERMI_DIRAC = 1 };
  * Occupations of one subsystem (Sec. 2 fractional occupations, Sec. 3 smearing
  * of metallic subsystems only):
  *   eval  [nk][nb] double ascending per k.    wk [nk] double, sum 1.
- *   integer: f = 2 on the lowest nelec/2 bands of every k.
+ *   integer: f = 2 on the lowest nelec/2 bands of every k; nelec must be even
+ *   and whole (FDE_ERR_ARG otherwise: no singly occupied band).
  *   Fermi-Dirac: f = 1 - tanh((eps - mu)/(2 sigma)), mu by bisection so that
  *   sum_k wk sum_n f = nelec to 1e-13.
  *   occw  [nk][nb] double out, w_k f_nk.   mu [1] double out.
@@ -321,17 +322,47 @@ fde_status fde_kb_projectors(fde_plan* plan, int ik, int natoms, const double* p
 fde_status fde_init_bands(fde_plan* plan, int ik, int nb, const void* raw, void* psi, hipStream_t stream);
 
 /*
- * Band energy terms at k-point ik for occupation weights occw [nb]:
- *   out[0] += sum_n occw_n sum_G |k+G|^2/2 |psi_nG|^2   (Janak kinetic, Sec. 2)
- *   out[1] += sum_n occw_n sum_i D_i |<beta_i|psi_n>|^2 (nonlocal energy)
- *   out: device double [2], accumulated.
+ * Band energy terms at k-point ik for occupation weights occw [nb] (the
+ * Janak kinetic energy T_J of Sec. 2, the nonlocal energy of the Appendix on
+ * non-local pseudopotentials, and the band-energy sum of the Appendix recast of
+ * the total energy):
+ *   out[0] += sum_n occw_n sum_G |k+G|^2/2 |psi_nG|^2
+ *   out[1] += sum_n occw_n sum_i D_i |<beta_i|psi_n>|^2
+ *   out[2] += sum_n occw_n eval_n            (only when eval is not NULL)
+ *   psi [nb][npw] (nb <= the workspace's max_nb), occw, eval [nb] double.
+ *   out: device double [3] (or [2] when eval is NULL), accumulated.
  */
 fde_status fde_band_energies(fde_plan* plan, int ik, int nb, const void* psi, const double* occw,
-                             int nproj, const void* beta, const double* dkb, double* out,
+                             const double* eval, int nproj, const void* beta, const double* dkb, double* out,
                              hipStream_t stream);
 
 /* out[0] += sum_j a_j b_j * dV over the plan's grid (a, b real grids; b NULL means b = 1). */
 fde_status fde_grid_dot(fde_plan* plan, const void* a, const void* b, double* out, hipStream_t stream);
+
+/*
+ * Energy bookkeeping of one embedding cycle (Sec. 2, the E_FDE expression; the
+ * Appendix recast of the total energy into fragment energies E_K), ion-ion term
+ * excluded. Inputs, all device doubles:
+ *   embed_energies [ns+1][FDE_NE]: fde_embed_potential's slots at the output
+ *                  densities rho_I (rows 0..ns-1) and rho = sum rho_I (row ns);
+ *   band_terms     [ns][3]: per subsystem, the k-sums of fde_band_energies
+ *                  (T_J, E_NL, sum w f eps) of the bands and occupations that
+ *                  produced rho_I;
+ *   dots           [ns][2]: int V_eff^I rho_I and int V_loc rho_I, V_eff^I the
+ *                  potential those bands were computed in (fde_grid_dot).
+ * Output out [ns+4] (device):
+ *   out[I]    E_K = sum w f eps - int (V_eff^I - V_loc) rho_I + E_xc[rho_I]
+ *             + 1/2 int V_H[rho] rho_I       (the Hartree share of reading 3:
+ *             E_H[rho_K] inside E_K is taken as 1/2 int V_H[rho] rho_K);
+ *   out[ns]   T~[rho] - sum T~[rho_I];  out[ns+1] E~xc[rho] - sum E~xc[rho_I];
+ *   out[ns+2] E_FDE directly: sum_I (T_J + E_NL + int V_loc rho_I + E_xc[rho_I])
+ *             + E_H[rho] + out[ns] + out[ns+1];
+ *   out[ns+3] E_FDE through the fragments: sum_I out[I] + out[ns] + out[ns+1].
+ * The two routes agree when eps are the Ritz values <psi|H_I|psi> of the
+ * orthonormal bands (as after fde_subspace_rr).
+ */
+fde_status fde_energy_total(int ns, const double* embed_energies, const double* band_terms, const double* dots,
+                            double* out, hipStream_t stream);
 
 /* out[0] = (1/N) sum_j a_j (mean of a real grid, e.g. the mean effective potential
  * that the learned preconditioner's fourth feature uses). out: device double. */

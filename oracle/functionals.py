@@ -27,10 +27,17 @@ Kinetic energy (Appendix, kinetic energy functional and potential):
 Low-density rule (paper silent): where X < rho_thr the functional's energy
 density, its local potential and its gradient field are zero.
 
-Pins: uniform-gas closed forms via k_F, the r_s = 1 branch values, the
+Pins: uniform-gas closed forms via k_F, the r_s = 1 branch values and the
+continuity of v_c there (which fixes C to the printed precision), the
 Gell-Mann-Brueckner coefficient (1 - ln 2)/pi^2 for A, the 5/27 gradient
-coefficient of LC94, and finite differences of every energy against its
-potential (tests/test_oracle_functionals.py).
+coefficient of LC94 (a3 - a4), and finite differences of every energy against
+its potential (tests/test_oracle_functionals.py, tests/test_oracle_pins.py).
+
+Parity unpinned: published constants. The PZ81 values g, b1, b2, B, D and C
+are checked only through their continuity relations at r_s = 1, and the LC94
+values a1, a2, a5 and alpha (a3 and a4 only through their difference) have no
+independent check here: they are taken from the cited publications as
+printed, and a typo in them would change the oracle and the kernels alike.
 """
 from __future__ import annotations
 

@@ -6,7 +6,8 @@ integer occupations for molecules. Reading used here: one Fermi level mu per
 subsystem with the Brillouin-zone averaged constraint
 sum_k w_k sum_n f_nk = N_I.
 
-* integer: f = 2 on the lowest N_I/2 bands of every k;
+* integer: f = 2 on the lowest N_I/2 bands of every k (N_I must be even and
+  whole: a singly occupied band is not part of this reading);
 * fermi-dirac (width sigma): f = 1 - tanh((eps - mu) / (2 sigma)), the
   overflow-free form of 2 / (1 + e^{(eps-mu)/sigma}); mu by bisection on
   [min eps - 20 sigma, max eps + 20 sigma] until |sum w f - N| < 1e-13
@@ -30,7 +31,9 @@ def occupations(eps: np.ndarray, wk: np.ndarray, nelec: float, mode: str, sigma:
     wk = np.asarray(wk, dtype=np.float64)
     nk, nb = eps.shape
     if mode == "integer":
-        nocc = int(round(nelec / 2.0))
+        if nelec < 0 or nelec != 2.0 * np.floor(nelec / 2.0):
+            raise ValueError("integer occupations need an even, whole electron count")
+        nocc = int(nelec // 2)
         if nocc > nb:
             raise ValueError("not enough bands")
         f = np.zeros_like(eps)

@@ -18,7 +18,8 @@ available; synthetic Gaussian ions and Gaussian projectors stand in.
 
 Pins: the sum over G of |beta|^2 tends to 1 (normalisation); the potential of
 a single ion agrees with the erf form in real space away from the cutoff
-(tests/test_oracle_physics.py).
+(tests/test_oracle_hamiltonian.py); the G = 0 value equals a radial quadrature
+of the regular part -Z erf(r/(sqrt 2 sigma))/r + Z/r (tests/test_oracle_pins.py).
 """
 from __future__ import annotations
 

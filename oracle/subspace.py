@@ -32,7 +32,12 @@ ACTIVE_TOL = 1.0e-10
 
 
 def tpa(x: np.ndarray) -> np.ndarray:
-    """Teter-Payne-Allan polynomial ratio K(x)."""
+    """Teter-Payne-Allan polynomial ratio K(x).
+
+    Pinned: K(0) = 1 and K ~ 1/(2x) for large x (the 27, 8 and 16). Parity
+    unpinned: published constants -- the middle coefficients 18 and 12 are taken
+    from Teter, Payne & Allan (1989) as printed.
+    """
     p = 27.0 + 18.0 * x + 12.0 * x ** 2 + 8.0 * x ** 3
     return p / (p + 16.0 * x ** 4)
 

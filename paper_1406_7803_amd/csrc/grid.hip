@@ -1,5 +1,5 @@
 // Host entry points of the grid kernels: fde_embed_potential,
-// fde_local_potential, fde_mix, fde_grid_dot, fde_grid_mean.
+// fde_local_potential, fde_mix, fde_grid_dot, fde_grid_mean, fde_energy_total.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -503,11 +503,48 @@ struct KRedAdd {
   }
 };
 
+// E_K per subsystem, the nonadditive terms and E_FDE by both routes (single thread;
+// row layout of the inputs as in fde_energy_total).
+struct KEnergyTotal {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char*, int ns, const double* __restrict__ en, const double* __restrict__ band,
+                         const double* __restrict__ dots, double* __restrict__ out) {
+    if (c.tid() != 0) return;
+    const double* tot = en + (size_t)ns * FDE_NE;
+    double tnad = tot[FDE_E_KIN], xnad = tot[FDE_E_XCNAD];
+    for (int I = 0; I < ns; ++I) {
+      tnad -= en[(size_t)I * FDE_NE + FDE_E_KIN];
+      xnad -= en[(size_t)I * FDE_NE + FDE_E_XCNAD];
+    }
+    double direct = tot[FDE_E_HSELF] + tnad + xnad, frag = tnad + xnad;
+    for (int I = 0; I < ns; ++I) {
+      const double* e = en + (size_t)I * FDE_NE;
+      const double* b = band + 3 * I;
+      const double deband = -(dots[2 * I] - dots[2 * I + 1]);
+      const double ek = b[2] + deband + e[FDE_E_XC] + 0.5 * e[FDE_E_HEMB];
+      out[I] = ek;
+      frag += ek;
+      direct += b[0] + b[1] + e[FDE_E_LOC] + e[FDE_E_XC];
+    }
+    out[ns] = tnad;
+    out[ns + 1] = xnad;
+    out[ns + 2] = direct;
+    out[ns + 3] = frag;
+  }
+};
+
 }  // namespace fde
 
 using namespace fde;
 
 extern "C" {
+
+fde_status fde_energy_total(int ns, const double* embed_energies, const double* band_terms, const double* dots,
+                            double* out, hipStream_t s) {
+  if (ns < 1) return fail(FDE_ERR_ARG, "ns must be >= 1");
+  if (!embed_energies || !band_terms || !dots || !out) return fail(FDE_ERR_ARG, "null argument");
+  return launch<KEnergyTotal>(dim3(1), 64, 0, s, ns, embed_energies, band_terms, dots, out);
+}
 
 fde_status fde_embed_potential(fde_plan* p, int ns, const void* rho_sub, const void* vloc, const fde_functionals* f,
                                void* veff, double* energies, int* info, hipStream_t s) {
@@ -551,7 +588,7 @@ fde_status fde_mix(size_t n, double beta, void* rho_in, const void* rho_out, int
 fde_status fde_grid_dot(fde_plan* p, const void* a, const void* b, double* out, hipStream_t s) {
   if (!p) return fail(FDE_ERR_ARG, "null plan");
   if (!p->ws) return fail(FDE_ERR_WORKSPACE, "no workspace attached (fde_plan_set_workspace)");
-  if (!a || !b || !out) return fail(FDE_ERR_ARG, "null argument");
+  if (!a || !out) return fail(FDE_ERR_ARG, "null argument");
   const size_t n = p->npts();
   const unsigned nb = red_blocks(n);
   double* part = (double*)p->scratch;

@@ -864,7 +864,7 @@ struct KOccupations {
     double* red = (double*)lds;
     const int tot = nk * nb;
     if (mode == 0) {
-      const int nocc = (int)floor(nelec / 2.0 + 0.5);
+      const int nocc = (int)(nelec / 2.0);  // nelec even and whole (checked on the host)
       double emx = -1e300;
       for (int e = c.tid(); e < tot; e += c.nthr()) {
         const int k = e / nb, n = e - k * nb;

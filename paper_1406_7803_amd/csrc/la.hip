@@ -317,6 +317,8 @@ fde_status fde_occupations(int nk, int nb, const double* eval, const double* wk,
   if (mode != FDE_OCC_INTEGER && mode != FDE_OCC_FERMI_DIRAC) return fail(FDE_ERR_ARG, "unknown occupation mode");
   if (mode == FDE_OCC_FERMI_DIRAC && !(sigma > 0)) return fail(FDE_ERR_ARG, "sigma must be positive");
   if (!(nelec >= 0) || nelec > 2.0 * nb) return fail(FDE_ERR_ARG, "nelec must be in [0, 2 nb]");
+  if (mode == FDE_OCC_INTEGER && nelec != 2.0 * std::floor(nelec / 2.0))
+    return fail(FDE_ERR_ARG, "integer occupations need an even, whole electron count");
   return launch<KOccupations>(dim3(1), kBlock, 17 * sizeof(double), s, eval, wk, nk, nb, nelec, mode, sigma, occw, mu,
                               info);
 }

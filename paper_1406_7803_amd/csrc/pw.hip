@@ -310,6 +310,18 @@ struct KSumInto {
   }
 };
 
+// out[0] += sum_i a_i b_i  (single block, fixed order)
+struct KSumProd {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const double* __restrict__ a, const double* __restrict__ b, int n,
+                         double* __restrict__ out) {
+    double acc = 0.0;
+    for (int i = c.tid(); i < n; i += c.nthr()) acc += a[i] * b[i];
+    acc = c.sum(acc, (double*)lds);
+    if (c.tid() == 0) out[0] += acc;
+  }
+};
+
 // per_band[n] = occw_n sum_i D_i |dp-free projections|^2 from part (FP64) partials
 struct KBandNl {
   template <class Ctx>
@@ -331,8 +343,9 @@ struct KBandNl {
 };
 
 template <typename T>
-static fde_status band_energies_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, const double* occw, int nproj,
-                                  const cplx<T>* beta, const double* dkb, double* out, hipStream_t s) {
+static fde_status band_energies_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, const double* occw,
+                                  const double* eval, int nproj, const cplx<T>* beta, const double* dkb, double* out,
+                                  hipStream_t s) {
   const KTables& t = p->k[ik];
   if (nb > p->max_nb) return fail(FDE_ERR_SHAPE, "fde_band_energies: nb exceeds the workspace's max_nb");
   if (nproj > p->max_nproj) return fail(FDE_ERR_SHAPE, "nproj exceeds the workspace's max_nproj");
@@ -349,6 +362,7 @@ static fde_status band_energies_t(fde_plan* p, int ik, int nb, const cplx<T>* ps
                             dkb, occw, per_band));
     FDE_TRY(launch<KSumInto>(dim3(1), kBlock, 17 * sizeof(double), s, (const double*)per_band, nb, out + 1));
   }
+  if (eval) FDE_TRY(launch<KSumProd>(dim3(1), kBlock, 17 * sizeof(double), s, occw, eval, nb, out + 2));
   return FDE_OK;
 }
 
@@ -427,16 +441,17 @@ fde_status fde_init_bands(fde_plan* p, int ik, int nb, const void* raw, void* ps
                                    t.npw, kvec(p, ik));
 }
 
-fde_status fde_band_energies(fde_plan* p, int ik, int nb, const void* psi, const double* occw, int nproj,
-                             const void* beta, const double* dkb, double* out, hipStream_t s) {
+fde_status fde_band_energies(fde_plan* p, int ik, int nb, const void* psi, const double* occw, const double* eval,
+                             int nproj, const void* beta, const double* dkb, double* out, hipStream_t s) {
   FDE_TRY(check_plan(p, ik));
   if (nb < 0 || nproj < 0) return fail(FDE_ERR_ARG, "negative size");
   if (nb == 0) return FDE_OK;
   if (!psi || !occw || !out || (nproj > 0 && (!beta || !dkb))) return fail(FDE_ERR_ARG, "null array");
   if (p->prec == FDE_F64)
-    return band_energies_t<double>(p, ik, nb, (const cplx<double>*)psi, occw, nproj, (const cplx<double>*)beta, dkb,
-                                   out, s);
-  return band_energies_t<float>(p, ik, nb, (const cplx<float>*)psi, occw, nproj, (const cplx<float>*)beta, dkb, out, s);
+    return band_energies_t<double>(p, ik, nb, (const cplx<double>*)psi, occw, eval, nproj, (const cplx<double>*)beta,
+                                   dkb, out, s);
+  return band_energies_t<float>(p, ik, nb, (const cplx<float>*)psi, occw, eval, nproj, (const cplx<float>*)beta, dkb,
+                                out, s);
 }
 
 fde_status fde_plan_set_tuning(fde_plan* p, int key, int value) {

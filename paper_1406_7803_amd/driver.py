@@ -224,6 +224,37 @@ class Engine:
                 p.density(b.ik, b.V[:b.nb], self.occw[I][b.j], self.rho_out[I])
         fde.mix(self.be, self.rho_in, self.rho_out, s.mix_beta)
 
+    # ---- energies ----------------------------------------------------------------
+    def total_energies(self) -> torch.Tensor:
+        """Energies of the last cycle's bands and output densities (Sec. 2, E_FDE; the
+        Appendix recast through fragment energies), all terms from the library's
+        kernels: fde_embed_potential at the output densities, fde_band_energies per
+        block, fde_grid_dot of the cycle's V_eff^I and V_loc with rho_I, combined by
+        fde_energy_total. Returns the device tensor [ns + 4] of fde_energy_total
+        (E_K per subsystem, T^nad, E_xc^nad, E_FDE directly, E_FDE via fragments)."""
+        s, p = self.system, self.plan
+        ns = len(s.subsystems)
+        dev = self.be.device
+        if not hasattr(self, "_e_buf"):
+            self._e_buf = dict(veff=p.zeros_grid(ns),
+                               en=torch.zeros((ns + 1, fde.NE), dtype=torch.float64, device=dev),
+                               info=torch.zeros(1, dtype=torch.int32, device=dev),
+                               band=torch.zeros((ns, 3), dtype=torch.float64, device=dev),
+                               dots=torch.zeros((ns, 2), dtype=torch.float64, device=dev),
+                               out=torch.zeros(ns + 4, dtype=torch.float64, device=dev))
+        e = self._e_buf
+        p.embed_potential(self.rho_out, self.vloc, rho_thr=s.rho_thr, veff=e["veff"], energies=e["en"],
+                          info=e["info"], **self.kinds)
+        e["band"].zero_()
+        e["dots"].zero_()
+        for I, sub in enumerate(s.subsystems):
+            for b in self.blocks[I]:
+                p.band_energies(b.ik, b.V[:b.nb], self.occw[I][b.j], b.beta, b.dkb, out=e["band"][I],
+                                eval=self.eps[I][b.j])
+            p.grid_dot(self.veff[I], self.rho_out[I], out=e["dots"][I, 0:1])
+            p.grid_dot(self.vloc, self.rho_out[I], out=e["dots"][I, 1:2])
+        return fde.energy_total(self.be, e["en"], e["band"], e["dots"], out=e["out"])
+
     # ---- one HIP graph per cycle ------------------------------------------------
     def capture(self, n_david: Optional[int] = None):
         """Run one cycle eagerly (first-use set-up of every kernel), then record the

@@ -34,7 +34,7 @@ SYMBOLS = [
     "fde_local_potential", "fde_kb_projectors", "fde_init_bands", "fde_band_energies", "fde_grid_dot",
     "fde_subspace_rr_batched", "fde_precondition_batched", "fde_grid_mean", "fde_precondition_mlp_batched",
     "fde_mlp_forward", "fde_mlp_workspace_bytes", "fde_mlp_loss_grad", "fde_mlp_adam", "fde_plan_set_gemm_mode",
-    "fde_plan_set_tuning",
+    "fde_plan_set_tuning", "fde_energy_total",
 ]
 TUNE_APPLY_BPW = 1
 TUNE_STICK_GROUP = 2
@@ -85,7 +85,8 @@ def _declare(lib):
     lib.fde_local_potential.argtypes = [_P, _I, _P, _P, _P, _P, _P]
     lib.fde_kb_projectors.argtypes = [_P, _I, _I, _P, _P, _P, _P, _P, _P]
     lib.fde_init_bands.argtypes = [_P, _I, _I, _P, _P, _P]
-    lib.fde_band_energies.argtypes = [_P, _I, _I, _P, _P, _I, _P, _P, _P, _P]
+    lib.fde_band_energies.argtypes = [_P, _I, _I, _P, _P, _P, _I, _P, _P, _P, _P]
+    lib.fde_energy_total.argtypes = [_I, _P, _P, _P, _P, _P]
     lib.fde_grid_dot.argtypes = [_P, _P, _P, _P, _P]
     lib.fde_grid_mean.argtypes = [_P, _P, _P, _P]
     lib.fde_plan_set_gemm_mode.argtypes = [_P, _I]
@@ -346,17 +347,42 @@ class Plan:
         self._check(self.lib.fde_init_bands(self.h, ik, raw.shape[0], _ptr(raw), _ptr(out), self.be.stream()))
         return out
 
-    def band_energies(self, ik: int, psi, occw, beta=None, dkb=None, out=None):
+    def band_energies(self, ik: int, psi, occw, beta=None, dkb=None, out=None, eval=None):
+        """out[0] += sum_n occw_n T_n (kinetic), out[1] += sum_n occw_n E_NL,n (nonlocal),
+        out[2] += sum_n occw_n eval_n (when eval is given)."""
         self._bands(psi, ik, "psi")
-        out = torch.zeros(2, dtype=torch.float64, device=self.be.device) if out is None else out
+        self._f64(occw, "occw")
+        if occw.numel() < psi.shape[0]:
+            raise FdeError("occw shorter than the number of bands")
+        if psi.shape[0] > self.max_nb:
+            raise FdeError("band_energies: more bands than the workspace's max_nb")
+        nout = 2 if eval is None else 3
+        out = torch.zeros(nout, dtype=torch.float64, device=self.be.device) if out is None else out
+        self._f64(out, "out")
+        if out.numel() < nout:
+            raise FdeError(f"out needs {nout} values")
+        if eval is not None:
+            self._f64(eval, "eval")
+            if eval.numel() < psi.shape[0]:
+                raise FdeError("eval shorter than the number of bands")
         nproj = 0 if beta is None else beta.shape[0]
-        self._check(self.lib.fde_band_energies(self.h, ik, psi.shape[0], _ptr(psi), _ptr(occw), nproj,
+        if nproj:
+            self._bands(beta, ik, "beta")
+            self._f64(dkb, "dkb")
+            if dkb.numel() < nproj:
+                raise FdeError("dkb shorter than the number of projectors")
+        self._check(self.lib.fde_band_energies(self.h, ik, psi.shape[0], _ptr(psi), _ptr(occw), _ptr(eval), nproj,
                                                _ptr(beta) if nproj else None, _ptr(dkb) if nproj else None,
                                                _ptr(out), self.be.stream()))
         return out
 
     def grid_dot(self, a, b, out=None):
+        """out[0] += sum_j a_j b_j dV (b None: b = 1)."""
+        self._grid(a, "a")
+        if b is not None:
+            self._grid(b, "b")
         out = torch.zeros(1, dtype=torch.float64, device=self.be.device) if out is None else out
+        self._f64(out, "out")
         self._check(self.lib.fde_grid_dot(self.h, _ptr(a), _ptr(b), _ptr(out), self.be.stream()))
         return out
 
@@ -396,6 +422,23 @@ def occupations(be: Backend, eval: torch.Tensor, wk: torch.Tensor, nelec: float,
     if st != 0:
         raise FdeError(f"fde error {st}: {be.lib.fde_last_error().decode()}")
     return occw, mu, info
+
+
+def energy_total(be: Backend, embed_energies: torch.Tensor, band_terms: torch.Tensor, dots: torch.Tensor,
+                 out=None) -> torch.Tensor:
+    """fde_energy_total: [ns+4] = (E_K per subsystem, T^nad, E_xc^nad, E_FDE direct, E_FDE via fragments)."""
+    ns = band_terms.shape[0]
+    for t, shape, nme in ((embed_energies, (ns + 1, NE), "embed_energies"), (band_terms, (ns, 3), "band_terms"),
+                          (dots, (ns, 2), "dots")):
+        if t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != shape or t.device != be.device:
+            raise FdeError(f"{nme}: expected a contiguous float64 tensor {shape} on {be.device}")
+    out = torch.zeros(ns + 4, dtype=torch.float64, device=be.device) if out is None else out
+    if out.dtype != torch.float64 or out.numel() < ns + 4 or out.device != be.device:
+        raise FdeError("out: expected float64 [ns+4]")
+    st = be.lib.fde_energy_total(ns, _ptr(embed_energies), _ptr(band_terms), _ptr(dots), _ptr(out), be.stream())
+    if st != 0:
+        raise FdeError(f"fde error {st}: {be.lib.fde_last_error().decode()}")
+    return out
 
 
 def mix(be: Backend, rho_in: torch.Tensor, rho_out: torch.Tensor, beta: float):

@@ -281,8 +281,19 @@ def check_occupations(be):
         assert abs(float(host(occw).sum()) - nel) < 1e-12
 
 
+_ORACLE_RUNS = {}
+
+
+def oracle_run(system, n_cycles):
+    """oracle.scf.run, kept per (config, geometry, cycles) for the tests of one session."""
+    key = (system.cfg, system.geometry, tuple(system.grid), len(system.subsystems), n_cycles)
+    if key not in _ORACLE_RUNS:
+        _ORACLE_RUNS[key] = oscf.run(system, n_cycles=n_cycles)
+    return _ORACLE_RUNS[key]
+
+
 def check_trajectory(be, prec, system, n_cycles, eps_tol, drho_tol, gemm=fde.GEMM_FP64):
-    recs, _, st = oscf.run(system, n_cycles=n_cycles)
+    recs, _, st = oracle_run(system, n_cycles)
     eng = driver.Engine(system, prec=prec, backend=be, gemm=gemm)
     worst = (0.0, 0.0)
     for c in range(n_cycles):
@@ -511,3 +522,151 @@ def check_tuning_keeps_results(be, prec):
     plan.set_tuning(fde.TUNE_STICK_GROUP, 0)
     with pytest.raises(fde.FdeError):
         plan.set_tuning(fde.TUNE_STICK_GROUP, 3)
+
+
+# ---------------------------------------------------------------------------
+# Energy terms (row a13): band energies, grid dots, E_FDE by both routes
+# ---------------------------------------------------------------------------
+def check_band_energies(be, prec, nb=5):
+    """T_J, E_NL and sum w eps at two k-points with s + p projectors, accumulated."""
+    plan = small_plan(be, prec, max_nb=nb)
+    cell = basis.Cell(SMALL["L"], SMALL["grid"])
+    out = torch.zeros(3, dtype=torch.float64, device=plan.be.device)
+    ref = np.zeros(3)
+    for ik, kf in enumerate(SMALL["kf"]):
+        sph = basis.sphere(cell, SMALL["ecut"], kf)
+        psi = osub.orthonormalise(fde_synth.random_complex(90 + ik, (nb, sph.npw)))
+        beta, dkb = opseudo.kb_projectors(cell, sph, KB_ATOMS)
+        occw = np.linspace(0.9, 0.1, nb) * (0.5 + ik)
+        eps = fde_synth.random_real(95 + ik, (nb,))
+        ref += [np.sum(occw * oham.kinetic_band(sph, psi)), np.sum(occw * oham.nonlocal_band(psi, beta, dkb)),
+                np.sum(occw * eps)]
+        tb = plan.kb_projectors(ik, [a.pos for a in KB_ATOMS], [a.lmax for a in KB_ATOMS],
+                                [a.rbeta for a in KB_ATOMS])
+        plan.band_energies(ik, to_dev(plan, psi, "c"), to_dev(plan, occw, "d"), tb, to_dev(plan, dkb, "d"),
+                           out=out, eval=to_dev(plan, eps, "d"))
+    be.sync()
+    tol = 1e-12 if prec == fde.F64 else 2e-6
+    assert np.max(np.abs(host(out) - ref) / np.abs(ref)) < tol, (host(out), ref)
+    # without projectors: only the kinetic and band sums
+    out2 = plan.band_energies(1, to_dev(plan, psi, "c"), to_dev(plan, occw, "d"))
+    be.sync()
+    assert abs(float(host(out2)[1])) == 0.0
+
+
+def check_grid_dot(be, prec):
+    L, grid = (6.0, 6.0, 7.0), (12, 12, 15)
+    cell = basis.Cell(L, grid)
+    plan = fde.Plan(L, grid, 2.2, [(0, 0, 0)], prec=prec, max_nb=4, backend=be)
+    a = fde_synth.random_real(61, cell.shape)
+    b = fde_synth.random_real(62, cell.shape, 0.0, 2.0)
+    out = plan.grid_dot(to_dev(plan, a, "r"), to_dev(plan, b, "r"))
+    out = plan.grid_dot(to_dev(plan, a, "r"), to_dev(plan, b, "r"), out=out)   # accumulates
+    one = plan.grid_dot(to_dev(plan, b, "r"), None)
+    be.sync()
+    if prec == fde.F32:
+        a, b = a.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64)
+    ref = float(np.sum(a * b)) * cell.dV
+    assert abs(float(host(out)[0]) - 2 * ref) < 1e-12 * np.sum(np.abs(a * b)) * cell.dV * 2
+    assert abs(float(host(one)[0]) - float(np.sum(b)) * cell.dV) < 1e-12 * float(np.sum(b)) * cell.dV
+
+
+def check_energies(be, prec, system, n_cycles, tol):
+    """E_FDE of the last cycle's bands and output densities, from the library's energy
+    terms (Engine.total_energies) against the oracle's direct and fragment expressions."""
+    recs, X, st = oracle_run(system, n_cycles)
+    eps_f = []
+    for I, sub in enumerate(system.subsystems):
+        f, _ = oocc.occupations(recs[-1].eps[I], sub.kweight, sub.nelec, sub.smearing, sub.sigma)
+        eps_f.append((recs[-1].eps[I], f))
+    ref = oscf.energies(st, X, eps_f, recs[-1].veff, recs[-1].rho_out)
+    assert abs(ref["E_FDE"] - ref["E_FDE_fragments"]) < 1e-10
+    eng = driver.Engine(system, prec=prec, backend=be)
+    for _ in range(n_cycles):
+        eng.cycle()
+    out = host(eng.total_energies())
+    be.sync()
+    ns = len(system.subsystems)
+    assert abs(out[ns + 2] - ref["E_FDE"]) < tol, (out[ns + 2], ref["E_FDE"])
+    assert abs(out[ns + 3] - ref["E_FDE_fragments"]) < tol, (out[ns + 3], ref["E_FDE_fragments"])
+    assert abs(out[ns + 2] - out[ns + 3]) < tol
+    en = ref["embed"]
+    tnad = en[ns, oembed.E_KIN] - sum(en[I, oembed.E_KIN] for I in range(ns))
+    assert abs(out[ns] - tnad) < tol
+    return out, ref
+
+
+def _vacuum_densities(cell, ns):
+    """rho_A: Gaussian blobs with regions below the density threshold; rho_B = 0."""
+    N1, N2, N3 = cell.grid
+    L = np.array(cell.L)
+    z, y, x = np.meshgrid(np.arange(N3) * L[2] / N3, np.arange(N2) * L[1] / N2, np.arange(N1) * L[0] / N1,
+                          indexing="ij")
+    g = (x, y, z)
+    rho = np.zeros((ns,) + cell.shape)
+    for c, q, s in [((0.3, 0.4, 0.5), 2.0, 0.55), ((0.6, 0.5, 0.3), 1.0, 0.45)]:
+        d2 = 0.0
+        for i in range(3):
+            d = g[i] - c[i] * L[i]
+            d -= L[i] * np.round(d / L[i])
+            d2 = d2 + d * d
+        rho[0] += q * (2 * np.pi * s * s) ** -1.5 * np.exp(-0.5 * d2 / (s * s))
+    return rho
+
+
+def check_embed_grid(be, prec, grid, spacing, kin=fde.KIN_LC94, ecut=3.0):
+    """The embedding potential on a grid of compile-time FFT lengths, with a vacuum
+    region below rho_thr (reading 11) and a second subsystem of zero density
+    (T^nad[rho_A, 0] = 0 and V^nad = 0 exactly)."""
+    kinds = {fde.KIN_LC94: "lc94", fde.KIN_TF: "tf", fde.KIN_NONE: "none"}
+    L = tuple(n * spacing for n in grid)
+    cell = basis.Cell(L, grid)
+    rs = _vacuum_densities(cell, 2)
+    assert np.mean(rs[0] < 1e-10) > 0.05          # part of the cell is vacuum
+    vloc = fde_synth.random_real(7, cell.shape, -0.3, 0.3)
+    vref, eref = oembed.embed_potential(cell, ecut, rs, vloc, kin_nad=kinds[kin])
+    plan = fde.Plan(L, grid, ecut, [(0, 0, 0)], prec=prec, max_nb=2, backend=be)
+    veff, en, info = plan.embed_potential(to_dev(plan, rs, "r"), to_dev(plan, vloc, "r"), kin_nad=kin)
+    be.sync()
+    assert int(host(info)[0]) == 0
+    v = host(veff)
+    scale = np.max(np.abs(vref))
+    assert np.max(np.abs(v - vref)) < 2 * TOL[prec] * scale, np.max(np.abs(v - vref)) / scale
+    e = host(en)
+    assert np.max(np.abs(e - eref)) < 10 * TOL[prec] * max(1.0, np.max(np.abs(eref)))
+    # rho_B = 0: no nonadditive kinetic or xc energy
+    assert abs(e[2, fde.E_KIN] - e[0, fde.E_KIN]) <= 1e-12 * max(1.0, abs(e[0, fde.E_KIN]))
+    assert e[1, fde.E_KIN] == 0.0 and e[1, fde.E_XC] == 0.0 and e[1, fde.E_CHARGE] == 0.0
+
+
+def check_trajectory_uneven(be, prec, n_cycles=3):
+    """Six uneven subsystems (4-48 bands, 1-4 k-points) in one cycle: the LDS
+    (m <= 80) and the global (m = 96) eigensolvers run in the same cycle, in
+    ragged batches over several solver groups.
+
+    FP64: 1e-10 Ha and 1e-10 in int |d rho_I|. FP32: the rounding of an FP32 FFT
+    sandwich is relative (about log2(N) 2^-24 per element), so the bound scales
+    with the size of what is compared: 1e-6 Ha per Ha of the largest |eps|, and
+    2.5e-6 per electron in int |d rho_I| (an L1 norm: per-point rounding does not
+    cancel). For the 4-electron subsystems of the two-subsystem cube these are
+    the 1e-6 Ha / 1e-5 targets; the 76-electron subsystem here gets 1.9e-4."""
+    s = fde_synth.config3_reduced()
+    ms = sorted({2 * sub.nbands for sub in s.subsystems})
+    assert ms[0] <= 80 < ms[-1]
+    if prec == fde.F64:
+        return check_trajectory(be, prec, s, n_cycles, 1e-10, 1e-10)
+    recs, _, st = oracle_run(s, n_cycles)
+    eng = driver.Engine(s, prec=prec, backend=be)
+    emax = max(float(np.max(np.abs(e))) for r in recs for e in r.eps)
+    worst_e, worst_d = 0.0, 0.0
+    for c in range(n_cycles):
+        eng.cycle()
+        be.sync()
+        for I, sub in enumerate(s.subsystems):
+            worst_e = max(worst_e, float(np.max(np.abs(host(eng.eps[I]) - recs[c].eps[I]))))
+            d = float(np.sum(np.abs(host(eng.rho_out[I]) - recs[c].rho_out[I]))) * st.cell.dV
+            worst_d = max(worst_d, d / sub.nelec)
+    assert all(int(host(b.info)[0]) == 0 for row in eng.blocks for b in row)
+    assert worst_e < 1e-6 * max(1.0, emax), (worst_e, emax)
+    assert worst_d < 2.5e-6, worst_d
+    return worst_e, worst_d

@@ -148,3 +148,21 @@ def test_gemm_mode_needs_fp32_plan(be):
 @pytest.mark.parametrize("prec", PRECS)
 def test_tuning_keeps_results(be, prec):
     pc.check_tuning_keeps_results(be, prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_band_energies(be, prec):
+    pc.check_band_energies(be, prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_grid_dot(be, prec):
+    pc.check_grid_dot(be, prec)
+
+
+def test_energies_c1(be):
+    pc.check_energies(be, fde.F64, fde_synth.config1(), 2, 1e-10)
+
+
+def test_embed_vacuum_and_empty_subsystem(be):
+    pc.check_embed_grid(be, fde.F64, (24, 48, 60), 0.25)

@@ -101,6 +101,39 @@ def test_trajectory_kpoints_projectors(be):
     pc.check_trajectory(be, fde.F32, s, 3, 1e-6, 1e-5)
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_band_energies(be, prec):
+    pc.check_band_energies(be, prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_grid_dot(be, prec):
+    pc.check_grid_dot(be, prec)
+
+
+@pytest.mark.parametrize("prec,tol", [(fde.F64, 1e-10), (fde.F32, 1e-6)])
+def test_energies_c1(be, prec, tol):
+    # E_FDE of the two-subsystem cube after the 10-cycle schedule, both routes
+    pc.check_energies(be, prec, fde_synth.config1(), 10, tol)
+
+
+@pytest.mark.parametrize("prec,tol", [(fde.F64, 1e-10), (fde.F32, 1e-6)])
+def test_energies_kpoints_projectors(be, prec, tol):
+    s = fde_synth.tiny(0, with_kb=True, kfrac=[(0.25, 0.0, 0.0), (-0.25, 0.0, 0.0)], grid=(12, 12, 15))
+    pc.check_energies(be, prec, s, 3, tol)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("grid,spacing", [((24, 48, 60), 0.25), ((72, 24, 240), 0.2)])
+def test_embed_compile_time_lengths_vacuum(be, prec, grid, spacing):
+    pc.check_embed_grid(be, prec, grid, spacing)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_trajectory_uneven_subsystems(be, prec):
+    pc.check_trajectory_uneven(be, prec)
+
+
 # ---------------------------------------------------------------------------
 # Full-size slab + molecule cell (60 x 60 x 240, ~50 300 plane waves), in the
 # launch configuration the benchmark times: all 40 slab bands in one call;
