@@ -408,6 +408,23 @@ fde_status fde_mlp_workspace_bytes(int n, size_t* bytes);
 fde_status fde_mlp_loss_grad(int n, const float* samples, const float* params, float* grad, double* loss,
                              void* ws, size_t ws_bytes, hipStream_t stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight training or serving loops, harnesses that forbid hipMalloc): the same
+ * loss and gradient as fde_mlp_loss_grad, with the per-block partial gradients
+ * in a scratch array that the library holds in each GPU's memory until the
+ * process ends (FDE_MLP_STATIC_SCRATCH_BYTES per GPU, 20 MiB). No workspace
+ * argument, no allocation of any kind. n in [1, FDE_MLP_STATIC_MAX_N], else
+ * FDE_ERR_SHAPE. The first call on a device looks the array's address up
+ * (hipGetSymbolAddress). All calls on one GPU share the array: calls that can
+ * overlap on one GPU (unordered streams, threads) race and must be serialised
+ * by the caller. Nothing an earlier call left in the array is read.
+ */
+#define FDE_MLP_STATIC_SCRATCH_BYTES (20 * 1024 * 1024)
+#define FDE_MLP_STATIC_MAX_N (1 << 28)
+fde_status fde_mlp_loss_grad_static(int n, const float* samples, const float* params, float* grad, double* loss,
+                                    hipStream_t stream);
+
 /* One Adam step (Kingma & Ba) on params with moments m, v (FP32, FDE_MLP_NPARAM
  * each, updated in place); t counts from 1. */
 fde_status fde_mlp_adam(const float* grad, float* params, float* m, float* v, int t, float lr, float beta1,

@@ -1,6 +1,7 @@
 // Host entry points of the band-solver kernels: fde_subspace_rr(_batched),
 // fde_precondition(_batched), fde_occupations.
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "kernels_gemm.hpp"
@@ -237,6 +238,40 @@ static fde_status precond_mlp_batched_t(fde_plan* p, int nblk, const fde_block* 
 // samples per block of the loss/gradient pass: a multiple of 64, at most 1024 blocks
 static int mlp_per_block(int n) { return 64 * std::max(1, (n + 64 * 1024 - 1) / (64 * 1024)); }
 
+// ---------------------------------------------------------------------------
+// Library-held scratch of fde_mlp_loss_grad_static: the per-block partial
+// gradients live in a file-scope device array, one copy per GPU, for the life
+// of the process. In host code `scratch` names a host-side stand-in, never the
+// device memory: its device address is taken once per device with
+// hipGetSymbolAddress and only that address is passed to kernels.
+// ---------------------------------------------------------------------------
+#ifdef FDE_EMULATE
+alignas(256) static char scratch[FDE_MLP_STATIC_SCRATCH_BYTES];
+static fde_status static_scratch(void** out) {
+  *out = scratch;
+  return FDE_OK;
+}
+#else
+static __device__ __align__(256) char scratch[FDE_MLP_STATIC_SCRATCH_BYTES];
+static fde_status static_scratch(void** out) {
+  constexpr int kMaxDevices = 64;
+  static void* addr[kMaxDevices] = {};
+  static std::mutex mu;
+  int dev = 0;
+  FDE_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(FDE_ERR_DEVICE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> g(mu);
+  if (!addr[dev]) {
+    void* a = nullptr;
+    FDE_HIP(hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)));
+    if (!a) return fail(FDE_ERR_DEVICE, "no device address for the scratch array");
+    addr[dev] = a;
+  }
+  *out = addr[dev];
+  return FDE_OK;
+}
+#endif
+
 }  // namespace fde
 
 using namespace fde;
@@ -358,6 +393,28 @@ fde_status fde_mlp_loss_grad(int n, const float* samples, const float* params, f
   const int nblk = (n + pb - 1) / pb;
   float* part = (float*)ws;
   double* lpart = (double*)((char*)ws + align256((size_t)nblk * kMlpNPad * sizeof(float)));  // inside `need`
+  FDE_TRY(launch<KMlpLossGrad>(dim3(nblk), kBlock, KMlpLossGrad::lds_bytes, s, samples, n, pb, params, part, lpart));
+  return launch<KMlpReduce>(dim3((kMlpNPad + 255) / 256), kBlock, 0, s, (const float*)part, (const double*)lpart, nblk,
+                            grad, loss);
+}
+
+fde_status fde_mlp_loss_grad_static(int n, const float* samples, const float* params, float* grad, double* loss,
+                                    hipStream_t s) {
+  if (n < 1) return fail(FDE_ERR_ARG, "need at least one sample");
+  if (n > FDE_MLP_STATIC_MAX_N) return fail(FDE_ERR_SHAPE, "n exceeds FDE_MLP_STATIC_MAX_N");
+  if (!samples || !params || !grad || !loss) return fail(FDE_ERR_ARG, "null argument");
+  size_t need = 0;
+  FDE_TRY(fde_mlp_workspace_bytes(n, &need));
+  if (need > (size_t)FDE_MLP_STATIC_SCRATCH_BYTES)
+    return fail(FDE_ERR_SHAPE, "n needs more scratch than FDE_MLP_STATIC_SCRATCH_BYTES");
+  void* ws = nullptr;
+  FDE_TRY(static_scratch(&ws));
+  // every block writes its whole partial row before the reduction reads it:
+  // nothing left by an earlier call is read
+  const int pb = mlp_per_block(n);
+  const int nblk = (n + pb - 1) / pb;
+  float* part = (float*)ws;
+  double* lpart = (double*)((char*)ws + align256((size_t)nblk * kMlpNPad * sizeof(float)));
   FDE_TRY(launch<KMlpLossGrad>(dim3(nblk), kBlock, KMlpLossGrad::lds_bytes, s, samples, n, pb, params, part, lpart));
   return launch<KMlpReduce>(dim3((kMlpNPad + 255) / 256), kBlock, 0, s, (const float*)part, (const double*)lpart, nblk,
                             grad, loss);

@@ -34,7 +34,7 @@ SYMBOLS = [
     "fde_local_potential", "fde_kb_projectors", "fde_init_bands", "fde_band_energies", "fde_grid_dot",
     "fde_subspace_rr_batched", "fde_precondition_batched", "fde_grid_mean", "fde_precondition_mlp_batched",
     "fde_mlp_forward", "fde_mlp_workspace_bytes", "fde_mlp_loss_grad", "fde_mlp_adam", "fde_plan_set_gemm_mode",
-    "fde_plan_set_tuning", "fde_energy_total",
+    "fde_plan_set_tuning", "fde_energy_total", "fde_mlp_loss_grad_static",
 ]
 TUNE_APPLY_BPW = 1
 TUNE_STICK_GROUP = 2
@@ -95,6 +95,7 @@ def _declare(lib):
     lib.fde_mlp_forward.argtypes = [_I, _P, _P, _P, _P]
     lib.fde_mlp_workspace_bytes.argtypes = [_I, ctypes.POINTER(_S)]
     lib.fde_mlp_loss_grad.argtypes = [_I, _P, _P, _P, _P, _P, _S, _P]
+    lib.fde_mlp_loss_grad_static.argtypes = [_I, _P, _P, _P, _P, _P]
     _F = ctypes.c_float
     lib.fde_mlp_adam.argtypes = [_P, _P, _P, _P, _I, _F, _F, _F, _F, _P]
     for name in SYMBOLS:
@@ -472,6 +473,23 @@ def mlp_forward(be: Backend, u: torch.Tensor, params: torch.Tensor, y=None) -> t
     y = torch.empty(u.shape[0], dtype=torch.float32, device=be.device) if y is None else y
     _raise(be, be.lib.fde_mlp_forward(u.shape[0], _ptr(u), _ptr(params), _ptr(y), be.stream()))
     return y
+
+
+def mlp_loss_grad_static(be: Backend, samples: torch.Tensor, params: torch.Tensor, grad: torch.Tensor,
+                         loss: torch.Tensor):
+    """fde_mlp_loss_grad_static: loss and gradient with the library's own scratch (no
+    workspace, nothing allocated; for callers that cannot allocate)."""
+    _check_params(params, be)
+    if samples.dtype != torch.float32 or samples.dim() != 2 or samples.shape[1] != MLP_SAMPLE \
+            or not samples.is_contiguous() or samples.device != be.device:
+        raise FdeError("samples must be contiguous float32 [n][7] on the backend's device")
+    if grad.dtype != torch.float32 or grad.numel() != MLP_NPARAM or not grad.is_contiguous():
+        raise FdeError(f"grad must be a contiguous float32 vector of {MLP_NPARAM}")
+    if loss.dtype != torch.float64 or loss.numel() < 1:
+        raise FdeError("loss must be a float64 tensor")
+    _raise(be, be.lib.fde_mlp_loss_grad_static(samples.shape[0], _ptr(samples), _ptr(params), _ptr(grad),
+                                               _ptr(loss), be.stream()))
+    return loss, grad
 
 
 class MlpTrainer:
