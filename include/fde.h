@@ -125,7 +125,11 @@ fde_status fde_plan_set_workspace(fde_plan* plan, void* d_ws, size_t bytes, int 
  * z-FFT passes of fde_apply_h and fde_density (a power of two, capped at 16
  * and by the LDS budget; used by the LDS z-passes). FDE_TUNE_Z_REGISTER: 1
  * keeps the LDS z-passes where a four-step register z-FFT exists (N3 = 240,
- * 120). 0 restores the automatic choice. The driver's
+ * 120). FDE_TUNE_PLANE_KIND: the in-plane pass of fde_apply_h and
+ * fde_density -- 1 whole-line register FFTs, 2 LDS Stockham passes, 3 two-factor
+ * FFTs in LDS (used where the kind applies; otherwise the automatic choice).
+ * FDE_TUNE_PLANE_ROWS: rows per batch of the two-factor pass (LDS size). 0
+ * restores the automatic choice. The driver's
  * autotuner times candidate values on the plan's own shapes and keeps the
  * fastest. Errors: FDE_ERR_ARG for an unknown key, a value outside [0, 1024]
  * or a stick group that is not a power of two.
@@ -133,6 +137,8 @@ fde_status fde_plan_set_workspace(fde_plan* plan, void* d_ws, size_t bytes, int 
 #define FDE_TUNE_APPLY_BPW 1
 #define FDE_TUNE_STICK_GROUP 2
 #define FDE_TUNE_Z_REGISTER 3
+#define FDE_TUNE_PLANE_KIND 4
+#define FDE_TUNE_PLANE_ROWS 5
 fde_status fde_plan_set_tuning(fde_plan* plan, int key, int value);
 
 #define FDE_GEMM_FP64 0

@@ -51,6 +51,8 @@ struct fde_plan {
   int tune_bpw = 0;  // bands per plane-pass workgroup of fde_apply_h (0: automatic)
   int tune_sz = 0;   // z-sticks per z-pass workgroup, power of two (0: automatic, at most 16)
   int tune_zreg = 0; // z-passes: 0 four-step register FFT where specialised, 1 LDS passes always
+  int tune_plane = 0; // plane pass: 0 automatic, 1 whole-line register, 2 LDS Stockham, 3 two-factor LDS
+  int tune_rows = 0;  // rows per batch of the two-factor plane pass (0: automatic)
   void* d_tw[3] = {nullptr, nullptr, nullptr};  // twiddles exp(-2 pi i m/N_a), plan precision
   char* scratch = nullptr;
   size_t scratch_bytes = 0;

@@ -1,0 +1,382 @@
+// Plane pass of the H application and of the density with two-factor FFTs in
+// LDS: every in-plane line of length N = P Q is transformed in place in two
+// steps, a Q-point register DFT over the strided elements a + P b followed by
+// a P-point register DFT over the contiguous block a + P k (and the mirror
+// image for the forward direction), so a line is spread over P or Q lanes and
+// every lane holds at most 16 complex values. The inverse column transform
+// leaves the rows in "slot" order (slot k1 + P k2 holds y = Q k1 + k2), the
+// row pass works on the rows in that order, and the forward column transform
+// takes slot order back to natural order, so no reordering pass is needed.
+//
+// Per band and z-plane (workgroup of 256 threads; one z-plane, BPW bands):
+//   1. compact plane P[y][xa] (only the nxa active x-columns) = zeros, then the
+//      ncol sticks of the band at their positions
+//   2. inverse y-FFT of the active columns (two steps, one barrier between)
+//   3. rows, RB at a time through a row buffer R[RB][N1]:
+//        step 1: Q1-point inverse DFT of the active inputs of each row
+//        step 2: P1-point inverse DFT, times V_eff (or |u|^2 into the density),
+//                P1-point forward DFT and twiddle, in registers
+//        step 3: Q1-point forward DFT; only the active outputs are kept
+//   4. forward y-FFT of the active columns
+//   5. sticks = compact plane at their positions
+#pragma once
+
+#include "common.hpp"
+
+namespace fde {
+
+// N = P Q of the in-plane lengths this pass supports (every factor a product
+// of 2, 3, 4, 5 and 8 up to 16, so both register DFTs are compile-time codelets).
+struct Split2 {
+  int p, q;
+};
+FDE_HD constexpr Split2 split2(int n) {
+  switch (n) {
+    case 24: return {4, 6};
+    case 30: return {5, 6};
+    case 36: return {6, 6};
+    case 40: return {5, 8};
+    case 48: return {6, 8};
+    case 60: return {6, 10};
+    case 72: return {8, 9};
+    case 80: return {8, 10};
+    case 90: return {9, 10};
+    case 96: return {8, 12};
+    case 120: return {10, 12};
+    case 144: return {12, 12};
+    case 160: return {10, 16};
+    case 180: return {12, 15};
+    case 240: return {15, 16};
+    default: return {0, 0};
+  }
+}
+inline bool plane4_len_ok(int n) { return split2(n).p > 0; }
+
+// Inverse, step 1 (lane a < P): Q-point DFT over positions a + P b, twiddle
+// w^{a k}, back to positions a + P k. L: line base, es: element stride, tw:
+// the N twiddles exp(-2 pi i m / N).
+template <typename T, int N>
+FDE_HD void inv_step1(cplx<T>* L, int es, int a, const cplx<T>* tw) {
+  constexpr int P = split2(N).p, Q = split2(N).q;
+  cplx<T> v[Q];
+#pragma unroll
+  for (int b = 0; b < Q; ++b) v[b] = L[(a + P * b) * es];
+  reg_fft<T, true, Q>(v, nullptr);
+#pragma unroll
+  for (int k = 1; k < Q; ++k) v[k] = cmulc(tw[(a * k) % N], v[k]);
+#pragma unroll
+  for (int k = 0; k < Q; ++k) L[(a + P * k) * es] = v[k];
+}
+
+// Inverse, step 2: lane k2 < Q, P-point DFT over the contiguous block k2 P + a;
+// output y = Q k1 + k2 lands in slot k1 + P k2.
+template <typename T, int N>
+FDE_HD void inv_step2(cplx<T>* L, int es, int k2) {
+  constexpr int P = split2(N).p;
+  cplx<T> v[P];
+#pragma unroll
+  for (int a = 0; a < P; ++a) v[a] = L[(a + P * k2) * es];
+  reg_fft<T, true, P>(v, nullptr);
+#pragma unroll
+  for (int k1 = 0; k1 < P; ++k1) L[(k1 + P * k2) * es] = v[k1];
+}
+
+// Forward, step 1: lane k2 < Q, P-point DFT over slots k1 + P k2 (values at
+// y = Q k1 + k2), twiddle w^{-k2 m1}, back to slots m1 + P k2.
+template <typename T, int N>
+FDE_HD void fwd_step1(cplx<T>* L, int es, int k2, const cplx<T>* tw) {
+  constexpr int P = split2(N).p;
+  cplx<T> v[P];
+#pragma unroll
+  for (int k1 = 0; k1 < P; ++k1) v[k1] = L[(k1 + P * k2) * es];
+  reg_fft<T, false, P>(v, nullptr);
+#pragma unroll
+  for (int m1 = 1; m1 < P; ++m1) v[m1] = tw[(k2 * m1) % N] * v[m1];
+#pragma unroll
+  for (int m1 = 0; m1 < P; ++m1) L[(m1 + P * k2) * es] = v[m1];
+}
+
+// Forward, step 2: lane m1 < P, Q-point DFT over slots m1 + P k2; the result
+// F[m1 + P m2] lands in slot m1 + P m2 (natural order).
+template <typename T, int N>
+FDE_HD void fwd_step2(cplx<T>* L, int es, int m1) {
+  constexpr int P = split2(N).p, Q = split2(N).q;
+  cplx<T> v[Q];
+#pragma unroll
+  for (int k2 = 0; k2 < Q; ++k2) v[k2] = L[(m1 + P * k2) * es];
+  reg_fft<T, false, Q>(v, nullptr);
+#pragma unroll
+  for (int m2 = 0; m2 < Q; ++m2) L[(m1 + P * m2) * es] = v[m2];
+}
+
+// Dispatch over the supported lengths (runtime n, compile-time codelets).
+#define FDE_SPLIT2_CASES(X) \
+  X(24) X(30) X(36) X(40) X(48) X(60) X(72) X(80) X(90) X(96) X(120) X(144) X(160) X(180) X(240)
+
+// Column passes of the compact plane: the nxa lines are columns xa (element
+// stride nxa). Lanes run with xa fastest, so neighbouring lanes touch
+// neighbouring LDS words.
+template <typename T, bool INV, class Ctx>
+FDE_HD void plane4_columns(const Ctx& c, cplx<T>* P, int N2, int nxa, const cplx<T>* tw2) {
+  const Split2 sp = split2(N2);
+  const int n1 = INV ? sp.p : sp.q;  // lanes per line in the first step
+  const int n2 = INV ? sp.q : sp.p;
+  for (int q = c.tid(); q < nxa * n1; q += c.nthr()) {
+    const int j = q / nxa, xa = q - j * nxa;
+    switch (N2) {
+#define FDE_C1(NN) \
+  case NN:         \
+    if (INV) inv_step1<T, NN>(P + xa, nxa, j, tw2); else fwd_step1<T, NN>(P + xa, nxa, j, tw2); break;
+      FDE_SPLIT2_CASES(FDE_C1)
+#undef FDE_C1
+      default: break;
+    }
+  }
+  c.sync();
+  for (int q = c.tid(); q < nxa * n2; q += c.nthr()) {
+    const int j = q / nxa, xa = q - j * nxa;
+    switch (N2) {
+#define FDE_C2(NN) \
+  case NN:         \
+    if (INV) inv_step2<T, NN>(P + xa, nxa, j); else fwd_step2<T, NN>(P + xa, nxa, j); break;
+      FDE_SPLIT2_CASES(FDE_C2)
+#undef FDE_C2
+      default: break;
+    }
+  }
+  c.sync();
+}
+
+// Row step 1 for row r of the batch (plane slot s): lane a gathers the active
+// inputs e = a + P1 b (centred index of e in [mlo, mlo + nxa)), Q1-point
+// inverse DFT, twiddle, into R[r][a + P1 k].
+template <typename T, int N>
+FDE_HD void row_step1(const cplx<T>* Prow, cplx<T>* Rr, int a, int nxa, int mlo, const cplx<T>* tw) {
+  constexpr int P = split2(N).p, Q = split2(N).q;
+  cplx<T> v[Q];
+#pragma unroll
+  for (int b = 0; b < Q; ++b) {
+    const int e = a + P * b;
+    const int xa = (e <= N / 2 ? e : e - N) - mlo;
+    const bool ok = (unsigned)xa < (unsigned)nxa;
+    const cplx<T> val = Prow[ok ? xa : 0];
+    v[b] = ok ? val : mk<T>(0, 0);
+  }
+  reg_fft<T, true, Q>(v, nullptr);
+#pragma unroll
+  for (int k = 1; k < Q; ++k) v[k] = cmulc(tw[(a * k) % N], v[k]);
+#pragma unroll
+  for (int k = 0; k < Q; ++k) Rr[a + P * k] = v[k];
+}
+
+// Row step 2 of the H application (lane k2): inverse P1-point DFT gives u at
+// x = Q1 k1 + k2; times V_eff; forward P1-point DFT over k1 and twiddle.
+template <typename T, int N>
+FDE_HD void row_step2_h(cplx<T>* Rr, int k2, const T* __restrict__ vrow, const cplx<T>* tw) {
+  constexpr int P = split2(N).p, Q = split2(N).q;
+  cplx<T> v[P];
+#pragma unroll
+  for (int a = 0; a < P; ++a) v[a] = Rr[a + P * k2];
+  reg_fft<T, true, P>(v, nullptr);
+#pragma unroll
+  for (int k1 = 0; k1 < P; ++k1) {
+    const T w = vrow[Q * k1 + k2];
+    v[k1] = mk<T>(w * v[k1].x, w * v[k1].y);
+  }
+  reg_fft<T, false, P>(v, nullptr);
+#pragma unroll
+  for (int m1 = 1; m1 < P; ++m1) v[m1] = tw[(k2 * m1) % N] * v[m1];
+#pragma unroll
+  for (int m1 = 0; m1 < P; ++m1) Rr[m1 + P * k2] = v[m1];
+}
+
+// Row step 2 of the density (lane k2): acc[x] += wgt |u(x)|^2, x = Q1 k1 + k2.
+template <typename T, int N>
+FDE_HD void row_step2_rho(const cplx<T>* Rr, int k2, T* __restrict__ arow, T wgt) {
+  constexpr int P = split2(N).p, Q = split2(N).q;
+  cplx<T> v[P];
+#pragma unroll
+  for (int a = 0; a < P; ++a) v[a] = Rr[a + P * k2];
+  reg_fft<T, true, P>(v, nullptr);
+#pragma unroll
+  for (int k1 = 0; k1 < P; ++k1) arow[Q * k1 + k2] += wgt * norm2(v[k1]);
+}
+
+// Row step 3 (lane m1): forward Q1-point DFT; the active outputs go back to the
+// compact plane row.
+template <typename T, int N>
+FDE_HD void row_step3(const cplx<T>* Rr, cplx<T>* Prow, int m1, int nxa, int mlo) {
+  constexpr int P = split2(N).p, Q = split2(N).q;
+  cplx<T> v[Q];
+#pragma unroll
+  for (int k2 = 0; k2 < Q; ++k2) v[k2] = Rr[m1 + P * k2];
+  reg_fft<T, false, Q>(v, nullptr);
+#pragma unroll
+  for (int m2 = 0; m2 < Q; ++m2) {
+    const int e = m1 + P * m2;
+    const int xa = (e <= N / 2 ? e : e - N) - mlo;
+    if ((unsigned)xa < (unsigned)nxa) Prow[xa] = v[m2];
+  }
+}
+
+// Plane slot s -> row y after the inverse column transform (N2 = P2 Q2).
+FDE_HD int plane4_row_of_slot(int s, int P2, int Q2) { return Q2 * (s % P2) + s / P2; }
+
+// LDS of the pass: compact plane [N2][nxa], row buffer [RB][N1], the N1 + N2
+// twiddles, the compact position of every stick.
+template <typename T>
+FDE_HD size_t plane4_lds(int N1, int N2, int nxa, int RB, int ncol) {
+  return sizeof(cplx<T>) * ((size_t)N2 * nxa + (size_t)RB * N1 + N1 + N2) + sizeof(int) * (size_t)ncol + 64;
+}
+
+template <typename T>
+struct Plane4Lds {
+  cplx<T>*P, *R, *tw1, *tw2;
+  int* cpos;
+  FDE_HD Plane4Lds(char* lds, int N1, int N2, int nxa, int RB) {
+    P = (cplx<T>*)lds;
+    R = P + (size_t)N2 * nxa;
+    tw1 = R + (size_t)RB * N1;
+    tw2 = tw1 + N1;
+    cpos = (int*)(tw2 + N2);
+  }
+};
+
+template <typename T, class Ctx>
+FDE_HD void plane4_setup(const Ctx& c, Plane4Lds<T>& L, const int4* __restrict__ sticks, int ncol, int nxa,
+                         const cplx<T>* __restrict__ tw1, const cplx<T>* __restrict__ tw2, int N1, int N2) {
+  for (int i = c.tid(); i < ncol; i += c.nthr()) {
+    const int w = sticks[i].w;
+    L.cpos[i] = (w >> 16) * nxa + (w & 0xffff);
+  }
+  for (int i = c.tid(); i < N1; i += c.nthr()) L.tw1[i] = tw1[i];
+  for (int i = c.tid(); i < N2; i += c.nthr()) L.tw2[i] = tw2[i];
+  c.sync();
+}
+
+// compact plane = zeros, then the sticks of one band; inverse y-FFT
+template <typename T, class Ctx>
+FDE_HD void plane4_load(const Ctx& c, Plane4Lds<T>& L, const cplx<T>* __restrict__ row, int ncol, int nxa, int N2) {
+  const int n = N2 * nxa;
+  for (int i = c.tid(); i < n; i += c.nthr()) L.P[i] = mk<T>(0, 0);
+  c.sync();
+  for (int i = c.tid(); i < ncol; i += c.nthr()) L.P[L.cpos[i]] = row[i];
+  c.sync();
+  plane4_columns<T, true>(c, L.P, N2, nxa, L.tw2);
+}
+
+// H application plane pass; grid (N3, ceil(nb / BPW)), 256 threads.
+template <typename T>
+struct KPlaneH4 {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, cplx<T>* __restrict__ sb, int nbands, int BPW,
+                         const int4* __restrict__ sticks, int ncol, int nxa, int mlo, int N1, int N2, int N3, int RB,
+                         const cplx<T>* __restrict__ tw1, const cplx<T>* __restrict__ tw2,
+                         const T* __restrict__ veff) {
+    const int z = c.bx();
+    Plane4Lds<T> L(lds, N1, N2, nxa, RB);
+    plane4_setup<T>(c, L, sticks, ncol, nxa, tw1, tw2, N1, N2);
+    const Split2 s1 = split2(N1), s2 = split2(N2);
+    const T* vz = veff + (size_t)z * N1 * N2;
+    const int b0 = c.by() * BPW;
+    for (int band = b0; band < b0 + BPW && band < nbands; ++band) {
+      cplx<T>* row = sb + ((size_t)band * N3 + z) * stick_stride(ncol);
+      plane4_load<T>(c, L, row, ncol, nxa, N2);
+      for (int y0 = 0; y0 < N2; y0 += RB) {
+        const int rb = (N2 - y0) < RB ? (N2 - y0) : RB;
+        for (int q = c.tid(); q < rb * s1.p; q += c.nthr()) {
+          const int r = q / s1.p, a = q - r * s1.p;
+          const cplx<T>* Prow = L.P + (size_t)(y0 + r) * nxa;
+          cplx<T>* Rr = L.R + (size_t)r * N1;
+          switch (N1) {
+#define FDE_R1(NN) case NN: row_step1<T, NN>(Prow, Rr, a, nxa, mlo, L.tw1); break;
+            FDE_SPLIT2_CASES(FDE_R1)
+#undef FDE_R1
+            default: break;
+          }
+        }
+        c.sync();
+        for (int q = c.tid(); q < rb * s1.q; q += c.nthr()) {
+          const int r = q / s1.q, k2 = q - r * s1.q;
+          const T* vrow = vz + (size_t)plane4_row_of_slot(y0 + r, s2.p, s2.q) * N1;
+          cplx<T>* Rr = L.R + (size_t)r * N1;
+          switch (N1) {
+#define FDE_R2(NN) case NN: row_step2_h<T, NN>(Rr, k2, vrow, L.tw1); break;
+            FDE_SPLIT2_CASES(FDE_R2)
+#undef FDE_R2
+            default: break;
+          }
+        }
+        c.sync();
+        for (int q = c.tid(); q < rb * s1.p; q += c.nthr()) {
+          const int r = q / s1.p, m1 = q - r * s1.p;
+          cplx<T>* Prow = L.P + (size_t)(y0 + r) * nxa;
+          const cplx<T>* Rr = L.R + (size_t)r * N1;
+          switch (N1) {
+#define FDE_R3(NN) case NN: row_step3<T, NN>(Rr, Prow, m1, nxa, mlo); break;
+            FDE_SPLIT2_CASES(FDE_R3)
+#undef FDE_R3
+            default: break;
+          }
+        }
+        c.sync();
+      }
+      plane4_columns<T, false>(c, L.P, N2, nxa, L.tw2);
+      for (int i = c.tid(); i < ncol; i += c.nthr()) row[i] = L.P[L.cpos[i]];
+      c.sync();
+    }
+  }
+};
+
+// Density plane pass: out[group][z] = scale sum_n occw_n |u_n|^2 over the
+// workgroup's bands, accumulated in place in the output plane (zeroed first).
+template <typename T>
+struct KPlaneRho4 {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const cplx<T>* __restrict__ sb, int nbands, int BPW,
+                         const double* __restrict__ occw, const int4* __restrict__ sticks, int ncol, int nxa, int mlo,
+                         int N1, int N2, int N3, int RB, const cplx<T>* __restrict__ tw1,
+                         const cplx<T>* __restrict__ tw2, T* __restrict__ out, double scale) {
+    const int z = c.bx();
+    Plane4Lds<T> L(lds, N1, N2, nxa, RB);
+    plane4_setup<T>(c, L, sticks, ncol, nxa, tw1, tw2, N1, N2);
+    const Split2 s1 = split2(N1), s2 = split2(N2);
+    T* o = out + ((size_t)c.by() * N3 + z) * N1 * N2;
+    for (int i = c.tid(); i < N1 * N2; i += c.nthr()) o[i] = T(0);
+    const int b0 = c.by() * BPW;
+    for (int band = b0; band < b0 + BPW && band < nbands; ++band) {
+      const T wgt = (T)(occw[band] * scale);
+      const cplx<T>* row = sb + ((size_t)band * N3 + z) * stick_stride(ncol);
+      plane4_load<T>(c, L, row, ncol, nxa, N2);
+      for (int y0 = 0; y0 < N2; y0 += RB) {
+        const int rb = (N2 - y0) < RB ? (N2 - y0) : RB;
+        for (int q = c.tid(); q < rb * s1.p; q += c.nthr()) {
+          const int r = q / s1.p, a = q - r * s1.p;
+          const cplx<T>* Prow = L.P + (size_t)(y0 + r) * nxa;
+          cplx<T>* Rr = L.R + (size_t)r * N1;
+          switch (N1) {
+#define FDE_R1(NN) case NN: row_step1<T, NN>(Prow, Rr, a, nxa, mlo, L.tw1); break;
+            FDE_SPLIT2_CASES(FDE_R1)
+#undef FDE_R1
+            default: break;
+          }
+        }
+        c.sync();
+        for (int q = c.tid(); q < rb * s1.q; q += c.nthr()) {
+          const int r = q / s1.q, k2 = q - r * s1.q;
+          T* arow = o + (size_t)plane4_row_of_slot(y0 + r, s2.p, s2.q) * N1;
+          const cplx<T>* Rr = L.R + (size_t)r * N1;
+          switch (N1) {
+#define FDE_R2(NN) case NN: row_step2_rho<T, NN>(Rr, k2, arow, wgt); break;
+            FDE_SPLIT2_CASES(FDE_R2)
+#undef FDE_R2
+            default: break;
+          }
+        }
+        c.sync();
+      }
+    }
+  }
+};
+
+}  // namespace fde

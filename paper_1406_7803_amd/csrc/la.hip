@@ -144,6 +144,10 @@ static fde_status rr_launch(fde_plan* p, ProbSet<T>& ps, hipStream_t s) {
   if (nbmax <= 128)
     return launch<KRotateChunk<T>, 256>(dim3((npwmax + 63) / 64, 2, ps.n), 256, KRotateChunk<T>::lds_bytes(nbmax), s,
                                         ps);
+  // matrix cores with the X rows of 16 columns in LDS (up to 512 bands)
+  if (nbmax <= 4 * kRotWideTiles * 16 && KRotateWide<T>::lds_bytes(nbmax) <= kLdsMax)
+    return launch<KRotateWide<T>, 256>(dim3((npwmax + 15) / 16, 2, ps.n), 256, KRotateWide<T>::lds_bytes(nbmax), s,
+                                       ps);
   // in-place rotation: plane-wave chunk of all m rows (+ C when it fits) in LDS
   const size_t cs = sizeof(cplx<T>);
   int GC = 64;

@@ -5,6 +5,7 @@
 
 #include "kernels_gemm.hpp"
 #include "kernels_plane.hpp"
+#include "kernels_plane4.hpp"
 #include "kernels_pw.hpp"
 #include "launch.hpp"
 
@@ -79,6 +80,63 @@ static int plane_rows(const fde_plan* p, int ik, bool acc, size_t* lds) {
   return 0;
 }
 
+// Rows per batch of the two-factor plane pass: the tuned value, else, among the
+// batch sizes whose LDS fits 80 KiB (two workgroups per CU; a whole CU if none
+// does), the one with the fewest passes of the 256 threads over the three row
+// steps, counting 1.5 passes per batch for its barriers. 0 when not even one
+// row fits.
+template <typename T>
+static int plane4_rows(const fde_plan* p, int ik, size_t* lds) {
+  const KTables& t = p->k[ik];
+  const int N1 = p->N[0], N2 = p->N[1];
+  if (p->tune_rows > 0) {
+    const int rb = std::min(N2, p->tune_rows);
+    *lds = plane4_lds<T>(N1, N2, t.nxa, rb, t.ncol);
+    return *lds <= kLdsMax ? rb : 0;
+  }
+  const Split2 s1 = split2(N1);
+  for (size_t budget : {(size_t)80 * 1024, kLdsMax}) {
+    int best = 0;
+    double best_cost = 1e300;
+    for (int rb = 1; rb <= N2; ++rb) {
+      if (plane4_lds<T>(N1, N2, t.nxa, rb, t.ncol) > budget) break;
+      const int nbatch = (N2 + rb - 1) / rb;
+      const double cost = nbatch * (2.0 * ((rb * s1.p + kBlock - 1) / kBlock) + ((rb * s1.q + kBlock - 1) / kBlock) + 1.5);
+      if (cost < best_cost) {
+        best_cost = cost;
+        best = rb;
+      }
+    }
+    if (best > 0) {
+      *lds = plane4_lds<T>(N1, N2, t.nxa, best, t.ncol);
+      return best;
+    }
+  }
+  return 0;
+}
+
+// Plane pass kind: the tuned one where it applies, else (FP32) the whole-line
+// register pass, else the two-factor LDS pass where both in-plane lengths are
+// supported, else the register pass, else the LDS Stockham pass. 0 when none
+// applies.
+enum { kPlaneReg = 1, kPlaneLds = 2, kPlane4 = 3 };
+template <typename T>
+static int plane_kind(const fde_plan* p, int ik, bool reg_ok, bool lds_ok, bool p4_ok) {
+  switch (p->tune_plane) {
+    case kPlaneReg: if (reg_ok) return kPlaneReg; break;
+    case kPlaneLds: if (lds_ok) return kPlaneLds; break;
+    case kPlane4: if (p4_ok) return kPlane4; break;
+    default: break;
+  }
+  // FP32: the whole-line register pass is the faster where it exists (60 x 60 planes,
+  // measured); FP64: the two-factor pass.
+  if (reg_ok && sizeof(T) == 4) return kPlaneReg;
+  if (p4_ok) return kPlane4;
+  if (reg_ok) return kPlaneReg;
+  if (lds_ok) return kPlaneLds;
+  return 0;
+}
+
 // part[chunk][i][n] = sum_{G in chunk} conj(beta_i(G)) psi_n(G), chunks of kKbChunk plane waves
 template <typename T>
 static fde_status kb_project(const cplx<T>* beta, const cplx<T>* psi, int npw, int nproj, int nb, int nchunk,
@@ -106,7 +164,10 @@ static fde_status apply_h_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, cpl
   const size_t rlds = reg_plane_lds<T>(N2, t.nxa, t.ncol);
   const int cls = reg_len_class(N1, fp64);
   const bool reg_plane = t.xrange && cls >= 0 && cls == reg_len_class(N2, fp64) && rlds <= kLdsMax;
-  if (RB == 0 && !reg_plane) return fail(FDE_ERR_UNSUPPORTED, "plane does not fit in LDS");
+  size_t lds4 = 0;
+  const int RB4 = (t.xrange && plane4_len_ok(N1) && plane4_len_ok(N2)) ? plane4_rows<T>(p, ik, &lds4) : 0;
+  const int kind = plane_kind<T>(p, ik, reg_plane, RB > 0, RB4 > 0);
+  if (kind == 0) return fail(FDE_ERR_UNSUPPORTED, "plane does not fit in LDS");
   const double invN = 1.0 / ((double)N1 * N2 * N3);
   const KVec kv = kvec(p, ik);
   cplx<T>* sb = (cplx<T>*)p->scratch;
@@ -131,7 +192,12 @@ static fde_status apply_h_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, cpl
     else
       FDE_TRY(launch<KZInv<T>>(dim3(ngz, nbc), zthreads(SZ), zlds, s, ps, t.npw, (const int4*)t.d_sticks, t.ncol,
                                p->rad[2], tw3, sb, SZ));
-    if (reg_plane) {
+    if (kind == kPlane4) {
+      // about 2048 workgroups over the chip, unless tuned
+      const int BPW = p->tune_bpw > 0 ? std::min(nbc, p->tune_bpw) : std::max(1, std::min(nbc, (N3 * nbc) / 2048));
+      FDE_TRY(launch<KPlaneH4<T>>(dim3(N3, (nbc + BPW - 1) / BPW), kBlock, lds4, s, sb, nbc, BPW,
+                                  (const int4*)t.d_sticks, t.ncol, t.nxa, t.mlo, N1, N2, N3, RB4, tw1, tw2, veff));
+    } else if (kind == kPlaneReg) {
       // about two workgroups (one wave each) per SIMD over the whole chip, unless tuned
       const int BPW = p->tune_bpw > 0 ? std::min(nbc, p->tune_bpw) : std::max(1, std::min(nbc, (N3 * nbc) / 4096));
       const dim3 g(N3, (nbc + BPW - 1) / BPW);
@@ -182,7 +248,10 @@ static fde_status density_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, con
   const size_t rlds = reg_plane_lds<T>(N2, t.nxa, t.ncol);
   const int cls = reg_len_class(N1, fp64);
   const bool reg_plane = t.xrange && cls >= 0 && cls == reg_len_class(N2, fp64) && rlds <= kLdsMax;
-  if (RB == 0 && !reg_plane) return fail(FDE_ERR_UNSUPPORTED, "plane does not fit in LDS");
+  size_t lds4 = 0;
+  const int RB4 = (t.xrange && plane4_len_ok(N1) && plane4_len_ok(N2)) ? plane4_rows<T>(p, ik, &lds4) : 0;
+  const int kind = plane_kind<T>(p, ik, reg_plane, RB > 0, RB4 > 0);
+  if (kind == 0) return fail(FDE_ERR_UNSUPPORTED, "plane does not fit in LDS");
   cplx<T>* sb = (cplx<T>*)p->scratch;
   T* part = (T*)(p->scratch + align256((size_t)p->max_nb * N3 * stick_stride(p->ncol_max) * sizeof(cplx<T>)));
   const cplx<T>* tw1 = (const cplx<T>*)p->d_tw[0];
@@ -203,11 +272,15 @@ static fde_status density_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, con
     const int ngroups = std::min(kRhoGroups, nbc);
     const int BPW = (nbc + ngroups - 1) / ngroups;
     const int ng = (nbc + BPW - 1) / BPW;
-    if (reg_plane && cls == 0)
+    if (kind == kPlane4)
+      FDE_TRY(launch<KPlaneRho4<T>>(dim3(N3, ng), kBlock, lds4, s, (const cplx<T>*)sb, nbc, BPW, occw + b0,
+                                    (const int4*)t.d_sticks, t.ncol, t.nxa, t.mlo, N1, N2, N3, RB4, tw1, tw2, part,
+                                    1.0 / p->omega));
+    else if (kind == kPlaneReg && cls == 0)
       FDE_TRY(launch<KPlaneRhoReg<T, 0>, 64, REGW>(dim3(N3, ng), 64, rlds, s, (const cplx<T>*)sb, nbc, BPW,
                                                    occw + b0, (const int4*)t.d_sticks, t.ncol, t.nxa, t.mlo, N1, N2,
                                                    N3, part, 1.0 / p->omega));
-    else if (reg_plane)
+    else if (kind == kPlaneReg)
       FDE_TRY(launch<KPlaneRhoReg<T, 1>, 64, REGW>(dim3(N3, ng), 64, rlds, s, (const cplx<T>*)sb, nbc, BPW,
                                                    occw + b0, (const int4*)t.d_sticks, t.ncol, t.nxa, t.mlo, N1, N2,
                                                    N3, part, 1.0 / p->omega));
@@ -462,6 +535,13 @@ fde_status fde_plan_set_tuning(fde_plan* p, int key, int value) {
     case FDE_TUNE_Z_REGISTER:
       if (value > 1) return fail(FDE_ERR_ARG, "z-pass register FFT switch must be 0 or 1");
       p->tune_zreg = value;
+      return FDE_OK;
+    case FDE_TUNE_PLANE_KIND:
+      if (value > 3) return fail(FDE_ERR_ARG, "plane pass kind must be 0..3");
+      p->tune_plane = value;
+      return FDE_OK;
+    case FDE_TUNE_PLANE_ROWS:
+      p->tune_rows = value;
       return FDE_OK;
     case FDE_TUNE_STICK_GROUP:
       if ((value & (value - 1)) != 0) return fail(FDE_ERR_ARG, "sticks per workgroup must be 0 or a power of two");

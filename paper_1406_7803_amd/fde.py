@@ -39,6 +39,9 @@ SYMBOLS = [
 TUNE_APPLY_BPW = 1
 TUNE_STICK_GROUP = 2
 TUNE_Z_REGISTER = 3
+TUNE_PLANE_KIND = 4
+TUNE_PLANE_ROWS = 5
+PLANE_REG, PLANE_LDS, PLANE_TWO_FACTOR = 1, 2, 3
 GEMM_FP64, GEMM_BF16X3, GEMM_BF16X6 = 0, 1, 2
 MLP_NPARAM, MLP_NIN, MLP_SAMPLE = 4545, 4, 7
 

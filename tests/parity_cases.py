@@ -327,6 +327,20 @@ def check_apply_h_grid(be, prec, grid, spacing=0.3, ecut=3.0, nb=2, kf=(0.25, -0
     assert rel(host(out), ref) < TOL[prec], rel(host(out), ref)
     rref = odens.density(cell, sph, psi, occw)
     assert rel(host(rho), rref) < TOL[prec]
+    # every in-plane pass that applies (the others fall back to the automatic choice),
+    # and the two-factor pass with small row batches
+    for kind, rows in ((fde.PLANE_REG, 0), (fde.PLANE_LDS, 0), (fde.PLANE_TWO_FACTOR, 0),
+                       (fde.PLANE_TWO_FACTOR, 7)):
+        plan.set_tuning(fde.TUNE_PLANE_KIND, kind)
+        plan.set_tuning(fde.TUNE_PLANE_ROWS, rows)
+        outk = plan.apply_h(0, to_dev(plan, psi, "c"), to_dev(plan, veff, "r"))
+        rhok = plan.zeros_grid()
+        plan.density(0, to_dev(plan, psi, "c"), to_dev(plan, occw, "d"), rhok)
+        be.sync()
+        assert rel(host(outk), ref) < TOL[prec], (kind, rows, rel(host(outk), ref))
+        assert rel(host(rhok), rref) < TOL[prec], (kind, rows)
+    plan.set_tuning(fde.TUNE_PLANE_KIND, 0)
+    plan.set_tuning(fde.TUNE_PLANE_ROWS, 0)
     # z-passes through LDS instead of the four-step register FFT (where one exists)
     plan.set_tuning(fde.TUNE_Z_REGISTER, 1)
     out2 = plan.apply_h(0, to_dev(plan, psi, "c"), to_dev(plan, veff, "r"))
