@@ -13,6 +13,11 @@ along an axis is the Miller index modulo N.
 
 Parseval, inverse-after-forward and the single-plane-wave delta pin these
 routines (tests/test_oracle_basis.py).
+
+A second mode evaluates the same pair with scipy.fft (pocketfft, FP64) for
+timing the oracle on the larger cells; it is used only by the benchmark's CPU
+baseline and is checked equal to the dense-matrix mode to 1e-13 on grids up to
+24^3 (tests/test_oracle_basis.py). Select it with set_mode("fft", workers).
 """
 from __future__ import annotations
 
@@ -36,8 +41,23 @@ def _apply_axis(a: np.ndarray, axis: int, M: np.ndarray) -> np.ndarray:
     return np.moveaxis(out, -1, axis)
 
 
+_MODE = {"kind": "naive", "workers": 1}
+
+
+def set_mode(kind: str, workers: int = 1) -> None:
+    """'naive' (dense per-axis DFT matrices, the parity mode) or 'fft' (scipy.fft)."""
+    if kind not in ("naive", "fft"):
+        raise ValueError(kind)
+    _MODE["kind"] = kind
+    _MODE["workers"] = int(workers)
+
+
 def to_reciprocal(f: np.ndarray) -> np.ndarray:
     """(1/N) sum_j f(r_j) e^{-iG.r_j} over the last three axes [N3, N2, N1]."""
+    if _MODE["kind"] == "fft":
+        import scipy.fft as sf
+        return sf.fftn(np.asarray(f, dtype=np.complex128), axes=(-3, -2, -1), norm="forward",
+                       workers=_MODE["workers"])
     a = np.asarray(f, dtype=np.complex128)
     N3, N2, N1 = a.shape[-3:]
     a = _apply_axis(a, -1, dft_matrix(N1, -1))
@@ -48,6 +68,10 @@ def to_reciprocal(f: np.ndarray) -> np.ndarray:
 
 def to_real(F: np.ndarray) -> np.ndarray:
     """sum_G F(G) e^{+iG.r_j} over the last three axes [N3, N2, N1]."""
+    if _MODE["kind"] == "fft":
+        import scipy.fft as sf
+        return sf.ifftn(np.asarray(F, dtype=np.complex128), axes=(-3, -2, -1), norm="forward",
+                        workers=_MODE["workers"])
     a = np.asarray(F, dtype=np.complex128)
     N3, N2, N1 = a.shape[-3:]
     a = _apply_axis(a, -1, dft_matrix(N1, +1))

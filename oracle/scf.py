@@ -9,8 +9,9 @@ with every subsystem seeing the densities of the cycle start (Jacobi order):
   2. per subsystem and k-point: HX = H X, Rayleigh-Ritz on X, then n_david
      block-Davidson iterations (see ``subspace``);
   3. occupations and mu_I (``occupations``); rho_I^out (``density``);
-  4. linear mixing rho_I^in <- (1 - beta) rho_I^in + beta rho_I^out
-     (beta = 0.3; the paper does not state its mixing);
+  4. mixing: linear rho_I^in <- (1 - beta) rho_I^in + beta rho_I^out
+     (beta = 0.3; the paper does not state its mixing), or Pulay with a Kerker
+     preconditioner (``mixing``);
   5. rho = sum_I rho_I^in (Eq. int1).
 
 Cycle 0 starts from the density of the initial bands c = r / (1 + |k+G|^2)
@@ -40,7 +41,7 @@ import numpy as np
 
 import fde_synth
 
-from . import basis, density as dens, embed, hamiltonian as ham, occupations as occ, pseudo
+from . import basis, density as dens, embed, hamiltonian as ham, mixing, occupations as occ, pseudo
 from . import subspace
 
 
@@ -126,9 +127,12 @@ class CycleRecord:
     energies: np.ndarray         # embed energies of the input densities
 
 
-def run(system, n_cycles=None, n_david=None, kinds=None, st: Setup = None, callback=None):
-    """Run the embedding cycle; returns (records, final bands, setup)."""
+def run(system, n_cycles=None, n_david=None, kinds=None, st: Setup = None, callback=None, mixer=None):
+    """Run the embedding cycle; returns (records, final bands, setup). mixer: None for
+    the linear mixing of the system (beta = system.mix_beta), else a
+    mixing.Mixer (e.g. Pulay with a Kerker preconditioner)."""
     st = st or setup(system, kinds)
+    mix = mixer or mixing.Mixer(st.cell, "linear", system.mix_beta)
     n_cycles = system.n_cycles if n_cycles is None else n_cycles
     n_david = system.n_david if n_david is None else n_david
     X = initial_bands(st)
@@ -151,7 +155,7 @@ def run(system, n_cycles=None, n_david=None, kinds=None, st: Setup = None, callb
                 rho_out[I] += dens.density(st.cell, st.spheres[ik], X[I][j], s.kweight[j] * f[j])
             eps_all.append(eps)
             mus.append(mu)
-        rho_in = (1.0 - system.mix_beta) * rho_in + system.mix_beta * rho_out
+        rho_in = mix(rho_in, rho_out)
         rec = CycleRecord(eps_all, mus, rho_out, rho_in.copy(), veff, en)
         records.append(rec)
         if callback:

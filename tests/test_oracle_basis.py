@@ -70,3 +70,18 @@ def test_grid_condition():
     with pytest.raises(ValueError):
         basis.check_grid(basis.Cell((10.0, 10.0, 10.0), (20, 24, 24)), 7.0)
     basis.check_grid(basis.Cell((10.0, 10.0, 10.0), (24, 24, 24)), 7.0)
+
+
+def test_fft_mode_equals_the_dense_dft():
+    import fde_synth
+    from oracle import dft
+    for shape in ((24, 24, 24), (9, 12, 10)):
+        f = fde_synth.random_complex(3, shape)
+        a, b = dft.to_reciprocal(f), dft.to_real(f)
+        dft.set_mode("fft", 2)
+        try:
+            c, d = dft.to_reciprocal(f), dft.to_real(f)
+        finally:
+            dft.set_mode("naive")
+        assert np.max(np.abs(a - c)) < 1e-13 * np.max(np.abs(a))
+        assert np.max(np.abs(b - d)) < 1e-13 * np.max(np.abs(b))
