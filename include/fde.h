@@ -280,7 +280,7 @@ fde_status fde_precondition(fde_plan* plan, int ik, int nb, const void* x, const
                             const double* eval, void* t, uint8_t* active, double* rnorm,
                             hipStream_t stream);
 
-enum { FDE_OCC_INTEGER = 0, FDE_OCC_FERMI_DIRAC = 1 };
+enum { FDE_OCC_INTEGER = 0, FDE_OCC_FERMI_DIRAC = 1, FDE_OCC_METHFESSEL_PAXTON = 2 };
 
 /*
  * Occupations of one subsystem (Sec. 2 fractional occupations, Sec. 3 smearing
@@ -290,6 +290,9 @@ enum { FDE_OCC_INTEGER = 0, FDE_OCC_FERMI_DIRAC = 1 };
  *   and whole (FDE_ERR_ARG otherwise: no singly occupied band).
  *   Fermi-Dirac: f = 1 - tanh((eps - mu)/(2 sigma)), mu by bisection so that
  *   sum_k wk sum_n f = nelec to 1e-13.
+ *   Methfessel-Paxton (first order, the smearing of metallic slabs in Sec. 3):
+ *   f = erfc(x) - x e^{-x^2}/sqrt(pi), x = (eps - mu)/sigma (f may leave [0, 2]
+ *   slightly), mu by the same bisection.
  *   occw  [nk][nb] double out, w_k f_nk.   mu [1] double out.
  *   info  device int: 0, or 1 if nelec/2 exceeds nb (integer mode).
  */
@@ -299,6 +302,31 @@ fde_status fde_occupations(int nk, int nb, const double* eval, const double* wk,
 /* Linear density mixing rho_in <- (1-beta) rho_in + beta rho_out over n
  * grid values of precision prec. */
 fde_status fde_mix(size_t n, double beta, void* rho_in, const void* rho_out, int prec, hipStream_t stream);
+
+/*
+ * Pulay mixing (direct inversion in the iterative subspace) of all subsystem
+ * densities with a Kerker preconditioner: the mixing step of the embedding
+ * cycle, which the paper leaves to the host code (Fig. 1; a later variant of
+ * its cycle). The densities of the ns subsystems form one vector x and
+ * R = rho_out - rho_in its residual. With the history state on the device
+ * (so a captured cycle replays correctly):
+ *   1. x_hist[slot] = rho_in, r_hist[slot] = rho_out - rho_in, slot = state[1];
+ *   2. a = argmin |sum_i a_i R_i|^2 subject to sum_i a_i = 1 over the
+ *      nh = min(state[0] + 1, nhmax) entries in use (grid inner product, FP64);
+ *   3. rho_in <- sum_i a_i x_i + beta K(sum_i a_i R_i), K = |G|^2/(|G|^2 + q0^2)
+ *      on each subsystem grid (q0 = 0: K = 1; q0 > 0 leaves the charge alone);
+ *   4. state[0] = nh, state[1] = (slot + 1) mod nhmax.
+ *   state   device int[3], all zero before the first call of a mixing run.
+ *   x_hist, r_hist  [nhmax][ns][N3][N2][N1] real, caller-owned.
+ *   rho_in [ns][N] in/out, rho_out [ns][N].   nhmax in [1, FDE_PULAY_MAX].
+ *   info  device int: 0, or 1 if the residuals were linearly dependent (pivot
+ *         below 1e-14 of the largest inner product: the new pair alone was
+ *         used, i.e. linear mixing with beta).
+ * With nhmax = 1 this is linear mixing rho_in + beta K (rho_out - rho_in).
+ */
+#define FDE_PULAY_MAX 8
+fde_status fde_mix_pulay(fde_plan* plan, int ns, int nhmax, int* state, void* x_hist, void* r_hist, void* rho_in,
+                         const void* rho_out, double beta, double q0, int* info, hipStream_t stream);
 
 /*
  * Local potential of Gaussian ions (the nuclei of all subsystems, Appendix

@@ -14,6 +14,8 @@ and leaves the mixing scheme to the host code; the readings used here are:
   multiplies each subsystem's residual by |G|^2 / (|G|^2 + q0^2) on the whole
   FFT grid (q0 = 0: K = 1). K leaves the G = 0 term (the charge) unchanged
   only when q0 = 0; for q0 > 0 it removes it, so the input charge is kept.
+  Residuals that are linearly dependent (rank below n at 1e-14 of the largest
+  inner product) fall back to the newest pair alone, i.e. linear mixing.
 
 Pins (tests/test_oracle_mixing.py): Pulay with K = 1 finds the fixed point of
 an affine map on R^n in at most n + 1 evaluations (it is then GMRES on the
@@ -50,6 +52,9 @@ def pulay_coefficients(res_hist) -> np.ndarray:
     M[n, :n] = 1.0
     rhs = np.zeros(n + 1)
     rhs[n] = 1.0
+    if np.linalg.matrix_rank(B, tol=1e-14 * np.max(np.abs(B))) < n:
+        # linearly dependent residuals: the newest pair alone (linear mixing)
+        return np.eye(n)[n - 1]
     return np.linalg.solve(M, rhs)[:n]
 
 

@@ -503,6 +503,223 @@ struct KRedAdd {
   }
 };
 
+// ---------------------------------------------------------------------------
+// Pulay mixing with a Kerker preconditioner
+// ---------------------------------------------------------------------------
+constexpr int kPulayBlocks = 128;
+
+// x_hist[slot] = rho_in, r_hist[slot] = rho_out - rho_in over n values
+// State of the history (device ints): [0] entries filled, [1] next slot, [2] entries in use
+// by the current call. x_hist[slot] = rho_in, r_hist[slot] = rho_out - rho_in over n values.
+template <typename T>
+struct KPulayStore {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char*, T* __restrict__ xh, T* __restrict__ rh, const int* __restrict__ state,
+                         const T* __restrict__ rin, const T* __restrict__ rout, size_t n, unsigned nblk) {
+    const size_t off = (size_t)state[1] * n;
+    GRID_FOR(c, n, nblk) {
+      const size_t i = i0_ + l_;
+      if (i >= n) break;
+      const T a = rin[i];
+      xh[off + i] = a;
+      rh[off + i] = (T)((double)rout[i] - (double)a);
+    }
+  }
+};
+
+// part[block][pair] = partial sums of R_i R_j for the pairs i <= j < nh (packed)
+template <typename T>
+struct KPulayGram {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const T* __restrict__ rh, size_t n, size_t hstride,
+                         const int* __restrict__ state, int nhmax, double* __restrict__ part, unsigned nblk) {
+    const int nh = state[0] + 1 < nhmax ? state[0] + 1 : nhmax;
+    double acc[FDE_PULAY_MAX * (FDE_PULAY_MAX + 1) / 2];
+    const int npair = nh * (nh + 1) / 2;
+    for (int q = 0; q < npair; ++q) acc[q] = 0.0;
+    GRID_FOR(c, n, nblk) {
+      const size_t i = i0_ + l_;
+      if (i >= n) break;
+      double r[FDE_PULAY_MAX];
+      for (int a = 0; a < nh; ++a) r[a] = (double)rh[(size_t)a * hstride + i];
+      int q = 0;
+      for (int a = 0; a < nh; ++a)
+        for (int b = a; b < nh; ++b) acc[q++] += r[a] * r[b];
+    }
+    for (int q = 0; q < npair; ++q) {
+      const double t = c.sum(acc[q], (double*)lds);
+      if (c.tid() == 0) part[(size_t)c.bx() * npair + q] = t;
+    }
+  }
+};
+
+// Reduce the pair partials in a fixed order and solve [B 1; 1^T 0][a; l] = [0; 1] by
+// Gaussian elimination with partial pivoting (one thread). A pivot below 1e-14 of the
+// largest entry of B (a history whose residuals are linearly dependent) falls back to
+// a = e_newest: linear mixing of the new pair; info = 1 then.
+struct KPulaySolve {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const double* __restrict__ part, int nblk, int* __restrict__ state,
+                         int nhmax, double* __restrict__ alpha, int* __restrict__ info) {
+    const int nh = state[0] + 1 < nhmax ? state[0] + 1 : nhmax;
+    const int newest = state[1];
+    double* Bp = (double*)lds + 17;  // packed pair sums
+    const int npair = nh * (nh + 1) / 2;
+    for (int q = 0; q < npair; ++q) {
+      double acc = 0.0;
+      for (int b = c.tid(); b < nblk; b += c.nthr()) acc += part[(size_t)b * npair + q];
+      acc = c.sum(acc, (double*)lds);
+      if (c.tid() == 0) Bp[q] = acc;
+      c.sync();
+    }
+    if (c.tid() != 0) return;
+    constexpr int M = FDE_PULAY_MAX + 1;
+    double A[M][M + 1];
+    const int n = nh + 1;
+    double bmax = 0.0;
+    int q = 0;
+    for (int a = 0; a < nh; ++a)
+      for (int b = a; b < nh; ++b) {
+        A[a][b] = A[b][a] = Bp[q++];
+        bmax = fabs(A[a][b]) > bmax ? fabs(A[a][b]) : bmax;
+      }
+    for (int a = 0; a < nh; ++a) {
+      A[a][nh] = A[nh][a] = 1.0;
+      A[a][n] = 0.0;
+    }
+    A[nh][nh] = 0.0;
+    A[nh][n] = 1.0;
+    bool ok = bmax > 0.0;
+    for (int k = 0; k < n && ok; ++k) {
+      int piv = k;
+      for (int r = k + 1; r < n; ++r)
+        if (fabs(A[r][k]) > fabs(A[piv][k])) piv = r;
+      if (!(fabs(A[piv][k]) > (k < nh ? 1e-14 * bmax : 1e-300))) ok = false;
+      if (!ok) break;
+      if (piv != k)
+        for (int j = 0; j <= n; ++j) {
+          const double t = A[k][j];
+          A[k][j] = A[piv][j];
+          A[piv][j] = t;
+        }
+      for (int r = k + 1; r < n; ++r) {
+        const double f = A[r][k] / A[k][k];
+        for (int j = k; j <= n; ++j) A[r][j] -= f * A[k][j];
+      }
+    }
+    if (ok) {
+      double x[M];
+      for (int k = n - 1; k >= 0; --k) {
+        double t = A[k][n];
+        for (int j = k + 1; j < n; ++j) t -= A[k][j] * x[j];
+        x[k] = t / A[k][k];
+      }
+      for (int a = 0; a < nh; ++a) alpha[a] = x[a];
+      info[0] = 0;
+    } else {
+      for (int a = 0; a < nh; ++a) alpha[a] = a == newest ? 1.0 : 0.0;
+      info[0] = 1;
+    }
+    state[2] = nh;
+    state[0] = nh;
+    state[1] = newest + 1 < nhmax ? newest + 1 : 0;
+  }
+};
+
+// rho_in = sum a_i x_i (+ beta sum a_i R_i when kerker == 0); rbar = sum a_i R_i otherwise
+template <typename T>
+struct KPulayCombine {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char*, const T* __restrict__ xh, const T* __restrict__ rh, size_t hstride,
+                         const int* __restrict__ state, const double* __restrict__ alpha, double beta, int kerker,
+                         T* __restrict__ rin, T* __restrict__ rbar, size_t n, unsigned nblk) {
+    const int nh = state[2];
+    GRID_FOR(c, n, nblk) {
+      const size_t i = i0_ + l_;
+      if (i >= n) break;
+      double xb = 0.0, rb = 0.0;
+      for (int a = 0; a < nh; ++a) {
+        xb += alpha[a] * (double)xh[(size_t)a * hstride + i];
+        rb += alpha[a] * (double)rh[(size_t)a * hstride + i];
+      }
+      if (kerker) {
+        rin[i] = (T)xb;
+        rbar[i] = (T)rb;
+      } else {
+        rin[i] = (T)(xb + beta * rb);
+      }
+    }
+  }
+};
+
+// W <- W |G|^2 / (|G|^2 + q0^2) / N over the whole grid (the 1/N of the forward transform)
+template <typename T>
+struct KKerker {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char*, cplx<T>* __restrict__ w, GridGeo g, double q0, double invN,
+                         unsigned nblk) {
+    GRID_FOR(c, g.n, nblk) {
+      const size_t i = i0_ + l_;
+      if (i >= g.n) break;
+      double gx, gy, gz;
+      grid_g(g, i, gx, gy, gz);
+      const double G2 = gx * gx + gy * gy + gz * gz;
+      const double k = G2 / (G2 + q0 * q0) * invN;
+      const cplx<T> v = w[i];
+      w[i] = mk<T>((T)(k * (double)v.x), (T)(k * (double)v.y));
+    }
+  }
+};
+
+// out += beta Re(w)
+template <typename T>
+struct KAddReal {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char*, const cplx<T>* __restrict__ w, double beta, T* __restrict__ out,
+                         size_t n, unsigned nblk) {
+    GRID_FOR(c, n, nblk) {
+      const size_t i = i0_ + l_;
+      if (i >= n) break;
+      out[i] = (T)((double)out[i] + beta * (double)w[i].x);
+    }
+  }
+};
+
+template <typename T>
+static fde_status pulay_t(fde_plan* p, int ns, int nhmax, int* state, T* xh, T* rh, T* rin, const T* rout,
+                          double beta, double q0, int* info, hipStream_t s) {
+  EmbedWs<T> e = embed_ws<T>(p);
+  const size_t N = p->npts();
+  const size_t n = (size_t)ns * N;
+  const unsigned nb = red_blocks(n);
+  const size_t red = 17 * sizeof(double);
+  const int pmax = nhmax * (nhmax + 1) / 2;
+  double* part = e.part;
+  double* alpha = e.part + (size_t)kPulayBlocks * pmax;
+  FDE_TRY(launch<KPulayStore<T>>(dim3(nb), kBlock, 0, s, xh, rh, (const int*)state, (const T*)rin, rout, n, nb));
+  FDE_TRY(launch<KPulayGram<T>>(dim3(kPulayBlocks), kBlock, red, s, (const T*)rh, n, n, (const int*)state, nhmax, part,
+                                (unsigned)kPulayBlocks));
+  FDE_TRY(launch<KPulaySolve>(dim3(1), kBlock, red + (size_t)pmax * sizeof(double), s, (const double*)part,
+                              kPulayBlocks, state, nhmax, alpha, info));
+  const int kerker = q0 > 0.0 ? 1 : 0;
+  if (!kerker)
+    return launch<KPulayCombine<T>>(dim3(nb), kBlock, 0, s, (const T*)xh, (const T*)rh, n, (const int*)state,
+                                    (const double*)alpha, beta, 0, rin, (T*)nullptr, n, nb);
+  const GridGeo g = geo(p);
+  const unsigned nbN = red_blocks(N);
+  for (int I = 0; I < ns; ++I) {
+    FDE_TRY(launch<KPulayCombine<T>>(dim3(nbN), kBlock, 0, s, (const T*)(xh + (size_t)I * N),
+                                     (const T*)(rh + (size_t)I * N), n, (const int*)state, (const double*)alpha, beta,
+                                     1, rin + (size_t)I * N, e.rho, N, nbN));
+    FDE_TRY(launch<KToComplex<T>>(dim3(nbN), kBlock, 0, s, (const T*)e.rho, N, e.W0, nbN));
+    FDE_TRY(fft3<T>(p, e.W0, false, s));
+    FDE_TRY(launch<KKerker<T>>(dim3(nbN), kBlock, 0, s, e.W0, g, q0, 1.0 / (double)N, nbN));
+    FDE_TRY(fft3<T>(p, e.W0, true, s));
+    FDE_TRY(launch<KAddReal<T>>(dim3(nbN), kBlock, 0, s, (const cplx<T>*)e.W0, beta, rin + (size_t)I * N, N, nbN));
+  }
+  return FDE_OK;
+}
+
 // E_K per subsystem, the nonadditive terms and E_FDE by both routes (single thread;
 // row layout of the inputs as in fde_energy_total).
 struct KEnergyTotal {
@@ -544,6 +761,21 @@ fde_status fde_energy_total(int ns, const double* embed_energies, const double* 
   if (ns < 1) return fail(FDE_ERR_ARG, "ns must be >= 1");
   if (!embed_energies || !band_terms || !dots || !out) return fail(FDE_ERR_ARG, "null argument");
   return launch<KEnergyTotal>(dim3(1), 64, 0, s, ns, embed_energies, band_terms, dots, out);
+}
+
+fde_status fde_mix_pulay(fde_plan* p, int ns, int nhmax, int* state, void* x_hist, void* r_hist, void* rho_in,
+                         const void* rho_out, double beta, double q0, int* info, hipStream_t s) {
+  if (!p) return fail(FDE_ERR_ARG, "null plan");
+  if (!p->ws) return fail(FDE_ERR_WORKSPACE, "no workspace attached (fde_plan_set_workspace)");
+  if (ns < 1) return fail(FDE_ERR_ARG, "ns must be >= 1");
+  if (nhmax < 1 || nhmax > FDE_PULAY_MAX) return fail(FDE_ERR_ARG, "nhmax must be in [1, FDE_PULAY_MAX]");
+  if (!state || !x_hist || !r_hist || !rho_in || !rho_out || !info) return fail(FDE_ERR_ARG, "null argument");
+  if (!(q0 >= 0.0) || !(beta > 0.0)) return fail(FDE_ERR_ARG, "need beta > 0 and q0 >= 0");
+  if (p->prec == FDE_F64)
+    return pulay_t<double>(p, ns, nhmax, state, (double*)x_hist, (double*)r_hist, (double*)rho_in,
+                           (const double*)rho_out, beta, q0, info, s);
+  return pulay_t<float>(p, ns, nhmax, state, (float*)x_hist, (float*)r_hist, (float*)rho_in, (const float*)rho_out,
+                        beta, q0, info, s);
 }
 
 fde_status fde_embed_potential(fde_plan* p, int ns, const void* rho_sub, const void* vloc, const fde_functionals* f,

@@ -950,6 +950,16 @@ struct KPrecondC : KPcBase<T> {
 // ---------------------------------------------------------------------------
 // Occupations of one subsystem (single block).
 // ---------------------------------------------------------------------------
+// occupation (f in [0, 2]) of a level eps at Fermi level mu: Fermi-Dirac (mode 1) or
+// first-order Methfessel-Paxton (mode 2)
+FDE_HD double smear(int mode, double eps, double mu, double sigma) {
+  if (mode == 2) {
+    const double x = (eps - mu) / sigma;
+    return erfc(x) - x * exp(-x * x) * 0.56418958354775628695;  // 1/sqrt(pi)
+  }
+  return 1.0 - tanh((eps - mu) / (2.0 * sigma));
+}
+
 struct KOccupations {
   template <class Ctx>
   FDE_HD static void run(const Ctx& c, char* lds, const double* __restrict__ eval, const double* __restrict__ wk,
@@ -983,14 +993,14 @@ struct KOccupations {
     for (int it = 0; it < 200; ++it) {
       m = 0.5 * (lo + hi);
       double s = 0.0;
-      for (int e = c.tid(); e < tot; e += c.nthr()) s += wk[e / nb] * (1.0 - tanh((eval[e] - m) / (2.0 * sigma)));
+      for (int e = c.tid(); e < tot; e += c.nthr()) s += wk[e / nb] * smear(mode, eval[e], m, sigma);
       s = c.sum(s, red);
       if (fabs(s - nelec) < 1e-13) break;
       if (s < nelec) lo = m;
       else hi = m;
     }
     for (int e = c.tid(); e < tot; e += c.nthr())
-      occw[e] = wk[e / nb] * (1.0 - tanh((eval[e] - m) / (2.0 * sigma)));
+      occw[e] = wk[e / nb] * smear(mode, eval[e], m, sigma);
     if (c.tid() == 0) {
       mu[0] = m;
       info[0] = 0;

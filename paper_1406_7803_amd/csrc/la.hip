@@ -353,8 +353,9 @@ fde_status fde_occupations(int nk, int nb, const double* eval, const double* wk,
                            double* occw, double* mu, int* info, hipStream_t s) {
   if (nk < 1 || nb < 1) return fail(FDE_ERR_ARG, "nk and nb must be >= 1");
   if (!eval || !wk || !occw || !mu || !info) return fail(FDE_ERR_ARG, "null argument");
-  if (mode != FDE_OCC_INTEGER && mode != FDE_OCC_FERMI_DIRAC) return fail(FDE_ERR_ARG, "unknown occupation mode");
-  if (mode == FDE_OCC_FERMI_DIRAC && !(sigma > 0)) return fail(FDE_ERR_ARG, "sigma must be positive");
+  if (mode != FDE_OCC_INTEGER && mode != FDE_OCC_FERMI_DIRAC && mode != FDE_OCC_METHFESSEL_PAXTON)
+    return fail(FDE_ERR_ARG, "unknown occupation mode");
+  if (mode != FDE_OCC_INTEGER && !(sigma > 0)) return fail(FDE_ERR_ARG, "sigma must be positive");
   if (!(nelec >= 0) || nelec > 2.0 * nb) return fail(FDE_ERR_ARG, "nelec must be in [0, 2 nb]");
   if (mode == FDE_OCC_INTEGER && nelec != 2.0 * std::floor(nelec / 2.0))
     return fail(FDE_ERR_ARG, "integer occupations need an even, whole electron count");

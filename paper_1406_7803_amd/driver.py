@@ -7,7 +7,8 @@ of the cycle start):
   2. per subsystem and k-point: fde_apply_h + fde_subspace_rr on X, then
      n_david iterations of fde_precondition, fde_apply_h, fde_subspace_rr on [X|T];
   3. fde_occupations, fde_density;
-  4. fde_mix (linear, beta = 0.3); the next fde_embed_potential sums rho = sum rho_I.
+  4. fde_mix (linear, beta = 0.3) or fde_mix_pulay (Pulay with a Kerker preconditioner);
+     the next fde_embed_potential sums rho = sum rho_I.
 Every arithmetic step runs in the library's kernels; this module only owns
 buffers (PyTorch tensors) and the order of the calls.
 """
@@ -60,6 +61,8 @@ class Engine:
     mlp_params: Optional[torch.Tensor] = None   # learned preconditioner (FP32, FDE_MLP_NPARAM); None = TPA
     gemm: int = fde.GEMM_FP64                   # arithmetic of the Rayleigh-Ritz subspace products
     streams: int = 3                            # band-solver groups run concurrently (GPU backend)
+    mixer: Optional[dict] = None                # None: linear (system.mix_beta); or dict(kind="pulay",
+                                                # nhist=6, beta=0.5, q0=0.5) for fde_mix_pulay
 
     def __post_init__(self):
         s = self.system
@@ -114,6 +117,14 @@ class Engine:
         self.mu = [torch.zeros(1, dtype=torch.float64, device=dev) for _ in s.subsystems]
         self.oinfo = [torch.zeros(1, dtype=torch.int32, device=dev) for _ in s.subsystems]
         self._make_groups(max_nb, nproj_max, nblocks)
+        if self.mixer is not None:
+            if self.mixer.get("kind", "pulay") != "pulay":
+                raise fde.FdeError("mixer kind must be 'pulay' (None for linear mixing)")
+            nh = int(self.mixer.get("nhist", 6))
+            self.mix_state = torch.zeros(3, dtype=torch.int32, device=dev)
+            self.mix_info = torch.zeros(1, dtype=torch.int32, device=dev)
+            self.x_hist = torch.zeros((nh, ns) + p.shape, dtype=p.rdtype, device=dev)
+            self.r_hist = torch.zeros_like(self.x_hist)
         self._initial_density()
 
     def _make_groups(self, max_nb, nproj_max, nblocks):
@@ -216,13 +227,18 @@ class Engine:
         for I, sub in enumerate(s.subsystems):
             for b in self.blocks[I]:
                 self.eps[I][b.j].copy_(b.eval)
-            mode = fde.OCC_INTEGER if sub.smearing == "integer" else fde.OCC_FERMI_DIRAC
+            mode = {"integer": fde.OCC_INTEGER, "fermi-dirac": fde.OCC_FERMI_DIRAC,
+                    "methfessel-paxton": fde.OCC_METHFESSEL_PAXTON}[sub.smearing]
             fde.occupations(self.be, self.eps[I], self.wk[I], sub.nelec, mode, max(sub.sigma, 1e-300),
                             occw=self.occw[I], mu=self.mu[I], info=self.oinfo[I])
             self.rho_out[I].zero_()
             for b in self.blocks[I]:
                 p.density(b.ik, b.V[:b.nb], self.occw[I][b.j], self.rho_out[I])
-        fde.mix(self.be, self.rho_in, self.rho_out, s.mix_beta)
+        if self.mixer is None:
+            fde.mix(self.be, self.rho_in, self.rho_out, s.mix_beta)
+        else:
+            p.mix_pulay(self.mix_state, self.x_hist, self.r_hist, self.rho_in, self.rho_out,
+                        float(self.mixer.get("beta", 0.5)), float(self.mixer.get("q0", 0.0)), info=self.mix_info)
 
     # ---- energies ----------------------------------------------------------------
     def total_energies(self) -> torch.Tensor:

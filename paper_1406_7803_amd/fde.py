@@ -23,7 +23,8 @@ EMU_PATH = os.path.join(HERE, "libfde_emu.so")
 F64, F32 = 0, 1
 XC_NONE, XC_LDA = 0, 1
 KIN_NONE, KIN_TF, KIN_LC94 = 0, 1, 2
-OCC_INTEGER, OCC_FERMI_DIRAC = 0, 1
+OCC_INTEGER, OCC_FERMI_DIRAC, OCC_METHFESSEL_PAXTON = 0, 1, 2
+PULAY_MAX = 8
 NE = 8
 E_XC, E_XCNAD, E_KIN, E_LOC, E_HEMB, E_HSELF, E_DEBAND, E_CHARGE = range(NE)
 
@@ -34,7 +35,7 @@ SYMBOLS = [
     "fde_local_potential", "fde_kb_projectors", "fde_init_bands", "fde_band_energies", "fde_grid_dot",
     "fde_subspace_rr_batched", "fde_precondition_batched", "fde_grid_mean", "fde_precondition_mlp_batched",
     "fde_mlp_forward", "fde_mlp_workspace_bytes", "fde_mlp_loss_grad", "fde_mlp_adam", "fde_plan_set_gemm_mode",
-    "fde_plan_set_tuning", "fde_energy_total", "fde_mlp_loss_grad_static",
+    "fde_plan_set_tuning", "fde_energy_total", "fde_mlp_loss_grad_static", "fde_mix_pulay",
 ]
 TUNE_APPLY_BPW = 1
 TUNE_STICK_GROUP = 2
@@ -85,6 +86,7 @@ def _declare(lib):
     lib.fde_precondition.argtypes = [_P, _I, _I, _P, _P, _P, _P, _P, _P, _P]
     lib.fde_occupations.argtypes = [_I, _I, _P, _P, _D, _I, _D, _P, _P, _P, _P]
     lib.fde_mix.argtypes = [_S, _D, _P, _P, _I, _P]
+    lib.fde_mix_pulay.argtypes = [_P, _I, _I, _P, _P, _P, _P, _P, _D, _D, _P, _P]
     lib.fde_local_potential.argtypes = [_P, _I, _P, _P, _P, _P, _P]
     lib.fde_kb_projectors.argtypes = [_P, _I, _I, _P, _P, _P, _P, _P, _P]
     lib.fde_init_bands.argtypes = [_P, _I, _I, _P, _P, _P]
@@ -402,6 +404,24 @@ class Plan:
         out = torch.zeros(1, dtype=torch.float64, device=self.be.device) if out is None else out
         self._check(self.lib.fde_grid_mean(self.h, _ptr(a), _ptr(out), self.be.stream()))
         return out
+
+    def mix_pulay(self, state: torch.Tensor, x_hist: torch.Tensor, r_hist: torch.Tensor, rho_in: torch.Tensor,
+                  rho_out: torch.Tensor, beta: float, q0: float, info=None):
+        """fde_mix_pulay: state int32 [3] (zero to start), histories [nhmax][ns][N3][N2][N1]."""
+        self._grid(rho_in, "rho_in")
+        self._grid(rho_out, "rho_out")
+        self._grid(x_hist, "x_hist")
+        self._grid(r_hist, "r_hist")
+        ns = rho_in.shape[0] if rho_in.dim() == 4 else 1
+        nhmax = x_hist.shape[0]
+        if x_hist.shape != r_hist.shape or x_hist.numel() != nhmax * rho_in.numel() or rho_out.shape != rho_in.shape:
+            raise FdeError("x_hist, r_hist must be [nhmax] + rho_in.shape")
+        if state.dtype != torch.int32 or state.numel() < 3 or state.device != self.be.device:
+            raise FdeError("state must be an int32 device tensor of 3 values")
+        info = torch.zeros(1, dtype=torch.int32, device=self.be.device) if info is None else info
+        self._check(self.lib.fde_mix_pulay(self.h, ns, nhmax, _ptr(state), _ptr(x_hist), _ptr(r_hist), _ptr(rho_in),
+                                           _ptr(rho_out), float(beta), float(q0), _ptr(info), self.be.stream()))
+        return rho_in, info
 
     def precondition_mlp_batched(self, blocks, params: torch.Tensor, vbar: torch.Tensor):
         """fde_precondition_batched with the learned network; vbar: [len(blocks)] float64 device."""

@@ -270,15 +270,24 @@ def check_occupations(be):
     dev = be.device
     eps = np.array([[-0.5, -0.3, -0.1, 0.2, 0.4], [-0.45, -0.28, -0.05, 0.25, 0.5]])
     wk = np.array([0.5, 0.5])
-    for nel, mode, sig in [(6.0, "fermi-dirac", 0.01), (5.0, "fermi-dirac", 0.05), (4.0, "integer", 0.0)]:
+    modes = {"integer": fde.OCC_INTEGER, "fermi-dirac": fde.OCC_FERMI_DIRAC,
+             "methfessel-paxton": fde.OCC_METHFESSEL_PAXTON}
+    for nel, mode, sig in [(6.0, "fermi-dirac", 0.01), (5.0, "fermi-dirac", 0.05), (4.0, "integer", 0.0),
+                           (6.0, "methfessel-paxton", 0.01), (5.0, "methfessel-paxton", 0.05),
+                           (7.3, "methfessel-paxton", 0.02)]:
         f, mu = oocc.occupations(eps, wk, nel, mode, sig)
-        m = fde.OCC_INTEGER if mode == "integer" else fde.OCC_FERMI_DIRAC
+        m = modes[mode]
         occw, tmu, info = fde.occupations(be, torch.tensor(eps, device=dev), torch.tensor(wk, device=dev), nel, m,
                                           max(sig, 1e-300))
         be.sync()
         assert int(host(info)[0]) == 0
         assert np.max(np.abs(host(occw) - wk[:, None] * f)) < 1e-10
         assert abs(float(host(occw).sum()) - nel) < 1e-12
+    # odd or fractional counts cannot fill whole bands
+    for nel in (5.0, 3.5):
+        with pytest.raises(fde.FdeError):
+            fde.occupations(be, torch.tensor(eps, device=dev), torch.tensor(wk, device=dev), nel, fde.OCC_INTEGER,
+                            1e-300)
 
 
 _ORACLE_RUNS = {}
@@ -684,3 +693,57 @@ def check_trajectory_uneven(be, prec, n_cycles=3):
     assert worst_e < 1e-6 * max(1.0, emax), (worst_e, emax)
     assert worst_d < 2.5e-6, worst_d
     return worst_e, worst_d
+
+
+# ---------------------------------------------------------------------------
+# Pulay mixing with a Kerker preconditioner; cycles with it and with
+# Methfessel-Paxton smearing
+# ---------------------------------------------------------------------------
+def check_mix_pulay(be, prec, q0, nhmax=4, ncalls=7, ns=2):
+    """A sequence of calls with the history wrapping around, against oracle.mixing."""
+    from oracle import mixing as omix
+    L, grid = (6.0, 6.0, 7.0), (12, 12, 15)
+    cell = basis.Cell(L, grid)
+    plan = fde.Plan(L, grid, 2.2, [(0, 0, 0)], prec=prec, max_nb=2, backend=be)
+    ref = omix.Mixer(cell, "pulay", beta=0.4, nhist=nhmax, q0=q0)
+    dev = plan.be.device
+    state = torch.zeros(3, dtype=torch.int32, device=dev)
+    xh = torch.zeros((nhmax, ns) + plan.shape, dtype=plan.rdtype, device=dev)
+    rh = torch.zeros_like(xh)
+    x = fde_synth.random_real(70, (ns,) + cell.shape, 0.0, 1.0)
+    if prec == fde.F32:
+        x = x.astype(np.float32).astype(np.float64)
+    rho_in = to_dev(plan, x, "r")
+    for k in range(ncalls):
+        # a smooth nonlinear map of the input, so the residuals stay independent
+        y = 0.5 * np.tanh(x + 0.3 * np.roll(x, 1, axis=-1)) + fde_synth.random_real(71 + k, x.shape, 0.0, 0.05)
+        if prec == fde.F32:
+            y = y.astype(np.float32).astype(np.float64)
+        want = ref(x, y)
+        got, info = plan.mix_pulay(state, xh, rh, rho_in, to_dev(plan, y, "r"), 0.4, q0)
+        be.sync()
+        assert int(host(info)[0]) == 0
+        g = host(got).astype(np.float64)
+        tol = 1e-11 if prec == fde.F64 else 5e-5
+        assert rel(g, want) < tol, (k, rel(g, want))
+        assert list(host(state)) [:2] == [min(k + 1, nhmax), (k + 1) % nhmax]
+        x = g  # continue from what the library produced (rounding stays in step)
+
+
+def check_trajectory_pulay(be, prec, system, n_cycles, eps_tol, drho_tol, mixer):
+    from oracle import mixing as omix
+    st = oscf.setup(system)
+    recs, _, _ = oscf.run(system, n_cycles=n_cycles, st=st,
+                          mixer=omix.Mixer(st.cell, "pulay", mixer["beta"], mixer["nhist"], mixer["q0"]))
+    eng = driver.Engine(system, prec=prec, backend=be, mixer=mixer)
+    worst = (0.0, 0.0)
+    for c in range(n_cycles):
+        eng.cycle()
+        be.sync()
+        for I in range(len(system.subsystems)):
+            e = np.max(np.abs(host(eng.eps[I]) - recs[c].eps[I]))
+            d = float(np.sum(np.abs(host(eng.rho_out[I]) - recs[c].rho_out[I]))) * st.cell.dV
+            worst = (max(worst[0], e), max(worst[1], d))
+    assert int(host(eng.mix_info)[0]) == 0
+    assert worst[0] < eps_tol and worst[1] < drho_tol, worst
+    return worst

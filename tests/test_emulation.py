@@ -166,3 +166,15 @@ def test_energies_c1(be):
 
 def test_embed_vacuum_and_empty_subsystem(be):
     pc.check_embed_grid(be, fde.F64, (24, 48, 60), 0.25)
+
+
+@pytest.mark.parametrize("q0", [0.0, 0.7])
+def test_mix_pulay(be, q0):
+    pc.check_mix_pulay(be, fde.F64, q0)
+
+
+def test_trajectory_pulay_mp(be):
+    s = fde_synth.tiny(0, with_kb=True, kfrac=[(0.25, 0.0, 0.0), (-0.25, 0.0, 0.0)], grid=(12, 12, 15))
+    for sub in s.subsystems:
+        sub.smearing = "methfessel-paxton"
+    pc.check_trajectory_pulay(be, fde.F64, s, 3, 1e-10, 1e-10, dict(kind="pulay", nhist=4, beta=0.5, q0=0.6))

@@ -134,6 +134,26 @@ def test_trajectory_uneven_subsystems(be, prec):
     pc.check_trajectory_uneven(be, prec)
 
 
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("q0", [0.0, 0.7])
+def test_mix_pulay(be, prec, q0):
+    pc.check_mix_pulay(be, prec, q0)
+
+
+def test_trajectory_pulay_kerker_c1(be):
+    pc.check_trajectory_pulay(be, fde.F64, fde_synth.config1(), 10, 1e-10, 1e-10,
+                              dict(kind="pulay", nhist=6, beta=0.5, q0=0.5))
+    pc.check_trajectory_pulay(be, fde.F32, fde_synth.config1(), 10, 1e-6, 1e-5,
+                              dict(kind="pulay", nhist=6, beta=0.5, q0=0.5))
+
+
+def test_trajectory_methfessel_paxton(be):
+    s = fde_synth.tiny(0, with_kb=True, kfrac=[(0.25, 0.0, 0.0), (-0.25, 0.0, 0.0)], grid=(12, 12, 15))
+    for sub in s.subsystems:
+        sub.smearing = "methfessel-paxton"
+    pc.check_trajectory_pulay(be, fde.F64, s, 4, 1e-10, 1e-10, dict(kind="pulay", nhist=4, beta=0.5, q0=0.6))
+
+
 # ---------------------------------------------------------------------------
 # Full-size slab + molecule cell (60 x 60 x 240, ~50 300 plane waves), in the
 # launch configuration the benchmark times: all 40 slab bands in one call;
