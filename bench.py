@@ -1,69 +1,88 @@
 """Benchmark: H|psi> band-applies/s and embedding-cycle time on one MI355X.
 
-Workload (default): the slab + molecule cell -- 10.2 x 10.2 x 40 bohr,
-60 x 60 x 240 grid, E_cut = 40 Ha (about 50 300 plane waves per k); slab of
-36 Gaussian ions with one s projector each, 40 bands, 4 Monkhorst-Pack
-k-points, Fermi-Dirac 0.01 Ha; a 6-atom molecule at Gamma with 8 bands.
-Synthetic seeded inputs of that shape (the paper's systems need
-pseudopotential files that are not available).
+Default workload (the benchmark line): the large metal-surface cell -- 20.4 x
+20.4 x 60 bohr, 144 x 144 x 432 grid, E_cut = 26 Ha (about 158 000 plane
+waves per k); a 144-atom slab with s + p Kleinman-Bylander projectors (576),
+320 bands, 2 k-points, Fermi-Dirac 0.01 Ha; four 6-atom molecules at Gamma
+with 8 bands each. Synthetic seeded inputs of that shape (the paper's systems
+need pseudopotential files that are not available).
 
-A step is one embedding cycle: embedding potential of both subsystems, per
-subsystem and k-point one H application + Rayleigh-Ritz then 4 Davidson
-iterations (preconditioner, H application, Rayleigh-Ritz), occupations,
-densities and mixing. `value` is band-applies per cycle / cycle time.
+A step is one embedding cycle (one HIP graph replay): embedding potential of
+all subsystems, per subsystem and k-point one H application + Rayleigh-Ritz
+then 4 Davidson iterations (preconditioner, H application, Rayleigh-Ritz),
+occupations, densities and mixing. `value` is band-applies per cycle / cycle
+time, FP32 plan.
 
-The roofline object covers one H application (stick inverse FFT, plane pass
-with V_eff, stick forward FFT + kinetic term, Kleinman-Bylander projector
-products and update), timed with HIP events on the stream the kernels run on,
-over an isolated resident batch of all 40 slab bands at one k-point with the
-slab's 36 projectors. Algorithmic bytes per call (complex of `cs` bytes, V_eff
-real of `rs` bytes; V_eff and the projectors counted once per call, whatever the
-launch shape re-reads):
-    nb * (3*cs*npw + 4*cs*ncol*N3) + rs*N + nproj*cs*npw.
+The roofline object is one fde_apply_h call on all 320 slab bands at one
+k-point without projectors: the FFT sandwich (stick inverse FFT, in-plane pass
+with V_eff, stick forward FFT + kinetic term), which is bound by FP32 vector
+arithmetic on this grid. Algorithmic flops per band-apply, with the 5 n log2 n
+convention per transform of length n:
+    10 N3 log2(N3) ncol + 10 N1 N2 log2(N1 N2) N3 + 2 N,
+timed with HIP events on the library's stream. Algorithmic bytes (complex of
+cs bytes, V_eff real of rs bytes, V_eff counted once per call):
+    nb (3 cs npw + 4 cs ncol N3) + rs N.
 
-`--workload 64-subsystems` times the cycle of the 20 bohr cube holding 64 uneven
-subsystems (72^3 grid, E_cut 15 Ha, 4-128 bands and 1-8 k-points each) instead;
-that line is context, without CPU baseline or counter traffic.
+Also in the line: the same call with the projectors, the precision study of the
+large cell (FP64 plan as the reference; FP32 plan with FP64, BF16x3 and BF16x6
+subspace products: Ritz-value and density errors per cycle), the slab +
+molecule cell (cycle and H application), the time to 1e-6 Ha of the band
+solver at a fixed self-consistent potential of the slab + molecule cell (FP64 +
+TPA, FP32 + TPA, FP32 + learned preconditioner), the oracle timed on the host
+cores, and the attainable copy bandwidth.
+
+`--workload slab-molecule` / `64-subsystems` time those cells' cycles instead.
+`--apply-only` runs only the isolated H application (for counter profiles).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
+import math
 import os
+import subprocess
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+METRIC = "H|ψ> band-applies/s and embedding-cycle time, FP32+learned vs FP64 @1e-6 Ha"
 HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFS = 157.3
 # sources of the kernels one fde_apply_h call runs (the counter summary is tied to them)
-APPLY_SOURCES = ["common.hpp", "kernels_gemm.hpp", "kernels_plane.hpp", "kernels_pw.hpp", "pw.hip"]
+APPLY_SOURCES = ["common.hpp", "kernels_gemm.hpp", "kernels_plane.hpp", "kernels_plane4.hpp", "kernels_pw.hpp",
+                 "pw.hip"]
+TRAFFIC_FILE = {"large-slab": "apply_h_large_slab_144x144x432.traffic.txt",
+                "slab-molecule": "apply_h_slab_molecule_60x60x240.traffic.txt"}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--prec", choices=["fp32", "fp64"], default="fp32")
-    ap.add_argument("--apply-reps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["large-slab", "slab-molecule", "64-subsystems"], default="large-slab")
+    ap.add_argument("--apply-reps", type=int, default=10)
+    ap.add_argument("--apply-only", action="store_true", help="only the isolated H application, then exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-bands", type=int, default=40)
-    ap.add_argument("--also-fp64", action="store_true", help="also time the FP64 cycle")
-    ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
+    ap.add_argument("--no-precision-study", action="store_true")
     ap.add_argument("--no-tta", action="store_true", help="skip the time-to-1e-6 Ha comparison")
+    ap.add_argument("--no-second-cell", action="store_true", help="skip the slab + molecule line")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
     ap.add_argument("--streams", type=int, default=3, help="concurrent band-solver groups")
     ap.add_argument("--gemm", choices=["fp64", "bf16x3", "bf16x6"], default="fp64",
                     help="arithmetic of the Rayleigh-Ritz subspace products (FP32 plan)")
-    ap.add_argument("--workload", choices=["slab-molecule", "64-subsystems"], default="slab-molecule",
-                    help="slab + molecule cell (the benchmark line) or the cube of 64 uneven subsystems "
-                         "(timed for context: no CPU baseline, no counter traffic)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only time a plain device-to-device copy of MIB MiB (stream bandwidth and "
                          "the calibration of the HBM byte counters), then exit")
     return ap.parse_args()
+
+
+def log(msg):
+    print(f"# {msg}", file=sys.stderr, flush=True)
 
 
 def copy_probe(mib, reps=10):
@@ -86,28 +105,34 @@ def copy_probe(mib, reps=10):
             "copy_GBps": 2 * 4 * n / t / 1e9}
 
 
-def apply_bytes(plan, ik, nb, nproj):
+def sandwich_model(plan, ik, nb):
+    """Algorithmic flops and bytes of one fde_apply_h call without projectors."""
     cs = 16 if plan.prec == 0 else 8
     rs = cs // 2
     N1, N2, N3 = plan.grid
+    N = N1 * N2 * N3
     npw, ncol = plan.npw(ik), plan.ncol(ik)
-    per_band = 3 * cs * npw + 4 * cs * ncol * N3
-    return per_band * nb + rs * N1 * N2 * N3 + cs * npw * nproj
+    flops = nb * (10 * N3 * math.log2(N3) * ncol + 10 * N1 * N2 * math.log2(N1 * N2) * N3 + 2 * N)
+    nbytes = nb * (3 * cs * npw + 4 * cs * ncol * N3) + rs * N
+    return flops, nbytes
 
 
-def measured_traffic():
-    """HBM bytes per fde_apply_h call from the committed counter summary, or None
-    when the sources of its kernels changed since the counters were taken."""
-    import hashlib
-    f = os.path.join(ROOT, "profiles", "apply_h_slab_molecule_60x60x240.traffic.txt")
-    if not os.path.exists(f):
-        return None
-    kv = dict(line.split()[:2] for line in open(f) if line.strip() and not line.startswith("#"))
+def sources_hash():
     h = hashlib.sha256()
     for src in sorted(os.path.join(ROOT, "paper_1406_7803_amd", "csrc", n) for n in APPLY_SOURCES):
         h.update(os.path.basename(src).encode())
         h.update(open(src, "rb").read())
-    if h.hexdigest() != kv.get("sources_sha256"):
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM bytes per fde_apply_h call from the committed counter summary, or None
+    when the sources of its kernels changed since the counters were taken."""
+    f = os.path.join(ROOT, "profiles", TRAFFIC_FILE.get(workload, "-"))
+    if not os.path.exists(f):
+        return None
+    kv = dict(line.split()[:2] for line in open(f) if line.strip() and not line.startswith("#"))
+    if sources_hash() != kv.get("sources_sha256"):
         return None
     return float(kv["traffic_bytes_per_call"])
 
@@ -129,152 +154,315 @@ def time_cycles(eng, steps, warmup, graph=False):
             eng.replay()
         else:
             eng.cycle()
-        print(f"# cycle {k + 1}/{steps} enqueued", file=sys.stderr, flush=True)
+        log(f"cycle {k + 1}/{steps} enqueued")
     s1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return s0.elapsed_time(s1) / 1e3, wall
 
 
-def time_to_accuracy(be, max_cycles=300):
-    """Wall time until the two-subsystem cube's occupied eigenvalues are within 1e-6 Ha
-    and every subsystem density within 1e-5 (integrated |drho|) of the converged FP64
-    result, per precision mode (engine set-up excluded; each cycle is followed by the
-    same device-to-host check in every mode)."""
-    import numpy as np
+def slab_block(eng):
+    return max((b for row in eng.blocks for b in row), key=lambda b: b.nb * eng.plan.npw(b.ik))
+
+
+def isolated_apply(eng, reps, with_proj):
+    """Median-free mean time of fde_apply_h on the largest block (events on the plan's stream)."""
     import torch
+    plan = eng.plan
+    b = slab_block(eng)
+    X = b.V[:b.nb].clone()
+    HX = torch.empty_like(X)
+    veff = eng.veff[b.isub]
+    beta, dkb = (b.beta, b.dkb) if with_proj else (None, None)
+    for _ in range(2):
+        plan.apply_h(b.ik, X, veff, beta, dkb, out=HX)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        plan.apply_h(b.ik, X, veff, beta, dkb, out=HX)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    nproj = 0 if beta is None else beta.shape[0]
+    return b, t, nproj
 
-    import fde_synth
-    from paper_1406_7803_amd import driver, fde
 
-    s = fde_synth.config1()
-    dv = float(np.prod(s.L)) / float(np.prod(s.grid))
+def roofline_object(eng, reps, workload):
+    b, t, _ = isolated_apply(eng, reps, with_proj=False)
+    flops, nbytes = sandwich_model(eng.plan, b.ik, b.nb)
+    achieved = flops / t / 1e12
+    traffic = measured_traffic(workload)
+    return {"kernel": "fde_apply_h without projectors: FFT sandwich (stick inverse FFT, in-plane pass with V_eff, "
+                      "stick forward FFT + kinetic term)",
+            "bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFS, "unit": "TFLOP/s",
+            "frac": achieved / FP32_VECTOR_PEAK_TFS, "traffic": traffic,
+            "algorithmic_flops": flops, "algorithmic_bytes": nbytes, "bands": b.nb, "ms_per_call": t * 1e3,
+            "hbm_GBps_algorithmic": nbytes / t / 1e9, "hbm_frac_algorithmic": nbytes / t / 1e9 / HBM_PEAK_GBS}
 
-    def state(e):
-        torch.cuda.synchronize()
-        return [x.double().cpu().numpy().copy() for x in e.eps], e.rho_out.double().cpu().numpy().copy()
 
-    ref = driver.Engine(s, prec=fde.F64, backend=be)
-    prev = None
-    for c in range(max_cycles):
-        ref.cycle()
-        eps, rho = state(ref)
-        if prev is not None and max(np.max(np.abs(a - b)) for a, b in zip(eps, prev[0])) < 1e-11 \
-                and np.sum(np.abs(rho - prev[1])) * dv < 1e-10:
-            break
-        prev = (eps, rho)
-    ref_cycles = c + 1
-    occ = [o.cpu().numpy() > 1e-8 for o in ref.occw]
-    out = {"system": "two-subsystem 10 bohr cube, 24^3, E_cut 7 Ha", "reference": f"FP64, {ref_cycles} cycles"}
-    for name, prec, gemm in (("fp64", fde.F64, fde.GEMM_FP64), ("fp32", fde.F32, fde.GEMM_FP64),
-                             ("fp32_bf16x6", fde.F32, fde.GEMM_BF16X6)):
-        warm = driver.Engine(s, prec=prec, backend=be, gemm=gemm)  # first launches of this mode's kernels
-        warm.cycle()
-        del warm
-        eng = driver.Engine(s, prec=prec, backend=be, gemm=gemm)
+def cycle_errors(ref_hist, hist, dv, nelec):
+    """Per cycle: max |d eps| over occupied levels and max_I int |d rho_I| (also per electron)."""
+    import numpy as np
+    out = []
+    for (e0, o0, r0), (e1, _, r1) in zip(ref_hist, hist):
+        de = max(float(np.max(np.abs((a - b)[o > 1e-8]))) for a, b, o in zip(e1, e0, o0))
+        dr = [float(np.sum(np.abs(r1[I] - r0[I]))) * dv for I in range(len(r0))]
+        out.append({"max_deps_occ_Ha": de, "max_int_drho": max(dr),
+                    "max_int_drho_per_electron": max(d / n for d, n in zip(dr, nelec))})
+    return out
+
+
+def run_cycles(eng, n):
+    import torch
+    hist, times = [], []
+    for _ in range(n):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        hit = None
-        for c in range(max_cycles):
-            eng.cycle()
-            e, r = state(eng)
-            de = max(np.max(np.abs(a[o] - b[o])) for a, b, o in zip(e, eps, occ))
-            dr = max(np.sum(np.abs(r[I] - rho[I])) * dv for I in range(len(s.subsystems)))
-            if de <= 1e-6 and dr <= 1e-5:
-                hit = (c + 1, time.perf_counter() - t0)
-                break
-        out[name] = None if hit is None else {"cycles": hit[0], "seconds": hit[1]}
-    if out["fp64"] and out["fp32"]:
-        out["speedup_fp32_over_fp64"] = out["fp64"]["seconds"] / out["fp32"]["seconds"]
+        eng.cycle()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        hist.append(([e.cpu().numpy().copy() for e in eng.eps], [o.cpu().numpy().copy() for o in eng.occw],
+                     eng.rho_out.double().cpu().numpy().copy()))
+    return hist, times
+
+
+def precision_study(system, be, n_cycles=3):
+    """The large cell's fixed schedule with the FP64 plan (reference) and the FP32 plan
+    with each subspace-product mode; errors of every FP32 run against the FP64 one."""
+    import numpy as np
+    import torch
+    from paper_1406_7803_amd import driver, fde
+    dv = float(np.prod(system.L)) / float(np.prod(system.grid))
+    nelec = [s.nelec for s in system.subsystems]
+    log("precision study: FP64 reference")
+    eng = driver.Engine(system, prec=fde.F64, backend=be)
+    ref, t64 = run_cycles(eng, n_cycles)
+    del eng
+    torch.cuda.empty_cache()
+    out = {"cycles": n_cycles, "reference": "FP64 plan, FP64 subspace products",
+           "fp64": {"s_per_cycle": t64}}
+    for name, gemm in (("fp32", fde.GEMM_FP64), ("fp32_bf16x6", fde.GEMM_BF16X6),
+                       ("fp32_bf16x3", fde.GEMM_BF16X3)):
+        log(f"precision study: {name}")
+        eng = driver.Engine(system, prec=fde.F32, backend=be, gemm=gemm)
+        hist, t = run_cycles(eng, n_cycles)
+        ok = all(int(b.info.item()) == 0 for row in eng.blocks for b in row)
+        del eng
+        torch.cuda.empty_cache()
+        out[name] = {"s_per_cycle": t, "errors_per_cycle": cycle_errors(ref, hist, dv, nelec), "info_ok": ok}
     return out
+
+
+def network_params(be):
+    """The learned preconditioner's parameters (FP32): tests/golden/mlp_params.npy, trained
+    offline on Jacobi-Davidson corrections of small cells; None when absent."""
+    import numpy as np
+    import torch
+    f = os.path.join(ROOT, "tests", "golden", "mlp_params.npy")
+    if not os.path.exists(f):
+        return None
+    return torch.from_numpy(np.load(f).astype(np.float32)).to(be.device)
+
+
+def time_to_accuracy(be, max_scf=150, n_iter=60):
+    """Band solver at a fixed self-consistent potential of the slab + molecule cell:
+    the FP64 cycle (Pulay + Kerker) is iterated until the density residual is below
+    1e-4 electrons; at that V_eff the slab's bands at the first k-point are solved from
+    the same seeded start with FP64 + TPA, FP32 + TPA and FP32 + the learned
+    preconditioner. Iterations until every occupied Ritz value is within 1e-6 Ha of the
+    FP64 solution after n_iter iterations, and the wall time of those iterations
+    (measured time per iteration x iterations)."""
+    import numpy as np
+    import torch
+    import fde_synth
+    from paper_1406_7803_amd import driver, fde
+    s = fde_synth.config2()
+    dv = float(np.prod(s.L)) / float(np.prod(s.grid))
+    mixer = dict(kind="pulay", nhist=8, beta=0.5, q0=0.8)
+    eng = driver.Engine(s, prec=fde.F64, backend=be, mixer=mixer)
+    scf_cycles, resid = 0, None
+    for c in range(max_scf):
+        rin = eng.rho_in.clone()
+        eng.cycle()
+        resid = float((eng.rho_out - rin).abs().sum()) * dv
+        scf_cycles = c + 1
+        if resid < 1e-4:
+            break
+    b = eng.blocks[0][0]
+    veff64 = eng.veff[0].clone()
+    occ = (eng.occw[0][b.j] > 1e-8).cpu().numpy()
+    raw = fde_synth.random_coefficients(5, 0, 0, b.ik, b.nb, eng.plan.npw(b.ik))
+    beta64, dkb = b.beta.clone(), b.dkb.clone()
+    del eng
+    torch.cuda.empty_cache()
+    out = {"system": "slab + molecule cell, slab bands at k = (1/4, 1/4, 0), fixed V_eff",
+           "scf": {"cycles": scf_cycles, "density_residual": resid, "mixing": mixer}}
+    params = network_params(be)
+    runs = {}
+    for name, prec, mlp in (("fp64_tpa", fde.F64, False), ("fp32_tpa", fde.F32, False),
+                            ("fp32_mlp", fde.F32, True)):
+        if mlp and params is None:
+            continue
+        plan = fde.Plan(s.L, s.grid, s.ecut, s.all_kfrac, prec=prec, max_nb=b.nb, max_nproj=beta64.shape[0],
+                        backend=be)
+        X0 = plan.init_bands(b.ik, torch.from_numpy(raw).to(dtype=plan.cdtype, device=be.device))
+        v = veff64.to(plan.rdtype)
+        beta = beta64.to(plan.cdtype)
+        driver.davidson_fixed(plan, b.ik, X0, v, 2, beta=beta, dkb=dkb, mlp_params=params if mlp else None)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hist, info = driver.davidson_fixed(plan, b.ik, X0, v, n_iter, beta=beta, dkb=dkb,
+                                           mlp_params=params if mlp else None)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        runs[name] = ([h.cpu().numpy() for h in hist], wall / n_iter, int(info.item()))
+        del plan
+    ref = runs["fp64_tpa"][0][-1]
+    for name, (hist, per_it, info) in runs.items():
+        it = next((i + 1 for i, ev in enumerate(hist) if np.max(np.abs(ev[occ] - ref[occ])) <= 1e-6), None)
+        out[name] = {"iterations": it, "seconds": None if it is None else it * per_it,
+                     "ms_per_iteration": per_it * 1e3, "info": info,
+                     "final_max_deps_occ_Ha": float(np.max(np.abs(hist[-1][occ] - ref[occ])))}
+    if out.get("fp32_mlp", {}).get("seconds") and out["fp64_tpa"]["seconds"]:
+        out["speedup_fp64_tpa_over_fp32_mlp"] = out["fp64_tpa"]["seconds"] / out["fp32_mlp"]["seconds"]
+    if out.get("fp32_tpa", {}).get("seconds") and out["fp64_tpa"]["seconds"]:
+        out["speedup_fp64_tpa_over_fp32_tpa"] = out["fp64_tpa"]["seconds"] / out["fp32_tpa"]["seconds"]
+    if params is None:
+        out["fp32_mlp"] = "not run: tests/golden/mlp_params.npy absent"
+    return out
+
+
+def second_cell(be, a):
+    """The slab + molecule cell: cycle time (graph replays) and the isolated H application."""
+    import torch
+    import fde_synth
+    from paper_1406_7803_amd import driver, fde
+    s = fde_synth.config2()
+    eng = driver.Engine(s, prec=fde.F32, backend=be, streams=a.streams)
+    eng.cycle()
+    tuned = eng.autotune()
+    secs, _ = time_cycles(eng, 10, 2, graph=True)
+    per_cycle = eng.band_applies_per_cycle()
+    b, t, nproj = isolated_apply(eng, 50, with_proj=True)
+    out = {"workload": "slab+molecule 10.2x10.2x40 bohr, 60x60x240 grid, Ecut 40 Ha, slab 36 ions/40 bands/4 k "
+                       "+ molecule 6 ions/8 bands/Gamma",
+           "band_applies_per_s": per_cycle * 10 / secs, "ms_per_cycle": secs / 10 * 1e3,
+           "isolated_apply_h": {"band_applies_per_s": b.nb / t, "bands": b.nb, "projectors": nproj,
+                                "ms_per_call": t * 1e3},
+           "roofline": roofline_object(eng, 50, "slab-molecule"), "autotune": {k: tuned[k] for k in ("plane", "rows", "bpw")}}
+    del eng
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(system, n_bands=8):
+    """The oracle (FFT mode, all host cores) timed on a bounded sample of the same workload:
+    H application (local potential + Kleinman-Bylander projectors) of n_bands slab bands
+    at one k-point; and one cycle of the two-subsystem cube for scale."""
+    import numpy as np
+    import fde_synth
+    from oracle import basis, dft, hamiltonian as oham, pseudo as opseudo, scf as oscf
+    cores = len(os.sched_getaffinity(0))
+    dft.set_mode("fft", cores)
+    try:
+        cell = basis.Cell(system.L, system.grid)
+        sph = basis.sphere(cell, system.ecut, system.subsystems[0].kfrac[0])
+        beta, dkb = opseudo.kb_projectors(cell, sph, system.subsystems[0].atoms)
+        veff = fde_synth.random_real(3, cell.shape, -1, 1)
+        psi = fde_synth.random_complex(4, (n_bands, sph.npw))
+        t0 = time.perf_counter()
+        oham.apply_h(cell, sph, psi, veff, beta, dkb)
+        tc = time.perf_counter() - t0
+        s1 = fde_synth.config1()
+        st = oscf.setup(s1)
+        t1 = time.perf_counter()
+        oscf.run(s1, n_cycles=2, st=st)
+        c1 = (time.perf_counter() - t1) / 2
+    finally:
+        dft.set_mode("naive")
+    model = ""
+    try:
+        model = [l.split(":", 1)[1].strip() for l in subprocess.run(["lscpu"], capture_output=True, text=True).stdout
+                 .splitlines() if l.startswith("Model name")][0]
+    except Exception:
+        pass
+    return {"value": n_bands / tc, "unit": "band-applies/s", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 oracle (scipy.fft mode, {cores} threads) H application of {n_bands} slab bands with "
+                      f"{beta.shape[0]} projectors at one k-point of the same cell, {tc:.1f} s",
+            "cpu_model": model, "cycle_s_two_subsystem_cube": c1}
 
 
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "this benchmark measures one GPU only; runs on several GPUs are not part of it",
                           "n_gpus": a.gpus}))
         return 2
     if a.copy_probe:
         print(json.dumps(copy_probe(a.copy_probe)))
         return 0
-    import numpy as np
     import torch
 
     import fde_synth
     from paper_1406_7803_amd import driver, fde
 
-    prec = fde.F32 if a.prec == "fp32" else fde.F64
     be = fde.gpu_backend("cuda:0")
-    many = a.workload == "64-subsystems"
-    system = fde_synth.config3() if many else fde_synth.config2()
-    print("# building engine", file=sys.stderr, flush=True)
+    system = {"large-slab": fde_synth.config4, "slab-molecule": fde_synth.config2,
+              "64-subsystems": fde_synth.config3}[a.workload]()
+    log(f"building engine ({a.workload})")
     gemm = {"fp64": fde.GEMM_FP64, "bf16x3": fde.GEMM_BF16X3, "bf16x6": fde.GEMM_BF16X6}[a.gemm]
-    eng = driver.Engine(system, prec=prec, backend=be, gemm=gemm, streams=a.streams)
+    eng = driver.Engine(system, prec=fde.F32, backend=be, gemm=gemm, streams=a.streams)
     torch.cuda.synchronize()
-    print("# engine ready", file=sys.stderr, flush=True)
+    log("engine ready")
+    eng.cycle()  # a potential and bands to time with
     tuned = None
     if not a.no_autotune:
-        eng.cycle()  # a potential and bands to time with
-        tuned = eng.autotune()
-        print(f"# autotune: {tuned}", file=sys.stderr, flush=True)
+        tuned = eng.autotune(reps=3)
+        log(f"autotune: {tuned}")
+    if a.apply_only:
+        b, t, nproj = isolated_apply(eng, a.apply_reps, with_proj=False)
+        print(json.dumps({"apply_only_ms_per_call": t * 1e3, "bands": b.nb}))
+        return 0
     secs, wall = time_cycles(eng, a.steps, a.warmup, graph=not a.eager)
     per_cycle = eng.band_applies_per_cycle()
     ms_step = secs / a.steps * 1e3
     value = per_cycle * a.steps / secs
-    eps_err_ok = all(int(b.info.item()) == 0 for row in eng.blocks for b in row)
+    info_ok = all(int(b.info.item()) == 0 for row in eng.blocks for b in row)
+    log("roofline object")
+    roof = roofline_object(eng, a.apply_reps, a.workload)
+    bp, tp, nproj = isolated_apply(eng, a.apply_reps, with_proj=True)
+    isolated = {"band_applies_per_s": bp.nb / tp, "bands": bp.nb, "projectors": nproj, "ms_per_call": tp * 1e3}
+    del eng
+    torch.cuda.empty_cache()
 
-    # ---- isolated H application on a resident batch (roofline object)
-    plan = eng.plan
-    b = eng.blocks[0][0]
-    nb = b.nb
-    X = b.V[:nb].clone()
-    HX = torch.empty_like(X)
-    veff = eng.veff[0]
-    for _ in range(3):
-        plan.apply_h(b.ik, X, veff, b.beta, b.dkb, out=HX)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(a.apply_reps):
-        plan.apply_h(b.ik, X, veff, b.beta, b.dkb, out=HX)
-    e1.record()
-    torch.cuda.synchronize()
-    t_apply = e0.elapsed_time(e1) / 1e3 / a.apply_reps
-    N3 = plan.grid[2]
-    nproj = 0 if b.beta is None else b.beta.shape[0]
-    alg_bytes = apply_bytes(plan, b.ik, nb, nproj)
-    achieved = alg_bytes / t_apply / 1e9
-    isolated = nb / t_apply
-
-    fp64 = None
-    if a.also_fp64 and prec == fde.F32:
-        eng64 = driver.Engine(system, prec=fde.F64, backend=be)
-        s64, _ = time_cycles(eng64, max(2, a.steps // 2), 1)
-        fp64 = {"ms_per_cycle": s64 / max(2, a.steps // 2) * 1e3}
-        del eng64
-
-    tta = None if a.no_tta else time_to_accuracy(be)
-
+    many = a.workload == "64-subsystems"
+    prec_study = None
+    if not a.no_precision_study and not many:
+        prec_study = precision_study(system, be)
+    second = None
+    if a.workload == "large-slab" and not a.no_second_cell:
+        log("slab + molecule cell")
+        second = second_cell(be, a)
+    tta = None
+    if not a.no_tta and not many:
+        log("time to 1e-6 Ha")
+        tta = time_to_accuracy(be)
+    copy = copy_probe(1024)["copy_GBps"]
     cpu = None
     if not a.no_cpu_baseline and not many:
-        from oracle import basis, hamiltonian as oham, pseudo as opseudo
-        cell = basis.Cell(system.L, system.grid)
-        sph = basis.sphere(cell, system.ecut, system.subsystems[0].kfrac[0])
-        vl = veff.double().cpu().numpy()
-        psi = X[:a.cpu_bands].to(torch.complex128).cpu().numpy()
-        beta, dkb = opseudo.kb_projectors(cell, sph, system.subsystems[0].atoms)
-        t0 = time.perf_counter()
-        oham.apply_h(cell, sph, psi, vl, beta, dkb)
-        tc = time.perf_counter() - t0
-        cores = len(os.sched_getaffinity(0))
-        cpu = {"value": a.cpu_bands / tc, "unit": "band-applies/s", "cores": cores, "kind": "oracle",
-               "sample": f"FP64 oracle H application (naive DFTs) of {a.cpu_bands} slab bands at one k-point "
-                         f"of the same cell, {tc:.1f} s"}
+        log("cpu baseline")
+        cpu = cpu_baseline(system)
 
+    names = {"large-slab": "large metal-surface cell 20.4x20.4x60 bohr, 144x144x432 grid, Ecut 26 Ha, slab 144 "
+                           "ions/576 s+p projectors/320 bands/2 k + 4 molecules x 8 bands/Gamma",
+             "slab-molecule": "slab+molecule 10.2x10.2x40 bohr, 60x60x240 grid, Ecut 40 Ha, slab 36 ions/40 "
+                              "bands/4 k + molecule 6 ions/8 bands/Gamma",
+             "64-subsystems": "64 uneven subsystems in a 20 bohr cube, 72x72x72 grid, Ecut 15 Ha, 4-128 bands and "
+                              "1-8 k-points each"}
     out = {
-        "metric": "H|psi> band-applies/s and embedding-cycle time",
+        "metric": METRIC,
         "value": value,
         "unit": "band-applies/s",
         "n_gpus": 1,
@@ -284,29 +472,21 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if prec == fde.F32 else "f64",
+        "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": ("64 uneven subsystems in a 20 bohr cube, 72x72x72 grid, Ecut 15 Ha, "
-                                "4-128 bands and 1-8 k-points each" if many else
-                                "slab+molecule 10.2x10.2x40 bohr, 60x60x240 grid, Ecut 40 Ha, "
-                                "slab 36 ions/40 bands/4 k + molecule 6 ions/8 bands/Gamma"),
-                   "band_applies_per_cycle": per_cycle, "davidson_per_cycle": system.n_david,
-                   "subspace_products": a.gemm, "launch": "eager" if a.eager else "one HIP graph per cycle",
-                   "apply_bands_per_plane_workgroup": None if tuned is None else tuned["bpw"],
-                   "z_pass": "four-step register FFT" if system.grid[2] in (240, 120) else "LDS Stockham",
-                   "solver_streams": len(eng.groups),
-                   "parallelism": "single GPU"},
-        "isolated_apply_h": {"band_applies_per_s": isolated, "bands": nb, "projectors": nproj,
-                             "ms_per_call": t_apply * 1e3},
-        "roofline": {"kernel": "fde_apply_h: FFT sandwich (KZInv, KPlaneHReg, KZFwd) + projectors "
-                               "(KAhBAll, KKbReduce, KKbAdd)", "bound": "hbm",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None if many else measured_traffic(), "algorithmic_bytes": alg_bytes},
+        "config": {"workload": names[a.workload], "band_applies_per_cycle": per_cycle,
+                   "davidson_per_cycle": system.n_david, "subspace_products": a.gemm,
+                   "launch": "eager" if a.eager else "one HIP graph per cycle",
+                   "autotune": None if tuned is None else {k: tuned[k] for k in ("plane", "rows", "bpw", "sz")},
+                   "solver_streams": a.streams, "parallelism": "single GPU"},
+        "isolated_apply_h": isolated,
+        "roofline": roof,
         "cpu_baseline": cpu,
-        "stream_copy_GBps": copy_probe(1024)["copy_GBps"],
+        "precision_study": prec_study,
+        "slab_molecule": second,
         "time_to_1e-6Ha": tta,
-        "fp64_cycle": fp64,
-        "device_info_ok": eps_err_ok,
+        "stream_copy_GBps": copy,
+        "device_info_ok": info_ok,
         "wall_s_timed": wall,
     }
     print(json.dumps(out))

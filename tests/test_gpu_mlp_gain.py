@@ -5,9 +5,10 @@ harvested from FP64 oracle solves of 12 seeded geometries, then both
 preconditioners run the same fixed-potential Davidson (FP64 plan) from the same
 seeded bands on 6 held-out geometries; the iterations until the lowest four of
 the six Ritz values (the occupied ones; two buffer bands) are within 1e-6 Ha of
-the dense eigenvalues are compared. Measured on this set the network is neutral
-(within a few per cent of TPA either way); the test records both counts and
-bounds the network at 15 % more iterations than TPA.
+the dense eigenvalues are compared. Both must converge on every held-out
+geometry. Measured on this set the network shows no gain: 79 iterations with it
+against 78 with TPA in total, so the claim of a gain is a test of its own,
+skipped with the measured counts as the reason until a network beats TPA here.
 """
 import numpy as np
 import pytest
@@ -21,11 +22,16 @@ import mlp_harvest as mh
 pytestmark = pytest.mark.gpu
 
 
+N_ITER = 40
+
+
 def _iters_to(hist, exact, tol=1e-6, nocc=4):
+    """Iterations until the nocc lowest Ritz values are within tol of the dense ones
+    (None: not within N_ITER)."""
     for i, ev in enumerate(hist):
         if np.max(np.abs(ev.cpu().numpy()[:nocc] - exact[:nocc])) < tol:
             return i + 1
-    return len(hist) + 1
+    return None
 
 
 def test_trained_network_vs_tpa():
@@ -48,10 +54,16 @@ def test_trained_network_vs_tpa():
         X = torch.from_numpy(np.ascontiguousarray(X0)).to(be.device)
         res = {}
         for name, prm in (("tpa", None), ("mlp", tr.params)):
-            hist, info = driver.davidson_fixed(plan, 0, X, v, 40, mlp_params=prm)
+            hist, info = driver.davidson_fixed(plan, 0, X, v, N_ITER, mlp_params=prm)
             assert int(info.item()) == 0
             res[name] = _iters_to(hist, exact)
+            assert res[name] is not None, (name, g)       # converged within N_ITER on every cell
             tot[name] += res[name]
         print(f"geometry {g}: iterations to 1e-6 Ha  TPA {res['tpa']}  network {res['mlp']}")
     print(f"total iterations: TPA {tot['tpa']}, network {tot['mlp']}")
-    assert tot["mlp"] <= 1.15 * tot["tpa"]
+
+
+@pytest.mark.skip(reason="measured: 79 iterations with the trained network against 78 with TPA on the six "
+                         "held-out cells -- the network does not gain yet")
+def test_trained_network_gains_over_tpa():
+    pass
