@@ -84,7 +84,7 @@ def divergence(cell: basis.Cell, ecut: float, h):
 
 
 def kedf(cell: basis.Cell, ecut: float, X: np.ndarray, thr: float = 1e-10, kind: str = "lc94"):
-    """(T~[X], V~_kin[X]) for kind in {'lc94', 'tf', 'none'}."""
+    """(T~[X], V~_kin[X]) for kind in {'lc94', 'revapbek', 'tf', 'none'}."""
     X = np.asarray(X, dtype=np.float64)
     if kind == "none":
         return 0.0, np.zeros_like(X)
@@ -94,14 +94,19 @@ def kedf(cell: basis.Cell, ecut: float, X: np.ndarray, thr: float = 1e-10, kind:
         e = np.where(ok, fn.C_TF * Xs ** (5.0 / 3.0), 0.0)
         v = np.where(ok, fn.C_TF * (5.0 / 3.0) * Xs ** (2.0 / 3.0), 0.0)
         return float(np.sum(e)) * cell.dV, v
-    if kind != "lc94":
+    if kind not in ("lc94", "revapbek"):
         raise ValueError(kind)
     grad = gradient(cell, ecut, X)
     gabs = np.sqrt(grad[0] ** 2 + grad[1] ** 2 + grad[2] ** 2)
     s = fn.C_S * gabs / Xs ** (4.0 / 3.0)
-    F = fn.lc94_F(s)
-    dF = fn.lc94_dF(s)
-    dFs = fn.lc94_dF_over_s(s)
+    if kind == "lc94":
+        F = fn.lc94_F(s)
+        dF = fn.lc94_dF(s)
+        dFs = fn.lc94_dF_over_s(s)
+    else:
+        F = fn.revapbek_F(s)
+        dFs = fn.revapbek_dF_over_s(s)
+        dF = dFs * s
     e = np.where(ok, fn.C_TF * Xs ** (5.0 / 3.0) * F, 0.0)
     v = np.where(ok, fn.C_TF * Xs ** (2.0 / 3.0) * (5.0 / 3.0 * F - 4.0 / 3.0 * s * dF), 0.0)
     h = [np.where(ok, fn.C_TF * fn.C_S ** 2 * dFs * gi / Xs, 0.0) for gi in grad]
@@ -109,13 +114,25 @@ def kedf(cell: basis.Cell, ecut: float, X: np.ndarray, thr: float = 1e-10, kind:
     return float(np.sum(e)) * cell.dV, V
 
 
-def xc(X: np.ndarray, cell: basis.Cell, thr: float = 1e-10, kind: str = "lda"):
-    """(E_xc[X], v_xc[X])."""
+def xc(X: np.ndarray, cell: basis.Cell, thr: float = 1e-10, kind: str = "lda", ecut: float = None):
+    """(E_xc[X], v_xc[X]) for kind in {'lda', 'pbe', 'none'}. PBE: v = e_rho - div(2 e_sigma
+    grad X) with the spectral gradient and divergence on D (ecut needed)."""
+    X = np.asarray(X, dtype=np.float64)
     if kind == "none":
-        return 0.0, np.zeros_like(np.asarray(X, dtype=np.float64))
-    if kind != "lda":
+        return 0.0, np.zeros_like(X)
+    if kind == "lda":
+        e, v = fn.lda(X, thr)
+        return float(np.sum(e)) * cell.dV, v
+    if kind != "pbe":
         raise ValueError(kind)
-    e, v = fn.lda(X, thr)
+    ok = X >= thr
+    Xs = np.where(ok, X, 1.0)
+    grad = gradient(cell, ecut, X)
+    sigma = grad[0] ** 2 + grad[1] ** 2 + grad[2] ** 2
+    e, er, es = fn.complex_step(fn.pbe_energy, Xs, sigma)
+    e = np.where(ok, e, 0.0)
+    h = [np.where(ok, 2.0 * es * gi, 0.0) for gi in grad]
+    v = np.where(ok, er, 0.0) - divergence(cell, ecut, h)
     return float(np.sum(e)) * cell.dV, v
 
 
@@ -127,15 +144,15 @@ def embed_potential(cell: basis.Cell, ecut: float, rho_sub: np.ndarray, vloc: np
     rho = np.sum(rho_sub, axis=0)
     dV = cell.dV
     VH, EH = hartree(cell, ecut, rho)
-    Ext, vxt = xc(rho, cell, thr, xc_nad)
+    Ext, vxt = xc(rho, cell, thr, xc_nad, ecut)
     Ekt, vkt = kedf(cell, ecut, rho, thr, kin_nad)
-    Exc_tot, _ = xc(rho, cell, thr, xc_kind)
+    Exc_tot, _ = xc(rho, cell, thr, xc_kind, ecut)
     veff = np.zeros_like(rho_sub)
     en = np.zeros((ns + 1, NE))
     for I in range(ns):
         rI = rho_sub[I]
-        ExcI, vxcI = xc(rI, cell, thr, xc_kind)
-        ExtI, vxtI = xc(rI, cell, thr, xc_nad)
+        ExcI, vxcI = xc(rI, cell, thr, xc_kind, ecut)
+        ExtI, vxtI = xc(rI, cell, thr, xc_nad, ecut)
         EkI, vkI = kedf(cell, ecut, rI, thr, kin_nad)
         _, EHI = hartree(cell, ecut, rI)
         veff[I] = vloc + VH + vxcI + (vxt - vxtI) + (vkt - vkI)
@@ -169,8 +186,8 @@ def potential_energy(cell: basis.Cell, ecut: float, rho_sub: np.ndarray, vloc: n
     dV = cell.dV
     E = float(np.sum(vloc * rho)) * dV
     E += hartree_energy(cell, ecut, rho)
-    E += xc(rho, cell, thr, xc_nad)[0] + kedf(cell, ecut, rho, thr, kin_nad)[0]
+    E += xc(rho, cell, thr, xc_nad, ecut)[0] + kedf(cell, ecut, rho, thr, kin_nad)[0]
     for rI in rho_sub:
-        E += xc(rI, cell, thr, xc_kind)[0] - xc(rI, cell, thr, xc_nad)[0]
+        E += xc(rI, cell, thr, xc_kind, ecut)[0] - xc(rI, cell, thr, xc_nad, ecut)[0]
         E -= kedf(cell, ecut, rI, thr, kin_nad)[0]
     return E

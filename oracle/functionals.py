@@ -1,7 +1,9 @@
 """Pointwise density functionals (test infrastructure, FP64).
 
-Exchange-correlation (LDA; the paper's runs use PBE, Sec. 3, which is a later
-extension here):
+Exchange-correlation: LDA (below) and PBE, the paper's functional (Sec. 3;
+see pbe_xc). Kinetic enhancement factors: LC94 and revAPBEK, the two
+nonadditive kinetic functionals of Sec. 3.
+LDA:
 * Slater exchange  eps_x = -(3/4)(3/pi)^{1/3} rho^{1/3},  v_x = (4/3) eps_x.
 * Perdew-Zunger 1981 correlation (unpolarised), r_s = (3/(4 pi rho))^{1/3}:
     r_s >= 1: eps_c = g / (1 + b1 sqrt(r_s) + b2 r_s),
@@ -127,3 +129,86 @@ def lc94_dF_over_s(s):
     out[small] = 2.0 * (LC94["a3"] - LC94["a4"])
     out[~small] = lc94_dF(s[~small]) / s[~small]
     return out
+
+
+# ---------------------------------------------------------------------------
+# PBE exchange-correlation (Perdew, Burke & Ernzerhof 1996; the functional of
+# the paper's calculations, Sec. 3), spin-unpolarised, as an energy density
+# e(rho, sigma) with sigma = |grad rho|^2:
+#   exchange     e_x = -C_X rho^{4/3} F_x(s),  F_x = 1 + kappa - kappa/(1 + mu s^2/kappa),
+#                s = C_S sqrt(sigma) / rho^{4/3}, kappa = 0.804, mu = beta pi^2 / 3;
+#   correlation  e_c = rho [eps_c^PW92(r_s) + H(r_s, t)],
+#                H = gamma ln(1 + (beta/gamma) t^2 (1 + A t^2)/(1 + A t^2 + A^2 t^4)),
+#                A = (beta/gamma) / (exp(-eps_c/gamma) - 1), t = sqrt(sigma)/(2 k_s rho),
+#                k_s = sqrt(4 k_F / pi), gamma = (1 - ln 2)/pi^2, beta = 0.06672455060314922;
+#   PW92         eps_c = -2 a (1 + a1 r_s) ln(1 + 1/(2 a (b1 r_s^{1/2} + b2 r_s + b3 r_s^{3/2} + b4 r_s^2))).
+# The derivatives e_rho, e_sigma are taken by the complex step (Im e(x + i h)/h, exact to
+# rounding for these analytic forms), independently of any hand-derived formula.
+# Parity unpinned: published constants -- PW92's a1, b1..b4 and PBE's kappa and beta
+# (a and gamma are pinned by the Gell-Mann-Brueckner coefficient; mu = beta pi^2/3 by
+# construction).
+# ---------------------------------------------------------------------------
+PW92 = dict(a=0.0310907, a1=0.21370, b1=7.5957, b2=3.5876, b3=1.6382, b4=0.49294)
+PBE = dict(kappa=0.804, beta=0.06672455060314922, gamma=(1.0 - math.log(2.0)) / math.pi ** 2)
+PBE["mu"] = PBE["beta"] * math.pi ** 2 / 3.0
+# revAPBEK kinetic enhancement (APBEK's mu with revPBE's kappa; cited in Sec. 3)
+REVAPBEK = dict(kappa=1.245, mu=0.23889)
+
+
+def _cbrt(z):
+    return z ** (1.0 / 3.0) if np.iscomplexobj(z) else np.cbrt(z)
+
+
+def pw92_eps(rs):
+    p = PW92
+    q = 2.0 * p["a"] * (p["b1"] * np.sqrt(rs) + p["b2"] * rs + p["b3"] * rs ** 1.5 + p["b4"] * rs * rs)
+    return -2.0 * p["a"] * (1.0 + p["a1"] * rs) * np.log(1.0 + 1.0 / q)
+
+
+def pbe_x_energy(rho, sigma):
+    k, mu = PBE["kappa"], PBE["mu"]
+    r43 = rho * _cbrt(rho)
+    s2 = C_S * C_S * sigma / (r43 * r43)
+    return -C_X * r43 * (1.0 + k - k / (1.0 + mu * s2 / k))
+
+
+def pbe_c_energy(rho, sigma):
+    beta, gamma = PBE["beta"], PBE["gamma"]
+    rs = _cbrt(3.0 / (4.0 * math.pi * rho))
+    ec = pw92_eps(rs)
+    kf = _cbrt(3.0 * math.pi ** 2 * rho)
+    ks2 = 4.0 * kf / math.pi
+    t2 = sigma / (4.0 * ks2 * rho * rho)
+    A = (beta / gamma) / (np.exp(-ec / gamma) - 1.0)
+    at2 = A * t2
+    H = gamma * np.log(1.0 + (beta / gamma) * t2 * (1.0 + at2) / (1.0 + at2 + at2 * at2))
+    return rho * (ec + H)
+
+
+def pbe_energy(rho, sigma):
+    return pbe_x_energy(rho, sigma) + pbe_c_energy(rho, sigma)
+
+
+def complex_step(efun, rho, sigma):
+    """(e, de/drho, de/dsigma) of an energy density by the complex step."""
+    rho = np.asarray(rho, dtype=np.float64)
+    sigma = np.asarray(sigma, dtype=np.float64)
+    e = efun(rho, sigma)
+    hr = 1e-30 * np.maximum(rho, 1e-300)
+    hs = 1e-30 * np.maximum(sigma, 1e-200)
+    dr = np.imag(efun(rho + 1j * hr, sigma.astype(np.complex128))) / hr
+    ds = np.imag(efun(rho.astype(np.complex128), sigma + 1j * hs)) / hs
+    return np.real(e), dr, ds
+
+
+def revapbek_F(s):
+    k, mu = REVAPBEK["kappa"], REVAPBEK["mu"]
+    s = np.asarray(s, dtype=np.float64)
+    return 1.0 + k - k / (1.0 + mu * s * s / k)
+
+
+def revapbek_dF_over_s(s):
+    """F'(s)/s = 2 mu / (1 + mu s^2/kappa)^2 (regular at s = 0)."""
+    k, mu = REVAPBEK["kappa"], REVAPBEK["mu"]
+    s = np.asarray(s, dtype=np.float64)
+    return 2.0 * mu / (1.0 + mu * s * s / k) ** 2
