@@ -173,8 +173,12 @@ fde_status fde_density(fde_plan* plan, int ik, int nb, const void* psi, const do
                        hipStream_t stream);
 
 /* Functional ids for fde_embed_potential. */
-enum { FDE_XC_NONE = 0, FDE_XC_LDA = 1 };            /* Slater + Perdew-Zunger 1981 */
-enum { FDE_KIN_NONE = 0, FDE_KIN_TF = 1, FDE_KIN_LC94 = 2 }; /* Thomas-Fermi x F(s) */
+/* xc: LDA = Slater + Perdew-Zunger 1981; PBE = Perdew-Burke-Ernzerhof 1996 with PW92
+ * correlation (the paper's functional, Sec. 3), potential de/drho - div(2 de/dsigma grad rho).
+ * kin: Thomas-Fermi x F(s) with F = 1 (TF), LC94 or revAPBEK (the two nonadditive kinetic
+ * functionals of Sec. 3). Gradient terms use the spectral gradient on the density sphere. */
+enum { FDE_XC_NONE = 0, FDE_XC_LDA = 1, FDE_XC_PBE = 2 };
+enum { FDE_KIN_NONE = 0, FDE_KIN_TF = 1, FDE_KIN_LC94 = 2, FDE_KIN_REVAPBEK = 3 };
 
 typedef struct fde_functionals {
   int xc;        /* V_XC[rho_I] of the subsystem                      */
@@ -319,9 +323,9 @@ fde_status fde_mix(size_t n, double beta, void* rho_in, const void* rho_out, int
  *   state   device int[3], all zero before the first call of a mixing run.
  *   x_hist, r_hist  [nhmax][ns][N3][N2][N1] real, caller-owned.
  *   rho_in [ns][N] in/out, rho_out [ns][N].   nhmax in [1, FDE_PULAY_MAX].
- *   info  device int: 0, or 1 if the residuals were linearly dependent (pivot
- *         below 1e-14 of the largest inner product: the new pair alone was
- *         used, i.e. linear mixing with beta).
+ *   info  device int: 0, or 1 if the system was exactly singular (a repeated
+ *         pair: the new pair alone was used, i.e. linear mixing with beta); a
+ *         zero residual selects its own input (info 0).
  * With nhmax = 1 this is linear mixing rho_in + beta K (rho_out - rho_in).
  */
 #define FDE_PULAY_MAX 8

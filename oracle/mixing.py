@@ -14,8 +14,10 @@ and leaves the mixing scheme to the host code; the readings used here are:
   multiplies each subsystem's residual by |G|^2 / (|G|^2 + q0^2) on the whole
   FFT grid (q0 = 0: K = 1). K leaves the G = 0 term (the charge) unchanged
   only when q0 = 0; for q0 > 0 it removes it, so the input charge is kept.
-  Residuals that are linearly dependent (rank below n at 1e-14 of the largest
-  inner product) fall back to the newest pair alone, i.e. linear mixing.
+  An exactly singular system (a repeated pair) falls back to the newest pair
+  alone, i.e. linear mixing; a zero residual selects its own input. Nearly
+  dependent residuals are kept: near a fixed point the minimising combination
+  is exactly such a dependency.
 
 Pins (tests/test_oracle_mixing.py): Pulay with K = 1 finds the fixed point of
 an affine map on R^n in at most n + 1 evaluations (it is then GMRES on the
@@ -52,10 +54,18 @@ def pulay_coefficients(res_hist) -> np.ndarray:
     M[n, :n] = 1.0
     rhs = np.zeros(n + 1)
     rhs[n] = 1.0
-    if np.linalg.matrix_rank(B, tol=1e-14 * np.max(np.abs(B))) < n:
-        # linearly dependent residuals: the newest pair alone (linear mixing)
+    d = np.sqrt(np.diag(B))
+    if np.any(d == 0.0):
+        # a zero residual: that input is the fixed point
+        return np.eye(n)[int(np.nonzero(d == 0.0)[0][0])]
+    try:
+        a = np.linalg.solve(M, rhs)[:n]
+    except np.linalg.LinAlgError:
+        a = None
+    if a is None or not np.all(np.isfinite(a)):
+        # exactly singular (e.g. a repeated pair): the newest pair alone, linear mixing
         return np.eye(n)[n - 1]
-    return np.linalg.solve(M, rhs)[:n]
+    return a
 
 
 def pulay(cell: basis.Cell, x_hist, res_hist, beta: float, q0: float) -> np.ndarray:

@@ -110,16 +110,26 @@ struct KGradPrep {
   }
 };
 
-// Kinetic functional at each point. kind 1: Thomas-Fermi, 2: TF x LC94.
-// In:  X, and for kind 2 the gradient in Re(W_d). Out: v (local part
-// dG/drho), and for kind 2 the field h_d = C_TF C_s^2 (F'/s) grad_d X / X in W_d.
-// q0 = sum of the energy density C_TF X^{5/3} F(s).
+// The functionals of one density X that need its gradient, at each point: the kinetic
+// functional (kin: 1 Thomas-Fermi, 2 TF x LC94, 3 TF x revAPBEK; coefficient 1) and up
+// to two PBE exchange-correlation terms with coefficients ca, cb (0: energy only).
+// In: X and, when grad != 0, the gradient in Re(W_d). Out: v = the sum of the local parts
+// de/dX, and (grad != 0) the field h = sum of the 2 de/dsigma grad X terms in W_d (the
+// kinetic one in the regular form C_TF C_s^2 (F'/s) grad X / X). q0, q1, q2 = sums of the
+// energy densities of kin, a, b. Below thr every term is zero.
+struct GgaSet {
+  int kin;
+  int xa, xb;      // FDE_XC_PBE or FDE_XC_NONE
+  double ca, cb;
+  int sa, sb;      // energy slots of a, b (-1: none)
+};
+
 template <typename T>
-struct KKedfPoint {
+struct KGgaPoint {
   template <class Ctx>
   FDE_HD static void run(const Ctx& c, char* lds, const T* __restrict__ X, cplx<T>* __restrict__ w1,
-                         cplx<T>* __restrict__ w2, cplx<T>* __restrict__ w3, T* __restrict__ v, size_t n, int kind,
-                         KinConst k, double thr, double* __restrict__ part, unsigned nblk) {
+                         cplx<T>* __restrict__ w2, cplx<T>* __restrict__ w3, T* __restrict__ v, size_t n, GgaSet f,
+                         int grad, KinConst k, double thr, double* __restrict__ part, unsigned nblk) {
     double acc[kNQ] = {0, 0, 0, 0, 0, 0, 0, 0};
     GRID_FOR(c, n, nblk) {
       const size_t i = i0_ + l_;
@@ -127,7 +137,7 @@ struct KKedfPoint {
       const double x = X[i];
       if (!(x >= thr)) {
         v[i] = T(0);
-        if (kind == 2) {
+        if (grad) {
           w1[i] = mk<T>(0, 0);
           w2[i] = mk<T>(0, 0);
           w3[i] = mk<T>(0, 0);
@@ -137,22 +147,46 @@ struct KKedfPoint {
       const double x13 = cbrt(x);
       const double x23 = x13 * x13;
       const double x53 = x * x23;
-      if (kind == 1) {
-        acc[0] += k.ctf * x53;
-        v[i] = (T)(k.ctf * (5.0 / 3.0) * x23);
-        continue;
+      double dx = 0.0, dy = 0.0, dz = 0.0;
+      if (grad) {
+        dx = w1[i].x;
+        dy = w2[i].x;
+        dz = w3[i].x;
       }
-      const double dx = w1[i].x, dy = w2[i].x, dz = w3[i].x;
-      const double gabs = sqrt(dx * dx + dy * dy + dz * dz);
-      const double s = k.cs * gabs / (x * x13);
-      double F, dFs;
-      lc94(s, F, dFs);
-      acc[0] += k.ctf * x53 * F;
-      v[i] = (T)(k.ctf * x23 * ((5.0 / 3.0) * F - (4.0 / 3.0) * s * s * dFs));
-      const double hf = k.ctf * k.cs * k.cs * dFs / x;
-      w1[i] = mk<T>((T)(hf * dx), T(0));
-      w2[i] = mk<T>((T)(hf * dy), T(0));
-      w3[i] = mk<T>((T)(hf * dz), T(0));
+      const double sigma = dx * dx + dy * dy + dz * dz;
+      double vl = 0.0, hf = 0.0;
+      if (f.kin == FDE_KIN_TF) {
+        acc[0] += k.ctf * x53;
+        vl += k.ctf * (5.0 / 3.0) * x23;
+      } else if (f.kin == FDE_KIN_LC94 || f.kin == FDE_KIN_REVAPBEK) {
+        const double s = k.cs * sqrt(sigma) / (x * x13);
+        double F, dFs;
+        if (f.kin == FDE_KIN_LC94) lc94(s, F, dFs);
+        else revapbek(s, F, dFs);
+        acc[0] += k.ctf * x53 * F;
+        vl += k.ctf * x23 * ((5.0 / 3.0) * F - (4.0 / 3.0) * s * s * dFs);
+        hf += k.ctf * k.cs * k.cs * dFs / x;
+      }
+      if (f.xa == FDE_XC_PBE || f.xb == FDE_XC_PBE) {
+        double e, er, es;
+        pbe_point(x, sigma, e, er, es);
+        if (f.xa == FDE_XC_PBE) {
+          acc[1] += e;
+          vl += f.ca * er;
+          hf += 2.0 * f.ca * es;
+        }
+        if (f.xb == FDE_XC_PBE) {
+          acc[2] += e;
+          vl += f.cb * er;
+          hf += 2.0 * f.cb * es;
+        }
+      }
+      v[i] = (T)vl;
+      if (grad) {
+        w1[i] = mk<T>((T)(hf * dx), T(0));
+        w2[i] = mk<T>((T)(hf * dy), T(0));
+        w3[i] = mk<T>((T)(hf * dz), T(0));
+      }
     }
     block_store(c, (double*)lds, acc, part);
   }
@@ -325,11 +359,11 @@ static EmbedWs<T> embed_ws(fde_plan* p) {
   return e;
 }
 
-// Kinetic potential of density X into vout; writes T~[X] and, from the
-// transformed density, E_H[X] into the energy row. If vh != nullptr also
-// returns V_H[X] (used for the total density).
+// Gradient functionals of density X into vout (the kinetic one and the PBE terms of f);
+// writes their energies into the row and, from the transformed density, E_H[X]. If
+// vh != nullptr also returns V_H[X] (used for the total density).
 template <typename T>
-static fde_status kinetic_and_hartree(fde_plan* p, EmbedWs<T>& e, const T* X, T* vout, const fde_functionals* f,
+static fde_status kinetic_and_hartree(fde_plan* p, EmbedWs<T>& e, const T* X, T* vout, const GgaSet& f, double thr,
                                       T* vh, double* erow, hipStream_t s) {
   const GridGeo g = geo(p);
   const size_t n = g.n;
@@ -348,25 +382,24 @@ static fde_status kinetic_and_hartree(fde_plan* p, EmbedWs<T>& e, const T* X, T*
     FDE_TRY(fft3<T>(p, e.W1, true, s));
     FDE_TRY(launch<KRealPart<T>>(dim3(nb), kBlock, 0, s, (const cplx<T>*)e.W1, vh, n, nb));
   }
-  if (f->kin_nad == FDE_KIN_NONE) {
+  const bool pbe = f.xa == FDE_XC_PBE || f.xb == FDE_XC_PBE;
+  if (f.kin == FDE_KIN_NONE && !pbe) {
     FDE_TRY(zero_bytes(vout, n * sizeof(T), s));
     FDE_TRY(zero_bytes(erow + FDE_E_KIN, sizeof(double), s));
     return FDE_OK;
   }
-  if (f->kin_nad == FDE_KIN_TF) {
-    FDE_TRY(launch<KKedfPoint<T>>(dim3(nb), kBlock, red, s, X, e.W1, e.W2, e.W3, vout, n, 1, kc, f->rho_thr, e.part,
-                                  nb));
-    FDE_TRY(launch<KRedFinal>(dim3(1), kBlock, red, s, (const double*)e.part, (int)nb, dV, erow, (int)FDE_E_KIN, -1,
-                              -1, -1, -1, -1, -1, -1));
-    return FDE_OK;
+  const int grad = (pbe || f.kin == FDE_KIN_LC94 || f.kin == FDE_KIN_REVAPBEK) ? 1 : 0;
+  const int skin = f.kin == FDE_KIN_NONE ? -1 : (int)FDE_E_KIN;
+  if (f.kin == FDE_KIN_NONE) FDE_TRY(zero_bytes(erow + FDE_E_KIN, sizeof(double), s));
+  if (grad) {
+    FDE_TRY(launch<KGradPrep<T>>(dim3(nb), kBlock, 0, s, (const cplx<T>*)e.W0, e.W1, e.W2, e.W3, g, nb));
+    FDE_TRY(fft3<T>(p, e.W1, true, s, 3, (size_t)(e.W2 - e.W1)));  // the three components, W1..W3
   }
-  // gradient
-  FDE_TRY(launch<KGradPrep<T>>(dim3(nb), kBlock, 0, s, (const cplx<T>*)e.W0, e.W1, e.W2, e.W3, g, nb));
-  FDE_TRY(fft3<T>(p, e.W1, true, s, 3, (size_t)(e.W2 - e.W1)));  // the three components, W1..W3
-  FDE_TRY(launch<KKedfPoint<T>>(dim3(nb), kBlock, red, s, X, e.W1, e.W2, e.W3, vout, n, 2, kc, f->rho_thr, e.part,
-                                nb));
-  FDE_TRY(launch<KRedFinal>(dim3(1), kBlock, red, s, (const double*)e.part, (int)nb, dV, erow, (int)FDE_E_KIN, -1, -1,
-                            -1, -1, -1, -1, -1));
+  FDE_TRY(launch<KGgaPoint<T>>(dim3(nb), kBlock, red, s, X, e.W1, e.W2, e.W3, vout, n, f, grad, kc, thr, e.part,
+                               nb));
+  FDE_TRY(launch<KRedFinal>(dim3(1), kBlock, red, s, (const double*)e.part, (int)nb, dV, erow, skin, f.sa, f.sb, -1,
+                            -1, -1, -1, -1));
+  if (!grad) return FDE_OK;
   // divergence of h
   FDE_TRY(fft3<T>(p, e.W1, false, s, 3, (size_t)(e.W2 - e.W1)));
   FDE_TRY(launch<KDivPrep<T>>(dim3(nb), kBlock, 0, s, e.W0, (const cplx<T>*)e.W1, (const cplx<T>*)e.W2,
@@ -388,21 +421,31 @@ static fde_status embed_t(fde_plan* p, int ns, const T* rho_sub, const T* vloc, 
   FDE_TRY(zero_bytes(en, (size_t)(ns + 1) * FDE_NE * sizeof(double), s));
   FDE_TRY(launch<KSumSub<T>>(dim3(nb), kBlock, 0, s, rho_sub, ns, n, e.rho, nb));
   double* etot = en + (size_t)ns * FDE_NE;
-  FDE_TRY(kinetic_and_hartree<T>(p, e, e.rho, e.vkt, f, e.vh, etot, s));
-  FDE_TRY(launch<KXcTotal<T>>(dim3(nb), kBlock, red, s, (const T*)e.rho, vloc, (const T*)e.vh, e.vxt, n, f->xc,
-                              f->xc_nad, f->rho_thr, e.part, nb));
-  FDE_TRY(launch<KRedFinal>(dim3(1), kBlock, red, s, (const double*)e.part, (int)nb, dV, etot, (int)FDE_E_XCNAD,
-                            (int)FDE_E_XC, -1, (int)FDE_E_LOC, (int)FDE_E_HEMB, -1, -1, (int)FDE_E_CHARGE));
+  // PBE terms go with the gradient functionals; the pointwise kernels see them as "none"
+  const bool xpbe = f->xc == FDE_XC_PBE, npbe = f->xc_nad == FDE_XC_PBE;
+  const int xc_pt = xpbe ? FDE_XC_NONE : f->xc, nad_pt = npbe ? FDE_XC_NONE : f->xc_nad;
+  // total density: V~kin[rho] + V~xc[rho] (PBE), energies E~xc[rho] and E_xc[rho] (PBE)
+  const GgaSet ftot{f->kin_nad, npbe ? FDE_XC_PBE : FDE_XC_NONE, xpbe ? FDE_XC_PBE : FDE_XC_NONE, 1.0, 0.0,
+                    npbe ? (int)FDE_E_XCNAD : -1, xpbe ? (int)FDE_E_XC : -1};
+  FDE_TRY(kinetic_and_hartree<T>(p, e, e.rho, e.vkt, ftot, f->rho_thr, e.vh, etot, s));
+  FDE_TRY(launch<KXcTotal<T>>(dim3(nb), kBlock, red, s, (const T*)e.rho, vloc, (const T*)e.vh, e.vxt, n, xc_pt,
+                              nad_pt, f->rho_thr, e.part, nb));
+  FDE_TRY(launch<KRedFinal>(dim3(1), kBlock, red, s, (const double*)e.part, (int)nb, dV, etot,
+                            npbe ? -1 : (int)FDE_E_XCNAD, xpbe ? -1 : (int)FDE_E_XC, -1, (int)FDE_E_LOC,
+                            (int)FDE_E_HEMB, -1, -1, (int)FDE_E_CHARGE));
+  // subsystem I: V~kin[rho_I] - V_xc[rho_I] (PBE) + V~xc[rho_I] (PBE), subtracted in KAssemble
+  const GgaSet fsub{f->kin_nad, xpbe ? FDE_XC_PBE : FDE_XC_NONE, npbe ? FDE_XC_PBE : FDE_XC_NONE, -1.0, 1.0,
+                    xpbe ? (int)FDE_E_XC : -1, npbe ? (int)FDE_E_XCNAD : -1};
   for (int I = 0; I < ns; ++I) {
     const T* rI = rho_sub + (size_t)I * n;
     T* vI = veff + (size_t)I * n;
     double* erow = en + (size_t)I * FDE_NE;
-    FDE_TRY(kinetic_and_hartree<T>(p, e, rI, vI, f, (T*)nullptr, erow, s));
+    FDE_TRY(kinetic_and_hartree<T>(p, e, rI, vI, fsub, f->rho_thr, (T*)nullptr, erow, s));
     FDE_TRY(launch<KAssemble<T>>(dim3(nb), kBlock, red, s, rI, vloc, (const T*)e.vh, (const T*)e.vxt,
-                                 (const T*)e.vkt, vI, n, f->xc, f->xc_nad, f->rho_thr, e.part, info, nb));
-    FDE_TRY(launch<KRedFinal>(dim3(1), kBlock, red, s, (const double*)e.part, (int)nb, dV, erow, (int)FDE_E_XC,
-                              (int)FDE_E_XCNAD, -1, (int)FDE_E_LOC, (int)FDE_E_HEMB, -1, (int)FDE_E_DEBAND,
-                              (int)FDE_E_CHARGE));
+                                 (const T*)e.vkt, vI, n, xc_pt, nad_pt, f->rho_thr, e.part, info, nb));
+    FDE_TRY(launch<KRedFinal>(dim3(1), kBlock, red, s, (const double*)e.part, (int)nb, dV, erow,
+                              xpbe ? -1 : (int)FDE_E_XC, npbe ? -1 : (int)FDE_E_XCNAD, -1, (int)FDE_E_LOC,
+                              (int)FDE_E_HEMB, -1, (int)FDE_E_DEBAND, (int)FDE_E_CHARGE));
   }
   return FDE_OK;
 }
@@ -553,10 +596,13 @@ struct KPulayGram {
   }
 };
 
-// Reduce the pair partials in a fixed order and solve [B 1; 1^T 0][a; l] = [0; 1] by
-// Gaussian elimination with partial pivoting (one thread). A pivot below 1e-14 of the
-// largest entry of B (a history whose residuals are linearly dependent) falls back to
-// a = e_newest: linear mixing of the new pair; info = 1 then.
+// Reduce the pair partials in a fixed order and solve [B 1; 1^T 0][a; l] = [0; 1] (one
+// thread): with d_i = sqrt(B_ii) and a_i = a'_i / d_i the system is solved for the unit-
+// diagonal B'_ij = B_ij / (d_i d_j), bordered by 1/d_i, by Gaussian elimination with
+// partial pivoting. An exactly zero pivot or a non-finite solution (a repeated pair)
+// falls back to a = e_newest, linear mixing of the new pair, with info = 1; a zero
+// residual (d_i = 0) selects its own input. Nearly dependent residuals are kept (near a
+// fixed point the minimising combination is such a dependency).
 struct KPulaySolve {
   template <class Ctx>
   FDE_HD static void run(const Ctx& c, char* lds, const double* __restrict__ part, int nblk, int* __restrict__ state,
@@ -574,27 +620,32 @@ struct KPulaySolve {
     }
     if (c.tid() != 0) return;
     constexpr int M = FDE_PULAY_MAX + 1;
-    double A[M][M + 1];
+    double A[M][M + 1], d[M];
     const int n = nh + 1;
-    double bmax = 0.0;
-    int q = 0;
+    int q = 0, zero = -1;
     for (int a = 0; a < nh; ++a)
       for (int b = a; b < nh; ++b) {
         A[a][b] = A[b][a] = Bp[q++];
-        bmax = fabs(A[a][b]) > bmax ? fabs(A[a][b]) : bmax;
       }
     for (int a = 0; a < nh; ++a) {
-      A[a][nh] = A[nh][a] = 1.0;
-      A[a][n] = 0.0;
+      d[a] = sqrt(A[a][a] > 0.0 ? A[a][a] : 0.0);
+      if (d[a] == 0.0 && zero < 0) zero = a;
     }
-    A[nh][nh] = 0.0;
-    A[nh][n] = 1.0;
-    bool ok = bmax > 0.0;
+    bool ok = zero < 0;
+    if (ok) {
+      for (int a = 0; a < nh; ++a) {
+        for (int b = 0; b < nh; ++b) A[a][b] /= d[a] * d[b];
+        A[a][nh] = A[nh][a] = 1.0 / d[a];
+        A[a][n] = 0.0;
+      }
+      A[nh][nh] = 0.0;
+      A[nh][n] = 1.0;
+    }
     for (int k = 0; k < n && ok; ++k) {
       int piv = k;
       for (int r = k + 1; r < n; ++r)
         if (fabs(A[r][k]) > fabs(A[piv][k])) piv = r;
-      if (!(fabs(A[piv][k]) > (k < nh ? 1e-14 * bmax : 1e-300))) ok = false;
+      if (!(fabs(A[piv][k]) > 0.0)) ok = false;
       if (!ok) break;
       if (piv != k)
         for (int j = 0; j <= n; ++j) {
@@ -614,11 +665,16 @@ struct KPulaySolve {
         for (int j = k + 1; j < n; ++j) t -= A[k][j] * x[j];
         x[k] = t / A[k][k];
       }
-      for (int a = 0; a < nh; ++a) alpha[a] = x[a];
+      for (int a = 0; a < nh; ++a) {
+        alpha[a] = x[a] / d[a];
+        if (!(alpha[a] == alpha[a]) || fabs(alpha[a]) > 1e300) ok = false;
+      }
       info[0] = 0;
-    } else {
-      for (int a = 0; a < nh; ++a) alpha[a] = a == newest ? 1.0 : 0.0;
-      info[0] = 1;
+    }
+    if (!ok) {
+      const int pick = zero >= 0 ? zero : newest;
+      for (int a = 0; a < nh; ++a) alpha[a] = a == pick ? 1.0 : 0.0;
+      info[0] = zero >= 0 ? 0 : 1;
     }
     state[2] = nh;
     state[0] = nh;
@@ -784,7 +840,7 @@ fde_status fde_embed_potential(fde_plan* p, int ns, const void* rho_sub, const v
   if (!p->ws) return fail(FDE_ERR_WORKSPACE, "no workspace attached (fde_plan_set_workspace)");
   if (ns < 1) return fail(FDE_ERR_ARG, "ns must be >= 1");
   if (!rho_sub || !vloc || !f || !veff || !energies || !info) return fail(FDE_ERR_ARG, "null argument");
-  if (f->xc < 0 || f->xc > 1 || f->xc_nad < 0 || f->xc_nad > 1 || f->kin_nad < 0 || f->kin_nad > 2)
+  if (f->xc < 0 || f->xc > 2 || f->xc_nad < 0 || f->xc_nad > 2 || f->kin_nad < 0 || f->kin_nad > 3)
     return fail(FDE_ERR_ARG, "unknown functional id");
   if (!(f->rho_thr >= 0)) return fail(FDE_ERR_ARG, "rho_thr must be >= 0");
   if (p->prec == FDE_F64)

@@ -148,4 +148,65 @@ FDE_HD void lc94(double s, double& F, double& dFs) {
   dFs = dDs / den - Ds * dden / (den * den);
 }
 
+// revAPBEK enhancement (APBEK's mu with revPBE's kappa): F = 1 + k - k/(1 + mu s^2/k),
+// F'/s = 2 mu / (1 + mu s^2/k)^2.
+FDE_HD void revapbek(double s, double& F, double& dFs) {
+  const double k = 1.245, mu = 0.23889;
+  const double d = 1.0 + mu * s * s / k;
+  F = 1.0 + k - k / d;
+  dFs = 2.0 * mu / (d * d);
+}
+
+// PBE exchange-correlation (spin-unpolarised) at one point as e(rho, sigma), sigma =
+// |grad rho|^2: energy per volume e, er = de/drho, es = de/dsigma.
+//   exchange: e_x = -C_X rho^{4/3} F(u), u = s^2 = C_S^2 sigma / rho^{8/3},
+//             F = 1 + kappa - kappa / (1 + mu u / kappa), F_u = mu / (1 + mu u/kappa)^2;
+//             er = -C_X rho^{1/3} (4/3)(F - 2 u F_u),  es = -C_X C_S^2 F_u / rho^{4/3}.
+//   correlation: e_c = rho (eps + H(eps, y)), y = t^2 = c_t sigma rho^{-7/3},
+//             c_t = pi / (16 (3 pi^2)^{1/3}); PW92 eps(r_s) with r_s = (3/(4 pi rho))^{1/3};
+//             H = gamma ln(1 + R), R = (beta/gamma) y P/Q, P = 1 + A y, Q = P + A^2 y^2,
+//             A = (beta/gamma)/(E - 1), E = exp(-eps/gamma), dA/deps = A^2 E / beta;
+//             er = eps + H + rho [(1 + H_A dA/deps) deps/drho - (7/3) H_y y / rho],
+//             deps/drho = -eps'(r_s) r_s / (3 rho),   es = rho H_y c_t rho^{-7/3}.
+FDE_HD void pbe_point(double rho, double sigma, double& e, double& er, double& es) {
+  const double pi = 3.14159265358979323846;
+  const double cx = 0.75 * cbrt(3.0 / pi);
+  const double cs2 = 1.0 / (4.0 * cbrt(9.0 * pi * pi * pi * pi));  // C_S^2 = 1/(4 (3 pi^2)^{2/3})
+  const double kap = 0.804, beta = 0.06672455060314922, gam = (1.0 - log(2.0)) / (pi * pi);
+  const double mu = beta * pi * pi / 3.0;
+  const double r13 = cbrt(rho), r43 = rho * r13;
+  // exchange
+  const double u = cs2 * sigma / (r43 * r43);
+  const double dx = 1.0 + mu * u / kap;
+  const double F = 1.0 + kap - kap / dx, Fu = mu / (dx * dx);
+  e = -cx * r43 * F;
+  er = -cx * r13 * (4.0 / 3.0) * (F - 2.0 * u * Fu);
+  es = -cx * cs2 * Fu / r43;
+  // PW92 correlation energy per electron and its r_s derivative
+  const double a = 0.0310907, a1 = 0.21370, b1 = 7.5957, b2 = 3.5876, b3 = 1.6382, b4 = 0.49294;
+  const double rs = cbrt(3.0 / (4.0 * pi * rho)), srs = sqrt(rs);
+  const double q = 2.0 * a * (b1 * srs + b2 * rs + b3 * rs * srs + b4 * rs * rs);
+  const double dq = 2.0 * a * (0.5 * b1 / srs + b2 + 1.5 * b3 * srs + 2.0 * b4 * rs);
+  const double lg = log(1.0 + 1.0 / q);
+  const double eps = -2.0 * a * (1.0 + a1 * rs) * lg;
+  const double deps_rs = -2.0 * a * a1 * lg + 2.0 * a * (1.0 + a1 * rs) * dq / (q * q + q);
+  const double deps = -deps_rs * rs / (3.0 * rho);
+  // gradient correction H
+  const double ct = pi / (16.0 * cbrt(3.0 * pi * pi));
+  const double r73 = rho * r43;  // rho^{7/3}
+  const double y = ct * sigma / r73;
+  const double E = exp(-eps / gam);
+  const double A = (beta / gam) / (E - 1.0);
+  const double P = 1.0 + A * y, Q = P + A * A * y * y;
+  const double R = (beta / gam) * y * P / Q;
+  const double H = gam * log1p(R);
+  const double Ry = (beta / gam) * ((P + A * y) / Q - y * P * (A + 2.0 * A * A * y) / (Q * Q));
+  const double RA = (beta / gam) * y * (y / Q - P * (y + 2.0 * A * y * y) / (Q * Q));
+  const double Hy = gam * Ry / (1.0 + R), HA = gam * RA / (1.0 + R);
+  const double dA = A * A * E / beta;
+  e += rho * (eps + H);
+  er += eps + H + rho * ((1.0 + HA * dA) * deps - (7.0 / 3.0) * Hy * y / rho);
+  es += rho * Hy * ct / r73;
+}
+
 }  // namespace fde

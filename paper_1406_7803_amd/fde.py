@@ -21,8 +21,8 @@ LIB_PATH = os.path.join(HERE, "libfde.so")
 EMU_PATH = os.path.join(HERE, "libfde_emu.so")
 
 F64, F32 = 0, 1
-XC_NONE, XC_LDA = 0, 1
-KIN_NONE, KIN_TF, KIN_LC94 = 0, 1, 2
+XC_NONE, XC_LDA, XC_PBE = 0, 1, 2
+KIN_NONE, KIN_TF, KIN_LC94, KIN_REVAPBEK = 0, 1, 2, 3
 OCC_INTEGER, OCC_FERMI_DIRAC, OCC_METHFESSEL_PAXTON = 0, 1, 2
 PULAY_MAX = 8
 NE = 8

@@ -123,14 +123,20 @@ def _smooth_densities(cell, ecut, ns=2, nb=3, seed=20):
     return np.array(out)
 
 
-def check_embed(be, prec, kin=fde.KIN_LC94, grid=(12, 12, 15), L=(6.0, 6.0, 7.0), ecut=2.2, ns=2):
-    kinds = {fde.KIN_LC94: "lc94", fde.KIN_TF: "tf", fde.KIN_NONE: "none"}
+KIN_NAMES = {fde.KIN_LC94: "lc94", fde.KIN_TF: "tf", fde.KIN_NONE: "none", fde.KIN_REVAPBEK: "revapbek"}
+XC_NAMES = {fde.XC_LDA: "lda", fde.XC_PBE: "pbe", fde.XC_NONE: "none"}
+
+
+def check_embed(be, prec, kin=fde.KIN_LC94, grid=(12, 12, 15), L=(6.0, 6.0, 7.0), ecut=2.2, ns=2, xc=fde.XC_LDA,
+                xc_nad=fde.XC_LDA):
     cell = basis.Cell(L, grid)
     rs = _smooth_densities(cell, ecut, ns=ns)
     vloc = fde_synth.random_real(5, cell.shape, -0.3, 0.3)
-    vref, eref = oembed.embed_potential(cell, ecut, rs, vloc, kin_nad=kinds[kin])
+    vref, eref = oembed.embed_potential(cell, ecut, rs, vloc, kin_nad=KIN_NAMES[kin], xc_kind=XC_NAMES[xc],
+                                        xc_nad=XC_NAMES[xc_nad])
     plan = fde.Plan(L, grid, ecut, [(0, 0, 0)], prec=prec, max_nb=4, backend=be)
-    veff, en, info = plan.embed_potential(to_dev(plan, rs, "r"), to_dev(plan, vloc, "r"), kin_nad=kin)
+    veff, en, info = plan.embed_potential(to_dev(plan, rs, "r"), to_dev(plan, vloc, "r"), kin_nad=kin, xc=xc,
+                                          xc_nad=xc_nad)
     be.sync()
     assert int(host(info)[0]) == 0
     assert rel(host(veff), vref) < TOL[prec]
@@ -637,19 +643,20 @@ def _vacuum_densities(cell, ns):
     return rho
 
 
-def check_embed_grid(be, prec, grid, spacing, kin=fde.KIN_LC94, ecut=3.0):
+def check_embed_grid(be, prec, grid, spacing, kin=fde.KIN_LC94, ecut=3.0, xc=fde.XC_LDA, xc_nad=fde.XC_LDA):
     """The embedding potential on a grid of compile-time FFT lengths, with a vacuum
     region below rho_thr (reading 11) and a second subsystem of zero density
     (T^nad[rho_A, 0] = 0 and V^nad = 0 exactly)."""
-    kinds = {fde.KIN_LC94: "lc94", fde.KIN_TF: "tf", fde.KIN_NONE: "none"}
     L = tuple(n * spacing for n in grid)
     cell = basis.Cell(L, grid)
     rs = _vacuum_densities(cell, 2)
     assert np.mean(rs[0] < 1e-10) > 0.05          # part of the cell is vacuum
     vloc = fde_synth.random_real(7, cell.shape, -0.3, 0.3)
-    vref, eref = oembed.embed_potential(cell, ecut, rs, vloc, kin_nad=kinds[kin])
+    vref, eref = oembed.embed_potential(cell, ecut, rs, vloc, kin_nad=KIN_NAMES[kin], xc_kind=XC_NAMES[xc],
+                                        xc_nad=XC_NAMES[xc_nad])
     plan = fde.Plan(L, grid, ecut, [(0, 0, 0)], prec=prec, max_nb=2, backend=be)
-    veff, en, info = plan.embed_potential(to_dev(plan, rs, "r"), to_dev(plan, vloc, "r"), kin_nad=kin)
+    veff, en, info = plan.embed_potential(to_dev(plan, rs, "r"), to_dev(plan, vloc, "r"), kin_nad=kin, xc=xc,
+                                          xc_nad=xc_nad)
     be.sync()
     assert int(host(info)[0]) == 0
     v = host(veff)
@@ -745,5 +752,24 @@ def check_trajectory_pulay(be, prec, system, n_cycles, eps_tol, drho_tol, mixer)
             d = float(np.sum(np.abs(host(eng.rho_out[I]) - recs[c].rho_out[I]))) * st.cell.dV
             worst = (max(worst[0], e), max(worst[1], d))
     assert int(host(eng.mix_info)[0]) == 0
+    assert worst[0] < eps_tol and worst[1] < drho_tol, worst
+    return worst
+
+
+def check_trajectory_gga(be, prec, n_cycles, eps_tol, drho_tol):
+    """The two-subsystem cube with the paper's functionals: PBE xc both ways, revAPBEK."""
+    s = fde_synth.config1()
+    st = oscf.setup(s, dict(xc_kind="pbe", xc_nad="pbe", kin_nad="revapbek"))
+    recs, _, _ = oscf.run(s, n_cycles=n_cycles, st=st)
+    eng = driver.Engine(s, prec=prec, backend=be,
+                        kinds=dict(xc=fde.XC_PBE, xc_nad=fde.XC_PBE, kin_nad=fde.KIN_REVAPBEK))
+    worst = (0.0, 0.0)
+    for c in range(n_cycles):
+        eng.cycle()
+        be.sync()
+        for I in range(len(s.subsystems)):
+            e = np.max(np.abs(host(eng.eps[I]) - recs[c].eps[I]))
+            d = float(np.sum(np.abs(host(eng.rho_out[I]) - recs[c].rho_out[I]))) * st.cell.dV
+            worst = (max(worst[0], e), max(worst[1], d))
     assert worst[0] < eps_tol and worst[1] < drho_tol, worst
     return worst

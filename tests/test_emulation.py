@@ -178,3 +178,19 @@ def test_trajectory_pulay_mp(be):
     for sub in s.subsystems:
         sub.smearing = "methfessel-paxton"
     pc.check_trajectory_pulay(be, fde.F64, s, 3, 1e-10, 1e-10, dict(kind="pulay", nhist=4, beta=0.5, q0=0.6))
+
+
+@pytest.mark.parametrize("xc,xc_nad,kin", [(fde.XC_PBE, fde.XC_PBE, fde.KIN_REVAPBEK),
+                                           (fde.XC_LDA, fde.XC_PBE, fde.KIN_LC94),
+                                           (fde.XC_PBE, fde.XC_LDA, fde.KIN_TF),
+                                           (fde.XC_PBE, fde.XC_NONE, fde.KIN_NONE)])
+def test_embed_gga(be, xc, xc_nad, kin):
+    pc.check_embed(be, fde.F64, kin, xc=xc, xc_nad=xc_nad)
+
+
+def test_embed_gga_vacuum(be):
+    pc.check_embed_grid(be, fde.F64, (24, 48, 60), 0.25, kin=fde.KIN_REVAPBEK, xc=fde.XC_PBE, xc_nad=fde.XC_PBE)
+
+
+def test_trajectory_gga(be):
+    pc.check_trajectory_gga(be, fde.F64, 2, 1e-10, 1e-10)

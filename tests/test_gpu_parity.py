@@ -154,6 +154,25 @@ def test_trajectory_methfessel_paxton(be):
     pc.check_trajectory_pulay(be, fde.F64, s, 4, 1e-10, 1e-10, dict(kind="pulay", nhist=4, beta=0.5, q0=0.6))
 
 
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("xc,xc_nad,kin", [(fde.XC_PBE, fde.XC_PBE, fde.KIN_REVAPBEK),
+                                           (fde.XC_LDA, fde.XC_PBE, fde.KIN_LC94),
+                                           (fde.XC_PBE, fde.XC_LDA, fde.KIN_TF),
+                                           (fde.XC_PBE, fde.XC_NONE, fde.KIN_NONE)])
+def test_embed_gga(be, prec, xc, xc_nad, kin):
+    pc.check_embed(be, prec, kin, xc=xc, xc_nad=xc_nad)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_embed_gga_compile_time_lengths_vacuum(be, prec):
+    pc.check_embed_grid(be, prec, (24, 48, 60), 0.25, kin=fde.KIN_REVAPBEK, xc=fde.XC_PBE, xc_nad=fde.XC_PBE)
+
+
+def test_trajectory_gga(be):
+    pc.check_trajectory_gga(be, fde.F64, 10, 1e-10, 1e-10)
+    pc.check_trajectory_gga(be, fde.F32, 10, 1e-6, 1e-5)
+
+
 # ---------------------------------------------------------------------------
 # Full-size slab + molecule cell (60 x 60 x 240, ~50 300 plane waves), in the
 # launch configuration the benchmark times: all 40 slab bands in one call;
