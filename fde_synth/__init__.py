@@ -293,6 +293,33 @@ CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4}
 
 
 # ----------------------------------------------------------------------------
+# Partitions of one geometry (layout only): the supersystem and the fragments
+# ----------------------------------------------------------------------------
+def supersystem(system: System, sigma: float = 0.01) -> System:
+    """All atoms, bands and electrons of `system` in one subsystem (Kohn-Sham of the
+    whole: N_S = 1), on the k-mesh of the subsystem with the most k-points, Fermi-Dirac
+    smearing of width sigma (the slab is metallic)."""
+    kmain = max(system.subsystems, key=lambda s: len(s.kfrac))
+    atoms = [a for s in system.subsystems for a in s.atoms]
+    sub = Subsystem("supersystem", atoms, nbands=sum(s.nbands for s in system.subsystems),
+                    nelec=sum(s.nelec for s in system.subsystems), kfrac=kmain.kfrac.copy(),
+                    kweight=kmain.kweight.copy(), smearing="fermi-dirac", sigma=sigma)
+    return System(system.cfg, system.geometry, system.L, system.grid, system.ecut, [sub],
+                  n_cycles=system.n_cycles, n_david=system.n_david, mix_beta=system.mix_beta,
+                  rho_thr=system.rho_thr)
+
+
+def fragment(system: System, isub: int) -> System:
+    """Subsystem isub alone in the same cell (its own atoms, bands, electrons and k-points)."""
+    s = system.subsystems[isub]
+    sub = Subsystem(s.name, list(s.atoms), s.nbands, s.nelec, s.kfrac.copy(), s.kweight.copy(), s.smearing,
+                    s.sigma)
+    return System(system.cfg, system.geometry, system.L, system.grid, system.ecut, [sub],
+                  n_cycles=system.n_cycles, n_david=system.n_david, mix_beta=system.mix_beta,
+                  rho_thr=system.rho_thr)
+
+
+# ----------------------------------------------------------------------------
 # Random numbers consumed by the method
 # ----------------------------------------------------------------------------
 def random_coefficients(cfg: int, geometry: int, isub: int, ik: int, nb: int, npw: int,

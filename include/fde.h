@@ -402,6 +402,12 @@ fde_status fde_grid_dot(fde_plan* plan, const void* a, const void* b, double* ou
 fde_status fde_energy_total(int ns, const double* embed_energies, const double* band_terms, const double* dots,
                             double* out, hipStream_t stream);
 
+/* out[0] += int |sum_{I < ns} rho_sub[I] - rho_ref| dV over the plan's grid: the
+ * integrated density difference (Sec. 4 measures FDE against Kohn-Sham by half of it)
+ * and the self-consistency residual of the cycle. rho_sub [ns][N], rho_ref [N]. */
+fde_status fde_density_l1(fde_plan* plan, int ns, const void* rho_sub, const void* rho_ref, double* out,
+                          hipStream_t stream);
+
 /* out[0] = (1/N) sum_j a_j (mean of a real grid, e.g. the mean effective potential
  * that the learned preconditioner's fourth feature uses). out: device double. */
 fde_status fde_grid_mean(fde_plan* plan, const void* a, double* out, hipStream_t stream);

@@ -1,5 +1,6 @@
 // Host entry points of the grid kernels: fde_embed_potential,
-// fde_local_potential, fde_mix, fde_grid_dot, fde_grid_mean, fde_energy_total.
+// fde_local_potential, fde_mix, fde_mix_pulay, fde_grid_dot, fde_density_l1, fde_grid_mean,
+// fde_energy_total.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -534,6 +535,24 @@ struct KDot {
   }
 };
 
+// |sum_{I < ns} a_I - b| per point, summed per block
+template <typename T>
+struct KAbsDiff {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const T* __restrict__ a, int ns, const T* __restrict__ b, size_t n,
+                         double* __restrict__ part, unsigned nblk) {
+    double acc[kNQ] = {0, 0, 0, 0, 0, 0, 0, 0};
+    GRID_FOR(c, n, nblk) {
+      const size_t i = i0_ + l_;
+      if (i >= n) break;
+      double t = -(double)b[i];
+      for (int I = 0; I < ns; ++I) t += (double)a[(size_t)I * n + i];
+      acc[0] += fabs(t);
+    }
+    block_store(c, (double*)lds, acc, part);
+  }
+};
+
 // out[0] += scale * sum part[b][0]   (out[0] = ... when set)
 struct KRedAdd {
   template <class Ctx>
@@ -885,6 +904,25 @@ fde_status fde_grid_dot(fde_plan* p, const void* a, const void* b, double* out, 
     FDE_TRY(launch<KDot<double>>(dim3(nb), kBlock, red, s, (const double*)a, (const double*)b, n, part, nb));
   else
     FDE_TRY(launch<KDot<float>>(dim3(nb), kBlock, red, s, (const float*)a, (const float*)b, n, part, nb));
+  return launch<KRedAdd>(dim3(1), kBlock, red, s, (const double*)part, (int)nb, p->omega / (double)n, out, 0);
+}
+
+fde_status fde_density_l1(fde_plan* p, int ns, const void* rho_sub, const void* rho_ref, double* out,
+                          hipStream_t s) {
+  if (!p) return fail(FDE_ERR_ARG, "null plan");
+  if (!p->ws) return fail(FDE_ERR_WORKSPACE, "no workspace attached (fde_plan_set_workspace)");
+  if (ns < 1) return fail(FDE_ERR_ARG, "ns must be >= 1");
+  if (!rho_sub || !rho_ref || !out) return fail(FDE_ERR_ARG, "null argument");
+  const size_t n = p->npts();
+  const unsigned nb = red_blocks(n);
+  double* part = (double*)p->scratch;
+  const size_t red = 17 * sizeof(double);
+  if (p->prec == FDE_F64)
+    FDE_TRY(launch<KAbsDiff<double>>(dim3(nb), kBlock, red, s, (const double*)rho_sub, ns, (const double*)rho_ref, n,
+                                     part, nb));
+  else
+    FDE_TRY(launch<KAbsDiff<float>>(dim3(nb), kBlock, red, s, (const float*)rho_sub, ns, (const float*)rho_ref, n,
+                                    part, nb));
   return launch<KRedAdd>(dim3(1), kBlock, red, s, (const double*)part, (int)nb, p->omega / (double)n, out, 0);
 }
 

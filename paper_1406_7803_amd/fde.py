@@ -35,7 +35,7 @@ SYMBOLS = [
     "fde_local_potential", "fde_kb_projectors", "fde_init_bands", "fde_band_energies", "fde_grid_dot",
     "fde_subspace_rr_batched", "fde_precondition_batched", "fde_grid_mean", "fde_precondition_mlp_batched",
     "fde_mlp_forward", "fde_mlp_workspace_bytes", "fde_mlp_loss_grad", "fde_mlp_adam", "fde_plan_set_gemm_mode",
-    "fde_plan_set_tuning", "fde_energy_total", "fde_mlp_loss_grad_static", "fde_mix_pulay",
+    "fde_plan_set_tuning", "fde_energy_total", "fde_mlp_loss_grad_static", "fde_mix_pulay", "fde_density_l1",
 ]
 TUNE_APPLY_BPW = 1
 TUNE_STICK_GROUP = 2
@@ -94,6 +94,7 @@ def _declare(lib):
     lib.fde_energy_total.argtypes = [_I, _P, _P, _P, _P, _P]
     lib.fde_grid_dot.argtypes = [_P, _P, _P, _P, _P]
     lib.fde_grid_mean.argtypes = [_P, _P, _P, _P]
+    lib.fde_density_l1.argtypes = [_P, _I, _P, _P, _P, _P]
     lib.fde_plan_set_gemm_mode.argtypes = [_P, _I]
     lib.fde_plan_set_tuning.argtypes = [_P, _I, _I]
     lib.fde_precondition_mlp_batched.argtypes = [_P, _I, _P, _P, _P, _P]
@@ -398,6 +399,18 @@ class Plan:
     def set_gemm_mode(self, mode: int):
         """Arithmetic of the Rayleigh-Ritz subspace products (GEMM_FP64, GEMM_BF16X3, GEMM_BF16X6)."""
         self._check(self.lib.fde_plan_set_gemm_mode(self.h, int(mode)))
+
+    def density_l1(self, rho_sub, rho_ref, out=None):
+        """out[0] += int |sum_I rho_sub[I] - rho_ref| dV (rho_sub [ns][N] or [N])."""
+        self._grid(rho_sub, "rho_sub")
+        self._grid(rho_ref, "rho_ref")
+        if rho_ref.numel() != int(np.prod(self.shape)):
+            raise FdeError("rho_ref must be one grid")
+        ns = rho_sub.numel() // int(np.prod(self.shape))
+        out = torch.zeros(1, dtype=torch.float64, device=self.be.device) if out is None else out
+        self._f64(out, "out")
+        self._check(self.lib.fde_density_l1(self.h, ns, _ptr(rho_sub), _ptr(rho_ref), _ptr(out), self.be.stream()))
+        return out
 
     def grid_mean(self, a, out=None):
         self._grid(a, "a")

@@ -773,3 +773,35 @@ def check_trajectory_gga(be, prec, n_cycles, eps_tol, drho_tol):
             worst = (max(worst[0], e), max(worst[1], d))
     assert worst[0] < eps_tol and worst[1] < drho_tol, worst
     return worst
+
+
+def oracle_supersystem_comparison(system, kinds, mixer, n_cycles):
+    """The Table 1 quantities from the oracle alone, after a fixed number of cycles."""
+    from oracle import mixing as omix
+    okinds = dict(xc_kind=XC_NAMES[kinds["xc"]], xc_nad=XC_NAMES[kinds["xc_nad"]], kin_nad=KIN_NAMES[kinds["kin_nad"]])
+
+    def run(sysm):
+        st = oscf.setup(sysm, okinds)
+        recs, X, _ = oscf.run(sysm, n_cycles=n_cycles, st=st,
+                              mixer=omix.Mixer(st.cell, "pulay", mixer["beta"], mixer["nhist"], mixer["q0"]))
+        r = recs[-1]
+        ef = [(r.eps[I], oocc.occupations(r.eps[I], sub.kweight, sub.nelec, sub.smearing, sub.sigma)[0])
+              for I, sub in enumerate(sysm.subsystems)]
+        return r, oscf.energies(st, X, ef, r.veff, r.rho_out)["E_FDE"], st
+
+    rks, eks, st = run(fde_synth.supersystem(system))
+    rfde, efde, _ = run(system)
+    efrag = [run(fde_synth.fragment(system, I))[1] for I in range(len(system.subsystems))]
+    dd = 0.5 * float(np.sum(np.abs(rfde.rho_out.sum(0) - rks.rho_out[0]))) * st.cell.dV
+    return dict(dens_diff=dd, E_KS=eks, E_FDE=efde, E_frag=efrag, int_KS=eks - sum(efrag), int_FDE=efde - sum(efrag))
+
+
+def check_supersystem_comparison(be, prec, kinds, n_cycles=6, tol=1e-9):
+    s = fde_synth.tiny(0, with_kb=True, kfrac=[(0.25, 0.0, 0.0), (-0.25, 0.0, 0.0)], grid=(12, 12, 15))
+    mixer = dict(kind="pulay", nhist=4, beta=0.5, q0=0.6)
+    ref = oracle_supersystem_comparison(s, kinds, mixer, n_cycles)
+    got = driver.supersystem_comparison(s, prec=prec, backend=be, kinds=kinds, mixer=mixer, fixed_cycles=n_cycles)
+    for k in ("dens_diff", "E_KS", "E_FDE", "int_KS", "int_FDE"):
+        assert abs(got[k] - ref[k]) < tol * max(1.0, abs(ref[k])), (k, got[k], ref[k])
+    assert ref["dens_diff"] > 1e-4    # FDE and KS densities do differ
+    return got, ref

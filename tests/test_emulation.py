@@ -194,3 +194,8 @@ def test_embed_gga_vacuum(be):
 
 def test_trajectory_gga(be):
     pc.check_trajectory_gga(be, fde.F64, 2, 1e-10, 1e-10)
+
+
+def test_supersystem_comparison(be):
+    pc.check_supersystem_comparison(be, fde.F64, dict(xc=fde.XC_PBE, xc_nad=fde.XC_PBE, kin_nad=fde.KIN_LC94),
+                                    n_cycles=3)

@@ -173,6 +173,13 @@ def test_trajectory_gga(be):
     pc.check_trajectory_gga(be, fde.F32, 10, 1e-6, 1e-5)
 
 
+@pytest.mark.parametrize("kin", [fde.KIN_LC94, fde.KIN_REVAPBEK])
+def test_supersystem_comparison(be, kin):
+    # Table 1's quantities (density difference, interaction energies of KS and FDE) on a
+    # k-point cell with projectors, PBE, after a fixed number of Pulay cycles
+    pc.check_supersystem_comparison(be, fde.F64, dict(xc=fde.XC_PBE, xc_nad=fde.XC_PBE, kin_nad=kin))
+
+
 # ---------------------------------------------------------------------------
 # Full-size slab + molecule cell (60 x 60 x 240, ~50 300 plane waves), in the
 # launch configuration the benchmark times: all 40 slab bands in one call;
