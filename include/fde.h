@@ -119,7 +119,8 @@ fde_status fde_plan_set_workspace(fde_plan* plan, void* d_ws, size_t bytes, int 
  * 1e-6 (BF16X6) of S_jj: about ten times the products' relative noise.
  */
 /*
- * Launch-shape tuning (no effect on results). FDE_TUNE_APPLY_BPW: bands per
+ * Launch-shape tuning (no effect on results but the one FDE_TUNE_RR_SPLIT
+ * states). FDE_TUNE_APPLY_BPW: bands per
  * plane-pass workgroup of fde_apply_h (each workgroup reads one V_eff plane
  * for that many bands). FDE_TUNE_STICK_GROUP: z-sticks per workgroup of the
  * z-FFT passes of fde_apply_h and fde_density (a power of two, capped at 16
@@ -128,8 +129,12 @@ fde_status fde_plan_set_workspace(fde_plan* plan, void* d_ws, size_t bytes, int 
  * 120). FDE_TUNE_PLANE_KIND: the in-plane pass of fde_apply_h and
  * fde_density -- 1 whole-line register FFTs, 2 LDS Stockham passes, 3 two-factor
  * FFTs in LDS (used where the kind applies; otherwise the automatic choice).
- * FDE_TUNE_PLANE_ROWS: rows per batch of the two-factor pass (LDS size). 0
- * restores the automatic choice. The driver's
+ * FDE_TUNE_PLANE_ROWS: rows per batch of the two-factor pass (LDS size).
+ * FDE_TUNE_RR_SPLIT: the smallest m (columns of [X W P]) for which the
+ * Rayleigh-Ritz step of fde_subspace_rr runs its eigensolver as a sequence of
+ * multi-workgroup launches instead of one workgroup per problem (the two agree
+ * to rounding, not bit for bit; up to m = 768). 0 restores the automatic
+ * choice (a value of 1024 never splits). The driver's
  * autotuner times candidate values on the plan's own shapes and keeps the
  * fastest. Errors: FDE_ERR_ARG for an unknown key, a value outside [0, 1024]
  * or a stick group that is not a power of two.
@@ -139,6 +144,7 @@ fde_status fde_plan_set_workspace(fde_plan* plan, void* d_ws, size_t bytes, int 
 #define FDE_TUNE_Z_REGISTER 3
 #define FDE_TUNE_PLANE_KIND 4
 #define FDE_TUNE_PLANE_ROWS 5
+#define FDE_TUNE_RR_SPLIT 6
 fde_status fde_plan_set_tuning(fde_plan* plan, int key, int value);
 
 #define FDE_GEMM_FP64 0
@@ -401,6 +407,16 @@ fde_status fde_grid_dot(fde_plan* plan, const void* a, const void* b, double* ou
  */
 fde_status fde_energy_total(int ns, const double* embed_energies, const double* band_terms, const double* dots,
                             double* out, hipStream_t stream);
+
+/* Frozen environments of the freeze-and-thaw scheme (Fig. 1b caption: a subsystem
+ * iterated to self-consistency against the densities of the last broadcast; Sec. 2 on
+ * the freeze-and-thaw procedure): env[I * ld + i] = sum_{J != I} rho_sub[J][i], summed
+ * in ascending J (zero when ns = 1). rho_sub [ns][N] device, plan precision; env rows
+ * of ld >= N elements (ld = 2N writes the second density of [ns][2][N] pairs {rho_I,
+ * env_I}, whose fde_embed_potential gives V_eff^I in that environment as its first
+ * potential). Must not overlap rho_sub. FDE_ERR_ARG: ns < 1, ld < N, null pointers. */
+fde_status fde_frozen_environment(fde_plan* plan, int ns, const void* rho_sub, void* env, size_t ld,
+                                  hipStream_t stream);
 
 /* out[0] += int |sum_{I < ns} rho_sub[I] - rho_ref| dV over the plan's grid: the
  * integrated density difference (Sec. 4 measures FDE against Kohn-Sham by half of it)

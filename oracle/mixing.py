@@ -85,6 +85,10 @@ class Mixer:
         self.cell, self.kind, self.beta, self.nhist, self.q0 = cell, kind, beta, nhist, q0
         self.x_hist, self.r_hist = [], []
 
+    def reset(self):
+        """Forget the Pulay history (the next call mixes with its own pair only)."""
+        self.x_hist, self.r_hist = [], []
+
     def __call__(self, rho_in: np.ndarray, rho_out: np.ndarray) -> np.ndarray:
         R = rho_out - rho_in
         if self.kind == "linear":

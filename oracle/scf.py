@@ -2,7 +2,10 @@
 
 Fig. 1b and Sec. 2: the subsystem SCF step is executed once per embedding
 cycle and the total density is rebuilt every cycle, so all subsystem
-densities become self-consistent together (not freeze-and-thaw). One cycle,
+densities become self-consistent together. (The freeze-and-thaw scheme the
+Fig. 1b caption recovers, with every subsystem iterated against a frozen
+environment before the densities are broadcast, is the option
+scheme="freeze-thaw" of ``run``.) One cycle,
 with every subsystem seeing the densities of the cycle start (Jacobi order):
 
   1. V_eff^I for all I (recast effective potential, Appendix);
@@ -127,10 +130,46 @@ class CycleRecord:
     energies: np.ndarray         # embed energies of the input densities
 
 
-def run(system, n_cycles=None, n_david=None, kinds=None, st: Setup = None, callback=None, mixer=None):
+def environment(rho_in):
+    """env_I = sum_{J != I} rho_J (ascending J; zero for a single subsystem)."""
+    env = np.zeros_like(rho_in)
+    for I in range(rho_in.shape[0]):
+        for J in range(rho_in.shape[0]):
+            if J != I:
+                env[I] += rho_in[J]
+    return env
+
+
+def frozen_potentials(st: Setup, rho_in, env):
+    """V_eff^I with the environment of subsystem I frozen at env[I] (Fig. 1b caption:
+    each subsystem iterates against the densities of the last broadcast). The
+    recast V_eff^I depends only on rho = rho_I + env_I and on rho_I, so it is the
+    first potential of the two-density set {rho_I, env_I}."""
+    sysm = st.system
+    veff = np.zeros_like(rho_in)
+    for I in range(rho_in.shape[0]):
+        v2, _ = embed.embed_potential(st.cell, sysm.ecut, np.stack([rho_in[I], env[I]]), st.vloc, sysm.rho_thr,
+                                      **st.kinds)
+        veff[I] = v2[0]
+    return veff
+
+
+def run(system, n_cycles=None, n_david=None, kinds=None, st: Setup = None, callback=None, mixer=None,
+        scheme="jacobi", n_inner=1):
     """Run the embedding cycle; returns (records, final bands, setup). mixer: None for
     the linear mixing of the system (beta = system.mix_beta), else a
-    mixing.Mixer (e.g. Pulay with a Kerker preconditioner)."""
+    mixing.Mixer (e.g. Pulay with a Kerker preconditioner).
+
+    scheme "jacobi": the cycle above, the total density rebuilt every cycle.
+    scheme "freeze-thaw" (Fig. 1b caption; Sec. 2 on the freeze-and-thaw
+    procedure): each of the n_cycles outer cycles freezes every subsystem's
+    environment env_I = sum_{J != I} rho_J^in at its start and runs n_inner
+    subsystem SCF cycles against it (V_eff^I from rho_I + env_I and rho_I, steps
+    2-4 above for all I); only then is the total density rebuilt. A Pulay mixer
+    restarts its history at every outer cycle. One record per inner cycle.
+    n_inner = 1 is the Jacobi cycle up to the summation order of rho."""
+    if scheme not in ("jacobi", "freeze-thaw"):
+        raise ValueError("scheme must be 'jacobi' or 'freeze-thaw'")
     st = st or setup(system, kinds)
     mix = mixer or mixing.Mixer(st.cell, "linear", system.mix_beta)
     n_cycles = system.n_cycles if n_cycles is None else n_cycles
@@ -140,9 +179,18 @@ def run(system, n_cycles=None, n_david=None, kinds=None, st: Setup = None, callb
     for I in range(len(X)):
         X[I] = [subspace.orthonormalise(x) for x in X[I]]
     records = []
-    for c in range(n_cycles):
-        veff, en = embed.embed_potential(st.cell, system.ecut, rho_in, st.vloc, system.rho_thr,
-                                         **st.kinds)
+    inner = n_inner if scheme == "freeze-thaw" else 1
+    for c in range(n_cycles * inner):
+        if scheme == "jacobi":
+            veff, en = embed.embed_potential(st.cell, system.ecut, rho_in, st.vloc, system.rho_thr,
+                                             **st.kinds)
+        else:
+            if c % inner == 0:
+                env = environment(rho_in)
+                if c > 0:
+                    mix.reset()
+            veff = frozen_potentials(st, rho_in, env)
+            _, en = embed.embed_potential(st.cell, system.ecut, rho_in, st.vloc, system.rho_thr, **st.kinds)
         rho_out = np.zeros_like(rho_in)
         eps_all, mus = [], []
         for I, s in enumerate(system.subsystems):

@@ -50,6 +50,24 @@ struct KSumSub {
   }
 };
 
+// env[I * ld + i] = sum_{J != I} rho_sub[J][i], J ascending. grid (nblk, ns)
+template <typename T>
+struct KEnvironment {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char*, const T* __restrict__ sub, int ns, size_t n, T* __restrict__ env,
+                         size_t ld, unsigned nblk) {
+    const int I = c.by();
+    GRID_FOR(c, n, nblk) {
+      const size_t i = i0_ + l_;
+      if (i >= n) break;
+      T s = 0;
+      for (int J = 0; J < ns; ++J)
+        if (J != I) s += sub[(size_t)J * n + i];
+      env[(size_t)I * ld + i] = s;
+    }
+  }
+};
+
 template <typename T>
 struct KToComplex {
   template <class Ctx>
@@ -924,6 +942,20 @@ fde_status fde_density_l1(fde_plan* p, int ns, const void* rho_sub, const void* 
     FDE_TRY(launch<KAbsDiff<float>>(dim3(nb), kBlock, red, s, (const float*)rho_sub, ns, (const float*)rho_ref, n,
                                     part, nb));
   return launch<KRedAdd>(dim3(1), kBlock, red, s, (const double*)part, (int)nb, p->omega / (double)n, out, 0);
+}
+
+fde_status fde_frozen_environment(fde_plan* p, int ns, const void* rho_sub, void* env, size_t ld,
+                                  hipStream_t s) {
+  if (!p) return fail(FDE_ERR_ARG, "null plan");
+  if (ns < 1) return fail(FDE_ERR_ARG, "ns must be >= 1");
+  if (!rho_sub || !env) return fail(FDE_ERR_ARG, "null argument");
+  const size_t n = p->npts();
+  if (ld < n) return fail(FDE_ERR_ARG, "ld must be at least the number of grid points");
+  const unsigned nb = red_blocks(n);
+  if (p->prec == FDE_F64)
+    return launch<KEnvironment<double>>(dim3(nb, ns), kBlock, 0, s, (const double*)rho_sub, ns, n, (double*)env, ld,
+                                        nb);
+  return launch<KEnvironment<float>>(dim3(nb, ns), kBlock, 0, s, (const float*)rho_sub, ns, n, (float*)env, ld, nb);
 }
 
 fde_status fde_grid_mean(fde_plan* p, const void* a, double* out, hipStream_t s) {

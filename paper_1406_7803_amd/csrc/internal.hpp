@@ -53,6 +53,7 @@ struct fde_plan {
   int tune_zreg = 0; // z-passes: 0 four-step register FFT where specialised, 1 LDS passes always
   int tune_plane = 0; // plane pass: 0 automatic, 1 whole-line register, 2 LDS Stockham, 3 two-factor LDS
   int tune_rows = 0;  // rows per batch of the two-factor plane pass (0: automatic)
+  int tune_rr_split = 0;  // smallest m of the split Rayleigh-Ritz eigensolver (0: automatic)
   void* d_tw[3] = {nullptr, nullptr, nullptr};  // twiddles exp(-2 pi i m/N_a), plan precision
   char* scratch = nullptr;
   size_t scratch_bytes = 0;

@@ -138,6 +138,20 @@ struct KRRSolve {
   // positive pivot.
   template <class Ctx>
   FDE_HD static bool front(const Ctx& c, double* red, const Prob<T>& a, double drop_tol) {
+    if (!front_chol(c, red, a, drop_tol)) return false;
+    const int m = a.m, tid = c.tid(), nt = c.nthr();
+    cplx<double>*A = a.A, *L = a.L, *B = a.B;
+    // ---- B = L^{-1} A, then A~ = L^{-1} B^H into A: column per thread
+    for (int col = tid; col < m; col += nt) tri_solve_col(L, m, A + col, m, false, B + col, m, false);
+    c.sync();
+    for (int col = tid; col < m; col += nt) tri_solve_col(L, m, B + (size_t)col * m, 1, true, A + col, m, false);
+    c.sync();
+    return true;
+  }
+
+  // Masks and the Cholesky factor with dropping (the first part of front).
+  template <class Ctx>
+  FDE_HD static bool front_chol(const Ctx& c, double* red, const Prob<T>& a, double drop_tol) {
     const int m = a.m, nb = a.nb;
     const int tid = c.tid(), nt = c.nthr();
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -217,11 +231,7 @@ struct KRRSolve {
       }
       c.sync();
     }
-    // ---- B = L^{-1} A, then A~ = L^{-1} B^H into A: column per thread
-    for (int col = tid; col < m; col += nt) tri_solve_col(L, m, A + col, m, false, B + col, m, false);
-    c.sync();
-    for (int col = tid; col < m; col += nt) tri_solve_col(L, m, B + (size_t)col * m, 1, true, A + col, m, false);
-    c.sync();
+    (void)B;
     return true;
   }
 

@@ -22,6 +22,8 @@
 namespace fde {
 
 constexpr int kRRLdsMax = 80;
+// smallest m of a batch that takes the split multi-workgroup eigensolver
+constexpr int kRRSplitMin = 256;
 constexpr int kWRows = 15;  // row groups of the eigenvector update items
 
 FDE_HD int tri(int i, int j) { return i * (i + 1) / 2 + j; }  // j <= i
@@ -551,6 +553,7 @@ struct KRRSolveTri {
   static constexpr int kWaves = kThreads / 64;
   static constexpr int kGroup = 16;
   static constexpr int kInvIt = 3;
+  static constexpr int kBigCluster = 16;  // larger clusters: vectors in parallel, then orthonormalised
   static constexpr int kMsPoints = 7;  // multisection points per eigenvalue and step
 
   FDE_HD static size_t lu_stride(int m) { return ((size_t)m * (4 * sizeof(double) + 1) + 15) & ~(size_t)15; }
@@ -971,10 +974,13 @@ struct KRRSolveTri {
   // are loaded once for the NV vectors. Slots whose rows all lie outside k + 1 .. ma - 1 are
   // skipped by the whole group.
   template <int GL, int ZR, int NV, class Ctx>
-  FDE_HD static void back_transform(const Ctx& c, const TriWork& w, int m, int ma, int nw) {
+  FDE_HD static void back_transform(const Ctx& c, const TriWork& w, int m, int ma, int nw, int g0 = 0,
+                                    int gstride = 0) {
     const int tid = c.tid(), nt = c.nthr();
     const int gl = tid % GL, ngrp = nt / GL;
-    for (int n0 = (tid / GL) * NV; n0 < nw; n0 += ngrp * NV) {
+    // vector groups g0 + tid/GL, advancing by gstride groups (default: this workgroup's groups)
+    const int gs = gstride > 0 ? gstride : ngrp;
+    for (int n0 = (g0 + tid / GL) * NV; n0 < nw; n0 += gs * NV) {
       cplx<double> z[NV][ZR];
 #pragma unroll
       for (int q = 0; q < NV; ++q) {
@@ -1048,7 +1054,7 @@ struct KRRSolveTri {
   // Steps 3b-3e on the reduced active block (ma rows; dg, beta and alpha from the reduction):
   // eigenvalues and eigenvectors of the lowest nb, W^T rows n < nb with physical row indices,
   // masked rows zero, masked eigenpairs after the active ones. ZMAX bounds m.
-  template <int ZMAX, class Ctx>
+  template <int ZMAX, bool BACK = true, class Ctx>
   FDE_HD static void tri_eigen(const Ctx& c, const TriWork& w, int m, int nb, int ma) {
     const int tid = c.tid(), nt = c.nthr();
     const int lane = c.lane(), wl = c.wlanes(), wv = c.wave(), nwv = c.nwave();
@@ -1256,49 +1262,134 @@ struct KRRSolveTri {
       unsigned char* piv = (unsigned char*)(lu + 4 * ma);
       double* yl = lds_it ? (double*)((char*)lu + (((size_t)ma * (4 * sizeof(double) + 1) + 15) & ~(size_t)15))
                           : nullptr;
+      // one vector on one wavefront: shift lj, start vector, kInvIt solves, each followed by
+      // modified Gram-Schmidt against the vectors q0 .. j - 1 (none when q0 = j) and normalisation
+      auto inv_iter = [&](int j, double lj, int q0) {
+        double* const yout = Y + (size_t)j * ma;
+        double* y = lds_it ? yl : yout;
+        for (int i = lane; i < ma; i += wl) y[i] = start_value(i, j);
+        if (lane == 0) lu_factor<Ctx>(ma, dg, ea, lj, eps * tnorm, lu, piv);
+        c.wsync();
+        for (int it = 0; it < kInvIt; ++it) {
+          if (lane == 0) lu_solve(ma, lu, piv, y);
+          c.wsync();
+          for (int q = q0; q < j; ++q) {
+            const double* yq = Y + (size_t)q * ma;
+            double d = 0.0;
+            for (int i = lane; i < ma; i += wl) d += yq[i] * y[i];
+            d = c.template gsum<64>(d);
+            for (int i = lane; i < ma; i += wl) y[i] -= d * yq[i];
+          }
+          double nr = 0.0;
+          for (int i = lane; i < ma; i += wl) nr += y[i] * y[i];
+          nr = c.template gsum<64>(nr);
+          if (nr > 0.0) {
+            const double sc = 1.0 / sqrt(nr);
+            for (int i = lane; i < ma; i += wl) y[i] *= sc;
+          } else {
+            for (int i = lane; i < ma; i += wl) y[i] = i == j % ma ? 1.0 : 0.0;
+          }
+          c.wsync();
+        }
+        if (lds_it) {
+          for (int i = lane; i < ma; i += wl) yout[i] = y[i];
+          c.wsync();
+        }
+      };
+      // clusters of up to kBigCluster vectors: one wavefront each, its vectors in turn
       for (int ci = wv; wv < nit && ci < ncl; ci += nit) {
         const int j0 = cls[ci], j1 = cls[ci + 1];
         if (j1 - j0 == 1 && lo[j0] == 0.0) continue;
+        if (j1 - j0 > kBigCluster) continue;
         double lprev = 0.0;
         for (int j = j0; j < j1; ++j) {
           double lj = lam[j];
           if (j > j0 && lj - lprev < pertol) lj = lprev + pertol;
           lprev = lj;
-          double* const yout = Y + (size_t)j * ma;
-          double* y = lds_it ? yl : yout;
-          for (int i = lane; i < ma; i += wl) y[i] = start_value(i, j);
-          if (lane == 0) lu_factor<Ctx>(ma, dg, ea, lj, eps * tnorm, lu, piv);
-          c.wsync();
-          for (int it = 0; it < kInvIt; ++it) {
-            if (lane == 0) lu_solve(ma, lu, piv, y);
-            c.wsync();
-            for (int q = j0; q < j; ++q) {
-              const double* yq = Y + (size_t)q * ma;
-              double d = 0.0;
-              for (int i = lane; i < ma; i += wl) d += yq[i] * y[i];
-              d = c.template gsum<64>(d);
-              for (int i = lane; i < ma; i += wl) y[i] -= d * yq[i];
+          inv_iter(j, lj, j0);
+        }
+      }
+      // Larger clusters: the shifts (same perturbation rule) into hi, every vector iterated on
+      // its own with the wavefronts taking vectors in turn, then each cluster orthonormalised by
+      // the whole workgroup in index order: classical Gram-Schmidt against the earlier vectors
+      // (the projections summed over all of them at once), repeated once when the first pass
+      // removed more than half of the norm. The iterates of distinct shifts are already close to
+      // orthogonal, so one pass is the rule and the repeat covers near-degenerate pairs.
+      if (tid == 0) {
+        for (int ci = 0; ci < ncl; ++ci) {
+          const int j0 = cls[ci], j1 = cls[ci + 1];
+          if (j1 - j0 <= kBigCluster) continue;
+          double lprev = 0.0;
+          for (int j = j0; j < j1; ++j) {
+            double lj = lam[j];
+            if (j > j0 && lj - lprev < pertol) lj = lprev + pertol;
+            lprev = lj;
+            hi[j] = lj;
+          }
+        }
+      }
+      c.sync();
+      for (int ci = 0; ci < ncl; ++ci) {
+        const int j0 = cls[ci], j1 = cls[ci + 1];
+        if (j1 - j0 <= kBigCluster) continue;
+        for (int j = j0 + wv; wv < nit && j < j1; j += nit) inv_iter(j, hi[j], j);
+      }
+      c.sync();
+      // projections in e2 and the block sums in lo (both free once the vectors are computed)
+      double* dq = e2;
+      double* red = lo;
+      for (int ci = 0; ci < ncl; ++ci) {
+        const int j0 = cls[ci], j1 = cls[ci + 1];
+        if (j1 - j0 <= kBigCluster) continue;
+        for (int j = j0 + 1; j < j1; ++j) {
+          double* y = Y + (size_t)j * ma;
+          for (int pass = 0; pass < 2; ++pass) {
+            constexpr int QB = 4;  // earlier vectors per wavefront step, loaded together
+            for (int q = j0 + wv * QB; q < j; q += nwv * QB) {
+              double sq[QB];
+#pragma unroll
+              for (int t = 0; t < QB; ++t) sq[t] = 0.0;
+              for (int i = lane; i < ma; i += wl) {
+                const double yi = y[i];
+#pragma unroll
+                for (int t = 0; t < QB; ++t) {
+                  const int qq = q + t < j ? q + t : q;
+                  sq[t] += Y[(size_t)qq * ma + i] * yi;
+                }
+              }
+#pragma unroll
+              for (int t = 0; t < QB; ++t) {
+                const double v = c.template gsum<64>(sq[t]);
+                if (lane == 0 && q + t < j) dq[q + t - j0] = v;
+              }
             }
+            c.sync();
             double nr = 0.0;
-            for (int i = lane; i < ma; i += wl) nr += y[i] * y[i];
-            nr = c.template gsum<64>(nr);
+            for (int i = tid; i < ma; i += nt) {
+              double acc = 0.0;
+              for (int q = j0; q < j; ++q) acc += dq[q - j0] * Y[(size_t)q * ma + i];
+              const double v = y[i] - acc;
+              y[i] = v;
+              nr += v * v;
+            }
+            nr = c.sum(nr, red);
+            const bool again = pass == 0 && !(nr >= 0.25);  // the vector entered with unit norm
             if (nr > 0.0) {
               const double sc = 1.0 / sqrt(nr);
-              for (int i = lane; i < ma; i += wl) y[i] *= sc;
+              for (int i = tid; i < ma; i += nt) y[i] *= sc;
             } else {
-              for (int i = lane; i < ma; i += wl) y[i] = i == j % ma ? 1.0 : 0.0;
+              for (int i = tid; i < ma; i += nt) y[i] = i == j % ma ? 1.0 : 0.0;
             }
-            c.wsync();
-          }
-          if (lds_it) {
-            for (int i = lane; i < ma; i += wl) yout[i] = y[i];
-            c.wsync();
+            c.sync();
+            if (!again) break;
           }
         }
       }
       c.sync();
       // ---- 3e. W^T rows n < nw: z = D y, H_k z for k = ma - 2 .. 0, written to the physical
-      //      indices act[i], masked rows zero
+      //      indices act[i], masked rows zero (BACK false: left to a separate launch)
+      if constexpr (!BACK) {
+      } else
 #if defined(__HIP_DEVICE_COMPILE__)
       if constexpr (ZMAX > 16 * kGroup) {  // a whole wavefront per vector
         if (ma <= 256)
@@ -1309,7 +1400,9 @@ struct KRRSolveTri {
         back_transform<kGroup, (ZMAX + kGroup - 1) / kGroup, 1>(c, w, m, ma, nw);
       }
 #else
-      back_transform<1, ZMAX, 1>(c, w, m, ma, nw);
+      {
+        back_transform<1, ZMAX, 1>(c, w, m, ma, nw);
+      }
 #endif
     }
     // masked eigenpairs (A~ = kInactiveDiag e_p e_p^H) fill the columns beyond the active count
@@ -1559,6 +1652,324 @@ struct KRRSolveTriG {
     for (int e = tid; e < m * nb; e += nt) {
       const cplx<double> v = a.Cd[e];
       ((cplx<T>*)a.Ct)[e] = mk<T>((T)v.x, (T)v.y);
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// The same solve for large m split over launches so that most of it runs on many
+// workgroups (the single-workgroup solver above is latency-bound on one CU):
+//   KRRBigChol    masks and the Cholesky factor with dropping (one workgroup per problem);
+//   KRRBigSolve   B = L^{-1} A, then A~ = L^{-1} B^H: one column per thread, many workgroups;
+//   KRRBigPrep    the active indices, (A~ + A~^H)/2 on them into W, the first reflector;
+//   KRRBigHhP(k)  p = beta_k G' v_k, rows of the trailing block over many workgroups;
+//   KRRBigHhU(k)  the rank-2 update G' -= v w^H + w v^H (w = p - K v, K = beta/2 v^H p, summed
+//                 by every workgroup in the same order), rows over many workgroups; the
+//                 workgroup owning row k + 1 then forms reflector k + 1 from it;
+//   KRRBigTri     real tridiagonal, multisection and eigenvectors (one workgroup per problem);
+//   KRRBigBack    back-transformation W = Q D Y, one wavefront per eigenvector, many workgroups;
+//   KRRBigC       C = L^{-H} W[:, :nb], one column per thread, and the eigenvalues.
+// A problem whose Cholesky reported a dependent band column (info > 0) is skipped by every
+// later launch. Per-problem vectors live in the Gram-partial area, free after the Gram sums.
+// ---------------------------------------------------------------------------
+struct BigWs {
+  cplx<double>* v[2];  // reflector v_k, double-buffered by k parity
+  cplx<double>* p;     // beta_k G' v_k
+  double *dg, *beta, *ar, *ai, *dre, *dim;
+  int* act;
+  int* nact;
+  template <typename T>
+  FDE_HD explicit BigWs(const Prob<T>& a) {
+    double* b = (double*)a.part;
+    const size_t m = (size_t)a.m;
+    v[0] = (cplx<double>*)b;
+    v[1] = (cplx<double>*)(b + 2 * m);
+    p = (cplx<double>*)(b + 4 * m);
+    dg = b + 6 * m;
+    beta = b + 7 * m;
+    ar = b + 8 * m;
+    ai = b + 9 * m;
+    dre = b + 10 * m;
+    dim = b + 11 * m;
+    act = (int*)(b + 12 * m);
+    nact = act + m;
+  }
+};
+
+// reflector k of the active block G (ld ma) from row k (one workgroup): v into vbuf and
+// V's column-packed slot, beta, alpha, the diagonal G_kk
+template <class Ctx>
+FDE_HD void big_reflector(const Ctx& c, double* red, const cplx<double>* G, int ma, int k, cplx<double>* V,
+                          cplx<double>* vbuf, const BigWs& w) {
+  const int tid = c.tid(), nt = c.nthr();
+  const int n1 = ma - k - 1;
+  const cplx<double>* gk = G + (size_t)k * ma + k + 1;  // x_r = conj(gk[r])
+  double s2 = 0.0;
+  for (int r = tid; r < n1; r += nt) s2 += norm2(gk[r]);
+  s2 = c.sum(s2, red);
+  const cplx<double> x0 = conj(gk[0]);
+  double bt = 0.0;
+  cplx<double> alpha = x0, v0 = x0;
+  if (n1 > 1 && s2 > norm2(x0)) {
+    const double ax0 = sqrt(norm2(x0)), sg = sqrt(s2);
+    const cplx<double> ph = ax0 > 0.0 ? mk<double>(x0.x / ax0, x0.y / ax0) : mk<double>(1.0, 0.0);
+    alpha = mk<double>(-ph.x * sg, -ph.y * sg);
+    v0 = mk<double>(x0.x + ph.x * sg, x0.y + ph.y * sg);
+    bt = 1.0 / (sg * (sg + ax0));
+  }
+  if (tid == 0) {
+    w.beta[k] = bt;
+    w.ar[k] = alpha.x;
+    w.ai[k] = alpha.y;
+    w.dg[k] = G[(size_t)k * ma + k].x;
+  }
+  cplx<double>* vk = V + KRRSolveTri<double>::voff(k, ma);
+  for (int r = tid; r < n1; r += nt) {
+    const cplx<double> v = r == 0 ? v0 : conj(gk[r]);
+    vbuf[r] = v;
+    vk[r] = v;
+  }
+}
+
+FDE_HD cplx<double>* big_reflectors(const cplx<double>* S, int m) {
+  return (cplx<double>*)((double*)S + (size_t)m * m);  // behind the eigenvectors Y in S
+}
+
+template <typename T>
+struct KRRBigChol {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const ProbSet<T> ps) {
+    KRRSolve<T>::front_chol(c, (double*)lds, ps.p[c.bx()], ps.drop_tol);
+  }
+};
+
+// PASS 0: B = L^{-1} A (columns of A); PASS 1: A~ = L^{-1} B^H (rows of B) into A.
+// grid (ceil(m / 64), n), one column per thread.
+template <typename T, int PASS>
+struct KRRBigSolve {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char*, const ProbSet<T> ps) {
+    const Prob<T>& a = ps.p[c.by()];
+    if (a.info[0] > 0) return;
+    const int m = a.m;
+    for (int l = c.tid(); l < 64; l += c.nthr()) {
+      const int col = c.bx() * 64 + l;
+      if (col >= m) break;
+      if (PASS == 0)
+        tri_solve_col(a.L, m, a.A + col, m, false, a.B + col, m, false);
+      else
+        tri_solve_col(a.L, m, a.B + (size_t)col * m, 1, true, a.A + col, m, false);
+    }
+  }
+};
+
+template <typename T>
+struct KRRBigPrep {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const ProbSet<T> ps) {
+    const Prob<T>& a = ps.p[c.bx()];
+    if (a.info[0] > 0) return;
+    const int m = a.m, tid = c.tid(), nt = c.nthr();
+    double* red = (double*)lds;
+    int* sh = (int*)(red + 32);
+    const BigWs w(a);
+    if (tid == 0) {
+      int k = 0;
+      for (int j = 0; j < m; ++j)
+        if (!a.masked[j]) w.act[k++] = j;
+      w.nact[0] = k;
+      sh[0] = k;
+    }
+    c.sync();
+    const int ma = sh[0];
+    cplx<double>* G = a.W;
+    for (int e = tid; e < ma * ma; e += nt) {
+      const int i = e / ma, j = e - i * ma;
+      const int ai = w.act[i], aj = w.act[j];
+      const cplx<double> l = a.A[(size_t)ai * m + aj], u = a.A[(size_t)aj * m + ai];
+      G[e] = mk<double>(0.5 * (l.x + u.x), 0.5 * (l.y - u.y));
+    }
+    c.sync();
+    if (ma >= 2)
+      big_reflector(c, red, G, ma, 0, big_reflectors(a.S, m), w.v[0], w);
+    else if (tid == 0 && ma == 1)
+      w.dg[0] = G[0].x;
+  }
+};
+
+// rows per workgroup of the Householder launches, lanes per row
+constexpr int kHhRows = 16;
+
+template <typename T>
+struct KRRBigHhP {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char*, const ProbSet<T> ps, int k) {
+    const Prob<T>& a = ps.p[c.by()];
+    if (a.info[0] > 0) return;
+    const BigWs w(a);
+    const int ma = w.nact[0];
+    if (!(k + 1 < ma)) return;
+    const double bt = w.beta[k];
+    if (bt == 0.0) return;
+    const int n1 = ma - k - 1;
+#if defined(__HIP_DEVICE_COMPILE__)
+    constexpr int GL = 16;
+#else
+    constexpr int GL = 1;
+#endif
+    const cplx<double>* G = a.W;
+    const cplx<double>* v = w.v[k & 1];
+    const int tid = c.tid(), nt = c.nthr();
+    const int gl = tid % GL, grp = tid / GL, ng = nt / GL;
+    for (int rl = grp; rl < kHhRows; rl += ng) {
+      const int r = c.bx() * kHhRows + rl;
+      if (r >= n1) break;  // uniform per lane group
+      const cplx<double>* g = G + (size_t)(k + 1 + r) * ma + k + 1;
+      double sx = 0.0, sy = 0.0;
+      for (int j = gl; j < n1; j += GL) {
+        const cplx<double> gj = g[j], vj = v[j];
+        sx += gj.x * vj.x - gj.y * vj.y;
+        sy += gj.x * vj.y + gj.y * vj.x;
+      }
+      sx = c.template gsum<GL>(sx);
+      sy = c.template gsum<GL>(sy);
+      if (gl == 0) w.p[r] = mk<double>(bt * sx, bt * sy);
+    }
+  }
+};
+
+template <typename T>
+struct KRRBigHhU {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const ProbSet<T> ps, int k) {
+    const Prob<T>& a = ps.p[c.by()];
+    if (a.info[0] > 0) return;
+    const BigWs w(a);
+    const int ma = w.nact[0];
+    if (!(k + 1 < ma)) return;
+    const int n1 = ma - k - 1, m = a.m;
+    const int tid = c.tid(), nt = c.nthr();
+    double* red = (double*)lds;
+    cplx<double>* G = a.W;
+    const cplx<double>* v = w.v[k & 1];
+    const double bt = w.beta[k];
+    if (bt != 0.0) {  // uniform per problem
+      // K = beta/2 v^H p, summed in the same order by every workgroup
+      double kk = 0.0;
+      for (int r = tid; r < n1; r += nt) kk += v[r].x * w.p[r].x + v[r].y * w.p[r].y;
+      kk = 0.5 * bt * c.sum(kk, red);
+      for (int e = tid; e < kHhRows * n1; e += nt) {
+        const int rl = e / n1, j = e - rl * n1;
+        const int r = c.bx() * kHhRows + rl;
+        if (r >= n1) break;
+        const cplx<double> vj = v[j], vr = v[r], pj = w.p[j], pr = w.p[r];
+        const double wjx = pj.x - kk * vj.x, wjy = pj.y - kk * vj.y;
+        const double wrx = pr.x - kk * vr.x, wry = pr.y - kk * vr.y;
+        cplx<double>& t = G[(size_t)(k + 1 + r) * ma + k + 1 + j];
+        t.x -= (vr.x * wjx + vr.y * wjy) + (wrx * vj.x + wry * vj.y);
+        t.y -= (vr.y * wjx - vr.x * wjy) + (wry * vj.x - wrx * vj.y);
+      }
+    }
+    if (c.bx() != 0) return;
+    c.sync();  // row k + 1 (trailing row 0) is updated by this workgroup
+    if (k + 2 < ma)
+      big_reflector(c, red, G, ma, k + 1, big_reflectors(a.S, m), w.v[(k + 1) & 1], w);
+    else if (tid == 0)
+      w.dg[ma - 1] = G[(size_t)(ma - 1) * ma + ma - 1].x;
+  }
+};
+
+template <typename T>
+struct KRRBigTri {
+  using Tri = KRRSolveTri<T>;
+  using TriG = KRRSolveTriG<T>;
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const ProbSet<T> ps) {
+    const Prob<T>& a = ps.p[c.bx()];
+    if (a.info[0] > 0) return;
+    const int m = a.m, nb = a.nb;
+    const int tid = c.tid(), nt = c.nthr();
+    double* red = (double*)lds;
+    double* dg = red + 32;
+    double *e2 = dg + m, *ea = e2 + m, *beta = ea + m, *ar = beta + m, *ai = ar + m, *dre = ai + m, *dim = dre + m;
+    double *lam = dim + m, *lo = lam + m, *hi = lo + m, *pbx = hi + m, *pby = pbx + m;
+    cplx<double>* vl = (cplx<double>*)(((size_t)(pby + m) + 15) & ~(size_t)15);
+    int* act = (int*)(vl + m);
+    int* cls = act + m;
+    int* cnt = cls + m + 3;
+    const BigWs w(a);
+    const int ma = w.nact[0];
+    for (int i = tid; i < m; i += nt) {
+      dg[i] = i < ma ? w.dg[i] : 0.0;
+      beta[i] = i + 1 < ma ? w.beta[i] : 0.0;
+      ar[i] = i + 1 < ma ? w.ar[i] : 0.0;
+      ai[i] = i + 1 < ma ? w.ai[i] : 0.0;
+      act[i] = i < ma ? w.act[i] : 0;
+    }
+    if (tid == 0) cls[m + 1] = ma;
+    c.sync();
+    typename Tri::TriWork tw{dg,  e2,     ea,       beta, ar, ai,    dre,  dim,     lam,
+                             lo,  hi,     act,      cls,  a.masked, cnt, (char*)a.B,
+                             Tri::lu_stride(m), (double*)a.S, big_reflectors(a.S, m), a.A, m, a.theta};
+    int mmax = 0;
+    for (int q = 0; q < ps.n; ++q) mmax = ps.p[q].m > mmax ? ps.p[q].m : mmax;
+    if (TriG::lds_waves(mmax) > 0) {
+      tw.lul = lds + ((TriG::base_bytes(mmax) + 15) & ~(size_t)15);
+      tw.luls = Tri::lul_stride(mmax);
+      tw.nlw = TriG::lds_waves(mmax);
+    }
+    Tri::template tri_eigen<kRRTriMax, false>(c, tw, m, nb, ma);
+    c.sync();
+    for (int i = tid; i < ma; i += nt) {
+      w.dre[i] = dre[i];
+      w.dim[i] = dim[i];
+    }
+  }
+};
+
+// back-transformation: one wavefront (host: one thread) per eigenvector.
+// grid (nwg, n), 256 threads.
+template <typename T>
+struct KRRBigBack {
+  using Tri = KRRSolveTri<T>;
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char*, const ProbSet<T> ps) {
+    const Prob<T>& a = ps.p[c.by()];
+    if (a.info[0] > 0) return;
+    const BigWs w(a);
+    const int m = a.m, nb = a.nb, ma = w.nact[0];
+    const int nw = nb < ma ? nb : ma;
+    typename Tri::TriWork tw{w.dg, nullptr, nullptr, w.beta, w.ar, w.ai, w.dre, w.dim, nullptr,
+                             nullptr, nullptr, w.act, nullptr, a.masked, nullptr, nullptr,
+                             0, (double*)a.S, big_reflectors(a.S, m), a.A, m, a.theta};
+#if defined(__HIP_DEVICE_COMPILE__)
+    const int gpb = c.nthr() / 64;  // vector groups per workgroup
+    Tri::template back_transform<64, (kRRTriMax + 63) / 64, 1>(c, tw, m, ma, nw, c.bx() * gpb, gpb * gridDim.x);
+#else
+    (void)tw;
+    if (c.bx() == 0) Tri::template back_transform<1, kRRTriMax, 1>(c, tw, m, ma, nw);
+#endif
+  }
+};
+
+// C = L^{-H} W[:, :nb] (W^T rows in A), eigenvalues, C in plan precision; column per thread.
+// grid (ceil(nb / 64), n)
+template <typename T>
+struct KRRBigC {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char*, const ProbSet<T> ps) {
+    const Prob<T>& a = ps.p[c.by()];
+    if (a.info[0] > 0) return;
+    const int m = a.m, nb = a.nb;
+    for (int l = c.tid(); l < 64; l += c.nthr()) {
+      const int n = c.bx() * 64 + l;
+      if (n >= nb) break;
+      a.eval[n] = a.theta[n];
+      tri_solve_col(a.L, m, a.A + (size_t)n * m, 1, false, a.Cd + n, nb, true);
+      for (int i = 0; i < m; ++i) {
+        const cplx<double> v = a.Cd[(size_t)i * nb + n];
+        ((cplx<T>*)a.Ct)[(size_t)i * nb + n] = mk<T>((T)v.x, (T)v.y);
+      }
     }
   }
 };

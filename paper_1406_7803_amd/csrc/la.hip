@@ -85,6 +85,30 @@ static Prob<T> make_prob(fde_plan* p, const fde_block& b) {
   return P;
 }
 
+// The eigensolver of a batch with large m as phase launches (Cholesky, triangular solves,
+// one pair of launches per Householder column, tridiagonal eigenproblem, back-transformation,
+// C): most phases spread over many workgroups instead of one.
+template <typename T>
+static fde_status rr_split(ProbSet<T>& ps, int mmax, int nbmax, hipStream_t s) {
+  constexpr int TT = KRRSolveTri<T>::kThreads;
+  const size_t red = 64 * sizeof(double);
+  FDE_TRY((launch<KRRBigChol<T>, 1024>(dim3(ps.n), 1024, red, s, ps)));
+  const dim3 gcol((mmax + 63) / 64, ps.n);
+  FDE_TRY((launch<KRRBigSolve<T, 0>>(gcol, 64, 0, s, ps)));
+  FDE_TRY((launch<KRRBigSolve<T, 1>>(gcol, 64, 0, s, ps)));
+  FDE_TRY(launch<KRRBigPrep<T>>(dim3(ps.n), kBlock, red, s, ps));
+  for (int k = 0; k + 1 < mmax; ++k) {
+    // the trailing block shrinks with k: rows k + 1 .. ma - 1 in blocks of kHhRows
+    const dim3 g((mmax - k - 1 + kHhRows - 1) / kHhRows, ps.n);
+    FDE_TRY(launch<KRRBigHhP<T>>(g, kHhRows * 16, 0, s, ps, k));
+    FDE_TRY(launch<KRRBigHhU<T>>(g, kBlock, red, s, ps, k));
+  }
+  FDE_TRY((launch<KRRBigTri<T>, TT>(dim3(ps.n), TT, KRRSolveTriG<T>::lds_bytes(mmax), s, ps)));
+  FDE_TRY(launch<KRRBigBack<T>>(dim3((nbmax + 3) / 4, ps.n), kBlock, 0, s, ps));
+  FDE_TRY((launch<KRRBigC<T>>(dim3((nbmax + 63) / 64, ps.n), 64, 0, s, ps)));
+  return FDE_OK;
+}
+
 template <typename T>
 static fde_status rr_launch(fde_plan* p, ProbSet<T>& ps, hipStream_t s) {
   int mmax = 0, nbmax = 0, npwmax = 0;
@@ -123,7 +147,10 @@ static fde_status rr_launch(fde_plan* p, ProbSet<T>& ps, hipStream_t s) {
   size_t mats = 0;
   if (fixed + 2 * mbytes <= kLdsMax) mats = 2 * mbytes;
   else if (fixed + mbytes <= kLdsMax) mats = mbytes;
-  if (mmax <= kRRLdsMax && KRRSolveTri<T>::lds_bytes(mmax, nbmax) <= kLdsMax)
+  const int split_min = p->tune_rr_split > 0 ? p->tune_rr_split : kRRSplitMin;
+  if (mmax >= split_min && mmax <= kRRTriMax && KRRSolveTriG<T>::lds_bytes(mmax) <= kLdsMax) {
+    FDE_TRY(rr_split<T>(ps, mmax, nbmax, s));
+  } else if (mmax <= kRRLdsMax && KRRSolveTri<T>::lds_bytes(mmax, nbmax) <= kLdsMax)
     FDE_TRY((launch<KRRSolveTri<T>, KRRSolveTri<T>::kThreads>(dim3(ps.n), KRRSolveTri<T>::kThreads,
                                                                 KRRSolveTri<T>::lds_bytes(mmax, nbmax), s, ps)));
   else if (mmax > kRRLdsMax && mmax <= kRRTriMax && KRRSolveTriG<T>::lds_bytes(mmax) <= kLdsMax)

@@ -543,6 +543,9 @@ fde_status fde_plan_set_tuning(fde_plan* p, int key, int value) {
     case FDE_TUNE_PLANE_ROWS:
       p->tune_rows = value;
       return FDE_OK;
+    case FDE_TUNE_RR_SPLIT:
+      p->tune_rr_split = value;
+      return FDE_OK;
     case FDE_TUNE_STICK_GROUP:
       if ((value & (value - 1)) != 0) return fail(FDE_ERR_ARG, "sticks per workgroup must be 0 or a power of two");
       p->tune_sz = value;

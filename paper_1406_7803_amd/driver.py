@@ -63,6 +63,8 @@ class Engine:
     streams: int = 3                            # band-solver groups run concurrently (GPU backend)
     mixer: Optional[dict] = None                # None: linear (system.mix_beta); or dict(kind="pulay",
                                                 # nhist=6, beta=0.5, q0=0.5) for fde_mix_pulay
+    scheme: str = "jacobi"                      # or "freeze-thaw": n_inner cycles per frozen environment
+    n_inner: int = 1
 
     def __post_init__(self):
         s = self.system
@@ -125,6 +127,14 @@ class Engine:
             self.mix_info = torch.zeros(1, dtype=torch.int32, device=dev)
             self.x_hist = torch.zeros((nh, ns) + p.shape, dtype=p.rdtype, device=dev)
             self.r_hist = torch.zeros_like(self.x_hist)
+        if self.scheme not in ("jacobi", "freeze-thaw") or self.n_inner < 1:
+            raise fde.FdeError("scheme must be 'jacobi' or 'freeze-thaw' with n_inner >= 1")
+        if self.scheme == "freeze-thaw":
+            # {rho_I, env_I} pairs and their two potentials, per subsystem
+            self.pairs = torch.zeros((ns, 2) + p.shape, dtype=p.rdtype, device=dev)
+            self.pair_veff = torch.zeros_like(self.pairs)
+            self.pair_en = torch.zeros((ns, 3, fde.NE), dtype=torch.float64, device=dev)
+            self.inner = 0
         self._initial_density()
 
     def _make_groups(self, max_nb, nproj_max, nblocks):
@@ -217,12 +227,33 @@ class Engine:
             if g.stream is not None:
                 main.wait_stream(g.stream)
 
+    def _frozen_potentials(self):
+        """Freeze-and-thaw (Fig. 1b caption: each subsystem iterated against the densities
+        of the last broadcast): at the first of n_inner cycles the environments
+        env_I = sum_{J != I} rho_J are frozen (and a Pulay history restarts); every cycle
+        V_eff^I is the first potential of the pair {rho_I, env_I}."""
+        s, p = self.system, self.plan
+        if self.inner == 0:
+            p.frozen_environment(self.rho_in, self.pairs)
+            if self.mixer is not None:
+                self.mix_state.zero_()
+        self.inner = (self.inner + 1) % self.n_inner
+        for I in range(len(s.subsystems)):
+            self.pairs[I, 0].copy_(self.rho_in[I])
+            p.embed_potential(self.pairs[I], self.vloc, rho_thr=s.rho_thr, veff=self.pair_veff[I],
+                              energies=self.pair_en[I], info=self.einfo, **self.kinds)
+            self.veff[I].copy_(self.pair_veff[I, 0])
+
     def cycle(self, n_david: Optional[int] = None):
+        """One embedding cycle (Jacobi), or one inner cycle of the freeze-and-thaw scheme."""
         s = self.system
         p = self.plan
         n_david = s.n_david if n_david is None else n_david
-        p.embed_potential(self.rho_in, self.vloc, rho_thr=s.rho_thr, veff=self.veff, energies=self.energies,
-                          info=self.einfo, **self.kinds)
+        if self.scheme == "jacobi":
+            p.embed_potential(self.rho_in, self.vloc, rho_thr=s.rho_thr, veff=self.veff, energies=self.energies,
+                              info=self.einfo, **self.kinds)
+        else:
+            self._frozen_potentials()
         self.solve(n_david)
         for I, sub in enumerate(s.subsystems):
             for b in self.blocks[I]:
@@ -278,6 +309,8 @@ class Engine:
         tensors are fixed, so every replay advances the same engine by one cycle."""
         if self.be.emulated:
             raise fde.FdeError("graph capture needs the GPU backend")
+        if self.scheme != "jacobi":
+            raise fde.FdeError("graph capture records the Jacobi cycle only")
         self.cycle(n_david)
         torch.cuda.synchronize(self.be.device)
         self._graph = torch.cuda.CUDAGraph()

@@ -36,12 +36,14 @@ SYMBOLS = [
     "fde_subspace_rr_batched", "fde_precondition_batched", "fde_grid_mean", "fde_precondition_mlp_batched",
     "fde_mlp_forward", "fde_mlp_workspace_bytes", "fde_mlp_loss_grad", "fde_mlp_adam", "fde_plan_set_gemm_mode",
     "fde_plan_set_tuning", "fde_energy_total", "fde_mlp_loss_grad_static", "fde_mix_pulay", "fde_density_l1",
+    "fde_frozen_environment",
 ]
 TUNE_APPLY_BPW = 1
 TUNE_STICK_GROUP = 2
 TUNE_Z_REGISTER = 3
 TUNE_PLANE_KIND = 4
 TUNE_PLANE_ROWS = 5
+TUNE_RR_SPLIT = 6
 PLANE_REG, PLANE_LDS, PLANE_TWO_FACTOR = 1, 2, 3
 GEMM_FP64, GEMM_BF16X3, GEMM_BF16X6 = 0, 1, 2
 MLP_NPARAM, MLP_NIN, MLP_SAMPLE = 4545, 4, 7
@@ -95,6 +97,7 @@ def _declare(lib):
     lib.fde_grid_dot.argtypes = [_P, _P, _P, _P, _P]
     lib.fde_grid_mean.argtypes = [_P, _P, _P, _P]
     lib.fde_density_l1.argtypes = [_P, _I, _P, _P, _P, _P]
+    lib.fde_frozen_environment.argtypes = [_P, _I, _P, _P, _S, _P]
     lib.fde_plan_set_gemm_mode.argtypes = [_P, _I]
     lib.fde_plan_set_tuning.argtypes = [_P, _I, _I]
     lib.fde_precondition_mlp_batched.argtypes = [_P, _I, _P, _P, _P, _P]
@@ -410,6 +413,21 @@ class Plan:
         out = torch.zeros(1, dtype=torch.float64, device=self.be.device) if out is None else out
         self._f64(out, "out")
         self._check(self.lib.fde_density_l1(self.h, ns, _ptr(rho_sub), _ptr(rho_ref), _ptr(out), self.be.stream()))
+        return out
+
+    def frozen_environment(self, rho_sub, out):
+        """out[I] = sum_{J != I} rho_sub[J] (out [ns][N]), or into the second density of
+        [ns][2][N] pairs {rho_I, env_I}."""
+        self._grid(rho_sub, "rho_sub")
+        self._grid(out, "out")
+        n = int(np.prod(self.shape))
+        ns = rho_sub.numel() // n
+        if out.shape[0] != ns or out.numel() not in (ns * n, 2 * ns * n):
+            raise FdeError("out must be [ns][N] or [ns][2][N]")
+        ld = out.numel() // ns
+        dst = out if ld == n else out[:, 1]
+        self._check(self.lib.fde_frozen_environment(self.h, ns, _ptr(rho_sub), dst.data_ptr(), ld,
+                                                    self.be.stream()))
         return out
 
     def grid_mean(self, a, out=None):

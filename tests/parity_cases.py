@@ -164,18 +164,14 @@ LARGE = dict(L=(12.0, 12.0, 12.0), grid=(32, 32, 32), ecut=8.0, kf=[(0.25, 0.0, 
 GEMM_TOL = {fde.GEMM_FP64: (2e-5, 1e-4), fde.GEMM_BF16X6: (2e-5, 1e-4), fde.GEMM_BF16X3: (3e-4, 3e-3)}
 
 
-def check_subspace_rr(be, prec, drop_case=False, nb=4, case=SMALL, gemm=fde.GEMM_FP64):
-    """nb = 45 (m = 90) and nb = 140 (m = 280) exercise the tridiagonal solver with its matrices in
-    global memory, smaller m the LDS ones."""
-    plan = small_plan(be, prec, max_nb=max(4, nb), case=case)
-    if gemm != fde.GEMM_FP64:
-        plan.set_gemm_mode(gemm)
+def _rr_inputs(case, nb, drop_case, ik=0, seed=21):
+    """[X; T] and [HX; HT] of a Davidson step (m = 2 nb) with its column flags, and the oracle's
+    Rayleigh-Ritz result on them."""
     cell = basis.Cell(case["L"], case["grid"])
-    ik = 0
     sph = basis.sphere(cell, case["ecut"], case["kf"][ik])
     v = opseudo.local_potential(cell, case["ecut"], KB_ATOMS)
     beta, dkb = opseudo.kb_projectors(cell, sph, KB_ATOMS)
-    X = osub.orthonormalise(fde_synth.random_complex(21, (nb, sph.npw)))
+    X = osub.orthonormalise(fde_synth.random_complex(seed, (nb, sph.npw)))
     HX = oham.apply_h(cell, sph, X, v, beta, dkb)
     X, HX, lam = osub.subspace_rr(X, HX, nb)
     T, active, _ = osub.precondition(X, HX, lam, sph.kin)
@@ -186,10 +182,11 @@ def check_subspace_rr(be, prec, drop_case=False, nb=4, case=SMALL, gemm=fde.GEMM
         T[2] = X[0] + 1e-7 * T[3]     # nearly dependent: dropped by the pivot test
     HT = oham.apply_h(cell, sph, T, v, beta, dkb)
     Xr, HXr, lr = osub.subspace_rr(np.vstack([X, T]), np.vstack([HX, HT]), nb, act)
-    V = to_dev(plan, np.vstack([X, T]), "c")
-    HV = to_dev(plan, np.vstack([HX, HT]), "c")
-    ev, info = plan.subspace_rr(ik, V, HV, nb, active=torch.from_numpy(act.astype(np.uint8)).to(plan.be.device))
-    be.sync()
+    H = lambda Y: oham.apply_h(cell, sph, Y, v, beta, dkb)  # noqa: E731
+    return np.vstack([X, T]), np.vstack([HX, HT]), act, Xr, lr, H
+
+
+def _rr_compare(prec, gemm, nb, V, HV, ev, info, Xr, lr, H):
     assert int(host(info)[0]) == 0
     tol, ptol = (1e-11, 1e-10) if prec == fde.F64 else GEMM_TOL[gemm]
     assert np.max(np.abs(host(ev) - lr)) < tol, np.max(np.abs(host(ev) - lr))
@@ -200,7 +197,95 @@ def check_subspace_rr(be, prec, drop_case=False, nb=4, case=SMALL, gemm=fde.GEMM
     P_ref = Xr.T @ Xr.conj()
     assert np.max(np.abs(P_gpu - P_ref)) < ptol, np.max(np.abs(P_gpu - P_ref))
     # HX rows are H applied to the new X
-    assert rel(host(HV)[:nb], oham.apply_h(cell, sph, Xg, v, beta, dkb)) < (1e-10 if prec == fde.F64 else 1e-4)
+    assert rel(host(HV)[:nb], H(Xg)) < (1e-10 if prec == fde.F64 else 1e-4)
+
+
+def check_subspace_rr(be, prec, drop_case=False, nb=4, case=SMALL, gemm=fde.GEMM_FP64, split=None):
+    """nb = 45 (m = 90) and nb = 140 (m = 280) exercise the tridiagonal solver with its matrices in
+    global memory, smaller m the LDS ones; from m = 256 on (or from m = split) the eigensolver runs
+    as multi-workgroup phase launches."""
+    plan = small_plan(be, prec, max_nb=max(4, nb), case=case)
+    if gemm != fde.GEMM_FP64:
+        plan.set_gemm_mode(gemm)
+    if split is not None:
+        plan.set_tuning(fde.TUNE_RR_SPLIT, split)
+    ik = 0
+    VT, HVT, act, Xr, lr, H = _rr_inputs(case, nb, drop_case, ik)
+    V = to_dev(plan, VT, "c")
+    HV = to_dev(plan, HVT, "c")
+    ev, info = plan.subspace_rr(ik, V, HV, nb, active=torch.from_numpy(act.astype(np.uint8)).to(plan.be.device))
+    be.sync()
+    _rr_compare(prec, gemm, nb, V, HV, ev, info, Xr, lr, H)
+
+
+def check_subspace_rr_clustered(be, prec, m, nb, split=None, case=MEDIUM):
+    """A Rayleigh-Ritz problem with a designed spectrum: orthonormal V and HV = M V with
+    M = U diag(lam) U^H (U random unitary), lam holding a chain of 40 values 2e-5 apart
+    (one cluster for the eigenvector phase), an exactly degenerate pair inside the chain, a
+    triple 1e-12 apart, and a gap of 0.5 above band nb so the wanted subspace is well defined."""
+    plan = small_plan(be, prec, max_nb=max(4, nb, (m + 1) // 2), case=case)
+    if split is not None:
+        plan.set_tuning(fde.TUNE_RR_SPLIT, split)
+    npw = plan.npw(0)
+    assert npw >= m
+    rng = np.random.default_rng(77)
+    lam = np.sort(rng.uniform(-2.0, 1.0, m))
+    lam[5:45] = -1.0 + 2e-5 * np.arange(40)
+    lam[20] = lam[21]
+    lam[nb - 3:nb] = 0.3 + 1e-12 * np.arange(3)
+    lam[nb:] = np.sort(rng.uniform(0.8, 3.0, m - nb))
+    lam[:nb] = np.sort(lam[:nb])
+    Z = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+    U, _ = np.linalg.qr(Z)
+    M = (U * lam) @ U.conj().T
+    M = 0.5 * (M + M.conj().T)
+    V = osub.orthonormalise(fde_synth.random_complex(23, (m, npw)))
+    HV = M.T @ V  # hv_j = sum_k M_kj v_k: <v_i|H v_j> = M_ij
+    Xr, HXr, lr = osub.subspace_rr(V, HV, nb)
+    assert np.max(np.abs(lr - lam[:nb])) < 1e-10  # the oracle sees the designed spectrum
+    Vd, HVd = to_dev(plan, V, "c"), to_dev(plan, HV, "c")
+    ev, info = plan.subspace_rr(0, Vd, HVd, nb)
+    be.sync()
+    assert int(host(info)[0]) == 0
+    tol, ptol, otol = (1e-11, 1e-10, 1e-12) if prec == fde.F64 else (2e-5, 1e-4, 1e-5)
+    assert np.max(np.abs(host(ev) - lr)) < tol, np.max(np.abs(host(ev) - lr))
+    Xg = host(Vd)[:nb]
+    assert np.max(np.abs(Xg.conj() @ Xg.T - np.eye(nb))) < otol, np.max(np.abs(Xg.conj() @ Xg.T - np.eye(nb)))
+    P = Xg.T @ Xg.conj() - Xr.T @ Xr.conj()
+    assert np.max(np.abs(P)) < ptol, np.max(np.abs(P))
+
+
+def check_subspace_rr_batched_split(be, prec, split):
+    """One batch of blocks of different m through the split eigensolver (split = smallest m that
+    takes it): m = 90, m = 60 with an inactive and a dropped column, and m = 3 with two equal band
+    columns (info = 3, its X left unchanged, the other blocks unaffected)."""
+    case = MEDIUM
+    plan = fde.Plan(case["L"], case["grid"], case["ecut"], case["kf"], prec=prec, max_nb=45, max_nproj=8,
+                    max_batch=3, backend=be)
+    plan.set_tuning(fde.TUNE_RR_SPLIT, split)
+    dev = plan.be.device
+    blocks, want = [], []
+    for nb, drop, seed in [(45, False, 21), (30, True, 22)]:
+        VT, HVT, act, Xr, lr, H = _rr_inputs(case, nb, drop, 0, seed)
+        V, HV = to_dev(plan, VT, "c"), to_dev(plan, HVT, "c")
+        a = torch.from_numpy(act.astype(np.uint8)).to(dev)
+        ev = torch.zeros(nb, dtype=torch.float64, device=dev)
+        info = torch.full((1,), -7, dtype=torch.int32, device=dev)
+        blocks.append(plan.make_block(0, nb, 2 * nb, V, HV, active=a, eval=ev, info=info))
+        want.append((nb, V, HV, ev, info, Xr, lr, H, a))
+    Xs = fde_synth.random_complex(31, (3, plan.npw(0)))
+    Xs[2] = Xs[1]
+    Vs = to_dev(plan, Xs, "c")
+    HVs = Vs.clone()
+    evs = torch.zeros(3, dtype=torch.float64, device=dev)
+    infos = torch.zeros(1, dtype=torch.int32, device=dev)
+    blocks.insert(1, plan.make_block(0, 3, 3, Vs, HVs, eval=evs, info=infos))
+    plan.subspace_rr_batched(blocks)
+    be.sync()
+    for nb, V, HV, ev, info, Xr, lr, H, a in want:
+        _rr_compare(prec, fde.GEMM_FP64, nb, V, HV, ev, info, Xr, lr, H)
+    assert int(host(infos)[0]) == 3
+    assert np.array_equal(host(Vs), Xs.astype(host(Vs).dtype))
 
 
 def check_singular_gram(be, prec):
@@ -754,6 +839,51 @@ def check_trajectory_pulay(be, prec, system, n_cycles, eps_tol, drho_tol, mixer)
     assert int(host(eng.mix_info)[0]) == 0
     assert worst[0] < eps_tol and worst[1] < drho_tol, worst
     return worst
+
+
+def check_trajectory_freeze_thaw(be, prec, n_outer, n_inner, eps_tol, drho_tol, mixer=None):
+    """The two-subsystem cube in the freeze-and-thaw scheme: n_outer frozen environments,
+    n_inner cycles each (linear mixing, or Pulay restarted per environment)."""
+    from oracle import mixing as omix
+    s = fde_synth.config1()
+    st = oscf.setup(s)
+    om = None if mixer is None else omix.Mixer(st.cell, "pulay", mixer["beta"], mixer["nhist"], mixer["q0"])
+    recs, _, _ = oscf.run(s, n_cycles=n_outer, st=st, mixer=om, scheme="freeze-thaw", n_inner=n_inner)
+    eng = driver.Engine(s, prec=prec, backend=be, mixer=mixer, scheme="freeze-thaw", n_inner=n_inner)
+    worst = (0.0, 0.0, 0.0)
+    for c in range(n_outer * n_inner):
+        eng.cycle()
+        be.sync()
+        for I in range(len(s.subsystems)):
+            e = np.max(np.abs(host(eng.eps[I]) - recs[c].eps[I]))
+            d = float(np.sum(np.abs(host(eng.rho_out[I]) - recs[c].rho_out[I]))) * st.cell.dV
+            v = float(np.max(np.abs(host(eng.veff[I]) - recs[c].veff[I])))
+            worst = (max(worst[0], e), max(worst[1], d), max(worst[2], v))
+    assert all(int(host(b.info)[0]) == 0 for row in eng.blocks for b in row)
+    assert worst[0] < eps_tol and worst[1] < drho_tol, worst
+    return worst
+
+
+def check_frozen_environment(be, prec):
+    """env_I = sum_{J != I} rho_J for three subsystems, into [ns][N] and into the pairs'
+    second slot (first slot untouched); one subsystem gives zero."""
+    plan = small_plan(be, prec)
+    n = int(np.prod(plan.shape))
+    rho = fde_synth.random_real(91, (3,) + plan.shape)
+    want = oscf.environment(rho)
+    got = plan.frozen_environment(to_dev(plan, rho, "r"), plan.zeros_grid(3))
+    be.sync()
+    tol = 1e-15 if prec == fde.F64 else 1e-6
+    assert np.max(np.abs(host(got) - want)) < tol
+    pairs = torch.full((3, 2) + plan.shape, 7.0, dtype=plan.rdtype, device=plan.be.device)
+    plan.frozen_environment(to_dev(plan, rho, "r"), pairs)
+    be.sync()
+    assert np.max(np.abs(host(pairs)[:, 1] - want)) < tol
+    assert np.all(host(pairs)[:, 0] == 7.0)
+    one = plan.frozen_environment(to_dev(plan, rho[:1], "r"), plan.zeros_grid(1) + 5.0)
+    be.sync()
+    assert np.all(host(one) == 0.0)
+    assert n == rho[0].size
 
 
 def check_trajectory_gga(be, prec, n_cycles, eps_tol, drho_tol):

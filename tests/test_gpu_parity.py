@@ -68,6 +68,28 @@ def test_subspace_rr_large_m(be, prec):
     pc.check_subspace_rr(be, prec, nb=300, case=pc.LARGE)
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_subspace_rr_split_eigensolver(be, prec):
+    """The multi-workgroup eigensolver forced on small m, alone and in a batch of mixed m."""
+    pc.check_subspace_rr(be, prec, nb=45, case=pc.MEDIUM, split=1)
+    pc.check_subspace_rr(be, prec, drop_case=True, nb=40, case=pc.MEDIUM, split=64)
+    pc.check_subspace_rr(be, prec, nb=4, split=1)
+    pc.check_subspace_rr_batched_split(be, prec, split=1)
+    # and kept off for m = 280, which then takes the single-workgroup solver
+    pc.check_subspace_rr(be, prec, nb=140, case=pc.MEDIUM, split=1024)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_subspace_rr_clustered_spectrum(be, prec):
+    """A 40-vector eigenvalue cluster with a degenerate pair: the eigenvector phase's parallel
+    iteration and workgroup orthonormalisation, in the global solver (m = 120), the split one
+    (m = 120 forced, m = 300) and the LDS solver (m = 80)."""
+    pc.check_subspace_rr_clustered(be, prec, 120, 60)
+    pc.check_subspace_rr_clustered(be, prec, 120, 60, split=1)
+    pc.check_subspace_rr_clustered(be, prec, 300, 100, case=pc.LARGE)
+    pc.check_subspace_rr_clustered(be, prec, 80, 60)
+
+
 def test_singular_gram(be):
     pc.check_singular_gram(be, fde.F64)
 
@@ -392,3 +414,16 @@ def test_c3_cycle_properties(be):
     for I, sub in enumerate(s.subsystems):
         q = float(pc.host(eng.rho_out[I]).astype(np.float64).sum()) * dv
         assert abs(q - sub.nelec) < 1e-3 * max(1.0, sub.nelec), (I, q, sub.nelec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_frozen_environment(be, prec):
+    pc.check_frozen_environment(be, prec)
+
+
+def test_trajectory_freeze_thaw(be):
+    """2 frozen environments x 3 inner cycles, linear mixing and Pulay restarted per environment."""
+    pc.check_trajectory_freeze_thaw(be, fde.F64, 2, 3, 1e-10, 1e-10)
+    pc.check_trajectory_freeze_thaw(be, fde.F64, 2, 3, 1e-10, 1e-10,
+                                    mixer=dict(kind="pulay", nhist=4, beta=0.5, q0=0.6))
+    pc.check_trajectory_freeze_thaw(be, fde.F32, 2, 3, 1e-6, 1e-5)
