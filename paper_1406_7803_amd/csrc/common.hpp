@@ -64,6 +64,26 @@ struct DevCtx {
     __syncthreads();
     return red[16];
   }
+  // XCD-aware tile of a 2-D grid (gx, gy). The dispatcher hands consecutive workgroups to
+  // the eight XCDs in turn; this maps them so that every XCD runs one contiguous range of
+  // the order "x major, y minor" (XMAJOR) or "y major, x minor": neighbouring tiles of that
+  // order, which read the same data or the same cache lines, then share one XCD's L2
+  // instead of fetching it once per XCD.
+  template <bool XMAJOR>
+  __device__ __forceinline__ void xcd_tile(int& tx, int& ty) const {
+    constexpr unsigned kXcds = 8;
+    const unsigned gx = gridDim.x, gy = gridDim.y, total = gx * gy;
+    const unsigned L = blockIdx.x + gx * blockIdx.y;
+    const unsigned k = L % kXcds, idx = L / kXcds, base = total / kXcds, rem = total % kXcds;
+    const unsigned logical = k * base + (k < rem ? k : rem) + idx;
+    if (XMAJOR) {
+      tx = (int)(logical / gy);
+      ty = (int)(logical % gy);
+    } else {
+      ty = (int)(logical / gx);
+      tx = (int)(logical % gx);
+    }
+  }
   // Wavefront-level helpers: lane and wavefront index, an LDS ordering point among the lanes
   // of one wavefront, and a fixed-order sum over aligned groups of W lanes that every lane of
   // the group receives (call with all W lanes of the group active).
@@ -138,6 +158,11 @@ struct HostCtx {
   int bx() const { return x; }
   int by() const { return y; }
   int bz() const { return z; }
+  template <bool XMAJOR>
+  void xcd_tile(int& tx, int& ty) const {
+    tx = x;
+    ty = y;
+  }
   void sync() const {}
   double sum(double v, double*) const { return v; }
   double max(double v, double*) const { return v; }

@@ -273,12 +273,14 @@ struct KPlaneH4 {
                          const int4* __restrict__ sticks, int ncol, int nxa, int mlo, int N1, int N2, int N3, int RB,
                          const cplx<T>* __restrict__ tw1, const cplx<T>* __restrict__ tw2,
                          const T* __restrict__ veff) {
-    const int z = c.bx();
+    // the band groups of one plane run on one XCD, so its V_eff plane is read from that L2
+    int z, grp;
+    c.template xcd_tile<true>(z, grp);
     Plane4Lds<T> L(lds, N1, N2, nxa, RB);
     plane4_setup<T>(c, L, sticks, ncol, nxa, tw1, tw2, N1, N2);
     const Split2 s1 = split2(N1), s2 = split2(N2);
     const T* vz = veff + (size_t)z * N1 * N2;
-    const int b0 = c.by() * BPW;
+    const int b0 = grp * BPW;
     for (int band = b0; band < b0 + BPW && band < nbands; ++band) {
       cplx<T>* row = sb + ((size_t)band * N3 + z) * stick_stride(ncol);
       plane4_load<T>(c, L, row, ncol, nxa, N2);

@@ -51,8 +51,10 @@ struct KZInv {
                          cplx<T>* __restrict__ sb, int SZ) {
     const int N3 = r3.n;
     const int ES = SZ + 1;
-    const int c0 = c.bx() * SZ;
-    const int band = c.by();
+    // neighbouring stick groups of a band on one XCD (their row segments share cache lines)
+    int grp, band;
+    c.template xcd_tile<false>(grp, band);
+    const int c0 = grp * SZ;
     const int nsz = (ncol - c0) < SZ ? (ncol - c0) : SZ;
     cplx<T>* a = (cplx<T>*)lds;
     cplx<T>* b = a + N3 * ES;
@@ -92,8 +94,11 @@ struct KZFwd {
                          const cplx<T>* __restrict__ tw, KVec kv, double invN, int SZ) {
     const int N3 = r3.n;
     const int ES = SZ + 1;
-    const int c0 = c.bx() * SZ;
-    const int band = c.by();
+    // neighbouring stick groups of a band on one XCD: row segments narrower than a cache
+    // line are then fetched once, not once per XCD
+    int grp, band;
+    c.template xcd_tile<false>(grp, band);
+    const int c0 = grp * SZ;
     const int nsz = (ncol - c0) < SZ ? (ncol - c0) : SZ;
     cplx<T>* a = (cplx<T>*)lds;
     cplx<T>* b = a + N3 * ES;
