@@ -962,6 +962,7 @@ struct KRRSolveTri {
     char* lul = nullptr;
     size_t luls = 0;
     int nlw = 0;
+    double* tn = nullptr;  // optional: receives |T| (the scale of the pivot floor)
   };
   // bytes of one wavefront's LDS slot for the inverse iteration of an m-row problem
   FDE_HD static size_t lul_stride(int m) {
@@ -1051,10 +1052,65 @@ struct KRRSolveTri {
     }
   }
 
+  // Orthonormalisation of the cluster j0 .. j1 - 1 of unit vectors in Y (rows of ma), in index
+  // order by the whole workgroup: classical Gram-Schmidt of vector j against all earlier ones
+  // at once (their projections in dq), repeated once when the pass removed more than half of
+  // the norm, then normalisation. red: block-sum scratch.
+  template <class Ctx>
+  FDE_HD static void cluster_orth(const Ctx& c, double* Y, int ma, int j0, int j1, double* dq, double* red) {
+    const int tid = c.tid(), nt = c.nthr();
+    const int lane = c.lane(), wl = c.wlanes(), wv = c.wave(), nwv = c.nwave();
+    for (int j = j0 + 1; j < j1; ++j) {
+      double* y = Y + (size_t)j * ma;
+      for (int pass = 0; pass < 2; ++pass) {
+        constexpr int QB = 4;  // earlier vectors per wavefront step, loaded together
+        for (int q = j0 + wv * QB; q < j; q += nwv * QB) {
+          double sq[QB];
+#pragma unroll
+          for (int t = 0; t < QB; ++t) sq[t] = 0.0;
+          for (int i = lane; i < ma; i += wl) {
+            const double yi = y[i];
+#pragma unroll
+            for (int t = 0; t < QB; ++t) {
+              const int qq = q + t < j ? q + t : q;
+              sq[t] += Y[(size_t)qq * ma + i] * yi;
+            }
+          }
+#pragma unroll
+          for (int t = 0; t < QB; ++t) {
+            const double v = c.template gsum<64>(sq[t]);
+            if (lane == 0 && q + t < j) dq[q + t - j0] = v;
+          }
+        }
+        c.sync();
+        double nr = 0.0;
+        for (int i = tid; i < ma; i += nt) {
+          double acc = 0.0;
+          for (int q = j0; q < j; ++q) acc += dq[q - j0] * Y[(size_t)q * ma + i];
+          const double v = y[i] - acc;
+          y[i] = v;
+          nr += v * v;
+        }
+        nr = c.sum(nr, red);
+        const bool again = pass == 0 && !(nr >= 0.25);  // the vector entered with unit norm
+        if (nr > 0.0) {
+          const double sc = 1.0 / sqrt(nr);
+          for (int i = tid; i < ma; i += nt) y[i] *= sc;
+        } else {
+          for (int i = tid; i < ma; i += nt) y[i] = i == j % ma ? 1.0 : 0.0;
+        }
+        c.sync();
+        if (!again) break;
+      }
+    }
+  }
+
   // Steps 3b-3e on the reduced active block (ma rows; dg, beta and alpha from the reduction):
   // eigenvalues and eigenvectors of the lowest nb, W^T rows n < nb with physical row indices,
   // masked rows zero, masked eigenpairs after the active ones. ZMAX bounds m.
-  template <int ZMAX, bool BACK = true, class Ctx>
+  // DEFER: every vector that needs inverse iteration (clusters, failed singles) gets its shift
+  // in hi but neither its iteration nor its orthonormalisation, which separate launches do.
+  template <int ZMAX, bool BACK = true, bool DEFER = false, class Ctx>
   FDE_HD static void tri_eigen(const Ctx& c, const TriWork& w, int m, int nb, int ma) {
     const int tid = c.tid(), nt = c.nthr();
     const int lane = c.lane(), wl = c.wlanes(), wv = c.wave(), nwv = c.nwave();
@@ -1297,7 +1353,7 @@ struct KRRSolveTri {
         }
       };
       // clusters of up to kBigCluster vectors: one wavefront each, its vectors in turn
-      for (int ci = wv; wv < nit && ci < ncl; ci += nit) {
+      for (int ci = wv; !DEFER && wv < nit && ci < ncl; ci += nit) {
         const int j0 = cls[ci], j1 = cls[ci + 1];
         if (j1 - j0 == 1 && lo[j0] == 0.0) continue;
         if (j1 - j0 > kBigCluster) continue;
@@ -1318,7 +1374,7 @@ struct KRRSolveTri {
       if (tid == 0) {
         for (int ci = 0; ci < ncl; ++ci) {
           const int j0 = cls[ci], j1 = cls[ci + 1];
-          if (j1 - j0 <= kBigCluster) continue;
+          if (j1 - j0 <= (DEFER ? 0 : kBigCluster)) continue;
           double lprev = 0.0;
           for (int j = j0; j < j1; ++j) {
             double lj = lam[j];
@@ -1329,62 +1385,20 @@ struct KRRSolveTri {
         }
       }
       c.sync();
-      for (int ci = 0; ci < ncl; ++ci) {
-        const int j0 = cls[ci], j1 = cls[ci + 1];
-        if (j1 - j0 <= kBigCluster) continue;
-        for (int j = j0 + wv; wv < nit && j < j1; j += nit) inv_iter(j, hi[j], j);
-      }
+      if constexpr (!DEFER)
+        for (int ci = 0; ci < ncl; ++ci) {
+          const int j0 = cls[ci], j1 = cls[ci + 1];
+          if (j1 - j0 <= kBigCluster) continue;
+          for (int j = j0 + wv; wv < nit && j < j1; j += nit) inv_iter(j, hi[j], j);
+        }
+      if (w.tn && tid == 0) *w.tn = tnorm;
       c.sync();
       // projections in e2 and the block sums in lo (both free once the vectors are computed)
-      double* dq = e2;
-      double* red = lo;
-      for (int ci = 0; ci < ncl; ++ci) {
-        const int j0 = cls[ci], j1 = cls[ci + 1];
-        if (j1 - j0 <= kBigCluster) continue;
-        for (int j = j0 + 1; j < j1; ++j) {
-          double* y = Y + (size_t)j * ma;
-          for (int pass = 0; pass < 2; ++pass) {
-            constexpr int QB = 4;  // earlier vectors per wavefront step, loaded together
-            for (int q = j0 + wv * QB; q < j; q += nwv * QB) {
-              double sq[QB];
-#pragma unroll
-              for (int t = 0; t < QB; ++t) sq[t] = 0.0;
-              for (int i = lane; i < ma; i += wl) {
-                const double yi = y[i];
-#pragma unroll
-                for (int t = 0; t < QB; ++t) {
-                  const int qq = q + t < j ? q + t : q;
-                  sq[t] += Y[(size_t)qq * ma + i] * yi;
-                }
-              }
-#pragma unroll
-              for (int t = 0; t < QB; ++t) {
-                const double v = c.template gsum<64>(sq[t]);
-                if (lane == 0 && q + t < j) dq[q + t - j0] = v;
-              }
-            }
-            c.sync();
-            double nr = 0.0;
-            for (int i = tid; i < ma; i += nt) {
-              double acc = 0.0;
-              for (int q = j0; q < j; ++q) acc += dq[q - j0] * Y[(size_t)q * ma + i];
-              const double v = y[i] - acc;
-              y[i] = v;
-              nr += v * v;
-            }
-            nr = c.sum(nr, red);
-            const bool again = pass == 0 && !(nr >= 0.25);  // the vector entered with unit norm
-            if (nr > 0.0) {
-              const double sc = 1.0 / sqrt(nr);
-              for (int i = tid; i < ma; i += nt) y[i] *= sc;
-            } else {
-              for (int i = tid; i < ma; i += nt) y[i] = i == j % ma ? 1.0 : 0.0;
-            }
-            c.sync();
-            if (!again) break;
-          }
+      if constexpr (!DEFER)
+        for (int ci = 0; ci < ncl; ++ci) {
+          const int j0 = cls[ci], j1 = cls[ci + 1];
+          if (j1 - j0 > kBigCluster) cluster_orth(c, Y, ma, j0, j1, e2, lo);
         }
-      }
       c.sync();
       // ---- 3e. W^T rows n < nw: z = D y, H_k z for k = ma - 2 .. 0, written to the physical
       //      indices act[i], masked rows zero (BACK false: left to a separate launch)
@@ -1659,25 +1673,28 @@ struct KRRSolveTriG {
 // ---------------------------------------------------------------------------
 // The same solve for large m split over launches so that most of it runs on many
 // workgroups (the single-workgroup solver above is latency-bound on one CU):
-//   KRRBigChol    masks and the Cholesky factor with dropping (one workgroup per problem);
-//   KRRBigSolve   B = L^{-1} A, then A~ = L^{-1} B^H: one column per thread, many workgroups;
+//   KRRChol*      blocked Cholesky with dropping (below);
+//   KRRBigTrsm    B = L^{-1} A, A~ = L^{-1} B^H and, at the end, C = L^{-H} W, by column strips;
 //   KRRBigPrep    the active indices, (A~ + A~^H)/2 on them into W, the first reflector;
 //   KRRBigHhP(k)  p = beta_k G' v_k, rows of the trailing block over many workgroups;
 //   KRRBigHhU(k)  the rank-2 update G' -= v w^H + w v^H (w = p - K v, K = beta/2 v^H p, summed
 //                 by every workgroup in the same order), rows over many workgroups; the
 //                 workgroup owning row k + 1 then forms reflector k + 1 from it;
-//   KRRBigTri     real tridiagonal, multisection and eigenvectors (one workgroup per problem);
-//   KRRBigBack    back-transformation W = Q D Y, one wavefront per eigenvector, many workgroups;
-//   KRRBigC       C = L^{-H} W[:, :nb], one column per thread, and the eigenvalues.
+//   KRRBigTri     real tridiagonal, multisection, twisted factorisations of isolated eigenvalues
+//                 and the shifts of the rest (one workgroup per problem);
+//   KRRBigInv     inverse iteration of the clustered eigenvalues' vectors, one per wavefront;
+//   KRRBigOrth    their orthonormalisation per cluster (one workgroup per problem);
+//   KRRBigBack    back-transformation W = Q D Y, one wavefront per eigenvector, many workgroups.
 // A problem whose Cholesky reported a dependent band column (info > 0) is skipped by every
 // later launch. Per-problem vectors live in the Gram-partial area, free after the Gram sums.
 // ---------------------------------------------------------------------------
 struct BigWs {
   cplx<double>* v[2];  // reflector v_k, double-buffered by k parity
   cplx<double>* p;     // beta_k G' v_k
-  double *dg, *beta, *ar, *ai, *dre, *dim;
-  int* act;
-  int* nact;
+  double *dg, *beta, *ar, *ai, *dre, *dim, *ea, *shift, *sdiag, *tnorm;
+  int *act, *nact;     // active indices and their count
+  int *cls, *ncl;      // cluster starts (ncl + 1) and the cluster count
+  int *bigv, *nbig;    // the vectors that need inverse iteration, in order, and their count
   template <typename T>
   FDE_HD explicit BigWs(const Prob<T>& a) {
     double* b = (double*)a.part;
@@ -1691,8 +1708,16 @@ struct BigWs {
     ai = b + 9 * m;
     dre = b + 10 * m;
     dim = b + 11 * m;
-    act = (int*)(b + 12 * m);
+    ea = b + 12 * m;
+    shift = b + 13 * m;
+    sdiag = b + 14 * m;
+    tnorm = b + 15 * m;
+    act = (int*)(b + 15 * m + 2);
     nact = act + m;
+    cls = nact + 1;
+    ncl = cls + m + 1;
+    bigv = ncl + 1;
+    nbig = bigv + m;
   }
 };
 
@@ -1735,30 +1760,188 @@ FDE_HD cplx<double>* big_reflectors(const cplx<double>* S, int m) {
   return (cplx<double>*)((double*)S + (size_t)m * m);  // behind the eigenvectors Y in S
 }
 
-template <typename T>
-struct KRRBigChol {
-  template <class Ctx>
-  FDE_HD static void run(const Ctx& c, char* lds, const ProbSet<T> ps) {
-    KRRSolve<T>::front_chol(c, (double*)lds, ps.p[c.bx()], ps.drop_tol);
-  }
-};
+// Blocked right-looking Cholesky with dropping (the same decisions as KRRSolve::front_chol: a
+// correction column j >= nb whose pivot d = S_jj - sum_k |L_jk|^2 falls below drop_tol S_jj is
+// dropped, a band column with such a pivot is an error), in column blocks of kCholB:
+//   KRRCholInit    masks, S and A of masked columns, L = 0, the diagonal of S kept;
+//   KRRCholDiag    the block's columns in turn on one wavefront (S' holds S minus the earlier
+//                  blocks' terms), drop decisions, the block's own rows of L;
+//   KRRCholPanel   L for the rows below the block, one row per thread (zero in dropped columns);
+//   KRRCholUpdate  S'_il -= sum over the block L_ip conj(L_lp) on the trailing lower triangle,
+//                  32 x 32 tiles over many workgroups.
+constexpr int kCholB = 32;
 
-// PASS 0: B = L^{-1} A (columns of A); PASS 1: A~ = L^{-1} B^H (rows of B) into A.
-// grid (ceil(m / 64), n), one column per thread.
-template <typename T, int PASS>
-struct KRRBigSolve {
+template <typename T>
+struct KRRCholInit {
   template <class Ctx>
   FDE_HD static void run(const Ctx& c, char*, const ProbSet<T> ps) {
     const Prob<T>& a = ps.p[c.by()];
-    if (a.info[0] > 0) return;
     const int m = a.m;
+    const BigWs w(a);
+    const size_t mm = (size_t)m * m;
+    for (int l = c.tid(); l < 1024; l += c.nthr()) {
+      const size_t e = (size_t)c.bx() * 1024 + l;
+      if (e >= mm) break;
+      const int i = (int)(e / m), j = (int)(e - (size_t)i * m);
+      const bool mi = a.active && !a.active[i], mj = a.active && !a.active[j];
+      if (mi || mj) {
+        a.S[e] = mk<double>(i == j ? 1.0 : 0.0, 0.0);
+        a.A[e] = mk<double>(i == j ? kInactiveDiag : 0.0, 0.0);
+      }
+      a.L[e] = mk<double>(0.0, 0.0);
+      if (i == j) {
+        a.masked[j] = mi ? 1 : 0;
+        w.sdiag[j] = mi ? 1.0 : a.S[e].x;
+      }
+      if (e == 0) a.info[0] = 0;
+    }
+  }
+};
+
+template <typename T>
+struct KRRCholDiag {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const ProbSet<T> ps, int j0) {
+    const Prob<T>& a = ps.p[c.bx()];
+    const int m = a.m, nb = a.nb;
+    if (a.info[0] > 0 || j0 >= m) return;
+    const int j1 = j0 + kCholB < m ? j0 + kCholB : m;
+    const int tid = c.tid(), nt = c.nthr();
+    double* red = (double*)lds;
+    const BigWs w(a);
+    cplx<double>*S = a.S, *L = a.L, *A = a.A;
+    const double drop_tol = ps.drop_tol;
+    for (int j = j0; j < j1; ++j) {
+      double part = 0.0;
+      for (int k = j0 + tid; k < j; k += nt) part += norm2(L[(size_t)j * m + k]);
+      const double sjj = w.sdiag[j];
+      const double d = S[(size_t)j * m + j].x - c.sum(part, red);
+      const bool drop = (j >= nb) && !(d >= drop_tol * sjj);
+      if (drop) {
+        for (int k = tid; k < j; k += nt) L[(size_t)j * m + k] = mk<double>(0, 0);
+        for (int i = tid; i < m; i += nt) {
+          if (i != j) {
+            A[(size_t)i * m + j] = mk<double>(0, 0);
+            A[(size_t)j * m + i] = mk<double>(0, 0);
+          }
+        }
+        if (tid == 0) {
+          L[(size_t)j * m + j] = mk<double>(1.0, 0.0);
+          A[(size_t)j * m + j] = mk<double>(kInactiveDiag, 0.0);
+          a.masked[j] = 1;
+        }
+        c.sync();
+        continue;
+      }
+      if (!(d >= drop_tol * sjj) || !(d > 0.0)) {
+        // a dependent band column: report, C = I, NaN eigenvalues; later launches skip
+        if (tid == 0) a.info[0] = j + 1;
+        for (int e = tid; e < m * nb; e += nt) {
+          const int i = e / nb, n = e - i * nb;
+          const cplx<double> v = mk<double>(i == n ? 1.0 : 0.0, 0.0);
+          a.Cd[e] = v;
+          ((cplx<T>*)a.Ct)[e] = mk<T>((T)v.x, (T)v.y);
+        }
+        for (int n = tid; n < nb; n += nt) a.eval[n] = 0.0 / 0.0;
+        return;  // uniform
+      }
+      const double ljj = sqrt(d);
+      if (tid == 0) L[(size_t)j * m + j] = mk<double>(ljj, 0.0);
+      for (int i = j + 1 + tid; i < j1; i += nt) {
+        double ax = 0.0, ay = 0.0;  // sum over the block's earlier columns of L_ip conj(L_jp)
+        for (int p = j0; p < j; ++p) {
+          const cplx<double> lip = L[(size_t)i * m + p], ljp = L[(size_t)j * m + p];
+          ax += lip.x * ljp.x + lip.y * ljp.y;
+          ay += lip.y * ljp.x - lip.x * ljp.y;
+        }
+        const cplx<double> sij = S[(size_t)i * m + j];
+        L[(size_t)i * m + j] = cdiv_real(mk<double>(sij.x - ax, sij.y - ay), ljj);
+      }
+      c.sync();
+    }
+  }
+};
+
+// rows j1 .. m - 1 of L in the block's columns; grid (ceil((m - j1) / 64), n), 64 threads
+template <typename T>
+struct KRRCholPanel {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const ProbSet<T> ps, int j0) {
+    const Prob<T>& a = ps.p[c.by()];
+    const int m = a.m;
+    if (a.info[0] > 0 || j0 >= m) return;
+    const int j1 = j0 + kCholB < m ? j0 + kCholB : m, nbk = j1 - j0;
+    cplx<double>* Lb = (cplx<double>*)lds;  // the block's diagonal tile [nbk][nbk]
+    for (int e = c.tid(); e < nbk * nbk; e += c.nthr()) {
+      const int r = e / nbk, q = e - r * nbk;
+      Lb[e] = a.L[(size_t)(j0 + r) * m + j0 + q];
+    }
+    c.sync();
     for (int l = c.tid(); l < 64; l += c.nthr()) {
-      const int col = c.bx() * 64 + l;
-      if (col >= m) break;
-      if (PASS == 0)
-        tri_solve_col(a.L, m, a.A + col, m, false, a.B + col, m, false);
-      else
-        tri_solve_col(a.L, m, a.B + (size_t)col * m, 1, true, a.A + col, m, false);
+      const int i = j1 + c.bx() * 64 + l;
+      if (i >= m) break;
+      cplx<double>* li = a.L + (size_t)i * m;
+      const cplx<double>* si = a.S + (size_t)i * m;
+      for (int j = j0; j < j1; ++j) {
+        const int q = j - j0;
+        if (a.masked[j]) {
+          li[j] = mk<double>(0.0, 0.0);
+          continue;
+        }
+        double ax = 0.0, ay = 0.0;
+        for (int p = 0; p < q; ++p) {
+          const cplx<double> lip = li[j0 + p], ljp = Lb[q * nbk + p];
+          ax += lip.x * ljp.x + lip.y * ljp.y;
+          ay += lip.y * ljp.x - lip.x * ljp.y;
+        }
+        li[j] = cdiv_real(mk<double>(si[j].x - ax, si[j].y - ay), Lb[q * nbk + q].x);
+      }
+    }
+  }
+};
+
+// S'_il -= sum_{p in block} L_ip conj(L_lp), j1 <= l <= i < m; one 32 x 32 tile of the trailing
+// lower triangle per workgroup (tile index over the triangle), 256 threads
+template <typename T>
+struct KRRCholUpdate {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const ProbSet<T> ps, int j0) {
+    const Prob<T>& a = ps.p[c.by()];
+    const int m = a.m;
+    if (a.info[0] > 0) return;
+    const int j1 = j0 + kCholB;
+    if (j1 >= m) return;
+    const int ntile = (m - j1 + 31) / 32;
+    // tile (ti, tl), tl <= ti, from the workgroup index
+    int t = c.bx(), ti = 0;
+    while (ti < ntile && t > ti) {
+      t -= ti + 1;
+      ++ti;
+    }
+    if (ti >= ntile) return;
+    const int tl = t;
+    cplx<double>* Li = (cplx<double>*)lds;  // [32][kCholB] rows i of the block's columns
+    cplx<double>* Ll = Li + 32 * kCholB;     // [32][kCholB] rows l
+    const int i0 = j1 + ti * 32, l0 = j1 + tl * 32;
+    for (int e = c.tid(); e < 32 * kCholB; e += c.nthr()) {
+      const int r = e / kCholB, p = e - r * kCholB;
+      Li[e] = i0 + r < m ? a.L[(size_t)(i0 + r) * m + j0 + p] : mk<double>(0.0, 0.0);
+      Ll[e] = l0 + r < m ? a.L[(size_t)(l0 + r) * m + j0 + p] : mk<double>(0.0, 0.0);
+    }
+    c.sync();
+    for (int e = c.tid(); e < 32 * 32; e += c.nthr()) {
+      const int r = e / 32, q = e - r * 32;
+      const int i = i0 + r, l = l0 + q;
+      if (i >= m || l > i) continue;
+      double ax = 0.0, ay = 0.0;
+      for (int p = 0; p < kCholB; ++p) {
+        const cplx<double> x = Li[r * kCholB + p], y = Ll[q * kCholB + p];
+        ax += x.x * y.x + x.y * y.y;
+        ay += x.y * y.x - x.x * y.y;
+      }
+      cplx<double>& s = a.S[(size_t)i * m + l];
+      s.x -= ax;
+      s.y -= ay;
     }
   }
 };
@@ -1918,11 +2101,104 @@ struct KRRBigTri {
       tw.luls = Tri::lul_stride(mmax);
       tw.nlw = TriG::lds_waves(mmax);
     }
-    Tri::template tri_eigen<kRRTriMax, false>(c, tw, m, nb, ma);
+    tw.tn = w.tnorm;
+    Tri::template tri_eigen<kRRTriMax, false, true>(c, tw, m, nb, ma);
     c.sync();
+    // the phases of the later launches: D, the off-diagonal, the shifts and the vectors that
+    // need inverse iteration (clusters and failed singles)
+    const int nw = nb < ma ? nb : ma;
     for (int i = tid; i < ma; i += nt) {
       w.dre[i] = dre[i];
       w.dim[i] = dim[i];
+      w.ea[i] = ea[i];
+    }
+    for (int j = tid; j < nw; j += nt) w.shift[j] = hi[j];
+    if (tid == 0) {
+      const int ncl = nw > 0 ? cls[m + 2] : 0;
+      int nbig = 0;
+      for (int ci = 0; ci <= ncl; ++ci) w.cls[ci] = cls[ci];
+      for (int ci = 0; ci < ncl; ++ci)
+        if (cls[ci + 1] - cls[ci] > 1 || lo[cls[ci]] != 0.0)
+          for (int j = cls[ci]; j < cls[ci + 1]; ++j) w.bigv[nbig++] = j;
+      w.ncl[0] = ncl;
+      w.nbig[0] = nbig;
+    }
+  }
+};
+
+// Inverse iteration of the vectors of clusters (and of failed singles), each on its own
+// wavefront with its factors and working vector in LDS (the tridiagonal in LDS too), no
+// orthogonalisation.
+// grid (ceil(max nbig / 4), n), 256 threads.
+template <typename T>
+struct KRRBigInv {
+  using Tri = KRRSolveTri<T>;
+  static constexpr int kVec = 4;  // vectors (wavefronts) per workgroup
+  FDE_HD static size_t slot_bytes(int m) { return Tri::lul_stride(m); }
+  FDE_HD static size_t lds_bytes(int m) { return 2 * (size_t)m * sizeof(double) + kVec * slot_bytes(m); }
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const ProbSet<T> ps, int mmax) {
+    const Prob<T>& a = ps.p[c.by()];
+    if (a.info[0] > 0) return;
+    const BigWs w(a);
+    const int nbig = w.nbig[0];
+    if (c.bx() * kVec >= nbig) return;
+    const int ma = w.nact[0];
+    const int tid = c.tid(), nt = c.nthr(), lane = c.lane(), wl = c.wlanes();
+    double* dgl = (double*)lds;
+    double* eal = dgl + mmax;
+    for (int i = tid; i < ma; i += nt) {
+      dgl[i] = w.dg[i];
+      eal[i] = w.ea[i];
+    }
+    c.sync();
+    const double tiny = 2.220446049250313e-16 * w.tnorm[0];
+    double* Y = (double*)a.S;
+    for (int v = c.wave(); v < kVec; v += c.nwave()) {
+      const int k = c.bx() * kVec + v;
+      if (k >= nbig) break;  // wavefront-uniform
+      const int j = w.bigv[k];
+      double* lu = (double*)(lds + 2 * (size_t)mmax * sizeof(double) + (size_t)v * slot_bytes(mmax));
+      unsigned char* piv = (unsigned char*)(lu + 4 * ma);
+      double* y = (double*)((char*)lu + Tri::lu_stride(ma));
+      for (int i = lane; i < ma; i += wl) y[i] = Tri::start_value(i, j);
+      if (lane == 0) Tri::template lu_factor<Ctx>(ma, dgl, eal, w.shift[j], tiny, lu, piv);
+      c.wsync();
+      for (int it = 0; it < Tri::kInvIt; ++it) {
+        if (lane == 0) Tri::lu_solve(ma, lu, piv, y);
+        c.wsync();
+        double nr = 0.0;
+        for (int i = lane; i < ma; i += wl) nr += y[i] * y[i];
+        nr = c.template gsum<64>(nr);
+        if (nr > 0.0) {
+          const double sc = 1.0 / sqrt(nr);
+          for (int i = lane; i < ma; i += wl) y[i] *= sc;
+        } else {
+          for (int i = lane; i < ma; i += wl) y[i] = i == j % ma ? 1.0 : 0.0;
+        }
+        c.wsync();
+      }
+      double* yout = Y + (size_t)j * ma;
+      for (int i = lane; i < ma; i += wl) yout[i] = y[i];
+    }
+  }
+};
+
+// Orthonormalisation of every cluster (one workgroup per problem).
+template <typename T>
+struct KRRBigOrth {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const ProbSet<T> ps) {
+    const Prob<T>& a = ps.p[c.bx()];
+    if (a.info[0] > 0) return;
+    const BigWs w(a);
+    if (w.nbig[0] == 0) return;
+    const int ma = w.nact[0], ncl = w.ncl[0];
+    double* red = (double*)lds;
+    double* dq = red + 32;
+    for (int ci = 0; ci < ncl; ++ci) {
+      const int j0 = w.cls[ci], j1 = w.cls[ci + 1];
+      if (j1 - j0 > 1) KRRSolveTri<T>::cluster_orth(c, (double*)a.S, ma, j0, j1, dq, red);
     }
   }
 };
@@ -1952,25 +2228,95 @@ struct KRRBigBack {
   }
 };
 
-// C = L^{-H} W[:, :nb] (W^T rows in A), eigenvalues, C in plan precision; column per thread.
-// grid (ceil(nb / 64), n)
-template <typename T>
-struct KRRBigC {
+// Triangular solves of the split path by column strips: a workgroup of 32 x 8 threads takes
+// 8 columns, keeps them in LDS, and walks the rows in blocks of 32 (forward, or backward for
+// L^H): thread (r, q) first subtracts from row r of the block the terms of every row already
+// solved (a dot product over them, the rows of the block in parallel), then one thread per
+// column solves the block's own triangle.
+//   MODE 0: B = L^{-1} A;  MODE 1: A~ = L^{-1} B^H (into A);
+//   MODE 2: C = L^{-H} W[:, :nb] (W^T rows in A) into Cd and, in plan precision, Ct, and the
+//           eigenvalues.
+// grid (ceil(ncols / 8), n), 256 threads, LDS m x 8 complex doubles.
+template <typename T, int MODE>
+struct KRRBigTrsm {
+  static constexpr int RB = 32, CB = 8;
+  FDE_HD static size_t lds_bytes(int m) { return (size_t)m * CB * sizeof(cplx<double>); }
   template <class Ctx>
-  FDE_HD static void run(const Ctx& c, char*, const ProbSet<T> ps) {
+  FDE_HD static void run(const Ctx& c, char* lds, const ProbSet<T> ps) {
     const Prob<T>& a = ps.p[c.by()];
     if (a.info[0] > 0) return;
     const int m = a.m, nb = a.nb;
-    for (int l = c.tid(); l < 64; l += c.nthr()) {
-      const int n = c.bx() * 64 + l;
-      if (n >= nb) break;
-      a.eval[n] = a.theta[n];
-      tri_solve_col(a.L, m, a.A + (size_t)n * m, 1, false, a.Cd + n, nb, true);
-      for (int i = 0; i < m; ++i) {
-        const cplx<double> v = a.Cd[(size_t)i * nb + n];
-        ((cplx<T>*)a.Ct)[(size_t)i * nb + n] = mk<T>((T)v.x, (T)v.y);
+    const int ncols = MODE == 2 ? nb : m;
+    const int c0 = c.bx() * CB;
+    if (c0 >= ncols) return;
+    const int tid = c.tid(), nt = c.nthr();
+    constexpr bool up = MODE == 2;
+    const cplx<double>* L = a.L;
+    cplx<double>* X = (cplx<double>*)lds;  // [m][CB]
+    for (int e = tid; e < m * CB; e += nt) {
+      const int i = e / CB, q = e - i * CB, col = c0 + q;
+      cplx<double> v = mk<double>(0.0, 0.0);
+      if (col < ncols) {
+        if (MODE == 0) v = a.A[(size_t)i * m + col];
+        if (MODE == 1) v = conj(a.B[(size_t)col * m + i]);
+        if (MODE == 2) v = a.A[(size_t)col * m + i];
+      }
+      X[e] = v;
+    }
+    c.sync();
+    // logical row t in solve order <-> physical row
+    auto row = [&](int t) { return up ? m - 1 - t : t; };
+    // factor of row i against solved row k: L_ik (forward), conj(L_ki) (backward)
+    auto lf = [&](int i, int k) {
+      const cplx<double> l = up ? L[(size_t)k * m + i] : L[(size_t)i * m + k];
+      return up ? conj(l) : l;
+    };
+    for (int b0 = 0; b0 < m; b0 += RB) {
+      const int nr = m - b0 < RB ? m - b0 : RB;
+      for (int e = tid; e < RB * CB; e += nt) {
+        const int r = e % RB, q = e / RB;
+        if (r >= nr) continue;
+        const int i = row(b0 + r);
+        double ax = 0.0, ay = 0.0;
+        for (int t = 0; t < b0; ++t) {
+          const int k = row(t);
+          const cplx<double> l = lf(i, k), xk = X[k * CB + q];
+          ax += l.x * xk.x - l.y * xk.y;
+          ay += l.x * xk.y + l.y * xk.x;
+        }
+        X[i * CB + q].x -= ax;
+        X[i * CB + q].y -= ay;
+      }
+      c.sync();
+      for (int q = tid; q < CB; q += nt) {
+        for (int r = 0; r < nr; ++r) {
+          const int i = row(b0 + r);
+          double sx = X[i * CB + q].x, sy = X[i * CB + q].y;
+          for (int p = 0; p < r; ++p) {
+            const int k = row(b0 + p);
+            const cplx<double> l = lf(i, k), xk = X[k * CB + q];
+            sx -= l.x * xk.x - l.y * xk.y;
+            sy -= l.x * xk.y + l.y * xk.x;
+          }
+          X[i * CB + q] = cdiv_real(mk<double>(sx, sy), L[(size_t)i * m + i].x);
+        }
+      }
+      c.sync();
+    }
+    for (int e = tid; e < m * CB; e += nt) {
+      const int i = e / CB, q = e - i * CB, col = c0 + q;
+      if (col >= ncols) continue;
+      const cplx<double> v = X[e];
+      if (MODE == 0) a.B[(size_t)i * m + col] = v;
+      if (MODE == 1) a.A[(size_t)i * m + col] = v;
+      if (MODE == 2) {
+        a.Cd[(size_t)i * nb + col] = v;
+        ((cplx<T>*)a.Ct)[(size_t)i * nb + col] = mk<T>((T)v.x, (T)v.y);
       }
     }
+    if (MODE == 2)
+      for (int q = tid; q < CB; q += nt)
+        if (c0 + q < nb) a.eval[c0 + q] = a.theta[c0 + q];
   }
 };
 

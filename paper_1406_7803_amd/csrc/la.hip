@@ -92,10 +92,21 @@ template <typename T>
 static fde_status rr_split(ProbSet<T>& ps, int mmax, int nbmax, hipStream_t s) {
   constexpr int TT = KRRSolveTri<T>::kThreads;
   const size_t red = 64 * sizeof(double);
-  FDE_TRY((launch<KRRBigChol<T>, 1024>(dim3(ps.n), 1024, red, s, ps)));
-  const dim3 gcol((mmax + 63) / 64, ps.n);
-  FDE_TRY((launch<KRRBigSolve<T, 0>>(gcol, 64, 0, s, ps)));
-  FDE_TRY((launch<KRRBigSolve<T, 1>>(gcol, 64, 0, s, ps)));
+  FDE_TRY(launch<KRRCholInit<T>>(dim3((unsigned)(((size_t)mmax * mmax + 1023) / 1024), ps.n), kBlock, 0, s, ps));
+  for (int j0 = 0; j0 < mmax; j0 += kCholB) {
+    FDE_TRY(launch<KRRCholDiag<T>>(dim3(ps.n), 64, red, s, ps, j0));
+    const int rows = mmax - j0 - kCholB;
+    if (rows <= 0) continue;
+    FDE_TRY(launch<KRRCholPanel<T>>(dim3((rows + 63) / 64, ps.n), 64, (size_t)kCholB * kCholB * sizeof(cplx<double>),
+                                    s, ps, j0));
+    const int ntile = (rows + 31) / 32;
+    FDE_TRY(launch<KRRCholUpdate<T>>(dim3(ntile * (ntile + 1) / 2, ps.n), kBlock,
+                                     2 * 32 * kCholB * sizeof(cplx<double>), s, ps, j0));
+  }
+  using S0 = KRRBigTrsm<T, 0>;
+  const dim3 gstrip((mmax + S0::CB - 1) / S0::CB, ps.n), gcstrip((nbmax + S0::CB - 1) / S0::CB, ps.n);
+  FDE_TRY((launch<KRRBigTrsm<T, 0>>(gstrip, S0::RB * S0::CB, S0::lds_bytes(mmax), s, ps)));
+  FDE_TRY((launch<KRRBigTrsm<T, 1>>(gstrip, S0::RB * S0::CB, S0::lds_bytes(mmax), s, ps)));
   FDE_TRY(launch<KRRBigPrep<T>>(dim3(ps.n), kBlock, red, s, ps));
   for (int k = 0; k + 1 < mmax; ++k) {
     // the trailing block shrinks with k: rows k + 1 .. ma - 1 in blocks of kHhRows
@@ -104,8 +115,12 @@ static fde_status rr_split(ProbSet<T>& ps, int mmax, int nbmax, hipStream_t s) {
     FDE_TRY(launch<KRRBigHhU<T>>(g, kBlock, red, s, ps, k));
   }
   FDE_TRY((launch<KRRBigTri<T>, TT>(dim3(ps.n), TT, KRRSolveTriG<T>::lds_bytes(mmax), s, ps)));
+  // the large clusters' vectors: at most nbmax per problem, four per workgroup
+  FDE_TRY(launch<KRRBigInv<T>>(dim3((nbmax + KRRBigInv<T>::kVec - 1) / KRRBigInv<T>::kVec, ps.n), kBlock,
+                               KRRBigInv<T>::lds_bytes(mmax), s, ps, mmax));
+  FDE_TRY((launch<KRRBigOrth<T>, 1024>(dim3(ps.n), 1024, (32 + (size_t)mmax) * sizeof(double), s, ps)));
   FDE_TRY(launch<KRRBigBack<T>>(dim3((nbmax + 3) / 4, ps.n), kBlock, 0, s, ps));
-  FDE_TRY((launch<KRRBigC<T>>(dim3((nbmax + 63) / 64, ps.n), 64, 0, s, ps)));
+  FDE_TRY((launch<KRRBigTrsm<T, 2>>(gcstrip, S0::RB * S0::CB, S0::lds_bytes(mmax), s, ps)));
   return FDE_OK;
 }
 
