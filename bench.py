@@ -266,71 +266,62 @@ def network_params(be):
     return torch.from_numpy(np.load(f).astype(np.float32)).to(be.device)
 
 
-def time_to_accuracy(be, max_scf=150, n_iter=60):
-    """Band solver at a fixed self-consistent potential of the slab + molecule cell:
-    the FP64 cycle (Pulay + Kerker) is iterated until the density residual is below
-    1e-4 electrons; at that V_eff the slab's bands at the first k-point are solved from
-    the same seeded start with FP64 + TPA, FP32 + TPA and FP32 + the learned
-    preconditioner. Iterations until every occupied Ritz value is within 1e-6 Ha of the
-    FP64 solution after n_iter iterations, and the wall time of those iterations
-    (measured time per iteration x iterations)."""
+def time_to_accuracy(be, max_cycles=150):
+    """Time to 1e-6 Ha on the two-subsystem cube: the embedding cycle from the seeded start
+    with FP64 + TPA, FP32 + TPA and FP32 + the learned preconditioner, each run until every
+    occupied eigenvalue is within 1e-6 Ha of the converged FP64 cycle (density residual
+    below 1e-11 electrons) and every int |rho_I - rho_I^ref| <= 1e-5. Seconds are the summed
+    per-cycle times (each cycle synchronised; the host-side checks between cycles are not
+    counted); every variant first runs two cycles on a throwaway engine so that no kernel's
+    first-use set-up is timed."""
     import numpy as np
     import torch
     import fde_synth
     from paper_1406_7803_amd import driver, fde
-    s = fde_synth.config2()
+    s = fde_synth.config1()
     dv = float(np.prod(s.L)) / float(np.prod(s.grid))
-    mixer = dict(kind="pulay", nhist=8, beta=0.5, q0=0.8)
-    eng = driver.Engine(s, prec=fde.F64, backend=be, mixer=mixer)
-    scf_cycles, resid = 0, None
-    for c in range(max_scf):
-        rin = eng.rho_in.clone()
-        eng.cycle()
-        resid = float((eng.rho_out - rin).abs().sum()) * dv
-        scf_cycles = c + 1
-        if resid < 1e-4:
-            break
-    b = eng.blocks[0][0]
-    veff64 = eng.veff[0].clone()
-    occ = (eng.occw[0][b.j] > 1e-8).cpu().numpy()
-    raw = fde_synth.random_coefficients(5, 0, 0, b.ik, b.nb, eng.plan.npw(b.ik))
-    beta64, dkb = b.beta.clone(), b.dkb.clone()
-    del eng
-    torch.cuda.empty_cache()
-    out = {"system": "slab + molecule cell, slab bands at k = (1/4, 1/4, 0), fixed V_eff",
-           "scf": {"cycles": scf_cycles, "density_residual": resid, "mixing": mixer}}
+    ref = driver.Engine(s, prec=fde.F64, backend=be, streams=1)
+    ref_cycles, ref_res = driver.converge(ref, 1e-11, 600)
+    eps_ref = [e.cpu().numpy().copy() for e in ref.eps]
+    occ = [(o > 1e-8).cpu().numpy() for o in ref.occw]
+    rho_ref = ref.rho_out.double().cpu().numpy()
+    del ref
+    out = {"system": "two-subsystem cube 10 bohr, 24^3 grid, Ecut 7 Ha, 2 x 2 bands, Gamma; linear mixing 0.3, "
+                     "4 Davidson iterations per cycle",
+           "reference": {"prec": "fp64", "cycles": ref_cycles, "density_residual": ref_res}}
     params = network_params(be)
-    runs = {}
     for name, prec, mlp in (("fp64_tpa", fde.F64, False), ("fp32_tpa", fde.F32, False),
                             ("fp32_mlp", fde.F32, True)):
         if mlp and params is None:
+            out[name] = "not run: tests/golden/mlp_params.npy absent"
             continue
-        plan = fde.Plan(s.L, s.grid, s.ecut, s.all_kfrac, prec=prec, max_nb=b.nb, max_nproj=beta64.shape[0],
-                        backend=be)
-        X0 = plan.init_bands(b.ik, torch.from_numpy(raw).to(dtype=plan.cdtype, device=be.device))
-        v = veff64.to(plan.rdtype)
-        beta = beta64.to(plan.cdtype)
-        driver.davidson_fixed(plan, b.ik, X0, v, 2, beta=beta, dkb=dkb, mlp_params=params if mlp else None)
+        kw = dict(prec=prec, backend=be, streams=1, mlp_params=params if mlp else None)
+        warm = driver.Engine(s, **kw)
+        warm.cycle()
+        warm.cycle()
+        del warm
+        eng = driver.Engine(s, **kw)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        hist, info = driver.davidson_fixed(plan, b.ik, X0, v, n_iter, beta=beta, dkb=dkb,
-                                           mlp_params=params if mlp else None)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        runs[name] = ([h.cpu().numpy() for h in hist], wall / n_iter, int(info.item()))
-        del plan
-    ref = runs["fp64_tpa"][0][-1]
-    for name, (hist, per_it, info) in runs.items():
-        it = next((i + 1 for i, ev in enumerate(hist) if np.max(np.abs(ev[occ] - ref[occ])) <= 1e-6), None)
-        out[name] = {"iterations": it, "seconds": None if it is None else it * per_it,
-                     "ms_per_iteration": per_it * 1e3, "info": info,
-                     "final_max_deps_occ_Ha": float(np.max(np.abs(hist[-1][occ] - ref[occ])))}
-    if out.get("fp32_mlp", {}).get("seconds") and out["fp64_tpa"]["seconds"]:
-        out["speedup_fp64_tpa_over_fp32_mlp"] = out["fp64_tpa"]["seconds"] / out["fp32_mlp"]["seconds"]
-    if out.get("fp32_tpa", {}).get("seconds") and out["fp64_tpa"]["seconds"]:
-        out["speedup_fp64_tpa_over_fp32_tpa"] = out["fp64_tpa"]["seconds"] / out["fp32_tpa"]["seconds"]
-    if params is None:
-        out["fp32_mlp"] = "not run: tests/golden/mlp_params.npy absent"
+        t, reached, errs = 0.0, None, None
+        for c in range(max_cycles):
+            t0 = time.perf_counter()
+            eng.cycle()
+            torch.cuda.synchronize()
+            t += time.perf_counter() - t0
+            de = max(float(np.max(np.abs(e.cpu().numpy() - r)[o])) for e, r, o in zip(eng.eps, eps_ref, occ))
+            rho = eng.rho_out.double().cpu().numpy()
+            dr = max(float(np.sum(np.abs(rho[I] - rho_ref[I]))) * dv for I in range(len(s.subsystems)))
+            errs = (de, dr)
+            if de <= 1e-6 and dr <= 1e-5:
+                reached = c + 1
+                break
+        out[name] = {"cycles": reached, "seconds": t if reached else None, "ms_per_cycle": 1e3 * t / (c + 1),
+                     "final_max_deps_occ_Ha": errs[0], "final_max_int_drho": errs[1]}
+        del eng
+    for v in ("fp32_mlp", "fp32_tpa"):
+        a, b = out.get("fp64_tpa"), out.get(v)
+        if isinstance(a, dict) and isinstance(b, dict) and a["seconds"] and b["seconds"]:
+            out[f"speedup_fp64_tpa_over_{v}"] = a["seconds"] / b["seconds"]
     return out
 
 
@@ -342,11 +333,13 @@ def table1_analogue(be):
     import fde_synth
     from paper_1406_7803_amd import driver, fde
     s = fde_synth.config2()
-    out = {"system": "slab + molecule cell; xc PBE; interaction energies in Ha without the ion-ion term"}
+    mixer = dict(kind="pulay", nhist=8, beta=0.2, q0=0.8)
+    out = {"system": "slab + molecule cell; xc PBE; interaction energies in Ha without the ion-ion term",
+           "mixing": mixer, "tolerance_electrons": 1e-5}
     for name, kin in (("lc94", fde.KIN_LC94), ("revapbek", fde.KIN_REVAPBEK)):
         r = driver.supersystem_comparison(s, prec=fde.F64, backend=be,
                                           kinds=dict(xc=fde.XC_PBE, xc_nad=fde.XC_PBE, kin_nad=kin),
-                                          tol=1e-5, max_cycles=250)
+                                          tol=1e-5, max_cycles=500, mixer=mixer)
         out[name] = {k: r[k] for k in ("dens_diff", "int_KS", "int_FDE", "E_KS", "E_FDE", "cycles", "residuals")}
     return out
 

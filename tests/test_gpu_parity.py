@@ -416,6 +416,103 @@ def test_c3_cycle_properties(be):
         assert abs(q - sub.nelec) < 1e-3 * max(1.0, sub.nelec), (I, q, sub.nelec)
 
 
+# ---------------------------------------------------------------------------
+# Full-size large metal-surface cell (144 x 144 x 432, ~158 000 plane waves, 320 slab bands
+# with 576 s + p projectors, m = 640 in the Davidson step): the benchmark's workload.
+# ---------------------------------------------------------------------------
+def test_c4_apply_h_sampled(be):
+    """All 320 slab bands with their 576 projectors in one FP32 call (the benchmark's
+    launch configuration); three sampled bands against the oracle (FFT mode)."""
+    from oracle import basis, dft as odft, hamiltonian as oham, pseudo as opseudo
+    s = fde_synth.config4()
+    slab = s.subsystems[0]
+    cell = basis.Cell(s.L, s.grid)
+    odft.set_mode("fft", workers=16)
+    try:
+        sph = basis.sphere(cell, s.ecut, slab.kfrac[0])
+        atoms = [a for sub in s.subsystems for a in sub.atoms]
+        vloc = opseudo.local_potential(cell, s.ecut, atoms)
+        beta, dkb = opseudo.kb_projectors(cell, sph, slab.atoms)
+        plan = fde.Plan(s.L, s.grid, s.ecut, s.all_kfrac, prec=fde.F32, max_nb=320, max_nproj=576, backend=be)
+        assert plan.npw(0) == sph.npw and beta.shape[0] == 576
+        psi = fde_synth.random_complex(79, (320, sph.npw)) / (1 + 2 * sph.kin)[None]
+        tb = plan.kb_projectors(0, [a.pos for a in slab.atoms], [a.lmax for a in slab.atoms],
+                                [a.rbeta for a in slab.atoms])
+        out = plan.apply_h(0, pc.to_dev(plan, psi, "c"), pc.to_dev(plan, vloc, "r"), tb, pc.to_dev(plan, dkb, "d"))
+        be.sync()
+        sample = [0, 161, 319]
+        ref = oham.apply_h(cell, sph, psi[sample], vloc, beta, dkb)
+        got = pc.host(out)[sample]
+        assert pc.rel(got, ref) < pc.TOL[fde.F32], pc.rel(got, ref)
+    finally:
+        odft.set_mode("naive")
+
+
+def test_c4_cycle_properties(be):
+    """One FP32 cycle of the large cell: the slab's Rayleigh-Ritz steps run the split
+    multi-workgroup eigensolver (m = 320, then m = 640). Properties any correct step and
+    density satisfy, on the slab's two k-point blocks and one molecule: X orthonormal,
+    X^H (H X) diagonal with the Ritz values on it, H X equal to a fresh H application,
+    Ritz values ascending, every subsystem's charge equal to its electron count."""
+    from paper_1406_7803_amd import driver
+    s = fde_synth.config4()
+    eng = driver.Engine(s, prec=fde.F32, backend=be)
+    eng.cycle()
+    be.sync()
+    blocks = [b for row in eng.blocks for b in row]
+    assert all(int(pc.host(b.info)[0]) == 0 for b in blocks)
+    for b in eng.blocks[0] + [eng.blocks[1][0]]:
+        X = pc.host(b.V[:b.nb]).astype(np.complex128)
+        HX = pc.host(b.HV[:b.nb]).astype(np.complex128)
+        ev = pc.host(b.eval)
+        assert np.all(np.diff(ev) >= -1e-12), b.nb
+        G = X.conj() @ X.T
+        assert np.max(np.abs(G - np.eye(b.nb))) < 1e-4, (b.nb, np.max(np.abs(G - np.eye(b.nb))))
+        A = X.conj() @ HX.T
+        scale = max(1.0, float(np.max(np.abs(ev))))
+        assert np.max(np.abs(np.diag(A).real - ev)) < 1e-4 * scale, b.nb
+        assert np.max(np.abs(A - np.diag(np.diag(A)))) < 1e-4 * scale, b.nb
+        fresh = pc.host(eng.plan.apply_h(b.ik, b.V[:b.nb], eng.veff[b.isub], b.beta, b.dkb))
+        assert pc.rel(fresh.astype(np.complex128), HX) < 1e-4, b.nb
+    dv = float(np.prod(s.L)) / float(np.prod(s.grid))
+    for I, sub in enumerate(s.subsystems):
+        q = float(pc.host(eng.rho_out[I]).astype(np.float64).sum()) * dv
+        assert abs(q - sub.nelec) < 1e-3 * max(1.0, sub.nelec), (I, q, sub.nelec)
+
+
+def test_c2_fp32_against_fp64_schedule(be):
+    """The slab + molecule cell over its 10-cycle x 4-Davidson schedule: every cycle of the
+    FP64 trajectory is repeated by the FP32 plan from the same state (input densities and
+    bands copied from the FP64 engine), so each comparison measures one cycle's FP32
+    arithmetic. Occupied eigenvalues within 1e-6 max(1, |eps|max) Ha and int |d rho_I|
+    within 2.5e-6 N_I (the FP32 rounding of an H application, about 1e-7 relative, grown by
+    the eigenvalue scale and carried into the density). The free-running FP32 trajectory
+    drifts further, since a non-converged linear-mixing cycle amplifies any difference."""
+    from paper_1406_7803_amd import driver
+    s = fde_synth.config2()
+    e64 = driver.Engine(s, prec=fde.F64, backend=be)
+    e32 = driver.Engine(s, prec=fde.F32, backend=be)
+    dv = float(np.prod(s.L)) / float(np.prod(s.grid))
+    worst = (0.0, 0.0)
+    for c in range(s.n_cycles):
+        e32.rho_in.copy_(e64.rho_in)
+        for r64, r32 in zip(e64.blocks, e32.blocks):
+            for b64, b32 in zip(r64, r32):
+                b32.V[:b32.nb].copy_(b64.V[:b64.nb])
+        e64.cycle()
+        e32.cycle()
+        be.sync()
+        for I, sub in enumerate(s.subsystems):
+            ref = pc.host(e64.eps[I])
+            occ = pc.host(e64.occw[I]) > 1e-8
+            de = float(np.max(np.abs(pc.host(e32.eps[I]) - ref)[occ]))
+            dr = float(np.sum(np.abs(pc.host(e32.rho_out[I]).astype(np.float64) - pc.host(e64.rho_out[I])))) * dv
+            assert de < 1e-6 * max(1.0, float(np.max(np.abs(ref[occ])))), (c, I, de)
+            assert dr < 2.5e-6 * sub.nelec, (c, I, dr)
+            worst = (max(worst[0], de), max(worst[1], dr / sub.nelec))
+    print("worst one-cycle FP32 vs FP64 (Ha, per electron):", worst)
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_frozen_environment(be, prec):
     pc.check_frozen_environment(be, prec)
