@@ -502,10 +502,11 @@ struct KKbReduce {
 };
 
 // hpsi[n][G] += sum_i beta_i(G) dp[i][n]. grid ceil(npw / 64), 256 threads.
-// Per block: a tile of 64 plane waves; projectors in chunks of PC staged in
-// LDS (beta read from HBM once per chunk), bands in chunks of 64 (dp staged in
-// LDS); a thread item is a quarter of the band chunk at one G (lanes run along
-// G), with its 16 sums in registers.
+// Per block: a tile of 64 plane waves; bands in chunks of 64, each chunk's sums over
+// all projectors kept in registers so that every hpsi element is read and written
+// once; projectors in chunks of PC, beta and dp staged in LDS per chunk. A thread
+// item is a quarter of the band chunk at one G (lanes run along G), with its 16
+// sums in registers.
 template <typename T>
 struct KKbAdd {
   static constexpr int TG = 64, PC = sizeof(T) == 4 ? 40 : 20, NBC = 64, NQ = NBC / 4;
@@ -516,35 +517,39 @@ struct KKbAdd {
     cplx<T>* sB = (cplx<T>*)lds;   // [PC][TG]
     cplx<T>* sD = sB + PC * TG;    // [PC][NBC]
     const int g0 = c.bx() * TG;
-    for (int i0 = 0; i0 < nproj; i0 += PC) {
-      const int np = (nproj - i0) < PC ? (nproj - i0) : PC;
-      c.sync();
-      for (int idx = c.tid(); idx < np * TG; idx += c.nthr()) {
-        const int i = idx / TG, g = idx - i * TG;
-        sB[idx] = (g0 + g < npw) ? beta[(size_t)(i0 + i) * npw + g0 + g] : mk<T>(0, 0);
-      }
-      for (int n0 = 0; n0 < nb; n0 += NBC) {
-        const int nbc = (nb - n0) < NBC ? (nb - n0) : NBC;
-        c.sync();
-        for (int idx = c.tid(); idx < np * nbc; idx += c.nthr()) {
-          const int i = idx / nbc, q = idx - i * nbc;
-          sD[i * NBC + q] = dp[(size_t)(i0 + i) * nb + n0 + q];
-        }
-        c.sync();
-        // item (quarter w of the band chunk, G): NQ accumulators, beta_i(G) read once per i
-        for (int idx = c.tid(); idx < 4 * TG; idx += c.nthr()) {
-          const int w = idx / TG, g = idx - w * TG;
-          const int qa = w * NQ, qn = (nbc - qa) < NQ ? (nbc - qa) : NQ;
-          if (g0 + g >= npw || qn <= 0) continue;
-          cplx<T> acc[NQ];  // compile-time indices only: stays in registers
+    // the thread items of one pass; the host runs them one after another
+    constexpr int kItems = 4 * TG;
+    for (int n0 = 0; n0 < nb; n0 += NBC) {
+      const int nbc = (nb - n0) < NBC ? (nb - n0) : NBC;
+      for (int it0 = 0; it0 < kItems; it0 += c.nthr()) {
+        const int idx = it0 + c.tid();
+        const int w = idx / TG, g = idx - w * TG;
+        const int qa = w * NQ, qn = (nbc - qa) < NQ ? (nbc - qa) : NQ;
+        const bool live = idx < kItems && g0 + g < npw && qn > 0;
+        cplx<T> acc[NQ];  // compile-time indices only: stays in registers
 #pragma unroll
-          for (int q = 0; q < NQ; ++q) acc[q] = mk<T>(0, 0);
-          for (int i = 0; i < np; ++i) {
-            const cplx<T> b = sB[i * TG + g];
-            const cplx<T>* d = sD + i * NBC + qa;
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) acc[q] = acc[q] + b * d[q];
+        for (int q = 0; q < NQ; ++q) acc[q] = mk<T>(0, 0);
+        for (int i0 = 0; i0 < nproj; i0 += PC) {
+          const int np = (nproj - i0) < PC ? (nproj - i0) : PC;
+          c.sync();
+          for (int e = c.tid(); e < np * TG; e += c.nthr()) {
+            const int i = e / TG, gg = e - i * TG;
+            sB[e] = (g0 + gg < npw) ? beta[(size_t)(i0 + i) * npw + g0 + gg] : mk<T>(0, 0);
           }
+          for (int e = c.tid(); e < np * nbc; e += c.nthr()) {
+            const int i = e / nbc, q = e - i * nbc;
+            sD[i * NBC + q] = dp[(size_t)(i0 + i) * nb + n0 + q];
+          }
+          c.sync();
+          if (live)
+            for (int i = 0; i < np; ++i) {
+              const cplx<T> b = sB[i * TG + g];
+              const cplx<T>* d = sD + i * NBC + qa;
+#pragma unroll
+              for (int q = 0; q < NQ; ++q) acc[q] = acc[q] + b * d[q];
+            }
+        }
+        if (live) {
 #pragma unroll
           for (int q = 0; q < NQ; ++q) {
             if (q < qn) {

@@ -1105,6 +1105,101 @@ struct KRRSolveTri {
     }
   }
 
+  // The same orthonormalisation by blocks of kOrthBlock vectors (block classical Gram-Schmidt,
+  // applied twice): a block, staged in LDS (YB, kOrthBlock x ma), is projected against all
+  // earlier vectors of the cluster at once (projections in D, [nq][kOrthBlock]), each
+  // earlier vector read once per block; then its vectors are orthonormalised among
+  // themselves in order (a projection repeated once when it removed more than three
+  // quarters of the squared norm); then both steps once more. red: 32 doubles of LDS.
+  static constexpr int kOrthBlock = 8;
+  template <class Ctx>
+  FDE_HD static void cluster_orth_block(const Ctx& c, double* Y, int ma, int j0, int j1, double* YB, double* D,
+                                        double* red) {
+    constexpr int QB = kOrthBlock;
+    const int tid = c.tid(), nt = c.nthr();
+    const int lane = c.lane(), wl = c.wlanes(), wv = c.wave(), nwv = c.nwave();
+    double* d2 = red + 20;  // projections on the block's earlier vectors (< QB)
+    for (int b0 = j0; b0 < j1; b0 += QB) {
+      const int nbk = j1 - b0 < QB ? j1 - b0 : QB;
+      for (int e = tid; e < QB * ma; e += nt) {
+        const int r = e / ma, i = e - r * ma;
+        YB[e] = r < nbk ? Y[(size_t)(b0 + r) * ma + i] : 0.0;
+      }
+      c.sync();
+      for (int pass = 0; pass < 2; ++pass) {
+        const int nq = b0 - j0;
+        if (nq > 0) {
+          for (int q = wv; q < nq; q += nwv) {
+            const double* yq = Y + (size_t)(j0 + q) * ma;
+            double sq[QB];
+#pragma unroll
+            for (int r = 0; r < QB; ++r) sq[r] = 0.0;
+            for (int i = lane; i < ma; i += wl) {
+              const double v = yq[i];
+#pragma unroll
+              for (int r = 0; r < QB; ++r) sq[r] += v * YB[r * ma + i];
+            }
+#pragma unroll
+            for (int r = 0; r < QB; ++r) {
+              const double t = c.template gsum<64>(sq[r]);
+              if (lane == 0) D[q * QB + r] = t;
+            }
+          }
+          c.sync();
+          for (int i = tid; i < ma; i += nt) {
+            double acc[QB];
+#pragma unroll
+            for (int r = 0; r < QB; ++r) acc[r] = 0.0;
+            for (int q = 0; q < nq; ++q) {
+              const double v = Y[(size_t)(j0 + q) * ma + i];
+#pragma unroll
+              for (int r = 0; r < QB; ++r) acc[r] += D[q * QB + r] * v;
+            }
+#pragma unroll
+            for (int r = 0; r < QB; ++r) YB[r * ma + i] -= acc[r];
+          }
+          c.sync();
+        }
+        for (int r = 0; r < nbk; ++r) {
+          double* y = YB + r * ma;
+          double n0 = 0.0;
+          for (int i = tid; i < ma; i += nt) n0 += y[i] * y[i];
+          n0 = c.sum(n0, red);
+          double nr = n0;
+          for (int rep = 0; rep < 2 && r > 0; ++rep) {
+            for (int rp = wv; rp < r; rp += nwv) {
+              double t = 0.0;
+              for (int i = lane; i < ma; i += wl) t += YB[rp * ma + i] * y[i];
+              t = c.template gsum<64>(t);
+              if (lane == 0) d2[rp] = t;
+            }
+            c.sync();
+            double part = 0.0;
+            for (int i = tid; i < ma; i += nt) {
+              double v = y[i];
+              for (int rp = 0; rp < r; ++rp) v -= d2[rp] * YB[rp * ma + i];
+              y[i] = v;
+              part += v * v;
+            }
+            const double n1 = c.sum(part, red);
+            const bool again = !(n1 >= 0.25 * nr);
+            nr = n1;
+            if (!again) break;
+          }
+          if (nr > 0.0) {
+            const double sc = 1.0 / sqrt(nr);
+            for (int i = tid; i < ma; i += nt) y[i] *= sc;
+          } else {
+            for (int i = tid; i < ma; i += nt) y[i] = i == (b0 + r) % ma ? 1.0 : 0.0;
+          }
+          c.sync();
+        }
+      }
+      for (int e = tid; e < nbk * ma; e += nt) Y[(size_t)b0 * ma + e] = YB[e];
+      c.sync();
+    }
+  }
+
   // Steps 3b-3e on the reduced active block (ma rows; dg, beta and alpha from the reduction):
   // eigenvalues and eigenvectors of the lowest nb, W^T rows n < nb with physical row indices,
   // masked rows zero, masked eigenpairs after the active ones. ZMAX bounds m.
@@ -1676,10 +1771,10 @@ struct KRRSolveTriG {
 //   KRRChol*      blocked Cholesky with dropping (below);
 //   KRRBigTrsm    B = L^{-1} A, A~ = L^{-1} B^H and, at the end, C = L^{-H} W, by column strips;
 //   KRRBigPrep    the active indices, (A~ + A~^H)/2 on them into W, the first reflector;
-//   KRRBigHhP(k)  p = beta_k G' v_k, rows of the trailing block over many workgroups;
-//   KRRBigHhU(k)  the rank-2 update G' -= v w^H + w v^H (w = p - K v, K = beta/2 v^H p, summed
-//                 by every workgroup in the same order), rows over many workgroups; the
-//                 workgroup owning row k + 1 then forms reflector k + 1 from it;
+//   KRRBigHhP(0)  p_0 = beta_0 G' v_0, rows of the trailing block over many workgroups;
+//   KRRBigHh(k)   one launch per Householder column: the rank-2 update G' -= v w^H + w v^H
+//                 (w = p - K v, K = beta/2 v^H p) on rows over many workgroups, reflector
+//                 k + 1 formed by every workgroup from the updated row k + 1, and p_{k+1};
 //   KRRBigTri     real tridiagonal, multisection, twisted factorisations of isolated eigenvalues
 //                 and the shifts of the rest (one workgroup per problem);
 //   KRRBigInv     inverse iteration of the clustered eigenvalues' vectors, one per wavefront;
@@ -1690,7 +1785,7 @@ struct KRRSolveTriG {
 // ---------------------------------------------------------------------------
 struct BigWs {
   cplx<double>* v[2];  // reflector v_k, double-buffered by k parity
-  cplx<double>* p;     // beta_k G' v_k
+  cplx<double>* pp[2];  // beta_k G' v_k, double-buffered by k parity
   double *dg, *beta, *ar, *ai, *dre, *dim, *ea, *shift, *sdiag, *tnorm;
   int *act, *nact;     // active indices and their count
   int *cls, *ncl;      // cluster starts (ncl + 1) and the cluster count
@@ -1701,18 +1796,20 @@ struct BigWs {
     const size_t m = (size_t)a.m;
     v[0] = (cplx<double>*)b;
     v[1] = (cplx<double>*)(b + 2 * m);
-    p = (cplx<double>*)(b + 4 * m);
-    dg = b + 6 * m;
-    beta = b + 7 * m;
-    ar = b + 8 * m;
-    ai = b + 9 * m;
-    dre = b + 10 * m;
-    dim = b + 11 * m;
-    ea = b + 12 * m;
-    shift = b + 13 * m;
-    sdiag = b + 14 * m;
-    tnorm = b + 15 * m;
-    act = (int*)(b + 15 * m + 2);
+    pp[0] = (cplx<double>*)(b + 4 * m);
+    pp[1] = (cplx<double>*)(b + 6 * m);
+    double* q = b + 8 * m;
+    dg = q;
+    beta = q + m;
+    ar = q + 2 * m;
+    ai = q + 3 * m;
+    dre = q + 4 * m;
+    dim = q + 5 * m;
+    ea = q + 6 * m;
+    shift = q + 7 * m;
+    sdiag = q + 8 * m;
+    tnorm = q + 9 * m;
+    act = (int*)(q + 9 * m + 2);
     nact = act + m;
     cls = nact + 1;
     ncl = cls + m + 1;
@@ -2016,13 +2113,20 @@ struct KRRBigHhP {
       }
       sx = c.template gsum<GL>(sx);
       sy = c.template gsum<GL>(sy);
-      if (gl == 0) w.p[r] = mk<double>(bt * sx, bt * sy);
+      if (gl == 0) w.pp[k & 1][r] = mk<double>(bt * sx, bt * sy);
     }
   }
 };
 
+// One Householder column k as one launch: with v_k, beta_k and p_k = beta_k G' v_k from the
+// previous launch, every workgroup forms K = beta_k/2 v_k^H p_k and w = p_k - K v_k, the
+// updated row k + 1 (in LDS; that row is read by all and written by none), and from it
+// reflector k + 1 (all identically; workgroup 0 stores it, with the diagonal). Then it
+// applies the rank-2 update to its own rows below row k + 1 and, in the same pass, forms
+// their entries of p_{k+1} = beta_{k+1} G'' v_{k+1}. grid (max(1, ceil((m - k - 2) / 16)), n),
+// 256 threads (16 rows of 16 lanes).
 template <typename T>
-struct KRRBigHhU {
+struct KRRBigHh {
   template <class Ctx>
   FDE_HD static void run(const Ctx& c, char* lds, const ProbSet<T> ps, int k) {
     const Prob<T>& a = ps.p[c.by()];
@@ -2032,33 +2136,99 @@ struct KRRBigHhU {
     if (!(k + 1 < ma)) return;
     const int n1 = ma - k - 1, m = a.m;
     const int tid = c.tid(), nt = c.nthr();
+#if defined(__HIP_DEVICE_COMPILE__)
+    constexpr int GL = 16;
+#else
+    constexpr int GL = 1;
+#endif
+    const int gl = tid % GL, grp = tid / GL, ng = nt / GL;
     double* red = (double*)lds;
+    cplx<double>* row = (cplx<double>*)(red + 32);  // updated row k + 1, trailing columns [n1]
+    cplx<double>* vn = row + n1;                    // v_{k+1} [n1 - 1]
     cplx<double>* G = a.W;
     const cplx<double>* v = w.v[k & 1];
+    const cplx<double>* p = w.pp[k & 1];
     const double bt = w.beta[k];
+    double kk = 0.0;
     if (bt != 0.0) {  // uniform per problem
-      // K = beta/2 v^H p, summed in the same order by every workgroup
-      double kk = 0.0;
-      for (int r = tid; r < n1; r += nt) kk += v[r].x * w.p[r].x + v[r].y * w.p[r].y;
+      for (int r = tid; r < n1; r += nt) kk += v[r].x * p[r].x + v[r].y * p[r].y;
       kk = 0.5 * bt * c.sum(kk, red);
-      for (int e = tid; e < kHhRows * n1; e += nt) {
-        const int rl = e / n1, j = e - rl * n1;
-        const int r = c.bx() * kHhRows + rl;
-        if (r >= n1) break;
-        const cplx<double> vj = v[j], vr = v[r], pj = w.p[j], pr = w.p[r];
-        const double wjx = pj.x - kk * vj.x, wjy = pj.y - kk * vj.y;
-        const double wrx = pr.x - kk * vr.x, wry = pr.y - kk * vr.y;
-        cplx<double>& t = G[(size_t)(k + 1 + r) * ma + k + 1 + j];
-        t.x -= (vr.x * wjx + vr.y * wjy) + (wrx * vj.x + wry * vj.y);
-        t.y -= (vr.y * wjx - vr.x * wjy) + (wry * vj.x - wrx * vj.y);
+    }
+    // updated row k + 1: t_j - (v_0 conj(w_j) + w_0 conj(v_j))
+    const cplx<double>* g1 = G + (size_t)(k + 1) * ma + k + 1;
+    {
+      const cplx<double> v0 = v[0];
+      const double w0x = p[0].x - kk * v0.x, w0y = p[0].y - kk * v0.y;
+      for (int j = tid; j < n1; j += nt) {
+        cplx<double> t = g1[j];
+        if (bt != 0.0) {
+          const cplx<double> vj = v[j];
+          const double wjx = p[j].x - kk * vj.x, wjy = p[j].y - kk * vj.y;
+          t.x -= (v0.x * wjx + v0.y * wjy) + (w0x * vj.x + w0y * vj.y);
+          t.y -= (v0.y * wjx - v0.x * wjy) + (w0y * vj.x - w0x * vj.y);
+        }
+        row[j] = t;
       }
     }
-    if (c.bx() != 0) return;
-    c.sync();  // row k + 1 (trailing row 0) is updated by this workgroup
-    if (k + 2 < ma)
-      big_reflector(c, red, G, ma, k + 1, big_reflectors(a.S, m), w.v[(k + 1) & 1], w);
-    else if (tid == 0)
-      w.dg[ma - 1] = G[(size_t)(ma - 1) * ma + ma - 1].x;
+    c.sync();
+    // reflector k + 1 from the row (x_r = conj(row[1 + r])), as big_reflector does
+    const int n2 = n1 - 1;
+    double bt1 = 0.0;
+    if (n2 >= 1) {
+      double s2 = 0.0;
+      for (int r = tid; r < n2; r += nt) s2 += norm2(row[1 + r]);
+      s2 = c.sum(s2, red);
+      const cplx<double> x0 = conj(row[1]);
+      cplx<double> alpha = x0, v0 = x0;
+      if (n2 > 1 && s2 > norm2(x0)) {
+        const double ax0 = sqrt(norm2(x0)), sg = sqrt(s2);
+        const cplx<double> ph = ax0 > 0.0 ? mk<double>(x0.x / ax0, x0.y / ax0) : mk<double>(1.0, 0.0);
+        alpha = mk<double>(-ph.x * sg, -ph.y * sg);
+        v0 = mk<double>(x0.x + ph.x * sg, x0.y + ph.y * sg);
+        bt1 = 1.0 / (sg * (sg + ax0));
+      }
+      cplx<double>* vk = big_reflectors(a.S, m) + KRRSolveTri<double>::voff(k + 1, ma);
+      for (int r = tid; r < n2; r += nt) {
+        const cplx<double> vr = r == 0 ? v0 : conj(row[1 + r]);
+        vn[r] = vr;
+        if (c.bx() == 0) {
+          w.v[(k + 1) & 1][r] = vr;
+          vk[r] = vr;
+        }
+      }
+      if (c.bx() == 0 && tid == 0) {
+        w.beta[k + 1] = bt1;
+        w.ar[k + 1] = alpha.x;
+        w.ai[k + 1] = alpha.y;
+      }
+    }
+    if (c.bx() == 0 && tid == 0) w.dg[k + 1] = row[0].x;
+    c.sync();
+    // own rows k + 2 + r (r < n2): rank-2 update of columns k + 2 .. ma - 1, and p_{k+1}
+    for (int rl = grp; rl < kHhRows; rl += ng) {
+      const int r = c.bx() * kHhRows + rl;
+      if (r >= n2) break;  // uniform per lane group
+      cplx<double>* g = G + (size_t)(k + 2 + r) * ma + k + 2;
+      const cplx<double> vr = v[1 + r];
+      const double wrx = p[1 + r].x - kk * vr.x, wry = p[1 + r].y - kk * vr.y;
+      double sx = 0.0, sy = 0.0;
+      for (int j = gl; j < n2; j += GL) {
+        cplx<double> t = g[j];
+        if (bt != 0.0) {
+          const cplx<double> vj = v[1 + j];
+          const double wjx = p[1 + j].x - kk * vj.x, wjy = p[1 + j].y - kk * vj.y;
+          t.x -= (vr.x * wjx + vr.y * wjy) + (wrx * vj.x + wry * vj.y);
+          t.y -= (vr.y * wjx - vr.x * wjy) + (wry * vj.x - wrx * vj.y);
+          g[j] = t;
+        }
+        const cplx<double> u = vn[j];
+        sx += t.x * u.x - t.y * u.y;
+        sy += t.x * u.y + t.y * u.x;
+      }
+      sx = c.template gsum<GL>(sx);
+      sy = c.template gsum<GL>(sy);
+      if (gl == 0) w.pp[(k + 1) & 1][r] = mk<double>(bt1 * sx, bt1 * sy);
+    }
   }
 };
 
@@ -2184,7 +2354,8 @@ struct KRRBigInv {
   }
 };
 
-// Orthonormalisation of every cluster (one workgroup per problem).
+// Orthonormalisation of every cluster (one workgroup per problem, block Gram-Schmidt).
+// LDS: 32 + 2 kOrthBlock mmax doubles.
 template <typename T>
 struct KRRBigOrth {
   template <class Ctx>
@@ -2195,10 +2366,11 @@ struct KRRBigOrth {
     if (w.nbig[0] == 0) return;
     const int ma = w.nact[0], ncl = w.ncl[0];
     double* red = (double*)lds;
-    double* dq = red + 32;
+    double* YB = red + 32;                                   // [kOrthBlock][ma]
+    double* D = YB + (size_t)KRRSolveTri<T>::kOrthBlock * ma;  // [ma][kOrthBlock]
     for (int ci = 0; ci < ncl; ++ci) {
       const int j0 = w.cls[ci], j1 = w.cls[ci + 1];
-      if (j1 - j0 > 1) KRRSolveTri<T>::cluster_orth(c, (double*)a.S, ma, j0, j1, dq, red);
+      if (j1 - j0 > 1) KRRSolveTri<T>::cluster_orth_block(c, (double*)a.S, ma, j0, j1, YB, D, red);
     }
   }
 };
@@ -2240,7 +2412,7 @@ struct KRRBigBack {
 template <typename T, int MODE>
 struct KRRBigTrsm {
   static constexpr int RB = 32, CB = 8;
-  FDE_HD static size_t lds_bytes(int m) { return (size_t)m * CB * sizeof(cplx<double>); }
+  FDE_HD static size_t lds_bytes(int m) { return ((size_t)m * CB + RB * RB) * sizeof(cplx<double>); }
   template <class Ctx>
   FDE_HD static void run(const Ctx& c, char* lds, const ProbSet<T> ps) {
     const Prob<T>& a = ps.p[c.by()];
@@ -2253,6 +2425,7 @@ struct KRRBigTrsm {
     constexpr bool up = MODE == 2;
     const cplx<double>* L = a.L;
     cplx<double>* X = (cplx<double>*)lds;  // [m][CB]
+    cplx<double>* Ld = X + (size_t)m * CB;  // the block's own factors [RB][RB] (diagonal: real)
     for (int e = tid; e < m * CB; e += nt) {
       const int i = e / CB, q = e - i * CB, col = c0 + q;
       cplx<double> v = mk<double>(0.0, 0.0);
@@ -2287,6 +2460,12 @@ struct KRRBigTrsm {
         X[i * CB + q].x -= ax;
         X[i * CB + q].y -= ay;
       }
+      for (int e = tid; e < nr * nr; e += nt) {
+        const int r = e / nr, p = e - r * nr;
+        if (p > r) continue;
+        const int i = row(b0 + r);
+        Ld[r * RB + p] = p < r ? lf(i, row(b0 + p)) : mk<double>(L[(size_t)i * m + i].x, 0.0);
+      }
       c.sync();
       for (int q = tid; q < CB; q += nt) {
         for (int r = 0; r < nr; ++r) {
@@ -2294,11 +2473,11 @@ struct KRRBigTrsm {
           double sx = X[i * CB + q].x, sy = X[i * CB + q].y;
           for (int p = 0; p < r; ++p) {
             const int k = row(b0 + p);
-            const cplx<double> l = lf(i, k), xk = X[k * CB + q];
+            const cplx<double> l = Ld[r * RB + p], xk = X[k * CB + q];
             sx -= l.x * xk.x - l.y * xk.y;
             sy -= l.x * xk.y + l.y * xk.x;
           }
-          X[i * CB + q] = cdiv_real(mk<double>(sx, sy), L[(size_t)i * m + i].x);
+          X[i * CB + q] = cdiv_real(mk<double>(sx, sy), Ld[r * RB + r].x);
         }
       }
       c.sync();

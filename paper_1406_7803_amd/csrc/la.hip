@@ -108,17 +108,19 @@ static fde_status rr_split(ProbSet<T>& ps, int mmax, int nbmax, hipStream_t s) {
   FDE_TRY((launch<KRRBigTrsm<T, 0>>(gstrip, S0::RB * S0::CB, S0::lds_bytes(mmax), s, ps)));
   FDE_TRY((launch<KRRBigTrsm<T, 1>>(gstrip, S0::RB * S0::CB, S0::lds_bytes(mmax), s, ps)));
   FDE_TRY(launch<KRRBigPrep<T>>(dim3(ps.n), kBlock, red, s, ps));
+  // p_0, then one launch per column: the update and the next reflector and p
+  FDE_TRY(launch<KRRBigHhP<T>>(dim3((mmax + kHhRows - 1) / kHhRows, ps.n), kHhRows * 16, 0, s, ps, 0));
+  const size_t hlds = 32 * sizeof(double) + 2 * (size_t)mmax * sizeof(cplx<double>);
   for (int k = 0; k + 1 < mmax; ++k) {
-    // the trailing block shrinks with k: rows k + 1 .. ma - 1 in blocks of kHhRows
-    const dim3 g((mmax - k - 1 + kHhRows - 1) / kHhRows, ps.n);
-    FDE_TRY(launch<KRRBigHhP<T>>(g, kHhRows * 16, 0, s, ps, k));
-    FDE_TRY(launch<KRRBigHhU<T>>(g, kBlock, red, s, ps, k));
+    const dim3 g((unsigned)std::max(1, (mmax - k - 2 + kHhRows - 1) / kHhRows), ps.n);
+    FDE_TRY(launch<KRRBigHh<T>>(g, kHhRows * 16, hlds, s, ps, k));
   }
   FDE_TRY((launch<KRRBigTri<T>, TT>(dim3(ps.n), TT, KRRSolveTriG<T>::lds_bytes(mmax), s, ps)));
   // the large clusters' vectors: at most nbmax per problem, four per workgroup
   FDE_TRY(launch<KRRBigInv<T>>(dim3((nbmax + KRRBigInv<T>::kVec - 1) / KRRBigInv<T>::kVec, ps.n), kBlock,
                                KRRBigInv<T>::lds_bytes(mmax), s, ps, mmax));
-  FDE_TRY((launch<KRRBigOrth<T>, 1024>(dim3(ps.n), 1024, (32 + (size_t)mmax) * sizeof(double), s, ps)));
+  FDE_TRY((launch<KRRBigOrth<T>, 1024>(dim3(ps.n), 1024,
+                                       (32 + 2 * (size_t)KRRSolveTri<T>::kOrthBlock * mmax) * sizeof(double), s, ps)));
   FDE_TRY(launch<KRRBigBack<T>>(dim3((nbmax + 3) / 4, ps.n), kBlock, 0, s, ps));
   FDE_TRY((launch<KRRBigTrsm<T, 2>>(gcstrip, S0::RB * S0::CB, S0::lds_bytes(mmax), s, ps)));
   return FDE_OK;

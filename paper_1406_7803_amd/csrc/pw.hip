@@ -137,11 +137,22 @@ static int plane_kind(const fde_plan* p, int ik, bool reg_ok, bool lds_ok, bool 
   return 0;
 }
 
-// part[chunk][i][n] = sum_{G in chunk} conj(beta_i(G)) psi_n(G), chunks of kKbChunk plane waves
+// Plane-wave chunks of the projections: kKbChunk per workgroup for the one-block product
+// (few projectors and bands); for the tiled product about 2048 workgroups over the chip, so
+// that each runs a long k loop and the FP64 partials stay small. A chunk count at most
+// that of kKbChunk-wide chunks, which sizes the workspace.
+static int kb_chunk(int npw, int nproj, int nb) {
+  if (nproj <= 64 && nb <= 64) return kKbChunk;
+  const int tiles = ((nproj + 31) / 32) * ((nb + 31) / 32);
+  const int nc = std::max(1, std::min((npw + kKbChunk - 1) / kKbChunk, 2048 / tiles));
+  return std::max(kKbChunk, ((npw + nc - 1) / nc + 63) / 64 * 64);
+}
+
+// part[chunk][i][n] = sum_{G in chunk} conj(beta_i(G)) psi_n(G), chunks of kb_chunk plane waves
 template <typename T>
 static fde_status kb_project(const cplx<T>* beta, const cplx<T>* psi, int npw, int nproj, int nb, int nchunk,
                              cplx<double>* part, hipStream_t s) {
-  const AhBProb<T> prob{beta, psi, nullptr, nproj, nb, npw, nchunk, kKbChunk, part};
+  const AhBProb<T> prob{beta, psi, nullptr, nproj, nb, npw, nchunk, kb_chunk(npw, nproj, nb), part};
   if (nproj <= 64 && nb <= 64)
     return launch<KAhBAll<T>, 512>(dim3(nchunk), 512, KAhBAll<T>::lds_bytes(nproj, nb), s, prob);
   AhBSet<T> set;
@@ -222,10 +233,11 @@ static fde_status apply_h_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, cpl
                                (const int4*)t.d_sticks, (const int*)t.d_xlist, t.ncol, N1, N2, p->rad[2], tw3, kv,
                                invN, SZ));
     if (nproj > 0) {
-      FDE_TRY(kb_project<T>(beta, ps, t.npw, nproj, nbc, nchunk, part, s));
+      const int kc = kb_chunk(t.npw, nproj, nbc), nck = (t.npw + kc - 1) / kc;
+      FDE_TRY(kb_project<T>(beta, ps, t.npw, nproj, nbc, nck, part, s));
       FDE_TRY(launch<KKbReduce<T>>(dim3((nproj * nbc + KKbReduce<T>::NO - 1) / KKbReduce<T>::NO), kBlock,
                                    KKbReduce<T>::NG * KKbReduce<T>::NO * sizeof(cplx<double>), s,
-                                   (const cplx<double>*)part, nchunk,
+                                   (const cplx<double>*)part, nck,
                                    nproj, nbc, dkb, dp));
       FDE_TRY(launch<KKbAdd<T>>(dim3((t.npw + KKbAdd<T>::TG - 1) / KKbAdd<T>::TG), kBlock, KKbAdd<T>::lds_bytes(), s,
                                 beta, (const cplx<T>*)dp, hs, t.npw, nproj, nbc));
@@ -430,8 +442,9 @@ static fde_status band_energies_t(fde_plan* p, int ik, int nb, const cplx<T>* ps
                               per_band));
   FDE_TRY(launch<KSumInto>(dim3(1), kBlock, 17 * sizeof(double), s, (const double*)per_band, nb, out));
   if (nproj > 0) {
-    FDE_TRY(kb_project<T>(beta, psi, t.npw, nproj, nb, nchunk, part, s));
-    FDE_TRY(launch<KBandNl>(dim3(nb), kBlock, 17 * sizeof(double), s, (const cplx<double>*)part, nchunk, nproj, nb,
+    const int kc = kb_chunk(t.npw, nproj, nb), nck = (t.npw + kc - 1) / kc;
+    FDE_TRY(kb_project<T>(beta, psi, t.npw, nproj, nb, nck, part, s));
+    FDE_TRY(launch<KBandNl>(dim3(nb), kBlock, 17 * sizeof(double), s, (const cplx<double>*)part, nck, nproj, nb,
                             dkb, occw, per_band));
     FDE_TRY(launch<KSumInto>(dim3(1), kBlock, 17 * sizeof(double), s, (const double*)per_band, nb, out + 1));
   }
