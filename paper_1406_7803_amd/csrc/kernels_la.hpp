@@ -626,17 +626,28 @@ struct KRotateWide {
       re[t] = v4{0, 0, 0, 0};
       im[t] = v4{0, 0, 0, 0};
     }
-    for (int k0 = 0; k0 < m; k0 += 4) {
+    // operands of step k0 + 4 are loaded while the matrix cores work on step k0
+    auto load = [&](int k0, cplx<T>& b, cplx<T>* a) {
       const int k = k0 + kq;
-      cplx<T> b = mk<T>(0, 0);
+      b = mk<T>(0, 0);
       if (k < nb) b = sX[k * 16 + col];
       else if (k < m && gin) b = M[(size_t)k * npw + g];
 #pragma unroll
       for (int i = 0; i < kRotWideTiles; ++i) {
+        const int n = 16 * (w + 4 * i) + col;
+        a[i] = (k < m && n < nb) ? Cg[(size_t)k * nb + n] : mk<T>(0, 0);
+      }
+    };
+    cplx<T> bc, ac[kRotWideTiles], bn, an[kRotWideTiles];
+    load(0, bc, ac);
+    for (int k0 = 0; k0 < m; k0 += 4) {
+      if (k0 + 4 < m) load(k0 + 4, bn, an);
+      const cplx<T> b = bc;
+#pragma unroll
+      for (int i = 0; i < kRotWideTiles; ++i) {
         const int t = w + 4 * i;
         if (t >= ntile) break;
-        const int n = 16 * t + col;
-        const cplx<T> a_ = (k < m && n < nb) ? Cg[(size_t)k * nb + n] : mk<T>(0, 0);
+        const cplx<T> a_ = ac[i];
         if constexpr (sizeof(T) == 8) {
           re[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_.x, b.x, re[i], 0, 0, 0);
           re[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_.y, b.y, re[i], 0, 0, 0);
@@ -649,6 +660,9 @@ struct KRotateWide {
           im[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_.y, b.x, im[i], 0, 0, 0);
         }
       }
+      bc = bn;
+#pragma unroll
+      for (int i = 0; i < kRotWideTiles; ++i) ac[i] = an[i];
     }
     if (gin) {
 #pragma unroll

@@ -239,8 +239,12 @@ static fde_status apply_h_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, cpl
                                    KKbReduce<T>::NG * KKbReduce<T>::NO * sizeof(cplx<double>), s,
                                    (const cplx<double>*)part, nck,
                                    nproj, nbc, dkb, dp));
-      FDE_TRY(launch<KKbAdd<T>>(dim3((t.npw + KKbAdd<T>::TG - 1) / KKbAdd<T>::TG), kBlock, KKbAdd<T>::lds_bytes(), s,
-                                beta, (const cplx<T>*)dp, hs, t.npw, nproj, nbc));
+      if (nbc <= 4 * kKbAddTiles * 16)
+        FDE_TRY(launch<KKbAddMfma<T>>(dim3((t.npw + 15) / 16), kBlock, 0, s, beta, (const cplx<T>*)dp, hs, t.npw,
+                                      nproj, nbc));
+      else
+        FDE_TRY(launch<KKbAdd<T>>(dim3((t.npw + KKbAdd<T>::TG - 1) / KKbAdd<T>::TG), kBlock, KKbAdd<T>::lds_bytes(),
+                                  s, beta, (const cplx<T>*)dp, hs, t.npw, nproj, nbc));
     }
   }
   return FDE_OK;

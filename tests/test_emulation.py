@@ -30,6 +30,8 @@ def test_apply_h(be, prec):
 @pytest.mark.parametrize("prec", PRECS)
 def test_apply_h_many_projectors(be, prec):
     pc.check_apply_h_many_projectors(be, prec)
+    # more than 512 bands: the projector add's vector-unit path
+    pc.check_apply_h_many_projectors(be, prec, nb=520)
 
 
 @pytest.mark.parametrize("prec", PRECS)
