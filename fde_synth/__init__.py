@@ -292,6 +292,34 @@ def tiny(geometry: int = 0, grid=(12, 12, 12), L=(6.0, 6.0, 6.0), ecut=3.0, nban
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4}
 
 
+def augmentation_q(atoms, q_s: float = 0.4, q_p: float = 0.15, q_sp: float = 0.05):
+    """Synthetic augmentation overlaps for the projectors of `atoms` (channel order s,
+    p_x, p_y, p_z as the projectors): a real symmetric positive definite block per atom
+    (s and p diagonal, an s-p_x coupling), zero between atoms; and the atom of every
+    projector. Returns (q [nproj, nproj], atom_of [nproj])."""
+    blocks, owner = [], []
+    for a_i, a in enumerate(atoms):
+        if a.lmax < 0:
+            continue
+        n = 1 if a.lmax == 0 else 4
+        b = np.zeros((n, n))
+        b[0, 0] = q_s
+        for i in range(1, n):
+            b[i, i] = q_p
+        if n > 1:
+            b[0, 1] = b[1, 0] = q_sp
+        blocks.append(b)
+        owner += [a_i] * n
+    nproj = len(owner)
+    q = np.zeros((nproj, nproj))
+    o = 0
+    for b in blocks:
+        n = b.shape[0]
+        q[o:o + n, o:o + n] = b
+        o += n
+    return q, np.array(owner, dtype=np.int32)
+
+
 # ----------------------------------------------------------------------------
 # Partitions of one geometry (layout only): the supersystem and the fragments
 # ----------------------------------------------------------------------------
