@@ -262,6 +262,14 @@ typedef struct fde_block {
   double* eval;        /* [nb] Ritz values (Rayleigh-Ritz output, preconditioner input) */
   double* rnorm;       /* [nb] residual norms (preconditioner output)        */
   int* info;           /* [1] Rayleigh-Ritz status, as fde_subspace_rr        */
+  void* sv;            /* [m][npw] S v of the generalised problem H x = e S x  */
+                       /* (Appendix, non-local pseudopotentials: the overlap   */
+                       /* S^I of the subsystem's own augmentation projectors,  */
+                       /* see fde_apply_s), or NULL for S = 1. With sv the     */
+                       /* Rayleigh-Ritz step uses S = V^H (S V) (FP64 matrix   */
+                       /* cores whatever the GEMM mode) and rotates sv with v  */
+                       /* and hv; the TPA preconditioner's residual is         */
+                       /* hx - eval sx (the learned one rejects sv).           */
 } fde_block;
 
 /*
@@ -407,6 +415,36 @@ fde_status fde_grid_dot(fde_plan* plan, const void* a, const void* b, double* ou
  */
 fde_status fde_energy_total(int ns, const double* embed_energies, const double* band_terms, const double* dots,
                             double* out, hipStream_t stream);
+
+/*
+ * Subsystem-specific augmentation (Appendix, non-local pseudopotentials: with
+ * PAW/ultrasoft pseudopotentials a subsystem's smooth orbitals solve
+ * H psi = e S^I psi with the overlap of its own atoms' projectors only).
+ *
+ * fde_apply_s: spsi = psi + sum_ij beta_i q_ij <beta_j|psi>, i.e. S^I psi.
+ *   psi, spsi [nb][npw] complex (plan precision), distinct; beta [nproj][npw]
+ *   the augmentation projectors (as from fde_kb_projectors); q device
+ *   [nproj][nproj] real symmetric FP64 (zero between atoms). The projections
+ *   are summed in FP64. nproj = 0 copies psi. FDE_ERR_SHAPE when nproj exceeds
+ *   the workspace's max_nproj.
+ * fde_aug_charges: charges[atom_of[i]] += sum_n occw_n Re(conj(P_in) (q P)_in),
+ *   P = beta^H psi: the charge of each atom's augmentation density
+ *   (sum_ij rho_ij q_ij with rho_ij = sum_n f_n <psi_n|beta_i><beta_j|psi_n>).
+ *   occw [nb] device FP64 (w_k f_nk); atom_of [nproj] device int; charges
+ *   device FP64, accumulated (+=) in projector order.
+ * fde_aug_density: rho += sum_a c_a g_a(r), g_a the unit-normalised Gaussian of
+ *   width w_a at R_a (the synthetic augmentation function Q_ij = q_ij g_a),
+ *   from its Fourier series on the density sphere. atoms device [natom][4] =
+ *   (x, y, z, w) in bohr; charges device [natom] (fde_aug_charges); rho [N]
+ *   plan precision. Uses the plan's embedding work grids.
+ */
+fde_status fde_apply_s(fde_plan* plan, int ik, int nb, const void* psi, void* spsi, int nproj, const void* beta,
+                       const double* q, hipStream_t stream);
+fde_status fde_aug_charges(fde_plan* plan, int ik, int nb, const void* psi, const double* occw, int nproj,
+                           const void* beta, const double* q, const int* atom_of, double* charges,
+                           hipStream_t stream);
+fde_status fde_aug_density(fde_plan* plan, int natom, const double* atoms, const double* charges, void* rho,
+                           hipStream_t stream);
 
 /* Frozen environments of the freeze-and-thaw scheme (Fig. 1b caption: a subsystem
  * iterated to self-consistency against the densities of the last broadcast; Sec. 2 on

@@ -508,6 +508,34 @@ struct KVlocG {
   }
 };
 
+// Augmentation charge in G: sum_a c_a exp(-G^2 w_a^2 / 2) e^{-iG.R_a} / Omega on the density
+// sphere (atoms [natom][4] = x, y, z, w and charges c on the device).
+template <typename T>
+struct KAugG {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char*, const double* __restrict__ atoms, const double* __restrict__ q,
+                         int natom, GridGeo g, double omega, cplx<T>* __restrict__ w, unsigned nblk) {
+    GRID_FOR(c, g.n, nblk) {
+      const size_t i = i0_ + l_;
+      if (i >= g.n) break;
+      double gx, gy, gz;
+      grid_g(g, i, gx, gy, gz);
+      const double G2 = gx * gx + gy * gy + gz * gz;
+      double re = 0.0, im = 0.0;
+      if (G2 <= g.gd2) {
+        for (int a = 0; a < natom; ++a) {
+          const double* at = atoms + 4 * a;
+          const double amp = q[a] * exp(-0.5 * G2 * at[3] * at[3]);
+          const double ph = -(gx * at[0] + gy * at[1] + gz * at[2]);
+          re += amp * cos(ph);
+          im += amp * sin(ph);
+        }
+      }
+      w[i] = mk<T>((T)(re / omega), (T)(im / omega));
+    }
+  }
+};
+
 template <typename T>
 static fde_status vloc_t(fde_plan* p, const std::vector<Ion>& ions, T* vloc, hipStream_t s) {
   EmbedWs<T> e = embed_ws<T>(p);
@@ -899,6 +927,26 @@ fde_status fde_local_potential(fde_plan* p, int natoms, const double* pos, const
   }
   if (p->prec == FDE_F64) return vloc_t<double>(p, ions, (double*)vloc, s);
   return vloc_t<float>(p, ions, (float*)vloc, s);
+}
+
+fde_status fde_aug_density(fde_plan* p, int natom, const double* atoms, const double* charges, void* rho,
+                           hipStream_t s) {
+  if (!p) return fail(FDE_ERR_ARG, "null plan");
+  if (!p->ws) return fail(FDE_ERR_WORKSPACE, "no workspace attached (fde_plan_set_workspace)");
+  if (natom < 0 || (natom > 0 && (!atoms || !charges)) || !rho) return fail(FDE_ERR_ARG, "null argument");
+  if (natom == 0) return FDE_OK;
+  const size_t n = p->npts();
+  const unsigned nb = red_blocks(n);
+  if (p->prec == FDE_F64) {
+    EmbedWs<double> e = embed_ws<double>(p);
+    FDE_TRY(launch<KAugG<double>>(dim3(nb), kBlock, 0, s, atoms, charges, natom, geo(p), p->omega, e.W0, nb));
+    FDE_TRY(fft3<double>(p, e.W0, true, s));
+    return launch<KAddReal<double>>(dim3(nb), kBlock, 0, s, (const cplx<double>*)e.W0, 1.0, (double*)rho, n, nb);
+  }
+  EmbedWs<float> e = embed_ws<float>(p);
+  FDE_TRY(launch<KAugG<float>>(dim3(nb), kBlock, 0, s, atoms, charges, natom, geo(p), p->omega, e.W0, nb));
+  FDE_TRY(fft3<float>(p, e.W0, true, s));
+  return launch<KAddReal<float>>(dim3(nb), kBlock, 0, s, (const cplx<float>*)e.W0, 1.0, (float*)rho, n, nb);
 }
 
 fde_status fde_mix(size_t n, double beta, void* rho_in, const void* rho_out, int prec, hipStream_t s) {

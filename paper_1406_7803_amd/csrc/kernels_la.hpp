@@ -20,6 +20,7 @@ template <typename T>
 struct Prob {
   cplx<T>* v;
   cplx<T>* hv;
+  cplx<T>* sv;             // [m][npw] S v of the generalised problem, or null (S = 1)
   cplx<T>* t;              // [nb][npw] preconditioner output (rows nb.. of v in a block)
   const uint8_t* active;   // [m] or null (Rayleigh-Ritz input)
   uint8_t* act_out;        // [nb] (preconditioner output, the T rows' flags)
@@ -412,7 +413,8 @@ struct KRotate {
     const int g0 = c.bx() * GC;
     if (g0 >= npw) return;  // uniform per block
     const int gc = (npw - g0) < GC ? (npw - g0) : GC;
-    cplx<T>* M = c.by() == 0 ? P.v : P.hv;
+    cplx<T>* M = c.by() == 0 ? P.v : (c.by() == 1 ? P.hv : P.sv);
+    if (!M) return;  // no S v rows in this problem (uniform per block)
     const cplx<T>* Cg = (const cplx<T>*)P.Ct;
     cplx<T>* sV = (cplx<T>*)lds;               // [m][GC]
     cplx<T>* sC = sV + (size_t)m * GC;         // [m][nb] when staged
@@ -505,7 +507,8 @@ struct KRotateChunk {
     const int m = P.m, nb = P.nb, npw = P.npw;
     const int g0 = c.bx() * 64;
     if (g0 >= npw) return;  // uniform per block
-    cplx<T>* M = c.by() == 0 ? P.v : P.hv;
+    cplx<T>* M = c.by() == 0 ? P.v : (c.by() == 1 ? P.hv : P.sv);
+    if (!M) return;  // no S v rows in this problem (uniform per block)
     const cplx<T>* Cg = (const cplx<T>*)P.Ct;
     cplx<T>* sC = (cplx<T>*)lds;  // [kRotChunk][nb]
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -605,7 +608,8 @@ struct KRotateWide {
     const int m = P.m, nb = P.nb, npw = P.npw;
     const int g0 = c.bx() * 16;
     if (g0 >= npw) return;  // uniform per block
-    cplx<T>* M = c.by() == 0 ? P.v : P.hv;
+    cplx<T>* M = c.by() == 0 ? P.v : (c.by() == 1 ? P.hv : P.sv);
+    if (!M) return;  // no S v rows in this problem (uniform per block)
     const cplx<T>* Cg = (const cplx<T>*)P.Ct;
     cplx<T>* sX = (cplx<T>*)lds;  // [nb][16]
     for (int idx = c.tid(); idx < nb * 16; idx += c.nthr()) {
@@ -709,7 +713,8 @@ struct KRotateStream {
   FDE_HD static void run(const Ctx& c, char* lds, const ProbSet<T> ps, int gx) {
     const Prob<T>& P = ps.p[c.bz()];
     const int m = P.m, nb = P.nb, npw = P.npw;
-    cplx<T>* M = c.by() == 0 ? P.v : P.hv;
+    cplx<T>* M = c.by() == 0 ? P.v : (c.by() == 1 ? P.hv : P.sv);
+    if (!M) return;  // no S v rows in this problem (uniform per block)
     const cplx<T>* Cg = (const cplx<T>*)P.Ct;
     cplx<T>* sC = (cplx<T>*)lds;
     for (int idx = c.tid(); idx < m * nb; idx += c.nthr()) sC[idx] = Cg[idx];
@@ -810,13 +815,14 @@ struct KPrecond {
     const double lam = P.eval[n];
     const cplx<T>* xn = P.v + (size_t)n * npw;
     const cplx<T>* hn = P.hv + (size_t)n * npw;
+    const cplx<T>* sn = P.sv ? P.sv + (size_t)n * npw : xn;  // residual H x - lambda S x
     cplx<T>* tn = P.t + (size_t)n * npw;
     const double kf0 = P.kf[0], kf1 = P.kf[1], kf2 = P.kf[2];
     const double b0 = ps.b[0], b1 = ps.b[1], b2 = ps.b[2];
     double r2 = 0.0, tk = 0.0;
     for (int g = c.tid(); g < npw; g += c.nthr()) {
-      const cplx<T> xv = xn[g], hv = hn[g];
-      const double rx = (double)hv.x - lam * xv.x, ry = (double)hv.y - lam * xv.y;
+      const cplx<T> xv = xn[g], hv = hn[g], sv = sn[g];
+      const double rx = (double)hv.x - lam * sv.x, ry = (double)hv.y - lam * sv.y;
       r2 += rx * rx + ry * ry;
       const int p = P.millp[g];
       const double q1 = (((p & 1023) - 512) + kf0) * b0;
@@ -830,8 +836,8 @@ struct KPrecond {
     const bool act = rn > 1e-10;
     double t2 = 0.0;
     for (int g = c.tid(); g < npw; g += c.nthr()) {
-      const cplx<T> xv = xn[g], hv = hn[g];
-      const double rx = (double)hv.x - lam * xv.x, ry = (double)hv.y - lam * xv.y;
+      const cplx<T> hv = hn[g], sv = sn[g];
+      const double rx = (double)hv.x - lam * sv.x, ry = (double)hv.y - lam * sv.y;
       const int p = P.millp[g];
       const double q1 = (((p & 1023) - 512) + kf0) * b0;
       const double q2 = ((((p >> 10) & 1023) - 512) + kf1) * b1;
@@ -892,10 +898,11 @@ struct KPrecondA : KPcBase<T> {
     const double lam = P.eval[n];
     const cplx<T>* xn = P.v + (size_t)n * P.npw;
     const cplx<T>* hn = P.hv + (size_t)n * P.npw;
+    const cplx<T>* sn = P.sv ? P.sv + (size_t)n * P.npw : xn;  // residual H x - lambda S x
     double r2 = 0.0, tk = 0.0;
     for (int g = g0 + c.tid(); g < g1; g += c.nthr()) {
-      const cplx<T> xv = xn[g], hv = hn[g];
-      const double rx = (double)hv.x - lam * xv.x, ry = (double)hv.y - lam * xv.y;
+      const cplx<T> xv = xn[g], hv = hn[g], sv = sn[g];
+      const double rx = (double)hv.x - lam * sv.x, ry = (double)hv.y - lam * sv.y;
       r2 += rx * rx + ry * ry;
       tk += KPcBase<T>::kin_of_g(P, ps, g) * ((double)xv.x * xv.x + (double)xv.y * xv.y);
     }
@@ -924,11 +931,12 @@ struct KPrecondB : KPcBase<T> {
     const double lam = P.eval[n];
     const cplx<T>* xn = P.v + (size_t)n * P.npw;
     const cplx<T>* hn = P.hv + (size_t)n * P.npw;
+    const cplx<T>* sn = P.sv ? P.sv + (size_t)n * P.npw : xn;  // residual H x - lambda S x
     cplx<T>* tn = P.t + (size_t)n * P.npw;
     double t2 = 0.0;
     for (int g = g0 + c.tid(); g < g1; g += c.nthr()) {
-      const cplx<T> xv = xn[g], hv = hn[g];
-      const double rx = (double)hv.x - lam * xv.x, ry = (double)hv.y - lam * xv.y;
+      const cplx<T> hv = hn[g], sv = sn[g];
+      const double rx = (double)hv.x - lam * sv.x, ry = (double)hv.y - lam * sv.y;
       const double xx = KPcBase<T>::kin_of_g(P, ps, g) / tk;
       const double pp = 27.0 + xx * (18.0 + xx * (12.0 + 8.0 * xx));
       const double K = pp / (pp + 16.0 * xx * xx * xx * xx);

@@ -6,6 +6,7 @@
 
 #include "kernels_gemm.hpp"
 #include "kernels_la.hpp"
+#include "kernels_pw.hpp"
 #include "kernels_mlp.hpp"
 #include "kernels_rr.hpp"
 #include "launch.hpp"
@@ -68,6 +69,7 @@ static Prob<T> make_prob(fde_plan* p, const fde_block& b) {
   const KTables& t = p->k[b.ik];
   P.v = (cplx<T>*)b.v;
   P.hv = (cplx<T>*)b.hv;
+  P.sv = (cplx<T>*)b.sv;
   P.t = P.v + (size_t)b.nb * t.npw;
   P.active = b.active;
   P.act_out = b.t_active;
@@ -136,12 +138,16 @@ static fde_status rr_launch(fde_plan* p, ProbSet<T>& ps, hipStream_t s) {
   }
   AhBSet<T> gs;
   gs.n = ps.n;
+  bool gen = false;  // a generalised problem: S = V^H (S V), full tiles on the FP64 matrix cores
   for (int i = 0; i < ps.n; ++i) {
     const Prob<T>& P = ps.p[i];
-    gs.p[i] = AhBProb<T>{P.v, P.v, P.hv, P.m, P.m, P.npw, P.nchunk, P.chunk, P.part};
+    gs.p[i] = AhBProb<T>{P.v, P.sv ? P.sv : P.v, P.hv, P.m, P.m, P.npw, P.nchunk, P.chunk, P.part};
+    gen = gen || P.sv != nullptr;
   }
   const int nt = (mmax + KAhB<T>::TI - 1) / KAhB<T>::TI;
-  if constexpr (sizeof(T) == 4) {
+  if (gen) {
+    FDE_TRY(launch<KAhB<T>>(dim3(kMaxChunks, nt * nt, ps.n), kBlock, KAhB<T>::lds_bytes(), s, gs));
+  } else if constexpr (sizeof(T) == 4) {
     if (p->gemm == FDE_GEMM_BF16X3)
       FDE_TRY(launch<KAhBSplit<2>>(dim3(kMaxChunks, nt * nt, ps.n), kBlock, KAhBSplit<2>::lds_bytes(), s, gs));
     else if (p->gemm == FDE_GEMM_BF16X6)
@@ -177,20 +183,21 @@ static fde_status rr_launch(fde_plan* p, ProbSet<T>& ps, hipStream_t s) {
     FDE_TRY((launch<KRRSolveLds<T>, 1024>(dim3(ps.n), 1024, KRRSolveLds<T>::lds_bytes(mmax), s, ps)));
   else
     FDE_TRY((launch<KRRSolve<T>, 1024>(dim3(ps.n), 1024, fixed + mats, s, ps, mats)));
+  const int nrot = gen ? 3 : 2;  // X = V C, HX = HV C (and SX = SV C)
   if (mmax <= 4 * kRotSteps && nbmax <= 64 && KRotateStream<T>::lds_bytes(mmax, nbmax) <= kLdsMax) {
     // streamed rotation: about eight workgroups of four wavefronts per CU over all problems
     const int groups = (npwmax + 15) / 16;
     const int gx = std::max(1, std::min((groups + 3) / 4, 2048 / (2 * ps.n)));
-    return launch<KRotateStream<T>, 256, 3>(dim3(gx, 2, ps.n), kBlock, KRotateStream<T>::lds_bytes(mmax, nbmax), s,
+    return launch<KRotateStream<T>, 256, 3>(dim3(gx, nrot, ps.n), kBlock, KRotateStream<T>::lds_bytes(mmax, nbmax), s,
                                             ps, gx);
   }
   // matrix cores with C in chunks through LDS (up to 128 bands)
   if (nbmax <= 128)
-    return launch<KRotateChunk<T>, 256>(dim3((npwmax + 63) / 64, 2, ps.n), 256, KRotateChunk<T>::lds_bytes(nbmax), s,
+    return launch<KRotateChunk<T>, 256>(dim3((npwmax + 63) / 64, nrot, ps.n), 256, KRotateChunk<T>::lds_bytes(nbmax), s,
                                         ps);
   // matrix cores with the X rows of 16 columns in LDS (up to 512 bands)
   if (nbmax <= 4 * kRotWideTiles * 16 && KRotateWide<T>::lds_bytes(nbmax) <= kLdsMax)
-    return launch<KRotateWide<T>, 256>(dim3((npwmax + 15) / 16, 2, ps.n), 256, KRotateWide<T>::lds_bytes(nbmax), s,
+    return launch<KRotateWide<T>, 256>(dim3((npwmax + 15) / 16, nrot, ps.n), 256, KRotateWide<T>::lds_bytes(nbmax), s,
                                        ps);
   // in-place rotation: plane-wave chunk of all m rows (+ C when it fits) in LDS
   const size_t cs = sizeof(cplx<T>);
@@ -198,7 +205,7 @@ static fde_status rr_launch(fde_plan* p, ProbSet<T>& ps, hipStream_t s) {
   while (GC > 4 && (size_t)mmax * GC * cs > 96 * 1024) GC /= 2;
   const int c_in_lds = ((size_t)mmax * GC * cs + (size_t)mmax * nbmax * cs) <= kLdsMax ? 1 : 0;
   const size_t rl = (size_t)mmax * GC * cs + (c_in_lds ? (size_t)mmax * nbmax * cs : 0);
-  FDE_TRY(launch<KRotate<T>>(dim3((npwmax + GC - 1) / GC, 2, ps.n), kBlock, rl, s, ps, GC, c_in_lds));
+  FDE_TRY(launch<KRotate<T>>(dim3((npwmax + GC - 1) / GC, nrot, ps.n), kBlock, rl, s, ps, GC, c_in_lds));
   return FDE_OK;
 }
 
@@ -278,6 +285,8 @@ static fde_status precond_mlp_batched_t(fde_plan* p, int nblk, const fde_block* 
       ps.p[i] = make_prob<T>(p, blk[b0 + i]);
       nbmax = std::max(nbmax, ps.p[i].nb);
     }
+    for (int i = 0; i < ps.n; ++i)
+      if (ps.p[i].sv) return fail(FDE_ERR_UNSUPPORTED, "the learned preconditioner takes standard problems (sv = NULL)");
     FDE_TRY(launch<KPrecondMlp<T>>(dim3(nbmax, ps.n), kBlock, KPrecondMlp<T>::lds_bytes, s, ps, params, vbar + b0));
   }
   return FDE_OK;
@@ -323,6 +332,167 @@ static fde_status static_scratch(void** out) {
 }  // namespace fde
 
 using namespace fde;
+
+
+// ---------------------------------------------------------------------------
+// Subsystem-specific augmentation (Appendix, non-local pseudopotentials): the
+// projections P = beta^H psi in FP64, S psi = psi + beta (q P), and the atom
+// charges of the augmentation density.
+// ---------------------------------------------------------------------------
+// P[o] = sum over the plane-wave chunks of part[chunk][o], o < nproj nb (fixed order)
+struct KPReduce {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char*, const cplx<double>* __restrict__ part, int nchunk, int nout,
+                         cplx<double>* __restrict__ P) {
+    for (int l = c.tid(); l < 256; l += c.nthr()) {
+      const int o = c.bx() * 256 + l;
+      if (o >= nout) break;
+      double sx = 0.0, sy = 0.0;
+      for (int k = 0; k < nchunk; ++k) {
+        const cplx<double> v = part[(size_t)k * nout + o];
+        sx += v.x;
+        sy += v.y;
+      }
+      P[o] = mk<double>(sx, sy);
+    }
+  }
+};
+
+// dp[i][n] = sum_j q[i][j] P[j][n] (q real, [nproj][nproj]); grid ceil(nproj nb / 256)
+template <typename T>
+struct KQMul {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char*, const double* __restrict__ q, const cplx<double>* __restrict__ P,
+                         int nproj, int nb, cplx<T>* __restrict__ dp) {
+    for (int l = c.tid(); l < 256; l += c.nthr()) {
+      const int o = c.bx() * 256 + l;
+      if (o >= nproj * nb) break;
+      const int i = o / nb, n = o - i * nb;
+      double sx = 0.0, sy = 0.0;
+      for (int j = 0; j < nproj; ++j) {
+        const double qij = q[(size_t)i * nproj + j];
+        if (qij == 0.0) continue;
+        const cplx<double> v = P[(size_t)j * nb + n];
+        sx += qij * v.x;
+        sy += qij * v.y;
+      }
+      dp[o] = mk<T>((T)sx, (T)sy);
+    }
+  }
+};
+
+// charges[atom_of[i]] += sum_n occw_n Re(conj(P_in) sum_j q_ij P_jn), projectors in order
+// (one workgroup; t_i in LDS, then one thread adds them up in index order)
+struct KAugCharges {
+  template <class Ctx>
+  FDE_HD static void run(const Ctx& c, char* lds, const double* __restrict__ q, const cplx<double>* __restrict__ P,
+                         const double* __restrict__ occw, int nproj, int nb, const int* __restrict__ atom_of,
+                         double* __restrict__ charges) {
+    double* t = (double*)lds;
+    for (int i = c.tid(); i < nproj; i += c.nthr()) {
+      double acc = 0.0;
+      for (int n = 0; n < nb; ++n) {
+        double sx = 0.0, sy = 0.0;
+        for (int j = 0; j < nproj; ++j) {
+          const double qij = q[(size_t)i * nproj + j];
+          if (qij == 0.0) continue;
+          const cplx<double> v = P[(size_t)j * nb + n];
+          sx += qij * v.x;
+          sy += qij * v.y;
+        }
+        const cplx<double> pi = P[(size_t)i * nb + n];
+        acc += occw[n] * (pi.x * sx + pi.y * sy);
+      }
+      t[i] = acc;
+    }
+    c.sync();
+    if (c.tid() == 0)
+      for (int i = 0; i < nproj; ++i) charges[atom_of[i]] += t[i];
+  }
+};
+
+// P = beta^H psi in FP64 for one band chunk (scratch: chunk partials at off_part, P at off_p)
+template <typename T>
+static fde_status projections_fp64(fde_plan* p, int ik, int nbc, const cplx<T>* psi, int nproj, const cplx<T>* beta,
+                                   cplx<double>* part, cplx<double>* P, hipStream_t s) {
+  const KTables& t = p->k[ik];
+  int chunk = kKbChunk;
+  if (!(nproj <= 64 && nbc <= 64)) {
+    const int tiles = ((nproj + 31) / 32) * ((nbc + 31) / 32);
+    const int nc = std::max(1, std::min((t.npw + kKbChunk - 1) / kKbChunk, 2048 / tiles));
+    chunk = std::max(kKbChunk, ((t.npw + nc - 1) / nc + 63) / 64 * 64);
+  }
+  const int nchunk = (t.npw + chunk - 1) / chunk;
+  const AhBProb<T> prob{beta, psi, nullptr, nproj, nbc, t.npw, nchunk, chunk, part};
+  if (nproj <= 64 && nbc <= 64) {
+    FDE_TRY((launch<KAhBAll<T>, 512>(dim3(nchunk), 512, KAhBAll<T>::lds_bytes(nproj, nbc), s, prob)));
+  } else {
+    AhBSet<T> set;
+    set.n = 1;
+    set.p[0] = prob;
+    const int nti = (nproj + KAhB<T>::TI - 1) / KAhB<T>::TI, ntj = (nbc + KAhB<T>::TJ - 1) / KAhB<T>::TJ;
+    FDE_TRY(launch<KAhB<T>>(dim3(nchunk, nti * ntj, 1), kBlock, KAhB<T>::lds_bytes(), s, set));
+  }
+  return launch<KPReduce>(dim3((nproj * nbc + 255) / 256), kBlock, 0, s, (const cplx<double>*)part, nchunk,
+                          nproj * nbc, P);
+}
+
+// scratch of the augmentation calls: P (FP64) in the stick-buffer area, the chunk partials
+// and dp where fde_apply_h keeps its own
+template <typename T>
+static fde_status aug_scratch(fde_plan* p, int nproj, cplx<double>** part, cplx<double>** P, cplx<T>** dp) {
+  const size_t sb = align256((size_t)p->max_nb * p->N[2] * stick_stride(p->ncol_max) * p->csize());
+  if ((size_t)nproj * p->max_nb * sizeof(cplx<double>) > sb)
+    return fail(FDE_ERR_SHAPE, "too many projectors for the workspace's stick buffer");
+  const size_t nchunk = (p->npw_max + kKbChunk - 1) / kKbChunk;
+  *P = (cplx<double>*)p->scratch;
+  *part = (cplx<double>*)(p->scratch + sb);
+  *dp = (cplx<T>*)(p->scratch + sb + align256(nchunk * (size_t)p->max_nproj * p->max_nb * 16));
+  return FDE_OK;
+}
+
+template <typename T>
+static fde_status apply_s_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, cplx<T>* spsi, int nproj,
+                            const cplx<T>* beta, const double* q, hipStream_t s) {
+  const KTables& t = p->k[ik];
+  cplx<double>*part, *P;
+  cplx<T>* dp;
+  FDE_TRY(aug_scratch<T>(p, nproj, &part, &P, &dp));
+  for (int b0 = 0; b0 < nb; b0 += p->max_nb) {
+    const int nbc = std::min(p->max_nb, nb - b0);
+    const cplx<T>* ps = psi + (size_t)b0 * t.npw;
+    cplx<T>* ss = spsi + (size_t)b0 * t.npw;
+    FDE_TRY(copy_d2d(ss, ps, (size_t)nbc * t.npw * sizeof(cplx<T>), s));
+    if (nproj == 0) continue;
+    FDE_TRY(projections_fp64<T>(p, ik, nbc, ps, nproj, beta, part, P, s));
+    FDE_TRY(launch<KQMul<T>>(dim3((nproj * nbc + 255) / 256), kBlock, 0, s, q, (const cplx<double>*)P, nproj, nbc,
+                             dp));
+    if (nbc <= 4 * kKbAddTiles * 16)
+      FDE_TRY(launch<KKbAddMfma<T>>(dim3((t.npw + 15) / 16), kBlock, 0, s, beta, (const cplx<T>*)dp, ss, t.npw, nproj,
+                                    nbc));
+    else
+      FDE_TRY(launch<KKbAdd<T>>(dim3((t.npw + KKbAdd<T>::TG - 1) / KKbAdd<T>::TG), kBlock, KKbAdd<T>::lds_bytes(), s,
+                                beta, (const cplx<T>*)dp, ss, t.npw, nproj, nbc));
+  }
+  return FDE_OK;
+}
+
+template <typename T>
+static fde_status aug_charges_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, const double* occw, int nproj,
+                                const cplx<T>* beta, const double* q, const int* atom_of, double* charges,
+                                hipStream_t s) {
+  const KTables& t = p->k[ik];
+  cplx<double>*part, *P;
+  cplx<T>* dp;
+  FDE_TRY(aug_scratch<T>(p, nproj, &part, &P, &dp));
+  for (int b0 = 0; b0 < nb; b0 += p->max_nb) {
+    const int nbc = std::min(p->max_nb, nb - b0);
+    FDE_TRY(projections_fp64<T>(p, ik, nbc, psi + (size_t)b0 * t.npw, nproj, beta, part, P, s));
+    FDE_TRY(launch<KAugCharges>(dim3(1), kBlock, (size_t)nproj * sizeof(double), s, q, (const cplx<double>*)P,
+                                occw + b0, nproj, nbc, atom_of, charges));
+  }
+  return FDE_OK;
+}
 
 extern "C" {
 
@@ -475,6 +645,38 @@ fde_status fde_mlp_adam(const float* grad, float* params, float* m, float* v, in
   if (t < 1 || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
     return fail(FDE_ERR_ARG, "bad Adam hyper-parameters");
   return launch<KMlpAdam>(dim3((kMlpNParam + 255) / 256), kBlock, 0, s, grad, params, m, v, t, lr, beta1, beta2, eps);
+}
+
+
+fde_status fde_apply_s(fde_plan* p, int ik, int nb, const void* psi, void* spsi, int nproj, const void* beta,
+                       const double* q, hipStream_t s) {
+  FDE_TRY(check_plan(p, ik));
+  if (nb < 0 || nproj < 0) return fail(FDE_ERR_ARG, "negative size");
+  if (nb == 0) return FDE_OK;
+  if (!psi || !spsi) return fail(FDE_ERR_ARG, "null array");
+  if (psi == spsi) return fail(FDE_ERR_ARG, "spsi must not alias psi");
+  if (nproj > 0 && (!beta || !q)) return fail(FDE_ERR_ARG, "nproj > 0 needs beta and q");
+  if (nproj > p->max_nproj) return fail(FDE_ERR_SHAPE, "nproj exceeds the workspace's max_nproj");
+  if (p->prec == FDE_F64)
+    return apply_s_t<double>(p, ik, nb, (const cplx<double>*)psi, (cplx<double>*)spsi, nproj,
+                             (const cplx<double>*)beta, q, s);
+  return apply_s_t<float>(p, ik, nb, (const cplx<float>*)psi, (cplx<float>*)spsi, nproj, (const cplx<float>*)beta, q,
+                          s);
+}
+
+fde_status fde_aug_charges(fde_plan* p, int ik, int nb, const void* psi, const double* occw, int nproj,
+                           const void* beta, const double* q, const int* atom_of, double* charges, hipStream_t s) {
+  FDE_TRY(check_plan(p, ik));
+  if (nb < 0 || nproj < 0) return fail(FDE_ERR_ARG, "negative size");
+  if (nb == 0 || nproj == 0) return FDE_OK;
+  if (!psi || !occw || !beta || !q || !atom_of || !charges) return fail(FDE_ERR_ARG, "null array");
+  if (nproj > p->max_nproj) return fail(FDE_ERR_SHAPE, "nproj exceeds the workspace's max_nproj");
+  if ((size_t)nproj * sizeof(double) > kLdsMax) return fail(FDE_ERR_SHAPE, "too many projectors");
+  if (p->prec == FDE_F64)
+    return aug_charges_t<double>(p, ik, nb, (const cplx<double>*)psi, occw, nproj, (const cplx<double>*)beta, q,
+                                 atom_of, charges, s);
+  return aug_charges_t<float>(p, ik, nb, (const cplx<float>*)psi, occw, nproj, (const cplx<float>*)beta, q, atom_of,
+                              charges, s);
 }
 
 }  // extern "C"

@@ -375,15 +375,19 @@ class Engine:
 
 
 def davidson_fixed(plan: fde.Plan, ik: int, X0: torch.Tensor, veff: torch.Tensor, n_iter: int, beta=None, dkb=None,
-                   mlp_params: Optional[torch.Tensor] = None):
+                   mlp_params: Optional[torch.Tensor] = None, aug=None):
     """Block Davidson at a fixed potential (the band solver of one cycle, iterated):
     H X and Rayleigh-Ritz on X, then n_iter iterations of preconditioner (TPA, or
     the learned network when mlp_params is given), H T and Rayleigh-Ritz on [X | T].
-    Returns the Ritz values after every iteration (list of float64 tensors [nb])."""
+    aug = (beta_aug, q): the generalised problem H x = e S x with the subsystem's
+    augmentation overlap S (fde_apply_s), its rows S V kept beside V and HV.
+    Returns the Ritz values after every iteration (list of float64 tensors [nb]);
+    with aug also (X, S X) at the end."""
     nb, npw = X0.shape
     dev = plan.be.device
     V = torch.zeros((2 * nb, npw), dtype=plan.cdtype, device=dev)
     HV = torch.zeros_like(V)
+    SV = torch.zeros_like(V) if aug is not None else None
     V[:nb].copy_(X0)
     eval_ = torch.zeros(nb, dtype=torch.float64, device=dev)
     active = torch.ones(2 * nb, dtype=torch.uint8, device=dev)
@@ -391,17 +395,24 @@ def davidson_fixed(plan: fde.Plan, ik: int, X0: torch.Tensor, veff: torch.Tensor
     info = torch.zeros(1, dtype=torch.int32, device=dev)
     vbar = plan.grid_mean(veff) if mlp_params is not None else None
     plan.apply_h(ik, V[:nb], veff, beta, dkb, out=HV[:nb])
-    plan.subspace_rr_batched([plan.make_block(ik, nb, nb, V, HV, active=active, eval=eval_, info=info)])
+    if aug is not None:
+        plan.apply_s(ik, V[:nb], aug[0], aug[1], out=SV[:nb])
+    plan.subspace_rr_batched([plan.make_block(ik, nb, nb, V, HV, active=active, eval=eval_, info=info, sv=SV)])
     hist = []
     for _ in range(n_iter):
-        pcb = [plan.make_block(ik, nb, nb, V, HV, t_active=active[nb:], eval=eval_, rnorm=rnorm)]
+        pcb = [plan.make_block(ik, nb, nb, V, HV, t_active=active[nb:], eval=eval_, rnorm=rnorm, sv=SV)]
         if mlp_params is None:
             plan.precondition_batched(pcb)
         else:
             plan.precondition_mlp_batched(pcb, mlp_params, vbar)
         plan.apply_h(ik, V[nb:], veff, beta, dkb, out=HV[nb:])
-        plan.subspace_rr_batched([plan.make_block(ik, nb, 2 * nb, V, HV, active=active, eval=eval_, info=info)])
+        if aug is not None:
+            plan.apply_s(ik, V[nb:], aug[0], aug[1], out=SV[nb:])
+        plan.subspace_rr_batched([plan.make_block(ik, nb, 2 * nb, V, HV, active=active, eval=eval_, info=info,
+                                                  sv=SV)])
         hist.append(eval_.clone())
+    if aug is not None:
+        return hist, info, V[:nb], SV[:nb]
     return hist, info
 
 

@@ -36,7 +36,7 @@ SYMBOLS = [
     "fde_subspace_rr_batched", "fde_precondition_batched", "fde_grid_mean", "fde_precondition_mlp_batched",
     "fde_mlp_forward", "fde_mlp_workspace_bytes", "fde_mlp_loss_grad", "fde_mlp_adam", "fde_plan_set_gemm_mode",
     "fde_plan_set_tuning", "fde_energy_total", "fde_mlp_loss_grad_static", "fde_mix_pulay", "fde_density_l1",
-    "fde_frozen_environment",
+    "fde_frozen_environment", "fde_apply_s", "fde_aug_charges", "fde_aug_density",
 ]
 TUNE_APPLY_BPW = 1
 TUNE_STICK_GROUP = 2
@@ -67,7 +67,7 @@ _S = ctypes.c_size_t
 class Block(ctypes.Structure):
     """fde_block: one (subsystem, k-point) band block of the solver."""
     _fields_ = [("ik", _I), ("nb", _I), ("m", _I), ("v", _P), ("hv", _P), ("active", _P), ("t_active", _P),
-                ("eval", _P), ("rnorm", _P), ("info", _P)]
+                ("eval", _P), ("rnorm", _P), ("info", _P), ("sv", _P)]
 
 
 def _declare(lib):
@@ -98,6 +98,9 @@ def _declare(lib):
     lib.fde_grid_mean.argtypes = [_P, _P, _P, _P]
     lib.fde_density_l1.argtypes = [_P, _I, _P, _P, _P, _P]
     lib.fde_frozen_environment.argtypes = [_P, _I, _P, _P, _S, _P]
+    lib.fde_apply_s.argtypes = [_P, _I, _I, _P, _P, _I, _P, _P, _P]
+    lib.fde_aug_charges.argtypes = [_P, _I, _I, _P, _P, _I, _P, _P, _P, _P, _P]
+    lib.fde_aug_density.argtypes = [_P, _I, _P, _P, _P, _P]
     lib.fde_plan_set_gemm_mode.argtypes = [_P, _I]
     lib.fde_plan_set_tuning.argtypes = [_P, _I, _I]
     lib.fde_precondition_mlp_batched.argtypes = [_P, _I, _P, _P, _P, _P]
@@ -312,14 +315,20 @@ class Plan:
         self._check(self.lib.fde_precondition_batched(self.h, len(blocks), arr, self.be.stream()))
 
     def make_block(self, ik: int, nb: int, m: int, v, hv, active=None, t_active=None, eval=None, rnorm=None,
-                   info=None) -> Block:
+                   info=None, sv=None) -> Block:
+        """sv: the rows S v of a generalised problem (fde_apply_s), or None (S = 1)."""
         self._bands(v, ik, "v")
         self._bands(hv, ik, "hv")
         if v.shape[0] < m or hv.shape[0] < m:
             raise FdeError("block: v and hv need m rows")
+        if sv is not None:
+            self._bands(sv, ik, "sv")
+            if sv.shape[0] < m:
+                raise FdeError("block: sv needs m rows")
         return Block(ik, nb, m, v.data_ptr(), hv.data_ptr(), None if active is None else active.data_ptr(),
                      None if t_active is None else t_active.data_ptr(), None if eval is None else eval.data_ptr(),
-                     None if rnorm is None else rnorm.data_ptr(), None if info is None else info.data_ptr())
+                     None if rnorm is None else rnorm.data_ptr(), None if info is None else info.data_ptr(),
+                     None if sv is None else sv.data_ptr())
 
     def precondition(self, ik: int, x: torch.Tensor, hx: torch.Tensor, eval: torch.Tensor, t: torch.Tensor,
                      active: torch.Tensor, rnorm: torch.Tensor):
@@ -414,6 +423,47 @@ class Plan:
         self._f64(out, "out")
         self._check(self.lib.fde_density_l1(self.h, ns, _ptr(rho_sub), _ptr(rho_ref), _ptr(out), self.be.stream()))
         return out
+
+    def apply_s(self, ik: int, psi: torch.Tensor, beta, q, out=None):
+        """out = S psi = psi + beta q beta^H psi (q: float64 [nproj][nproj] device)."""
+        self._bands(psi, ik, "psi")
+        out = torch.empty_like(psi) if out is None else out
+        self._bands(out, ik, "out")
+        nproj = 0 if beta is None else beta.shape[0]
+        if nproj:
+            self._bands(beta, ik, "beta")
+            self._f64(q, "q")
+            if tuple(q.shape) != (nproj, nproj):
+                raise FdeError("q must be [nproj][nproj]")
+        self._check(self.lib.fde_apply_s(self.h, ik, psi.shape[0], _ptr(psi), _ptr(out), nproj, _ptr(beta),
+                                         _ptr(q), self.be.stream()))
+        return out
+
+    def aug_charges(self, ik: int, psi: torch.Tensor, occw, beta, q, atom_of, charges):
+        """charges[atom_of[i]] += sum_n occw_n Re(conj(P_in) (q P)_in), P = beta^H psi."""
+        self._bands(psi, ik, "psi")
+        self._bands(beta, ik, "beta")
+        self._f64(occw, "occw")
+        self._f64(q, "q")
+        self._f64(charges, "charges")
+        if atom_of.dtype != torch.int32 or atom_of.numel() != beta.shape[0]:
+            raise FdeError("atom_of must be int32 [nproj]")
+        if occw.numel() < psi.shape[0]:
+            raise FdeError("occw needs one weight per band")
+        self._check(self.lib.fde_aug_charges(self.h, ik, psi.shape[0], _ptr(psi), _ptr(occw), beta.shape[0],
+                                             _ptr(beta), _ptr(q), _ptr(atom_of), _ptr(charges), self.be.stream()))
+        return charges
+
+    def aug_density(self, atoms, charges, rho):
+        """rho += sum_a c_a g_a (atoms: float64 [natom][4] = x, y, z, width, on the device)."""
+        self._f64(atoms, "atoms")
+        self._f64(charges, "charges")
+        self._grid(rho, "rho")
+        if atoms.dim() != 2 or atoms.shape[1] != 4 or charges.numel() != atoms.shape[0]:
+            raise FdeError("atoms must be [natom][4] with one charge each")
+        self._check(self.lib.fde_aug_density(self.h, atoms.shape[0], _ptr(atoms), _ptr(charges), _ptr(rho),
+                                             self.be.stream()))
+        return rho
 
     def frozen_environment(self, rho_sub, out):
         """out[I] = sum_{J != I} rho_sub[J] (out [ns][N]), or into the second density of

@@ -935,3 +935,113 @@ def check_supersystem_comparison(be, prec, kinds, n_cycles=6, tol=1e-9):
         assert abs(got[k] - ref[k]) < tol * max(1.0, abs(ref[k])), (k, got[k], ref[k])
     assert ref["dens_diff"] > 1e-4    # FDE and KS densities do differ
     return got, ref
+
+
+# ---------------------------------------------------------------------------
+# Subsystem-specific augmentation: overlap S^I, generalised Rayleigh-Ritz and
+# Davidson, augmentation charge (Appendix, non-local pseudopotentials)
+# ---------------------------------------------------------------------------
+def _aug_setup(be, prec, nb, natoms=3, case=None, max_nb=None):
+    from oracle import augment as oaug  # noqa: F401
+    case = case or MEDIUM
+    plan = small_plan(be, prec, max_nb=max_nb or max(4, nb), max_nproj=4 * natoms, case=case)
+    cell = basis.Cell(case["L"], case["grid"])
+    rng = np.random.default_rng(4242)
+    atoms = [fde_synth.Atom(tuple(rng.uniform(0, 1, 3) * np.array(case["L"])), 1.0, 0.7, lmax=1,
+                            rbeta=0.8 + 0.05 * i, d_s=0.6, d_p=-0.25) for i in range(natoms)]
+    sph = basis.sphere(cell, case["ecut"], case["kf"][0])
+    beta, dkb = opseudo.kb_projectors(cell, sph, atoms)
+    q, atom_of = fde_synth.augmentation_q(atoms)
+    v = opseudo.local_potential(cell, case["ecut"], atoms)
+    tb = plan.kb_projectors(0, [a.pos for a in atoms], [a.lmax for a in atoms], [a.rbeta for a in atoms])
+    dev = plan.be.device
+    tq = torch.from_numpy(q).to(device=dev)
+    return plan, cell, sph, atoms, beta, dkb, q, atom_of, v, tb, tq
+
+
+def check_apply_s(be, prec, nb=9, natoms=3):
+    """S psi against the oracle; nb above max_nb exercises the band chunks, 20 atoms (80
+    projectors) the tiled projection."""
+    from oracle import augment as oaug
+    plan, cell, sph, atoms, beta, dkb, q, atom_of, v, tb, tq = _aug_setup(be, prec, nb, natoms, max_nb=4)
+    psi = fde_synth.random_complex(61, (nb, sph.npw))
+    out = plan.apply_s(0, to_dev(plan, psi, "c"), tb, tq)
+    be.sync()
+    ref = oaug.apply_s(psi, beta, q)
+    assert rel(host(out), ref) < TOL[prec], rel(host(out), ref)
+    # no projectors: a copy
+    out0 = plan.apply_s(0, to_dev(plan, psi, "c"), None, None)
+    be.sync()
+    assert np.array_equal(host(out0), psi.astype(host(out0).dtype))
+
+
+def check_subspace_rr_gen(be, prec, nb=12):
+    """Rayleigh-Ritz of the generalised problem on [X | T]-like rows (m = 2 nb) with an
+    inactive column: Ritz values, projectors X X^H, and S X = S applied to the new X."""
+    from oracle import augment as oaug
+    from oracle import hamiltonian as oh
+    plan, cell, sph, atoms, beta, dkb, q, atom_of, v, tb, tq = _aug_setup(be, prec, 2 * nb)
+    V = fde_synth.random_complex(62, (2 * nb, sph.npw)) / (1 + sph.kin)[None]
+    HV = oh.apply_h(cell, sph, V, v, beta, dkb)
+    SV = oaug.apply_s(V, beta, q)
+    act = np.ones(2 * nb, bool)
+    act[nb + 2] = False
+    Xr, HXr, SXr, lr = oaug.subspace_rr_gen(V, HV, SV, nb, act)
+    dev = plan.be.device
+    tV, tHV, tSV = to_dev(plan, V, "c"), to_dev(plan, HV, "c"), to_dev(plan, SV, "c")
+    ev = torch.zeros(nb, dtype=torch.float64, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    plan.subspace_rr_batched([plan.make_block(0, nb, 2 * nb, tV, tHV, active=torch.from_numpy(act.astype(np.uint8)).to(dev),
+                                              eval=ev, info=info, sv=tSV)])
+    be.sync()
+    assert int(host(info)[0]) == 0
+    tol, ptol = (1e-10, 1e-9) if prec == fde.F64 else (2e-5, 1e-4)
+    assert np.max(np.abs(host(ev) - lr)) < tol * max(1.0, np.max(np.abs(lr))), np.max(np.abs(host(ev) - lr))
+    Xg = host(tV)[:nb].astype(np.complex128)
+    assert np.max(np.abs(Xg.T @ Xg.conj() - Xr.T @ Xr.conj())) < ptol
+    assert rel(host(tSV)[:nb].astype(np.complex128), oaug.apply_s(Xg, beta, q)) < (1e-10 if prec == fde.F64 else 1e-4)
+    assert np.max(np.abs(Xg.conj() @ host(tSV)[:nb].T - np.eye(nb))) < (1e-10 if prec == fde.F64 else 1e-4)
+
+
+def check_davidson_gen(be, prec, nb=6, n_iter=8):
+    """The generalised band solver at a fixed potential, iteration by iteration against
+    the oracle's Davidson with the same start."""
+    from oracle import augment as oaug
+    from oracle import hamiltonian as oh
+    from paper_1406_7803_amd import driver
+    plan, cell, sph, atoms, beta, dkb, q, atom_of, v, tb, tq = _aug_setup(be, prec, nb)
+    X0 = fde_synth.random_complex(63, (nb, sph.npw)) / (1 + sph.kin)[None]
+    Hf = lambda Y: oh.apply_h(cell, sph, Y, v, beta, dkb)  # noqa: E731
+    Sf = lambda Y: oaug.apply_s(Y, beta, q)  # noqa: E731
+    _, _, _, hist = oaug.davidson_gen(Hf, Sf, X0, n_iter, sph.kin)
+    g = driver.davidson_fixed(plan, 0, to_dev(plan, X0, "c"), to_dev(plan, v, "r"), n_iter, beta=tb,
+                              dkb=to_dev(plan, dkb, "d"), aug=(tb, tq))
+    ghist, info, X, SX = g
+    be.sync()
+    assert int(host(info)[0]) == 0
+    tol = 1e-10 if prec == fde.F64 else 2e-5
+    for it, (a, b) in enumerate(zip(ghist, hist[1:])):
+        assert np.max(np.abs(host(a) - b)) < tol * max(1.0, np.max(np.abs(b))), (it, np.max(np.abs(host(a) - b)))
+    Xg = host(X).astype(np.complex128)
+    assert np.max(np.abs(Xg.conj() @ host(SX).T - np.eye(nb))) < (1e-10 if prec == fde.F64 else 1e-4)
+
+
+def check_aug_density(be, prec, nb=5):
+    """Atom charges from the projections and the augmentation density on the grid."""
+    from oracle import augment as oaug
+    plan, cell, sph, atoms, beta, dkb, q, atom_of, v, tb, tq = _aug_setup(be, prec, nb)
+    X = fde_synth.random_complex(64, (nb, sph.npw)) / (1 + sph.kin)[None]
+    occw = np.linspace(2.0, 0.5, nb)
+    dev = plan.be.device
+    ch = torch.full((len(atoms),), 0.25, dtype=torch.float64, device=dev)  # accumulates
+    plan.aug_charges(0, to_dev(plan, X, "c"), to_dev(plan, occw, "d"), tb, tq,
+                     torch.from_numpy(atom_of).to(dev), ch)
+    be.sync()
+    ref = oaug.atom_charges(beta, X, occw, q, atom_of)
+    assert np.max(np.abs(host(ch) - 0.25 - ref)) < (1e-11 if prec == fde.F64 else 1e-5) * max(1.0, np.max(np.abs(ref)))
+    at = torch.tensor([[*a.pos, a.rbeta] for a in atoms], dtype=torch.float64, device=dev)
+    rho = plan.zeros_grid() + 0.125
+    plan.aug_density(at, to_dev(plan, ref, "d"), rho)
+    be.sync()
+    want = oaug.augmentation_density(cell, MEDIUM["ecut"], [a.pos for a in atoms], [a.rbeta for a in atoms], ref)
+    assert rel(host(rho).astype(np.float64) - 0.125, want) < TOL[prec], rel(host(rho).astype(np.float64) - 0.125, want)

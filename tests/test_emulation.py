@@ -232,3 +232,15 @@ def test_frozen_environment(be, prec):
 
 def test_trajectory_freeze_thaw(be):
     pc.check_trajectory_freeze_thaw(be, fde.F64, 2, 2, 1e-10, 1e-10)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_augmentation(be, prec):
+    pc.check_apply_s(be, prec)
+    pc.check_apply_s(be, prec, nb=5, natoms=20)
+    pc.check_subspace_rr_gen(be, prec)
+    pc.check_aug_density(be, prec)
+
+
+def test_generalised_davidson(be):
+    pc.check_davidson_gen(be, fde.F64)

@@ -526,3 +526,18 @@ def test_trajectory_freeze_thaw(be):
     pc.check_trajectory_freeze_thaw(be, fde.F64, 2, 3, 1e-10, 1e-10,
                                     mixer=dict(kind="pulay", nhist=4, beta=0.5, q0=0.6))
     pc.check_trajectory_freeze_thaw(be, fde.F32, 2, 3, 1e-6, 1e-5)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_augmentation(be, prec):
+    """Subsystem-specific augmentation: S psi (band chunks; 80 projectors on the tiled
+    projection), the generalised Rayleigh-Ritz, atom charges and the augmentation density."""
+    pc.check_apply_s(be, prec)
+    pc.check_apply_s(be, prec, nb=5, natoms=20)
+    pc.check_subspace_rr_gen(be, prec)
+    pc.check_aug_density(be, prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_generalised_davidson(be, prec):
+    pc.check_davidson_gen(be, prec)
