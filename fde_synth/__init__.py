@@ -54,6 +54,8 @@ class Subsystem:
     kweight: np.ndarray               # [nk], sums to 1
     smearing: str                     # "integer" | "fermi-dirac"
     sigma: float = 0.0                # smearing width (Ha)
+    aug: bool = False                 # augmentation overlap on the subsystem's own projectors
+                                      # (augmentation_q; Gaussian augmentation of width rbeta)
 
 
 @dataclass

@@ -88,24 +88,82 @@ def initial_bands(st: Setup):
     return X
 
 
+def orthonormal_start(st: Setup, I: int, ik: int, X: np.ndarray) -> np.ndarray:
+    """Orthonormal (S^I-orthonormal when augmented) rows spanning X."""
+    ag = aug_of(st, I)
+    if ag is None:
+        return subspace.orthonormalise(X)
+    from . import augment
+    SX = augment.apply_s(X, st.proj[(I, ik)][0], ag[0])
+    return augment.subspace_rr_gen(X, SX, SX, X.shape[0])[0]
+
+
+def subsystem_density(st: Setup, I: int, Xs, occws) -> np.ndarray:
+    """rho_I from the bands of every k-point of subsystem I, plus, when augmented, the
+    augmentation density of its atoms' charges (summed over k)."""
+    sysm = st.system
+    s = sysm.subsystems[I]
+    rho = np.zeros(st.cell.shape)
+    ag = aug_of(st, I)
+    charges = None
+    for j, ik in enumerate(sysm.k_index(I)):
+        rho += dens.density(st.cell, st.spheres[ik], Xs[j], occws[j])
+        if ag is not None:
+            from . import augment
+            c = augment.atom_charges(st.proj[(I, ik)][0], Xs[j], occws[j], ag[0], ag[1])
+            charges = c if charges is None else charges + c
+    if ag is not None:
+        from . import augment
+        owners = [a for a in s.atoms if a.lmax >= 0]
+        rho += augment.augmentation_density(st.cell, sysm.ecut, [a.pos for a in owners], [a.rbeta for a in owners],
+                                            charges)
+    return rho
+
+
 def initial_density(st: Setup, X) -> np.ndarray:
     sysm = st.system
     rho = np.zeros((len(sysm.subsystems),) + st.cell.shape)
     for I, s in enumerate(sysm.subsystems):
+        Xs, occws = [], []
         for j, ik in enumerate(sysm.k_index(I)):
-            Xo = subspace.orthonormalise(X[I][j])
-            occw = np.full(s.nbands, s.kweight[j] * s.nelec / s.nbands)
-            rho[I] += dens.density(st.cell, st.spheres[ik], Xo, occw)
+            Xs.append(orthonormal_start(st, I, ik, X[I][j]))
+            occws.append(np.full(s.nbands, s.kweight[j] * s.nelec / s.nbands))
+        rho[I] = subsystem_density(st, I, Xs, occws)
     return rho
+
+
+def aug_of(st: Setup, I: int):
+    """(q, atom_of) of an augmented subsystem (the Appendix's subsystem-specific
+    projectors), else None."""
+    sub = st.system.subsystems[I]
+    if not getattr(sub, "aug", False):
+        return None
+    return fde_synth.augmentation_q(sub.atoms)
 
 
 def davidson(st: Setup, I: int, ik: int, X: np.ndarray, veff: np.ndarray, n_david: int,
              history=None):
-    """Per-cycle solve of one (subsystem, k): RR on X, then n_david iterations."""
+    """Per-cycle solve of one (subsystem, k): RR on X, then n_david iterations (the
+    generalised problem H x = e S^I x for an augmented subsystem)."""
     sph = st.spheres[ik]
     beta, dkb = st.proj[(I, ik)]
     nb = X.shape[0]
     H = lambda Y: ham.apply_h(st.cell, sph, Y, veff, beta, dkb)  # noqa: E731
+    ag = aug_of(st, I)
+    if ag is not None:
+        from . import augment
+        S = lambda Y: augment.apply_s(Y, beta, ag[0])  # noqa: E731
+        X, HX, SX, lam = augment.subspace_rr_gen(X, H(X), S(X), nb)
+        if history is not None:
+            history.append(lam.copy())
+        for _ in range(n_david):
+            T, active, _ = augment.precondition_gen(X, HX, SX, lam, sph.kin)
+            act = np.concatenate([np.ones(nb, dtype=bool), active])
+            X, HX, SX, lam = augment.subspace_rr_gen(np.vstack([X, T]), np.vstack([HX, H(T)]),
+                                                     np.vstack([SX, S(T)]), nb, act)
+            if history is not None:
+                history.append(lam.copy())
+        return X, HX, lam
     HX = H(X)
     X, HX, lam = subspace.subspace_rr(X, HX, nb)
     if history is not None:
@@ -177,7 +235,7 @@ def run(system, n_cycles=None, n_david=None, kinds=None, st: Setup = None, callb
     X = initial_bands(st)
     rho_in = initial_density(st, X)
     for I in range(len(X)):
-        X[I] = [subspace.orthonormalise(x) for x in X[I]]
+        X[I] = [orthonormal_start(st, I, ik, x) for ik, x in zip(system.k_index(I), X[I])]
     records = []
     inner = n_inner if scheme == "freeze-thaw" else 1
     for c in range(n_cycles * inner):
@@ -199,8 +257,7 @@ def run(system, n_cycles=None, n_david=None, kinds=None, st: Setup = None, callb
             for j, ik in enumerate(ks):
                 X[I][j], _, eps[j] = davidson(st, I, ik, X[I][j], veff[I], n_david)
             f, mu = occ.occupations(eps, s.kweight, s.nelec, s.smearing, s.sigma)
-            for j, ik in enumerate(ks):
-                rho_out[I] += dens.density(st.cell, st.spheres[ik], X[I][j], s.kweight[j] * f[j])
+            rho_out[I] = subsystem_density(st, I, X[I], [s.kweight[j] * f[j] for j in range(len(ks))])
             eps_all.append(eps)
             mus.append(mu)
         rho_in = mix(rho_in, rho_out)
