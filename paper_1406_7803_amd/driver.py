@@ -40,6 +40,8 @@ class BandBlock:
     rnorm: torch.Tensor  # [nb] float64
     info: torch.Tensor   # [1] int32
     nb: int
+    SV: Optional[torch.Tensor] = None   # [2 nb][npw] S V of an augmented subsystem
+    aug_q: Optional[torch.Tensor] = None  # [nproj][nproj] float64 augmentation overlaps
 
 
 @dataclass
@@ -101,12 +103,30 @@ class Engine:
                 raw = torch.from_numpy(fde_synth.random_coefficients(s.cfg, s.geometry, I, ik, nb, npw)).to(
                     dtype=p.cdtype, device=dev)
                 p.init_bands(ik, raw, out=V[:nb])
+                SV = aq = None
+                if getattr(sub, "aug", False):
+                    if beta is None:
+                        raise fde.FdeError("an augmented subsystem needs projectors")
+                    if self.mlp_params is not None:
+                        raise fde.FdeError("the learned preconditioner takes standard problems only")
+                    SV = torch.zeros_like(V)
+                    aq = torch.from_numpy(fde_synth.augmentation_q(sub.atoms)[0]).to(device=dev)
                 row.append(BandBlock(I, ik, j, V, torch.zeros_like(V), beta, dkb,
                                      torch.zeros(nb, dtype=torch.float64, device=dev),
                                      torch.ones(2 * nb, dtype=torch.uint8, device=dev),
                                      torch.zeros(nb, dtype=torch.float64, device=dev),
-                                     torch.zeros(1, dtype=torch.int32, device=dev), nb))
+                                     torch.zeros(1, dtype=torch.int32, device=dev), nb, SV, aq))
             self.blocks.append(row)
+        # augmentation charges and atoms (x, y, z, width) of the augmented subsystems
+        self.aug = {}
+        for I, sub in enumerate(s.subsystems):
+            if getattr(sub, "aug", False):
+                owners = [a for a in sub.atoms if a.lmax >= 0]
+                _, atom_of = fde_synth.augmentation_q(sub.atoms)
+                self.aug[I] = dict(
+                    atom_of=torch.from_numpy(atom_of).to(device=dev),
+                    atoms=torch.tensor([[*a.pos, a.rbeta] for a in owners], dtype=torch.float64, device=dev),
+                    charges=torch.zeros(len(owners), dtype=torch.float64, device=dev))
         ns = len(s.subsystems)
         self.rho_in = p.zeros_grid(ns)
         self.rho_out = p.zeros_grid(ns)
@@ -171,24 +191,32 @@ class Engine:
         """Orthonormalise the initial bands and take their density with f = N_I / nb."""
         p = self.plan
         for I, sub in enumerate(self.system.subsystems):
+            occws = []
             for b in self.blocks[I]:
                 X = b.V[:b.nb]
                 HX = b.HV[:b.nb]
-                HX.copy_(X)                       # A = S: the Rayleigh-Ritz step only orthonormalises
-                p.subspace_rr(b.ik, X, HX, b.nb, eval=b.eval, info=b.info)
                 w = float(sub.kweight[b.j]) * sub.nelec / sub.nbands
                 occw = torch.full((b.nb,), w, dtype=torch.float64, device=self.be.device)
-                p.density(b.ik, X, occw, self.rho_in[I])
+                occws.append(occw)
+                if b.SV is None:
+                    HX.copy_(X)                   # A = S: the Rayleigh-Ritz step only orthonormalises
+                    p.subspace_rr(b.ik, X, HX, b.nb, eval=b.eval, info=b.info)
+                else:                             # S-orthonormal: A = S = X^H S X
+                    p.apply_s(b.ik, X, b.beta, b.aug_q, out=b.SV[:b.nb])
+                    HX.copy_(b.SV[:b.nb])
+                    p.subspace_rr_batched([p.make_block(b.ik, b.nb, b.nb, b.V, b.HV, eval=b.eval, info=b.info,
+                                                        sv=b.SV)])
+            self._subsystem_density(I, occws, self.rho_in[I])
 
     @staticmethod
     def _rr_blocks(g: SolverGroup, m_of):
-        return [g.plan.make_block(b.ik, b.nb, m_of(b), b.V, b.HV, active=b.active, eval=b.eval, info=b.info)
-                for b in g.blocks]
+        return [g.plan.make_block(b.ik, b.nb, m_of(b), b.V, b.HV, active=b.active, eval=b.eval, info=b.info,
+                                  sv=b.SV) for b in g.blocks]
 
     @staticmethod
     def _pc_blocks(g: SolverGroup):
         return [g.plan.make_block(b.ik, b.nb, b.nb, b.V, b.HV, t_active=b.active[b.nb:], eval=b.eval,
-                                  rnorm=b.rnorm) for b in g.blocks]
+                                  rnorm=b.rnorm, sv=b.SV) for b in g.blocks]
 
     def solve(self, n_david: int):
         """Every band block in lockstep within its group: H X and Rayleigh-Ritz on X, then
@@ -222,10 +250,25 @@ class Engine:
                         p.precondition_mlp_batched(self._pc_blocks(g), self.mlp_params, g.vbar)
                     for b in g.blocks:
                         p.apply_h(b.ik, b.V[b.nb:], self.veff[b.isub], b.beta, b.dkb, out=b.HV[b.nb:])
+                        if b.SV is not None:
+                            p.apply_s(b.ik, b.V[b.nb:], b.beta, b.aug_q, out=b.SV[b.nb:])
                     p.subspace_rr_batched(self._rr_blocks(g, lambda b: 2 * b.nb))
         for g in self.groups:
             if g.stream is not None:
                 main.wait_stream(g.stream)
+
+    def _subsystem_density(self, I: int, occws, rho):
+        """rho += the density of subsystem I's bands over its k-points and, when the
+        subsystem is augmented, the augmentation density of its atoms' charges."""
+        p = self.plan
+        for b, occw in zip(self.blocks[I], occws):
+            p.density(b.ik, b.V[:b.nb], occw, rho)
+        if I in self.aug:
+            a = self.aug[I]
+            a["charges"].zero_()
+            for b, occw in zip(self.blocks[I], occws):
+                p.aug_charges(b.ik, b.V[:b.nb], occw, b.beta, b.aug_q, a["atom_of"], a["charges"])
+            p.aug_density(a["atoms"], a["charges"], rho)
 
     def _frozen_potentials(self):
         """Freeze-and-thaw (Fig. 1b caption: each subsystem iterated against the densities
@@ -263,8 +306,7 @@ class Engine:
             fde.occupations(self.be, self.eps[I], self.wk[I], sub.nelec, mode, max(sub.sigma, 1e-300),
                             occw=self.occw[I], mu=self.mu[I], info=self.oinfo[I])
             self.rho_out[I].zero_()
-            for b in self.blocks[I]:
-                p.density(b.ik, b.V[:b.nb], self.occw[I][b.j], self.rho_out[I])
+            self._subsystem_density(I, [self.occw[I][b.j] for b in self.blocks[I]], self.rho_out[I])
         if self.mixer is None:
             fde.mix(self.be, self.rho_in, self.rho_out, s.mix_beta)
         else:

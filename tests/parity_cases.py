@@ -1045,3 +1045,25 @@ def check_aug_density(be, prec, nb=5):
     be.sync()
     want = oaug.augmentation_density(cell, MEDIUM["ecut"], [a.pos for a in atoms], [a.rbeta for a in atoms], ref)
     assert rel(host(rho).astype(np.float64) - 0.125, want) < TOL[prec], rel(host(rho).astype(np.float64) - 0.125, want)
+
+
+def check_trajectory_aug(be, prec, n_cycles, eps_tol, drho_tol):
+    """A k-point cell with projectors whose first subsystem is augmented (generalised band
+    solver, augmentation density) and whose second is not, against the oracle cycle."""
+    s = fde_synth.tiny(4, with_kb=True, nbands=3, kfrac=[(0.25, 0.0, 0.0), (-0.25, 0.0, 0.0)], grid=(12, 12, 15))
+    s.subsystems[0].aug = True
+    recs, _, st = oscf.run(s, n_cycles=n_cycles)
+    eng = driver.Engine(s, prec=prec, backend=be)
+    worst = (0.0, 0.0)
+    for c in range(n_cycles):
+        eng.cycle()
+        be.sync()
+        for I, sub in enumerate(s.subsystems):
+            e = np.max(np.abs(host(eng.eps[I]) - recs[c].eps[I]))
+            d = float(np.sum(np.abs(host(eng.rho_out[I]) - recs[c].rho_out[I]))) * st.cell.dV
+            q = float(host(eng.rho_out[I]).astype(np.float64).sum()) * st.cell.dV
+            assert abs(q - sub.nelec) < (1e-10 if prec == fde.F64 else 1e-4), (c, I, q)
+            worst = (max(worst[0], e), max(worst[1], d))
+    assert all(int(host(b.info)[0]) == 0 for row in eng.blocks for b in row)
+    assert worst[0] < eps_tol and worst[1] < drho_tol, worst
+    return worst

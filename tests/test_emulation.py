@@ -244,3 +244,7 @@ def test_augmentation(be, prec):
 
 def test_generalised_davidson(be):
     pc.check_davidson_gen(be, fde.F64)
+
+
+def test_trajectory_augmented(be):
+    pc.check_trajectory_aug(be, fde.F64, 3, 1e-10, 1e-10)

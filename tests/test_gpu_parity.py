@@ -541,3 +541,9 @@ def test_augmentation(be, prec):
 @pytest.mark.parametrize("prec", PRECS)
 def test_generalised_davidson(be, prec):
     pc.check_davidson_gen(be, prec)
+
+
+def test_trajectory_augmented(be):
+    """One augmented and one plain subsystem over three cycles (FP64 and FP32)."""
+    pc.check_trajectory_aug(be, fde.F64, 3, 1e-10, 1e-10)
+    pc.check_trajectory_aug(be, fde.F32, 3, 1e-6, 1e-5)
