@@ -288,6 +288,10 @@ def band_terms(st: Setup, X, eps_f):
 def energies(st: Setup, X, eps_f, veff_in, rho_out):
     """E_FDE both ways plus the band-energy identity terms (see module docstring)."""
     sysm = st.system
+    if any(aug_of(st, I) is not None for I in range(len(sysm.subsystems))):
+        # an augmented subsystem's energy needs the one-centre terms of its augmentation
+        # spheres, which the synthetic overlaps do not define
+        raise ValueError("energies of augmented subsystems are not defined")
     cell = st.cell
     _, en = embed.embed_potential(cell, sysm.ecut, rho_out, st.vloc, sysm.rho_thr, **st.kinds)
     ns = len(sysm.subsystems)

@@ -322,6 +322,11 @@ class Engine:
         fde_energy_total. Returns the device tensor [ns + 4] of fde_energy_total
         (E_K per subsystem, T^nad, E_xc^nad, E_FDE directly, E_FDE via fragments)."""
         s, p = self.system, self.plan
+        if self.aug:
+            # the augmented energy needs the one-centre terms of each atom's augmentation
+            # sphere (Appendix, non-local pseudopotentials), which the synthetic q blocks
+            # do not define
+            raise fde.FdeError("energies of augmented subsystems are not defined")
         ns = len(s.subsystems)
         dev = self.be.device
         if not hasattr(self, "_e_buf"):

@@ -991,11 +991,22 @@ def check_subspace_rr_gen(be, prec, nb=12):
     tV, tHV, tSV = to_dev(plan, V, "c"), to_dev(plan, HV, "c"), to_dev(plan, SV, "c")
     ev = torch.zeros(nb, dtype=torch.float64, device=dev)
     info = torch.zeros(1, dtype=torch.int32, device=dev)
+    # a standard problem in the same batch (no S V rows: the third rotation skips it)
+    W = fde_synth.random_complex(65, (2 * nb, sph.npw)) / (1 + sph.kin)[None]
+    HW = oh.apply_h(cell, sph, W, v, beta, dkb)
+    Xw, _, lw = osub.subspace_rr(W, HW, nb)
+    tW, tHW = to_dev(plan, W, "c"), to_dev(plan, HW, "c")
+    ev2 = torch.zeros(nb, dtype=torch.float64, device=dev)
+    info2 = torch.zeros(1, dtype=torch.int32, device=dev)
     plan.subspace_rr_batched([plan.make_block(0, nb, 2 * nb, tV, tHV, active=torch.from_numpy(act.astype(np.uint8)).to(dev),
-                                              eval=ev, info=info, sv=tSV)])
+                                              eval=ev, info=info, sv=tSV),
+                              plan.make_block(0, nb, 2 * nb, tW, tHW, eval=ev2, info=info2)])
     be.sync()
-    assert int(host(info)[0]) == 0
+    assert int(host(info)[0]) == 0 and int(host(info2)[0]) == 0
     tol, ptol = (1e-10, 1e-9) if prec == fde.F64 else (2e-5, 1e-4)
+    assert np.max(np.abs(host(ev2) - lw)) < tol * max(1.0, np.max(np.abs(lw)))
+    Wg = host(tW)[:nb].astype(np.complex128)
+    assert np.max(np.abs(Wg.T @ Wg.conj() - Xw.T @ Xw.conj())) < ptol
     assert np.max(np.abs(host(ev) - lr)) < tol * max(1.0, np.max(np.abs(lr))), np.max(np.abs(host(ev) - lr))
     Xg = host(tV)[:nb].astype(np.complex128)
     assert np.max(np.abs(Xg.T @ Xg.conj() - Xr.T @ Xr.conj())) < ptol
@@ -1066,4 +1077,6 @@ def check_trajectory_aug(be, prec, n_cycles, eps_tol, drho_tol):
             worst = (max(worst[0], e), max(worst[1], d))
     assert all(int(host(b.info)[0]) == 0 for row in eng.blocks for b in row)
     assert worst[0] < eps_tol and worst[1] < drho_tol, worst
+    with pytest.raises(fde.FdeError, match="augmented"):
+        eng.total_energies()
     return worst

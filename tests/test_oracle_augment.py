@@ -1,6 +1,7 @@
 """Pins of the oracle's augmentation: overlap operator, generalised Rayleigh-Ritz and
 augmentation charge (CPU only)."""
 import numpy as np
+import pytest
 import scipy.linalg as sla
 
 import fde_synth
@@ -121,3 +122,12 @@ def test_augmented_cycle_conserves_charge_and_solves_the_generalised_problem():
         else:
             ev = np.linalg.eigvalsh(H)[:2]
         assert np.max(np.abs(last.eps[I][0][:2] - ev)) < 1e-8, (I, last.eps[I][0][:2], ev)
+
+
+def test_energies_of_augmented_subsystems_are_rejected():
+    """The augmented energy needs one-centre terms the synthetic overlaps do not define."""
+    from oracle import scf
+    s = _aug_system()
+    recs, X, st = scf.run(s, n_cycles=1, n_david=1)
+    with pytest.raises(ValueError, match="augmented"):
+        scf.energies(st, X, [], recs[-1].veff, recs[-1].rho_out)
