@@ -491,7 +491,7 @@ def main():
         "config": {"workload": names[a.workload], "band_applies_per_cycle": per_cycle,
                    "davidson_per_cycle": system.n_david, "subspace_products": a.gemm,
                    "launch": "eager" if a.eager else "one HIP graph per cycle",
-                   "autotune": None if tuned is None else {k: tuned[k] for k in ("plane", "rows", "bpw", "sz")},
+                   "autotune": None if tuned is None else {k: tuned[k] for k in ("plane", "rows", "bpw", "zlds", "sz")},
                    "solver_streams": a.streams, "parallelism": "single GPU"},
         "isolated_apply_h": isolated,
         "roofline": roof,

@@ -126,7 +126,7 @@ fde_status fde_plan_set_workspace(fde_plan* plan, void* d_ws, size_t bytes, int 
  * z-FFT passes of fde_apply_h and fde_density (a power of two, capped at 16
  * and by the LDS budget; used by the LDS z-passes). FDE_TUNE_Z_REGISTER: 1
  * keeps the LDS z-passes where a four-step register z-FFT exists (N3 = 240,
- * 120). FDE_TUNE_PLANE_KIND: the in-plane pass of fde_apply_h and
+ * 120, and 432 in FP32 plans). FDE_TUNE_PLANE_KIND: the in-plane pass of fde_apply_h and
  * fde_density -- 1 whole-line register FFTs, 2 LDS Stockham passes, 3 two-factor
  * FFTs in LDS (used where the kind applies; otherwise the automatic choice).
  * FDE_TUNE_PLANE_ROWS: rows per batch of the two-factor pass (LDS size).

@@ -8,6 +8,12 @@
 // row pass works on the rows in that order, and the forward column transform
 // takes slot order back to natural order, so no reordering pass is needed.
 //
+// LDS layout against bank conflicts: in the row buffer element e = a + P k of
+// a line sits at a + (P + 1) k, so the lanes of the strided steps (a fixed,
+// k = lane) hit distinct banks as well as those of the contiguous ones; the
+// twiddles of each step are stored in the order its lanes read them (lane
+// index fastest); stick positions are 16-bit.
+//
 // Per band and z-plane (workgroup of 256 threads; one z-plane, BPW bands):
 //   1. compact plane P[y][xa] (only the nxa active x-columns) = zeros, then the
 //      ncol sticks of the band at their positions
@@ -52,18 +58,21 @@ FDE_HD constexpr Split2 split2(int n) {
 }
 inline bool plane4_len_ok(int n) { return split2(n).p > 0; }
 
+// Twiddle tables of one line length N = P Q (w = exp(-2 pi i / N)):
+// ta[k P + a] = w^{a k} (a < P, k < Q) for the steps whose lane is a, and
+// tb[m Q + k2] = w^{k2 m} (k2 < Q, m < P) for those whose lane is k2.
+
 // Inverse, step 1 (lane a < P): Q-point DFT over positions a + P b, twiddle
-// w^{a k}, back to positions a + P k. L: line base, es: element stride, tw:
-// the N twiddles exp(-2 pi i m / N).
+// w^{a k}, back to positions a + P k. L: line base, es: element stride.
 template <typename T, int N>
-FDE_HD void inv_step1(cplx<T>* L, int es, int a, const cplx<T>* tw) {
+FDE_HD void inv_step1(cplx<T>* L, int es, int a, const cplx<T>* ta) {
   constexpr int P = split2(N).p, Q = split2(N).q;
   cplx<T> v[Q];
 #pragma unroll
   for (int b = 0; b < Q; ++b) v[b] = L[(a + P * b) * es];
   reg_fft<T, true, Q>(v, nullptr);
 #pragma unroll
-  for (int k = 1; k < Q; ++k) v[k] = cmulc(tw[(a * k) % N], v[k]);
+  for (int k = 1; k < Q; ++k) v[k] = cmulc(ta[k * P + a], v[k]);
 #pragma unroll
   for (int k = 0; k < Q; ++k) L[(a + P * k) * es] = v[k];
 }
@@ -84,14 +93,14 @@ FDE_HD void inv_step2(cplx<T>* L, int es, int k2) {
 // Forward, step 1: lane k2 < Q, P-point DFT over slots k1 + P k2 (values at
 // y = Q k1 + k2), twiddle w^{-k2 m1}, back to slots m1 + P k2.
 template <typename T, int N>
-FDE_HD void fwd_step1(cplx<T>* L, int es, int k2, const cplx<T>* tw) {
-  constexpr int P = split2(N).p;
+FDE_HD void fwd_step1(cplx<T>* L, int es, int k2, const cplx<T>* tb) {
+  constexpr int P = split2(N).p, Q = split2(N).q;
   cplx<T> v[P];
 #pragma unroll
   for (int k1 = 0; k1 < P; ++k1) v[k1] = L[(k1 + P * k2) * es];
   reg_fft<T, false, P>(v, nullptr);
 #pragma unroll
-  for (int m1 = 1; m1 < P; ++m1) v[m1] = tw[(k2 * m1) % N] * v[m1];
+  for (int m1 = 1; m1 < P; ++m1) v[m1] = tb[m1 * Q + k2] * v[m1];
 #pragma unroll
   for (int m1 = 0; m1 < P; ++m1) L[(m1 + P * k2) * es] = v[m1];
 }
@@ -117,7 +126,7 @@ FDE_HD void fwd_step2(cplx<T>* L, int es, int m1) {
 // stride nxa). Lanes run with xa fastest, so neighbouring lanes touch
 // neighbouring LDS words.
 template <typename T, bool INV, class Ctx>
-FDE_HD void plane4_columns(const Ctx& c, cplx<T>* P, int N2, int nxa, const cplx<T>* tw2) {
+FDE_HD void plane4_columns(const Ctx& c, cplx<T>* P, int N2, int nxa, const cplx<T>* ta2, const cplx<T>* tb2) {
   const Split2 sp = split2(N2);
   const int n1 = INV ? sp.p : sp.q;  // lanes per line in the first step
   const int n2 = INV ? sp.q : sp.p;
@@ -126,7 +135,7 @@ FDE_HD void plane4_columns(const Ctx& c, cplx<T>* P, int N2, int nxa, const cplx
     switch (N2) {
 #define FDE_C1(NN) \
   case NN:         \
-    if (INV) inv_step1<T, NN>(P + xa, nxa, j, tw2); else fwd_step1<T, NN>(P + xa, nxa, j, tw2); break;
+    if (INV) inv_step1<T, NN>(P + xa, nxa, j, ta2); else fwd_step1<T, NN>(P + xa, nxa, j, tb2); break;
       FDE_SPLIT2_CASES(FDE_C1)
 #undef FDE_C1
       default: break;
@@ -147,11 +156,14 @@ FDE_HD void plane4_columns(const Ctx& c, cplx<T>* P, int N2, int nxa, const cplx
   c.sync();
 }
 
+// Row-buffer length of a line of N = P Q points (element a + P k at a + (P + 1) k).
+FDE_HD constexpr int rrow_len(int n) { return n + split2(n).q; }
+
 // Row step 1 for row r of the batch (plane slot s): lane a gathers the active
 // inputs e = a + P1 b (centred index of e in [mlo, mlo + nxa)), Q1-point
-// inverse DFT, twiddle, into R[r][a + P1 k].
+// inverse DFT, twiddle, into R[r] at element a + P1 k.
 template <typename T, int N>
-FDE_HD void row_step1(const cplx<T>* Prow, cplx<T>* Rr, int a, int nxa, int mlo, const cplx<T>* tw) {
+FDE_HD void row_step1(const cplx<T>* Prow, cplx<T>* Rr, int a, int nxa, int mlo, const cplx<T>* ta) {
   constexpr int P = split2(N).p, Q = split2(N).q;
   cplx<T> v[Q];
 #pragma unroll
@@ -164,19 +176,19 @@ FDE_HD void row_step1(const cplx<T>* Prow, cplx<T>* Rr, int a, int nxa, int mlo,
   }
   reg_fft<T, true, Q>(v, nullptr);
 #pragma unroll
-  for (int k = 1; k < Q; ++k) v[k] = cmulc(tw[(a * k) % N], v[k]);
+  for (int k = 1; k < Q; ++k) v[k] = cmulc(ta[k * P + a], v[k]);
 #pragma unroll
-  for (int k = 0; k < Q; ++k) Rr[a + P * k] = v[k];
+  for (int k = 0; k < Q; ++k) Rr[a + (P + 1) * k] = v[k];
 }
 
 // Row step 2 of the H application (lane k2): inverse P1-point DFT gives u at
 // x = Q1 k1 + k2; times V_eff; forward P1-point DFT over k1 and twiddle.
 template <typename T, int N>
-FDE_HD void row_step2_h(cplx<T>* Rr, int k2, const T* __restrict__ vrow, const cplx<T>* tw) {
+FDE_HD void row_step2_h(cplx<T>* Rr, int k2, const T* __restrict__ vrow, const cplx<T>* tb) {
   constexpr int P = split2(N).p, Q = split2(N).q;
   cplx<T> v[P];
 #pragma unroll
-  for (int a = 0; a < P; ++a) v[a] = Rr[a + P * k2];
+  for (int a = 0; a < P; ++a) v[a] = Rr[a + (P + 1) * k2];
   reg_fft<T, true, P>(v, nullptr);
 #pragma unroll
   for (int k1 = 0; k1 < P; ++k1) {
@@ -185,9 +197,9 @@ FDE_HD void row_step2_h(cplx<T>* Rr, int k2, const T* __restrict__ vrow, const c
   }
   reg_fft<T, false, P>(v, nullptr);
 #pragma unroll
-  for (int m1 = 1; m1 < P; ++m1) v[m1] = tw[(k2 * m1) % N] * v[m1];
+  for (int m1 = 1; m1 < P; ++m1) v[m1] = tb[m1 * Q + k2] * v[m1];
 #pragma unroll
-  for (int m1 = 0; m1 < P; ++m1) Rr[m1 + P * k2] = v[m1];
+  for (int m1 = 0; m1 < P; ++m1) Rr[m1 + (P + 1) * k2] = v[m1];
 }
 
 // Row step 2 of the density (lane k2): acc[x] += wgt |u(x)|^2, x = Q1 k1 + k2.
@@ -196,7 +208,7 @@ FDE_HD void row_step2_rho(const cplx<T>* Rr, int k2, T* __restrict__ arow, T wgt
   constexpr int P = split2(N).p, Q = split2(N).q;
   cplx<T> v[P];
 #pragma unroll
-  for (int a = 0; a < P; ++a) v[a] = Rr[a + P * k2];
+  for (int a = 0; a < P; ++a) v[a] = Rr[a + (P + 1) * k2];
   reg_fft<T, true, P>(v, nullptr);
 #pragma unroll
   for (int k1 = 0; k1 < P; ++k1) arow[Q * k1 + k2] += wgt * norm2(v[k1]);
@@ -209,7 +221,7 @@ FDE_HD void row_step3(const cplx<T>* Rr, cplx<T>* Prow, int m1, int nxa, int mlo
   constexpr int P = split2(N).p, Q = split2(N).q;
   cplx<T> v[Q];
 #pragma unroll
-  for (int k2 = 0; k2 < Q; ++k2) v[k2] = Rr[m1 + P * k2];
+  for (int k2 = 0; k2 < Q; ++k2) v[k2] = Rr[m1 + (P + 1) * k2];
   reg_fft<T, false, Q>(v, nullptr);
 #pragma unroll
   for (int m2 = 0; m2 < Q; ++m2) {
@@ -222,35 +234,51 @@ FDE_HD void row_step3(const cplx<T>* Rr, cplx<T>* Prow, int m1, int nxa, int mlo
 // Plane slot s -> row y after the inverse column transform (N2 = P2 Q2).
 FDE_HD int plane4_row_of_slot(int s, int P2, int Q2) { return Q2 * (s % P2) + s / P2; }
 
-// LDS of the pass: compact plane [N2][nxa], row buffer [RB][N1], the N1 + N2
-// twiddles, the compact position of every stick.
+// LDS of the pass: compact plane [N2][nxa], row buffer [RB][rrow_len(N1)], the
+// twiddle tables ta, tb of N1 and (when N2 differs) of N2, the compact position
+// of every stick (16 bits: N2 nxa complex values fit in LDS, so below 2^16).
 template <typename T>
 FDE_HD size_t plane4_lds(int N1, int N2, int nxa, int RB, int ncol) {
-  return sizeof(cplx<T>) * ((size_t)N2 * nxa + (size_t)RB * N1 + N1 + N2) + sizeof(int) * (size_t)ncol + 64;
+  const size_t ntw = (size_t)2 * N1 + (N2 == N1 ? 0 : (size_t)2 * N2);
+  return sizeof(cplx<T>) * ((size_t)N2 * nxa + (size_t)RB * rrow_len(N1) + ntw) + 2 * (size_t)ncol + 64;
 }
 
 template <typename T>
 struct Plane4Lds {
-  cplx<T>*P, *R, *tw1, *tw2;
-  int* cpos;
+  cplx<T>*P, *R, *ta1, *tb1, *ta2, *tb2;
+  unsigned short* cpos;
   FDE_HD Plane4Lds(char* lds, int N1, int N2, int nxa, int RB) {
     P = (cplx<T>*)lds;
     R = P + (size_t)N2 * nxa;
-    tw1 = R + (size_t)RB * N1;
-    tw2 = tw1 + N1;
-    cpos = (int*)(tw2 + N2);
+    ta1 = R + (size_t)RB * rrow_len(N1);
+    tb1 = ta1 + N1;
+    ta2 = N2 == N1 ? ta1 : tb1 + N1;
+    tb2 = N2 == N1 ? tb1 : ta2 + N2;
+    cpos = (unsigned short*)(tb2 + N2);
   }
 };
+
+// ta[k P + a] = w^{a k}, tb[m Q + k2] = w^{k2 m} from the natural table tw[m] = w^m.
+template <typename T, class Ctx>
+FDE_HD void plane4_twiddles(const Ctx& c, cplx<T>* ta, cplx<T>* tb, const cplx<T>* __restrict__ tw, int N) {
+  const Split2 s = split2(N);
+  for (int i = c.tid(); i < N; i += c.nthr()) {
+    const int k = i / s.p, a = i - k * s.p;
+    ta[i] = tw[(a * k) % N];
+    const int m = i / s.q, k2 = i - m * s.q;
+    tb[i] = tw[(k2 * m) % N];
+  }
+}
 
 template <typename T, class Ctx>
 FDE_HD void plane4_setup(const Ctx& c, Plane4Lds<T>& L, const int4* __restrict__ sticks, int ncol, int nxa,
                          const cplx<T>* __restrict__ tw1, const cplx<T>* __restrict__ tw2, int N1, int N2) {
   for (int i = c.tid(); i < ncol; i += c.nthr()) {
     const int w = sticks[i].w;
-    L.cpos[i] = (w >> 16) * nxa + (w & 0xffff);
+    L.cpos[i] = (unsigned short)((w >> 16) * nxa + (w & 0xffff));
   }
-  for (int i = c.tid(); i < N1; i += c.nthr()) L.tw1[i] = tw1[i];
-  for (int i = c.tid(); i < N2; i += c.nthr()) L.tw2[i] = tw2[i];
+  plane4_twiddles<T>(c, L.ta1, L.tb1, tw1, N1);
+  if (N2 != N1) plane4_twiddles<T>(c, L.ta2, L.tb2, tw2, N2);
   c.sync();
 }
 
@@ -262,7 +290,7 @@ FDE_HD void plane4_load(const Ctx& c, Plane4Lds<T>& L, const cplx<T>* __restrict
   c.sync();
   for (int i = c.tid(); i < ncol; i += c.nthr()) L.P[L.cpos[i]] = row[i];
   c.sync();
-  plane4_columns<T, true>(c, L.P, N2, nxa, L.tw2);
+  plane4_columns<T, true>(c, L.P, N2, nxa, L.ta2, L.tb2);
 }
 
 // H application plane pass; grid (N3, ceil(nb / BPW)), 256 threads.
@@ -279,6 +307,7 @@ struct KPlaneH4 {
     Plane4Lds<T> L(lds, N1, N2, nxa, RB);
     plane4_setup<T>(c, L, sticks, ncol, nxa, tw1, tw2, N1, N2);
     const Split2 s1 = split2(N1), s2 = split2(N2);
+    const int RS = rrow_len(N1);
     const T* vz = veff + (size_t)z * N1 * N2;
     const int b0 = grp * BPW;
     for (int band = b0; band < b0 + BPW && band < nbands; ++band) {
@@ -289,9 +318,9 @@ struct KPlaneH4 {
         for (int q = c.tid(); q < rb * s1.p; q += c.nthr()) {
           const int r = q / s1.p, a = q - r * s1.p;
           const cplx<T>* Prow = L.P + (size_t)(y0 + r) * nxa;
-          cplx<T>* Rr = L.R + (size_t)r * N1;
+          cplx<T>* Rr = L.R + (size_t)r * RS;
           switch (N1) {
-#define FDE_R1(NN) case NN: row_step1<T, NN>(Prow, Rr, a, nxa, mlo, L.tw1); break;
+#define FDE_R1(NN) case NN: row_step1<T, NN>(Prow, Rr, a, nxa, mlo, L.ta1); break;
             FDE_SPLIT2_CASES(FDE_R1)
 #undef FDE_R1
             default: break;
@@ -301,9 +330,9 @@ struct KPlaneH4 {
         for (int q = c.tid(); q < rb * s1.q; q += c.nthr()) {
           const int r = q / s1.q, k2 = q - r * s1.q;
           const T* vrow = vz + (size_t)plane4_row_of_slot(y0 + r, s2.p, s2.q) * N1;
-          cplx<T>* Rr = L.R + (size_t)r * N1;
+          cplx<T>* Rr = L.R + (size_t)r * RS;
           switch (N1) {
-#define FDE_R2(NN) case NN: row_step2_h<T, NN>(Rr, k2, vrow, L.tw1); break;
+#define FDE_R2(NN) case NN: row_step2_h<T, NN>(Rr, k2, vrow, L.tb1); break;
             FDE_SPLIT2_CASES(FDE_R2)
 #undef FDE_R2
             default: break;
@@ -313,7 +342,7 @@ struct KPlaneH4 {
         for (int q = c.tid(); q < rb * s1.p; q += c.nthr()) {
           const int r = q / s1.p, m1 = q - r * s1.p;
           cplx<T>* Prow = L.P + (size_t)(y0 + r) * nxa;
-          const cplx<T>* Rr = L.R + (size_t)r * N1;
+          const cplx<T>* Rr = L.R + (size_t)r * RS;
           switch (N1) {
 #define FDE_R3(NN) case NN: row_step3<T, NN>(Rr, Prow, m1, nxa, mlo); break;
             FDE_SPLIT2_CASES(FDE_R3)
@@ -323,7 +352,7 @@ struct KPlaneH4 {
         }
         c.sync();
       }
-      plane4_columns<T, false>(c, L.P, N2, nxa, L.tw2);
+      plane4_columns<T, false>(c, L.P, N2, nxa, L.ta2, L.tb2);
       for (int i = c.tid(); i < ncol; i += c.nthr()) row[i] = L.P[L.cpos[i]];
       c.sync();
     }
@@ -343,6 +372,7 @@ struct KPlaneRho4 {
     Plane4Lds<T> L(lds, N1, N2, nxa, RB);
     plane4_setup<T>(c, L, sticks, ncol, nxa, tw1, tw2, N1, N2);
     const Split2 s1 = split2(N1), s2 = split2(N2);
+    const int RS = rrow_len(N1);
     T* o = out + ((size_t)c.by() * N3 + z) * N1 * N2;
     for (int i = c.tid(); i < N1 * N2; i += c.nthr()) o[i] = T(0);
     const int b0 = c.by() * BPW;
@@ -355,9 +385,9 @@ struct KPlaneRho4 {
         for (int q = c.tid(); q < rb * s1.p; q += c.nthr()) {
           const int r = q / s1.p, a = q - r * s1.p;
           const cplx<T>* Prow = L.P + (size_t)(y0 + r) * nxa;
-          cplx<T>* Rr = L.R + (size_t)r * N1;
+          cplx<T>* Rr = L.R + (size_t)r * RS;
           switch (N1) {
-#define FDE_R1(NN) case NN: row_step1<T, NN>(Prow, Rr, a, nxa, mlo, L.tw1); break;
+#define FDE_R1(NN) case NN: row_step1<T, NN>(Prow, Rr, a, nxa, mlo, L.ta1); break;
             FDE_SPLIT2_CASES(FDE_R1)
 #undef FDE_R1
             default: break;
@@ -367,7 +397,7 @@ struct KPlaneRho4 {
         for (int q = c.tid(); q < rb * s1.q; q += c.nthr()) {
           const int r = q / s1.q, k2 = q - r * s1.q;
           T* arow = o + (size_t)plane4_row_of_slot(y0 + r, s2.p, s2.q) * N1;
-          const cplx<T>* Rr = L.R + (size_t)r * N1;
+          const cplx<T>* Rr = L.R + (size_t)r * RS;
           switch (N1) {
 #define FDE_R2(NN) case NN: row_step2_rho<T, NN>(Rr, k2, arow, wgt); break;
             FDE_SPLIT2_CASES(FDE_R2)

@@ -43,8 +43,11 @@ static fde_status z_fwd_reg(const fde_plan* p, const KTables& t, int nbc, const 
                                                 (const int*)t.d_xlist, t.ncol, p->N[0], p->N[1], tw3, kv, invN);
 }
 
+// 432 = 16 x 27 holds 27 complex values per lane in the first step: FP32 only (FP64
+// would spill).
 static int z_reg_kind(const fde_plan* p) {
   if (p->tune_zreg == 1) return 0;
+  if (p->N[2] == 432) return p->prec == FDE_F32 ? 3 : 0;
   return p->N[2] == 240 ? 1 : (p->N[2] == 120 ? 2 : 0);
 }
 
@@ -200,12 +203,16 @@ static fde_status apply_h_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, cpl
       FDE_TRY((z_inv_reg<T, 16, 15>(t, nbc, ps, tw3, sb, s)));
     else if (zk == 2)
       FDE_TRY((z_inv_reg<T, 8, 15>(t, nbc, ps, tw3, sb, s)));
+    else if (zk == 3)
+      FDE_TRY((z_inv_reg<T, 16, 27>(t, nbc, ps, tw3, sb, s)));
     else
       FDE_TRY(launch<KZInv<T>>(dim3(ngz, nbc), zthreads(SZ), zlds, s, ps, t.npw, (const int4*)t.d_sticks, t.ncol,
                                p->rad[2], tw3, sb, SZ));
     if (kind == kPlane4) {
-      // about 2048 workgroups over the chip, unless tuned
-      const int BPW = p->tune_bpw > 0 ? std::min(nbc, p->tune_bpw) : std::max(1, std::min(nbc, (N3 * nbc) / 2048));
+      // at most 8 bands per workgroup, fewer where that would leave under ~8192 workgroups
+      // (tail balance over 256 CUs at two workgroups each), unless tuned
+      const int BPW = p->tune_bpw > 0 ? std::min(nbc, p->tune_bpw)
+                                      : std::max(1, std::min(std::min(nbc, 8), (N3 * nbc) / 8192));
       FDE_TRY(launch<KPlaneH4<T>>(dim3(N3, (nbc + BPW - 1) / BPW), kBlock, lds4, s, sb, nbc, BPW,
                                   (const int4*)t.d_sticks, t.ncol, t.nxa, t.mlo, N1, N2, N3, RB4, tw1, tw2, veff));
     } else if (kind == kPlaneReg) {
@@ -228,6 +235,8 @@ static fde_status apply_h_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, cpl
       FDE_TRY((z_fwd_reg<T, 16, 15>(p, t, nbc, sb, ps, hs, tw3, kv, invN, s)));
     else if (zk == 2)
       FDE_TRY((z_fwd_reg<T, 8, 15>(p, t, nbc, sb, ps, hs, tw3, kv, invN, s)));
+    else if (zk == 3)
+      FDE_TRY((z_fwd_reg<T, 16, 27>(p, t, nbc, sb, ps, hs, tw3, kv, invN, s)));
     else
       FDE_TRY(launch<KZFwd<T>>(dim3(ngz, nbc), zthreads(SZ), zlds, s, (const cplx<T>*)sb, ps, hs, t.npw,
                                (const int4*)t.d_sticks, (const int*)t.d_xlist, t.ncol, N1, N2, p->rad[2], tw3, kv,
@@ -282,6 +291,8 @@ static fde_status density_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, con
       FDE_TRY((z_inv_reg<T, 16, 15>(t, nbc, psi + (size_t)b0 * t.npw, tw3, sb, s)));
     else if (zk == 2)
       FDE_TRY((z_inv_reg<T, 8, 15>(t, nbc, psi + (size_t)b0 * t.npw, tw3, sb, s)));
+    else if (zk == 3)
+      FDE_TRY((z_inv_reg<T, 16, 27>(t, nbc, psi + (size_t)b0 * t.npw, tw3, sb, s)));
     else
       FDE_TRY(launch<KZInv<T>>(dim3(ngz, nbc), zthreads(SZ), zlds, s, psi + (size_t)b0 * t.npw, t.npw,
                                (const int4*)t.d_sticks, t.ncol, p->rad[2], tw3, sb, SZ));

@@ -372,11 +372,13 @@ class Engine:
     def autotune(self, candidates=(1, 2, 4, 8, 16), sz_candidates=None, reps: int = 5):
         """Time fde_apply_h of the largest band block with each in-plane pass kind
         (and, for the two-factor pass, each row-batch size), then with each
-        bands-per-plane-workgroup value, then (on grids without a register z-FFT)
-        with each z-sticks-per-workgroup value, and keep the fastest of each (launch
-        shapes and FFT factorisations only). Returns the best value and the timings
-        in ms of every search: {"plane", "plane_ms", "rows", "rows_ms", "bpw",
-        "bpw_ms", "sz", "sz_ms"}."""
+        bands-per-plane-workgroup value, then, where a register z-FFT exists, with
+        it and with the LDS z-passes, then (for the LDS z-passes) with each
+        z-sticks-per-workgroup value, and keep the fastest of each (launch shapes and
+        FFT factorisations only). A value replaces the automatic choice (0) only when
+        it is more than 1 % faster. Returns the best value and the timings in ms of
+        every search: {"plane", "plane_ms", "rows", "rows_ms", "bpw", "bpw_ms",
+        "zlds", "zlds_ms", "sz", "sz_ms"}."""
         if self.be.emulated:
             return None
         b = max((b for row in self.blocks for b in row), key=lambda b: b.nb * self.plan.npw(b.ik))
@@ -401,20 +403,25 @@ class Engine:
                 self.plan.set_tuning(key, v)
                 times[v] = timed()
             best = min(times, key=times.get)
+            if 0 in times and times[best] > 0.99 * times[0]:
+                best = 0
             self.set_tuning(key, best)
             return best, times
 
-        kind, kind_ms = search(fde.TUNE_PLANE_KIND, (fde.PLANE_REG, fde.PLANE_LDS, fde.PLANE_TWO_FACTOR))
+        kind, kind_ms = search(fde.TUNE_PLANE_KIND, (0, fde.PLANE_REG, fde.PLANE_LDS, fde.PLANE_TWO_FACTOR))
         rows, rows_ms = (None, {})
-        if kind == fde.PLANE_TWO_FACTOR:
+        if kind in (0, fde.PLANE_TWO_FACTOR):
             rows, rows_ms = search(fde.TUNE_PLANE_ROWS, [0] + [r for r in (8, 12, 16, 24, 30, 42)
                                                            if r < self.system.grid[1]])
-        bpw, bpw_ms = search(fde.TUNE_APPLY_BPW, [v for v in candidates if v <= b.nb])
+        bpw, bpw_ms = search(fde.TUNE_APPLY_BPW, [0] + [v for v in candidates if v <= b.nb])
+        n3 = self.system.grid[2]
+        zreg = n3 in (240, 120) or (n3 == 432 and self.prec == fde.F32)
+        zlds, zlds_ms = search(fde.TUNE_Z_REGISTER, (0, 1)) if zreg else (None, {})
         if sz_candidates is None:  # the stick group only shapes the LDS z-passes
-            sz_candidates = () if self.system.grid[2] in (240, 120) else (1, 2, 4, 8, 16)
+            sz_candidates = () if zreg and zlds == 0 else (1, 2, 4, 8, 16)
         sz, sz_ms = search(fde.TUNE_STICK_GROUP, sz_candidates) if sz_candidates else (None, {})
         return {"plane": kind, "plane_ms": kind_ms, "rows": rows, "rows_ms": rows_ms, "bpw": bpw, "bpw_ms": bpw_ms,
-                "sz": sz, "sz_ms": sz_ms}
+                "zlds": zlds, "zlds_ms": zlds_ms, "sz": sz, "sz_ms": sz_ms}
 
     def band_applies_per_cycle(self, n_david: Optional[int] = None) -> int:
         n_david = self.system.n_david if n_david is None else n_david

@@ -126,6 +126,11 @@ def test_apply_h_specialised_lengths(be, grid):
     pc.check_apply_h_grid(be, fde.F64, grid)
 
 
+def test_apply_h_register_z432_fp32(be):
+    """432-point sticks in FP32 take the 16 x 27 register z-passes."""
+    pc.check_apply_h_grid(be, fde.F32, (144, 24, 432))
+
+
 def test_apply_h_register_plane(be):
     """24 x 24 planes take the register plane pass (FP64 too); three bands."""
     pc.check_apply_h_grid(be, fde.F64, (24, 24, 30), nb=3)

@@ -353,9 +353,11 @@ def test_autotune_on_c2(be):
     t = eng.autotune(sz_candidates=(2, 4, 8))
     print(f"\napply_h ms by bands per plane workgroup: {t['bpw_ms']}; chosen {t['bpw']}; "
           f"by z-sticks per workgroup: {t['sz_ms']}; chosen {t['sz']}")
-    assert t["bpw_ms"][t["bpw"]] == min(t["bpw_ms"].values())
-    assert t["sz_ms"][t["sz"]] == min(t["sz_ms"].values())
-    assert eng.autotune()["sz"] is None  # 60 x 60 x 240: register z-FFT, no stick group to tune
+    assert t["bpw_ms"][t["bpw"]] <= 1.01 * min(t["bpw_ms"].values())
+    assert t["sz_ms"][t["sz"]] <= 1.01 * min(t["sz_ms"].values())
+    t2 = eng.autotune()
+    # 60 x 60 x 240 has a register z-FFT: the stick group is tuned only if the LDS z-passes win
+    assert t2["zlds"] in (0, 1) and (t2["zlds"] == 1 or t2["sz"] is None)
 
 
 @pytest.mark.parametrize("prec", PRECS)
