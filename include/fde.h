@@ -129,7 +129,8 @@ fde_status fde_plan_set_workspace(fde_plan* plan, void* d_ws, size_t bytes, int 
  * 120, and 432 in FP32 plans). FDE_TUNE_PLANE_KIND: the in-plane pass of fde_apply_h and
  * fde_density -- 1 whole-line register FFTs, 2 LDS Stockham passes, 3 two-factor
  * FFTs in LDS (used where the kind applies; otherwise the automatic choice).
- * FDE_TUNE_PLANE_ROWS: rows per batch of the two-factor pass (LDS size).
+ * FDE_TUNE_PLANE_ROWS: rows per batch of the two-factor pass (LDS size),
+ * rounded down to a multiple of its four wavefronts, at least one row each.
  * FDE_TUNE_RR_SPLIT: the smallest m (columns of [X W P]) for which the
  * Rayleigh-Ritz step of fde_subspace_rr runs its eigensolver as a sequence of
  * multi-workgroup launches instead of one workgroup per problem (the two agree

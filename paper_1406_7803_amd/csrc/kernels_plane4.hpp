@@ -12,7 +12,11 @@
 // a line sits at a + (P + 1) k, so the lanes of the strided steps (a fixed,
 // k = lane) hit distinct banks as well as those of the contiguous ones; the
 // twiddles of each step are stored in the order its lanes read them (lane
-// index fastest); stick positions are 16-bit.
+// index fastest).
+//
+// Rows are private to wavefronts: each of the four wavefronts owns RW rows of
+// the row buffer and takes its rows of every batch through the three row steps
+// with wavefront-level ordering only, so no workgroup barrier separates them.
 //
 // Per band and z-plane (workgroup of 256 threads; one z-plane, BPW bands):
 //   1. compact plane P[y][xa] (only the nxa active x-columns) = zeros, then the
@@ -234,19 +238,20 @@ FDE_HD void row_step3(const cplx<T>* Rr, cplx<T>* Prow, int m1, int nxa, int mlo
 // Plane slot s -> row y after the inverse column transform (N2 = P2 Q2).
 FDE_HD int plane4_row_of_slot(int s, int P2, int Q2) { return Q2 * (s % P2) + s / P2; }
 
+// Wavefronts per workgroup of the pass; the row buffer holds RB = kPlane4Waves RW rows.
+constexpr int kPlane4Waves = 4;
+
 // LDS of the pass: compact plane [N2][nxa], row buffer [RB][rrow_len(N1)], the
-// twiddle tables ta, tb of N1 and (when N2 differs) of N2, the compact position
-// of every stick (16 bits: N2 nxa complex values fit in LDS, so below 2^16).
+// twiddle tables ta, tb of N1 and (when N2 differs) of N2.
 template <typename T>
-FDE_HD size_t plane4_lds(int N1, int N2, int nxa, int RB, int ncol) {
+FDE_HD size_t plane4_lds(int N1, int N2, int nxa, int RB) {
   const size_t ntw = (size_t)2 * N1 + (N2 == N1 ? 0 : (size_t)2 * N2);
-  return sizeof(cplx<T>) * ((size_t)N2 * nxa + (size_t)RB * rrow_len(N1) + ntw) + 2 * (size_t)ncol + 64;
+  return sizeof(cplx<T>) * ((size_t)N2 * nxa + (size_t)RB * rrow_len(N1) + ntw) + 64;
 }
 
 template <typename T>
 struct Plane4Lds {
   cplx<T>*P, *R, *ta1, *tb1, *ta2, *tb2;
-  unsigned short* cpos;
   FDE_HD Plane4Lds(char* lds, int N1, int N2, int nxa, int RB) {
     P = (cplx<T>*)lds;
     R = P + (size_t)N2 * nxa;
@@ -254,9 +259,14 @@ struct Plane4Lds {
     tb1 = ta1 + N1;
     ta2 = N2 == N1 ? ta1 : tb1 + N1;
     tb2 = N2 == N1 ? tb1 : ta2 + N2;
-    cpos = (unsigned short*)(tb2 + N2);
   }
 };
+
+// Compact-plane position of stick i (packed x-slot | y << 16 in the stick table).
+FDE_HD int plane4_pos(const int4* __restrict__ sticks, int i, int nxa) {
+  const int w = sticks[i].w;
+  return (w >> 16) * nxa + (w & 0xffff);
+}
 
 // ta[k P + a] = w^{a k}, tb[m Q + k2] = w^{k2 m} from the natural table tw[m] = w^m.
 template <typename T, class Ctx>
@@ -271,12 +281,8 @@ FDE_HD void plane4_twiddles(const Ctx& c, cplx<T>* ta, cplx<T>* tb, const cplx<T
 }
 
 template <typename T, class Ctx>
-FDE_HD void plane4_setup(const Ctx& c, Plane4Lds<T>& L, const int4* __restrict__ sticks, int ncol, int nxa,
-                         const cplx<T>* __restrict__ tw1, const cplx<T>* __restrict__ tw2, int N1, int N2) {
-  for (int i = c.tid(); i < ncol; i += c.nthr()) {
-    const int w = sticks[i].w;
-    L.cpos[i] = (unsigned short)((w >> 16) * nxa + (w & 0xffff));
-  }
+FDE_HD void plane4_setup(const Ctx& c, Plane4Lds<T>& L, const cplx<T>* __restrict__ tw1,
+                         const cplx<T>* __restrict__ tw2, int N1, int N2) {
   plane4_twiddles<T>(c, L.ta1, L.tb1, tw1, N1);
   if (N2 != N1) plane4_twiddles<T>(c, L.ta2, L.tb2, tw2, N2);
   c.sync();
@@ -284,16 +290,17 @@ FDE_HD void plane4_setup(const Ctx& c, Plane4Lds<T>& L, const int4* __restrict__
 
 // compact plane = zeros, then the sticks of one band; inverse y-FFT
 template <typename T, class Ctx>
-FDE_HD void plane4_load(const Ctx& c, Plane4Lds<T>& L, const cplx<T>* __restrict__ row, int ncol, int nxa, int N2) {
+FDE_HD void plane4_load(const Ctx& c, Plane4Lds<T>& L, const cplx<T>* __restrict__ row,
+                        const int4* __restrict__ sticks, int ncol, int nxa, int N2) {
   const int n = N2 * nxa;
   for (int i = c.tid(); i < n; i += c.nthr()) L.P[i] = mk<T>(0, 0);
   c.sync();
-  for (int i = c.tid(); i < ncol; i += c.nthr()) L.P[L.cpos[i]] = row[i];
+  for (int i = c.tid(); i < ncol; i += c.nthr()) L.P[plane4_pos(sticks, i, nxa)] = row[i];
   c.sync();
   plane4_columns<T, true>(c, L.P, N2, nxa, L.ta2, L.tb2);
 }
 
-// H application plane pass; grid (N3, ceil(nb / BPW)), 256 threads.
+// H application plane pass; grid (N3, ceil(nb / BPW)), 64 kPlane4Waves threads.
 template <typename T>
 struct KPlaneH4 {
   template <class Ctx>
@@ -305,20 +312,21 @@ struct KPlaneH4 {
     int z, grp;
     c.template xcd_tile<true>(z, grp);
     Plane4Lds<T> L(lds, N1, N2, nxa, RB);
-    plane4_setup<T>(c, L, sticks, ncol, nxa, tw1, tw2, N1, N2);
+    plane4_setup<T>(c, L, tw1, tw2, N1, N2);
     const Split2 s1 = split2(N1), s2 = split2(N2);
-    const int RS = rrow_len(N1);
+    const int RS = rrow_len(N1), RW = RB / kPlane4Waves;
     const T* vz = veff + (size_t)z * N1 * N2;
     const int b0 = grp * BPW;
     for (int band = b0; band < b0 + BPW && band < nbands; ++band) {
       cplx<T>* row = sb + ((size_t)band * N3 + z) * stick_stride(ncol);
-      plane4_load<T>(c, L, row, ncol, nxa, N2);
+      plane4_load<T>(c, L, row, sticks, ncol, nxa, N2);
+      // wavefront w takes rows y0 + w RW + r (r < RW) of each batch into row-buffer rows w RW + r
       for (int y0 = 0; y0 < N2; y0 += RB) {
-        const int rb = (N2 - y0) < RB ? (N2 - y0) : RB;
-        for (int q = c.tid(); q < rb * s1.p; q += c.nthr()) {
-          const int r = q / s1.p, a = q - r * s1.p;
-          const cplx<T>* Prow = L.P + (size_t)(y0 + r) * nxa;
-          cplx<T>* Rr = L.R + (size_t)r * RS;
+        for (int q = c.tid(); q < 64 * kPlane4Waves; q += c.nthr()) {
+          const int w = q >> 6, l = q & 63, r = l / s1.p, a = l - r * s1.p, y = y0 + w * RW + r;
+          if (r >= RW || y >= N2) continue;
+          const cplx<T>* Prow = L.P + (size_t)y * nxa;
+          cplx<T>* Rr = L.R + (size_t)(w * RW + r) * RS;
           switch (N1) {
 #define FDE_R1(NN) case NN: row_step1<T, NN>(Prow, Rr, a, nxa, mlo, L.ta1); break;
             FDE_SPLIT2_CASES(FDE_R1)
@@ -326,11 +334,12 @@ struct KPlaneH4 {
             default: break;
           }
         }
-        c.sync();
-        for (int q = c.tid(); q < rb * s1.q; q += c.nthr()) {
-          const int r = q / s1.q, k2 = q - r * s1.q;
-          const T* vrow = vz + (size_t)plane4_row_of_slot(y0 + r, s2.p, s2.q) * N1;
-          cplx<T>* Rr = L.R + (size_t)r * RS;
+        c.wsync();
+        for (int q = c.tid(); q < 64 * kPlane4Waves; q += c.nthr()) {
+          const int w = q >> 6, l = q & 63, r = l / s1.q, k2 = l - r * s1.q, y = y0 + w * RW + r;
+          if (r >= RW || y >= N2) continue;
+          const T* vrow = vz + (size_t)plane4_row_of_slot(y, s2.p, s2.q) * N1;
+          cplx<T>* Rr = L.R + (size_t)(w * RW + r) * RS;
           switch (N1) {
 #define FDE_R2(NN) case NN: row_step2_h<T, NN>(Rr, k2, vrow, L.tb1); break;
             FDE_SPLIT2_CASES(FDE_R2)
@@ -338,11 +347,12 @@ struct KPlaneH4 {
             default: break;
           }
         }
-        c.sync();
-        for (int q = c.tid(); q < rb * s1.p; q += c.nthr()) {
-          const int r = q / s1.p, m1 = q - r * s1.p;
-          cplx<T>* Prow = L.P + (size_t)(y0 + r) * nxa;
-          const cplx<T>* Rr = L.R + (size_t)r * RS;
+        c.wsync();
+        for (int q = c.tid(); q < 64 * kPlane4Waves; q += c.nthr()) {
+          const int w = q >> 6, l = q & 63, r = l / s1.p, m1 = l - r * s1.p, y = y0 + w * RW + r;
+          if (r >= RW || y >= N2) continue;
+          cplx<T>* Prow = L.P + (size_t)y * nxa;
+          const cplx<T>* Rr = L.R + (size_t)(w * RW + r) * RS;
           switch (N1) {
 #define FDE_R3(NN) case NN: row_step3<T, NN>(Rr, Prow, m1, nxa, mlo); break;
             FDE_SPLIT2_CASES(FDE_R3)
@@ -350,10 +360,11 @@ struct KPlaneH4 {
             default: break;
           }
         }
-        c.sync();
+        c.wsync();
       }
+      c.sync();
       plane4_columns<T, false>(c, L.P, N2, nxa, L.ta2, L.tb2);
-      for (int i = c.tid(); i < ncol; i += c.nthr()) row[i] = L.P[L.cpos[i]];
+      for (int i = c.tid(); i < ncol; i += c.nthr()) row[i] = L.P[plane4_pos(sticks, i, nxa)];
       c.sync();
     }
   }
@@ -370,22 +381,24 @@ struct KPlaneRho4 {
                          const cplx<T>* __restrict__ tw2, T* __restrict__ out, double scale) {
     const int z = c.bx();
     Plane4Lds<T> L(lds, N1, N2, nxa, RB);
-    plane4_setup<T>(c, L, sticks, ncol, nxa, tw1, tw2, N1, N2);
+    plane4_setup<T>(c, L, tw1, tw2, N1, N2);
     const Split2 s1 = split2(N1), s2 = split2(N2);
-    const int RS = rrow_len(N1);
+    const int RS = rrow_len(N1), RW = RB / kPlane4Waves;
     T* o = out + ((size_t)c.by() * N3 + z) * N1 * N2;
     for (int i = c.tid(); i < N1 * N2; i += c.nthr()) o[i] = T(0);
     const int b0 = c.by() * BPW;
     for (int band = b0; band < b0 + BPW && band < nbands; ++band) {
       const T wgt = (T)(occw[band] * scale);
       const cplx<T>* row = sb + ((size_t)band * N3 + z) * stick_stride(ncol);
-      plane4_load<T>(c, L, row, ncol, nxa, N2);
+      plane4_load<T>(c, L, row, sticks, ncol, nxa, N2);
+      // wavefront w owns rows y0 + w RW + r of each batch, in every band, so its
+      // accumulation into those output rows is never shared
       for (int y0 = 0; y0 < N2; y0 += RB) {
-        const int rb = (N2 - y0) < RB ? (N2 - y0) : RB;
-        for (int q = c.tid(); q < rb * s1.p; q += c.nthr()) {
-          const int r = q / s1.p, a = q - r * s1.p;
-          const cplx<T>* Prow = L.P + (size_t)(y0 + r) * nxa;
-          cplx<T>* Rr = L.R + (size_t)r * RS;
+        for (int q = c.tid(); q < 64 * kPlane4Waves; q += c.nthr()) {
+          const int w = q >> 6, l = q & 63, r = l / s1.p, a = l - r * s1.p, y = y0 + w * RW + r;
+          if (r >= RW || y >= N2) continue;
+          const cplx<T>* Prow = L.P + (size_t)y * nxa;
+          cplx<T>* Rr = L.R + (size_t)(w * RW + r) * RS;
           switch (N1) {
 #define FDE_R1(NN) case NN: row_step1<T, NN>(Prow, Rr, a, nxa, mlo, L.ta1); break;
             FDE_SPLIT2_CASES(FDE_R1)
@@ -393,11 +406,12 @@ struct KPlaneRho4 {
             default: break;
           }
         }
-        c.sync();
-        for (int q = c.tid(); q < rb * s1.q; q += c.nthr()) {
-          const int r = q / s1.q, k2 = q - r * s1.q;
-          T* arow = o + (size_t)plane4_row_of_slot(y0 + r, s2.p, s2.q) * N1;
-          const cplx<T>* Rr = L.R + (size_t)r * RS;
+        c.wsync();
+        for (int q = c.tid(); q < 64 * kPlane4Waves; q += c.nthr()) {
+          const int w = q >> 6, l = q & 63, r = l / s1.q, k2 = l - r * s1.q, y = y0 + w * RW + r;
+          if (r >= RW || y >= N2) continue;
+          T* arow = o + (size_t)plane4_row_of_slot(y, s2.p, s2.q) * N1;
+          const cplx<T>* Rr = L.R + (size_t)(w * RW + r) * RS;
           switch (N1) {
 #define FDE_R2(NN) case NN: row_step2_rho<T, NN>(Rr, k2, arow, wgt); break;
             FDE_SPLIT2_CASES(FDE_R2)
@@ -405,8 +419,9 @@ struct KPlaneRho4 {
             default: break;
           }
         }
-        c.sync();
+        c.wsync();
       }
+      c.sync();
     }
   }
 };

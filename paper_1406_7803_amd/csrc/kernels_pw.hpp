@@ -138,13 +138,23 @@ struct KZFwd {
 // W^{n2 k1}, exchange through LDS inside their wavefront, and transform the P values
 // of each row k1 (result X[k1 + Q k2]). 64 / P sticks per wavefront, four wavefronts per
 // workgroup; no workgroup barrier. grid (ceil(ncol / (256 / P)), nb). tw: the N3 twiddles.
+// In the exchange buffer of a stick, row k1 starts at k1 (P + 1): the step-2 lanes (one
+// row each) then read distinct banks; stick buffers start 8 banks apart.
 // ---------------------------------------------------------------------------
 template <typename T, int P, int Q>
 struct ZReg {
   // sticks per wavefront, rows per thread in step 2, wavefronts per block (the block's
   // 4 SPW consecutive sticks share cache lines of the stick buffer, so they stay on one CU)
   static constexpr int N = P * Q, SPW = 64 / P, RPT = (Q + P - 1) / P, WPB = 4, SPB = WPB * SPW;
-  FDE_HD static size_t lds_bytes() { return sizeof(cplx<T>) * (size_t)SPB * N; }
+  static constexpr int RS = P + 1;  // row stride of the exchange buffer
+  // complex values per stick buffer: at least Q RS (and N), 32-bit word count = 8 mod 32
+  static constexpr int SB = [] {
+    constexpr int w = (int)(sizeof(cplx<T>) / 4);
+    int s = Q * RS > N ? Q * RS : N;
+    while ((s * w) % 32 != 8) ++s;
+    return s;
+  }();
+  FDE_HD static size_t lds_bytes() { return sizeof(cplx<T>) * (size_t)SPB * SB; }
   // step 1 for lane l: v = the stick's elements P n1 + n2 (filled by the caller), transformed,
   // twiddled, written to buf [stick][k1][n2]
   template <bool INV>
@@ -156,7 +166,7 @@ struct ZReg {
       v[k1] = INV ? cmulc(w, v[k1]) : w * v[k1];
     }
 #pragma unroll
-    for (int k1 = 0; k1 < Q; ++k1) sbuf[k1 * P + n2] = v[k1];
+    for (int k1 = 0; k1 < Q; ++k1) sbuf[k1 * RS + n2] = v[k1];
   }
   // step 2 for lane l: rows k1 = r, r + P, ... of the stick: u[j][k2] = X[k1 + Q k2]
   template <bool INV>
@@ -166,7 +176,7 @@ struct ZReg {
       const int k1 = r + P * j;
       if (k1 < Q) {
 #pragma unroll
-        for (int n2 = 0; n2 < P; ++n2) u[j][n2] = sbuf[k1 * P + n2];
+        for (int n2 = 0; n2 < P; ++n2) u[j][n2] = sbuf[k1 * RS + n2];
         reg_fft<T, INV, P>(u[j], nullptr);
       }
     }
@@ -198,7 +208,7 @@ struct KZInvReg {
         const int t = imod(P * n1 + n2 - st.z, N);
         v[n1] = t < st.y ? pb[st.x + t] : mk<T>(0, 0);
       }
-      Z::template step1<true>(v, tw, buf + (w * Z::SPW + l / P) * N, n2);
+      Z::template step1<true>(v, tw, buf + (w * Z::SPW + l / P) * Z::SB, n2);
     }
     c.wsync();
     // sticks fastest along the lanes for the stores (adjacent lanes write one row segment)
@@ -208,7 +218,7 @@ struct KZInvReg {
       const int s = (c.bx() * Z::WPB + w) * Z::SPW + sl;
       if (s >= ncol || r >= Q) continue;
       cplx<T> u[Z::RPT][P];
-      Z::template step2<true>(u, buf + (w * Z::SPW + sl) * N, r);
+      Z::template step2<true>(u, buf + (w * Z::SPW + sl) * Z::SB, r);
 #pragma unroll
       for (int j = 0; j < Z::RPT; ++j) {
         const int k1 = r + P * j;
@@ -244,7 +254,7 @@ struct KZFwdReg {
       cplx<T> v[Q];
 #pragma unroll
       for (int n1 = 0; n1 < Q; ++n1) v[n1] = ib[(size_t)(P * n1 + n2) * ncs + s];
-      Z::template step1<false>(v, tw, buf + (w * Z::SPW + sl) * N, n2);
+      Z::template step1<false>(v, tw, buf + (w * Z::SPW + sl) * Z::SB, n2);
     }
     c.wsync();
     // every row of a stick is read before any lane of that stick overwrites the buffer
@@ -259,14 +269,14 @@ struct KZFwdReg {
       const int w = q >> 6, l = q & 63;
       const int s = (c.bx() * Z::WPB + w) * Z::SPW + l / P, r = l % P;
       if (s >= ncol || r >= Q) continue;
-      Z::template step2<false>(u[NL == 1 ? 0 : q], buf + (w * Z::SPW + l / P) * N, r);
+      Z::template step2<false>(u[NL == 1 ? 0 : q], buf + (w * Z::SPW + l / P) * Z::SB, r);
     }
     c.wsync();
     for (int q = c.tid(); q < 64 * Z::WPB; q += c.nthr()) {
       const int w = q >> 6, l = q & 63;
       const int s = (c.bx() * Z::WPB + w) * Z::SPW + l / P, r = l % P;
       if (s >= ncol || r >= Q) continue;
-      cplx<T>* sbuf = buf + (w * Z::SPW + l / P) * N;
+      cplx<T>* sbuf = buf + (w * Z::SPW + l / P) * Z::SB;
 #pragma unroll
       for (int j = 0; j < Z::RPT; ++j) {
         const int k1 = r + P * j;
@@ -285,7 +295,7 @@ struct KZFwdReg {
       const int s = (c.bx() * Z::WPB + w) * Z::SPW + l / P, n2 = l % P;
       if (s >= ncol) continue;
       const int4 st = sticks[s];
-      const cplx<T>* sbuf = buf + (w * Z::SPW + l / P) * N;
+      const cplx<T>* sbuf = buf + (w * Z::SPW + l / P) * Z::SB;
       const int m1 = centred(xlist[st.w & 0xffff], N1);
       const int m2 = centred(st.w >> 16, N2);
       for (int t = n2; t < st.y; t += P) {

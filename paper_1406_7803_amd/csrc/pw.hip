@@ -83,36 +83,28 @@ static int plane_rows(const fde_plan* p, int ik, bool acc, size_t* lds) {
   return 0;
 }
 
-// Rows per batch of the two-factor plane pass: the tuned value, else, among the
-// batch sizes whose LDS fits 80 KiB (two workgroups per CU; a whole CU if none
-// does), the one with the fewest passes of the 256 threads over the three row
-// steps, counting 1.5 passes per batch for its barriers. 0 when not even one
-// row fits.
+// Rows of the two-factor plane pass's row buffer: kPlane4Waves RW, RW rows per wavefront
+// (RW times the larger factor of N1 at most 64 lanes). The tuned value rounded down to a
+// multiple of kPlane4Waves, else the largest RW whose LDS fits 80 KiB (two workgroups per
+// CU; a whole CU if none does). 0 when not even one row per wavefront fits.
 template <typename T>
 static int plane4_rows(const fde_plan* p, int ik, size_t* lds) {
   const KTables& t = p->k[ik];
   const int N1 = p->N[0], N2 = p->N[1];
+  const Split2 s1 = split2(N1);
+  const int rwmax = 64 / std::max(s1.p, s1.q);
   if (p->tune_rows > 0) {
-    const int rb = std::min(N2, p->tune_rows);
-    *lds = plane4_lds<T>(N1, N2, t.nxa, rb, t.ncol);
+    const int rb = kPlane4Waves * std::max(1, std::min(rwmax, p->tune_rows / kPlane4Waves));
+    *lds = plane4_lds<T>(N1, N2, t.nxa, rb);
     return *lds <= kLdsMax ? rb : 0;
   }
-  const Split2 s1 = split2(N1);
   for (size_t budget : {(size_t)80 * 1024, kLdsMax}) {
-    int best = 0;
-    double best_cost = 1e300;
-    for (int rb = 1; rb <= N2; ++rb) {
-      if (plane4_lds<T>(N1, N2, t.nxa, rb, t.ncol) > budget) break;
-      const int nbatch = (N2 + rb - 1) / rb;
-      const double cost = nbatch * (2.0 * ((rb * s1.p + kBlock - 1) / kBlock) + ((rb * s1.q + kBlock - 1) / kBlock) + 1.5);
-      if (cost < best_cost) {
-        best_cost = cost;
-        best = rb;
+    for (int rw = rwmax; rw >= 1; --rw) {
+      const size_t b = plane4_lds<T>(N1, N2, t.nxa, kPlane4Waves * rw);
+      if (b <= budget) {
+        *lds = b;
+        return kPlane4Waves * rw;
       }
-    }
-    if (best > 0) {
-      *lds = plane4_lds<T>(N1, N2, t.nxa, best, t.ncol);
-      return best;
     }
   }
   return 0;
@@ -213,7 +205,7 @@ static fde_status apply_h_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, cpl
       // (tail balance over 256 CUs at two workgroups each), unless tuned
       const int BPW = p->tune_bpw > 0 ? std::min(nbc, p->tune_bpw)
                                       : std::max(1, std::min(std::min(nbc, 8), (N3 * nbc) / 8192));
-      FDE_TRY(launch<KPlaneH4<T>>(dim3(N3, (nbc + BPW - 1) / BPW), kBlock, lds4, s, sb, nbc, BPW,
+      FDE_TRY(launch<KPlaneH4<T>>(dim3(N3, (nbc + BPW - 1) / BPW), 64 * kPlane4Waves, lds4, s, sb, nbc, BPW,
                                   (const int4*)t.d_sticks, t.ncol, t.nxa, t.mlo, N1, N2, N3, RB4, tw1, tw2, veff));
     } else if (kind == kPlaneReg) {
       // about two workgroups (one wave each) per SIMD over the whole chip, unless tuned
@@ -300,7 +292,7 @@ static fde_status density_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, con
     const int BPW = (nbc + ngroups - 1) / ngroups;
     const int ng = (nbc + BPW - 1) / BPW;
     if (kind == kPlane4)
-      FDE_TRY(launch<KPlaneRho4<T>>(dim3(N3, ng), kBlock, lds4, s, (const cplx<T>*)sb, nbc, BPW, occw + b0,
+      FDE_TRY(launch<KPlaneRho4<T>>(dim3(N3, ng), 64 * kPlane4Waves, lds4, s, (const cplx<T>*)sb, nbc, BPW, occw + b0,
                                     (const int4*)t.d_sticks, t.ncol, t.nxa, t.mlo, N1, N2, N3, RB4, tw1, tw2, part,
                                     1.0 / p->omega));
     else if (kind == kPlaneReg && cls == 0)

@@ -411,7 +411,7 @@ class Engine:
         kind, kind_ms = search(fde.TUNE_PLANE_KIND, (0, fde.PLANE_REG, fde.PLANE_LDS, fde.PLANE_TWO_FACTOR))
         rows, rows_ms = (None, {})
         if kind in (0, fde.PLANE_TWO_FACTOR):
-            rows, rows_ms = search(fde.TUNE_PLANE_ROWS, [0] + [r for r in (8, 12, 16, 24, 30, 42)
+            rows, rows_ms = search(fde.TUNE_PLANE_ROWS, [0] + [r for r in (4, 8, 12, 16, 20)
                                                            if r < self.system.grid[1]])
         bpw, bpw_ms = search(fde.TUNE_APPLY_BPW, [0] + [v for v in candidates if v <= b.nb])
         n3 = self.system.grid[2]
