@@ -186,19 +186,17 @@ FDE_HD void row_step1(const cplx<T>* Prow, cplx<T>* Rr, int a, int nxa, int mlo,
 }
 
 // Row step 2 of the H application (lane k2): inverse P1-point DFT gives u at
-// x = Q1 k1 + k2; times V_eff; forward P1-point DFT over k1 and twiddle.
+// x = Q1 k1 + k2; times V_eff (vv[k1], loaded beforehand); forward P1-point DFT
+// over k1 and twiddle.
 template <typename T, int N>
-FDE_HD void row_step2_h(cplx<T>* Rr, int k2, const T* __restrict__ vrow, const cplx<T>* tb) {
+FDE_HD void row_step2_hv(cplx<T>* Rr, int k2, const T* vv, const cplx<T>* tb) {
   constexpr int P = split2(N).p, Q = split2(N).q;
   cplx<T> v[P];
 #pragma unroll
   for (int a = 0; a < P; ++a) v[a] = Rr[a + (P + 1) * k2];
   reg_fft<T, true, P>(v, nullptr);
 #pragma unroll
-  for (int k1 = 0; k1 < P; ++k1) {
-    const T w = vrow[Q * k1 + k2];
-    v[k1] = mk<T>(w * v[k1].x, w * v[k1].y);
-  }
+  for (int k1 = 0; k1 < P; ++k1) v[k1] = mk<T>(vv[k1] * v[k1].x, vv[k1] * v[k1].y);
   reg_fft<T, false, P>(v, nullptr);
 #pragma unroll
   for (int m1 = 1; m1 < P; ++m1) v[m1] = tb[m1 * Q + k2] * v[m1];
@@ -300,6 +298,49 @@ FDE_HD void plane4_load(const Ctx& c, Plane4Lds<T>& L, const cplx<T>* __restrict
   plane4_columns<T, true>(c, L.P, N2, nxa, L.ta2, L.tb2);
 }
 
+// The row steps of the H application for one band: wavefront w takes rows y0 + w RW + r
+// (r < RW) of each batch into row-buffer rows w RW + r. Each lane's V_eff values for step 2
+// are loaded at the start of step 1, so their latency is spent on step 1's arithmetic.
+template <typename T, int N1, class Ctx>
+FDE_HD void plane4_rows_h(const Ctx& c, Plane4Lds<T>& L, int N2, int nxa, int mlo, int RB, const T* __restrict__ vz,
+                          Split2 s2) {
+  constexpr int P = split2(N1).p, Q = split2(N1).q, RS = rrow_len(N1);
+  const int RW = RB / kPlane4Waves;
+#if defined(__HIP_DEVICE_COMPILE__)
+  constexpr int NL = 1;
+#else
+  constexpr int NL = 64 * kPlane4Waves;  // the serial host run keeps every lane's values
+#endif
+  T vv[NL][P];
+  for (int y0 = 0; y0 < N2; y0 += RB) {
+    for (int q = c.tid(); q < 64 * kPlane4Waves; q += c.nthr()) {
+      const int w = q >> 6, l = q & 63;
+      const int r2 = l / Q, k2 = l - r2 * Q, y2 = y0 + w * RW + r2;
+      if (r2 < RW && y2 < N2) {
+        const T* vrow = vz + (size_t)plane4_row_of_slot(y2, s2.p, s2.q) * N1;
+#pragma unroll
+        for (int k1 = 0; k1 < P; ++k1) vv[NL == 1 ? 0 : q][k1] = vrow[Q * k1 + k2];
+      }
+      const int r = l / P, a = l - r * P, y = y0 + w * RW + r;
+      if (r >= RW || y >= N2) continue;
+      row_step1<T, N1>(L.P + (size_t)y * nxa, L.R + (size_t)(w * RW + r) * RS, a, nxa, mlo, L.ta1);
+    }
+    c.wsync();
+    for (int q = c.tid(); q < 64 * kPlane4Waves; q += c.nthr()) {
+      const int w = q >> 6, l = q & 63, r = l / Q, k2 = l - r * Q, y = y0 + w * RW + r;
+      if (r >= RW || y >= N2) continue;
+      row_step2_hv<T, N1>(L.R + (size_t)(w * RW + r) * RS, k2, vv[NL == 1 ? 0 : q], L.tb1);
+    }
+    c.wsync();
+    for (int q = c.tid(); q < 64 * kPlane4Waves; q += c.nthr()) {
+      const int w = q >> 6, l = q & 63, r = l / P, m1 = l - r * P, y = y0 + w * RW + r;
+      if (r >= RW || y >= N2) continue;
+      row_step3<T, N1>(L.R + (size_t)(w * RW + r) * RS, L.P + (size_t)y * nxa, m1, nxa, mlo);
+    }
+    c.wsync();
+  }
+}
+
 // H application plane pass; grid (N3, ceil(nb / BPW)), 64 kPlane4Waves threads.
 template <typename T>
 struct KPlaneH4 {
@@ -313,54 +354,17 @@ struct KPlaneH4 {
     c.template xcd_tile<true>(z, grp);
     Plane4Lds<T> L(lds, N1, N2, nxa, RB);
     plane4_setup<T>(c, L, tw1, tw2, N1, N2);
-    const Split2 s1 = split2(N1), s2 = split2(N2);
-    const int RS = rrow_len(N1), RW = RB / kPlane4Waves;
+    const Split2 s2 = split2(N2);
     const T* vz = veff + (size_t)z * N1 * N2;
     const int b0 = grp * BPW;
     for (int band = b0; band < b0 + BPW && band < nbands; ++band) {
       cplx<T>* row = sb + ((size_t)band * N3 + z) * stick_stride(ncol);
       plane4_load<T>(c, L, row, sticks, ncol, nxa, N2);
-      // wavefront w takes rows y0 + w RW + r (r < RW) of each batch into row-buffer rows w RW + r
-      for (int y0 = 0; y0 < N2; y0 += RB) {
-        for (int q = c.tid(); q < 64 * kPlane4Waves; q += c.nthr()) {
-          const int w = q >> 6, l = q & 63, r = l / s1.p, a = l - r * s1.p, y = y0 + w * RW + r;
-          if (r >= RW || y >= N2) continue;
-          const cplx<T>* Prow = L.P + (size_t)y * nxa;
-          cplx<T>* Rr = L.R + (size_t)(w * RW + r) * RS;
-          switch (N1) {
-#define FDE_R1(NN) case NN: row_step1<T, NN>(Prow, Rr, a, nxa, mlo, L.ta1); break;
-            FDE_SPLIT2_CASES(FDE_R1)
-#undef FDE_R1
-            default: break;
-          }
-        }
-        c.wsync();
-        for (int q = c.tid(); q < 64 * kPlane4Waves; q += c.nthr()) {
-          const int w = q >> 6, l = q & 63, r = l / s1.q, k2 = l - r * s1.q, y = y0 + w * RW + r;
-          if (r >= RW || y >= N2) continue;
-          const T* vrow = vz + (size_t)plane4_row_of_slot(y, s2.p, s2.q) * N1;
-          cplx<T>* Rr = L.R + (size_t)(w * RW + r) * RS;
-          switch (N1) {
-#define FDE_R2(NN) case NN: row_step2_h<T, NN>(Rr, k2, vrow, L.tb1); break;
-            FDE_SPLIT2_CASES(FDE_R2)
-#undef FDE_R2
-            default: break;
-          }
-        }
-        c.wsync();
-        for (int q = c.tid(); q < 64 * kPlane4Waves; q += c.nthr()) {
-          const int w = q >> 6, l = q & 63, r = l / s1.p, m1 = l - r * s1.p, y = y0 + w * RW + r;
-          if (r >= RW || y >= N2) continue;
-          cplx<T>* Prow = L.P + (size_t)y * nxa;
-          const cplx<T>* Rr = L.R + (size_t)(w * RW + r) * RS;
-          switch (N1) {
-#define FDE_R3(NN) case NN: row_step3<T, NN>(Rr, Prow, m1, nxa, mlo); break;
-            FDE_SPLIT2_CASES(FDE_R3)
-#undef FDE_R3
-            default: break;
-          }
-        }
-        c.wsync();
+      switch (N1) {
+#define FDE_RH(NN) case NN: plane4_rows_h<T, NN>(c, L, N2, nxa, mlo, RB, vz, s2); break;
+        FDE_SPLIT2_CASES(FDE_RH)
+#undef FDE_RH
+        default: break;
       }
       c.sync();
       plane4_columns<T, false>(c, L.P, N2, nxa, L.ta2, L.tb2);
