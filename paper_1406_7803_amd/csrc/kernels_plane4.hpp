@@ -266,6 +266,46 @@ FDE_HD int plane4_pos(const int4* __restrict__ sticks, int i, int nxa) {
   return (w >> 16) * nxa + (w & 0xffff);
 }
 
+// Sticks of one band into / out of the compact plane, kStickBatch per thread at a time so
+// that the global loads of a batch are in flight together.
+constexpr int kStickBatch = 8;
+template <typename T, class Ctx>
+FDE_HD void plane4_scatter(const Ctx& c, cplx<T>* P, const cplx<T>* __restrict__ row,
+                           const int4* __restrict__ sticks, int ncol, int nxa) {
+  for (int i0 = c.tid(); i0 < ncol; i0 += kStickBatch * c.nthr()) {
+    int ps[kStickBatch];
+    cplx<T> v[kStickBatch];
+#pragma unroll
+    for (int j = 0; j < kStickBatch; ++j) {
+      const int i = i0 + j * c.nthr();
+      if (i < ncol) {
+        ps[j] = plane4_pos(sticks, i, nxa);
+        v[j] = row[i];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kStickBatch; ++j)
+      if (i0 + j * c.nthr() < ncol) P[ps[j]] = v[j];
+  }
+}
+template <typename T, class Ctx>
+FDE_HD void plane4_gather(const Ctx& c, const cplx<T>* P, cplx<T>* __restrict__ row,
+                          const int4* __restrict__ sticks, int ncol, int nxa) {
+  for (int i0 = c.tid(); i0 < ncol; i0 += kStickBatch * c.nthr()) {
+    int ps[kStickBatch];
+#pragma unroll
+    for (int j = 0; j < kStickBatch; ++j) {
+      const int i = i0 + j * c.nthr();
+      if (i < ncol) ps[j] = plane4_pos(sticks, i, nxa);
+    }
+#pragma unroll
+    for (int j = 0; j < kStickBatch; ++j) {
+      const int i = i0 + j * c.nthr();
+      if (i < ncol) row[i] = P[ps[j]];
+    }
+  }
+}
+
 // ta[k P + a] = w^{a k}, tb[m Q + k2] = w^{k2 m} from the natural table tw[m] = w^m.
 template <typename T, class Ctx>
 FDE_HD void plane4_twiddles(const Ctx& c, cplx<T>* ta, cplx<T>* tb, const cplx<T>* __restrict__ tw, int N) {
@@ -293,7 +333,7 @@ FDE_HD void plane4_load(const Ctx& c, Plane4Lds<T>& L, const cplx<T>* __restrict
   const int n = N2 * nxa;
   for (int i = c.tid(); i < n; i += c.nthr()) L.P[i] = mk<T>(0, 0);
   c.sync();
-  for (int i = c.tid(); i < ncol; i += c.nthr()) L.P[plane4_pos(sticks, i, nxa)] = row[i];
+  plane4_scatter<T>(c, L.P, row, sticks, ncol, nxa);
   c.sync();
   plane4_columns<T, true>(c, L.P, N2, nxa, L.ta2, L.tb2);
 }
@@ -368,7 +408,7 @@ struct KPlaneH4 {
       }
       c.sync();
       plane4_columns<T, false>(c, L.P, N2, nxa, L.ta2, L.tb2);
-      for (int i = c.tid(); i < ncol; i += c.nthr()) row[i] = L.P[plane4_pos(sticks, i, nxa)];
+      plane4_gather<T>(c, L.P, row, sticks, ncol, nxa);
       c.sync();
     }
   }
