@@ -333,7 +333,7 @@ def table1_analogue(be):
     import fde_synth
     from paper_1406_7803_amd import driver, fde
     s = fde_synth.config2()
-    mixer = dict(kind="pulay", nhist=8, beta=0.2, q0=0.8)
+    mixer = dict(kind="pulay", nhist=8, beta=0.2, q0=0.4)
     out = {"system": "slab + molecule cell; xc PBE; interaction energies in Ha without the ion-ion term",
            "mixing": mixer, "tolerance_electrons": 1e-5}
     for name, kin in (("lc94", fde.KIN_LC94), ("revapbek", fde.KIN_REVAPBEK)):
