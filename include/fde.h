@@ -135,9 +135,8 @@ fde_status fde_plan_set_workspace(fde_plan* plan, void* d_ws, size_t bytes, int 
  * Rayleigh-Ritz step of fde_subspace_rr runs its eigensolver as a sequence of
  * multi-workgroup launches instead of one workgroup per problem (the two agree
  * to rounding, not bit for bit; up to m = 768). 0 restores the automatic
- * choice (a value of 1024 never splits). The driver's
- * autotuner times candidate values on the plan's own shapes and keeps the
- * fastest. Errors: FDE_ERR_ARG for an unknown key, a value outside [0, 1024]
+ * choice (a value of 1024 never splits; the automatic 256 was the fastest of
+ * the thresholds 128 to 256 timed on the 64-subsystem cube). Errors: FDE_ERR_ARG for an unknown key, a value outside [0, 1024]
  * or a stick group that is not a power of two.
  */
 #define FDE_TUNE_APPLY_BPW 1
