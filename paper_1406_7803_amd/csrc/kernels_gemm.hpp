@@ -16,6 +16,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "launch.hpp"
 
 namespace fde {
 
@@ -40,9 +41,12 @@ struct AhBSet {
 typedef double fde_d4 __attribute__((ext_vector_type(4)));
 #endif
 
-template <typename T>
+// Tile of TS x TS outputs per workgroup (TS = 32 or 64), four wavefronts in a 2 x 2 grid,
+// each holding (TS/32)^2 16 x 16 sub-tiles; k chunks of KT plane waves staged in LDS.
+// The 64 tile reads every operand row half as often per output as the 32 tile.
+template <typename T, int TS = 32>
 struct KAhB {
-  static constexpr int TI = 32, TJ = 32, KT = 64, LD = KT + 1;
+  static constexpr int TI = TS, TJ = TS, KT = TS == 32 ? 64 : 32, LD = KT + 1, SW = TS / 32;
   static size_t lds_bytes() {
     size_t s = sizeof(cplx<T>) * LD * (TI + 2 * TJ);
 #ifdef FDE_EMULATE
@@ -69,8 +73,17 @@ struct KAhB {
     cplx<T>* sB1 = sB0 + TJ * LD;
 #if defined(__HIP_DEVICE_COMPILE__)
     const int lane = c.tid() & 63, wave = c.tid() >> 6;
-    const int wi = wave >> 1, wj = wave & 1;  // 4 waves: a 2 x 2 grid of 16 x 16 sub-tiles
-    fde_d4 re0 = {0, 0, 0, 0}, im0 = {0, 0, 0, 0}, re1 = {0, 0, 0, 0}, im1 = {0, 0, 0, 0};
+    const int wi = wave >> 1, wj = wave & 1;  // 4 waves: a 2 x 2 grid of (TS/2) x (TS/2) blocks
+    fde_d4 re0[SW][SW], im0[SW][SW], re1[SW][SW], im1[SW][SW];
+#pragma unroll
+    for (int s = 0; s < SW; ++s)
+#pragma unroll
+      for (int u = 0; u < SW; ++u) {
+        re0[s][u] = fde_d4{0, 0, 0, 0};
+        im0[s][u] = fde_d4{0, 0, 0, 0};
+        re1[s][u] = fde_d4{0, 0, 0, 0};
+        im1[s][u] = fde_d4{0, 0, 0, 0};
+      }
 #else
     cplx<double>* acc = (cplx<double>*)(sB1 + TJ * LD);  // [2][TI][TJ]
     for (int o = c.tid(); o < 2 * TI * TJ; o += c.nthr()) acc[o] = mk<double>(0, 0);
@@ -86,25 +99,40 @@ struct KAhB {
       }
       c.sync();
 #if defined(__HIP_DEVICE_COMPILE__)
-      const int ra = (wi * 16 + (lane & 15)) * LD + (lane >> 4);
-      const int rb = (wj * 16 + (lane & 15)) * LD + (lane >> 4);
+      const int ra = (wi * (TS / 2) + (lane & 15)) * LD + (lane >> 4);
+      const int rb = (wj * (TS / 2) + (lane & 15)) * LD + (lane >> 4);
 #pragma unroll 4
       for (int k0 = 0; k0 < KT; k0 += 4) {
-        const cplx<T> a = sA[ra + k0];
-        const cplx<T> b = sB0[rb + k0];
-        const double ax = a.x, ay = a.y, bx = b.x, by = b.y;
-        re0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, bx, re0, 0, 0, 0);
-        re0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ay, by, re0, 0, 0, 0);
-        im0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, by, im0, 0, 0, 0);
-        im0 = __builtin_amdgcn_mfma_f64_16x16x4f64(-ay, bx, im0, 0, 0, 0);
-        if (two) {
-          const cplx<T> h = sB1[rb + k0];
-          const double hx = h.x, hy = h.y;
-          re1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, hx, re1, 0, 0, 0);
-          re1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ay, hy, re1, 0, 0, 0);
-          im1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, hy, im1, 0, 0, 0);
-          im1 = __builtin_amdgcn_mfma_f64_16x16x4f64(-ay, hx, im1, 0, 0, 0);
+        double ax[SW], ay[SW], bx[SW], by[SW], hx[SW], hy[SW];
+#pragma unroll
+        for (int s = 0; s < SW; ++s) {
+          const cplx<T> a = sA[ra + s * 16 * LD + k0];
+          const cplx<T> b = sB0[rb + s * 16 * LD + k0];
+          ax[s] = a.x;
+          ay[s] = a.y;
+          bx[s] = b.x;
+          by[s] = b.y;
+          if (two) {
+            const cplx<T> h = sB1[rb + s * 16 * LD + k0];
+            hx[s] = h.x;
+            hy[s] = h.y;
+          }
         }
+#pragma unroll
+        for (int s = 0; s < SW; ++s)
+#pragma unroll
+          for (int u = 0; u < SW; ++u) {
+            re0[s][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax[s], bx[u], re0[s][u], 0, 0, 0);
+            re0[s][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ay[s], by[u], re0[s][u], 0, 0, 0);
+            im0[s][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax[s], by[u], im0[s][u], 0, 0, 0);
+            im0[s][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ay[s], bx[u], im0[s][u], 0, 0, 0);
+            if (two) {
+              re1[s][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax[s], hx[u], re1[s][u], 0, 0, 0);
+              re1[s][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ay[s], hy[u], re1[s][u], 0, 0, 0);
+              im1[s][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax[s], hy[u], im1[s][u], 0, 0, 0);
+              im1[s][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ay[s], hx[u], im1[s][u], 0, 0, 0);
+            }
+          }
       }
 #else
       for (int o = c.tid(); o < TI * TJ; o += c.nthr()) {
@@ -132,18 +160,23 @@ struct KAhB {
     const size_t mab = (size_t)P.ma * P.mb;
     cplx<double>* out = P.part + (size_t)c.bx() * nprod * mab;
 #if defined(__HIP_DEVICE_COMPILE__)
-    const int j = j0 + wj * 16 + (lane & 15);
-    for (int r = 0; r < 4; ++r) {
-      const int i = i0 + wi * 16 + 4 * r + (lane >> 4);
-      if (i < P.ma && j < P.mb && (!herm || j <= i)) {
-        out[(size_t)i * P.mb + j] = mk<double>(re0[r], im0[r]);
-        if (two) out[mab + (size_t)i * P.mb + j] = mk<double>(re1[r], im1[r]);
-        if (herm && j < i) {
-          out[(size_t)j * P.mb + i] = mk<double>(re0[r], -im0[r]);
-          out[mab + (size_t)j * P.mb + i] = mk<double>(re1[r], -im1[r]);
+#pragma unroll
+    for (int s = 0; s < SW; ++s)
+#pragma unroll
+      for (int u = 0; u < SW; ++u) {
+        const int j = j0 + wj * (TS / 2) + u * 16 + (lane & 15);
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0 + wi * (TS / 2) + s * 16 + 4 * r + (lane >> 4);
+          if (i < P.ma && j < P.mb && (!herm || j <= i)) {
+            out[(size_t)i * P.mb + j] = mk<double>(re0[s][u][r], im0[s][u][r]);
+            if (two) out[mab + (size_t)i * P.mb + j] = mk<double>(re1[s][u][r], im1[s][u][r]);
+            if (herm && j < i) {
+              out[(size_t)j * P.mb + i] = mk<double>(re0[s][u][r], -im0[s][u][r]);
+              out[mab + (size_t)j * P.mb + i] = mk<double>(re1[s][u][r], -im1[s][u][r]);
+            }
+          }
         }
       }
-    }
 #else
     for (int o = c.tid(); o < TI * TJ; o += c.nthr()) {
       const int i = i0 + o / TJ, j = j0 + o % TJ;
@@ -159,6 +192,21 @@ struct KAhB {
 #endif
   }
 };
+
+// Launch of KAhB over grid (nchunk, tiles, nz): the 64 tile for FP32 operands when both
+// product dimensions reach 128 (fewer operand reads per output; its FP64 staging would
+// not leave room for a second workgroup per CU), else the 32 tile.
+template <typename T>
+inline fde_status launch_ahb(unsigned nchunk, int ma, int mb, unsigned nz, const AhBSet<T>& set, hipStream_t s) {
+  if (sizeof(T) == 4 && ma >= 128 && mb >= 128) {
+    using K = KAhB<T, 64>;
+    const unsigned nt = (unsigned)(((ma + K::TI - 1) / K::TI) * ((mb + K::TJ - 1) / K::TJ));
+    return launch<K, 256, 2>(dim3(nchunk, nt, nz), kBlock, K::lds_bytes(), s, set);
+  }
+  using K = KAhB<T>;
+  const unsigned nt = (unsigned)(((ma + K::TI - 1) / K::TI) * ((mb + K::TJ - 1) / K::TJ));
+  return launch<K>(dim3(nchunk, nt, nz), kBlock, K::lds_bytes(), s, set);
+}
 
 // ---------------------------------------------------------------------------
 // The same products from FP32 inputs on BF16 matrix cores (FP32 plans only).

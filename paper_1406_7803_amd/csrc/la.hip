@@ -146,7 +146,7 @@ static fde_status rr_launch(fde_plan* p, ProbSet<T>& ps, hipStream_t s) {
   }
   const int nt = (mmax + KAhB<T>::TI - 1) / KAhB<T>::TI;
   if (gen) {
-    FDE_TRY(launch<KAhB<T>>(dim3(kMaxChunks, nt * nt, ps.n), kBlock, KAhB<T>::lds_bytes(), s, gs));
+    FDE_TRY(launch_ahb<T>(kMaxChunks, mmax, mmax, ps.n, gs, s));
   } else if constexpr (sizeof(T) == 4) {
     if (p->gemm == FDE_GEMM_BF16X3)
       FDE_TRY(launch<KAhBSplit<2>>(dim3(kMaxChunks, nt * nt, ps.n), kBlock, KAhBSplit<2>::lds_bytes(), s, gs));
@@ -155,12 +155,12 @@ static fde_status rr_launch(fde_plan* p, ProbSet<T>& ps, hipStream_t s) {
     else if (mmax <= 16 * kGramTiles)
       FDE_TRY((launch<KGram<T>, 512>(dim3(kMaxChunks, ps.n), 512, KGram<T>::lds_bytes(mmax), s, gs)));
     else
-      FDE_TRY(launch<KAhB<T>>(dim3(kMaxChunks, nt * nt, ps.n), kBlock, KAhB<T>::lds_bytes(), s, gs));
+      FDE_TRY(launch_ahb<T>(kMaxChunks, mmax, mmax, ps.n, gs, s));
   } else {
     if (mmax <= 16 * kGramTiles)
       FDE_TRY((launch<KGram<T>, 512>(dim3(kMaxChunks, ps.n), 512, KGram<T>::lds_bytes(mmax), s, gs)));
     else
-      FDE_TRY(launch<KAhB<T>>(dim3(kMaxChunks, nt * nt, ps.n), kBlock, KAhB<T>::lds_bytes(), s, gs));
+      FDE_TRY(launch_ahb<T>(kMaxChunks, mmax, mmax, ps.n, gs, s));
   }
   FDE_TRY(launch<KGramReduce<T>>(dim3((unsigned)((2 * (size_t)mmax * mmax + kLBlk - 1) / kLBlk), ps.n), kBlock, 0, s,
                                  ps));
@@ -430,8 +430,7 @@ static fde_status projections_fp64(fde_plan* p, int ik, int nbc, const cplx<T>* 
     AhBSet<T> set;
     set.n = 1;
     set.p[0] = prob;
-    const int nti = (nproj + KAhB<T>::TI - 1) / KAhB<T>::TI, ntj = (nbc + KAhB<T>::TJ - 1) / KAhB<T>::TJ;
-    FDE_TRY(launch<KAhB<T>>(dim3(nchunk, nti * ntj, 1), kBlock, KAhB<T>::lds_bytes(), s, set));
+    FDE_TRY(launch_ahb<T>(nchunk, nproj, nbc, 1, set, s));
   }
   return launch<KPReduce>(dim3((nproj * nbc + 255) / 256), kBlock, 0, s, (const cplx<double>*)part, nchunk,
                           nproj * nbc, P);

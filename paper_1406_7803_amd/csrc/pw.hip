@@ -153,8 +153,7 @@ static fde_status kb_project(const cplx<T>* beta, const cplx<T>* psi, int npw, i
   AhBSet<T> set;
   set.n = 1;
   set.p[0] = prob;
-  const int nti = (nproj + KAhB<T>::TI - 1) / KAhB<T>::TI, ntj = (nb + KAhB<T>::TJ - 1) / KAhB<T>::TJ;
-  return launch<KAhB<T>>(dim3(nchunk, nti * ntj, 1), kBlock, KAhB<T>::lds_bytes(), s, set);
+  return launch_ahb<T>(nchunk, nproj, nb, 1, set, s);
 }
 
 template <typename T>
