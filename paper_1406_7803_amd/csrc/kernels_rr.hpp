@@ -2403,8 +2403,8 @@ struct KRRBigBack {
 // Triangular solves of the split path by column strips: a workgroup of 32 x 8 threads takes
 // 8 columns, keeps them in LDS, and walks the rows in blocks of 32 (forward, or backward for
 // L^H): thread (r, q) first subtracts from row r of the block the terms of every row already
-// solved (a dot product over them, the rows of the block in parallel), then one thread per
-// column solves the block's own triangle.
+// solved (a dot product over them, the rows of the block in parallel), then the first
+// wavefront solves the block's own triangle, all its rows and columns in parallel per step.
 //   MODE 0: B = L^{-1} A;  MODE 1: A~ = L^{-1} B^H (into A);
 //   MODE 2: C = L^{-H} W[:, :nb] (W^T rows in A) into Cd and, in plan precision, Ct, and the
 //           eigenvalues.
@@ -2467,17 +2467,22 @@ struct KRRBigTrsm {
         Ld[r * RB + p] = p < r ? lf(i, row(b0 + p)) : mk<double>(L[(size_t)i * m + i].x, 0.0);
       }
       c.sync();
-      for (int q = tid; q < CB; q += nt) {
-        for (int r = 0; r < nr; ++r) {
-          const int i = row(b0 + r);
-          double sx = X[i * CB + q].x, sy = X[i * CB + q].y;
-          for (int p = 0; p < r; ++p) {
-            const int k = row(b0 + p);
-            const cplx<double> l = Ld[r * RB + p], xk = X[k * CB + q];
-            sx -= l.x * xk.x - l.y * xk.y;
-            sy -= l.x * xk.y + l.y * xk.x;
+      // the block's own triangle by the first wavefront, row by row: row p is final once
+      // divided by its diagonal, then every row below subtracts its term of row p (the same
+      // terms in the same order as a row-by-row dot product)
+      if (c.wave() == 0) {
+        for (int p = 0; p < nr; ++p) {
+          const int ip = row(b0 + p);
+          for (int q = c.lane(); q < CB; q += c.wlanes()) X[ip * CB + q] = cdiv_real(X[ip * CB + q], Ld[p * RB + p].x);
+          c.wsync();
+          for (int e = c.lane(); e < (nr - 1 - p) * CB; e += c.wlanes()) {
+            const int r = p + 1 + e / CB, q = e % CB;
+            const int i = row(b0 + r);
+            const cplx<double> l = Ld[r * RB + p], xk = X[ip * CB + q];
+            X[i * CB + q].x -= l.x * xk.x - l.y * xk.y;
+            X[i * CB + q].y -= l.x * xk.y + l.y * xk.x;
           }
-          X[i * CB + q] = cdiv_real(mk<double>(sx, sy), Ld[r * RB + r].x);
+          c.wsync();
         }
       }
       c.sync();
