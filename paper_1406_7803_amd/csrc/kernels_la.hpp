@@ -590,85 +590,99 @@ struct KRotateChunk {
 
 // ---------------------------------------------------------------------------
 // The same rotation for any m and nb > 128 on the matrix cores. A workgroup of
-// four wavefronts takes 16 plane-wave columns. Only the rows 0..nb-1 of V are
+// four wavefronts takes 16 CG plane-wave columns. Only the rows 0..nb-1 of V are
 // overwritten, so only those (the X rows of the columns) are staged in LDS
 // before any output is written; the rows nb..m-1 are read straight from global
 // memory. Wavefront w accumulates the band tiles w, w + 4, ... (16 bands each,
 // at most kRotWideTiles per wavefront) over all m rows, then writes them.
-// grid (ceil(npw / 16), 2, n).
+// grid (ceil(npw / (16 CG)), number of rotated matrices, n).
 // ---------------------------------------------------------------------------
 constexpr int kRotWideTiles = 8;  // per wavefront: nb <= 4 * 8 * 16 = 512
 
-template <typename T>
+// CG groups of 16 plane-wave columns per workgroup (1 or 2): with two, every C element
+// loaded feeds twice the matrix-core work and C is read half as often over the grid.
+template <typename T, int CG = 1>
 struct KRotateWide {
-  FDE_HD static size_t lds_bytes(int nb) { return sizeof(cplx<T>) * (size_t)nb * 16; }
+  static constexpr int NC = 16 * CG;  // plane-wave columns per workgroup
+  FDE_HD static size_t lds_bytes(int nb) { return sizeof(cplx<T>) * (size_t)nb * NC; }
   template <class Ctx>
   FDE_HD static void run(const Ctx& c, char* lds, const ProbSet<T> ps) {
     const Prob<T>& P = ps.p[c.bz()];
     const int m = P.m, nb = P.nb, npw = P.npw;
-    const int g0 = c.bx() * 16;
+    const int g0 = c.bx() * NC;
     if (g0 >= npw) return;  // uniform per block
     cplx<T>* M = c.by() == 0 ? P.v : (c.by() == 1 ? P.hv : P.sv);
     if (!M) return;  // no S v rows in this problem (uniform per block)
     const cplx<T>* Cg = (const cplx<T>*)P.Ct;
-    cplx<T>* sX = (cplx<T>*)lds;  // [nb][16]
-    for (int idx = c.tid(); idx < nb * 16; idx += c.nthr()) {
-      const int j = idx >> 4, g = g0 + (idx & 15);
+    cplx<T>* sX = (cplx<T>*)lds;  // [nb][NC]
+    for (int idx = c.tid(); idx < nb * NC; idx += c.nthr()) {
+      const int j = idx / NC, g = g0 + (idx % NC);
       sX[idx] = g < npw ? M[(size_t)j * npw + g] : mk<T>(0, 0);
     }
     c.sync();
 #if defined(__HIP_DEVICE_COMPILE__)
     const int lane = c.tid() & 63, w = c.tid() >> 6;
     const int col = lane & 15, kq = lane >> 4;
-    const int g = g0 + col;
-    const bool gin = g < npw;
     const int ntile = (nb + 15) / 16;
     typedef T v4 __attribute__((ext_vector_type(4)));
-    v4 re[kRotWideTiles], im[kRotWideTiles];
+    v4 re[kRotWideTiles][CG], im[kRotWideTiles][CG];
 #pragma unroll
-    for (int t = 0; t < kRotWideTiles; ++t) {
-      re[t] = v4{0, 0, 0, 0};
-      im[t] = v4{0, 0, 0, 0};
-    }
+    for (int t = 0; t < kRotWideTiles; ++t)
+#pragma unroll
+      for (int h = 0; h < CG; ++h) {
+        re[t][h] = v4{0, 0, 0, 0};
+        im[t][h] = v4{0, 0, 0, 0};
+      }
     // operands of step k0 + 4 are loaded while the matrix cores work on step k0
-    auto load = [&](int k0, cplx<T>& b, cplx<T>* a) {
+    auto load = [&](int k0, cplx<T>* b, cplx<T>* a) {
       const int k = k0 + kq;
-      b = mk<T>(0, 0);
-      if (k < nb) b = sX[k * 16 + col];
-      else if (k < m && gin) b = M[(size_t)k * npw + g];
+#pragma unroll
+      for (int h = 0; h < CG; ++h) {
+        const int g = g0 + 16 * h + col;
+        b[h] = mk<T>(0, 0);
+        if (k < nb) b[h] = sX[k * NC + 16 * h + col];
+        else if (k < m && g < npw) b[h] = M[(size_t)k * npw + g];
+      }
 #pragma unroll
       for (int i = 0; i < kRotWideTiles; ++i) {
         const int n = 16 * (w + 4 * i) + col;
         a[i] = (k < m && n < nb) ? Cg[(size_t)k * nb + n] : mk<T>(0, 0);
       }
     };
-    cplx<T> bc, ac[kRotWideTiles], bn, an[kRotWideTiles];
+    cplx<T> bc[CG], ac[kRotWideTiles], bn[CG], an[kRotWideTiles];
     load(0, bc, ac);
     for (int k0 = 0; k0 < m; k0 += 4) {
       if (k0 + 4 < m) load(k0 + 4, bn, an);
-      const cplx<T> b = bc;
 #pragma unroll
       for (int i = 0; i < kRotWideTiles; ++i) {
         const int t = w + 4 * i;
         if (t >= ntile) break;
         const cplx<T> a_ = ac[i];
-        if constexpr (sizeof(T) == 8) {
-          re[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_.x, b.x, re[i], 0, 0, 0);
-          re[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_.y, b.y, re[i], 0, 0, 0);
-          im[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_.x, b.y, im[i], 0, 0, 0);
-          im[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_.y, b.x, im[i], 0, 0, 0);
-        } else {
-          re[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_.x, b.x, re[i], 0, 0, 0);
-          re[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a_.y, b.y, re[i], 0, 0, 0);
-          im[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_.x, b.y, im[i], 0, 0, 0);
-          im[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_.y, b.x, im[i], 0, 0, 0);
+#pragma unroll
+        for (int h = 0; h < CG; ++h) {
+          const cplx<T> b = bc[h];
+          if constexpr (sizeof(T) == 8) {
+            re[i][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_.x, b.x, re[i][h], 0, 0, 0);
+            re[i][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_.y, b.y, re[i][h], 0, 0, 0);
+            im[i][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_.x, b.y, im[i][h], 0, 0, 0);
+            im[i][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_.y, b.x, im[i][h], 0, 0, 0);
+          } else {
+            re[i][h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_.x, b.x, re[i][h], 0, 0, 0);
+            re[i][h] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a_.y, b.y, re[i][h], 0, 0, 0);
+            im[i][h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_.x, b.y, im[i][h], 0, 0, 0);
+            im[i][h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_.y, b.x, im[i][h], 0, 0, 0);
+          }
         }
       }
-      bc = bn;
+#pragma unroll
+      for (int h = 0; h < CG; ++h) bc[h] = bn[h];
 #pragma unroll
       for (int i = 0; i < kRotWideTiles; ++i) ac[i] = an[i];
     }
-    if (gin) {
+#pragma unroll
+    for (int h = 0; h < CG; ++h) {
+      const int g = g0 + 16 * h + col;
+      if (g >= npw) continue;
 #pragma unroll
       for (int i = 0; i < kRotWideTiles; ++i) {
         const int t = w + 4 * i;
@@ -677,17 +691,17 @@ struct KRotateWide {
         for (int r = 0; r < 4; ++r) {
           // output row of register r: FP64 MFMA 4 r + l/16, FP32 MFMA 4 (l/16) + r
           const int n = 16 * t + (sizeof(T) == 8 ? 4 * r + kq : 4 * kq + r);
-          if (n < nb) M[(size_t)n * npw + g] = mk<T>(re[i][r], im[i][r]);
+          if (n < nb) M[(size_t)n * npw + g] = mk<T>(re[i][h][r], im[i][h][r]);
         }
       }
     }
 #else
     // host: the X rows come from LDS, the rest from global memory (never written)
-    for (int gg = g0; gg < g0 + 16 && gg < npw; ++gg) {
+    for (int gg = g0; gg < g0 + NC && gg < npw; ++gg) {
       for (int n = 0; n < nb; ++n) {
         cplx<T> acc = mk<T>(0, 0);
         for (int k = 0; k < m; ++k) {
-          const cplx<T> v = k < nb ? sX[k * 16 + (gg - g0)] : M[(size_t)k * npw + gg];
+          const cplx<T> v = k < nb ? sX[k * NC + (gg - g0)] : M[(size_t)k * npw + gg];
           acc = acc + v * Cg[(size_t)k * nb + n];
         }
         M[(size_t)n * npw + gg] = acc;

@@ -196,6 +196,10 @@ static fde_status rr_launch(fde_plan* p, ProbSet<T>& ps, hipStream_t s) {
     return launch<KRotateChunk<T>, 256>(dim3((npwmax + 63) / 64, nrot, ps.n), 256, KRotateChunk<T>::lds_bytes(nbmax), s,
                                         ps);
   // matrix cores with the X rows of 16 columns in LDS (up to 512 bands)
+  // two column groups per workgroup where that still leaves two workgroups per CU
+  if (nbmax <= 4 * kRotWideTiles * 16 && KRotateWide<T, 2>::lds_bytes(nbmax) <= kLdsMax / 2)
+    return launch<KRotateWide<T, 2>, 256, 2>(dim3((npwmax + 31) / 32, nrot, ps.n), 256, KRotateWide<T, 2>::lds_bytes(nbmax),
+                                          s, ps);
   if (nbmax <= 4 * kRotWideTiles * 16 && KRotateWide<T>::lds_bytes(nbmax) <= kLdsMax)
     return launch<KRotateWide<T>, 256>(dim3((npwmax + 15) / 16, nrot, ps.n), 256, KRotateWide<T>::lds_bytes(nbmax), s,
                                        ps);
