@@ -574,68 +574,80 @@ struct KKbAdd {
 };
 
 // The same add on the matrix cores (up to 512 bands): a workgroup of four wavefronts takes
-// 16 plane waves; wavefront w accumulates the band tiles w, w + 4, ... (16 bands each) over
-// all projectors, four per step (A = dp^T tile, B = beta rows of the 16 plane waves), then
-// adds the tiles into hpsi, each element read and written once. grid ceil(npw / 16).
+// 16 CG plane waves; wavefront w accumulates the band tiles w, w + 4, ... (16 bands each)
+// over all projectors, four per step (A = dp^T tile, B = beta rows of the plane waves), then
+// adds the tiles into hpsi, each element read and written once. With CG = 2 every dp element
+// loaded feeds two column groups. grid ceil(npw / (16 CG)).
 constexpr int kKbAddTiles = 8;  // per wavefront: nb <= 4 * 8 * 16 = 512
 
-template <typename T>
+template <typename T, int CG = 1>
 struct KKbAddMfma {
   template <class Ctx>
   FDE_HD static void run(const Ctx& c, char*, const cplx<T>* __restrict__ beta, const cplx<T>* __restrict__ dp,
                          cplx<T>* __restrict__ hpsi, int npw, int nproj, int nb) {
-    const int g0 = c.bx() * 16;
+    const int g0 = c.bx() * 16 * CG;
     if (g0 >= npw) return;
 #if defined(__HIP_DEVICE_COMPILE__)
     const int lane = c.tid() & 63, w = c.tid() >> 6;
     const int col = lane & 15, kq = lane >> 4;
-    const int g = g0 + col;
-    const bool gin = g < npw;
     const int ntile = (nb + 15) / 16;
     typedef T v4 __attribute__((ext_vector_type(4)));
-    v4 re[kKbAddTiles], im[kKbAddTiles];
+    v4 re[kKbAddTiles][CG], im[kKbAddTiles][CG];
 #pragma unroll
-    for (int t = 0; t < kKbAddTiles; ++t) {
-      re[t] = v4{0, 0, 0, 0};
-      im[t] = v4{0, 0, 0, 0};
-    }
+    for (int t = 0; t < kKbAddTiles; ++t)
+#pragma unroll
+      for (int h = 0; h < CG; ++h) {
+        re[t][h] = v4{0, 0, 0, 0};
+        im[t][h] = v4{0, 0, 0, 0};
+      }
     // operands of step k0 + 4 are loaded while the matrix cores work on step k0
-    auto load = [&](int k0, cplx<T>& b, cplx<T>* a) {
+    auto load = [&](int k0, cplx<T>* b, cplx<T>* a) {
       const int k = k0 + kq;
-      b = (k < nproj && gin) ? beta[(size_t)k * npw + g] : mk<T>(0, 0);
+#pragma unroll
+      for (int h = 0; h < CG; ++h) {
+        const int g = g0 + 16 * h + col;
+        b[h] = (k < nproj && g < npw) ? beta[(size_t)k * npw + g] : mk<T>(0, 0);
+      }
 #pragma unroll
       for (int i = 0; i < kKbAddTiles; ++i) {
         const int n = 16 * (w + 4 * i) + col;
         a[i] = (k < nproj && n < nb) ? dp[(size_t)k * nb + n] : mk<T>(0, 0);
       }
     };
-    cplx<T> bc, ac[kKbAddTiles], bn, an[kKbAddTiles];
+    cplx<T> bc[CG], ac[kKbAddTiles], bn[CG], an[kKbAddTiles];
     load(0, bc, ac);
     for (int k0 = 0; k0 < nproj; k0 += 4) {
       if (k0 + 4 < nproj) load(k0 + 4, bn, an);
-      const cplx<T> b = bc;
 #pragma unroll
       for (int i = 0; i < kKbAddTiles; ++i) {
         const int t = w + 4 * i;
         if (t >= ntile) break;
         const cplx<T> a_ = ac[i];
-        if constexpr (sizeof(T) == 8) {
-          re[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_.x, b.x, re[i], 0, 0, 0);
-          re[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_.y, b.y, re[i], 0, 0, 0);
-          im[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_.x, b.y, im[i], 0, 0, 0);
-          im[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_.y, b.x, im[i], 0, 0, 0);
-        } else {
-          re[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_.x, b.x, re[i], 0, 0, 0);
-          re[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a_.y, b.y, re[i], 0, 0, 0);
-          im[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_.x, b.y, im[i], 0, 0, 0);
-          im[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_.y, b.x, im[i], 0, 0, 0);
+#pragma unroll
+        for (int h = 0; h < CG; ++h) {
+          const cplx<T> b = bc[h];
+          if constexpr (sizeof(T) == 8) {
+            re[i][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_.x, b.x, re[i][h], 0, 0, 0);
+            re[i][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_.y, b.y, re[i][h], 0, 0, 0);
+            im[i][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_.x, b.y, im[i][h], 0, 0, 0);
+            im[i][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_.y, b.x, im[i][h], 0, 0, 0);
+          } else {
+            re[i][h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_.x, b.x, re[i][h], 0, 0, 0);
+            re[i][h] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a_.y, b.y, re[i][h], 0, 0, 0);
+            im[i][h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_.x, b.y, im[i][h], 0, 0, 0);
+            im[i][h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_.y, b.x, im[i][h], 0, 0, 0);
+          }
         }
       }
-      bc = bn;
+#pragma unroll
+      for (int h = 0; h < CG; ++h) bc[h] = bn[h];
 #pragma unroll
       for (int i = 0; i < kKbAddTiles; ++i) ac[i] = an[i];
     }
-    if (gin) {
+#pragma unroll
+    for (int h = 0; h < CG; ++h) {
+      const int g = g0 + 16 * h + col;
+      if (g >= npw) continue;
 #pragma unroll
       for (int i = 0; i < kKbAddTiles; ++i) {
         const int t = w + 4 * i;
@@ -645,14 +657,14 @@ struct KKbAddMfma {
           // output row of register r: FP64 MFMA 4 r + l/16, FP32 MFMA 4 (l/16) + r
           const int n = 16 * t + (sizeof(T) == 8 ? 4 * r + kq : 4 * kq + r);
           if (n < nb) {
-            cplx<T>& h = hpsi[(size_t)n * npw + g];
-            h = mk<T>(h.x + re[i][r], h.y + im[i][r]);
+            cplx<T>& hv = hpsi[(size_t)n * npw + g];
+            hv = mk<T>(hv.x + re[i][h][r], hv.y + im[i][h][r]);
           }
         }
       }
     }
 #else
-    for (int gg = g0; gg < g0 + 16 && gg < npw; ++gg)
+    for (int gg = g0; gg < g0 + 16 * CG && gg < npw; ++gg)
       for (int n = 0; n < nb; ++n) {
         cplx<T> acc = mk<T>(0, 0);
         for (int k = 0; k < nproj; ++k) acc = acc + beta[(size_t)k * npw + gg] * dp[(size_t)k * nb + n];

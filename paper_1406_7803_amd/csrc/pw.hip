@@ -240,8 +240,13 @@ static fde_status apply_h_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, cpl
                                    (const cplx<double>*)part, nck,
                                    nproj, nbc, dkb, dp));
       if (nbc <= 4 * kKbAddTiles * 16)
-        FDE_TRY(launch<KKbAddMfma<T>>(dim3((t.npw + 15) / 16), kBlock, 0, s, beta, (const cplx<T>*)dp, hs, t.npw,
-                                      nproj, nbc));
+        // FP32: two column groups per workgroup (dp read half as often), two waves per SIMD
+        if (sizeof(T) == 4)
+          FDE_TRY((launch<KKbAddMfma<T, 2>, 256, 2>(dim3((t.npw + 31) / 32), kBlock, 0, s, beta, (const cplx<T>*)dp,
+                                                    hs, t.npw, nproj, nbc)));
+        else
+          FDE_TRY(launch<KKbAddMfma<T>>(dim3((t.npw + 15) / 16), kBlock, 0, s, beta, (const cplx<T>*)dp, hs, t.npw,
+                                        nproj, nbc));
       else
         FDE_TRY(launch<KKbAdd<T>>(dim3((t.npw + KKbAdd<T>::TG - 1) / KKbAdd<T>::TG), kBlock, KKbAdd<T>::lds_bytes(),
                                   s, beta, (const cplx<T>*)dp, hs, t.npw, nproj, nbc));
