@@ -72,7 +72,8 @@ def parse():
     ap.add_argument("--no-second-cell", action="store_true", help="skip the slab + molecule line")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
-    ap.add_argument("--streams", type=int, default=3, help="concurrent band-solver groups")
+    ap.add_argument("--streams", type=int, default=0,
+                    help="concurrent band-solver groups (0: one for blocks that fill the GPU, else three)")
     ap.add_argument("--gemm", choices=["fp64", "bf16x3", "bf16x6"], default="fp64",
                     help="arithmetic of the Rayleigh-Ritz subspace products (FP32 plan)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -228,7 +229,7 @@ def run_cycles(eng, n):
     return hist, times
 
 
-def precision_study(system, be, n_cycles=3):
+def precision_study(system, be, n_cycles=3, streams=0):
     """The large cell's fixed schedule with the FP64 plan (reference) and the FP32 plan
     with each subspace-product mode; errors of every FP32 run against the FP64 one."""
     import numpy as np
@@ -237,7 +238,7 @@ def precision_study(system, be, n_cycles=3):
     dv = float(np.prod(system.L)) / float(np.prod(system.grid))
     nelec = [s.nelec for s in system.subsystems]
     log("precision study: FP64 reference")
-    eng = driver.Engine(system, prec=fde.F64, backend=be)
+    eng = driver.Engine(system, prec=fde.F64, backend=be, streams=streams)
     ref, t64 = run_cycles(eng, n_cycles)
     del eng
     torch.cuda.empty_cache()
@@ -246,7 +247,7 @@ def precision_study(system, be, n_cycles=3):
     for name, gemm in (("fp32", fde.GEMM_FP64), ("fp32_bf16x6", fde.GEMM_BF16X6),
                        ("fp32_bf16x3", fde.GEMM_BF16X3)):
         log(f"precision study: {name}")
-        eng = driver.Engine(system, prec=fde.F32, backend=be, gemm=gemm)
+        eng = driver.Engine(system, prec=fde.F32, backend=be, gemm=gemm, streams=streams)
         hist, t = run_cycles(eng, n_cycles)
         ok = all(int(b.info.item()) == 0 for row in eng.blocks for b in row)
         del eng
@@ -444,13 +445,14 @@ def main():
     roof = roofline_object(eng, a.apply_reps, a.workload)
     bp, tp, nproj = isolated_apply(eng, a.apply_reps, with_proj=True)
     isolated = {"band_applies_per_s": bp.nb / tp, "bands": bp.nb, "projectors": nproj, "ms_per_call": tp * 1e3}
+    n_groups = eng.n_groups
     del eng
     torch.cuda.empty_cache()
 
     many = a.workload == "64-subsystems"
     prec_study = None
     if not a.no_precision_study and not many:
-        prec_study = precision_study(system, be)
+        prec_study = precision_study(system, be, streams=a.streams)
     second = None
     if a.workload == "large-slab" and not a.no_second_cell:
         log("slab + molecule cell")
@@ -492,7 +494,7 @@ def main():
                    "davidson_per_cycle": system.n_david, "subspace_products": a.gemm,
                    "launch": "eager" if a.eager else "one HIP graph per cycle",
                    "autotune": None if tuned is None else {k: tuned[k] for k in ("plane", "rows", "bpw", "zlds", "sz")},
-                   "solver_streams": a.streams, "parallelism": "single GPU"},
+                   "solver_streams": n_groups, "parallelism": "single GPU"},
         "isolated_apply_h": isolated,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -54,6 +54,13 @@ class SolverGroup:
     vbar: Optional[torch.Tensor] = None
 
 
+# Blocks this large (nb npw) fill the GPU on their own: concurrent solver groups then only
+# contend (large metal-surface cell, 320 x 158 149: one group 508 ms per cycle, three
+# 605 ms), while smaller blocks gain from them (slab + molecule cell, 40 x 50 300: three
+# groups 11.9 ms, one 13.9 ms; 64-subsystem cube: 272 against 370 ms).
+AUTO_ONE_STREAM_LOAD = 10_000_000
+
+
 @dataclass
 class Engine:
     system: object
@@ -62,7 +69,9 @@ class Engine:
     kinds: dict = field(default_factory=lambda: dict(xc=fde.XC_LDA, xc_nad=fde.XC_LDA, kin_nad=fde.KIN_LC94))
     mlp_params: Optional[torch.Tensor] = None   # learned preconditioner (FP32, FDE_MLP_NPARAM); None = TPA
     gemm: int = fde.GEMM_FP64                   # arithmetic of the Rayleigh-Ritz subspace products
-    streams: int = 3                            # band-solver groups run concurrently (GPU backend)
+    streams: int = 3                            # band-solver groups run concurrently (GPU backend);
+                                                # 0: one group when a block alone fills the GPU
+                                                # (nb npw >= AUTO_ONE_STREAM_LOAD), else three
     mixer: Optional[dict] = None                # None: linear (system.mix_beta); or dict(kind="pulay",
                                                 # nhist=6, beta=0.5, q0=0.5) for fde_mix_pulay
     scheme: str = "jacobi"                      # or "freeze-thaw": n_inner cycles per frozen environment
@@ -161,7 +170,12 @@ class Engine:
         """Split the band blocks into `streams` groups of about equal nb * npw."""
         s, p = self.system, self.plan
         blocks = [b for row in self.blocks for b in row]
-        ng = 1 if self.be.emulated else max(1, min(self.streams, len(blocks)))
+        streams = self.streams
+        if streams <= 0:
+            big = max(b.nb * p.npw(b.ik) for b in blocks)
+            streams = 1 if big >= AUTO_ONE_STREAM_LOAD else 3
+        self.n_groups = 1 if self.be.emulated else max(1, min(streams, len(blocks)))
+        ng = self.n_groups
         loads, members = [0] * ng, [[] for _ in range(ng)]
         for b in sorted(blocks, key=lambda b: -b.nb * p.npw(b.ik)):
             g = loads.index(min(loads))
