@@ -500,6 +500,18 @@ FDE_HD cplx<T> tw_const(int m) {
   return mk<T>((T)kTwTable<N>.re[m], (T)kTwTable<N>.im[m]);
 }
 
+// v times w^m (conjugated for INV), m in [0, N): the quarter turns as swaps and sign
+// flips, which unrolled code resolves at compile time.
+template <typename T, bool INV, int N>
+FDE_HD cplx<T> tw_mul(int m, cplx<T> v) {
+  if (m == 0) return v;
+  if (4 * m == N) return INV ? mk<T>(-v.y, v.x) : mk<T>(v.y, -v.x);
+  if (2 * m == N) return mk<T>(-v.x, -v.y);
+  if (4 * m == 3 * N) return INV ? mk<T>(v.y, -v.x) : mk<T>(-v.y, v.x);
+  const cplx<T> w = tw_const<T, N>(m);
+  return INV ? cmulc(w, v) : w * v;
+}
+
 // --------------------------------------------------------------------------
 // Whole-line FFT in registers (one thread per line): compile-time Stockham
 // stages, every index a constant after unrolling, so v[] stays in VGPRs.
@@ -519,10 +531,7 @@ FDE_HD void reg_stage(cplx<T>* x, cplx<T>* y, const cplx<T>* __restrict__ tw) {
       for (int r = 0; r < R; ++r) v[r] = x[j + r * nbf];
       if (k != 0) {
 #pragma unroll
-        for (int r = 1; r < R; ++r) {
-          const cplx<T> w = tw_const<T, N>(r * k * step);
-          v[r] = INV ? cmulc(w, v[r]) : w * v[r];
-        }
+        for (int r = 1; r < R; ++r) v[r] = tw_mul<T, INV, N>(r * k * step, v[r]);
       }
       if (R == 2) dft2<T, INV>(v);
       if (R == 3) dft3<T, INV>(v);
