@@ -197,8 +197,12 @@ struct KAhB {
 // product dimensions reach 128 (fewer operand reads per output; its FP64 staging would
 // not leave room for a second workgroup per CU), else the 32 tile.
 template <typename T>
+inline int ahb_tile(int ma, int mb) {
+  return sizeof(T) == 4 && ma >= 128 && mb >= 128 ? 64 : 32;
+}
+template <typename T>
 inline fde_status launch_ahb(unsigned nchunk, int ma, int mb, unsigned nz, const AhBSet<T>& set, hipStream_t s) {
-  if (sizeof(T) == 4 && ma >= 128 && mb >= 128) {
+  if (ahb_tile<T>(ma, mb) == 64) {
     using K = KAhB<T, 64>;
     const unsigned nt = (unsigned)(((ma + K::TI - 1) / K::TI) * ((mb + K::TJ - 1) / K::TJ));
     return launch<K, 256, 2>(dim3(nchunk, nt, nz), kBlock, K::lds_bytes(), s, set);

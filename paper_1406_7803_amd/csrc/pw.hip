@@ -133,12 +133,14 @@ static int plane_kind(const fde_plan* p, int ik, bool reg_ok, bool lds_ok, bool 
 }
 
 // Plane-wave chunks of the projections: kKbChunk per workgroup for the one-block product
-// (few projectors and bands); for the tiled product about 2048 workgroups over the chip, so
-// that each runs a long k loop and the FP64 partials stay small. A chunk count at most
-// that of kKbChunk-wide chunks, which sizes the workspace.
+// (few projectors and bands); for the tiled product (tiles of launch_ahb) about 2048
+// workgroups over the chip, so that each runs a long k loop and the FP64 partials stay
+// small. A chunk count at most that of kKbChunk-wide chunks, which sizes the workspace.
+template <typename T>
 static int kb_chunk(int npw, int nproj, int nb) {
   if (nproj <= 64 && nb <= 64) return kKbChunk;
-  const int tiles = ((nproj + 31) / 32) * ((nb + 31) / 32);
+  const int ts = ahb_tile<T>(nproj, nb);
+  const int tiles = ((nproj + ts - 1) / ts) * ((nb + ts - 1) / ts);
   const int nc = std::max(1, std::min((npw + kKbChunk - 1) / kKbChunk, 2048 / tiles));
   return std::max(kKbChunk, ((npw + nc - 1) / nc + 63) / 64 * 64);
 }
@@ -147,7 +149,7 @@ static int kb_chunk(int npw, int nproj, int nb) {
 template <typename T>
 static fde_status kb_project(const cplx<T>* beta, const cplx<T>* psi, int npw, int nproj, int nb, int nchunk,
                              cplx<double>* part, hipStream_t s) {
-  const AhBProb<T> prob{beta, psi, nullptr, nproj, nb, npw, nchunk, kb_chunk(npw, nproj, nb), part};
+  const AhBProb<T> prob{beta, psi, nullptr, nproj, nb, npw, nchunk, kb_chunk<T>(npw, nproj, nb), part};
   if (nproj <= 64 && nb <= 64)
     return launch<KAhBAll<T>, 512>(dim3(nchunk), 512, KAhBAll<T>::lds_bytes(nproj, nb), s, prob);
   AhBSet<T> set;
@@ -233,7 +235,7 @@ static fde_status apply_h_t(fde_plan* p, int ik, int nb, const cplx<T>* psi, cpl
                                (const int4*)t.d_sticks, (const int*)t.d_xlist, t.ncol, N1, N2, p->rad[2], tw3, kv,
                                invN, SZ));
     if (nproj > 0) {
-      const int kc = kb_chunk(t.npw, nproj, nbc), nck = (t.npw + kc - 1) / kc;
+      const int kc = kb_chunk<T>(t.npw, nproj, nbc), nck = (t.npw + kc - 1) / kc;
       FDE_TRY(kb_project<T>(beta, ps, t.npw, nproj, nbc, nck, part, s));
       FDE_TRY(launch<KKbReduce<T>>(dim3((nproj * nbc + KKbReduce<T>::NO - 1) / KKbReduce<T>::NO), kBlock,
                                    KKbReduce<T>::NG * KKbReduce<T>::NO * sizeof(cplx<double>), s,
@@ -453,7 +455,7 @@ static fde_status band_energies_t(fde_plan* p, int ik, int nb, const cplx<T>* ps
                               per_band));
   FDE_TRY(launch<KSumInto>(dim3(1), kBlock, 17 * sizeof(double), s, (const double*)per_band, nb, out));
   if (nproj > 0) {
-    const int kc = kb_chunk(t.npw, nproj, nb), nck = (t.npw + kc - 1) / kc;
+    const int kc = kb_chunk<T>(t.npw, nproj, nb), nck = (t.npw + kc - 1) / kc;
     FDE_TRY(kb_project<T>(beta, psi, t.npw, nproj, nb, nck, part, s));
     FDE_TRY(launch<KBandNl>(dim3(nb), kBlock, 17 * sizeof(double), s, (const cplx<double>*)part, nck, nproj, nb,
                             dkb, occw, per_band));
